@@ -1,0 +1,8 @@
+"""CPU FP64 oracle of the linear bond-based peridynamic model (test infrastructure only).
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg import
+this package.  The product library never does, and the two share no code.
+"""
+from .oracle import (Problem, alpha_2d, alpha_3d, apply, assemble_dense, broken_csr,  # noqa: F401
+                     build_oracle, crack_to_bonds, energy, force, grad_dense, lifted_rhs,
+                     solve_cg, solve_dense, vv)

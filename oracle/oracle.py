@@ -1,0 +1,397 @@
+"""CPU oracle for the linear bond-based peridynamic model, FP64.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product library.  It shares no code
+with the GPU library; only the seeded input generators are common to both.
+
+Every function is the plain definition of what the paper's method reproduces
+exactly ("without loss of accuracy", Sec. 1): the meshfree sum of eq. (mat:f1)
+evaluated bond by bond (``oracle_core.c``), the dense stiffness matrix of
+eqs. (matrix)/(mae:e1), and the model equations built on it:
+
+* ``force``/``apply``      -- f = A u, eq. (mat:f1); constrained rows reported as 0
+                              (their content is arbitrary, Remark 1).
+* ``assemble_dense``       -- A, eq. (matrix); used at small sizes only.
+* ``solve_dense``          -- static model eq. (mat:e2): K = -A, K_FF u_F =
+                              b_F - K_FC g_C, u_C = g_C (Sec. 3.4, eq. (up));
+                              dense Cholesky.
+* ``solve_cg``             -- the same system by conjugate gradients with the
+                              bond-sum apply (for grids too big to factor).
+* ``vv``                   -- velocity Verlet, Alg. 2, with a = (A u + b)/rho and
+                              constrained DOFs overwritten after each update (eq. (up)).
+* ``energy``               -- kinetic + elastic - external work of the discrete system.
+* ``grad_dense``           -- exact gradient of ||u - u_t||^2 w.r.t. the body force
+                              and the influence coefficients a_k (omega = sum_k a_k (r/delta)^k).
+* ``crack_to_bonds``       -- broken set of eq. (mu) for a pre-crack: a bond is broken
+                              iff its segment properly crosses a crack segment.
+
+Parity of the paper's own displacement results is unpinned (they are figures
+only and are absent from the text); the tests pin this oracle with
+invariants and closed forms instead.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle_core.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile ``oracle_core.c`` with gcc (IEEE FP64, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build_oracle(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_force_rows.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_int, P, P, P, P, P,
+                                          ctypes.c_int64, P]
+        lib.oracle_force_rows.restype = None
+        lib.oracle_assemble_dense.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_int, P, P, P, P]
+        lib.oracle_assemble_dense.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class Problem:
+    """Uniform-grid linear BB-PD problem (Sec. 3 for 2D, Sec. 4 for 3D).
+
+    n      -- nodes per axis (nx, ny) or (nx, ny, nz); node (i,j,k) at ((i+1/2)h, ...)
+    h      -- grid spacing; node volume V = h^dim
+    M      -- horizon in cells, delta = M h
+    alpha  -- micromodulus scale of eq. (ker:e1) (caller computes it, Sec. 2.1)
+    infl   -- influence coefficients a_k, omega(r) = sum_k a_k (r/delta)^k; empty -> 1
+    rho    -- mass density (dynamic model, eq. (mat:e1))
+    """
+    n: Sequence[int]
+    h: float
+    M: int
+    alpha: float
+    infl: Sequence[float] = field(default_factory=tuple)
+    rho: float = 1.0
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def delta(self) -> float:
+        return self.M * self.h
+
+    def node_coords(self) -> np.ndarray:
+        """[dim][N] node coordinates x = (i + 1/2) h, node id (k*ny + j)*nx + i."""
+        axes = [(np.arange(m) + 0.5) * self.h for m in self.n]
+        grids = np.meshgrid(*axes[::-1], indexing="ij")[::-1]
+        return np.stack([g.reshape(-1) for g in grids])
+
+
+def alpha_2d(E: float, delta: float, thickness: float = 1.0) -> float:
+    """alpha = 9E / (pi delta^3 t), plane stress/strain (Sec. 2.1)."""
+    return 9.0 * E / (math.pi * delta ** 3 * thickness)
+
+
+def alpha_3d(E: float, delta: float) -> float:
+    """alpha = 12E / (pi delta^4) (Sec. 2.1)."""
+    return 12.0 * E / (math.pi * delta ** 4)
+
+
+def broken_csr(N: int, pairs: Optional[np.ndarray]):
+    """Per-node sorted neighbour lists of the broken set (mu = 0, eq. (mu))."""
+    if pairs is None or len(pairs) == 0:
+        return None, None
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    src = np.concatenate([pairs[:, 0], pairs[:, 1]])
+    dst = np.concatenate([pairs[:, 1], pairs[:, 0]])
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    ptr = np.zeros(N + 1, dtype=np.int64)
+    np.add.at(ptr, src + 1, 1)
+    ptr = np.cumsum(ptr)
+    return np.ascontiguousarray(ptr), np.ascontiguousarray(dst)
+
+
+def _infl_arr(prob: Problem):
+    a = np.ascontiguousarray(np.asarray(prob.infl, dtype=np.float64))
+    return a, len(a)
+
+
+def force(prob: Problem, u: np.ndarray, broken=None, rows: Optional[np.ndarray] = None) -> np.ndarray:
+    """f = A u evaluated bond by bond, eq. (mat:f1), on every row (or on ``rows``).
+
+    u: [dim][N] (or flat).  Returns [dim][N] (or [dim][len(rows)])."""
+    lib = _load()
+    d, N = prob.dim, prob.N
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(d, N))
+    n = np.array(list(prob.n) + [1] * (3 - d), dtype=np.int64)
+    ptr, idx = broken_csr(N, broken)
+    infl, ni = _infl_arr(prob)
+    if rows is not None:
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        nr = len(rows)
+    else:
+        nr = N
+    f = np.empty((d, nr), dtype=np.float64)
+    lib.oracle_force_rows(d, _ptr(n), prob.h, prob.M, prob.alpha, ni,
+                          _ptr(infl) if ni else None, _ptr(u), _ptr(ptr), _ptr(idx),
+                          _ptr(rows), nr, _ptr(f))
+    return f
+
+
+def apply(prob: Problem, u: np.ndarray, fixed: Optional[np.ndarray] = None, broken=None) -> np.ndarray:
+    """f = A u with rows of constrained DOFs reported as 0 (Remark 1)."""
+    f = force(prob, u, broken)
+    if fixed is not None:
+        f[np.asarray(fixed, dtype=bool).reshape(f.shape)] = 0.0
+    return f
+
+
+def assemble_dense(prob: Problem, broken=None) -> np.ndarray:
+    """Dense A (dim*N square), eq. (matrix); row/column index c*N + p."""
+    lib = _load()
+    d, N = prob.dim, prob.N
+    n = np.array(list(prob.n) + [1] * (3 - d), dtype=np.int64)
+    ptr, idx = broken_csr(N, broken)
+    infl, ni = _infl_arr(prob)
+    A = np.empty((d * N, d * N), dtype=np.float64)
+    lib.oracle_assemble_dense(d, _ptr(n), prob.h, prob.M, prob.alpha, ni,
+                              _ptr(infl) if ni else None, _ptr(ptr), _ptr(idx), _ptr(A))
+    return A
+
+
+def _split(prob: Problem, fixed):
+    d, N = prob.dim, prob.N
+    if fixed is None:
+        fx = np.zeros(d * N, dtype=bool)
+    else:
+        fx = np.asarray(fixed, dtype=bool).reshape(-1)
+    return fx
+
+
+def solve_dense(prob: Problem, b, fixed=None, g=None, broken=None, A=None) -> np.ndarray:
+    """Static model eq. (mat:e2) by dense Cholesky.
+
+    K = -A; K_FF u_F = b_F - K_FC g_C; u_C = g_C (eq. (up), Sec. 3.4).  Returns [dim][N]."""
+    import scipy.linalg as sla
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed)
+    F, C = ~fx, fx
+    if A is None:
+        A = assemble_dense(prob, broken)
+    K = -A
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    gv = np.zeros(d * N) if g is None else np.asarray(g, dtype=np.float64).reshape(-1)
+    rhs = b[F] - K[np.ix_(F, C)] @ gv[C]
+    cf = sla.cho_factor(K[np.ix_(F, F)], lower=True)
+    u = np.zeros(d * N)
+    u[F] = sla.cho_solve(cf, rhs)
+    u[C] = gv[C]
+    return u.reshape(d, N)
+
+
+def lifted_rhs(prob: Problem, b, fixed=None, g=None, broken=None) -> np.ndarray:
+    """b_F - K_FC g_C on free DOFs (0 on constrained), via the bond-sum apply."""
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed)
+    b = np.asarray(b, dtype=np.float64).reshape(-1).copy()
+    if g is not None:
+        gc = np.where(fx, np.asarray(g, dtype=np.float64).reshape(-1), 0.0)
+        b += force(prob, gc, broken).reshape(-1)   # -K_FC g_C = A_FC g_C
+    b[fx] = 0.0
+    return b.reshape(d, N)
+
+
+def solve_cg(prob: Problem, b, fixed=None, g=None, broken=None, tol: float = 1e-14,
+             maxit: int = 100000, x0=None):
+    """Static model eq. (mat:e2) by plain conjugate gradients on the free DOFs.
+
+    Operator v -> -(A v) restricted to free DOFs (v is zero on constrained DOFs);
+    stops when ||r||_2 <= tol ||b'||_2.  Returns (u [dim][N], iterations, rel_residual)."""
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed)
+
+    def K(v):
+        w = -force(prob, v, broken).reshape(-1)
+        w[fx] = 0.0
+        return w
+
+    bp = lifted_rhs(prob, b, fixed, g, broken).reshape(-1)
+    x = np.zeros(d * N) if x0 is None else np.where(fx, 0.0, np.asarray(x0).reshape(-1))
+    r = bp - K(x)
+    p = r.copy()
+    rr = r @ r
+    bn = math.sqrt(bp @ bp)
+    it = 0
+    while math.sqrt(rr) > tol * bn and it < maxit:
+        q = K(p)
+        a = rr / (p @ q)
+        x += a * p
+        r -= a * q
+        rr_new = r @ r
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    rtrue = bp - K(x)
+    u = x.copy()
+    if g is not None:
+        u[fx] = np.asarray(g, dtype=np.float64).reshape(-1)[fx]
+    return u.reshape(d, N), it, math.sqrt(rtrue @ rtrue) / bn
+
+
+def vv(prob: Problem, u0, v0, b, dt: float, nsteps: int, fixed=None, g=None, broken=None,
+       energy_every: int = 0):
+    """Velocity Verlet, Alg. 2, with acceleration a = (A u + b)/rho (eq. (mat:e1)).
+
+    Constrained DOFs are overwritten with g after each displacement update
+    (eq. (up)); their velocity and acceleration are held at 0.
+    Returns (u, v, a, energies) with energies sampled after every
+    ``energy_every`` steps (empty when 0)."""
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed).reshape(d, N)
+    b = np.asarray(b, dtype=np.float64).reshape(d, N)
+    u = np.asarray(u0, dtype=np.float64).reshape(d, N).copy()
+    v = np.asarray(v0, dtype=np.float64).reshape(d, N).copy()
+    gv = None if g is None else np.asarray(g, dtype=np.float64).reshape(d, N)
+    if gv is not None:
+        u[fx] = gv[fx]
+    v[fx] = 0.0
+
+    def accel(uu):
+        a = (force(prob, uu, broken) + b) / prob.rho
+        a[fx] = 0.0
+        return a
+
+    a = accel(u)
+    energies = []
+    for n in range(1, nsteps + 1):
+        u = u + dt * v + 0.5 * dt * dt * a
+        if gv is not None:
+            u[fx] = gv[fx]
+        a_new = accel(u)
+        v = v + 0.5 * dt * (a + a_new)
+        v[fx] = 0.0
+        a = a_new
+        if energy_every and n % energy_every == 0:
+            energies.append(energy(prob, u, v, b, fixed, broken))
+    return u, v, a, np.array(energies)
+
+
+def energy(prob: Problem, u, v, b, fixed=None, broken=None) -> float:
+    """H = 1/2 rho V sum v^2 - 1/2 V sum u (A u) - V sum b u over free DOFs.
+
+    -A is symmetric positive semidefinite, so this is the conserved energy of
+    rho u'' = A u + b (eq. (mat:e1)) and VV keeps it bounded."""
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed)
+    F = ~fx
+    V = prob.h ** d
+    u = np.asarray(u, dtype=np.float64).reshape(-1)
+    v = np.asarray(v, dtype=np.float64).reshape(-1)
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    Au = force(prob, u, broken).reshape(-1)
+    return float(0.5 * prob.rho * V * (v[F] @ v[F]) - 0.5 * V * (u[F] @ Au[F]) - V * (b[F] @ u[F]))
+
+
+def grad_dense(prob: Problem, b, u_target, fixed=None, g=None, broken=None):
+    """Loss L = ||u - u_t||^2 (all DOFs) of the static solution and its exact gradient.
+
+    u solves K(a) u = b on free DOFs, K = -A(a), A(a) = sum_k a_k A_k with A_k the
+    stiffness built with omega = (r/delta)^k.  Adjoint: K_FF symmetric, so
+    w = K_FF^{-1} dL/du_F; dL/db_F = w; dL/da_k = w . (A_k u)_F (u including g).
+    Returns (L, u, dL/db [dim][N] (0 on constrained), dL/da [n_infl])."""
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed)
+    F = ~fx
+    A = assemble_dense(prob, broken)
+    u = solve_dense(prob, b, fixed, g, broken, A=A).reshape(-1)
+    ut = np.asarray(u_target, dtype=np.float64).reshape(-1)
+    L = float((u - ut) @ (u - ut))
+    import scipy.linalg as sla
+    cf = sla.cho_factor(-A[np.ix_(F, F)], lower=True)
+    w = np.zeros(d * N)
+    w[F] = sla.cho_solve(cf, 2.0 * (u - ut)[F])
+    ga = np.zeros(len(prob.infl))
+    for k in range(len(prob.infl)):
+        e = np.zeros(len(prob.infl))
+        e[k] = 1.0
+        pk = Problem(prob.n, prob.h, prob.M, prob.alpha, tuple(e), prob.rho)
+        Aku = force(pk, u, broken).reshape(-1)
+        ga[k] = w[F] @ Aku[F]
+    return L, u.reshape(d, N), w.reshape(d, N), ga
+
+
+def crack_to_bonds(prob: Problem, segments) -> np.ndarray:
+    """Broken bonds of a 2D pre-crack: {p, q} (p < q, inside each other's horizon)
+    is broken iff the closed segment [x_p, x_q] properly crosses a crack segment,
+    i.e. both orientation pairs have strictly opposite signs (FP64; touching or
+    collinear does not count).  Brute force over every bond.  Returns [nb][2]."""
+    assert prob.dim == 2
+    nx, ny = prob.n
+    M = prob.M
+    xs = prob.node_coords()
+    out = []
+    segs = np.asarray(segments, dtype=np.float64).reshape(-1, 4)
+    ids = np.arange(prob.N).reshape(ny, nx)
+
+    def orient(ax, ay, bx, by, cx, cy):
+        return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax)
+
+    for oy in range(0, M + 1):
+        for ox in range(-M, M + 1):
+            if oy == 0 and ox <= 0:
+                continue                         # each undirected bond once
+            if ox * ox + oy * oy > M * M:
+                continue
+            i0, i1 = max(0, -ox), min(nx, nx - ox)
+            j0, j1 = 0, ny - oy
+            if i0 >= i1 or j0 >= j1:
+                continue
+            P = ids[j0:j1, i0:i1].reshape(-1)
+            Q = ids[j0 + oy:j1 + oy, i0 + ox:i1 + ox].reshape(-1)
+            px, py = xs[0][P], xs[1][P]
+            qx, qy = xs[0][Q], xs[1][Q]
+            cut = np.zeros(len(P), dtype=bool)
+            for (c0x, c0y, c1x, c1y) in segs:
+                d1 = orient(c0x, c0y, c1x, c1y, px, py)
+                d2 = orient(c0x, c0y, c1x, c1y, qx, qy)
+                d3 = orient(px, py, qx, qy, c0x, c0y)
+                d4 = orient(px, py, qx, qy, c1x, c1y)
+                cut |= (((d1 > 0) & (d2 < 0)) | ((d1 < 0) & (d2 > 0))) & \
+                       (((d3 > 0) & (d4 < 0)) | ((d3 < 0) & (d4 > 0)))
+            if cut.any():
+                pp, qq = P[cut], Q[cut]
+                out.append(np.stack([np.minimum(pp, qq), np.maximum(pp, qq)], axis=1))
+    if not out:
+        return np.zeros((0, 2), dtype=np.int64)
+    pairs = np.concatenate(out)
+    order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    return np.ascontiguousarray(pairs[order])
