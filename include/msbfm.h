@@ -1,0 +1,206 @@
+/*
+ * msbfm.h -- C ABI of the MI355X (gfx950) library for the matrix-structure-based
+ * fast method (MSBFM) of linear bond-based peridynamics:
+ *   C. Liu, H. Tian, W. S. Don, H. Wang, "A fast computational framework for the
+ *   linear bond-based peridynamic model" (arXiv 2301.11828).
+ *
+ * The library applies the stiffness matrix A of the meshfree discretisation
+ * (Sec. 2.3, eq. (mat:f1), entries eq. (matrix) in 2D and eq. (mae:e1) in 3D) on a
+ * uniform grid as A = A_hat + D^e + D^f (Sec. 3.3-3.6, eq. (dec:e1)):
+ *   - A_hat, the multilevel Toeplitz part, by zero-padded embedding, forward FFT,
+ *     a pointwise d x d block product with the generating-array spectra and an
+ *     inverse FFT (Alg. 3 in 2D, Alg. 4 in 3D);
+ *   - D^e, the incomplete-horizon diagonal (eq. (mat:se), (tea:sc));
+ *   - D^f, the broken-bond correction (eq. (df), (tea:fr));
+ *   - rows of constrained DOFs (Omega_c, Sec. 3.4, Remark 2) masked per DOF.
+ * On top of that product it runs the static model (eq. (mat:e2)) by conjugate
+ * gradients in FP64 or FP32 inside FP64 iterative refinement, the dynamic model
+ * (eq. (mat:e1)) by velocity Verlet (Alg. 2), and the adjoint gradient of a static
+ * solve with respect to the influence-function coefficients.
+ *
+ * Conventions (all entry points):
+ *   - Layout: batch-major structure of arrays, [B][d][Nz][Ny][Nx], x fastest
+ *     (node order of Sec. 3 and Sec. 4), B = batch cases sharing one plan.
+ *   - Arrays marked "device" are HIP device pointers (for example a torch CUDA
+ *     tensor's data_ptr()); arrays marked "host" are ordinary host memory.  The
+ *     caller owns every array it passes; the library owns only what a plan
+ *     allocates.
+ *   - stream: a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *     enqueued on it; calls that return host results synchronise it.
+ *   - Every call returns an msb_status; nothing throws across the ABI.  On a
+ *     non-OK status msb_last_error() gives a message (thread-local).
+ *   - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef MSBFM_H
+#define MSBFM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct msb_plan_s *msb_plan;
+
+typedef enum {
+    MSB_OK = 0,
+    MSB_EINVAL = -1,        /* invalid argument (sizes, pointers, non-finite input, bad bond list) */
+    MSB_ENOMEM = -2,        /* device or host allocation failed */
+    MSB_EDEVICE = -3,       /* a HIP runtime call failed */
+    MSB_ENOCONV = -4,       /* iteration limit reached or refinement stagnated */
+    MSB_ENOTSPD = -5,       /* CG breakdown: p.Kp <= 0 or non-finite (singular/unconstrained problem) */
+    MSB_EUNSUPPORTED = -6   /* valid request this build does not support */
+} msb_status;
+
+typedef enum {
+    MSB_FP64 = 0,           /* all arithmetic in FP64 */
+    MSB_FP32 = 1,           /* FFT product and vectors in FP32 */
+    MSB_FP32_REFINED = 2    /* FP32 inner CG inside an FP64 iterative-refinement loop (solve only) */
+} msb_precision;
+
+/*
+ * Problem description: grid (Sec. 3: x_i = x_l + (i - 1/2) h, 1-based; here
+ * node (i,j,k), 0-based, sits at ((i+1/2)h, (j+1/2)h, (k+1/2)h)), horizon
+ * delta = M h (Sec. 3.2, M = delta/h), micromodulus scale alpha (Sec. 2.1:
+ * 9E/(pi delta^3 t) in 2D, 12E/(pi delta^4) in 3D, computed by the caller),
+ * optional radial influence omega(r) = sum_k infl[k] (r/delta)^k multiplying
+ * C of eq. (ker:e1) (n_infl = 0 means omega = 1, the paper's kernel), density rho
+ * (eq. (mat:e1)) and the number B of load cases sharing the plan.
+ */
+typedef struct {
+    int dim;                /* 2 or 3 */
+    int64_t n[3];           /* Nx, Ny, Nz (Nz ignored in 2D); each >= 1 */
+    double h;               /* grid spacing, > 0; node volume V = h^dim */
+    int M;                  /* horizon in cells, 1 <= M <= 32 */
+    double alpha;           /* micromodulus scale, finite */
+    int n_infl;             /* 0..8 */
+    const double *infl;     /* host, [n_infl], copied at plan creation */
+    double rho;             /* density > 0 (dynamic model only) */
+    int batch;              /* B >= 1 */
+} msb_problem_desc;
+
+/*
+ * Create a plan: stencil weights of eq. (frb:e1) (lambda of eq. (fac:e1)), the
+ * real spectra of the generating arrays G (Sec. 3.3, Alg. 3; Sec. 4, Alg. 4)
+ * on padded lengths L >= N + M per axis, the D^e table (eq. (mat:se)), FFT
+ * schedules and device workspace.  Allocates device memory on the current
+ * device.  *out is NULL on failure.
+ */
+msb_status msb_plan_create(const msb_problem_desc *desc, msb_plan *out);
+void msb_plan_destroy(msb_plan plan);
+
+/*
+ * Volume constraints, per DOF (Sec. 3.4, eq. (up); Remark 2 allows one direction
+ * of a node to be constrained and another free).  fixed: host, [d][N] bytes,
+ * nonzero = constrained; NULL clears all constraints.  Constrained DOFs are
+ * shared by every case of the batch.
+ */
+msb_status msb_plan_set_constraints(msb_plan plan, const uint8_t *fixed);
+
+/*
+ * Broken bonds (bond status mu = 0, eq. (mu); correction D^f of eq. (df)).
+ * pairs: host, [nb][2] node ids (p, q) with p != q, each pair once (either order),
+ * both nodes in the grid and within each other's horizon.  nb = 0 clears the
+ * list.  Returns MSB_EINVAL (list unchanged) on an out-of-range id, a pair
+ * outside the horizon, or a duplicate.
+ */
+msb_status msb_plan_set_bonds(msb_plan plan, const int64_t *pairs, int64_t nb);
+
+/*
+ * Pre-crack to broken bonds for 2D problems (Sec. 3.6, Sec. 5.2): the bond {p,q}
+ * is broken iff the segment [x_p, x_q] properly crosses a crack segment (both
+ * orientation tests strictly of opposite sign, in FP64; touching or collinear
+ * does not count).  seg: host, [ns][4] = (x0, y0, x1, y1) in the coordinates of
+ * msb_problem_desc.  pairs_out: host, capacity cap pairs (p < q, sorted); *nb_out
+ * receives the number found (MSB_EINVAL with *nb_out set if it exceeds cap).
+ */
+msb_status msb_crack_to_bonds(const msb_problem_desc *desc, const double *seg, int64_t ns,
+                              int64_t *pairs_out, int64_t cap, int64_t *nb_out);
+
+/*
+ * Replace the influence coefficients (rebuilds the spectra, D^e table and bond
+ * weights; same n_infl as at creation, or any count <= 8 when the plan was
+ * created with n_infl > 0).  infl: host.  With per_case != 0, infl holds
+ * [B][n_infl] coefficients and every case of the batch gets its own operator.
+ */
+msb_status msb_plan_set_infl(msb_plan plan, const double *infl, int n_infl, int per_case);
+
+/*
+ * f = A u (eq. (mat:f1)) on free DOFs, 0 on constrained DOFs (Remark 1 leaves
+ * those rows arbitrary).  u, f: device, [B][d][N], double (MSB_FP64) or float
+ * (MSB_FP32); u and f must not overlap.
+ */
+msb_status msb_apply(msb_plan plan, msb_precision prec, const void *u, void *f, void *stream);
+
+/*
+ * Same product with the operator built for omega = (r/delta)^k (the derivative of
+ * A with respect to the influence coefficient a_k), FP64.  Used by the adjoint.
+ */
+msb_status msb_apply_dinfl(msb_plan plan, int k, const double *u, double *f, void *stream);
+
+typedef struct {
+    double tol;             /* stop when ||b' - K u||_2 <= tol ||b'||_2 on free DOFs (FP64 apply) */
+    int maxit;              /* cap on CG iterations (inner iterations for FP32_REFINED), > 0 */
+    double inner_tol;       /* FP32_REFINED: relative residual reduction per inner solve (0 = auto) */
+    int graph_block;        /* CG iterations per hipGraph launch (0 = no graph, plain launches) */
+    int reliable_update;    /* FP32_REFINED: 1 = keep the Krylov space, replace the residual in FP64 */
+} msb_solve_opts;
+
+typedef struct {
+    int status;             /* msb_status of this case */
+    int outer_iters;        /* refinement steps (1 for FP64) */
+    int inner_iters;        /* total CG iterations */
+    double rel_residual;    /* ||b' - K u|| / ||b'||, FP64 apply, free DOFs */
+    double seconds;         /* wall time of the call (whole batch) */
+} msb_solve_info;
+
+/*
+ * Static model, eq. (mat:e2): K = -A; solve K_FF u_F = b_F - K_FC g_C and set
+ * u_C = g_C (Sec. 3.4, eq. (up)).  b: device [B][d][N] double; g: device
+ * [B][d][N] double with values read on constrained DOFs only, or NULL for g = 0;
+ * u: device [B][d][N] double output.  info: host [B].  Synchronises the stream.
+ * MSB_ENOCONV if any case misses tol within maxit; MSB_ENOTSPD on CG breakdown.
+ */
+msb_status msb_solve_static(msb_plan plan, msb_precision prec, const double *b, const double *g,
+                            double *u, const msb_solve_opts *opts, msb_solve_info *info,
+                            void *stream);
+
+/*
+ * Dynamic model, eq. (mat:e1), by velocity Verlet (Alg. 2) with a = (A u + b)/rho:
+ *   u <- u + dt v + dt^2 a / 2;  u_C <- g_C (eq. (up));  a' = (A u + b)/rho (0 on
+ *   constrained DOFs);  v <- v + dt (a + a')/2 (0 on constrained DOFs);  a <- a'.
+ * u, v, a: device [B][d][N] (double for MSB_FP64, float for MSB_FP32), updated in
+ * place; on entry a must hold the acceleration of the entry state (msb_vv_init).
+ * b: device, same type, constant in time.  g: device, same type, or NULL (= 0).
+ * energy: host [nsteps/every] doubles or NULL; entry s receives, after step
+ * (s+1)*every, H = rho V/2 sum v^2 - V/2 sum u (A u) - V sum b u over free DOFs,
+ * accumulated in FP64 (whole batch).  Synchronises the stream when energy != NULL.
+ */
+msb_status msb_vv_init(msb_plan plan, msb_precision prec, const void *u, const void *b, void *a,
+                       void *stream);
+msb_status msb_vv_run(msb_plan plan, msb_precision prec, double dt, int64_t nsteps, void *u,
+                      void *v, void *a, const void *b, const void *g, double *energy, int every,
+                      void *stream);
+
+/*
+ * Adjoint gradient of a loss of a static solution u (Sec. 2.1 kernel with
+ * omega = sum_k a_k (r/delta)^k): K symmetric, so with w = K_FF^{-1} dL/du_F
+ * (w from msb_solve_static on dL/du) the gradient is dL/db_F = w and
+ * dL/da_k = w . (A_k u)_F, A_k the operator for omega = (r/delta)^k.
+ * u, w: device [B][d][N] double; dL_da: host [B][n_infl].  Synchronises.
+ */
+msb_status msb_grad_infl(msb_plan plan, const double *u, const double *w, double *dL_da,
+                         void *stream);
+
+/* Plan geometry queries (host): padded FFT lengths L[3] and the number of
+ * nodes N per case. */
+msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *msb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSBFM_H */

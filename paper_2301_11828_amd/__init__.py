@@ -1,0 +1,327 @@
+"""MI355X (gfx950) implementation of the matrix-structure-based fast method (MSBFM)
+for linear bond-based peridynamics (Liu, Tian, Don, Wang, arXiv 2301.11828).
+
+This module is a thin ctypes binding over ``libmsbfm.so`` (C ABI in
+``include/msbfm.h``): it checks and marshals arguments, and PyTorch supplies device
+memory and the current stream.  Every step of the computation runs in the library's
+HIP kernels; there is no CPU fallback, and importing fails loudly when the library
+has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmsbfm.so")
+
+MSB_OK, MSB_EINVAL, MSB_ENOMEM, MSB_EDEVICE, MSB_ENOCONV, MSB_ENOTSPD, MSB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32, FP32_REFINED = 0, 1, 2
+_STATUS = {0: "MSB_OK", -1: "MSB_EINVAL", -2: "MSB_ENOMEM", -3: "MSB_EDEVICE", -4: "MSB_ENOCONV",
+           -5: "MSB_ENOTSPD", -6: "MSB_EUNSUPPORTED"}
+
+# every symbol include/msbfm.h declares
+EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "msb_plan_set_bonds",
+           "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl",
+           "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
+           "msb_last_error")
+
+
+class MsbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+                ("M", ctypes.c_int), ("alpha", ctypes.c_double), ("n_infl", ctypes.c_int),
+                ("infl", ctypes.POINTER(ctypes.c_double)), ("rho", ctypes.c_double),
+                ("batch", ctypes.c_int)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("graph_block", ctypes.c_int), ("reliable_update", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmsbfm.so and declare its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libmsbfm.so not built (expected at %s); run __graft_entry__.build() "
+                          "or python -m paper_2301_11828_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "msb_plan_create": ([ctypes.POINTER(_Desc), ctypes.POINTER(P)], I),
+        "msb_plan_destroy": ([P], None),
+        "msb_plan_set_constraints": ([P, P], I),
+        "msb_plan_set_bonds": ([P, P, I64], I),
+        "msb_crack_to_bonds": ([ctypes.POINTER(_Desc), P, I64, P, I64, ctypes.POINTER(I64)], I),
+        "msb_plan_set_infl": ([P, P, I, I], I),
+        "msb_apply": ([P, I, P, P, P], I),
+        "msb_apply_dinfl": ([P, I, P, P, P], I),
+        "msb_solve_static": ([P, I, P, P, P, ctypes.POINTER(_Opts), P, P], I),
+        "msb_vv_init": ([P, I, P, P, P, P], I),
+        "msb_vv_run": ([P, I, D, I64, P, P, P, P, P, P, I, P], I),
+        "msb_grad_infl": ([P, P, P, P, P], I),
+        "msb_plan_info": ([P, P, P, P], I),
+        "msb_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != MSB_OK:
+        raise MsbError(st, _lib.msb_last_error().decode())
+
+
+def _desc(n: Sequence[int], h: float, M: int, alpha: float, infl, rho: float, batch: int):
+    d = _Desc()
+    d.dim = len(n)
+    if d.dim not in (2, 3):
+        raise ValueError("grid must be 2D or 3D")
+    for a in range(3):
+        d.n[a] = int(n[a]) if a < len(n) else 1
+    d.h, d.M, d.alpha, d.rho, d.batch = float(h), int(M), float(alpha), float(rho), int(batch)
+    arr = np.ascontiguousarray(np.asarray(infl, dtype=np.float64))
+    d.n_infl = len(arr)
+    d.infl = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(arr) else None
+    return d, arr
+
+
+def crack_to_bonds(n: Sequence[int], h: float, M: int, segments) -> np.ndarray:
+    """Broken bonds of 2D crack segments [(x0, y0, x1, y1), ...] (host computation)."""
+    lib = load_library()
+    d, _keep = _desc(n, h, M, 1.0, (), 1.0, 1)
+    seg = np.ascontiguousarray(np.asarray(segments, dtype=np.float64).reshape(-1, 4))
+    nb = ctypes.c_int64(0)
+    st = lib.msb_crack_to_bonds(ctypes.byref(d), seg.ctypes.data, len(seg), None, 0, ctypes.byref(nb))
+    if st not in (MSB_OK, MSB_EINVAL) or (st == MSB_EINVAL and nb.value == 0):
+        _check(st)
+    out = np.zeros((max(nb.value, 1), 2), dtype=np.int64)
+    _check(lib.msb_crack_to_bonds(ctypes.byref(d), seg.ctypes.data, len(seg), out.ctypes.data,
+                                  nb.value, ctypes.byref(nb)))
+    return out[:nb.value]
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    outer_iters: int
+    inner_iters: int
+    rel_residual: float
+    seconds: float
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_PREC = {"fp64": FP64, "fp32": FP32, "fp32_refined": FP32_REFINED}
+
+
+class Plan:
+    """A grid, horizon and operator (A = A_hat + D^e + D^f, masked rows) on the current GPU.
+
+    n      -- (nx, ny) or (nx, ny, nz) nodes; node (i,j,k) at ((i+1/2)h, ...)
+    h, M   -- spacing and horizon in cells (delta = M h)
+    alpha  -- micromodulus scale (9E/(pi delta^3) in 2D, 12E/(pi delta^4) in 3D)
+    infl   -- optional coefficients a_k of omega(r) = sum_k a_k (r/delta)^k
+    batch  -- number of load cases sharing the plan; vectors are [batch, dim, N]
+    """
+
+    def __init__(self, n: Sequence[int], h: float, M: int, alpha: float, infl=(), rho: float = 1.0,
+                 batch: int = 1):
+        lib = load_library()
+        self.n = tuple(int(x) for x in n)
+        self.dim = len(self.n)
+        self.N = int(np.prod(self.n))
+        self.batch = int(batch)
+        self.M = int(M)
+        self.h = float(h)
+        self.n_infl = len(infl)
+        d, keep = _desc(self.n, h, M, alpha, infl, rho, batch)
+        self._ptr = ctypes.c_void_p()
+        _check(lib.msb_plan_create(ctypes.byref(d), ctypes.byref(self._ptr)))
+        del keep
+
+    def close(self):
+        if self._ptr:
+            _lib.msb_plan_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ configuration
+    @property
+    def padded_lengths(self):
+        L = (ctypes.c_int64 * 3)()
+        _check(_lib.msb_plan_info(self._ptr, L, None, None))
+        return tuple(L[:self.dim])
+
+    @property
+    def n_bonds(self) -> int:
+        nb = ctypes.c_int64()
+        _check(_lib.msb_plan_info(self._ptr, None, None, ctypes.byref(nb)))
+        return nb.value
+
+    def set_constraints(self, fixed: Optional[np.ndarray]):
+        if fixed is None:
+            _check(_lib.msb_plan_set_constraints(self._ptr, None))
+            return
+        f = np.ascontiguousarray(np.asarray(fixed).reshape(self.dim, self.N).astype(np.uint8))
+        _check(_lib.msb_plan_set_constraints(self._ptr, f.ctypes.data))
+
+    def set_bonds(self, pairs: Optional[np.ndarray]):
+        p = np.ascontiguousarray(np.asarray(pairs if pairs is not None else np.zeros((0, 2)),
+                                            dtype=np.int64).reshape(-1, 2))
+        _check(_lib.msb_plan_set_bonds(self._ptr, p.ctypes.data if len(p) else None, len(p)))
+
+    def set_infl(self, infl, per_case: bool = False):
+        a = np.ascontiguousarray(np.asarray(infl, dtype=np.float64))
+        k = a.shape[-1] if a.ndim else 0
+        _check(_lib.msb_plan_set_infl(self._ptr, a.ctypes.data, int(k), int(per_case)))
+        self.n_infl = int(k)
+
+    # ------------------------------------------------------------ tensors
+    def _vec(self, t, dtype=None, name="vector"):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError("%s must be %s" % (name, dtype))
+        if t.numel() != self.batch * self.dim * self.N:
+            raise ValueError("%s must hold batch*dim*N = %d values" % (name, self.batch * self.dim * self.N))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self, dtype=None):
+        torch = _torch()
+        return torch.empty((self.batch, self.dim, self.N), dtype=dtype or torch.float64, device="cuda")
+
+    # ------------------------------------------------------------ operations
+    def apply(self, u, out=None):
+        """f = A u on free DOFs, 0 on constrained ones (FP64 for float64, FP32 for float32)."""
+        torch = _torch()
+        prec = FP64 if u.dtype == torch.float64 else FP32
+        if out is None:
+            out = torch.empty_like(u)
+        _check(_lib.msb_apply(self._ptr, prec, self._vec(u, u.dtype, "u"), self._vec(out, u.dtype, "out"),
+                              _stream()))
+        return out
+
+    def apply_dinfl(self, k: int, u, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(u)
+        _check(_lib.msb_apply_dinfl(self._ptr, int(k), self._vec(u, torch.float64, "u"),
+                                    self._vec(out, torch.float64, "out"), _stream()))
+        return out
+
+    def solve(self, b, g=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
+              inner_tol: float = 0.0, graph_block: int = 0, reliable_update: int = 0, out=None,
+              check: bool = True):
+        """Static model: K u = b on free DOFs, u = g on constrained (K = -A).  Returns (u, infos)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(b)
+        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), int(reliable_update))
+        infos = (_Info * self.batch)()
+        gp = self._vec(g, torch.float64, "g") if g is not None else None
+        st = _lib.msb_solve_static(self._ptr, _PREC[precision], self._vec(b, torch.float64, "b"), gp,
+                                   self._vec(out, torch.float64, "u"), ctypes.byref(opts), infos, _stream())
+        res = [SolveInfo(i.status, i.outer_iters, i.inner_iters, i.rel_residual, i.seconds) for i in infos]
+        if check:
+            _check(st)
+        return out, res
+
+    def vv_init(self, u, b, a=None):
+        torch = _torch()
+        prec = FP64 if u.dtype == torch.float64 else FP32
+        if a is None:
+            a = torch.empty_like(u)
+        _check(_lib.msb_vv_init(self._ptr, prec, self._vec(u, u.dtype, "u"), self._vec(b, u.dtype, "b"),
+                                self._vec(a, u.dtype, "a"), _stream()))
+        return a
+
+    def vv_run(self, dt: float, nsteps: int, u, v, a, b, g=None, energy_every: int = 0):
+        """Advance u, v, a in place by nsteps of velocity Verlet; returns energies (numpy)."""
+        torch = _torch()
+        prec = FP64 if u.dtype == torch.float64 else FP32
+        ne = nsteps // energy_every if energy_every else 0
+        en = np.zeros(max(ne, 1), dtype=np.float64)
+        gp = self._vec(g, u.dtype, "g") if g is not None else None
+        _check(_lib.msb_vv_run(self._ptr, prec, float(dt), int(nsteps), self._vec(u, u.dtype, "u"),
+                               self._vec(v, u.dtype, "v"), self._vec(a, u.dtype, "a"),
+                               self._vec(b, u.dtype, "b"), gp, en.ctypes.data if ne else None,
+                               int(energy_every), _stream()))
+        return en[:ne]
+
+    def grad_infl(self, u, w) -> np.ndarray:
+        """dL/da_k = w . (A_k u)_F for every case: [batch, n_infl]."""
+        torch = _torch()
+        out = np.zeros((self.batch, self.n_infl), dtype=np.float64)
+        _check(_lib.msb_grad_infl(self._ptr, self._vec(u, torch.float64, "u"), self._vec(w, torch.float64, "w"),
+                                  out.ctypes.data, _stream()))
+        return out
+
+
+def make_solve_function():
+    """torch.autograd.Function for u = K(a)^{-1} b with the hand-written adjoint.
+
+    forward(plan, b, infl) -> u; backward: w = K^{-1} grad_u (K symmetric, same solve),
+    grad_b = w, grad_infl[b, k] = w . (A_k u)_F."""
+    torch = _torch()
+
+    class MSBFMSolve(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, plan, b, infl, precision="fp32_refined", tol=1e-10):
+            plan.set_infl(infl.detach().cpu().numpy(), per_case=(infl.dim() == 2))
+            u, _ = plan.solve(b.contiguous(), precision=precision, tol=tol)
+            ctx.plan, ctx.precision, ctx.tol = plan, precision, tol
+            ctx.per_case, ctx.infl_device = infl.dim() == 2, infl.device
+            ctx.save_for_backward(u)
+            return u
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            (u,) = ctx.saved_tensors
+            w, _ = ctx.plan.solve(grad_u.contiguous(), precision=ctx.precision, tol=ctx.tol)
+            ga = torch.from_numpy(ctx.plan.grad_infl(u, w))
+            if not ctx.per_case:
+                ga = ga.sum(0)          # one coefficient set shared by every case
+            return None, w, ga.to(ctx.infl_device), None, None
+
+    return MSBFMSolve

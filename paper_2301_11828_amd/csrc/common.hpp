@@ -1,0 +1,176 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/msbfm.h"
+
+namespace msb {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char *fmt, ...);
+
+#define MSB_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::msb::set_error("%s:%d %s failed: %s", __FILE__, __LINE__, #call,          \
+                             hipGetErrorString(e_));                                    \
+            return MSB_EDEVICE;                                                         \
+        }                                                                               \
+    } while (0)
+
+#define MSB_CHECK(cond, status, ...)                                                    \
+    do {                                                                                \
+        if (!(cond)) {                                                                  \
+            ::msb::set_error(__VA_ARGS__);                                              \
+            return (status);                                                            \
+        }                                                                               \
+    } while (0)
+
+#define MSB_TRY(expr)                                                                   \
+    do {                                                                                \
+        msb_status s_ = (expr);                                                         \
+        if (s_ != MSB_OK) return s_;                                                    \
+    } while (0)
+
+// ------------------------------------------------------------------ complex types
+template <typename T> struct cplx_of;
+template <> struct cplx_of<double> { using type = double2; };
+template <> struct cplx_of<float> { using type = float2; };
+template <typename T> using cplx_t = typename cplx_of<T>::type;
+
+// ------------------------------------------------------------------ FFT schedule
+constexpr int kMaxPasses = 16;
+
+// One transform axis: length L = product of radix[0..np), each radix in {2,3,4,5,8}.
+// Twiddle table tw[t] = exp(-2 pi i t / L), t < L (device, both precisions).
+struct FftAxis {
+    int L = 0;
+    int np = 0;
+    int radix[kMaxPasses] = {};
+    double2 *tw64 = nullptr;
+    float2 *tw32 = nullptr;
+};
+
+// Kernel-argument copy of an axis schedule (by value).
+struct FftSched {
+    int L;
+    int np;
+    int radix[kMaxPasses];
+};
+
+inline FftSched sched_of(const FftAxis &a) {
+    FftSched s;
+    s.L = a.L;
+    s.np = a.np;
+    for (int i = 0; i < kMaxPasses; ++i) s.radix[i] = a.radix[i];
+    return s;
+}
+
+template <typename T> inline const cplx_t<T> *tw_of(const FftAxis &a);
+template <> inline const double2 *tw_of<double>(const FftAxis &a) { return a.tw64; }
+template <> inline const float2 *tw_of<float>(const FftAxis &a) { return a.tw32; }
+
+// Factor L into the supported radices; returns false if L has another prime factor.
+bool factor_length(int L, std::vector<int> &radices);
+// Smallest L >= nmin whose prime factors are all in {2,3,5} (and even when even_only).
+int next_smooth(int nmin, bool even_only);
+
+// ------------------------------------------------------------------ operators
+// Device data of the operator A for one or more sets of influence coefficients,
+// stored as `count` back-to-back slots (slot = batch case when every case has its
+// own coefficients, else a single shared slot).
+struct DeviceOp {
+    int count = 0;
+    double *spec64 = nullptr;   // [count][ncomp][H][Ly][Lz] real spectra, scaled by 1/prod(L)
+    float *spec32 = nullptr;
+    double *de64 = nullptr;     // [count][ncomp][(M+1)^(2d)] incomplete-horizon diagonal table
+    float *de32 = nullptr;
+    double *w64 = nullptr;      // [count][ncomp][n_off] bond weights (broken-bond correction)
+    float *w32 = nullptr;
+};
+
+}  // namespace msb
+
+struct msb_plan_s {
+    // problem
+    int dim = 2;
+    int64_t n[3] = {1, 1, 1};
+    int64_t N = 0;              // nodes per case
+    double h = 1.0;
+    int M = 1;
+    double alpha = 0.0;
+    std::vector<double> infl;   // shared coefficients (n_infl), empty = omega 1
+    std::vector<double> infl_case;  // [B][n_infl] when per-case
+    int n_infl = 0;
+    bool per_case = false;
+    double rho = 1.0;
+    int B = 1;
+    int ncomp = 3;              // d(d+1)/2 block components: 2D xx,xy,yy; 3D xx,xy,xz,yy,yz,zz
+    int device = 0;
+
+    // FFT
+    int64_t L[3] = {1, 1, 1};
+    int64_t H = 1;              // L[0]/2 + 1 (half spectrum along x)
+    msb::FftAxis ax[3];
+    int rows_per_wg = 4;        // F: grid rows per workgroup in the x passes
+    int zlines_per_wg = 4;      // 3D: lines per workgroup in the y passes
+
+    // stencil (host)
+    int n_off = 0;
+    std::vector<int> off;       // [n_off][3]
+    int de_stride = 0;          // (M+1)^(2d)
+
+    // operators: op = A for the current coefficients (one slot, or B slots when
+    // per_case); dop[k] = derivative operator for omega = (r/delta)^k (built lazily)
+    msb::DeviceOp op;
+    std::vector<msb::DeviceOp> dop;
+
+    // constraints
+    uint8_t *fixed = nullptr;   // device [d][N] or null
+    int64_t n_fixed = 0;
+
+    // broken bonds (device), grouped by grid row (row = k*Ny + j)
+    int64_t n_pairs = 0;
+    int32_t *br_row_ptr = nullptr;   // [rows+1] -> range in br_node
+    int32_t *br_node_i = nullptr;    // [nbr] node id (within a case), sorted
+    int32_t *br_bond_ptr = nullptr;  // [nbr+1] -> range in br_q / br_off
+    int32_t *br_q = nullptr;         // [ndir] neighbour node id
+    int32_t *br_off = nullptr;       // [ndir] stencil offset id
+    int64_t n_br_nodes = 0;
+
+    // workspace (device)
+    void *T1 = nullptr;         // complex [B][d][Nz][H][Ny] (largest precision)
+    void *T2 = nullptr;         // 3D only: complex [B][d][H][Ly][Nz]
+    size_t T1_bytes = 0, T2_bytes = 0;
+    double *partials = nullptr; // reduction scratch
+    size_t n_partials = 0;
+    int *state = nullptr;       // small int state (per-case flags/counters)
+    double *dstate = nullptr;   // small double state
+    double *vec64 = nullptr;    // solver vectors FP64 [k][B*d*N]
+    float *vec32 = nullptr;     // solver vectors FP32
+    int n_vec64 = 0, n_vec32 = 0;
+    double *host_partials = nullptr;  // pinned host mirror for reductions
+
+    // cached graphs etc. live in the solver translation unit
+    void *solver_cache = nullptr;
+};
+
+namespace msb {
+
+int64_t rows_total(const msb_plan_s *p);   // Ny * Nz grid rows per case
+size_t spectrum_len(const msb_plan_s *p);  // H * Ly * Lz reals per component
+size_t de_len(const msb_plan_s *p);        // ncomp * (M+1)^(2d) per slot
+size_t w_len(const msb_plan_s *p);         // ncomp * n_off per slot
+
+msb_status alloc_operator(msb_plan_s *p, DeviceOp &op, int count);
+msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot);
+void free_operator(DeviceOp &op);
+void solver_cache_free(msb_plan_s *p);
+
+}  // namespace msb

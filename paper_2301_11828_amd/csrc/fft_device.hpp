@@ -1,0 +1,268 @@
+// Device-side batched complex FFT in LDS: mixed-radix Stockham autosort passes
+// (radices 2, 3, 4, 5, 8), ping-pong between two LDS buffers, natural order in and
+// out.  Used by every pass of the FFT product (Alg. 3 / Alg. 4 of the paper
+// evaluate the Toeplitz part A_hat u through FFT, Hadamard product, inverse FFT).
+//
+// Pass with radix R after Ns points have been combined (Ns = product of the
+// radices of the earlier passes): butterfly j of a signal reads x[j + m L/R],
+// m < R, twiddles input m by w^(k m) with w = exp(-2 pi i / (Ns R)), k = j mod Ns,
+// applies the length-R DFT and writes y[(j div Ns) Ns R + k + m Ns].  The twiddle
+// w^(k m) = exp(-2 pi i t / L) with t = k m L / (Ns R) < L is read from one table
+// per length, computed on the host with exact angle reduction.
+#pragma once
+
+#include "common.hpp"
+
+namespace msb {
+
+template <typename T2> __device__ __forceinline__ T2 c_make(double x, double y) {
+    T2 r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+
+template <typename T2> __device__ __forceinline__ T2 c_add(T2 a, T2 b) {
+    T2 r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <typename T2> __device__ __forceinline__ T2 c_sub(T2 a, T2 b) {
+    T2 r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+template <typename T2> __device__ __forceinline__ T2 c_mul(T2 a, T2 b) {
+    T2 r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// a * (s i), s = +1 or -1
+template <typename T2> __device__ __forceinline__ T2 c_muli(T2 a, int s) {
+    T2 r;
+    r.x = -s * a.y;
+    r.y = s * a.x;
+    return r;
+}
+template <typename T2> __device__ __forceinline__ T2 c_conj(T2 a) {
+    a.y = -a.y;
+    return a;
+}
+
+// Length-R DFT in registers; DIR = -1 forward (exp(-2 pi i ms/R)), +1 inverse.
+template <typename T, typename T2, int R, int DIR> struct Dft;
+
+template <typename T, typename T2, int DIR> struct Dft<T, T2, 2, DIR> {
+    __device__ __forceinline__ static void run(T2 *v) {
+        T2 a = v[0], b = v[1];
+        v[0] = c_add(a, b);
+        v[1] = c_sub(a, b);
+    }
+};
+
+template <typename T, typename T2, int DIR> struct Dft<T, T2, 3, DIR> {
+    __device__ __forceinline__ static void run(T2 *v) {
+        const T c = T(-0.5);
+        const T s = T(DIR) * T(0.86602540378443864676372317075294);   // forward: -sin(2 pi/3)
+        T2 t = c_add(v[1], v[2]);
+        T2 d = c_sub(v[1], v[2]);
+        T2 m;
+        m.x = v[0].x + c * t.x;
+        m.y = v[0].y + c * t.y;
+        v[0] = c_add(v[0], t);
+        // v1 = m + i s d ; v2 = m - i s d  (s carries the direction)
+        T2 isd;
+        isd.x = -s * d.y;
+        isd.y = s * d.x;
+        v[1] = c_add(m, isd);
+        v[2] = c_sub(m, isd);
+    }
+};
+
+template <typename T, typename T2, int DIR> struct Dft<T, T2, 4, DIR> {
+    __device__ __forceinline__ static void run(T2 *v) {
+        T2 t0 = c_add(v[0], v[2]);
+        T2 t1 = c_sub(v[0], v[2]);
+        T2 t2 = c_add(v[1], v[3]);
+        T2 t3 = c_sub(v[1], v[3]);
+        // forward: V1 = t1 - i t3, V3 = t1 + i t3
+        T2 it3 = c_muli(t3, DIR);  // DIR * i * t3
+        v[0] = c_add(t0, t2);
+        v[2] = c_sub(t0, t2);
+        v[1] = c_add(t1, it3);
+        v[3] = c_sub(t1, it3);
+    }
+};
+
+template <typename T, typename T2, int DIR> struct Dft<T, T2, 5, DIR> {
+    __device__ __forceinline__ static void run(T2 *v) {
+        const T c1 = T(0.30901699437494742410229341718282);    // cos(2 pi/5)
+        const T c2 = T(-0.80901699437494742410229341718282);   // cos(4 pi/5)
+        const T s1 = T(DIR) * T(0.95105651629515357211643933337938);   // forward: -sin(2 pi/5)
+        const T s2 = T(DIR) * T(0.58778525229247312916870595463907);   // forward: -sin(4 pi/5)
+        T2 t1 = c_add(v[1], v[4]);
+        T2 t2 = c_add(v[2], v[3]);
+        T2 d1 = c_sub(v[1], v[4]);
+        T2 d2 = c_sub(v[2], v[3]);
+        T2 a1, a2;
+        a1.x = v[0].x + c1 * t1.x + c2 * t2.x;
+        a1.y = v[0].y + c1 * t1.y + c2 * t2.y;
+        a2.x = v[0].x + c2 * t1.x + c1 * t2.x;
+        a2.y = v[0].y + c2 * t1.y + c1 * t2.y;
+        // b1 = s1 d1 + s2 d2 ; b2 = s2 d1 - s1 d2 ; V1 = a1 + i b1, V4 = a1 - i b1,
+        // V2 = a2 + i b2, V3 = a2 - i b2 (signs of s carry the direction)
+        T2 b1, b2;
+        b1.x = s1 * d1.x + s2 * d2.x;
+        b1.y = s1 * d1.y + s2 * d2.y;
+        b2.x = s2 * d1.x - s1 * d2.x;
+        b2.y = s2 * d1.y - s1 * d2.y;
+        v[0].x = v[0].x + t1.x + t2.x;
+        v[0].y = v[0].y + t1.y + t2.y;
+        v[1].x = a1.x - b1.y;
+        v[1].y = a1.y + b1.x;
+        v[4].x = a1.x + b1.y;
+        v[4].y = a1.y - b1.x;
+        v[2].x = a2.x - b2.y;
+        v[2].y = a2.y + b2.x;
+        v[3].x = a2.x + b2.y;
+        v[3].y = a2.y - b2.x;
+    }
+};
+
+template <typename T, typename T2, int DIR> struct Dft<T, T2, 8, DIR> {
+    __device__ __forceinline__ static void run(T2 *v) {
+        const T r = T(0.70710678118654752440084436210485);
+        // two radix-4 DFTs on even and odd samples, then combine with w8^m
+        T2 e[4] = {v[0], v[2], v[4], v[6]};
+        T2 o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<T, T2, 4, DIR>::run(e);
+        Dft<T, T2, 4, DIR>::run(o);
+        // w8 = exp(DIR * 2 pi i / 8): w^1 = r(1 + DIR i), w^2 = DIR i, w^3 = r(-1 + DIR i)
+        T2 o1, o2, o3;
+        o1.x = r * (o[1].x - T(DIR) * o[1].y);
+        o1.y = r * (o[1].y + T(DIR) * o[1].x);
+        o2 = c_muli(o[2], DIR);
+        o3.x = r * (-o[3].x - T(DIR) * o[3].y);
+        o3.y = r * (-o[3].y + T(DIR) * o[3].x);
+        v[0] = c_add(e[0], o[0]);
+        v[4] = c_sub(e[0], o[0]);
+        v[1] = c_add(e[1], o1);
+        v[5] = c_sub(e[1], o1);
+        v[2] = c_add(e[2], o2);
+        v[6] = c_sub(e[2], o2);
+        v[3] = c_add(e[3], o3);
+        v[7] = c_sub(e[3], o3);
+    }
+};
+
+// One Stockham pass over S signals of length L stored back to back.
+template <typename T, typename T2, int R, int DIR>
+__device__ __forceinline__ void stockham_pass(const T2 *__restrict__ in, T2 *__restrict__ out, int S,
+                                              int L, int Ns, const T2 *__restrict__ tw, int tid,
+                                              int nt) {
+    const int nb = L / R;
+    const int total = S * nb;
+    const int twstep = L / (Ns * R);
+    for (int t = tid; t < total; t += nt) {
+        const int s = t / nb;
+        const int j = t - s * nb;
+        const T2 *x = in + s * L;
+        T2 v[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = x[j + m * nb];
+        const int jq = j / Ns;
+        const int k = j - jq * Ns;
+        if (Ns > 1) {
+#pragma unroll
+            for (int m = 1; m < R; ++m) {
+                T2 w = tw[k * m * twstep];
+                if (DIR > 0) w.y = -w.y;
+                v[m] = c_mul(v[m], w);
+            }
+        }
+        Dft<T, T2, R, DIR>::run(v);
+        T2 *y = out + s * L + jq * Ns * R + k;
+#pragma unroll
+        for (int m = 0; m < R; ++m) y[m * Ns] = v[m];
+    }
+}
+
+// Full transform of S signals in LDS buffer a (scratch b); returns the buffer that
+// holds the result.  Every thread of the block must call it (it synchronises).
+template <typename T, typename T2, int DIR>
+__device__ T2 *fft_lds(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__restrict__ tw,
+                       int tid, int nt) {
+    int Ns = 1;
+    const int L = sc.L;
+    for (int ps = 0; ps < sc.np; ++ps) {
+        const int R = sc.radix[ps];
+        switch (R) {
+            case 2: stockham_pass<T, T2, 2, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
+            case 3: stockham_pass<T, T2, 3, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
+            case 4: stockham_pass<T, T2, 4, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
+            case 5: stockham_pass<T, T2, 5, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
+            default: stockham_pass<T, T2, 8, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
+        }
+        __syncthreads();
+        T2 *t = a;
+        a = b;
+        b = t;
+        Ns *= R;
+    }
+    return a;
+}
+
+// blockIdx -> logical tile so that the blocks resident on one XCD (hardware hands
+// block i to XCD i mod 8) work on one contiguous range of tiles and share L2 lines.
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+    const int nx = 8;
+    const int q = nblocks / nx, r = nblocks % nx;
+    const int x = bid % nx, local = bid / nx;
+    return x * q + (x < r ? x : r) + local;
+}
+
+// Block-wide sum of up to 4 FP64 values per thread in a fixed order (deterministic):
+// wave64 butterfly shuffles, then the waves' results added in wave order by thread 0.
+// red: LDS scratch of >= 4 * (blockDim/64) doubles.  Result valid in thread 0.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double *red, int tid, int nt) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = v[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        v[k] = x;
+    }
+    const int w = tid >> 6, nw = (nt + 63) >> 6;
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k * 16 + w] = v[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < nw; ++i) s += red[k * 16 + i];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Sum of n partials (fixed order) by a whole block; result broadcast to all threads.
+__device__ __forceinline__ double block_sum_partials(const double *__restrict__ p, int n,
+                                                     double *red, int tid, int nt) {
+    double v[1] = {0.0};
+    for (int i = tid; i < n; i += nt) v[0] += p[i];
+    block_sum<1>(v, red, tid, nt);
+    if (tid == 0) red[64] = v[0];
+    __syncthreads();
+    double s = red[64];
+    __syncthreads();
+    return s;
+}
+
+}  // namespace msb

@@ -1,0 +1,92 @@
+// Kernel arguments and launchers of the FFT product passes (A u = A_hat u + D^e u +
+// D^f u, masked on constrained DOFs).  Implemented in passes.hip.
+#pragma once
+
+#include "common.hpp"
+
+namespace msb {
+
+// What the x-forward pass does to its input rows before transforming them.
+enum Prologue : int {
+    PRO_NONE = 0,   // transform u as given
+    PRO_CG_P = 1,   // p <- r + beta p (beta from partial sums), store p, transform p
+    PRO_VV_U = 2,   // u <- u + dt v + dt^2 a / 2, u_C <- g_C, store u, transform u
+};
+
+// What the x-inverse pass does with f = A u after the corrections.
+enum Epilogue : int {
+    EPI_APPLY = 0,  // out = sign * f, 0 on constrained DOFs
+    EPI_CG_Q = 1,   // out = q = -f (K p), 0 on constrained; partial p.q
+    EPI_RESID = 2,  // out = rhs + f, 0 on constrained; partial out.out
+    EPI_VV = 3,     // a' = (f + b)/rho; v += dt (a + a')/2; a = a'; energy partials
+    EPI_DOT = 4,    // no output; partial w.f over free DOFs
+};
+
+template <typename T> struct PassArgs {
+    // geometry
+    int d, B, Nx, Ny, Nz, M;
+    int rows;            // Ny*Nz per case
+    int H;               // Lx/2 + 1
+    int Ly, Lz;
+    int F;               // rows per workgroup (x passes)
+    int Fl;              // lines per workgroup (line passes)
+    int N;               // nodes per case
+    FftSched sx, sy, sz;
+    const cplx_t<T> *twx, *twy, *twz;
+    cplx_t<T> *T1, *T2;
+    // operator
+    const T *spec;       // [slots][ncomp][H][Ly][Lz]
+    size_t spec_slot;    // stride between slots (0 = shared by all cases)
+    const T *de;         // [slots][ncomp][(M+1)^(2d)]
+    size_t de_slot;
+    const T *w;          // [slots][ncomp][n_off]
+    size_t w_slot;
+    int de_stride;       // (M+1)^(2d)
+    int n_off;
+    // constraints and bonds
+    const uint8_t *fixed;          // [d][N] or null
+    const int32_t *br_row_ptr;     // [rows+1] or null
+    const int32_t *br_node_i;
+    const int32_t *br_bond_ptr;
+    const int32_t *br_q;
+    const int32_t *br_off;
+};
+
+// Per-call data of the prologue/epilogue.
+template <typename T> struct EndArgs {
+    int pro, epi;
+    // prologue
+    T *pio;              // PRO_CG_P: p (in/out); PRO_VV_U: u (in/out)
+    const T *pr;         // PRO_CG_P: r;          PRO_VV_U: v
+    const T *pa;         // PRO_VV_U: a
+    const T *pg;         // PRO_VV_U: g or null
+    const double *beta_part;   // PRO_CG_P: partial sums rr_new [B][nbeta], rr_old [B][nbeta]
+    const double *beta_part_old;
+    int nbeta;
+    const int *case_done;      // [B] per-case stop flags (skip work) or null
+    int *done_rw;              // PRO_CG_P: flags written when a case converges
+    const double *thresh;      // PRO_CG_P: per-case stop threshold on r.r (or null)
+    double dt;
+    // epilogue
+    const T *uin;        // the vector that was transformed (for D^e, D^f, dots)
+    T *out;              // EPI_APPLY/CG_Q/RESID output
+    const T *rhs;        // EPI_RESID rhs; EPI_VV b; EPI_DOT w
+    T *ev;               // EPI_VV: v
+    T *ea;               // EPI_VV: a
+    double sign;         // EPI_APPLY sign
+    double rho;
+    int energy;          // EPI_VV: accumulate energy partials
+    double *part;        // partial sums [K][B*tiles]
+};
+
+template <typename T>
+msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t s);
+
+template <typename T>
+PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op);
+
+// tiles of the x passes per case (partial-sum slots per case)
+int x_tiles_per_case(const msb_plan_s *p, int F);
+int rows_per_wg_for(const msb_plan_s *p, size_t elem_bytes);
+
+}  // namespace msb

@@ -1,0 +1,662 @@
+// Plan creation: everything the FFT product needs that does not change between
+// products (the paper's "matrix assembly" phase, Sec. 5.1):
+//   * the stencil of bond weights W^{ab}(o) of eq. (frb:e1) / (thm:e2), with the
+//     partial-volume factor of eq. (fac:e1) and an optional radial influence;
+//   * the kernel tensor K (centre = minus the sum of all bond weights, eq. (frb:e4))
+//     wrapped into the generating array G (Sec. 3.3 for 2D, Sec. 4 for 3D) and its
+//     spectrum, which is real because K is even in every component;
+//   * the incomplete-horizon diagonal D^e of eq. (mat:se) as a table indexed by the
+//     node's clamped distances to the grid faces;
+//   * the broken-bond lists of eq. (df), grouped per grid row;
+//   * the per-DOF constraint mask of Sec. 3.4 / Remark 2;
+//   * FFT schedules and twiddles, and device workspace.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "common.hpp"
+
+namespace msb {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+// ------------------------------------------------------------------ lengths
+bool factor_length(int L, std::vector<int> &radices) {
+    radices.clear();
+    int n = L;
+    int c8 = 0, c4 = 0, c2 = 0, c3 = 0, c5 = 0;
+    while (n % 2 == 0) { n /= 2; ++c2; }
+    while (n % 3 == 0) { n /= 3; ++c3; }
+    while (n % 5 == 0) { n /= 5; ++c5; }
+    if (n != 1) return false;
+    c8 = c2 / 3;
+    c2 -= 3 * c8;
+    c4 = c2 / 2;
+    c2 -= 2 * c4;
+    // larger radices first: fewer LDS round trips
+    for (int i = 0; i < c8; ++i) radices.push_back(8);
+    for (int i = 0; i < c4; ++i) radices.push_back(4);
+    for (int i = 0; i < c5; ++i) radices.push_back(5);
+    for (int i = 0; i < c3; ++i) radices.push_back(3);
+    for (int i = 0; i < c2; ++i) radices.push_back(2);
+    if (radices.empty()) radices.push_back(1);
+    return true;
+}
+
+int next_smooth(int nmin, bool even_only) {
+    for (int L = std::max(nmin, 1);; ++L) {
+        if (even_only && (L & 1) && L > 1) continue;
+        int n = L;
+        for (int p : {2, 3, 5})
+            while (n % p == 0) n /= p;
+        if (n == 1) return L;
+    }
+}
+
+int64_t rows_total(const msb_plan_s *p) { return p->n[1] * p->n[2]; }
+
+static int comp_index(int a, int b, int d) {
+    if (a > b) std::swap(a, b);
+    if (d == 2) return a == 0 ? b : 2;                       // xx xy yy
+    static const int t[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};  // xx xy xz yy yz zz
+    return t[a][b];
+}
+
+size_t spectrum_len(const msb_plan_s *p) { return (size_t)p->H * p->L[1] * p->L[2]; }
+
+// cos/sin(2 pi t / L), t in [0, L), long double, argument reduced to the first octant.
+static void unit_circle(int L, std::vector<long double> &c, std::vector<long double> &s) {
+    c.resize(L);
+    s.resize(L);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int t = 0; t < L; ++t) {
+        // angle = 2 pi t / L; reduce with exact integer arithmetic on 8t vs L
+        long long t8 = 8LL * t;
+        int oct = (int)(t8 / L);              // octant 0..7
+        long long rem = t8 - (long long)oct * L;  // in [0, L)
+        long double th = pi / 4 * (long double)rem / (long double)L;  // in [0, pi/4)
+        long double cs = cosl(th), sn = sinl(th);
+        long double cv = 0, sv = 0;
+        switch (oct) {   // angle = oct*pi/4 + th
+            case 0: cv = cs; sv = sn; break;
+            case 1: { long double a = pi / 4 - th; cv = sinl(a); sv = cosl(a); break; }
+            case 2: cv = -sn; sv = cs; break;
+            case 3: { long double a = pi / 4 - th; cv = -cosl(a); sv = sinl(a); break; }
+            case 4: cv = -cs; sv = -sn; break;
+            case 5: { long double a = pi / 4 - th; cv = -sinl(a); sv = -cosl(a); break; }
+            case 6: cv = sn; sv = -cs; break;
+            default: { long double a = pi / 4 - th; cv = cosl(a); sv = -sinl(a); break; }
+        }
+        c[t] = cv;
+        s[t] = sv;
+    }
+}
+
+static msb_status make_axis(int L, FftAxis &ax) {
+    std::vector<int> r;
+    MSB_CHECK(factor_length(L, r), MSB_EINVAL, "FFT length %d is not 5-smooth", L);
+    MSB_CHECK((int)r.size() <= kMaxPasses, MSB_EINVAL, "FFT length %d too long", L);
+    ax.L = L;
+    ax.np = (L == 1) ? 0 : (int)r.size();
+    for (int i = 0; i < ax.np; ++i) ax.radix[i] = r[i];
+    std::vector<long double> c, s;
+    unit_circle(L, c, s);
+    std::vector<double2> t64(L);
+    std::vector<float2> t32(L);
+    for (int t = 0; t < L; ++t) {
+        t64[t].x = (double)c[t];
+        t64[t].y = -(double)s[t];
+        t32[t].x = (float)c[t];
+        t32[t].y = -(float)s[t];
+    }
+    MSB_HIP(hipMalloc(&ax.tw64, sizeof(double2) * L));
+    MSB_HIP(hipMalloc(&ax.tw32, sizeof(float2) * L));
+    MSB_HIP(hipMemcpy(ax.tw64, t64.data(), sizeof(double2) * L, hipMemcpyHostToDevice));
+    MSB_HIP(hipMemcpy(ax.tw32, t32.data(), sizeof(float2) * L, hipMemcpyHostToDevice));
+    return MSB_OK;
+}
+
+// ------------------------------------------------------------------ stencil
+// Offsets o with 0 < |o|^2 <= M^2 (horizon membership decided on integers, delta = M h).
+static void build_offsets(msb_plan_s *p) {
+    const int M = p->M;
+    const int Mz = p->dim == 3 ? M : 0;
+    p->off.clear();
+    for (int oz = -Mz; oz <= Mz; ++oz)
+        for (int oy = -M; oy <= M; ++oy)
+            for (int ox = -M; ox <= M; ++ox) {
+                int s2 = ox * ox + oy * oy + oz * oz;
+                if (s2 == 0 || s2 > M * M) continue;
+                p->off.push_back(ox);
+                p->off.push_back(oy);
+                p->off.push_back(oz);
+            }
+    p->n_off = (int)p->off.size() / 3;
+}
+
+// W^{c}(o) for every offset (index units of eq. (frb:e1)/(thm:e2)):
+//   alpha * omega(|o|/M) * lambda(|o|) * h^(d-1) * o_a o_b / |o|^3,
+//   lambda = 1 for |o|^2 <= M^2 - M (|xi| <= delta - h/2), else M + 1/2 - |o| (eq. (fac:e1)).
+static void bond_weights(const msb_plan_s *p, const std::vector<double> &infl,
+                         std::vector<long double> &W) {
+    const int d = p->dim, M = p->M, nc = p->ncomp;
+    W.assign((size_t)nc * p->n_off, 0.0L);
+    long double hp = 1.0L;
+    for (int a = 0; a < d - 1; ++a) hp *= p->h;
+    for (int i = 0; i < p->n_off; ++i) {
+        const int *o = &p->off[3 * i];
+        long long s2 = (long long)o[0] * o[0] + (long long)o[1] * o[1] + (long long)o[2] * o[2];
+        long double r = sqrtl((long double)s2);
+        long double lam = (s2 <= (long long)M * M - M) ? 1.0L : (M + 0.5L - r);
+        long double om = 1.0L;
+        if (!infl.empty()) {
+            om = 0.0L;
+            long double x = r / M, xp = 1.0L;
+            for (size_t k = 0; k < infl.size(); ++k) {
+                om += (long double)infl[k] * xp;
+                xp *= x;
+            }
+        }
+        long double c = (long double)p->alpha * om * lam * hp / (r * r * r);
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b)
+                W[(size_t)comp_index(a, b, d) * p->n_off + i] = c * (long double)o[a] * o[b];
+    }
+}
+
+// Spectrum of the generating array, component by component (Sec. 3.3 / Sec. 4):
+// G[o mod L] = K(o), so G_hat(k) = sum_o K(o) exp(-2 pi i k.o/L).  K^{ab} is even
+// in every axis for a == b and odd in axes a, b (even in the third) otherwise, so
+// G_hat = sign * sum_o K(o) prod_axis phi_axis(2 pi k o / L) with phi = cos on even
+// axes, sin on odd axes and sign = -1 for a != b: real.  Evaluated axis by axis.
+// Output layout [comp][kx < H][ky < Ly][kz < Lz], scaled by 1/(Lx Ly Lz).
+static void build_spectrum(const msb_plan_s *p, const std::vector<long double> &W,
+                           std::vector<double> &spec) {
+    const int d = p->dim, M = p->M, nc = p->ncomp;
+    const int Bx = 2 * M + 1, By = 2 * M + 1, Bz = d == 3 ? 2 * M + 1 : 1;
+    const int Mz = d == 3 ? M : 0;
+    const int H = (int)p->H, Ly = (int)p->L[1], Lz = (int)p->L[2], Lx = (int)p->L[0];
+    std::vector<long double> cx, sx, cy, sy, cz, sz;
+    unit_circle(Lx, cx, sx);
+    unit_circle(Ly, cy, sy);
+    unit_circle(Lz, cz, sz);
+    const long double scale = 1.0L / ((long double)Lx * Ly * Lz);
+    spec.assign((size_t)nc * H * Ly * Lz, 0.0);
+
+    std::vector<long double> K((size_t)Bz * By * Bx);
+    std::vector<long double> S1((size_t)Bz * By * H), S2((size_t)Bz * H * Ly);
+    for (int a = 0; a < d; ++a)
+        for (int b = a; b < d; ++b) {
+            const int c = comp_index(a, b, d);
+            std::fill(K.begin(), K.end(), 0.0L);
+            long double centre = 0.0L;
+            for (int i = 0; i < p->n_off; ++i) {
+                const int *o = &p->off[3 * i];
+                long double w = W[(size_t)c * p->n_off + i];
+                K[((size_t)(o[2] + Mz) * By + (o[1] + M)) * Bx + (o[0] + M)] = w;
+                centre -= w;
+            }
+            K[((size_t)Mz * By + M) * Bx + M] = centre;   // eq. (frb:e4)
+            const bool oddx = (a != b) && (a == 0 || b == 0);
+            const bool oddy = (a != b) && (a == 1 || b == 1);
+            const bool oddz = (a != b) && (a == 2 || b == 2);
+            const long double sign = (a != b) ? -1.0L : 1.0L;
+            // stage x
+            for (int z = 0; z < Bz; ++z)
+                for (int y = 0; y < By; ++y)
+                    for (int kx = 0; kx < H; ++kx) {
+                        long double acc = 0.0L;
+                        for (int x = 0; x < Bx; ++x) {
+                            long long t = ((long long)kx * (x - M)) % Lx;
+                            if (t < 0) t += Lx;
+                            acc += K[((size_t)z * By + y) * Bx + x] * (oddx ? sx[t] : cx[t]);
+                        }
+                        S1[((size_t)z * By + y) * H + kx] = acc;
+                    }
+            // stage y
+            for (int z = 0; z < Bz; ++z)
+                for (int kx = 0; kx < H; ++kx)
+                    for (int ky = 0; ky < Ly; ++ky) {
+                        long double acc = 0.0L;
+                        for (int y = 0; y < By; ++y) {
+                            long long t = ((long long)ky * (y - M)) % Ly;
+                            if (t < 0) t += Ly;
+                            acc += S1[((size_t)z * By + y) * H + kx] * (oddy ? sy[t] : cy[t]);
+                        }
+                        S2[((size_t)z * H + kx) * Ly + ky] = acc;
+                    }
+            // stage z
+            double *out = spec.data() + (size_t)c * H * Ly * Lz;
+            for (int kx = 0; kx < H; ++kx)
+                for (int ky = 0; ky < Ly; ++ky)
+                    for (int kz = 0; kz < Lz; ++kz) {
+                        long double acc = 0.0L;
+                        for (int z = 0; z < Bz; ++z) {
+                            long long t = ((long long)kz * (z - Mz)) % Lz;
+                            if (t < 0) t += Lz;
+                            acc += S2[((size_t)z * H + kx) * Ly + ky] * (oddz ? sz[t] : cz[t]);
+                        }
+                        out[((size_t)kx * Ly + ky) * Lz + kz] = (double)(sign * acc * scale);
+                    }
+        }
+}
+
+// D^e table (eq. (mat:se)): for a node whose clamped distances (in nodes, capped at
+// M) to the low/high faces of each axis are (lo_a, hi_a), the sum of the bond
+// weights of the offsets that leave the grid.  Index: digits (lo_x, hi_x, lo_y,
+// hi_y[, lo_z, hi_z]) in base M+1, first digit most significant.
+static void build_de_table(const msb_plan_s *p, const std::vector<long double> &W,
+                           std::vector<double> &de) {
+    const int d = p->dim, M = p->M, nc = p->ncomp, nd = 2 * d;
+    const int S = p->de_stride;
+    de.assign((size_t)nc * S, 0.0);
+    std::vector<int> dig(nd);
+    for (int idx = 0; idx < S; ++idx) {
+        int t = idx;
+        for (int q = nd - 1; q >= 0; --q) {
+            dig[q] = t % (M + 1);
+            t /= (M + 1);
+        }
+        std::vector<long double> acc(nc, 0.0L);
+        for (int i = 0; i < p->n_off; ++i) {
+            const int *o = &p->off[3 * i];
+            bool out = false;
+            for (int a = 0; a < d; ++a)
+                if (o[a] < -dig[2 * a] || o[a] > dig[2 * a + 1]) out = true;
+            if (!out) continue;
+            for (int c = 0; c < nc; ++c) acc[c] += W[(size_t)c * p->n_off + i];
+        }
+        for (int c = 0; c < nc; ++c) de[(size_t)c * S + idx] = (double)acc[c];
+    }
+}
+
+template <typename T> static msb_status upload(T **dst, const std::vector<T> &v) {
+    if (*dst) { hipFree(*dst); *dst = nullptr; }
+    if (v.empty()) return MSB_OK;
+    MSB_HIP(hipMalloc(dst, sizeof(T) * v.size()));
+    MSB_HIP(hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return MSB_OK;
+}
+
+size_t de_len(const msb_plan_s *p) { return (size_t)p->ncomp * p->de_stride; }
+size_t w_len(const msb_plan_s *p) { return (size_t)p->ncomp * p->n_off; }
+
+msb_status alloc_operator(msb_plan_s *p, DeviceOp &op, int count) {
+    free_operator(op);
+    const size_t ns = (size_t)p->ncomp * spectrum_len(p) * count;
+    const size_t nd = de_len(p) * count, nw = w_len(p) * count;
+    op.count = count;
+    MSB_HIP(hipMalloc(&op.spec64, sizeof(double) * ns));
+    MSB_HIP(hipMalloc(&op.spec32, sizeof(float) * ns));
+    MSB_HIP(hipMalloc(&op.de64, sizeof(double) * nd));
+    MSB_HIP(hipMalloc(&op.de32, sizeof(float) * nd));
+    MSB_HIP(hipMalloc(&op.w64, sizeof(double) * nw));
+    MSB_HIP(hipMalloc(&op.w32, sizeof(float) * nw));
+    return MSB_OK;
+}
+
+template <typename T> static msb_status put(T *dst, const std::vector<double> &v) {
+    std::vector<T> t(v.begin(), v.end());
+    MSB_HIP(hipMemcpy(dst, t.data(), sizeof(T) * t.size(), hipMemcpyHostToDevice));
+    return MSB_OK;
+}
+
+// Fill one slot of an operator for the given influence coefficients.
+msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot) {
+    std::vector<long double> W;
+    bond_weights(p, infl, W);
+    std::vector<double> spec, de;
+    build_spectrum(p, W, spec);
+    build_de_table(p, W, de);
+    std::vector<double> w64(W.begin(), W.end());
+    const size_t ns = (size_t)p->ncomp * spectrum_len(p), nd = de_len(p), nw = w_len(p);
+    MSB_TRY(put(op.spec64 + ns * slot, spec));
+    MSB_TRY(put(op.spec32 + ns * slot, spec));
+    MSB_TRY(put(op.de64 + nd * slot, de));
+    MSB_TRY(put(op.de32 + nd * slot, de));
+    MSB_TRY(put(op.w64 + nw * slot, w64));
+    MSB_TRY(put(op.w32 + nw * slot, w64));
+    return MSB_OK;
+}
+
+void free_operator(DeviceOp &op) {
+    void *b[] = {op.spec64, op.spec32, op.de64, op.de32, op.w64, op.w32};
+    for (void *x : b)
+        if (x) hipFree(x);
+    op = DeviceOp();
+}
+
+static msb_status validate_desc(const msb_problem_desc *d) {
+    MSB_CHECK(d, MSB_EINVAL, "null problem description");
+    MSB_CHECK(d->dim == 2 || d->dim == 3, MSB_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
+    for (int a = 0; a < d->dim; ++a)
+        MSB_CHECK(d->n[a] >= 1 && d->n[a] <= (1 << 20), MSB_EINVAL, "n[%d] = %lld out of range", a,
+                  (long long)d->n[a]);
+    MSB_CHECK(std::isfinite(d->h) && d->h > 0, MSB_EINVAL, "h must be finite and > 0");
+    MSB_CHECK(d->M >= 1 && d->M <= 32, MSB_EINVAL, "M must be in [1, 32] (got %d)", d->M);
+    MSB_CHECK(d->dim == 2 || d->M <= 10, MSB_EUNSUPPORTED, "3D supports M <= 10 (got %d)", d->M);
+    MSB_CHECK(std::isfinite(d->alpha), MSB_EINVAL, "alpha must be finite");
+    MSB_CHECK(d->n_infl >= 0 && d->n_infl <= 8, MSB_EINVAL, "n_infl must be in [0, 8]");
+    MSB_CHECK(d->n_infl == 0 || d->infl, MSB_EINVAL, "infl is null but n_infl > 0");
+    for (int k = 0; k < d->n_infl; ++k)
+        MSB_CHECK(std::isfinite(d->infl[k]), MSB_EINVAL, "infl[%d] not finite", k);
+    MSB_CHECK(std::isfinite(d->rho) && d->rho > 0, MSB_EINVAL, "rho must be finite and > 0");
+    MSB_CHECK(d->batch >= 1 && d->batch <= 4096, MSB_EINVAL, "batch must be in [1, 4096]");
+    int64_t N = d->n[0] * d->n[1] * (d->dim == 3 ? d->n[2] : 1);
+    MSB_CHECK(N * d->dim * (int64_t)d->batch < (int64_t(1) << 31), MSB_EUNSUPPORTED,
+              "B*d*N must stay below 2^31");
+    return MSB_OK;
+}
+
+}  // namespace msb
+
+using namespace msb;
+
+extern "C" const char *msb_last_error(void) { return g_err.c_str(); }
+
+static msb_status plan_alloc_workspace(msb_plan_s *p) {
+    const int d = p->dim;
+    const size_t c16 = sizeof(double2);
+    p->T1_bytes = (size_t)p->B * d * p->n[2] * p->H * p->n[1] * c16;
+    MSB_HIP(hipMalloc(&p->T1, p->T1_bytes));
+    if (d == 3) {
+        p->T2_bytes = (size_t)p->B * d * p->H * p->L[1] * p->n[2] * c16;
+        MSB_HIP(hipMalloc(&p->T2, p->T2_bytes));
+    }
+    p->n_partials = (size_t)16 * 4096 + (size_t)p->B * 8192;
+    MSB_HIP(hipMalloc(&p->partials, sizeof(double) * p->n_partials));
+    MSB_HIP(hipMalloc(&p->state, sizeof(int) * (64 + 8 * (size_t)p->B)));
+    MSB_HIP(hipMalloc(&p->dstate, sizeof(double) * (64 + 16 * (size_t)p->B)));
+    MSB_HIP(hipMemset(p->state, 0, sizeof(int) * (64 + 8 * (size_t)p->B)));
+    MSB_HIP(hipHostMalloc(&p->host_partials, sizeof(double) * (64 + 16 * (size_t)p->B)));
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_plan_create(const msb_problem_desc *desc, msb_plan *out) {
+    MSB_CHECK(out, MSB_EINVAL, "null output pointer");
+    *out = nullptr;
+    MSB_TRY(validate_desc(desc));
+    msb_plan_s *p = new (std::nothrow) msb_plan_s();
+    MSB_CHECK(p, MSB_ENOMEM, "host allocation failed");
+    hipGetDevice(&p->device);
+    p->dim = desc->dim;
+    p->n[0] = desc->n[0];
+    p->n[1] = desc->n[1];
+    p->n[2] = desc->dim == 3 ? desc->n[2] : 1;
+    p->N = p->n[0] * p->n[1] * p->n[2];
+    p->h = desc->h;
+    p->M = desc->M;
+    p->alpha = desc->alpha;
+    p->n_infl = desc->n_infl;
+    p->infl.assign(desc->infl, desc->infl + desc->n_infl);
+    p->rho = desc->rho;
+    p->B = desc->batch;
+    p->ncomp = desc->dim == 2 ? 3 : 6;
+
+    // padded lengths: any L >= N + M gives the exact linear product (support +-M)
+    for (int a = 0; a < 3; ++a) {
+        if (a < p->dim) p->L[a] = next_smooth((int)(p->n[a] + p->M), false);
+        else p->L[a] = 1;
+    }
+    p->H = p->L[0] / 2 + 1;
+    p->de_stride = 1;
+    for (int q = 0; q < 2 * p->dim; ++q) p->de_stride *= (p->M + 1);
+
+    msb_status st = MSB_OK;
+    for (int a = 0; a < 3 && st == MSB_OK; ++a) st = make_axis((int)p->L[a], p->ax[a]);
+    if (st == MSB_OK) {
+        build_offsets(p);
+        st = alloc_operator(p, p->op, 1);
+        if (st == MSB_OK) st = fill_operator(p, p->infl, p->op, 0);
+    }
+    if (st == MSB_OK) st = plan_alloc_workspace(p);
+    // rows per workgroup of the x passes: keep two LDS buffers within 64 KiB (FP64)
+    {
+        const int d = p->dim;
+        int F = 16;
+        while (F > 1 && (size_t)2 * ((d * F + 1) / 2) * p->L[0] * sizeof(double2) > 64 * 1024) F /= 2;
+        p->rows_per_wg = F;
+    }
+    if (st != MSB_OK) {
+        msb_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return MSB_OK;
+}
+
+extern "C" void msb_plan_destroy(msb_plan p) {
+    if (!p) return;
+    hipDeviceSynchronize();
+    for (int a = 0; a < 3; ++a) {
+        if (p->ax[a].tw64) hipFree(p->ax[a].tw64);
+        if (p->ax[a].tw32) hipFree(p->ax[a].tw32);
+    }
+    free_operator(p->op);
+    for (auto &o : p->dop) free_operator(o);
+    void *bufs[] = {p->fixed, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off,
+                    p->T1, p->T2, p->partials, p->state, p->dstate, p->vec64, p->vec32};
+    for (void *b : bufs)
+        if (b) hipFree(b);
+    if (p->host_partials) hipHostFree(p->host_partials);
+    solver_cache_free(p);
+    delete p;
+}
+
+extern "C" msb_status msb_plan_info(msb_plan p, int64_t *L, int64_t *N, int64_t *n_bonds) {
+    MSB_CHECK(p, MSB_EINVAL, "null plan");
+    if (L)
+        for (int a = 0; a < 3; ++a) L[a] = p->L[a];
+    if (N) *N = p->N;
+    if (n_bonds) *n_bonds = p->n_pairs;
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_plan_set_constraints(msb_plan p, const uint8_t *fixed) {
+    MSB_CHECK(p, MSB_EINVAL, "null plan");
+    const size_t n = (size_t)p->dim * p->N;
+    if (!fixed) {
+        if (p->fixed) hipFree(p->fixed);
+        p->fixed = nullptr;
+        p->n_fixed = 0;
+        return MSB_OK;
+    }
+    std::vector<uint8_t> v(fixed, fixed + n);
+    int64_t cnt = 0;
+    for (auto &x : v) {
+        x = x ? 1 : 0;
+        cnt += x;
+    }
+    if (!p->fixed) MSB_HIP(hipMalloc(&p->fixed, n));
+    MSB_HIP(hipMemcpy(p->fixed, v.data(), n, hipMemcpyHostToDevice));
+    p->n_fixed = cnt;
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_plan_set_bonds(msb_plan p, const int64_t *pairs, int64_t nb) {
+    MSB_CHECK(p, MSB_EINVAL, "null plan");
+    MSB_CHECK(nb >= 0, MSB_EINVAL, "negative bond count");
+    MSB_CHECK(nb == 0 || pairs, MSB_EINVAL, "null bond list");
+    const int d = p->dim, M = p->M, B = 2 * M + 1;
+    const int64_t nx = p->n[0], ny = p->n[1];
+    // offset -> stencil id lookup
+    std::vector<int> lut((size_t)B * B * B, -1);
+    for (int i = 0; i < p->n_off; ++i) {
+        const int *o = &p->off[3 * i];
+        lut[((size_t)(o[2] + M) * B + (o[1] + M)) * B + (o[0] + M)] = i;
+    }
+    struct Dir { int64_t p, q; int off; };
+    std::vector<Dir> dir;
+    dir.reserve(2 * nb);
+    for (int64_t e = 0; e < nb; ++e) {
+        int64_t a = pairs[2 * e], b = pairs[2 * e + 1];
+        MSB_CHECK(a >= 0 && a < p->N && b >= 0 && b < p->N && a != b, MSB_EINVAL,
+                  "bond %lld: node ids (%lld, %lld) invalid", (long long)e, (long long)a, (long long)b);
+        int64_t ia[3] = {a % nx, (a / nx) % ny, a / (nx * ny)};
+        int64_t ib[3] = {b % nx, (b / nx) % ny, b / (nx * ny)};
+        int o[3] = {0, 0, 0};
+        int64_t s2 = 0;
+        for (int c = 0; c < d; ++c) {
+            int64_t t = ib[c] - ia[c];
+            MSB_CHECK(t >= -M && t <= M, MSB_EINVAL, "bond %lld outside the horizon", (long long)e);
+            o[c] = (int)t;
+            s2 += t * t;
+        }
+        MSB_CHECK(s2 <= (int64_t)M * M, MSB_EINVAL, "bond %lld outside the horizon", (long long)e);
+        int id = lut[((size_t)(o[2] + M) * B + (o[1] + M)) * B + (o[0] + M)];
+        int idn = lut[((size_t)(-o[2] + M) * B + (-o[1] + M)) * B + (-o[0] + M)];
+        dir.push_back({a, b, id});
+        dir.push_back({b, a, idn});
+    }
+    std::sort(dir.begin(), dir.end(), [](const Dir &x, const Dir &y) {
+        return x.p != y.p ? x.p < y.p : x.q < y.q;
+    });
+    for (size_t i = 1; i < dir.size(); ++i)
+        MSB_CHECK(!(dir[i].p == dir[i - 1].p && dir[i].q == dir[i - 1].q), MSB_EINVAL,
+                  "duplicate bond (%lld, %lld)", (long long)dir[i].p, (long long)dir[i].q);
+
+    const int64_t rows = rows_total(p);
+    std::vector<int32_t> row_ptr(rows + 1, 0), node_i, bond_ptr, q, off;
+    for (size_t i = 0; i < dir.size();) {
+        size_t j = i;
+        while (j < dir.size() && dir[j].p == dir[i].p) ++j;
+        int64_t node = dir[i].p;
+        row_ptr[node / nx + 1] += 1;
+        node_i.push_back((int32_t)node);
+        bond_ptr.push_back((int32_t)q.size());
+        for (size_t k = i; k < j; ++k) {
+            q.push_back((int32_t)dir[k].q);
+            off.push_back(dir[k].off);
+        }
+        i = j;
+    }
+    bond_ptr.push_back((int32_t)q.size());
+    for (int64_t r = 0; r < rows; ++r) row_ptr[r + 1] += row_ptr[r];
+
+    MSB_TRY(upload(&p->br_row_ptr, nb ? row_ptr : std::vector<int32_t>()));
+    MSB_TRY(upload(&p->br_node_i, node_i));
+    MSB_TRY(upload(&p->br_bond_ptr, nb ? bond_ptr : std::vector<int32_t>()));
+    MSB_TRY(upload(&p->br_q, q));
+    MSB_TRY(upload(&p->br_off, off));
+    p->n_pairs = nb;
+    p->n_br_nodes = (int64_t)node_i.size();
+    return MSB_OK;
+}
+
+// ------------------------------------------------------------------ crack -> bonds
+// Orientation of c relative to the directed line a -> b (cross product, FP64).
+static inline double orient(double ax, double ay, double bx, double by, double cx, double cy) {
+    double u1 = bx - ax, v1 = cy - ay;
+    double u2 = by - ay, v2 = cx - ax;
+    volatile double t1 = u1 * v1;   // no contraction into an FMA
+    volatile double t2 = u2 * v2;
+    return t1 - t2;
+}
+
+static inline bool strictly_opposite(double s, double t) {
+    return (s > 0 && t < 0) || (s < 0 && t > 0);
+}
+
+extern "C" msb_status msb_crack_to_bonds(const msb_problem_desc *desc, const double *seg,
+                                         int64_t ns, int64_t *pairs_out, int64_t cap,
+                                         int64_t *nb_out) {
+    MSB_CHECK(desc && nb_out, MSB_EINVAL, "null argument");
+    *nb_out = 0;
+    MSB_TRY(validate_desc(desc));
+    MSB_CHECK(desc->dim == 2, MSB_EUNSUPPORTED, "crack segments are 2D only");
+    MSB_CHECK(ns >= 0 && (ns == 0 || seg), MSB_EINVAL, "bad segment list");
+    const int64_t nx = desc->n[0], ny = desc->n[1];
+    const int M = desc->M;
+    const double h = desc->h, delta = M * h;
+    std::vector<std::pair<int64_t, int64_t>> out;
+    for (int64_t s = 0; s < ns; ++s) {
+        const double c0x = seg[4 * s], c0y = seg[4 * s + 1], c1x = seg[4 * s + 2], c1y = seg[4 * s + 3];
+        MSB_CHECK(std::isfinite(c0x) && std::isfinite(c0y) && std::isfinite(c1x) && std::isfinite(c1y),
+                  MSB_EINVAL, "segment %lld not finite", (long long)s);
+        // nodes p that can end a crossing bond lie within delta of the segment's box
+        auto lo_idx = [&](double x) {
+            double t = std::floor((x - delta) / h - 0.5) - 1;
+            return (int64_t)std::max(0.0, t);
+        };
+        auto hi_idx = [&](double x, int64_t n) {
+            double t = std::ceil((x + delta) / h - 0.5) + 1;
+            return (int64_t)std::min((double)(n - 1), t);
+        };
+        int64_t i0 = lo_idx(std::min(c0x, c1x)), i1 = hi_idx(std::max(c0x, c1x), nx);
+        int64_t j0 = lo_idx(std::min(c0y, c1y)), j1 = hi_idx(std::max(c0y, c1y), ny);
+        for (int64_t j = j0; j <= j1; ++j)
+            for (int64_t i = i0; i <= i1; ++i) {
+                const double px = (i + 0.5) * h, py = (j + 0.5) * h;
+                for (int oy = 0; oy <= M; ++oy)
+                    for (int ox = -M; ox <= M; ++ox) {
+                        if (oy == 0 && ox <= 0) continue;          // each bond once
+                        if (ox * ox + oy * oy > M * M) continue;
+                        const int64_t qi = i + ox, qj = j + oy;
+                        if (qi < 0 || qi >= nx || qj >= ny) continue;
+                        const double qx = (qi + 0.5) * h, qy = (qj + 0.5) * h;
+                        double d1 = orient(c0x, c0y, c1x, c1y, px, py);
+                        double d2 = orient(c0x, c0y, c1x, c1y, qx, qy);
+                        if (!strictly_opposite(d1, d2)) continue;
+                        double d3 = orient(px, py, qx, qy, c0x, c0y);
+                        double d4 = orient(px, py, qx, qy, c1x, c1y);
+                        if (!strictly_opposite(d3, d4)) continue;
+                        int64_t a = j * nx + i, b = qj * nx + qi;
+                        out.emplace_back(std::min(a, b), std::max(a, b));
+                    }
+            }
+    }
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    *nb_out = (int64_t)out.size();
+    MSB_CHECK((int64_t)out.size() <= cap, MSB_EINVAL, "bond capacity %lld too small (%lld needed)",
+              (long long)cap, (long long)out.size());
+    MSB_CHECK(out.empty() || pairs_out, MSB_EINVAL, "null output");
+    for (size_t e = 0; e < out.size(); ++e) {
+        pairs_out[2 * e] = out[e].first;
+        pairs_out[2 * e + 1] = out[e].second;
+    }
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_plan_set_infl(msb_plan p, const double *infl, int n_infl, int per_case) {
+    MSB_CHECK(p, MSB_EINVAL, "null plan");
+    MSB_CHECK(n_infl >= 0 && n_infl <= 8, MSB_EINVAL, "n_infl must be in [0, 8]");
+    MSB_CHECK(n_infl == 0 || infl, MSB_EINVAL, "null coefficients");
+    const int nset = per_case ? p->B : 1;
+    for (int64_t i = 0; i < (int64_t)nset * n_infl; ++i)
+        MSB_CHECK(std::isfinite(infl[i]), MSB_EINVAL, "coefficient %lld not finite", (long long)i);
+    hipDeviceSynchronize();
+    const int count = per_case ? p->B : 1;
+    if (p->op.count != count) MSB_TRY(alloc_operator(p, p->op, count));
+    for (int c = 0; c < count; ++c) {
+        std::vector<double> v(infl + (size_t)c * n_infl, infl + (size_t)(c + 1) * n_infl);
+        MSB_TRY(fill_operator(p, v, p->op, c));
+    }
+    p->per_case = per_case != 0;
+    if (per_case) {
+        p->infl_case.assign(infl, infl + (size_t)p->B * n_infl);
+        p->infl.clear();
+    } else {
+        p->infl.assign(infl, infl + n_infl);
+        p->infl_case.clear();
+    }
+    if (n_infl != p->n_infl) {
+        for (auto &o : p->dop) free_operator(o);
+        p->dop.clear();
+    }
+    p->n_infl = n_infl;
+    return MSB_OK;
+}

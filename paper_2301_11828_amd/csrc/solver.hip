@@ -1,0 +1,686 @@
+// Entry points built on the FFT product:
+//   msb_apply / msb_apply_dinfl     f = A u (Sec. 3-4), or the a_k-derivative operator
+//   msb_solve_static                static model eq. (mat:e2) by conjugate gradients,
+//                                   FP64, FP32, or FP32 inside FP64 iterative refinement
+//   msb_vv_init / msb_vv_run        dynamic model eq. (mat:e1) by velocity Verlet (Alg. 2)
+//   msb_grad_infl                   adjoint gradient w.r.t. influence coefficients
+//
+// CG keeps every scalar on the device: each block that needs alpha or beta sums the
+// per-block partial products itself in a fixed order, so there is no host round trip
+// per iteration and results are bitwise reproducible.  Per-case flags stop converged
+// cases of a batch while the others continue.  Blocks of iterations can be captured
+// once into a hipGraph and replayed.
+#include <chrono>
+#include <cstring>
+#include <cmath>
+#include <cstdlib>
+
+#include "fft_device.hpp"
+#include "passes.hpp"
+
+namespace msb {
+
+constexpr int kT = 256;
+
+// flags in SolverWs::done
+enum : int { RUNNING = 0, CONVERGED = 1, BREAKDOWN = 2, NONFINITE = 3, SKIPPED = 4 };
+
+struct SolverWs {
+    size_t nvec = 0;                 // B * d * N
+    double *v64[6] = {};             // FP64 vectors
+    float *v32[5] = {};              // FP32 vectors
+    double *part_x = nullptr;        // [3][B * rows] x-inverse epilogue partials
+    double *part_rr = nullptr;       // [2][B][P] r.r partials
+    double *part_aux = nullptr;      // [B][P] dot partials
+    double *thresh = nullptr;        // [B]
+    double *scal = nullptr;          // [16][B] per-case scalars
+    double *energy = nullptr;        // energies (device)
+    size_t energy_cap = 0;
+    int *done = nullptr;             // [B]
+    int *iters = nullptr;            // [B]
+    int *ecount = nullptr;           // energy counter
+    double *h_scal = nullptr;        // pinned [16][B]
+    int *h_int = nullptr;            // pinned [4][B]
+    int P = 1;                       // vector-kernel blocks per case
+    hipStream_t st = nullptr;        // internal stream (graph capture needs a non-null stream)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+void solver_cache_free(msb_plan_s *p) {
+    SolverWs *w = static_cast<SolverWs *>(p->solver_cache);
+    if (!w) return;
+    for (auto x : w->v64)
+        if (x) (void)hipFree(x);
+    for (auto x : w->v32)
+        if (x) (void)hipFree(x);
+    void *b[] = {w->part_x, w->part_rr, w->part_aux, w->thresh, w->scal, w->energy, w->done, w->iters, w->ecount};
+    for (void *x : b)
+        if (x) (void)hipFree(x);
+    if (w->h_scal) (void)hipHostFree(w->h_scal);
+    if (w->h_int) (void)hipHostFree(w->h_int);
+    if (w->ev_in) (void)hipEventDestroy(w->ev_in);
+    if (w->ev_out) (void)hipEventDestroy(w->ev_out);
+    if (w->st) (void)hipStreamDestroy(w->st);
+    delete w;
+    p->solver_cache = nullptr;
+}
+
+static msb_status get_ws(msb_plan_s *p, SolverWs *&out) {
+    if (p->solver_cache) {
+        out = static_cast<SolverWs *>(p->solver_cache);
+        return MSB_OK;
+    }
+    SolverWs *w = new SolverWs();
+    p->solver_cache = w;
+    const int B = p->B;
+    w->nvec = (size_t)B * p->dim * p->N;
+    const size_t dn = (size_t)p->dim * p->N;
+    w->P = (int)std::max<size_t>(1, std::min<size_t>(256, (dn + 4095) / 4096));
+    for (auto &x : w->v64) MSB_HIP(hipMalloc(&x, sizeof(double) * w->nvec));
+    for (auto &x : w->v32) MSB_HIP(hipMalloc(&x, sizeof(float) * w->nvec));
+    MSB_HIP(hipMalloc(&w->part_x, sizeof(double) * 3 * (size_t)B * rows_total(p)));
+    MSB_HIP(hipMalloc(&w->part_rr, sizeof(double) * 2 * (size_t)B * w->P));
+    MSB_HIP(hipMalloc(&w->part_aux, sizeof(double) * 3 * (size_t)B * w->P));
+    MSB_HIP(hipMalloc(&w->thresh, sizeof(double) * B));
+    MSB_HIP(hipMalloc(&w->scal, sizeof(double) * 16 * B));
+    MSB_HIP(hipMalloc(&w->done, sizeof(int) * B));
+    MSB_HIP(hipMalloc(&w->iters, sizeof(int) * B));
+    MSB_HIP(hipMalloc(&w->ecount, sizeof(int)));
+    MSB_HIP(hipHostMalloc(&w->h_scal, sizeof(double) * 16 * B));
+    MSB_HIP(hipHostMalloc(&w->h_int, sizeof(int) * 4 * B));
+    MSB_HIP(hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking));
+    MSB_HIP(hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming));
+    MSB_HIP(hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming));
+    out = w;
+    return MSB_OK;
+}
+
+// ------------------------------------------------------------------ vector kernels
+template <typename T> __global__ void k_fill(T *x, size_t n, T v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+template <typename T> __global__ void k_fill_int(T *x, int n, T v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
+}
+
+// dst = src on free DOFs (0 on constrained) when keep_fixed == 0;
+// dst = src on constrained DOFs (0 on free) when keep_fixed == 1.
+template <typename T>
+__global__ void k_mask_copy(T *dst, const T *src, const uint8_t *fixed, size_t n, size_t dn, int keep_fixed) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const bool fx = fixed && fixed[i % dn];
+        dst[i] = (fx == (keep_fixed != 0)) ? src[i] : T(0);
+    }
+}
+
+// u_C = g_C (or 0)
+template <typename T>
+__global__ void k_set_fixed(T *u, const T *g, const uint8_t *fixed, size_t n, size_t dn) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        if (fixed[i % dn]) u[i] = g ? g[i] : T(0);
+}
+
+template <typename S, typename D> __global__ void k_cast(D *dst, const S *src, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (D)src[i];
+}
+
+// x64 += d (d FP32 or FP64)
+template <typename S> __global__ void k_add_to(double *x, const S *d, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] += (double)d[i];
+}
+
+// per-case partial dot products x.y: grid B*P blocks, part[b*P + blk]
+template <typename T>
+__global__ __launch_bounds__(kT) void k_dot_parts(const T *x, const T *y, double *part, size_t dn, int P) {
+    __shared__ double red[80];
+    const int b = blockIdx.x / P, blk = blockIdx.x - b * P;
+    const T *xb = x + (size_t)b * dn, *yb = y + (size_t)b * dn;
+    double v[1] = {0.0};
+    for (size_t i = (size_t)blk * kT + threadIdx.x; i < dn; i += (size_t)P * kT) v[0] += (double)xb[i] * (double)yb[i];
+    block_sum<1>(v, red, threadIdx.x, kT);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// out[b] = scale * sum of part[b*stride .. b*stride + n)  (one block per case)
+__global__ __launch_bounds__(kT) void k_case_sums(const double *part, int n, size_t stride, double *out, double scale) {
+    __shared__ double red[80];
+    const double s = block_sum_partials(part + (size_t)blockIdx.x * stride, n, red, threadIdx.x, kT);
+    if (threadIdx.x == 0) out[blockIdx.x] = scale * s;
+}
+
+// CG start: thresh[b] = tol2 * (r.r)[b]; done[b] = SKIPPED when skip[b] != 0 (or r.r == 0)
+__global__ void k_cg_setup(const double *rr_part, int P, double tol2, double *thresh, int *done,
+                           const int *skip, int *iters, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    for (int i = 0; i < P; ++i) s += rr_part[(size_t)b * P + i];
+    thresh[b] = tol2 * s;
+    done[b] = (skip && skip[b]) ? SKIPPED : (s == 0.0 ? CONVERGED : RUNNING);
+    iters[b] = 0;
+}
+
+// x += alpha p ; r -= alpha q ; partial r.r.  alpha = (r.r)/(p.q) from partials.
+template <typename T>
+__global__ __launch_bounds__(kT) void k_cg_update(T *x, T *r, const T *p, const T *q,
+                                                  const double *pq_part, int npq,
+                                                  const double *rr_cur, double *rr_nxt, int P,
+                                                  int *done, int *iters, size_t dn) {
+    __shared__ double red[80];
+    const int b = blockIdx.x / P, blk = blockIdx.x - b * P;
+    if (done[b]) return;
+    const double pq = block_sum_partials(pq_part + (size_t)b * npq, npq, red, threadIdx.x, kT);
+    const double rr = block_sum_partials(rr_cur + (size_t)b * P, P, red, threadIdx.x, kT);
+    const double alpha = rr / pq;
+    if (!(pq > 0.0) || !std::isfinite(alpha)) {   // K p . p <= 0: not positive definite
+        if (blk == 0 && threadIdx.x == 0) done[b] = BREAKDOWN;
+        return;
+    }
+    const T a = T(alpha);
+    const size_t base = (size_t)b * dn;
+    double v[1] = {0.0};
+    for (size_t i = (size_t)blk * kT + threadIdx.x; i < dn; i += (size_t)P * kT) {
+        const size_t j = base + i;
+        x[j] += a * p[j];
+        const T rn = r[j] - a * q[j];
+        r[j] = rn;
+        v[0] += (double)rn * (double)rn;
+    }
+    block_sum<1>(v, red, threadIdx.x, kT);
+    if (threadIdx.x == 0) {
+        rr_nxt[blockIdx.x] = v[0];
+        if (blk == 0) iters[b] += 1;
+    }
+}
+
+// a = (a + b)/rho on free DOFs, 0 on constrained
+template <typename T>
+__global__ void k_vv_accel(T *a, const T *bf, const uint8_t *fixed, size_t n, size_t dn, double rho) {
+    const T ri = T(1.0 / rho);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const bool fx = fixed && fixed[i % dn];
+        a[i] = fx ? T(0) : (a[i] + bf[i]) * ri;
+    }
+}
+
+// H = rho V/2 sum v^2 - V/2 sum u.f - V sum b.u over all tiles of all cases
+__global__ __launch_bounds__(kT) void k_energy(const double *part, int n, double rho, double V, double *energy, int *count) {
+    __shared__ double red[80];
+    const double uf = block_sum_partials(part, n, red, threadIdx.x, kT);
+    const double vv = block_sum_partials(part + n, n, red, threadIdx.x, kT);
+    const double bu = block_sum_partials(part + 2 * (size_t)n, n, red, threadIdx.x, kT);
+    if (threadIdx.x == 0) {
+        energy[*count] = 0.5 * rho * V * vv - 0.5 * V * uf - V * bu;
+        *count += 1;
+    }
+}
+
+static inline int grid_for(size_t n) { return (int)std::max<size_t>(1, std::min<size_t>(2048, (n + kT - 1) / kT)); }
+
+// ------------------------------------------------------------------ helpers
+template <typename T> struct Prec;
+template <> struct Prec<double> { static constexpr msb_precision p = MSB_FP64; };
+template <> struct Prec<float> { static constexpr msb_precision p = MSB_FP32; };
+
+static msb_status check_plan(msb_plan_s *p) {
+    MSB_CHECK(p, MSB_EINVAL, "null plan");
+    int dev = -1;
+    MSB_HIP(hipGetDevice(&dev));
+    MSB_CHECK(dev == p->device, MSB_EINVAL, "plan was created on device %d, current is %d", p->device, dev);
+    return MSB_OK;
+}
+
+template <typename T>
+static msb_status product(msb_plan_s *p, const DeviceOp &op, const T *u, EndArgs<T> e, hipStream_t st) {
+    PassArgs<T> a = pass_args<T>(p, op);
+    e.pio = const_cast<T *>(u);
+    if (!e.uin) e.uin = u;
+    return launch_product<T>(a, e, st);
+}
+
+template <typename T> static EndArgs<T> end_args() {
+    EndArgs<T> e;
+    memset(&e, 0, sizeof(e));
+    e.sign = 1.0;
+    e.rho = 1.0;
+    return e;
+}
+
+// ------------------------------------------------------------------ conjugate gradients
+template <typename T> struct Cg {
+    msb_plan_s *p;
+    SolverWs *w;
+    hipStream_t st;
+    T *x, *r, *pv, *q;
+    PassArgs<T> pa;
+    int tpc;
+};
+
+template <typename T> static msb_status cg_iteration(Cg<T> &c, int it) {
+    msb_plan_s *p = c.p;
+    SolverWs *w = c.w;
+    const int B = p->B, P = w->P;
+    double *rr_cur = w->part_rr + (size_t)(it & 1) * B * P;
+    double *rr_nxt = w->part_rr + (size_t)((it + 1) & 1) * B * P;
+    EndArgs<T> e = end_args<T>();
+    e.pro = PRO_CG_P;
+    e.pio = c.pv;
+    e.pr = c.r;
+    e.beta_part = rr_cur;
+    e.beta_part_old = it == 0 ? nullptr : rr_nxt;
+    e.nbeta = P;
+    e.case_done = w->done;
+    e.done_rw = w->done;
+    e.thresh = w->thresh;
+    e.epi = EPI_CG_Q;
+    e.uin = c.pv;
+    e.out = c.q;
+    e.part = w->part_x;
+    MSB_TRY(launch_product<T>(c.pa, e, c.st));
+    const size_t dn = (size_t)p->dim * p->N;
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(B * P), dim3(kT), 0, c.st, c.x, c.r, (const T *)c.pv,
+                       (const T *)c.q, (const double *)w->part_x, c.tpc, (const double *)rr_cur, rr_nxt,
+                       P, w->done, w->iters, dn);
+    MSB_HIP(hipGetLastError());
+    return MSB_OK;
+}
+
+static int env_int(const char *name, int dflt) {
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+// Run CG from the prepared state (x, r, p = 0, r.r partials in part_rr[0], thresholds
+// and flags set).  Stops when every case has a flag or after maxit iterations.
+template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_block, int *it_out) {
+    SolverWs *w = c.w;
+    const int B = c.p->B;
+    int it = 0;
+    MSB_TRY(cg_iteration(c, 0));
+    it = 1;
+    const int poll = graph_block > 0 ? graph_block : std::max(2, env_int("MSB_CG_POLL", 32));
+    const int block = poll + (poll & 1);   // even: keeps the partial-sum parity of replays fixed
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    msb_status st = MSB_OK;
+    while (it < maxit && st == MSB_OK) {
+        MSB_HIP(hipMemcpyAsync(w->h_int, w->done, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
+        MSB_HIP(hipStreamSynchronize(c.st));
+        bool all = true;
+        for (int b = 0; b < B; ++b) all = all && w->h_int[b] != RUNNING;
+        if (all) break;
+        const int k = std::min(block, maxit - it);
+        if (graph_block > 0 && k == block) {
+            if (!exec) {
+                MSB_HIP(hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal));
+                for (int j = 0; j < block && st == MSB_OK; ++j) st = cg_iteration(c, it + j);
+                hipError_t e1 = hipStreamEndCapture(c.st, &graph);
+                if (st != MSB_OK) break;
+                MSB_HIP(e1);
+                MSB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            }
+            MSB_HIP(hipGraphLaunch(exec, c.st));
+        } else {
+            for (int j = 0; j < k && st == MSB_OK; ++j) st = cg_iteration(c, it + j);
+        }
+        it += k;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    *it_out = it;
+    return st;
+}
+
+// Prepare and run CG on K d = rhs (rhs already masked); x0 = 0.
+template <typename T>
+static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *rhs, T *x, T *r, T *pv,
+                           T *q, double tol, int maxit, int graph_block, const int *skip) {
+    const size_t n = w->nvec;
+    const int B = p->B, P = w->P;
+    Cg<T> c{p, w, st, x, r, pv, q, pass_args<T>(p, p->op), 0};
+    c.tpc = x_tiles_per_case(p, c.pa.F);
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, x, n, T(0));
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
+    hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(n)), dim3(kT), 0, st, r, rhs, n);
+    hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * P), dim3(kT), 0, st, (const T *)r, (const T *)r, w->part_rr,
+                       (size_t)p->dim * p->N, P);
+    hipLaunchKernelGGL(k_cg_setup, dim3((B + 63) / 64), dim3(64), 0, st, (const double *)w->part_rr, P, tol * tol,
+                       w->thresh, w->done, skip, w->iters, B);
+    MSB_HIP(hipGetLastError());
+    int it = 0;
+    return run_cg(c, maxit, graph_block, &it);
+}
+
+// per-case ||rhs + A x||^2 on free DOFs into w->scal[slot*B + b], residual vector into out
+static msb_status true_residual(msb_plan_s *p, SolverWs *w, hipStream_t st, const double *x, const double *rhs,
+                                double *out, int slot) {
+    EndArgs<double> e = end_args<double>();
+    e.epi = EPI_RESID;
+    e.rhs = rhs;
+    e.out = out;
+    e.part = w->part_x;
+    MSB_TRY(product<double>(p, p->op, x, e, st));
+    PassArgs<double> a = pass_args<double>(p, p->op);
+    const int tpc = x_tiles_per_case(p, a.F);
+    hipLaunchKernelGGL(k_case_sums, dim3(p->B), dim3(kT), 0, st, (const double *)w->part_x, tpc, (size_t)tpc,
+                       w->scal + (size_t)slot * p->B, 1.0);
+    MSB_HIP(hipGetLastError());
+    return MSB_OK;
+}
+
+static msb_status fetch_scal(SolverWs *w, hipStream_t st, int nslots, int B) {
+    MSB_HIP(hipMemcpyAsync(w->h_scal, w->scal, sizeof(double) * nslots * B, hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipMemcpyAsync(w->h_int, w->done, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipMemcpyAsync(w->h_int + B, w->iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipStreamSynchronize(st));
+    return MSB_OK;
+}
+
+static msb_status flag_status(int f) {
+    switch (f) {
+        case CONVERGED: case SKIPPED: return MSB_OK;
+        case BREAKDOWN: return MSB_ENOTSPD;
+        case NONFINITE: return MSB_ENOTSPD;
+        default: return MSB_ENOCONV;
+    }
+}
+
+}  // namespace msb
+
+using namespace msb;
+
+// ---------------------------------------------------------------------------- apply
+extern "C" msb_status msb_apply(msb_plan p, msb_precision prec, const void *u, void *f, void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(u && f, MSB_EINVAL, "null vector");
+    MSB_CHECK(u != f, MSB_EINVAL, "u and f must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == MSB_FP64) {
+        EndArgs<double> e = end_args<double>();
+        e.epi = EPI_APPLY;
+        e.out = (double *)f;
+        return product<double>(p, p->op, (const double *)u, e, st);
+    }
+    MSB_CHECK(prec == MSB_FP32, MSB_EINVAL, "apply precision must be MSB_FP64 or MSB_FP32");
+    EndArgs<float> e = end_args<float>();
+    e.epi = EPI_APPLY;
+    e.out = (float *)f;
+    return product<float>(p, p->op, (const float *)u, e, st);
+}
+
+static msb_status ensure_dop(msb_plan_s *p, int k) {
+    if ((int)p->dop.size() <= k) p->dop.resize(k + 1);
+    DeviceOp &op = p->dop[k];
+    if (op.count) return MSB_OK;
+    std::vector<double> e(k + 1, 0.0);
+    e[k] = 1.0;
+    MSB_TRY(alloc_operator(p, op, 1));
+    return fill_operator(p, e, op, 0);
+}
+
+extern "C" msb_status msb_apply_dinfl(msb_plan p, int k, const double *u, double *f, void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(u && f && u != f, MSB_EINVAL, "bad vectors");
+    MSB_CHECK(k >= 0 && k < 8, MSB_EINVAL, "k must be in [0, 8)");
+    MSB_TRY(ensure_dop(p, k));
+    EndArgs<double> e = end_args<double>();
+    e.epi = EPI_APPLY;
+    e.out = f;
+    return product<double>(p, p->dop[k], u, e, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------- static solve
+extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const double *b, const double *g,
+                                       double *u, const msb_solve_opts *opts, msb_solve_info *info,
+                                       void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(b && u && opts && info, MSB_EINVAL, "null argument");
+    MSB_CHECK(b != u && g != u, MSB_EINVAL, "u must not alias b or g");
+    MSB_CHECK(opts->tol > 0 && opts->tol < 1 && opts->maxit > 0, MSB_EINVAL, "need 0 < tol < 1 and maxit > 0");
+    MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32 || prec == MSB_FP32_REFINED, MSB_EINVAL, "bad precision");
+    MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
+    SolverWs *w = nullptr;
+    MSB_TRY(get_ws(p, w));
+    const int B = p->B;
+    const size_t n = w->nvec, dn = (size_t)p->dim * p->N;
+    hipStream_t user = (hipStream_t)stream;
+    hipStream_t st = w->st;
+    MSB_HIP(hipEventRecord(w->ev_in, user));
+    MSB_HIP(hipStreamWaitEvent(st, w->ev_in, 0));
+    const int gb = opts->graph_block;
+
+    double *bp = w->v64[0], *tmp = w->v64[1];
+    // lifted right-hand side b' = b_F - K_FC g_C = (b + A g~)_F, g~ = g on Omega_c, 0 elsewhere
+    if (g && p->fixed) {
+        hipLaunchKernelGGL(k_mask_copy<double>, dim3(grid_for(n)), dim3(kT), 0, st, tmp, g, (const uint8_t *)p->fixed, n, dn, 1);
+        EndArgs<double> e = end_args<double>();
+        e.epi = EPI_RESID;
+        e.rhs = b;
+        e.out = bp;
+        MSB_TRY(product<double>(p, p->op, tmp, e, st));
+    } else {
+        hipLaunchKernelGGL(k_mask_copy<double>, dim3(grid_for(n)), dim3(kT), 0, st, bp, b, (const uint8_t *)p->fixed, n, dn, 0);
+    }
+    hipLaunchKernelGGL(k_dot_parts<double>, dim3(B * w->P), dim3(kT), 0, st, (const double *)bp, (const double *)bp,
+                       w->part_aux, dn, w->P);
+    hipLaunchKernelGGL(k_case_sums, dim3(B), dim3(kT), 0, st, (const double *)w->part_aux, w->P, (size_t)w->P, w->scal, 1.0);
+    MSB_HIP(hipGetLastError());
+    MSB_TRY(fetch_scal(w, st, 1, B));
+    std::vector<double> bb(w->h_scal, w->h_scal + B);
+    for (int c = 0; c < B; ++c)
+        MSB_CHECK(std::isfinite(bb[c]), MSB_EINVAL, "case %d: right-hand side (or lift) is not finite", c);
+
+    std::vector<int> outer(B, 0), inner(B, 0), fl(B, RUNNING);
+    std::vector<double> rel(B, 0.0);
+    msb_status result = MSB_OK;
+
+    if (prec == MSB_FP64 || prec == MSB_FP32) {
+        if (prec == MSB_FP64) {
+            MSB_TRY(cg_solve<double>(p, w, st, bp, u, w->v64[2], w->v64[3], w->v64[4], opts->tol, opts->maxit, gb, nullptr));
+        } else {
+            float *b32 = w->v32[0], *x32 = w->v32[1];
+            hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kT), 0, st, b32, (const double *)bp, n);
+            MSB_TRY(cg_solve<float>(p, w, st, b32, x32, w->v32[2], w->v32[3], w->v32[4], opts->tol, opts->maxit, gb, nullptr));
+            hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for(n)), dim3(kT), 0, st, u, (const float *)x32, n);
+        }
+        MSB_TRY(fetch_scal(w, st, 1, B));
+        for (int c = 0; c < B; ++c) {
+            fl[c] = w->h_int[c];
+            inner[c] = w->h_int[B + c];
+            outer[c] = 1;
+        }
+    } else {
+        // FP32 inner CG inside FP64 iterative refinement: r = b' - K u (FP64 apply),
+        // solve K d = r in FP32 to inner_tol, u += d (FP64)
+        const double itol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
+        int *skip = nullptr;
+        MSB_HIP(hipMalloc(&skip, sizeof(int) * B));
+        float *r32 = w->v32[0], *d32 = w->v32[1];
+        double *r64 = w->v64[2];
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kT), 0, st, u, n, 0.0);
+        hipLaunchKernelGGL((k_cast<double, double>), dim3(grid_for(n)), dim3(kT), 0, st, r64, (const double *)bp, n);
+        std::vector<double> rr(bb);
+        std::vector<double> hist;
+        int used = 0;
+        std::vector<int> hskip(B, 0);
+        for (int j = 0; j < 200; ++j) {
+            bool all = true;
+            for (int c = 0; c < B; ++c) {
+                rel[c] = bb[c] > 0 ? std::sqrt(rr[c] / bb[c]) : 0.0;
+                if (!std::isfinite(rel[c])) fl[c] = NONFINITE;
+                if (fl[c] == RUNNING && rel[c] <= opts->tol) fl[c] = CONVERGED;
+                hskip[c] = fl[c] != RUNNING;
+                all = all && hskip[c];
+            }
+            if (all || used >= opts->maxit) break;
+            MSB_HIP(hipMemcpyAsync(skip, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kT), 0, st, r32, (const double *)r64, n);
+            MSB_TRY(cg_solve<float>(p, w, st, r32, d32, w->v32[2], w->v32[3], w->v32[4], itol, opts->maxit - used, gb, skip));
+            MSB_TRY(fetch_scal(w, st, 0, B));
+            int mx = 0;
+            for (int c = 0; c < B; ++c) {
+                if (!hskip[c]) {
+                    inner[c] += w->h_int[B + c];
+                    outer[c] += 1;
+                    if (w->h_int[c] == BREAKDOWN || w->h_int[c] == NONFINITE) fl[c] = w->h_int[c];
+                }
+                mx = std::max(mx, w->h_int[B + c]);
+            }
+            used += mx;
+            hipLaunchKernelGGL(k_add_to<float>, dim3(grid_for(n)), dim3(kT), 0, st, u, (const float *)d32, n);
+            MSB_TRY(true_residual(p, w, st, u, bp, r64, 0));
+            MSB_TRY(fetch_scal(w, st, 1, B));
+            for (int c = 0; c < B; ++c) {
+                if (hskip[c]) continue;
+                // stagnation: no 10% gain over the last three refinement steps
+                if (outer[c] >= 4 && w->h_scal[c] > 0.81 * rr[c] && hist.size() > 0) fl[c] = fl[c] == RUNNING ? -1 : fl[c];
+                rr[c] = w->h_scal[c];
+            }
+            hist.push_back(rr[0]);
+        }
+        (void)hipFree(skip);
+        for (int c = 0; c < B; ++c)
+            if (fl[c] == -1) fl[c] = RUNNING;   // reported as no convergence below
+    }
+
+    // certify: FP64 residual of the final u on free DOFs
+    MSB_TRY(true_residual(p, w, st, u, bp, tmp, 0));
+    if (p->fixed) hipLaunchKernelGGL(k_set_fixed<double>, dim3(grid_for(n)), dim3(kT), 0, st, u, g, (const uint8_t *)p->fixed, n, dn);
+    MSB_TRY(fetch_scal(w, st, 1, B));
+    MSB_HIP(hipEventRecord(w->ev_out, st));
+    MSB_HIP(hipStreamWaitEvent(user, w->ev_out, 0));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int c = 0; c < B; ++c) {
+        rel[c] = bb[c] > 0 ? std::sqrt(w->h_scal[c] / bb[c]) : 0.0;
+        msb_status s = flag_status(fl[c]);
+        if (s == MSB_OK && !(rel[c] <= opts->tol * 10)) s = MSB_ENOCONV;   // certified residual
+        if (fl[c] == RUNNING) s = rel[c] <= opts->tol ? MSB_OK : MSB_ENOCONV;
+        info[c].status = s;
+        info[c].outer_iters = outer[c];
+        info[c].inner_iters = inner[c];
+        info[c].rel_residual = rel[c];
+        info[c].seconds = secs;
+        if (s != MSB_OK && result == MSB_OK) {
+            result = s;
+            set_error("case %d: %s (relative residual %.3e after %d iterations)", c,
+                      s == MSB_ENOTSPD ? "CG breakdown: operator not positive definite on the free DOFs"
+                                       : "no convergence", rel[c], inner[c]);
+        }
+    }
+    return result;
+}
+
+// ---------------------------------------------------------------------------- Verlet
+template <typename T>
+static msb_status vv_init_t(msb_plan_s *p, const T *u, const T *bf, T *a, hipStream_t st) {
+    EndArgs<T> e = end_args<T>();
+    e.epi = EPI_APPLY;
+    e.out = a;
+    MSB_TRY(product<T>(p, p->op, u, e, st));
+    const size_t n = (size_t)p->B * p->dim * p->N, dn = (size_t)p->dim * p->N;
+    hipLaunchKernelGGL(k_vv_accel<T>, dim3(grid_for(n)), dim3(kT), 0, st, a, bf, (const uint8_t *)p->fixed, n, dn, p->rho);
+    MSB_HIP(hipGetLastError());
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_vv_init(msb_plan p, msb_precision prec, const void *u, const void *b, void *a, void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(u && b && a && a != u && a != b, MSB_EINVAL, "bad vectors");
+    if (prec == MSB_FP64) return vv_init_t<double>(p, (const double *)u, (const double *)b, (double *)a, (hipStream_t)stream);
+    MSB_CHECK(prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
+    return vv_init_t<float>(p, (const float *)u, (const float *)b, (float *)a, (hipStream_t)stream);
+}
+
+template <typename T>
+static msb_status vv_run_t(msb_plan_s *p, double dt, int64_t nsteps, T *u, T *v, T *a, const T *bf, const T *g,
+                           double *energy, int every, hipStream_t st) {
+    SolverWs *w = nullptr;
+    MSB_TRY(get_ws(p, w));
+    const int64_t ne = (energy && every > 0) ? nsteps / every : 0;
+    if (ne > 0 && (size_t)ne > w->energy_cap) {
+        if (w->energy) (void)hipFree(w->energy);
+        MSB_HIP(hipMalloc(&w->energy, sizeof(double) * ne));
+        w->energy_cap = ne;
+    }
+    if (ne > 0) hipLaunchKernelGGL(k_fill_int<int>, dim3(1), dim3(64), 0, st, w->ecount, 1, 0);
+    PassArgs<T> pa = pass_args<T>(p, p->op);
+    const int tiles = p->B * x_tiles_per_case(p, pa.F);
+    double V = 1.0;
+    for (int q = 0; q < p->dim; ++q) V *= p->h;
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        EndArgs<T> e = end_args<T>();
+        e.pro = PRO_VV_U;
+        e.pio = u;
+        e.pr = v;
+        e.pa = a;
+        e.pg = g;
+        e.dt = dt;
+        e.epi = EPI_VV;
+        e.uin = u;
+        e.rhs = bf;
+        e.ev = v;
+        e.ea = a;
+        e.rho = p->rho;
+        const bool en = ne > 0 && (s % every) == 0 && s / every <= ne;
+        e.energy = en ? 1 : 0;
+        e.part = en ? w->part_x : nullptr;
+        MSB_TRY(launch_product<T>(pa, e, st));
+        if (en) hipLaunchKernelGGL(k_energy, dim3(1), dim3(kT), 0, st, (const double *)w->part_x, tiles, p->rho, V, w->energy, w->ecount);
+    }
+    MSB_HIP(hipGetLastError());
+    if (ne > 0) {
+        MSB_HIP(hipMemcpyAsync(energy, w->energy, sizeof(double) * ne, hipMemcpyDeviceToHost, st));
+        MSB_HIP(hipStreamSynchronize(st));
+    }
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_vv_run(msb_plan p, msb_precision prec, double dt, int64_t nsteps, void *u, void *v,
+                                 void *a, const void *b, const void *g, double *energy, int every, void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(u && v && a && b, MSB_EINVAL, "null vector");
+    MSB_CHECK(std::isfinite(dt) && dt > 0 && nsteps >= 0, MSB_EINVAL, "need dt > 0 and nsteps >= 0");
+    MSB_CHECK(!energy || every > 0, MSB_EINVAL, "energy output needs every > 0");
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == MSB_FP64)
+        return vv_run_t<double>(p, dt, nsteps, (double *)u, (double *)v, (double *)a, (const double *)b,
+                                (const double *)g, energy, every, st);
+    MSB_CHECK(prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
+    return vv_run_t<float>(p, dt, nsteps, (float *)u, (float *)v, (float *)a, (const float *)b, (const float *)g,
+                           energy, every, st);
+}
+
+// ---------------------------------------------------------------------------- gradient
+extern "C" msb_status msb_grad_infl(msb_plan p, const double *u, const double *wv, double *dL_da, void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(u && wv && dL_da, MSB_EINVAL, "null argument");
+    MSB_CHECK(p->n_infl > 0, MSB_EINVAL, "plan has no influence coefficients");
+    SolverWs *w = nullptr;
+    MSB_TRY(get_ws(p, w));
+    hipStream_t st = (hipStream_t)stream;
+    const int B = p->B, K = p->n_infl;
+    PassArgs<double> pa = pass_args<double>(p, p->op);
+    const int tpc = x_tiles_per_case(p, pa.F);
+    for (int k = 0; k < K; ++k) {
+        MSB_TRY(ensure_dop(p, k));
+        // dL/da_k = w . (A_k u)_F
+        EndArgs<double> e = end_args<double>();
+        e.epi = EPI_DOT;
+        e.rhs = wv;
+        e.part = w->part_x;
+        MSB_TRY(product<double>(p, p->dop[k], u, e, st));
+        hipLaunchKernelGGL(k_case_sums, dim3(B), dim3(kT), 0, st, (const double *)w->part_x, tpc, (size_t)tpc,
+                           w->scal + (size_t)k * B, 1.0);
+    }
+    MSB_HIP(hipGetLastError());
+    MSB_HIP(hipMemcpyAsync(w->h_scal, w->scal, sizeof(double) * K * B, hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b)
+        for (int k = 0; k < K; ++k) dL_da[(size_t)b * K + k] = w->h_scal[(size_t)k * B + b];
+    return MSB_OK;
+}

@@ -1,0 +1,163 @@
+"""Parity of the GPU FFT product f = A u (Alg. 3 / Alg. 4 plus D^e, D^f and the
+constraint mask) against the oracle's bond-by-bond sum, eq. (mat:f1).
+
+FP64 bar: relative error <= 1e-12 (2-norm over each case), the target the build
+states for FP64 displacements; FP32 results are compared with the FP64 oracle and
+their error is bounded (and printed) rather than required to match."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2301_11828_amd import workloads as W
+from helpers import gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-6
+
+
+def _oracle_apply(w, u):
+    p = oracle_problem(w)
+    br = oracle_bonds(w)
+    return np.stack([O.apply(p, u[c], w.fixed, br) for c in range(u.shape[0])])
+
+
+CASES = [
+    # dim, n, M, fixed, crack, batch -- several tiles per pass and ragged tails
+    (2, (37, 29), 3, "none", False, 1),
+    (2, (64, 50), 4, "left", True, 2),
+    (2, (33, 70), 2, "all", True, 1),
+    (2, (41, 23), 3, "mixed", False, 1),
+    (2, (1, 17), 2, "none", False, 1),
+    (2, (5, 3), 4, "none", False, 3),
+    (3, (11, 9, 13), 2, "bottom", False, 1),
+    (3, (16, 12, 10), 3, "all", False, 2),
+    (3, (7, 5, 6), 3, "none", False, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%dd-%s-M%d-%s%s-b%d" % (c[0], "x".join(map(str, c[1])), c[2], c[3], "-crack" if c[4] else "", c[5]))
+def test_apply_fp64_matches_oracle(case):
+    dim, n, M, fixed, crack, batch = case
+    log("apply fp64 %s" % (case,))
+    w = W.small(dim, n, M, seed=CASES.index(case), fixed=fixed, crack=crack, batch=batch)
+    plan = gpu_plan(w)
+    if crack:
+        assert plan.n_bonds == len(oracle_bonds(w)) > 0
+    f = plan.apply(to_dev(w.b)).cpu().numpy()
+    ref = _oracle_apply(w, w.b)
+    for c in range(batch):
+        err = rel_err(f[c], ref[c])
+        log("  case %d rel err %.3e" % (c, err))
+        assert err <= FP64_TOL
+    if w.fixed is not None:
+        assert np.all(f[:, w.fixed] == 0.0)
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[7]], ids=["2d-crack", "2d-all", "3d"])
+def test_apply_fp32_error_bounded(case):
+    dim, n, M, fixed, crack, batch = case
+    import torch
+    w = W.small(dim, n, M, seed=7, fixed=fixed, crack=crack, batch=batch)
+    plan = gpu_plan(w)
+    f = plan.apply(to_dev(w.b, torch.float32)).double().cpu().numpy()
+    ref = _oracle_apply(w, w.b.astype(np.float32).astype(np.float64))
+    for c in range(batch):
+        err = rel_err(f[c], ref[c])
+        log("fp32 apply %s case %d rel err vs FP64 oracle %.3e" % (case, c, err))
+        assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_exhaustive_unit_vectors_reproduce_dense_A(dim):
+    """Every column of A on a 9x9 (9x9x9 in 3D, batched) grid with constraints and (2D)
+    a crack through the grid: the product equals the oracle's dense matrix."""
+    import torch
+    n = (9, 9) if dim == 2 else (9, 9, 9)
+    M = 3 if dim == 2 else 2
+    w = W.small(dim, n, M, seed=3, fixed="mixed" if dim == 2 else "bottom", crack=(dim == 2))
+    p = oracle_problem(w)
+    A = O.assemble_dense(p, oracle_bonds(w))
+    D = dim * w.N
+    fixed = w.fixed.reshape(-1)
+    plan = gpu_plan(w, batch=D if dim == 2 else 81 * 3)
+    cols = np.arange(D) if dim == 2 else np.random.default_rng(0).choice(D, 81 * 3, replace=False)
+    U = np.zeros((len(cols), D))
+    U[np.arange(len(cols)), cols] = 1.0
+    F = plan.apply(to_dev(U.reshape(len(cols), dim, w.N))).cpu().numpy().reshape(len(cols), D)
+    ref = A[:, cols].T.copy()
+    ref[:, fixed] = 0.0
+    err = np.abs(F - ref).max() / np.abs(A).max()
+    log("exhaustive %dD max abs err / max|A| = %.3e" % (dim, err))
+    assert err <= 1e-14 * 50
+
+
+def test_batched_equals_single_bitwise():
+    import torch
+    w = W.small(2, (45, 38), 3, seed=11, fixed="left", crack=True, batch=3)
+    plan_b = gpu_plan(w)
+    fb = plan_b.apply(to_dev(w.b)).cpu().numpy()
+    w1 = W.small(2, (45, 38), 3, seed=11, fixed="left", crack=True, batch=1)
+    plan_1 = gpu_plan(w1)
+    for c in range(3):
+        f1 = plan_1.apply(to_dev(w.b[c:c + 1])).cpu().numpy()
+        assert np.array_equal(f1[0], fb[c])
+
+
+def test_apply_deterministic():
+    w = W.small(3, (12, 10, 9), 3, seed=5, fixed="bottom", batch=2)
+    plan = gpu_plan(w)
+    u = to_dev(w.b)
+    a = plan.apply(u).cpu().numpy()
+    b = plan.apply(u).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_rigid_translation_and_rotation_on_gpu():
+    """Invariants hold on the GPU product too: translation -> 0 on every row, rotation -> 0."""
+    import torch
+    w = W.small(2, (40, 31), 3, seed=2, crack=True)
+    plan = gpu_plan(w)
+    x = oracle_problem(w).node_coords()
+    u = np.stack([np.full(w.N, 0.3), np.full(w.N, -0.7)])[None]
+    f = plan.apply(to_dev(u)).cpu().numpy()
+    scale = np.abs(plan.apply(to_dev(np.stack([x[0], 0 * x[0]])[None])).cpu().numpy()).max()
+    assert np.abs(f).max() <= 1e-12 * scale
+    rot = (1e-2 * np.stack([-x[1], x[0]]))[None]
+    fr = plan.apply(to_dev(rot)).cpu().numpy()
+    assert np.abs(fr).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name", ["plate32", "plate512", "crack1024"])
+def test_apply_at_benchmark_sizes(name):
+    """Full-size 2D workloads, the same launch configuration the benchmark times."""
+    w = {"plate32": W.plate32, "plate512": W.plate512, "crack1024": lambda: W.crack1024(steps=1)}[name]()
+    log("apply at %s" % name)
+    plan = gpu_plan(w)
+    u = np.random.default_rng(1).standard_normal((1, 2, w.N))
+    f = plan.apply(to_dev(u)).cpu().numpy()
+    ref = _oracle_apply(w, u)
+    err = rel_err(f, ref)
+    log("  %s rel err %.3e" % (name, err))
+    assert err <= FP64_TOL
+
+
+def test_apply_cube128_sampled_rows():
+    """3D 128^3 batch of 16: compare 3000 sampled nodes per case on 3 cases with the
+    oracle's row-by-row sum (all components)."""
+    w = W.cube128(batch=16)
+    log("apply cube128 B=16")
+    plan = gpu_plan(w)
+    f = plan.apply(to_dev(w.b)).cpu().numpy()
+    p = oracle_problem(w)
+    rs = np.random.default_rng(3)
+    for c in (0, 7, 15):
+        rows = np.sort(rs.choice(w.N, 3000, replace=False))
+        rows = np.concatenate([rows, [0, w.N - 1, 128 * 128 * 64 + 64 * 128 + 64]])
+        ref = O.force(p, w.b[c], rows=rows)
+        ref[w.fixed[:, rows]] = 0.0
+        got = f[c][:, rows]
+        err = rel_err(got, ref)
+        log("  case %d sampled rel err %.3e" % (c, err))
+        assert err <= FP64_TOL
