@@ -65,6 +65,14 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError("libmsbfm.so not built (expected at %s); run __graft_entry__.build() "
                           "or python -m paper_2301_11828_amd.build" % path)
+    # One HIP runtime per process: let PyTorch load (and initialise) its runtime first so
+    # that the library's libamdhip64.so.7 dependency binds to that same copy.
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -137,6 +145,16 @@ class SolveInfo:
 def _torch():
     import torch
     return torch
+
+
+def loaded_hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process (diagnostics)."""
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                paths.add(line.split()[-1])
+    return sorted(paths)
 
 
 def _stream():

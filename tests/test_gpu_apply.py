@@ -46,6 +46,9 @@ def test_apply_fp64_matches_oracle(case):
     if crack:
         assert plan.n_bonds == len(oracle_bonds(w)) > 0
     f = plan.apply(to_dev(w.b)).cpu().numpy()
+    import paper_2301_11828_amd as msb
+    log("  HIP runtime(s): %s" % msb.loaded_hip_runtimes())
+    assert len(msb.loaded_hip_runtimes()) == 1
     ref = _oracle_apply(w, w.b)
     for c in range(batch):
         err = rel_err(f[c], ref[c])
