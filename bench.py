@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFT-BTTB peridynamic product on one MI355X.
+
+Workload (plate512): 2D static linear bond-based peridynamics, 512 x 512 nodes
+(524,288 DOF), delta = 3h, plane stress, E = 1, alpha = 9E/(pi delta^3), left
+delta-layer constrained, synthetic seeded input.  One step = one FP64 product
+f = A u (x-forward pass, y line product pass, x-inverse pass with the D^e/D^f
+corrections and the constraint mask), inputs resident in HBM.
+
+Printed JSON line: GDOF/s of the product, per-kernel HIP-event timings with the
+roofline of the dominant kernel (algorithmic bytes per launch / mean duration vs
+8 TB/s), the FP32 product rate, CG time to a 1e-10 residual in FP64 and in FP32
+inside FP64 refinement, and the CPU oracle (bond-by-bond FP64 sum, OpenMP) timed
+on a bounded sample of the same product.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def pass_bytes(n, L, d, s):
+    """Algorithmic HBM bytes of each kernel of one 2D product (s = bytes per real).
+
+    x-forward: read u (d N reals), write the half spectrum d * Ny * H complex.
+    y line   : read + write d * H * Ny complex, read 3 * H * Ly real spectra.
+    x-inverse: read d * Ny * H complex, write f (d N reals)."""
+    nx, ny = n
+    Lx, Ly = L
+    H = Lx // 2 + 1
+    N = nx * ny
+    half = d * ny * H * 2 * s
+    return [d * N * s + half, 2 * half + 3 * H * Ly * s, half + d * N * s]
+
+
+def load_traffic(path):
+    """HBM traffic per launch (bytes) of the dominant kernel from a committed
+    rocprofv3 counter summary, if present and matching; else None."""
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic_bytes_per_launch:"):
+                    return float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-tolerance runs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "0")))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2301_11828_amd as msb
+    from paper_2301_11828_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.plate512()
+    plan = msb.Plan(w.n, w.h, w.M, w.alpha, batch=1)
+    plan.set_constraints(w.fixed)
+    L = plan.padded_lengths
+    dofs = w.dofs
+    u64 = torch.from_numpy(W.rng(2, 1).standard_normal((1, 2, w.N))).cuda()
+    f64 = torch.empty_like(u64)
+    u32, f32 = u64.float(), torch.empty_like(u64, dtype=torch.float32)
+
+    def timed(u, f, steps, warmup):
+        for _ in range(warmup):
+            plan.apply(u, f)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(steps):
+            plan.apply(u, f)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, ev0.elapsed_time(ev1) / steps
+
+    print("bench: plate512 FP64 product, %d warmup + %d steps" % (args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    wall, ev_ms = timed(u64, f64, args.steps, args.warmup)
+    ms_step = 1e3 * wall / args.steps
+    value = dofs * args.steps / wall / 1e9
+
+    wall32, ev_ms32 = timed(u32, f32, args.steps, args.warmup)
+
+    # per-kernel durations (HIP events recorded between the kernels on this stream)
+    names = ["x_forward", "y_line_product", "x_inverse"]
+    kms = plan.profile_apply(u64, f64, nrep=max(50, args.steps // 2))
+    kms32 = plan.profile_apply(u32, f32, nrep=max(50, args.steps // 2))
+    pb = pass_bytes(w.n, L, 2, 8)
+    pb32 = pass_bytes(w.n, L, 2, 4)
+    dom = int(np.argmax(kms))
+    achieved = pb[dom] / (kms[dom] * 1e-3) / 1e9
+    traffic = load_traffic(os.path.join(ROOT, "profiles", "y_line_product_plate512_fp64_counters.txt")) \
+        if names[dom] == "y_line_product" else None
+    roofline = {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "bytes_per_launch": pb[dom], "ms_per_launch": round(kms[dom], 5)}
+    chain_ms = float(sum(kms))
+    chain = {"bytes_per_matvec": sum(pb), "kernel_ms_sum": round(chain_ms, 5),
+             "achieved_GBs": round(sum(pb) / (chain_ms * 1e-3) / 1e9, 1),
+             "frac": round(sum(pb) / (chain_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "event_ms_per_matvec": round(ev_ms, 5)}
+
+    line = {
+        "metric": "BTTB PD matvec GDOF/s (%HBM roofline); CG time-to-1e-10, FP32-refined vs FP64",
+        "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "plate512: 2D static linear BB-PD, 512x512 nodes (524288 DOF), "
+                               "delta=3h, left layer constrained, FP64 FFT-BTTB product",
+                   "grid": list(w.n), "M": w.M, "dofs": dofs, "padded": list(L)},
+        "roofline": roofline,
+        "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kms)},
+        "kernels_bytes": dict(zip(names, pb)),
+        "chain": chain,
+        "fp32": {"GDOF_s": round(dofs * args.steps / wall32 / 1e9, 3),
+                 "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kms32)},
+                 "chain_frac": round(sum(pb32) / (float(sum(kms32)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+
+    if not args.no_cg:
+        b = torch.from_numpy(w.b).cuda()
+        cg = {}
+        for prec in ("fp64", "fp32_refined"):
+            print("bench: CG %s to 1e-10" % prec, file=sys.stderr, flush=True)
+            plan.solve(b, precision=prec, tol=1e-10, maxit=200000, graph_block=args.graph_block)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = plan.solve(b, precision=prec, tol=1e-10, maxit=200000, graph_block=args.graph_block)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            cg[prec] = {"seconds": round(dt, 4), "iterations": info[0].inner_iters,
+                        "outer": info[0].outer_iters, "rel_residual_fp64": info[0].rel_residual,
+                        "status": info[0].status}
+        cg["speedup_fp32_refined_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp32_refined"]["seconds"], 3)
+        line["cg"] = cg
+
+    if not args.no_cpu:
+        import oracle as O
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        p = O.Problem(w.n, w.h, w.M, w.alpha)
+        u = u64.cpu().numpy()[0]
+        O.apply(p, u, w.fixed)           # load / warm
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            O.apply(p, u, w.fixed)
+            reps += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        line["cpu_baseline"] = {"value": round(dofs * reps / dt / 1e9, 5), "unit": "GDOF/s",
+                                "cores": cores, "kind": "oracle",
+                                "sample": "%d full FP64 bond-by-bond products of plate512 (%.1f s)" % (reps, dt)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

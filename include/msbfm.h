@@ -192,6 +192,16 @@ msb_status msb_vv_run(msb_plan plan, msb_precision prec, double dt, int64_t nste
 msb_status msb_grad_infl(msb_plan plan, const double *u, const double *w, double *dL_da,
                          void *stream);
 
+/*
+ * Measurement helper: enqueues nrep products f = A u (as msb_apply) with HIP events
+ * recorded on `stream` between the kernels of the chain, and returns in ms[i] the
+ * mean duration in milliseconds of kernel i: 2D x-forward, y line product,
+ * x-inverse (*npass = 3); 3D x-forward, y-forward, z line product, y-inverse,
+ * x-inverse (*npass = 5).  ms: host, capacity >= 5.  Synchronises the stream.
+ */
+msb_status msb_profile_apply(msb_plan plan, msb_precision prec, const void *u, void *f, int nrep,
+                             double *ms, int *npass, void *stream);
+
 /* Plan geometry queries (host): padded FFT lengths L[3] and the number of
  * nodes N per case. */
 msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds);

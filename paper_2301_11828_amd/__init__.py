@@ -28,7 +28,7 @@ _STATUS = {0: "MSB_OK", -1: "MSB_EINVAL", -2: "MSB_ENOMEM", -3: "MSB_EDEVICE", -
 EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "msb_plan_set_bonds",
            "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl",
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
-           "msb_last_error")
+           "msb_profile_apply", "msb_last_error")
 
 
 class MsbError(RuntimeError):
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "msb_vv_run": ([P, I, D, I64, P, P, P, P, P, P, I, P], I),
         "msb_grad_infl": ([P, P, P, P, P], I),
         "msb_plan_info": ([P, P, P, P], I),
+        "msb_profile_apply": ([P, I, P, P, I, P, P, P], I),
         "msb_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -306,6 +307,18 @@ class Plan:
                                self._vec(b, u.dtype, "b"), gp, en.ctypes.data if ne else None,
                                int(energy_every), _stream()))
         return en[:ne]
+
+    def profile_apply(self, u, out=None, nrep: int = 20):
+        """Mean per-kernel durations (ms) of the product chain, timed with HIP events."""
+        torch = _torch()
+        prec = FP64 if u.dtype == torch.float64 else FP32
+        if out is None:
+            out = torch.empty_like(u)
+        ms = np.zeros(8, dtype=np.float64)
+        npass = ctypes.c_int(0)
+        _check(_lib.msb_profile_apply(self._ptr, prec, self._vec(u, u.dtype, "u"), self._vec(out, u.dtype, "out"),
+                                      int(nrep), ms.ctypes.data, ctypes.byref(npass), _stream()))
+        return ms[:npass.value]
 
     def grad_infl(self, u, w) -> np.ndarray:
         """dL/da_k = w . (A_k u)_F for every case: [batch, n_infl]."""

@@ -531,41 +531,50 @@ template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
 }
 
 template <typename T>
-msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st) {
+msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev) {
     using T2 = cplx_t<T>;
+    int evi = 0;
+    auto mark = [&]() -> hipError_t { return ev ? hipEventRecord(ev[evi++], st) : hipSuccess; };
     const int tpc = (a.rows + a.F - 1) / a.F;
     const size_t lds_x = (size_t)2 * ((a.d * a.F + 1) / 2) * a.sx.L * sizeof(T2);
     MSB_HIP(allow_lds(k_xfwd<T>, lds_x));
     MSB_HIP(allow_lds(k_xinv<T>, lds_x));
+    MSB_HIP(mark());
     hipLaunchKernelGGL(k_xfwd<T>, dim3(a.B * tpc), dim3(kThreads), lds_x, st, a, e);
+    MSB_HIP(mark());
     if (a.d == 2) {
         const int lpc = (a.H + a.Fl - 1) / a.Fl;
         const size_t lds = (size_t)2 * a.Fl * a.d * a.sy.L * sizeof(T2);
         MSB_HIP(allow_lds(k_line_prod<T>, lds));
         hipLaunchKernelGGL(k_line_prod<T>, dim3(a.B * lpc), dim3(kThreads), lds, st, a, e, a.T1,
                            a.H, a.Ny, a.sy, a.twy);
+        MSB_HIP(mark());
     } else {
         const int nzc = (a.Nz + a.Fl - 1) / a.Fl;
         const size_t lds_y = (size_t)2 * a.Fl * a.d * a.sy.L * sizeof(T2);
         MSB_HIP(allow_lds(k_yfwd<T>, lds_y));
         MSB_HIP(allow_lds(k_yinv<T>, lds_y));
         hipLaunchKernelGGL(k_yfwd<T>, dim3(a.B * a.H * nzc), dim3(kThreads), lds_y, st, a, e);
+        MSB_HIP(mark());
         const int nlines = a.H * a.Ly;
         const int lpc = (nlines + a.Fl - 1) / a.Fl;
         const size_t lds_z = (size_t)2 * a.Fl * a.d * a.sz.L * sizeof(T2);
         MSB_HIP(allow_lds(k_line_prod<T>, lds_z));
         hipLaunchKernelGGL(k_line_prod<T>, dim3(a.B * lpc), dim3(kThreads), lds_z, st, a, e, a.T2,
                            nlines, a.Nz, a.sz, a.twz);
+        MSB_HIP(mark());
         hipLaunchKernelGGL(k_yinv<T>, dim3(a.B * a.H * nzc), dim3(kThreads), lds_y, st, a, e);
+        MSB_HIP(mark());
     }
     hipLaunchKernelGGL(k_xinv<T>, dim3(a.B * tpc), dim3(kThreads), lds_x, st, a, e);
+    MSB_HIP(mark());
     MSB_HIP(hipGetLastError());
     return MSB_OK;
 }
 
 template PassArgs<double> pass_args<double>(const msb_plan_s *, const DeviceOp &);
 template PassArgs<float> pass_args<float>(const msb_plan_s *, const DeviceOp &);
-template msb_status launch_product<double>(const PassArgs<double> &, const EndArgs<double> &, hipStream_t);
-template msb_status launch_product<float>(const PassArgs<float> &, const EndArgs<float> &, hipStream_t);
+template msb_status launch_product<double>(const PassArgs<double> &, const EndArgs<double> &, hipStream_t, hipEvent_t *);
+template msb_status launch_product<float>(const PassArgs<float> &, const EndArgs<float> &, hipStream_t, hipEvent_t *);
 
 }  // namespace msb

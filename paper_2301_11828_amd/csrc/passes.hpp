@@ -79,8 +79,12 @@ template <typename T> struct EndArgs {
     double *part;        // partial sums [K][B*tiles]
 };
 
+// Launch the pass chain on stream s.  ev (optional, npasses+1 events) is recorded
+// before the first kernel and after each kernel (measurement only).
 template <typename T>
-msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t s);
+msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t s,
+                          hipEvent_t *ev = nullptr);
+inline int n_passes(int dim) { return dim == 2 ? 3 : 5; }
 
 template <typename T>
 PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op);

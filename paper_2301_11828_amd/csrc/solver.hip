@@ -433,6 +433,48 @@ extern "C" msb_status msb_apply_dinfl(msb_plan p, int k, const double *u, double
     return product<double>(p, p->dop[k], u, e, (hipStream_t)stream);
 }
 
+template <typename T>
+static msb_status profile_t(msb_plan_s *p, const T *u, T *f, int nrep, double *ms, int *npass, hipStream_t st) {
+    const int np = n_passes(p->dim);
+    std::vector<hipEvent_t> ev((size_t)(np + 1) * nrep, nullptr);
+    msb_status s = MSB_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) s = MSB_EDEVICE;
+    EndArgs<T> e = end_args<T>();
+    e.epi = EPI_APPLY;
+    e.out = f;
+    PassArgs<T> a = pass_args<T>(p, p->op);
+    e.pio = const_cast<T *>(u);
+    e.uin = u;
+    for (int r = 0; r < nrep && s == MSB_OK; ++r) s = launch_product<T>(a, e, st, ev.data() + (size_t)r * (np + 1));
+    if (s == MSB_OK && hipStreamSynchronize(st) != hipSuccess) s = MSB_EDEVICE;
+    for (int i = 0; i < np && s == MSB_OK; ++i) {
+        double acc = 0.0;
+        for (int r = 0; r < nrep; ++r) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[(size_t)r * (np + 1) + i], ev[(size_t)r * (np + 1) + i + 1]) != hipSuccess)
+                s = MSB_EDEVICE;
+            acc += t;
+        }
+        ms[i] = acc / nrep;
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    *npass = np;
+    if (s != MSB_OK) set_error("event timing failed");
+    return s;
+}
+
+extern "C" msb_status msb_profile_apply(msb_plan p, msb_precision prec, const void *u, void *f, int nrep,
+                                        double *ms, int *npass, void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(u && f && u != f && ms && npass && nrep > 0, MSB_EINVAL, "bad arguments");
+    if (prec == MSB_FP64)
+        return profile_t<double>(p, (const double *)u, (double *)f, nrep, ms, npass, (hipStream_t)stream);
+    MSB_CHECK(prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
+    return profile_t<float>(p, (const float *)u, (float *)f, nrep, ms, npass, (hipStream_t)stream);
+}
+
 // ---------------------------------------------------------------------------- static solve
 extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const double *b, const double *g,
                                        double *u, const msb_solve_opts *opts, msb_solve_info *info,

@@ -1,0 +1,168 @@
+"""Static model eq. (mat:e2) on the GPU: CG in FP64, FP32, and FP32 inside FP64
+iterative refinement, checked against the oracle's dense Cholesky solve (small
+plates) and against the oracle's bond-sum residual (full size)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2301_11828_amd import workloads as W
+from helpers import gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense(w, c=0, g=None):
+    p = oracle_problem(w)
+    return O.solve_dense(p, w.b[c], w.fixed, None if g is None else g[c], oracle_bonds(w))
+
+
+def test_plate32_fp64_cg_matches_cholesky():
+    w = W.plate32()
+    plan = gpu_plan(w)
+    u, info = plan.solve(to_dev(w.b), precision="fp64", tol=1e-14)
+    ref = _dense(w)
+    err = rel_err(u.cpu().numpy()[0], ref)
+    log("plate32 fp64 CG: %d it, residual %.2e, rel err vs Cholesky %.3e" % (info[0].inner_iters, info[0].rel_residual, err))
+    assert info[0].status == 0 and info[0].rel_residual <= 1e-13
+    assert err <= 1e-12
+
+
+def test_plate32_at_1e10_within_condition_bound():
+    """At a 1e-10 residual the error is bounded by kappa * 1e-10 (kappa ~ 68 here)."""
+    w = W.plate32()
+    plan = gpu_plan(w)
+    u, info = plan.solve(to_dev(w.b), precision="fp64", tol=1e-10)
+    err = rel_err(u.cpu().numpy()[0], _dense(w))
+    log("plate32 fp64 tol 1e-10: %d it, rel err %.3e" % (info[0].inner_iters, err))
+    assert info[0].rel_residual <= 1e-10 and err <= 100 * 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32_refined"])
+def test_plate32_refined_fp32_matches_cholesky(prec):
+    w = W.plate32()
+    plan = gpu_plan(w)
+    u, info = plan.solve(to_dev(w.b), precision=prec, tol=1e-13)
+    err = rel_err(u.cpu().numpy()[0], _dense(w))
+    log("plate32 %s: %d outer, %d inner, residual %.2e, rel err %.3e" % (prec, info[0].outer_iters,
+        info[0].inner_iters, info[0].rel_residual, err))
+    assert info[0].status == 0 and err <= 1e-10
+
+
+def test_plain_fp32_error_stated():
+    w = W.plate32()
+    plan = gpu_plan(w)
+    u, info = plan.solve(to_dev(w.b), precision="fp32", tol=1e-5, check=False)
+    err = rel_err(u.cpu().numpy()[0], _dense(w))
+    log("plate32 plain fp32 CG to 1e-5: %d it, FP64 residual %.2e, rel err %.3e" % (info[0].inner_iters, info[0].rel_residual, err))
+    assert err <= 1e-4
+
+
+def test_nonzero_prescribed_displacement_and_crack():
+    """u = g on the layer (lift b_F - K_FC g_C, Sec. 3.4) with a crack and the mixed
+    per-direction constraint of Remark 2."""
+    w = W.small(2, (30, 26), 3, seed=21, fixed="all", crack=True, batch=2)
+    g = np.where(w.fixed[None], np.random.default_rng(5).standard_normal((2, 2, w.N)), 0.0)
+    plan = gpu_plan(w)
+    for prec in ("fp64", "fp32_refined"):
+        u, info = plan.solve(to_dev(w.b), g=to_dev(g), precision=prec, tol=1e-13)
+        uu = u.cpu().numpy()
+        for c in range(2):
+            ref = _dense(w, c, g)
+            err = rel_err(uu[c], ref)
+            log("lift+crack %s case %d: %d it, rel err %.3e" % (prec, c, info[c].inner_iters, err))
+            assert err <= 1e-10
+            assert np.array_equal(uu[c][w.fixed], g[c][w.fixed])
+
+
+def test_mixed_direction_constraint():
+    w = W.small(2, (24, 20), 3, seed=22, fixed="mixed")
+    # constrain y on the right layer too, so no rigid motion remains
+    fx = w.fixed.copy()
+    fx[1] |= W.layer_mask(w.n, w.M, [(0, 1)])[1]
+    w.fixed = fx
+    plan = gpu_plan(w)
+    u, info = plan.solve(to_dev(w.b), precision="fp64", tol=1e-14)
+    err = rel_err(u.cpu().numpy()[0], _dense(w))
+    log("mixed constraint: rel err %.3e" % err)
+    assert err <= 1e-11
+
+
+def test_3d_fp64_and_refined_match_cholesky():
+    w = W.small(3, (9, 8, 10), 2, seed=23, fixed="bottom", batch=2)
+    plan = gpu_plan(w)
+    for prec in ("fp64", "fp32_refined"):
+        u, info = plan.solve(to_dev(w.b), precision=prec, tol=1e-13)
+        uu = u.cpu().numpy()
+        for c in range(2):
+            err = rel_err(uu[c], _dense(w, c))
+            log("3D %s case %d: %d it, rel err %.3e" % (prec, c, info[c].inner_iters, err))
+            assert err <= (1e-11 if prec == "fp64" else 1e-10)
+
+
+def test_batch_equals_single_and_graph_equals_plain():
+    w = W.small(2, (48, 40), 3, seed=24, fixed="left", batch=3)
+    plan = gpu_plan(w)
+    ub, ib = plan.solve(to_dev(w.b), precision="fp64", tol=1e-11)
+    ug, ig = plan.solve(to_dev(w.b), precision="fp64", tol=1e-11, graph_block=8)
+    assert np.array_equal(ub.cpu().numpy(), ug.cpu().numpy())
+    assert [i.inner_iters for i in ib] == [i.inner_iters for i in ig]
+    w1 = W.small(2, (48, 40), 3, seed=24, fixed="left", batch=1)
+    plan1 = gpu_plan(w1)
+    for c in range(3):
+        u1, i1 = plan1.solve(to_dev(w.b[c:c + 1]), precision="fp64", tol=1e-11)
+        assert np.array_equal(u1.cpu().numpy()[0], ub.cpu().numpy()[c])
+        assert i1[0].inner_iters == ib[c].inner_iters
+
+
+def test_plate512_both_precisions_certified_by_oracle():
+    """Full size: the FP64 residual of each solution, recomputed with the oracle's
+    bond sum, is below 1e-10; the two solutions agree within kappa-scaled bounds."""
+    w = W.plate512()
+    plan = gpu_plan(w)
+    p = oracle_problem(w)
+    sols = {}
+    for prec in ("fp64", "fp32_refined"):
+        log("plate512 %s" % prec)
+        u, info = plan.solve(to_dev(w.b), precision=prec, tol=1e-10, maxit=200000)
+        uu = u.cpu().numpy()[0]
+        bp = O.lifted_rhs(p, w.b[0], w.fixed).reshape(-1)
+        r = bp + O.apply(p, uu, w.fixed).reshape(-1)
+        res = np.linalg.norm(r) / np.linalg.norm(bp)
+        log("  %d outer %d inner it, lib residual %.3e, oracle residual %.3e, %.3f s" % (
+            info[0].outer_iters, info[0].inner_iters, info[0].rel_residual, res, info[0].seconds))
+        assert info[0].status == 0 and res <= 1.05e-10
+        sols[prec] = uu
+    d = rel_err(sols["fp32_refined"], sols["fp64"])
+    log("  fp32_refined vs fp64 solution rel diff %.3e" % d)
+    assert d <= 1e-4
+
+
+def test_nan_rhs_is_einval():
+    import paper_2301_11828_amd as msb
+    w = W.plate32()
+    plan = gpu_plan(w)
+    b = w.b.copy()
+    b[0, 0, 500] = np.nan
+    with pytest.raises(msb.MsbError) as e:
+        plan.solve(to_dev(b))
+    assert e.value.status == msb.MSB_EINVAL
+
+
+def test_unconstrained_problem_does_not_converge():
+    """No constraints: K is singular (rigid motions) and a load with a net force has
+    no solution; the solver reports failure instead of returning garbage."""
+    import paper_2301_11828_amd as msb
+    w = W.small(2, (20, 18), 3, seed=25)
+    plan = gpu_plan(w)
+    b = np.ones((1, 2, w.N))
+    u, info = plan.solve(to_dev(b), precision="fp64", tol=1e-12, maxit=3000, check=False)
+    log("unconstrained: status %d after %d it, residual %.2e" % (info[0].status, info[0].inner_iters, info[0].rel_residual))
+    assert info[0].status in (msb.MSB_ENOCONV, msb.MSB_ENOTSPD)
+
+
+def test_maxit_reports_noconv():
+    import paper_2301_11828_amd as msb
+    w = W.plate32()
+    plan = gpu_plan(w)
+    _, info = plan.solve(to_dev(w.b), precision="fp64", tol=1e-12, maxit=3, check=False)
+    assert info[0].status == msb.MSB_ENOCONV and info[0].inner_iters == 3

@@ -1,0 +1,84 @@
+"""Dynamic model eq. (mat:e1) by velocity Verlet (Alg. 2) on the GPU vs the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2301_11828_amd import workloads as W
+from helpers import gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(w, seed):
+    r = np.random.default_rng(seed)
+    u0 = 1e-4 * r.standard_normal((1, w.dim, w.N))
+    v0 = 1e-3 * r.standard_normal((1, w.dim, w.N))
+    return u0, v0
+
+
+def _stable_dt(w):
+    # explicit step well inside the stability limit of the bond stiffness
+    return 0.2 * w.h / np.sqrt(w.alpha * (w.M * w.h) ** 2)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_vv_fp64_matches_oracle(dim):
+    if dim == 2:
+        w = W.small(2, (36, 30), 3, seed=31, fixed="left", crack=True)
+    else:
+        w = W.small(3, (10, 9, 8), 2, seed=32, fixed="bottom")
+    w.rho = 1.7
+    u0, v0 = _setup(w, 1)
+    g = np.where(w.fixed[None], 1e-4, 0.0) if w.fixed is not None else None
+    if g is not None:
+        u0 = np.where(w.fixed[None], g, u0)
+        v0 = np.where(w.fixed[None], 0.0, v0)
+    dt, n, every = _stable_dt(w), 60, 10
+    plan = gpu_plan(w)
+    u, v = to_dev(u0), to_dev(v0)
+    b = to_dev(w.b)
+    a = plan.vv_init(u, b)
+    en = plan.vv_run(dt, n, u, v, a, b, g=None if g is None else to_dev(g), energy_every=every)
+    p = oracle_problem(w)
+    uo, vo, ao, eo = O.vv(p, u0[0], v0[0], w.b[0], dt, n, w.fixed, None if g is None else g[0],
+                          oracle_bonds(w), energy_every=every)
+    eu, ev, ea = rel_err(u.cpu().numpy()[0], uo), rel_err(v.cpu().numpy()[0], vo), rel_err(a.cpu().numpy()[0], ao)
+    ee = np.abs(en - eo).max() / np.abs(eo).max()
+    log("VV fp64 %dD %d steps: rel err u %.2e v %.2e a %.2e energy %.2e" % (dim, n, eu, ev, ea, ee))
+    assert eu <= 1e-12 and ev <= 1e-12 and ea <= 1e-12 and ee <= 1e-11
+
+
+def test_vv_fp32_error_stated():
+    w = W.small(2, (64, 60), 4, seed=33, crack=True)
+    u0, v0 = _setup(w, 2)
+    dt, n = _stable_dt(w), 100
+    import torch
+    plan = gpu_plan(w)
+    u, v, b = to_dev(u0, torch.float32), to_dev(v0, torch.float32), to_dev(w.b, torch.float32)
+    a = plan.vv_init(u, b)
+    plan.vv_run(dt, n, u, v, a, b)
+    p = oracle_problem(w)
+    uo, vo, _, _ = O.vv(p, u0[0].astype(np.float32).astype(np.float64), v0[0].astype(np.float32).astype(np.float64),
+                        w.b[0].astype(np.float32).astype(np.float64), dt, n, None, None, oracle_bonds(w))
+    eu, ev = rel_err(u.double().cpu().numpy()[0], uo), rel_err(v.double().cpu().numpy()[0], vo)
+    log("VV fp32 vs FP64 oracle after %d steps: rel err u %.2e v %.2e" % (n, eu, ev))
+    assert eu <= 1e-4 and ev <= 1e-4
+
+
+def test_crack1024_fp32_short_run_vs_oracle():
+    """Benchmark shape (1024^2, delta = 4h, pre-crack, opposing edge loads) for 20 steps:
+    FP32 state against the FP64 oracle trajectory; error stated."""
+    import torch
+    w = W.crack1024(steps=20)
+    plan = gpu_plan(w)
+    assert plan.n_bonds == 12654
+    u = torch.zeros((1, 2, w.N), dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(u)
+    b = to_dev(w.b, torch.float32)
+    a = plan.vv_init(u, b)
+    plan.vv_run(w.dt, w.steps, u, v, a, b)
+    p = oracle_problem(w)
+    uo, vo, _, _ = O.vv(p, np.zeros((2, w.N)), np.zeros((2, w.N)), w.b[0], w.dt, w.steps, None, None, oracle_bonds(w))
+    eu, ev = rel_err(u.double().cpu().numpy()[0], uo), rel_err(v.double().cpu().numpy()[0], vo)
+    log("crack1024 FP32 VV %d steps vs FP64 oracle: rel err u %.2e v %.2e" % (w.steps, eu, ev))
+    assert eu <= 1e-4 and ev <= 1e-4
