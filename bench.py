@@ -39,16 +39,20 @@ def pass_bytes(n, L, d, s):
     return [d * N * s + half, 2 * half + 3 * H * Ly * s, half + d * N * s]
 
 
-def load_traffic(path):
-    """HBM traffic per launch (bytes) of the dominant kernel from a committed
-    rocprofv3 counter summary, if present and matching; else None."""
+def load_traffic(path, kernel):
+    """HBM traffic per launch (bytes) of `kernel` from a committed rocprofv3 counter
+    summary, or None when absent or taken on a different kernel source."""
+    from paper_2301_11828_amd.profiling import source_hash
     try:
-        with open(path) as f:
-            for line in f:
-                if line.startswith("traffic_bytes_per_launch:"):
-                    return float(line.split(":", 1)[1])
+        lines = open(path).read().splitlines()
     except OSError:
-        pass
+        return None
+    if ("source_hash: %s" % source_hash()) not in lines:
+        return None
+    for line in lines:
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic" and parts[1] == kernel:
+            return float(parts[2])
     return None
 
 
@@ -112,8 +116,9 @@ def main():
     pb32 = pass_bytes(w.n, L, 2, 4)
     dom = int(np.argmax(kms))
     achieved = pb[dom] / (kms[dom] * 1e-3) / 1e9
-    traffic = load_traffic(os.path.join(ROOT, "profiles", "y_line_product_plate512_fp64_counters.txt")) \
-        if names[dom] == "y_line_product" else None
+    kname = {"x_forward": "k_xfwd<double>", "y_line_product": "k_line_prod<double>",
+             "x_inverse": "k_xinv<double>"}[names[dom]]
+    traffic = load_traffic(os.path.join(ROOT, "profiles", "plate512_fp64_hbm_counters.txt"), kname)
     roofline = {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "bytes_per_launch": pb[dom], "ms_per_launch": round(kms[dom], 5)}
@@ -139,6 +144,14 @@ def main():
                  "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kms32)},
                  "chain_frac": round(sum(pb32) / (float(sum(kms32)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
+
+    # calibration for the HBM byte counters: one plain 64 MiB device copy
+    src = torch.empty(8 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     if not args.no_cg:
         b = torch.from_numpy(w.b).cuda()

@@ -45,7 +45,7 @@ template <> struct cplx_of<float> { using type = float2; };
 template <typename T> using cplx_t = typename cplx_of<T>::type;
 
 // ------------------------------------------------------------------ FFT schedule
-constexpr int kMaxPasses = 16;
+constexpr int kMaxPasses = 12;
 
 // One transform axis: length L = product of radix[0..np), each radix in {2,3,4,5,8}.
 // Twiddle table tw[t] = exp(-2 pi i t / L), t < L (device, both precisions).
@@ -57,18 +57,45 @@ struct FftAxis {
     float2 *tw32 = nullptr;
 };
 
-// Kernel-argument copy of an axis schedule (by value).
+// Division by a runtime constant d < 2^16 for numerators < 2^16:
+// q = umulhi(n, ceil(2^32/d)) is exact in that range (m = 0 encodes d = 1).
+inline uint32_t div_magic(uint32_t d) { return d <= 1 ? 0u : (uint32_t)((((uint64_t)1 << 32) + d - 1) / d); }
+
+// Per-pass constants of a Stockham schedule (kernel argument, by value).
+struct FftPass {
+    int R;          // radix
+    int Ns;         // points already combined (product of earlier radices)
+    int nb;         // butterflies per signal, L / R
+    int twstep;     // L / (Ns R)
+    uint32_t m_nb;  // div_magic(nb)
+    uint32_t m_Ns;  // div_magic(Ns)
+};
+
 struct FftSched {
     int L;
     int np;
-    int radix[kMaxPasses];
+    FftPass ps[kMaxPasses];
 };
 
 inline FftSched sched_of(const FftAxis &a) {
     FftSched s;
     s.L = a.L;
     s.np = a.np;
-    for (int i = 0; i < kMaxPasses; ++i) s.radix[i] = a.radix[i];
+    int Ns = 1;
+    for (int i = 0; i < kMaxPasses; ++i) {
+        FftPass &p = s.ps[i];
+        if (i < a.np) {
+            p.R = a.radix[i];
+            p.Ns = Ns;
+            p.nb = a.L / p.R;
+            p.twstep = a.L / (Ns * p.R);
+            p.m_nb = div_magic((uint32_t)p.nb);
+            p.m_Ns = div_magic((uint32_t)Ns);
+            Ns *= p.R;
+        } else {
+            p = FftPass{1, 1, 1, 1, 0u, 0u};
+        }
+    }
     return s;
 }
 

@@ -158,27 +158,42 @@ template <typename T, typename T2, int DIR> struct Dft<T, T2, 8, DIR> {
     }
 };
 
-// One Stockham pass over S signals of length L stored back to back.
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m) { return m ? __umulhi(n, m) : n; }
+
+// Division by a block-uniform divisor d < 2^16 for numerators n < 2^16 (exact);
+// falls back to plain division when the numerator range is larger.
+struct FastDiv {
+    uint32_t d, m;
+    bool exact;
+    __device__ __forceinline__ FastDiv(uint32_t dd, uint32_t nmax) : d(dd) {
+        exact = dd < 65536u && nmax < 65536u;
+        m = dd <= 1 ? 0u : (uint32_t)((0x100000000ull + dd - 1) / dd);
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t n) const { return exact ? fdiv(n, m) : n / d; }
+};
+
+// One Stockham pass over S signals of length L stored back to back; twiddles in LDS.
 template <typename T, typename T2, int R, int DIR>
 __device__ __forceinline__ void stockham_pass(const T2 *__restrict__ in, T2 *__restrict__ out, int S,
-                                              int L, int Ns, const T2 *__restrict__ tw, int tid,
-                                              int nt) {
-    const int nb = L / R;
+                                              int L, const FftPass &ps, const T2 *__restrict__ tw,
+                                              int tid, int nt) {
+    const int nb = ps.nb;
+    const int Ns = ps.Ns;
     const int total = S * nb;
-    const int twstep = L / (Ns * R);
     for (int t = tid; t < total; t += nt) {
-        const int s = t / nb;
+        const int s = (int)fdiv((uint32_t)t, ps.m_nb);
         const int j = t - s * nb;
         const T2 *x = in + s * L;
         T2 v[R];
 #pragma unroll
         for (int m = 0; m < R; ++m) v[m] = x[j + m * nb];
-        const int jq = j / Ns;
+        const int jq = (int)fdiv((uint32_t)j, ps.m_Ns);
         const int k = j - jq * Ns;
         if (Ns > 1) {
+            const int step = k * ps.twstep;
 #pragma unroll
             for (int m = 1; m < R; ++m) {
-                T2 w = tw[k * m * twstep];
+                T2 w = tw[m * step];
                 if (DIR > 0) w.y = -w.y;
                 v[m] = c_mul(v[m], w);
             }
@@ -190,29 +205,65 @@ __device__ __forceinline__ void stockham_pass(const T2 *__restrict__ in, T2 *__r
     }
 }
 
-// Full transform of S signals in LDS buffer a (scratch b); returns the buffer that
-// holds the result.  Every thread of the block must call it (it synchronises).
+// Full transform of S signals in LDS buffer a (scratch b); tw: the length-L twiddle
+// table staged in LDS.  Returns the buffer that holds the result.  Every thread of
+// the block must call it (it synchronises).
 template <typename T, typename T2, int DIR>
 __device__ T2 *fft_lds(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__restrict__ tw,
                        int tid, int nt) {
-    int Ns = 1;
     const int L = sc.L;
-    for (int ps = 0; ps < sc.np; ++ps) {
-        const int R = sc.radix[ps];
-        switch (R) {
-            case 2: stockham_pass<T, T2, 2, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
-            case 3: stockham_pass<T, T2, 3, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
-            case 4: stockham_pass<T, T2, 4, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
-            case 5: stockham_pass<T, T2, 5, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
-            default: stockham_pass<T, T2, 8, DIR>(a, b, S, L, Ns, tw, tid, nt); break;
+    for (int p = 0; p < sc.np; ++p) {
+        const FftPass &ps = sc.ps[p];
+        switch (ps.R) {
+            case 2: stockham_pass<T, T2, 2, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+            case 3: stockham_pass<T, T2, 3, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+            case 4: stockham_pass<T, T2, 4, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+            case 5: stockham_pass<T, T2, 5, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+            default: stockham_pass<T, T2, 8, DIR>(a, b, S, L, ps, tw, tid, nt); break;
         }
         __syncthreads();
         T2 *t = a;
         a = b;
         b = t;
-        Ns *= R;
     }
     return a;
+}
+
+// Ordering point between Stockham stages of signals owned by a single wavefront:
+// LDS traffic of one wave is processed in order, so a wave-scope fence plus a
+// scheduling barrier is all that is needed (no block-wide s_barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Transform of S signals owned by one wavefront (lane = 0..63) in its private LDS
+// buffers a/b; returns the buffer holding the result.  No block barrier.
+template <typename T, typename T2, int DIR>
+__device__ T2 *fft_wave(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__restrict__ tw, int lane) {
+    const int L = sc.L;
+    for (int p = 0; p < sc.np; ++p) {
+        const FftPass &ps = sc.ps[p];
+        switch (ps.R) {
+            case 2: stockham_pass<T, T2, 2, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+            case 3: stockham_pass<T, T2, 3, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+            case 4: stockham_pass<T, T2, 4, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+            case 5: stockham_pass<T, T2, 5, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+            default: stockham_pass<T, T2, 8, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+        }
+        wave_sync();
+        T2 *t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Copy a length-L twiddle table into LDS (caller synchronises before use).
+template <typename T2>
+__device__ __forceinline__ void stage_twiddles(T2 *dst, const T2 *__restrict__ src, int L, int tid, int nt) {
+    for (int i = tid; i < L; i += nt) dst[i] = src[i];
 }
 
 // blockIdx -> logical tile so that the blocks resident on one XCD (hardware hands

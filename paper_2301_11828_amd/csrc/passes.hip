@@ -27,13 +27,56 @@ __device__ __forceinline__ int comp_of(int a, int b, int d) {
     return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);   // xx xy xz yy yz zz
 }
 
+// Work decomposition.  A block holds a set of signal slots in LDS.  Each slot set
+// is processed by a "team": with BLOCK = true the whole block cooperates on all of
+// the block's signals (block barriers between Stockham stages, every SIMD busy on a
+// few signals: best when there are few signals per CU); with BLOCK = false every
+// wavefront owns its own slots and runs all stages with wave-scope ordering only
+// (no block barriers: best when there are many signals per CU).
+template <bool BLOCK> struct Team {
+    int tid, nt;     // thread index within the team, team size
+    int w;           // wave index in the block
+    __device__ Team() {
+        w = threadIdx.x >> 6;
+        if (BLOCK) {
+            tid = threadIdx.x;
+            nt = blockDim.x;
+        } else {
+            tid = threadIdx.x & 63;
+            nt = 64;
+        }
+    }
+    __device__ __forceinline__ void sync() const {
+        if (BLOCK) __syncthreads();
+        else wave_sync();
+    }
+    // slot range [s0, s0 + n) of this team, given slots_per_wave in wave mode
+    __device__ __forceinline__ void slots(int total, int per_wave, int &s0, int &n) const {
+        if (BLOCK) {
+            s0 = 0;
+            n = total;
+        } else {
+            s0 = w * per_wave;
+            n = max(0, min(per_wave, total - s0));
+        }
+    }
+};
+
+template <typename T, typename T2, int DIR, bool BLOCK>
+__device__ __forceinline__ T2 *team_fft(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *tw, const Team<BLOCK> &tm) {
+    if (BLOCK) return fft_lds<T, T2, DIR>(a, b, S, sc, tw, tm.tid, tm.nt);
+    return fft_wave<T, T2, DIR>(a, b, S, sc, tw, tm.tid);
+}
+
 // ---------------------------------------------------------------------------- x-forward
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
+// F grid rows per block; complex slot s packs real rows sig = 2s and 2s+1
+// (sig = c * nr + r: component c of grid row r0 + r).  Wave mode: one slot per wave.
+template <typename T, bool BLOCK>
+__global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[80];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const Team<BLOCK> tm;
     const int tpc = (a.rows + a.F - 1) / a.F;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tpc;
@@ -43,7 +86,8 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(PassArgs<T> a, EndArgs<T> e) 
     const int S = (nsig + 1) >> 1;
     const int Lx = a.sx.L;
     const int Smax = (a.d * a.F + 1) >> 1;
-    T2 *bufA = reinterpret_cast<T2 *>(smem);
+    T2 *twl = reinterpret_cast<T2 *>(smem);
+    T2 *bufA = twl + Lx;
     T2 *bufB = bufA + (size_t)Smax * Lx;
     if (e.case_done && e.case_done[b]) return;
 
@@ -51,63 +95,81 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(PassArgs<T> a, EndArgs<T> e) 
     if (e.pro == PRO_CG_P) {
         // r.r of the current residual decides convergence (flag 1) or a
         // non-finite residual (flag 3) before any work; beta = r.r / r_old.r_old
-        const double rn = block_sum_partials(e.beta_part + (size_t)b * e.nbeta, e.nbeta, red, tid, nt);
+        const double rn = block_sum_partials(e.beta_part + (size_t)b * e.nbeta, e.nbeta, red, threadIdx.x, blockDim.x);
         if (e.thresh && !(rn > e.thresh[b])) {
-            if (r0 == 0 && tid == 0) e.done_rw[b] = (rn == rn && rn <= 1e300) ? 1 : 3;
+            if (r0 == 0 && threadIdx.x == 0) e.done_rw[b] = (rn == rn && rn <= 1e300) ? 1 : 3;
             return;
         }
         if (e.beta_part_old) {
-            const double ro = block_sum_partials(e.beta_part_old + (size_t)b * e.nbeta, e.nbeta, red, tid, nt);
+            const double ro = block_sum_partials(e.beta_part_old + (size_t)b * e.nbeta, e.nbeta, red, threadIdx.x, blockDim.x);
             beta = ro > 0.0 ? T(rn / ro) : T(0);
         }
     }
+    stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);
+    __syncthreads();
+    int s0, ns;
+    tm.slots(S, 1, s0, ns);
+
     const T hdt2 = T(0.5 * e.dt * e.dt);
     const T dtt = T(e.dt);
     const size_t cbase = (size_t)b * a.d * a.N;
-
-    for (int idx = tid; idx < S * Lx; idx += nt) {
-        const int s = idx / Lx;
-        const int n = idx - s * Lx;
-        T2 z;
-        z.x = T(0);
-        z.y = T(0);
-        if (n < a.Nx) {
+    for (int s = s0; s < s0 + ns; ++s) {
+        size_t rowaddr[2];
+        int rowfix[2];
+        bool has[2];
 #pragma unroll
-            for (int h2 = 0; h2 < 2; ++h2) {
-                const int sig = 2 * s + h2;
-                if (sig >= nsig) break;
-                const int c = sig / nr;
-                const int r = sig - c * nr;
-                const int node = (r0 + r) * a.Nx + n;
-                const size_t addr = cbase + (size_t)c * a.N + node;
-                T v;
-                if (e.pro == PRO_NONE) {
-                    v = e.pio[addr];
-                } else if (e.pro == PRO_CG_P) {
-                    v = e.pr[addr] + beta * e.pio[addr];
-                    e.pio[addr] = v;
-                } else {
-                    const bool fx = a.fixed && a.fixed[(size_t)c * a.N + node];
-                    if (fx) v = e.pg ? e.pg[addr] : T(0);
-                    else v = e.pio[addr] + dtt * e.pr[addr] + hdt2 * e.pa[addr];
-                    e.pio[addr] = v;
-                }
-                if (h2 == 0) z.x = v;
-                else z.y = v;
-            }
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const int sig = 2 * s + h2;
+            has[h2] = sig < nsig;
+            const int c = has[h2] ? sig / nr : 0;
+            const int r = has[h2] ? sig - c * nr : 0;
+            rowaddr[h2] = cbase + (size_t)c * a.N + (size_t)(r0 + r) * a.Nx;
+            rowfix[h2] = c * a.N + (r0 + r) * a.Nx;
         }
-        bufA[idx] = z;
+        T2 *dst = bufA + (size_t)s * Lx;
+        for (int n = tm.tid; n < Lx; n += tm.nt) {
+            T2 z;
+            z.x = T(0);
+            z.y = T(0);
+            if (n < a.Nx) {
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    if (!has[h2]) break;
+                    const size_t addr = rowaddr[h2] + n;
+                    T v;
+                    if (e.pro == PRO_NONE) {
+                        v = e.pio[addr];
+                    } else if (e.pro == PRO_CG_P) {
+                        v = e.pr[addr] + beta * e.pio[addr];
+                        e.pio[addr] = v;
+                    } else {
+                        const bool fx = a.fixed && a.fixed[rowfix[h2] + n];
+                        if (fx) v = e.pg ? e.pg[addr] : T(0);
+                        else v = e.pio[addr] + dtt * e.pr[addr] + hdt2 * e.pa[addr];
+                        e.pio[addr] = v;
+                    }
+                    if (h2 == 0) z.x = v;
+                    else z.y = v;
+                }
+            }
+            dst[n] = z;
+        }
     }
-    __syncthreads();
-    T2 *res = fft_lds<T, T2, -1>(bufA, bufB, S, a.sx, a.twx, tid, nt);
+    tm.sync();
+    if (ns > 0) team_fft<T, T2, -1, BLOCK>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
+    if (!BLOCK) __syncthreads();
+    const T2 *res = (a.sx.np & 1) ? bufB : bufA;
 
-    // unpack the two real transforms of each complex one; x-spectrum k < H
-    for (int idx = tid; idx < nsig * a.H; idx += nt) {
-        const int kx = idx / nsig;
+    // unpack the two real transforms of each slot; x-spectrum k < H into
+    // [b][c][z][kx][y]; the whole block stores, consecutive threads on consecutive
+    // rows of one kx (the transposed layout's contiguous axis)
+    const FastDiv dv(nsig, nsig * a.H), dr(nr, nsig), dy(a.Ny, a.rows);
+    for (int idx = threadIdx.x; idx < nsig * a.H; idx += blockDim.x) {
+        const int kx = dv.div(idx);
         const int sig = idx - kx * nsig;
-        const int s = sig >> 1;
-        const T2 Z = res[s * Lx + kx];
-        const T2 Zm = res[s * Lx + (kx == 0 ? 0 : Lx - kx)];
+        const T2 *zs = res + (size_t)(sig >> 1) * Lx;
+        const T2 Z = zs[kx];
+        const T2 Zm = zs[kx == 0 ? 0 : Lx - kx];
         T2 X;
         if ((sig & 1) == 0) {
             X.x = T(0.5) * (Z.x + Zm.x);
@@ -116,61 +178,70 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(PassArgs<T> a, EndArgs<T> e) 
             X.x = T(0.5) * (Z.y + Zm.y);
             X.y = T(0.5) * (Zm.x - Z.x);
         }
-        const int c = sig / nr;
+        const int c = dr.div(sig);
         const int row = r0 + sig - c * nr;
-        const int z = row / a.Ny;
+        const int z = dy.div(row);
         const int y = row - z * a.Ny;
         a.T1[((((size_t)b * a.d + c) * a.Nz + z) * a.H + kx) * a.Ny + y] = X;
     }
 }
 
 // ---------------------------------------------------------------------------- line product
-// Lines of one case: data[((b*d + c)*nlines + line)*Nl + t], t < Nl.  Each line is
-// zero-padded to L, transformed, multiplied by the real symmetric d x d spectrum
-// block (spec[(comp*nlines + line)*L + k]) and transformed back.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
-                                                       cplx_t<T> *data, int nlines, int Nl,
-                                                       FftSched sl, const cplx_t<T> *twl) {
+// Lines of one case: data[((b*d + c)*nlines + line)*Nl + t], t < Nl.  Fl lines per
+// block, slot = (line, component); wave mode: one line (d slots) per wave.  Each
+// line is zero-padded to L, transformed, multiplied by the real symmetric d x d
+// spectrum block spec[(comp*nlines + line)*L + k] and transformed back.
+template <typename T, bool BLOCK>
+__global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
+                                                   cplx_t<T> *data, int nlines, int Nl,
+                                                   FftSched sl, const cplx_t<T> *twg) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const Team<BLOCK> tm;
     const int tpc = (nlines + a.Fl - 1) / a.Fl;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tpc;
     const int l0 = (tile - b * tpc) * a.Fl;
     const int nl = min(a.Fl, nlines - l0);
     const int d = a.d;
-    const int S = nl * d;
     const int L = sl.L;
-    T2 *bufA = reinterpret_cast<T2 *>(smem);
+    T2 *tws = reinterpret_cast<T2 *>(smem);
+    T2 *bufA = tws + L;
     T2 *bufB = bufA + (size_t)a.Fl * d * L;
     if (e.case_done && e.case_done[b]) return;
-
-    for (int idx = tid; idx < S * L; idx += nt) {
-        const int s = idx / L;
-        const int t = idx - s * L;
-        const int li = s / d;
-        const int c = s - li * d;
-        T2 v;
-        v.x = T(0);
-        v.y = T(0);
-        if (t < Nl) v = data[(((size_t)b * d + c) * nlines + l0 + li) * Nl + t];
-        bufA[idx] = v;
-    }
+    stage_twiddles(tws, twg, L, threadIdx.x, blockDim.x);
     __syncthreads();
-    T2 *res = fft_lds<T, T2, -1>(bufA, bufB, S, sl, twl, tid, nt);
-    T2 *oth = (res == bufA) ? bufB : bufA;
+    int s0, ns;
+    tm.slots(nl * d, d, s0, ns);
+    if (ns <= 0) return;
+
+    for (int s = s0; s < s0 + ns; ++s) {
+        const int li = s / d, c = s - li * d;
+        const T2 *src = data + (((size_t)b * d + c) * nlines + l0 + li) * Nl;
+        T2 *dst = bufA + (size_t)s * L;
+        for (int t = tm.tid; t < L; t += tm.nt) {
+            T2 v;
+            v.x = T(0);
+            v.y = T(0);
+            if (t < Nl) v = src[t];
+            dst[t] = v;
+        }
+    }
+    tm.sync();
+    T2 *res = team_fft<T, T2, -1, BLOCK>(bufA + (size_t)s0 * L, bufB + (size_t)s0 * L, ns, sl, tws, tm);
+    T2 *oth = (res == bufA + (size_t)s0 * L) ? bufB + (size_t)s0 * L : bufA + (size_t)s0 * L;
 
     const T *spec = a.spec + (size_t)b * a.spec_slot;
     const size_t cstride = (size_t)nlines * L;
-    for (int idx = tid; idx < nl * L; idx += nt) {
-        const int li = idx / L;
-        const int k = idx - li * L;
-        const size_t g0 = (size_t)(l0 + li) * L + k;
-        T2 *u = res + (size_t)li * d * L + k;
+    const int lines_here = ns / d;
+    for (int idx = tm.tid; idx < lines_here * L; idx += tm.nt) {
+        const int lk = idx / L;
+        const int k = idx - lk * L;
+        const int line = l0 + s0 / d + lk;
+        const T *g0 = spec + (size_t)line * L + k;
+        T2 *u = res + (size_t)lk * d * L + k;
         if (d == 2) {
-            const T gxx = spec[g0], gxy = spec[cstride + g0], gyy = spec[2 * cstride + g0];
+            const T gxx = g0[0], gxy = g0[cstride], gyy = g0[2 * cstride];
             const T2 ux = u[0], uy = u[L];
             T2 fx, fy;
             fx.x = gxx * ux.x + gxy * uy.x;
@@ -182,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_line_prod(PassArgs<T> a, EndArgs<T
         } else {
             T g[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) g[q] = spec[q * cstride + g0];
+            for (int q = 0; q < 6; ++q) g[q] = g0[q * cstride];
             const T2 ux = u[0], uy = u[L], uz = u[2 * L];
             T2 fx, fy, fz;
             fx.x = g[0] * ux.x + g[1] * uy.x + g[2] * uz.x;
@@ -196,24 +267,25 @@ __global__ __launch_bounds__(kThreads) void k_line_prod(PassArgs<T> a, EndArgs<T
             u[2 * L] = fz;
         }
     }
-    __syncthreads();
-    T2 *out = fft_lds<T, T2, 1>(res, oth, S, sl, twl, tid, nt);
-    for (int idx = tid; idx < S * Nl; idx += nt) {
-        const int s = idx / Nl;
-        const int t = idx - s * Nl;
-        const int li = s / d;
-        const int c = s - li * d;
-        data[(((size_t)b * d + c) * nlines + l0 + li) * Nl + t] = out[(size_t)s * L + t];
+    tm.sync();
+    T2 *out = team_fft<T, T2, 1, BLOCK>(res, oth, ns, sl, tws, tm);
+    for (int s = 0; s < ns; ++s) {
+        const int sg = s0 + s;
+        const int li = sg / d, c = sg - li * d;
+        T2 *dst = data + (((size_t)b * d + c) * nlines + l0 + li) * Nl;
+        const T2 *o = out + (size_t)s * L;
+        for (int t = tm.tid; t < Nl; t += tm.nt) dst[t] = o[t];
     }
 }
 
 // ---------------------------------------------------------------------------- 3D y passes
-// y-forward: T1[b][c][z][kx][y<Ny] -> T2[b][c][kx][ky<Ly][z], Fl z-planes per block.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
+// y-forward: T1[b][c][z][kx][y<Ny] -> T2[b][c][kx][ky<Ly][z].  Block = Fl consecutive
+// z of one (b, kx); slot = (z, component); wave mode: one z-line (d slots) per wave.
+template <typename T, bool BLOCK>
+__global__ __launch_bounds__(1024) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const Team<BLOCK> tm;
     const int d = a.d, Ly = a.sy.L;
     const int nzc = (a.Nz + a.Fl - 1) / a.Fl;
     const int tpc = a.H * nzc;
@@ -223,38 +295,47 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(PassArgs<T> a, EndArgs<T> e) 
     const int kx = rem / nzc;
     const int z0 = (rem - kx * nzc) * a.Fl;
     const int nz = min(a.Fl, a.Nz - z0);
-    const int S = nz * d;
-    T2 *bufA = reinterpret_cast<T2 *>(smem);
+    T2 *twl = reinterpret_cast<T2 *>(smem);
+    T2 *bufA = twl + Ly;
     T2 *bufB = bufA + (size_t)a.Fl * d * Ly;
     if (e.case_done && e.case_done[b]) return;
-    for (int idx = tid; idx < S * Ly; idx += nt) {
-        const int s = idx / Ly;
-        const int t = idx - s * Ly;
-        const int zl = s / d;
-        const int c = s - zl * d;
-        T2 v;
-        v.x = T(0);
-        v.y = T(0);
-        if (t < a.Ny) v = a.T1[((((size_t)b * d + c) * a.Nz + z0 + zl) * a.H + kx) * a.Ny + t];
-        bufA[idx] = v;
-    }
+    stage_twiddles(twl, a.twy, Ly, threadIdx.x, blockDim.x);
     __syncthreads();
-    T2 *res = fft_lds<T, T2, -1>(bufA, bufB, S, a.sy, a.twy, tid, nt);
-    for (int idx = tid; idx < S * Ly; idx += nt) {
-        const int zl = idx % nz;
-        const int rest = idx / nz;
-        const int c = rest % d;
-        const int ky = rest / d;
-        a.T2[((((size_t)b * d + c) * a.H + kx) * Ly + ky) * a.Nz + z0 + zl] = res[(zl * d + c) * Ly + ky];
+    int s0, ns;
+    tm.slots(nz * d, d, s0, ns);
+    for (int s = s0; s < s0 + ns; ++s) {
+        const int zl = s / d, c = s - zl * d;
+        const T2 *src = a.T1 + ((((size_t)b * d + c) * a.Nz + z0 + zl) * a.H + kx) * a.Ny;
+        T2 *dst = bufA + (size_t)s * Ly;
+        for (int t = tm.tid; t < Ly; t += tm.nt) {
+            T2 v;
+            v.x = T(0);
+            v.y = T(0);
+            if (t < a.Ny) v = src[t];
+            dst[t] = v;
+        }
+    }
+    tm.sync();
+    if (ns > 0) team_fft<T, T2, -1, BLOCK>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
+    if (!BLOCK) __syncthreads();
+    const T2 *res = (a.sy.np & 1) ? bufB : bufA;
+    // the whole block stores, consecutive threads on consecutive z (T2's contiguous axis)
+    const FastDiv dz(nz, nz * d * Ly), dd(d, d * Ly);
+    for (int idx = threadIdx.x; idx < nz * d * Ly; idx += blockDim.x) {
+        const int rest = dz.div(idx);
+        const int zl = idx - rest * nz;
+        const int ky = dd.div(rest);
+        const int c = rest - ky * d;
+        a.T2[((((size_t)b * d + c) * a.H + kx) * Ly + ky) * a.Nz + z0 + zl] = res[(size_t)(zl * d + c) * Ly + ky];
     }
 }
 
 // y-inverse: T2[b][c][kx][ky][z] -> T1[b][c][z][kx][y<Ny]
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
+template <typename T, bool BLOCK>
+__global__ __launch_bounds__(1024) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const Team<BLOCK> tm;
     const int d = a.d, Ly = a.sy.L;
     const int nzc = (a.Nz + a.Fl - 1) / a.Fl;
     const int tpc = a.H * nzc;
@@ -264,35 +345,48 @@ __global__ __launch_bounds__(kThreads) void k_yinv(PassArgs<T> a, EndArgs<T> e) 
     const int kx = rem / nzc;
     const int z0 = (rem - kx * nzc) * a.Fl;
     const int nz = min(a.Fl, a.Nz - z0);
-    const int S = nz * d;
-    T2 *bufA = reinterpret_cast<T2 *>(smem);
+    T2 *twl = reinterpret_cast<T2 *>(smem);
+    T2 *bufA = twl + Ly;
     T2 *bufB = bufA + (size_t)a.Fl * d * Ly;
     if (e.case_done && e.case_done[b]) return;
-    for (int idx = tid; idx < S * Ly; idx += nt) {
-        const int zl = idx % nz;
-        const int rest = idx / nz;
-        const int c = rest % d;
-        const int ky = rest / d;
-        bufA[(zl * d + c) * Ly + ky] = a.T2[((((size_t)b * d + c) * a.H + kx) * Ly + ky) * a.Nz + z0 + zl];
+    stage_twiddles(twl, a.twy, Ly, threadIdx.x, blockDim.x);
+    __syncthreads();
+    int s0, ns;
+    tm.slots(nz * d, d, s0, ns);
+    {
+        // the whole block loads, consecutive threads on consecutive z
+        const FastDiv dz(nz, nz * d * Ly), dd(d, d * Ly);
+        for (int idx = threadIdx.x; idx < nz * d * Ly; idx += blockDim.x) {
+            const int rest = dz.div(idx);
+            const int zl = idx - rest * nz;
+            const int ky = dd.div(rest);
+            const int c = rest - ky * d;
+            bufA[(size_t)(zl * d + c) * Ly + ky] = a.T2[((((size_t)b * d + c) * a.H + kx) * Ly + ky) * a.Nz + z0 + zl];
+        }
     }
     __syncthreads();
-    T2 *res = fft_lds<T, T2, 1>(bufA, bufB, S, a.sy, a.twy, tid, nt);
-    for (int idx = tid; idx < S * a.Ny; idx += nt) {
-        const int s = idx / a.Ny;
-        const int t = idx - s * a.Ny;
-        const int zl = s / d;
-        const int c = s - zl * d;
-        a.T1[((((size_t)b * d + c) * a.Nz + z0 + zl) * a.H + kx) * a.Ny + t] = res[(size_t)s * Ly + t];
+    if (ns <= 0) return;
+    T2 *res = team_fft<T, T2, 1, BLOCK>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
+    for (int s = 0; s < ns; ++s) {
+        const int sg = s0 + s;
+        const int zl = sg / d, c = sg - zl * d;
+        T2 *dst = a.T1 + ((((size_t)b * d + c) * a.Nz + z0 + zl) * a.H + kx) * a.Ny;
+        const T2 *o = res + (size_t)s * Ly;
+        for (int t = tm.tid; t < a.Ny; t += tm.nt) dst[t] = o[t];
     }
 }
 
 // ---------------------------------------------------------------------------- x-inverse
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
+// Slots as in the x-forward pass.  Each slot's full x-spectrum is rebuilt from the
+// half spectra of its two real rows, transformed back, then the broken-bond
+// correction of those rows, the incomplete-horizon diagonal, the constraint mask and
+// the fused epilogue are applied.
+template <typename T, bool BLOCK>
+__global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[80];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const Team<BLOCK> tm;
     const int tpc = (a.rows + a.F - 1) / a.F;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tpc;
@@ -303,146 +397,154 @@ __global__ __launch_bounds__(kThreads) void k_xinv(PassArgs<T> a, EndArgs<T> e) 
     const int S = (nsig + 1) >> 1;
     const int Lx = a.sx.L;
     const int Smax = (d * a.F + 1) >> 1;
-    T2 *bufA = reinterpret_cast<T2 *>(smem);
+    T2 *twl = reinterpret_cast<T2 *>(smem);
+    T2 *bufA = twl + Lx;
     T2 *bufB = bufA + (size_t)Smax * Lx;
     if (e.case_done && e.case_done[b]) return;
+    stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);
+    __syncthreads();
+    int s0, ns;
+    tm.slots(S, 1, s0, ns);
 
-    // rebuild the full x-spectra of two real rows as one complex spectrum
-    for (int idx = tid; idx < S * a.H; idx += nt) {
-        const int kx = idx / S;
-        const int s = idx - kx * S;
-        T2 Xa, Xb;
-        Xb.x = T(0);
-        Xb.y = T(0);
-        {
-            const int sig = 2 * s, c = sig / nr, row = r0 + sig - c * nr;
-            const int z = row / a.Ny, y = row - z * a.Ny;
-            Xa = a.T1[((((size_t)b * d + c) * a.Nz + z) * a.H + kx) * a.Ny + y];
-        }
-        if (2 * s + 1 < nsig) {
-            const int sig = 2 * s + 1, c = sig / nr, row = r0 + sig - c * nr;
-            const int z = row / a.Ny, y = row - z * a.Ny;
-            Xb = a.T1[((((size_t)b * d + c) * a.Nz + z) * a.H + kx) * a.Ny + y];
-        }
-        T2 Z;
-        Z.x = Xa.x - Xb.y;
-        Z.y = Xa.y + Xb.x;
-        bufA[s * Lx + kx] = Z;
-        const int m = Lx - kx;
-        if (kx >= 1 && m >= a.H) {
-            T2 Zm;
-            Zm.x = Xa.x + Xb.y;
-            Zm.y = -Xa.y + Xb.x;
-            bufA[s * Lx + m] = Zm;
+    // full spectrum Z = Xa + i Xb of every slot with the Hermitian halves mirrored;
+    // the whole block loads, consecutive threads on consecutive rows of one kx
+    {
+        const FastDiv dv(S, S * a.H), dr(nr, nsig), dy(a.Ny, a.rows);
+        for (int idx = threadIdx.x; idx < S * a.H; idx += blockDim.x) {
+            const int kx = dv.div(idx);
+            const int sl = idx - kx * S;
+            T2 X[2];
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                X[h2].x = T(0);
+                X[h2].y = T(0);
+                const int sig = 2 * sl + h2;
+                if (sig < nsig) {
+                    const int c = dr.div(sig), row = r0 + sig - c * nr;
+                    const int z = dy.div(row), y = row - z * a.Ny;
+                    X[h2] = a.T1[((((size_t)b * d + c) * a.Nz + z) * a.H + kx) * a.Ny + y];
+                }
+            }
+            T2 *zs = bufA + (size_t)sl * Lx;
+            T2 Z;
+            Z.x = X[0].x - X[1].y;
+            Z.y = X[0].y + X[1].x;
+            zs[kx] = Z;
+            const int m = Lx - kx;
+            if (kx >= 1 && m >= a.H) {
+                T2 Zm;
+                Zm.x = X[0].x + X[1].y;
+                Zm.y = -X[0].y + X[1].x;
+                zs[m] = Zm;
+            }
         }
     }
     __syncthreads();
-    T2 *R = fft_lds<T, T2, 1>(bufA, bufB, S, a.sx, a.twx, tid, nt);
-    T *Rr = reinterpret_cast<T *>(R);   // real output sig at Rr[2*((sig>>1)*Lx + n) + (sig&1)]
-
-    const size_t cbase = (size_t)b * d * a.N;
-    const T *uin = e.uin;
-
-    // broken bonds (eq. (tea:fr)): f_p += sum_{q in v_p} W(q - p) (u_p - u_q)
-    if (a.br_row_ptr) {
-        const int e0 = a.br_row_ptr[r0], e1 = a.br_row_ptr[r0 + nr];
-        const T *w = a.w + (size_t)b * a.w_slot;
-        for (int idx = tid; idx < (e1 - e0) * d; idx += nt) {
-            const int ei = e0 + idx / d;
-            const int c = idx - (idx / d) * d;
-            const int node = a.br_node_i[ei];
-            const int row = node / a.Nx;
-            const int n = node - row * a.Nx;
-            double acc = 0.0;
-            for (int t = a.br_bond_ptr[ei]; t < a.br_bond_ptr[ei + 1]; ++t) {
-                const int q = a.br_q[t];
-                const int o = a.br_off[t];
-                for (int cb = 0; cb < d; ++cb) {
-                    const double du = (double)uin[cbase + (size_t)cb * a.N + node] -
-                                      (double)uin[cbase + (size_t)cb * a.N + q];
-                    acc += (double)w[(size_t)comp_of(c, cb, d) * a.n_off + o] * du;
-                }
-            }
-            const int sig = c * nr + (row - r0);
-            Rr[2 * ((sig >> 1) * Lx + n) + (sig & 1)] += T(acc);
-        }
-        __syncthreads();
-    }
-
-    const T *de = a.de + (size_t)b * a.de_slot;
-    const int M = a.M, M1 = a.M + 1;
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    const T dth = T(0.5 * e.dt);
-    const T rinv = T(1.0 / e.rho);
-    for (int idx = tid; idx < nsig * a.Nx; idx += nt) {
-        const int sig = idx / a.Nx;
-        const int n = idx - sig * a.Nx;
-        const int c = sig / nr;
-        const int row = r0 + sig - c * nr;
-        const int node = row * a.Nx + n;
-        const size_t addr = cbase + (size_t)c * a.N + node;
-        T f = Rr[2 * ((sig >> 1) * Lx + n) + (sig & 1)];
-        // incomplete horizon (eq. (tea:sc)): table by clamped distances to the faces
-        {
-            const int z = row / a.Ny, y = row - z * a.Ny;
-            const int lx = min(n, M), hx = min(a.Nx - 1 - n, M);
-            const int ly = min(y, M), hy = min(a.Ny - 1 - y, M);
-            int didx = ((lx * M1 + hx) * M1 + ly) * M1 + hy;
-            bool interior = (lx == M) & (hx == M) & (ly == M) & (hy == M);
-            if (d == 3) {
-                const int lz = min(z, M), hz = min(a.Nz - 1 - z, M);
-                didx = (didx * M1 + lz) * M1 + hz;
-                interior = interior & (lz == M) & (hz == M);
-            }
-            if (!interior) {
-                for (int cb = 0; cb < d; ++cb)
-                    f += de[(size_t)comp_of(c, cb, d) * a.de_stride + didx] *
-                         uin[cbase + (size_t)cb * a.N + node];
-            }
-        }
-        const bool fx = a.fixed && a.fixed[(size_t)c * a.N + node];
-        switch (e.epi) {
-            case EPI_APPLY:
-                e.out[addr] = fx ? T(0) : T(e.sign) * f;
-                break;
-            case EPI_CG_Q: {
-                const T q = fx ? T(0) : -f;
-                e.out[addr] = q;
-                acc0 += (double)uin[addr] * (double)q;
-                break;
-            }
-            case EPI_RESID: {
-                const T v = fx ? T(0) : e.rhs[addr] + f;
-                e.out[addr] = v;
-                acc0 += (double)v * (double)v;
-                break;
-            }
-            case EPI_VV: {
-                T an = T(0), vn = T(0);
-                const T bb = e.rhs[addr];
-                if (!fx) {
-                    an = (f + bb) * rinv;
-                    vn = e.ev[addr] + dth * (e.ea[addr] + an);
-                    if (e.energy) {
-                        const double uu = (double)uin[addr];
-                        acc0 += uu * (double)f;
-                        acc1 += (double)vn * (double)vn;
-                        acc2 += (double)bb * uu;
+    if (ns > 0) {
+        const int nsg = min(2 * ns, nsig - 2 * s0);   // real rows of this team
+        const size_t cbase = (size_t)b * d * a.N;
+        const T *uin = e.uin;
+        T2 *R = team_fft<T, T2, 1, BLOCK>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
+        T *Rr = reinterpret_cast<T *>(R);   // real row sl of this team at Rr[2 ((sl>>1) Lx + n) + (sl&1)]
+
+        // broken bonds (eq. (tea:fr)): f_p += sum_{q in v_p} W(q - p) (u_p - u_q)
+        if (a.br_row_ptr) {
+            const T *wt = a.w + (size_t)b * a.w_slot;
+            for (int sl = 0; sl < nsg; ++sl) {
+                const int sig = 2 * s0 + sl;
+                const int c = sig / nr, row = r0 + sig - c * nr;
+                const int e0 = a.br_row_ptr[row], e1 = a.br_row_ptr[row + 1];
+                for (int ei = e0 + tm.tid; ei < e1; ei += tm.nt) {
+                    const int node = a.br_node_i[ei];
+                    const int n = node - row * a.Nx;
+                    double accb = 0.0;
+                    for (int t = a.br_bond_ptr[ei]; t < a.br_bond_ptr[ei + 1]; ++t) {
+                        const int q = a.br_q[t];
+                        const int o = a.br_off[t];
+                        for (int cb = 0; cb < d; ++cb) {
+                            const double du = (double)uin[cbase + (size_t)cb * a.N + node] -
+                                              (double)uin[cbase + (size_t)cb * a.N + q];
+                            accb += (double)wt[(size_t)comp_of(c, cb, d) * a.n_off + o] * du;
+                        }
                     }
+                    Rr[2 * ((size_t)(sl >> 1) * Lx + n) + (sl & 1)] += T(accb);
                 }
-                e.ea[addr] = an;
-                e.ev[addr] = vn;
-                break;
             }
-            default:  // EPI_DOT
-                if (!fx) acc0 += (double)e.rhs[addr] * (double)f;
-                break;
+            tm.sync();
+        }
+
+        const T *de = a.de + (size_t)b * a.de_slot;
+        const int M = a.M, M1 = a.M + 1;
+        const T dth = T(0.5 * e.dt);
+        const T rinv = T(1.0 / e.rho);
+        for (int sl = 0; sl < nsg; ++sl) {
+            const int sig = 2 * s0 + sl;
+            const int c = sig / nr, row = r0 + sig - c * nr;
+            const int z = row / a.Ny, y = row - z * a.Ny;
+            const int ly = min(y, M), hy = min(a.Ny - 1 - y, M);
+            const int lz = d == 3 ? min(z, M) : 0, hz = d == 3 ? min(a.Nz - 1 - z, M) : 0;
+            const bool row_interior = (ly == M) & (hy == M) & (d == 2 || ((lz == M) & (hz == M)));
+            const size_t rbase = cbase + (size_t)c * a.N + (size_t)row * a.Nx;
+            const uint8_t *fxrow = a.fixed ? a.fixed + (size_t)c * a.N + (size_t)row * a.Nx : nullptr;
+            const T *Rrow = Rr + 2 * (size_t)(sl >> 1) * Lx + (sl & 1);
+            for (int n = tm.tid; n < a.Nx; n += tm.nt) {
+                const size_t addr = rbase + n;
+                T f = Rrow[2 * n];
+                // incomplete horizon (eq. (tea:sc)): table by clamped distances to the faces
+                const int lx = min(n, M), hx = min(a.Nx - 1 - n, M);
+                if (!(row_interior & (lx == M) & (hx == M))) {
+                    int didx = ((lx * M1 + hx) * M1 + ly) * M1 + hy;
+                    if (d == 3) didx = (didx * M1 + lz) * M1 + hz;
+                    const size_t node = (size_t)row * a.Nx + n;
+                    for (int cb = 0; cb < d; ++cb)
+                        f += de[(size_t)comp_of(c, cb, d) * a.de_stride + didx] * uin[cbase + (size_t)cb * a.N + node];
+                }
+                const bool fx = fxrow && fxrow[n];
+                switch (e.epi) {
+                    case EPI_APPLY:
+                        e.out[addr] = fx ? T(0) : T(e.sign) * f;
+                        break;
+                    case EPI_CG_Q: {
+                        const T q = fx ? T(0) : -f;
+                        e.out[addr] = q;
+                        acc0 += (double)uin[addr] * (double)q;
+                        break;
+                    }
+                    case EPI_RESID: {
+                        const T v = fx ? T(0) : e.rhs[addr] + f;
+                        e.out[addr] = v;
+                        acc0 += (double)v * (double)v;
+                        break;
+                    }
+                    case EPI_VV: {
+                        T an = T(0), vn = T(0);
+                        const T bb = e.rhs[addr];
+                        if (!fx) {
+                            an = (f + bb) * rinv;
+                            vn = e.ev[addr] + dth * (e.ea[addr] + an);
+                            if (e.energy) {
+                                const double uu = (double)uin[addr];
+                                acc0 += uu * (double)f;
+                                acc1 += (double)vn * (double)vn;
+                                acc2 += (double)bb * uu;
+                            }
+                        }
+                        e.ea[addr] = an;
+                        e.ev[addr] = vn;
+                        break;
+                    }
+                    default:  // EPI_DOT
+                        if (!fx) acc0 += (double)e.rhs[addr] * (double)f;
+                        break;
+                }
+            }
         }
     }
     if (e.part) {
         double v[3] = {acc0, acc1, acc2};
-        block_sum<3>(v, red, tid, nt);
-        if (tid == 0) {
+        block_sum<3>(v, red, threadIdx.x, blockDim.x);
+        if (threadIdx.x == 0) {
             const size_t stride = (size_t)gridDim.x;
             e.part[tile] = v[0];
             e.part[stride + tile] = v[1];
@@ -458,24 +560,55 @@ static size_t lds_budget() {
     static size_t b = 0;
     if (!b) {
         const char *e = getenv("MSB_LDS_BUDGET");
-        b = e ? (size_t)atol(e) : (size_t)64 * 1024;
+        b = e ? (size_t)atol(e) : (size_t)80 * 1024;
     }
     return b;
 }
 
+// LDS bytes: the shared twiddle table plus two buffers (ping-pong) of slots.
+static size_t lds_x_bytes(int d, int F, int64_t Lx, size_t cbytes) {
+    return ((size_t)2 * ((d * F + 1) / 2) + 1) * Lx * cbytes;
+}
+static size_t lds_line_bytes(int d, int Fl, int64_t L, size_t cbytes) {
+    return ((size_t)2 * Fl * d + 1) * L * cbytes;
+}
+static int waves_x(int d, int F) { return (d * F + 1) / 2; }
+
+// Team choice: wave-owned signals once there are enough independent signals to give
+// every SIMD of the chip (256 CUs x 4) several of them; whole-block teams otherwise.
+static bool wave_mode(int64_t units) {
+    const char *env = getenv("MSB_TEAM");
+    if (env) return env[0] == 'w';
+    return units >= 4096;
+}
+
+// Grid rows per block of the x passes.  Block teams: the largest power of two <= 8
+// that fits the LDS budget and leaves >= 1024 blocks (latency-bound small grids run
+// fastest with one row pair per block).  Wave teams: up to 16 waves
+// (slots) per block within the LDS budget.
 int rows_per_wg_for(const msb_plan_s *p, size_t cbytes) {
     const char *env = getenv("MSB_ROWS_PER_WG");
     if (env) return std::max(1, atoi(env));
+    const int64_t rows = rows_total(p);
+    const bool wm = wave_mode((int64_t)p->B * ((rows * p->dim + 1) / 2));
     int F = 8;
-    while (F > 1 && (size_t)2 * ((p->dim * F + 1) / 2) * p->L[0] * cbytes > lds_budget()) F /= 2;
+    while (F > 1 && (lds_x_bytes(p->dim, F, p->L[0], cbytes) > lds_budget() ||
+                     waves_x(p->dim, F) > 16 ||
+                     (!wm && (int64_t)p->B * ((rows + F - 1) / F) < 1024)))
+        F /= 2;
     return F;
 }
 
-static int lines_per_wg_for(const msb_plan_s *p, size_t cbytes, int L) {
+// Lines per block of the line passes (block teams: >= 256 blocks; wave teams: one
+// line per wave, up to 8 per block).
+static int lines_per_wg_for(const msb_plan_s *p, size_t cbytes, int L, int64_t nlines) {
     const char *env = getenv("MSB_LINES_PER_WG");
     if (env) return std::max(1, atoi(env));
+    const bool wm = wave_mode((int64_t)p->B * nlines);
     int F = 8;
-    while (F > 1 && (size_t)2 * F * p->dim * L * cbytes > lds_budget()) F /= 2;
+    while (F > 1 && (lds_line_bytes(p->dim, F, L, cbytes) > lds_budget() ||
+                     (!wm && (int64_t)p->B * ((nlines + F - 1) / F) < 256)))
+        F /= 2;
     return F;
 }
 
@@ -497,7 +630,11 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.Lz = (int)p->L[2];
     a.N = (int)p->N;
     a.F = rows_per_wg_for(p, sizeof(cplx_t<T>));
-    a.Fl = lines_per_wg_for(p, sizeof(cplx_t<T>), p->dim == 2 ? (int)p->L[1] : (int)std::max(p->L[1], p->L[2]));
+    const int64_t nl = p->dim == 2 ? p->H : p->H * p->n[2];
+    a.Fl = p->dim == 2 ? lines_per_wg_for(p, sizeof(cplx_t<T>), (int)p->L[1], nl)
+                       : lines_per_wg_for(p, sizeof(cplx_t<T>), (int)std::max(p->L[1], p->L[2]), nl);
+    a.wave_x = wave_mode((int64_t)p->B * ((rows_total(p) * p->dim + 1) / 2)) ? 1 : 0;
+    a.wave_l = wave_mode((int64_t)p->B * nl) ? 1 : 0;
     a.sx = sched_of(p->ax[0]);
     a.sy = sched_of(p->ax[1]);
     a.sz = sched_of(p->ax[2]);
@@ -530,46 +667,72 @@ template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename T>
-msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev) {
+template <typename T, bool B>
+static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev, bool wl) {
     using T2 = cplx_t<T>;
     int evi = 0;
     auto mark = [&]() -> hipError_t { return ev ? hipEventRecord(ev[evi++], st) : hipSuccess; };
     const int tpc = (a.rows + a.F - 1) / a.F;
-    const size_t lds_x = (size_t)2 * ((a.d * a.F + 1) / 2) * a.sx.L * sizeof(T2);
-    MSB_HIP(allow_lds(k_xfwd<T>, lds_x));
-    MSB_HIP(allow_lds(k_xinv<T>, lds_x));
+    const size_t lds_x = lds_x_bytes(a.d, a.F, a.sx.L, sizeof(T2));
+    const int bx = B ? 256 : 64 * waves_x(a.d, a.F);
+    MSB_HIP(allow_lds(k_xfwd<T, B>, lds_x));
+    MSB_HIP(allow_lds(k_xinv<T, B>, lds_x));
     MSB_HIP(mark());
-    hipLaunchKernelGGL(k_xfwd<T>, dim3(a.B * tpc), dim3(kThreads), lds_x, st, a, e);
+    hipLaunchKernelGGL((k_xfwd<T, B>), dim3(a.B * tpc), dim3(bx), lds_x, st, a, e);
     MSB_HIP(mark());
     if (a.d == 2) {
         const int lpc = (a.H + a.Fl - 1) / a.Fl;
-        const size_t lds = (size_t)2 * a.Fl * a.d * a.sy.L * sizeof(T2);
-        MSB_HIP(allow_lds(k_line_prod<T>, lds));
-        hipLaunchKernelGGL(k_line_prod<T>, dim3(a.B * lpc), dim3(kThreads), lds, st, a, e, a.T1,
-                           a.H, a.Ny, a.sy, a.twy);
+        const size_t lds = lds_line_bytes(a.d, a.Fl, a.sy.L, sizeof(T2));
+        if (wl) {
+            MSB_HIP(allow_lds(k_line_prod<T, false>, lds));
+            hipLaunchKernelGGL((k_line_prod<T, false>), dim3(a.B * lpc), dim3(64 * a.Fl), lds, st, a, e, a.T1,
+                               a.H, a.Ny, a.sy, a.twy);
+        } else {
+            MSB_HIP(allow_lds(k_line_prod<T, true>, lds));
+            hipLaunchKernelGGL((k_line_prod<T, true>), dim3(a.B * lpc), dim3(256), lds, st, a, e, a.T1,
+                               a.H, a.Ny, a.sy, a.twy);
+        }
         MSB_HIP(mark());
     } else {
         const int nzc = (a.Nz + a.Fl - 1) / a.Fl;
-        const size_t lds_y = (size_t)2 * a.Fl * a.d * a.sy.L * sizeof(T2);
-        MSB_HIP(allow_lds(k_yfwd<T>, lds_y));
-        MSB_HIP(allow_lds(k_yinv<T>, lds_y));
-        hipLaunchKernelGGL(k_yfwd<T>, dim3(a.B * a.H * nzc), dim3(kThreads), lds_y, st, a, e);
-        MSB_HIP(mark());
+        const size_t lds_y = lds_line_bytes(a.d, a.Fl, a.sy.L, sizeof(T2));
         const int nlines = a.H * a.Ly;
         const int lpc = (nlines + a.Fl - 1) / a.Fl;
-        const size_t lds_z = (size_t)2 * a.Fl * a.d * a.sz.L * sizeof(T2);
-        MSB_HIP(allow_lds(k_line_prod<T>, lds_z));
-        hipLaunchKernelGGL(k_line_prod<T>, dim3(a.B * lpc), dim3(kThreads), lds_z, st, a, e, a.T2,
-                           nlines, a.Nz, a.sz, a.twz);
-        MSB_HIP(mark());
-        hipLaunchKernelGGL(k_yinv<T>, dim3(a.B * a.H * nzc), dim3(kThreads), lds_y, st, a, e);
+        const size_t lds_z = lds_line_bytes(a.d, a.Fl, a.sz.L, sizeof(T2));
+        const int by = wl ? 64 * a.Fl : 256;
+        if (wl) {
+            MSB_HIP(allow_lds(k_yfwd<T, false>, lds_y));
+            MSB_HIP(allow_lds(k_yinv<T, false>, lds_y));
+            MSB_HIP(allow_lds(k_line_prod<T, false>, lds_z));
+            hipLaunchKernelGGL((k_yfwd<T, false>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
+            MSB_HIP(mark());
+            hipLaunchKernelGGL((k_line_prod<T, false>), dim3(a.B * lpc), dim3(by), lds_z, st, a, e, a.T2,
+                               nlines, a.Nz, a.sz, a.twz);
+            MSB_HIP(mark());
+            hipLaunchKernelGGL((k_yinv<T, false>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
+        } else {
+            MSB_HIP(allow_lds(k_yfwd<T, true>, lds_y));
+            MSB_HIP(allow_lds(k_yinv<T, true>, lds_y));
+            MSB_HIP(allow_lds(k_line_prod<T, true>, lds_z));
+            hipLaunchKernelGGL((k_yfwd<T, true>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
+            MSB_HIP(mark());
+            hipLaunchKernelGGL((k_line_prod<T, true>), dim3(a.B * lpc), dim3(by), lds_z, st, a, e, a.T2,
+                               nlines, a.Nz, a.sz, a.twz);
+            MSB_HIP(mark());
+            hipLaunchKernelGGL((k_yinv<T, true>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
+        }
         MSB_HIP(mark());
     }
-    hipLaunchKernelGGL(k_xinv<T>, dim3(a.B * tpc), dim3(kThreads), lds_x, st, a, e);
+    hipLaunchKernelGGL((k_xinv<T, B>), dim3(a.B * tpc), dim3(bx), lds_x, st, a, e);
     MSB_HIP(mark());
     MSB_HIP(hipGetLastError());
     return MSB_OK;
+}
+
+template <typename T>
+msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev) {
+    if (a.wave_x) return launch_chain<T, false>(a, e, st, ev, a.wave_l != 0);
+    return launch_chain<T, true>(a, e, st, ev, a.wave_l != 0);
 }
 
 template PassArgs<double> pass_args<double>(const msb_plan_s *, const DeviceOp &);

@@ -30,6 +30,7 @@ template <typename T> struct PassArgs {
     int Ly, Lz;
     int F;               // rows per workgroup (x passes)
     int Fl;              // lines per workgroup (line passes)
+    int wave_x, wave_l;  // 1: wave-owned signals, 0: whole-block teams (x passes / line passes)
     int N;               // nodes per case
     FftSched sx, sy, sz;
     const cplx_t<T> *twx, *twy, *twz;
