@@ -65,11 +65,20 @@ def main():
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-tolerance runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "0")))
+    ap.add_argument("--workload", default="plate512",
+                    choices=["plate512", "crack1024", "cube128", "plates64"],
+                    help="plate512 is the headline line; the others measure the remaining workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload != "plate512":
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"crack1024": bench_crack1024, "cube128": bench_cube128,
+                          "plates64": bench_plates64}[args.workload](args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -188,6 +197,140 @@ def main():
                                 "cores": cores, "kind": "oracle",
                                 "sample": "%d full FP64 bond-by-bond products of plate512 (%.1f s)" % (reps, dt)}
     print(json.dumps(line), flush=True)
+
+
+def _cpu_cores():
+    return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+
+
+def bench_crack1024(args):
+    """Dynamic pre-crack plate, 1024^2 (2.1M DOF), delta = 4h, 12,654 broken bonds:
+    velocity Verlet in FP32 with the FP64 energy every 10 steps; steps/s."""
+    import numpy as np
+    import torch
+    import paper_2301_11828_amd as msb
+    from paper_2301_11828_amd import workloads as W
+    w = W.crack1024(steps=1000)
+    plan = msb.Plan(w.n, w.h, w.M, w.alpha, rho=w.rho)
+    plan.set_bonds(msb.crack_to_bonds(w.n, w.h, w.M, w.cracks))
+    u = torch.zeros((1, 2, w.N), dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(u)
+    bf = torch.from_numpy(w.b).float().cuda()
+    a = plan.vv_init(u, bf)
+    plan.vv_run(w.dt, 20, u.clone(), v.clone(), a.clone(), bf)          # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    en = plan.vv_run(w.dt, w.steps, u, v, a, bf, energy_every=10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"workload": "crack1024: 2D dynamic pre-crack, 1024x1024 (2097152 DOF), delta=4h, "
+                       "12654 broken bonds, FP32 velocity Verlet, FP64 energy every 10 steps",
+           "steps": w.steps, "seconds": round(dt, 4), "steps_per_s": round(w.steps / dt, 1),
+           "GDOF_steps_per_s": round(w.dofs * w.steps / dt / 1e9, 3),
+           "energy_first_last": [float(en[0]), float(en[-1])],
+           "n_bonds": plan.n_bonds}
+    if not args.no_cpu:
+        import oracle as O
+        p = O.Problem(w.n, w.h, w.M, w.alpha, rho=w.rho)
+        br = O.crack_to_bonds(p, w.cracks)
+        t0 = time.perf_counter()
+        O.vv(p, np.zeros((2, w.N)), np.zeros((2, w.N)), w.b[0], w.dt, 5, None, None, br)
+        dtc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(5 / dtc, 3), "unit": "steps/s", "cores": _cpu_cores(),
+                               "kind": "oracle", "sample": "5 FP64 Verlet steps of crack1024"}
+    return out
+
+
+def bench_cube128(args):
+    """3D block 128^3 x 16 load cases (100.7M DOF): FP32 and FP64 products and
+    FP32-refined CG vs FP64 CG to 1e-8."""
+    import numpy as np
+    import torch
+    import paper_2301_11828_amd as msb
+    from paper_2301_11828_amd import workloads as W
+    w = W.cube128(batch=16)
+    plan = msb.Plan(w.n, w.h, w.M, w.alpha, batch=16)
+    plan.set_constraints(w.fixed)
+    b = torch.from_numpy(w.b).cuda()
+    dofs = w.dofs * 16
+    out = {"workload": "cube128: 3D static, 128^3 x 16 cases (100663296 DOF), delta=3h, z=0 layer fixed",
+           "padded": list(plan.padded_lengths)}
+    for dt in (torch.float64, torch.float32):
+        u = b.to(dt)
+        f = torch.empty_like(u)
+        for _ in range(3):
+            plan.apply(u, f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            plan.apply(u, f)
+        torch.cuda.synchronize()
+        s = (time.perf_counter() - t0) / 10
+        ks = plan.profile_apply(u, f, nrep=5)
+        out["matvec_" + str(dt)[6:]] = {"GDOF_s": round(dofs / s / 1e9, 2), "ms": round(1e3 * s, 3),
+                                        "kernels_ms": [round(float(x), 4) for x in ks]}
+        del u, f
+    cg = {}
+    for prec in ("fp64", "fp32_refined"):
+        t0 = time.perf_counter()
+        _, info = plan.solve(b, precision=prec, tol=1e-8, maxit=100000, graph_block=args.graph_block)
+        torch.cuda.synchronize()
+        cg[prec] = {"seconds": round(time.perf_counter() - t0, 3),
+                    "iterations_max": max(i.inner_iters for i in info),
+                    "max_rel_residual": max(i.rel_residual for i in info)}
+    cg["speedup_fp32_refined_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp32_refined"]["seconds"], 3)
+    out["cg_to_1e-8"] = cg
+    return out
+
+
+def bench_plates64(args):
+    """64 plates of uneven size: forward FP32-refined solve, loss, hand-written adjoint
+    solve and influence-coefficient gradient, grouped into one batched plan per size."""
+    import numpy as np
+    import torch
+    import paper_2301_11828_amd as msb
+    from paper_2301_11828_amd import workloads as W
+    ws = W.plates64()
+    groups = {}
+    for w in ws:
+        groups.setdefault(w.n[0], []).append(w)
+    plans = {}
+    for s, g in groups.items():
+        w0 = g[0]
+        pl = msb.Plan(w0.n, w0.h, w0.M, w0.alpha, infl=w0.infl, batch=len(g))
+        pl.set_constraints(w0.fixed)
+        plans[s] = pl
+    Solve = msb.make_solve_function()
+
+    def run():
+        total = 0.0
+        grads = []
+        for s, g in groups.items():
+            pl = plans[s]
+            b = torch.from_numpy(np.concatenate([w.b for w in g])).cuda().requires_grad_(True)
+            a = torch.tensor(np.array([w.infl for w in g]), dtype=torch.float64, requires_grad=True)
+            # target from the perturbed coefficients (no gradient)
+            pl.set_infl(np.array([w.extra["infl_target"] for w in g]), per_case=True)
+            ut, _ = pl.solve(b.detach(), precision="fp32_refined", tol=1e-10)
+            u = Solve.apply(pl, b, a, "fp32_refined", 1e-10)
+            loss = ((u - ut) ** 2).sum()
+            loss.backward()
+            total += loss.item()
+            grads.append(a.grad.numpy())
+        torch.cuda.synchronize()
+        return total, grads
+
+    run()
+    t0 = time.perf_counter()
+    loss, grads = run()
+    dt = time.perf_counter() - t0
+    dofs = sum(w.dofs for w in ws)
+    return {"workload": "plates64: 64 plates, sizes %s, delta=3h, omega=sum_k a_k (r/delta)^k, "
+                        "target + forward + adjoint FP32-refined solves to 1e-10 and dL/da" %
+                        sorted({w.n[0] for w in ws}),
+            "plates": len(ws), "dofs_total": dofs, "seconds": round(dt, 3),
+            "solves": 3 * len(ws), "loss": loss,
+            "plates_per_size": {int(k): len(v) for k, v in sorted(groups.items())}}
 
 
 if __name__ == "__main__":

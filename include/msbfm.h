@@ -141,9 +141,12 @@ msb_status msb_apply_dinfl(msb_plan plan, int k, const double *u, double *f, voi
 typedef struct {
     double tol;             /* stop when ||b' - K u||_2 <= tol ||b'||_2 on free DOFs (FP64 apply) */
     int maxit;              /* cap on CG iterations (inner iterations for FP32_REFINED), > 0 */
-    double inner_tol;       /* FP32_REFINED: relative residual reduction per inner solve (0 = auto) */
+    double inner_tol;       /* FP32_REFINED: relative residual reduction per inner solve
+                               (0 = auto: 1e-4 restarted, 0.1 with reliable updates) */
     int graph_block;        /* CG iterations per hipGraph launch (0 = no graph, plain launches) */
-    int reliable_update;    /* FP32_REFINED: 1 = keep the Krylov space, replace the residual in FP64 */
+    int reliable_update;    /* FP32_REFINED: 0 = restart CG after each FP64 residual update
+                               (iterative refinement); 1 = keep the search direction and
+                               replace the residual by the FP64 one (reliable updates) */
 } msb_solve_opts;
 
 typedef struct {

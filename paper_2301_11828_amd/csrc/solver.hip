@@ -258,6 +258,7 @@ template <typename T> struct Cg {
     T *x, *r, *pv, *q;
     PassArgs<T> pa;
     int tpc;
+    const double *prev_rr;   // r.r partials before a residual replacement (first beta), or null
 };
 
 template <typename T> static msb_status cg_iteration(Cg<T> &c, int it) {
@@ -271,7 +272,7 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it) {
     e.pio = c.pv;
     e.pr = c.r;
     e.beta_part = rr_cur;
-    e.beta_part_old = it == 0 ? nullptr : rr_nxt;
+    e.beta_part_old = it == 0 ? c.prev_rr : rr_nxt;
     e.nbeta = P;
     e.case_done = w->done;
     e.done_rw = w->done;
@@ -335,16 +336,26 @@ template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_bl
     return st;
 }
 
-// Prepare and run CG on K d = rhs (rhs already masked); x0 = 0.
+// per case: dst[b][.] = latest r.r partials, part_rr[iters[b] & 1][b][.]
+__global__ void k_save_rr(const double *part_rr, const int *iters, int P, int B, double *dst) {
+    const int b = blockIdx.x;
+    const double *src = part_rr + (size_t)(iters[b] & 1) * B * P + (size_t)b * P;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) dst[(size_t)b * P + i] = src[i];
+}
+
+// Prepare and run CG on K d = rhs (rhs already masked); x0 = 0.  With prev_rr the
+// search direction pv is kept (reliable update after a residual replacement) and the
+// first beta is (new r.r) / prev_rr; otherwise pv starts at 0 (plain restart).
 template <typename T>
 static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *rhs, T *x, T *r, T *pv,
-                           T *q, double tol, int maxit, int graph_block, const int *skip) {
+                           T *q, double tol, int maxit, int graph_block, const int *skip,
+                           const double *prev_rr = nullptr, int *iters_out = nullptr) {
     const size_t n = w->nvec;
     const int B = p->B, P = w->P;
-    Cg<T> c{p, w, st, x, r, pv, q, pass_args<T>(p, p->op), 0};
+    Cg<T> c{p, w, st, x, r, pv, q, pass_args<T>(p, p->op), 0, prev_rr};
     c.tpc = x_tiles_per_case(p, c.pa.F);
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, x, n, T(0));
-    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
+    if (!prev_rr) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
     hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(n)), dim3(kT), 0, st, r, rhs, n);
     hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * P), dim3(kT), 0, st, (const T *)r, (const T *)r, w->part_rr,
                        (size_t)p->dim * p->N, P);
@@ -352,7 +363,9 @@ static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *
                        w->thresh, w->done, skip, w->iters, B);
     MSB_HIP(hipGetLastError());
     int it = 0;
-    return run_cg(c, maxit, graph_block, &it);
+    msb_status r0 = run_cg(c, maxit, graph_block, &it);
+    if (iters_out) *iters_out = it;
+    return r0;
 }
 
 // per-case ||rhs + A x||^2 on free DOFs into w->scal[slot*B + b], residual vector into out
@@ -537,20 +550,27 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
             outer[c] = 1;
         }
     } else {
-        // FP32 inner CG inside FP64 iterative refinement: r = b' - K u (FP64 apply),
-        // solve K d = r in FP32 to inner_tol, u += d (FP64)
-        const double itol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
+        // FP32 inner CG inside FP64 refinement.  Each inner run reduces the FP32
+        // residual by inner_tol (default 0.1 with reliable updates, 1e-4 restarted);
+        // then u += d in FP64, the residual is replaced by the FP64 true residual
+        // r = b' - K u, and (reliable_update) CG continues with its search direction,
+        // or restarts from the new residual (plain iterative refinement).
+        const bool reliable = opts->reliable_update != 0;
+        const double itol = opts->inner_tol > 0 ? opts->inner_tol : (reliable ? 0.1 : 1e-4);
         int *skip = nullptr;
         MSB_HIP(hipMalloc(&skip, sizeof(int) * B));
-        float *r32 = w->v32[0], *d32 = w->v32[1];
+        float *r32 = w->v32[0], *d32 = w->v32[1], *p32 = w->v32[2];
         double *r64 = w->v64[2];
+        double *prev = w->part_aux + (size_t)B * w->P;
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kT), 0, st, u, n, 0.0);
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(kT), 0, st, p32, n, 0.0f);
         hipLaunchKernelGGL((k_cast<double, double>), dim3(grid_for(n)), dim3(kT), 0, st, r64, (const double *)bp, n);
-        std::vector<double> rr(bb);
-        std::vector<double> hist;
+        std::vector<double> rr(bb), best(bb);
+        std::vector<int> stall(B, 0);
         int used = 0;
+        bool first = true;
         std::vector<int> hskip(B, 0);
-        for (int j = 0; j < 200; ++j) {
+        for (int j = 0; j < 1000; ++j) {
             bool all = true;
             for (int c = 0; c < B; ++c) {
                 rel[c] = bb[c] > 0 ? std::sqrt(rr[c] / bb[c]) : 0.0;
@@ -560,9 +580,16 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
                 all = all && hskip[c];
             }
             if (all || used >= opts->maxit) break;
+            // inner target: reduce by itol, but not below what the outer tolerance needs
+            double ratio = itol;
+            for (int c = 0; c < B; ++c)
+                if (!hskip[c] && rr[c] > 0) ratio = std::max(ratio, 0.5 * opts->tol * std::sqrt(bb[c] / rr[c]));
+            ratio = std::min(ratio, 0.5);
             MSB_HIP(hipMemcpyAsync(skip, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
             hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kT), 0, st, r32, (const double *)r64, n);
-            MSB_TRY(cg_solve<float>(p, w, st, r32, d32, w->v32[2], w->v32[3], w->v32[4], itol, opts->maxit - used, gb, skip));
+            MSB_TRY(cg_solve<float>(p, w, st, r32, d32, p32, w->v32[3], w->v32[4], ratio, opts->maxit - used, gb,
+                                    skip, (reliable && !first) ? prev : nullptr));
+            first = false;
             MSB_TRY(fetch_scal(w, st, 0, B));
             int mx = 0;
             for (int c = 0; c < B; ++c) {
@@ -574,16 +601,22 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
                 mx = std::max(mx, w->h_int[B + c]);
             }
             used += mx;
+            if (reliable) hipLaunchKernelGGL(k_save_rr, dim3(B), dim3(64), 0, st, (const double *)w->part_rr,
+                                             (const int *)w->iters, w->P, B, prev);
             hipLaunchKernelGGL(k_add_to<float>, dim3(grid_for(n)), dim3(kT), 0, st, u, (const float *)d32, n);
             MSB_TRY(true_residual(p, w, st, u, bp, r64, 0));
             MSB_TRY(fetch_scal(w, st, 1, B));
             for (int c = 0; c < B; ++c) {
                 if (hskip[c]) continue;
-                // stagnation: no 10% gain over the last three refinement steps
-                if (outer[c] >= 4 && w->h_scal[c] > 0.81 * rr[c] && hist.size() > 0) fl[c] = fl[c] == RUNNING ? -1 : fl[c];
                 rr[c] = w->h_scal[c];
+                // stagnation: three replacements without a 10% gain on the best residual
+                if (rr[c] < 0.81 * best[c]) {
+                    best[c] = rr[c];
+                    stall[c] = 0;
+                } else if (++stall[c] >= 3 && fl[c] == RUNNING) {
+                    fl[c] = -1;
+                }
             }
-            hist.push_back(rr[0]);
         }
         (void)hipFree(skip);
         for (int c = 0; c < B; ++c)
