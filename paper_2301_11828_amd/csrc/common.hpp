@@ -51,8 +51,10 @@ constexpr int kMaxPasses = 12;
 // Twiddle table tw[t] = exp(-2 pi i t / L), t < L (device, both precisions).
 struct FftAxis {
     int L = 0;
-    int np = 0;
+    int np = 0;                       // FP64 schedule
     int radix[kMaxPasses] = {};
+    int np32 = 0;                     // FP32 schedule (may use the composite radices)
+    int radix32[kMaxPasses] = {};
     double2 *tw64 = nullptr;
     float2 *tw32 = nullptr;
 };
@@ -77,15 +79,16 @@ struct FftSched {
     FftPass ps[kMaxPasses];
 };
 
-inline FftSched sched_of(const FftAxis &a) {
+inline FftSched sched_of(const FftAxis &a, bool fp32 = false) {
     FftSched s;
     s.L = a.L;
-    s.np = a.np;
+    s.np = fp32 ? a.np32 : a.np;
+    const int *radix = fp32 ? a.radix32 : a.radix;
     int Ns = 1;
     for (int i = 0; i < kMaxPasses; ++i) {
         FftPass &p = s.ps[i];
-        if (i < a.np) {
-            p.R = a.radix[i];
+        if (i < s.np) {
+            p.R = radix[i];
             p.Ns = Ns;
             p.nb = a.L / p.R;
             p.twstep = a.L / (Ns * p.R);
@@ -103,8 +106,9 @@ template <typename T> inline const cplx_t<T> *tw_of(const FftAxis &a);
 template <> inline const double2 *tw_of<double>(const FftAxis &a) { return a.tw64; }
 template <> inline const float2 *tw_of<float>(const FftAxis &a) { return a.tw32; }
 
-// Factor L into the supported radices; returns false if L has another prime factor.
-bool factor_length(int L, std::vector<int> &radices);
+// Factor L into the fewest stages with radix <= rmax from the supported set;
+// returns false if L has a prime factor other than 2, 3, 5.
+bool factor_length(int L, std::vector<int> &radices, int rmax);
 // Smallest L >= nmin whose prime factors are all in {2,3,5} (and even when even_only).
 int next_smooth(int nmin, bool even_only);
 

@@ -56,7 +56,7 @@ template <typename T2> __device__ __forceinline__ T2 c_conj(T2 a) {
 template <typename T, typename T2, int R, int DIR> struct Dft;
 
 template <typename T, typename T2, int DIR> struct Dft<T, T2, 2, DIR> {
-    __device__ __forceinline__ static void run(T2 *v) {
+    __device__ __forceinline__ static void run(T2 *v, const T2 *__restrict__ tw = nullptr, int lr = 0) {
         T2 a = v[0], b = v[1];
         v[0] = c_add(a, b);
         v[1] = c_sub(a, b);
@@ -64,7 +64,7 @@ template <typename T, typename T2, int DIR> struct Dft<T, T2, 2, DIR> {
 };
 
 template <typename T, typename T2, int DIR> struct Dft<T, T2, 3, DIR> {
-    __device__ __forceinline__ static void run(T2 *v) {
+    __device__ __forceinline__ static void run(T2 *v, const T2 *__restrict__ tw = nullptr, int lr = 0) {
         const T c = T(-0.5);
         const T s = T(DIR) * T(0.86602540378443864676372317075294);   // forward: -sin(2 pi/3)
         T2 t = c_add(v[1], v[2]);
@@ -83,7 +83,7 @@ template <typename T, typename T2, int DIR> struct Dft<T, T2, 3, DIR> {
 };
 
 template <typename T, typename T2, int DIR> struct Dft<T, T2, 4, DIR> {
-    __device__ __forceinline__ static void run(T2 *v) {
+    __device__ __forceinline__ static void run(T2 *v, const T2 *__restrict__ tw = nullptr, int lr = 0) {
         T2 t0 = c_add(v[0], v[2]);
         T2 t1 = c_sub(v[0], v[2]);
         T2 t2 = c_add(v[1], v[3]);
@@ -98,7 +98,7 @@ template <typename T, typename T2, int DIR> struct Dft<T, T2, 4, DIR> {
 };
 
 template <typename T, typename T2, int DIR> struct Dft<T, T2, 5, DIR> {
-    __device__ __forceinline__ static void run(T2 *v) {
+    __device__ __forceinline__ static void run(T2 *v, const T2 *__restrict__ tw = nullptr, int lr = 0) {
         const T c1 = T(0.30901699437494742410229341718282);    // cos(2 pi/5)
         const T c2 = T(-0.80901699437494742410229341718282);   // cos(4 pi/5)
         const T s1 = T(DIR) * T(0.95105651629515357211643933337938);   // forward: -sin(2 pi/5)
@@ -133,13 +133,13 @@ template <typename T, typename T2, int DIR> struct Dft<T, T2, 5, DIR> {
 };
 
 template <typename T, typename T2, int DIR> struct Dft<T, T2, 8, DIR> {
-    __device__ __forceinline__ static void run(T2 *v) {
+    __device__ __forceinline__ static void run(T2 *v, const T2 *__restrict__ tw = nullptr, int lr = 0) {
         const T r = T(0.70710678118654752440084436210485);
         // two radix-4 DFTs on even and odd samples, then combine with w8^m
         T2 e[4] = {v[0], v[2], v[4], v[6]};
         T2 o[4] = {v[1], v[3], v[5], v[7]};
-        Dft<T, T2, 4, DIR>::run(e);
-        Dft<T, T2, 4, DIR>::run(o);
+        Dft<T, T2, 4, DIR>::run(e, tw, lr);
+        Dft<T, T2, 4, DIR>::run(o, tw, lr);
         // w8 = exp(DIR * 2 pi i / 8): w^1 = r(1 + DIR i), w^2 = DIR i, w^3 = r(-1 + DIR i)
         T2 o1, o2, o3;
         o1.x = r * (o[1].x - T(DIR) * o[1].y);
@@ -172,6 +172,54 @@ struct FastDiv {
     __device__ __forceinline__ uint32_t div(uint32_t n) const { return exact ? fdiv(n, m) : n / d; }
 };
 
+// Composite radix R = R1 * R2 (6, 9, 10, 12, 15, 16) computed in registers (two-level Cooley-Tukey):
+// input index m = m1 + R1 m2, output index s = s2 + R2 s1;
+//   A[m1][s2] = DFT_R2 over m2 of v[m1 + R1 m2];  A[m1][s2] *= W_R^(m1 s2);
+//   V[s2 + R2 s1] = DFT_R1 over m1 of A[m1][s2].
+// W_R^t = tw[t * lr] from the length-L table (lr = L / R), conjugated for DIR = +1.
+template <typename T, typename T2, int R1, int R2, int DIR> struct Dft2 {
+    __device__ __forceinline__ static void run(T2 *v, const T2 *__restrict__ tw, int lr) {
+        T2 A[R1][R2];
+#pragma unroll
+        for (int m1 = 0; m1 < R1; ++m1) {
+#pragma unroll
+            for (int m2 = 0; m2 < R2; ++m2) A[m1][m2] = v[m1 + R1 * m2];
+            Dft<T, T2, R2, DIR>::run(A[m1], tw, lr * R1);
+        }
+#pragma unroll
+        for (int m1 = 1; m1 < R1; ++m1)
+#pragma unroll
+            for (int s2 = 1; s2 < R2; ++s2) {
+                T2 w = tw[m1 * s2 * lr];
+                if (DIR > 0) w.y = -w.y;
+                A[m1][s2] = c_mul(A[m1][s2], w);
+            }
+#pragma unroll
+        for (int s2 = 0; s2 < R2; ++s2) {
+            T2 col[R1];
+#pragma unroll
+            for (int m1 = 0; m1 < R1; ++m1) col[m1] = A[m1][s2];
+            Dft<T, T2, R1, DIR>::run(col, tw, lr * R2);
+#pragma unroll
+            for (int s1 = 0; s1 < R1; ++s1) v[s2 + R2 * s1] = col[s1];
+        }
+    }
+};
+
+#define MSB_COMPOSITE(R, R1, R2)                                                              \
+    template <typename T, typename T2, int DIR> struct Dft<T, T2, R, DIR> {                   \
+        __device__ __forceinline__ static void run(T2 *v, const T2 *__restrict__ tw, int lr) { \
+            Dft2<T, T2, R1, R2, DIR>::run(v, tw, lr);                                         \
+        }                                                                                     \
+    };
+MSB_COMPOSITE(6, 3, 2)
+MSB_COMPOSITE(9, 3, 3)
+MSB_COMPOSITE(10, 5, 2)
+MSB_COMPOSITE(12, 4, 3)
+MSB_COMPOSITE(15, 5, 3)
+MSB_COMPOSITE(16, 4, 4)
+#undef MSB_COMPOSITE
+
 // One Stockham pass over S signals of length L stored back to back; twiddles in LDS.
 template <typename T, typename T2, int R, int DIR>
 __device__ __forceinline__ void stockham_pass(const T2 *__restrict__ in, T2 *__restrict__ out, int S,
@@ -198,7 +246,7 @@ __device__ __forceinline__ void stockham_pass(const T2 *__restrict__ in, T2 *__r
                 v[m] = c_mul(v[m], w);
             }
         }
-        Dft<T, T2, R, DIR>::run(v);
+        Dft<T, T2, R, DIR>::run(v, tw, L / R);
         T2 *y = out + s * L + jq * Ns * R + k;
 #pragma unroll
         for (int m = 0; m < R; ++m) y[m * Ns] = v[m];
@@ -208,7 +256,7 @@ __device__ __forceinline__ void stockham_pass(const T2 *__restrict__ in, T2 *__r
 // Full transform of S signals in LDS buffer a (scratch b); tw: the length-L twiddle
 // table staged in LDS.  Returns the buffer that holds the result.  Every thread of
 // the block must call it (it synchronises).
-template <typename T, typename T2, int DIR>
+template <typename T, typename T2, int DIR, int RMAX>
 __device__ T2 *fft_lds(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__restrict__ tw,
                        int tid, int nt) {
     const int L = sc.L;
@@ -219,7 +267,19 @@ __device__ T2 *fft_lds(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__rest
             case 3: stockham_pass<T, T2, 3, DIR>(a, b, S, L, ps, tw, tid, nt); break;
             case 4: stockham_pass<T, T2, 4, DIR>(a, b, S, L, ps, tw, tid, nt); break;
             case 5: stockham_pass<T, T2, 5, DIR>(a, b, S, L, ps, tw, tid, nt); break;
-            default: stockham_pass<T, T2, 8, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+            case 8: stockham_pass<T, T2, 8, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+            default:
+                if constexpr (RMAX >= 16) {
+                    switch (ps.R) {
+                        case 6: stockham_pass<T, T2, 6, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+                        case 9: stockham_pass<T, T2, 9, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+                        case 10: stockham_pass<T, T2, 10, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+                        case 12: stockham_pass<T, T2, 12, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+                        case 15: stockham_pass<T, T2, 15, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+                        default: stockham_pass<T, T2, 16, DIR>(a, b, S, L, ps, tw, tid, nt); break;
+                    }
+                }
+                break;
         }
         __syncthreads();
         T2 *t = a;
@@ -240,7 +300,7 @@ __device__ __forceinline__ void wave_sync() {
 
 // Transform of S signals owned by one wavefront (lane = 0..63) in its private LDS
 // buffers a/b; returns the buffer holding the result.  No block barrier.
-template <typename T, typename T2, int DIR>
+template <typename T, typename T2, int DIR, int RMAX>
 __device__ T2 *fft_wave(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__restrict__ tw, int lane) {
     const int L = sc.L;
     for (int p = 0; p < sc.np; ++p) {
@@ -250,7 +310,19 @@ __device__ T2 *fft_wave(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__res
             case 3: stockham_pass<T, T2, 3, DIR>(a, b, S, L, ps, tw, lane, 64); break;
             case 4: stockham_pass<T, T2, 4, DIR>(a, b, S, L, ps, tw, lane, 64); break;
             case 5: stockham_pass<T, T2, 5, DIR>(a, b, S, L, ps, tw, lane, 64); break;
-            default: stockham_pass<T, T2, 8, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+            case 8: stockham_pass<T, T2, 8, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+            default:
+                if constexpr (RMAX >= 16) {
+                    switch (ps.R) {
+                        case 6: stockham_pass<T, T2, 6, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+                        case 9: stockham_pass<T, T2, 9, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+                        case 10: stockham_pass<T, T2, 10, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+                        case 12: stockham_pass<T, T2, 12, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+                        case 15: stockham_pass<T, T2, 15, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+                        default: stockham_pass<T, T2, 16, DIR>(a, b, S, L, ps, tw, lane, 64); break;
+                    }
+                }
+                break;
         }
         wave_sync();
         T2 *t = a;

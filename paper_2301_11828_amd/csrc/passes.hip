@@ -62,16 +62,16 @@ template <bool BLOCK> struct Team {
     }
 };
 
-template <typename T, typename T2, int DIR, bool BLOCK>
+template <typename T, typename T2, int DIR, bool BLOCK, int RMAX>
 __device__ __forceinline__ T2 *team_fft(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *tw, const Team<BLOCK> &tm) {
-    if (BLOCK) return fft_lds<T, T2, DIR>(a, b, S, sc, tw, tm.tid, tm.nt);
-    return fft_wave<T, T2, DIR>(a, b, S, sc, tw, tm.tid);
+    if (BLOCK) return fft_lds<T, T2, DIR, RMAX>(a, b, S, sc, tw, tm.tid, tm.nt);
+    return fft_wave<T, T2, DIR, RMAX>(a, b, S, sc, tw, tm.tid);
 }
 
 // ---------------------------------------------------------------------------- x-forward
 // F grid rows per block; complex slot s packs real rows sig = 2s and 2s+1
 // (sig = c * nr + r: component c of grid row r0 + r).  Wave mode: one slot per wave.
-template <typename T, bool BLOCK>
+template <typename T, bool BLOCK, int RMAX>
 __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
     stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);
     __syncthreads();
     int s0, ns;
-    tm.slots(S, 1, s0, ns);
+    tm.slots(S, a.spw, s0, ns);
 
     const T hdt2 = T(0.5 * e.dt * e.dt);
     const T dtt = T(e.dt);
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
         }
     }
     tm.sync();
-    if (ns > 0) team_fft<T, T2, -1, BLOCK>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
+    if (ns > 0) team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
     if (!BLOCK) __syncthreads();
     const T2 *res = (a.sx.np & 1) ? bufB : bufA;
 
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
 // block, slot = (line, component); wave mode: one line (d slots) per wave.  Each
 // line is zero-padded to L, transformed, multiplied by the real symmetric d x d
 // spectrum block spec[(comp*nlines + line)*L + k] and transformed back.
-template <typename T, bool BLOCK>
+template <typename T, bool BLOCK, int RMAX>
 __global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
                                                    cplx_t<T> *data, int nlines, int Nl,
                                                    FftSched sl, const cplx_t<T> *twg) {
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
     stage_twiddles(tws, twg, L, threadIdx.x, blockDim.x);
     __syncthreads();
     int s0, ns;
-    tm.slots(nl * d, d, s0, ns);
+    tm.slots(nl * d, d * a.lpw, s0, ns);
     if (ns <= 0) return;
 
     for (int s = s0; s < s0 + ns; ++s) {
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
         }
     }
     tm.sync();
-    T2 *res = team_fft<T, T2, -1, BLOCK>(bufA + (size_t)s0 * L, bufB + (size_t)s0 * L, ns, sl, tws, tm);
+    T2 *res = team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * L, bufB + (size_t)s0 * L, ns, sl, tws, tm);
     T2 *oth = (res == bufA + (size_t)s0 * L) ? bufB + (size_t)s0 * L : bufA + (size_t)s0 * L;
 
     const T *spec = a.spec + (size_t)b * a.spec_slot;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
         }
     }
     tm.sync();
-    T2 *out = team_fft<T, T2, 1, BLOCK>(res, oth, ns, sl, tws, tm);
+    T2 *out = team_fft<T, T2, 1, BLOCK, RMAX>(res, oth, ns, sl, tws, tm);
     for (int s = 0; s < ns; ++s) {
         const int sg = s0 + s;
         const int li = sg / d, c = sg - li * d;
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
 // ---------------------------------------------------------------------------- 3D y passes
 // y-forward: T1[b][c][z][kx][y<Ny] -> T2[b][c][kx][ky<Ly][z].  Block = Fl consecutive
 // z of one (b, kx); slot = (z, component); wave mode: one z-line (d slots) per wave.
-template <typename T, bool BLOCK>
+template <typename T, bool BLOCK, int RMAX>
 __global__ __launch_bounds__(1024) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(1024) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
     stage_twiddles(twl, a.twy, Ly, threadIdx.x, blockDim.x);
     __syncthreads();
     int s0, ns;
-    tm.slots(nz * d, d, s0, ns);
+    tm.slots(nz * d, d * a.lpw, s0, ns);
     for (int s = s0; s < s0 + ns; ++s) {
         const int zl = s / d, c = s - zl * d;
         const T2 *src = a.T1 + ((((size_t)b * d + c) * a.Nz + z0 + zl) * a.H + kx) * a.Ny;
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(1024) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
         }
     }
     tm.sync();
-    if (ns > 0) team_fft<T, T2, -1, BLOCK>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
+    if (ns > 0) team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
     if (!BLOCK) __syncthreads();
     const T2 *res = (a.sy.np & 1) ? bufB : bufA;
     // the whole block stores, consecutive threads on consecutive z (T2's contiguous axis)
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(1024) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
 }
 
 // y-inverse: T2[b][c][kx][ky][z] -> T1[b][c][z][kx][y<Ny]
-template <typename T, bool BLOCK>
+template <typename T, bool BLOCK, int RMAX>
 __global__ __launch_bounds__(1024) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(1024) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
     stage_twiddles(twl, a.twy, Ly, threadIdx.x, blockDim.x);
     __syncthreads();
     int s0, ns;
-    tm.slots(nz * d, d, s0, ns);
+    tm.slots(nz * d, d * a.lpw, s0, ns);
     {
         // the whole block loads, consecutive threads on consecutive z
         const FastDiv dz(nz, nz * d * Ly), dd(d, d * Ly);
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(1024) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
     }
     __syncthreads();
     if (ns <= 0) return;
-    T2 *res = team_fft<T, T2, 1, BLOCK>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
+    T2 *res = team_fft<T, T2, 1, BLOCK, RMAX>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
     for (int s = 0; s < ns; ++s) {
         const int sg = s0 + s;
         const int zl = sg / d, c = sg - zl * d;
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(1024) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
 // half spectra of its two real rows, transformed back, then the broken-bond
 // correction of those rows, the incomplete-horizon diagonal, the constraint mask and
 // the fused epilogue are applied.
-template <typename T, bool BLOCK>
+template <typename T, bool BLOCK, int RMAX>
 __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
         const int nsg = min(2 * ns, nsig - 2 * s0);   // real rows of this team
         const size_t cbase = (size_t)b * d * a.N;
         const T *uin = e.uin;
-        T2 *R = team_fft<T, T2, 1, BLOCK>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
+        T2 *R = team_fft<T, T2, 1, BLOCK, RMAX>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
         T *Rr = reinterpret_cast<T *>(R);   // real row sl of this team at Rr[2 ((sl>>1) Lx + n) + (sl&1)]
 
         // broken bonds (eq. (tea:fr)): f_p += sum_{q in v_p} W(q - p) (u_p - u_q)
@@ -556,6 +556,11 @@ __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
 // ---------------------------------------------------------------------------- host side
 int x_tiles_per_case(const msb_plan_s *p, int F) { return (int)((rows_total(p) + F - 1) / F); }
 
+static int env_or(const char *name, int dflt) {
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
 static size_t lds_budget() {
     static size_t b = 0;
     if (!b) {
@@ -618,6 +623,7 @@ template <> const float *sel<float>(const double *, const float *b) { return b; 
 
 template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op) {
     PassArgs<T> a;
+    const bool f32 = sizeof(T) == 4;
     a.d = p->dim;
     a.B = p->B;
     a.Nx = (int)p->n[0];
@@ -635,9 +641,19 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
                        : lines_per_wg_for(p, sizeof(cplx_t<T>), (int)std::max(p->L[1], p->L[2]), nl);
     a.wave_x = wave_mode((int64_t)p->B * ((rows_total(p) * p->dim + 1) / 2)) ? 1 : 0;
     a.wave_l = wave_mode((int64_t)p->B * nl) ? 1 : 0;
-    a.sx = sched_of(p->ax[0]);
-    a.sy = sched_of(p->ax[1]);
-    a.sz = sched_of(p->ax[2]);
+    // wave mode: FP32 signals are cheap in registers, so a wave takes several (better
+    // lane use per Stockham stage); FP64 keeps one slot / one line per wave
+    a.spw = std::max(1, env_or("MSB_SLOTS_PER_WAVE", f32 ? 4 : 1));
+    a.lpw = std::max(1, env_or("MSB_LINES_PER_WAVE", f32 ? 2 : 1));
+    a.bthreads = std::max(64, std::min(1024, env_or("MSB_BLOCK_THREADS", 256)));
+    // block mode line pass: one thread per ~4 points of the block's signals, 256..512
+    {
+        const int64_t pts = (int64_t)a.Fl * p->dim * (p->dim == 2 ? p->L[1] : p->L[2]);
+        a.bthreads_line = std::max(64, std::min(1024, env_or("MSB_BLOCK_THREADS_LINE", pts >= 2048 ? 512 : 256)));
+    }
+    a.sx = sched_of(p->ax[0], f32);
+    a.sy = sched_of(p->ax[1], f32);
+    a.sz = sched_of(p->ax[2], f32);
     a.twx = tw_of<T>(p->ax[0]);
     a.twy = tw_of<T>(p->ax[1]);
     a.twz = tw_of<T>(p->ax[2]);
@@ -667,29 +683,29 @@ template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename T, bool B>
+template <typename T, bool B, int RM>
 static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev, bool wl) {
     using T2 = cplx_t<T>;
     int evi = 0;
     auto mark = [&]() -> hipError_t { return ev ? hipEventRecord(ev[evi++], st) : hipSuccess; };
     const int tpc = (a.rows + a.F - 1) / a.F;
     const size_t lds_x = lds_x_bytes(a.d, a.F, a.sx.L, sizeof(T2));
-    const int bx = B ? 256 : 64 * waves_x(a.d, a.F);
-    MSB_HIP(allow_lds(k_xfwd<T, B>, lds_x));
-    MSB_HIP(allow_lds(k_xinv<T, B>, lds_x));
+    const int bx = B ? a.bthreads : 64 * ((waves_x(a.d, a.F) + a.spw - 1) / a.spw);
+    MSB_HIP(allow_lds(k_xfwd<T, B, RM>, lds_x));
+    MSB_HIP(allow_lds(k_xinv<T, B, RM>, lds_x));
     MSB_HIP(mark());
-    hipLaunchKernelGGL((k_xfwd<T, B>), dim3(a.B * tpc), dim3(bx), lds_x, st, a, e);
+    hipLaunchKernelGGL((k_xfwd<T, B, RM>), dim3(a.B * tpc), dim3(bx), lds_x, st, a, e);
     MSB_HIP(mark());
     if (a.d == 2) {
         const int lpc = (a.H + a.Fl - 1) / a.Fl;
         const size_t lds = lds_line_bytes(a.d, a.Fl, a.sy.L, sizeof(T2));
         if (wl) {
-            MSB_HIP(allow_lds(k_line_prod<T, false>, lds));
-            hipLaunchKernelGGL((k_line_prod<T, false>), dim3(a.B * lpc), dim3(64 * a.Fl), lds, st, a, e, a.T1,
+            MSB_HIP(allow_lds(k_line_prod<T, false, RM>, lds));
+            hipLaunchKernelGGL((k_line_prod<T, false, RM>), dim3(a.B * lpc), dim3(64 * ((a.Fl + a.lpw - 1) / a.lpw)), lds, st, a, e, a.T1,
                                a.H, a.Ny, a.sy, a.twy);
         } else {
-            MSB_HIP(allow_lds(k_line_prod<T, true>, lds));
-            hipLaunchKernelGGL((k_line_prod<T, true>), dim3(a.B * lpc), dim3(256), lds, st, a, e, a.T1,
+            MSB_HIP(allow_lds(k_line_prod<T, true, RM>, lds));
+            hipLaunchKernelGGL((k_line_prod<T, true, RM>), dim3(a.B * lpc), dim3(a.bthreads_line), lds, st, a, e, a.T1,
                                a.H, a.Ny, a.sy, a.twy);
         }
         MSB_HIP(mark());
@@ -699,31 +715,31 @@ static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, hipStr
         const int nlines = a.H * a.Ly;
         const int lpc = (nlines + a.Fl - 1) / a.Fl;
         const size_t lds_z = lds_line_bytes(a.d, a.Fl, a.sz.L, sizeof(T2));
-        const int by = wl ? 64 * a.Fl : 256;
+        const int by = wl ? 64 * ((a.Fl + a.lpw - 1) / a.lpw) : a.bthreads;
         if (wl) {
-            MSB_HIP(allow_lds(k_yfwd<T, false>, lds_y));
-            MSB_HIP(allow_lds(k_yinv<T, false>, lds_y));
-            MSB_HIP(allow_lds(k_line_prod<T, false>, lds_z));
-            hipLaunchKernelGGL((k_yfwd<T, false>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
+            MSB_HIP(allow_lds(k_yfwd<T, false, RM>, lds_y));
+            MSB_HIP(allow_lds(k_yinv<T, false, RM>, lds_y));
+            MSB_HIP(allow_lds(k_line_prod<T, false, RM>, lds_z));
+            hipLaunchKernelGGL((k_yfwd<T, false, RM>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
             MSB_HIP(mark());
-            hipLaunchKernelGGL((k_line_prod<T, false>), dim3(a.B * lpc), dim3(by), lds_z, st, a, e, a.T2,
+            hipLaunchKernelGGL((k_line_prod<T, false, RM>), dim3(a.B * lpc), dim3(by), lds_z, st, a, e, a.T2,
                                nlines, a.Nz, a.sz, a.twz);
             MSB_HIP(mark());
-            hipLaunchKernelGGL((k_yinv<T, false>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
+            hipLaunchKernelGGL((k_yinv<T, false, RM>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
         } else {
-            MSB_HIP(allow_lds(k_yfwd<T, true>, lds_y));
-            MSB_HIP(allow_lds(k_yinv<T, true>, lds_y));
-            MSB_HIP(allow_lds(k_line_prod<T, true>, lds_z));
-            hipLaunchKernelGGL((k_yfwd<T, true>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
+            MSB_HIP(allow_lds(k_yfwd<T, true, RM>, lds_y));
+            MSB_HIP(allow_lds(k_yinv<T, true, RM>, lds_y));
+            MSB_HIP(allow_lds(k_line_prod<T, true, RM>, lds_z));
+            hipLaunchKernelGGL((k_yfwd<T, true, RM>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
             MSB_HIP(mark());
-            hipLaunchKernelGGL((k_line_prod<T, true>), dim3(a.B * lpc), dim3(by), lds_z, st, a, e, a.T2,
+            hipLaunchKernelGGL((k_line_prod<T, true, RM>), dim3(a.B * lpc), dim3(by), lds_z, st, a, e, a.T2,
                                nlines, a.Nz, a.sz, a.twz);
             MSB_HIP(mark());
-            hipLaunchKernelGGL((k_yinv<T, true>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
+            hipLaunchKernelGGL((k_yinv<T, true, RM>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
         }
         MSB_HIP(mark());
     }
-    hipLaunchKernelGGL((k_xinv<T, B>), dim3(a.B * tpc), dim3(bx), lds_x, st, a, e);
+    hipLaunchKernelGGL((k_xinv<T, B, RM>), dim3(a.B * tpc), dim3(bx), lds_x, st, a, e);
     MSB_HIP(mark());
     MSB_HIP(hipGetLastError());
     return MSB_OK;
@@ -731,8 +747,20 @@ static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, hipStr
 
 template <typename T>
 msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev) {
-    if (a.wave_x) return launch_chain<T, false>(a, e, st, ev, a.wave_l != 0);
-    return launch_chain<T, true>(a, e, st, ev, a.wave_l != 0);
+    // kernels built with RMAX = 8 only contain the basic radices 2, 3, 4, 5, 8
+    bool composite = false;
+    for (const FftSched *sc : {&a.sx, &a.sy, &a.sz})
+        for (int i = 0; i < sc->np; ++i) {
+            const int r = sc->ps[i].R;
+            composite = composite || !(r == 2 || r == 3 || r == 4 || r == 5 || r == 8);
+        }
+    const bool wl = a.wave_l != 0;
+    if (!composite) {
+        if (a.wave_x) return launch_chain<T, false, 8>(a, e, st, ev, wl);
+        return launch_chain<T, true, 8>(a, e, st, ev, wl);
+    }
+    if (a.wave_x) return launch_chain<T, false, 16>(a, e, st, ev, wl);
+    return launch_chain<T, true, 16>(a, e, st, ev, wl);
 }
 
 template PassArgs<double> pass_args<double>(const msb_plan_s *, const DeviceOp &);

@@ -31,6 +31,9 @@ template <typename T> struct PassArgs {
     int F;               // rows per workgroup (x passes)
     int Fl;              // lines per workgroup (line passes)
     int wave_x, wave_l;  // 1: wave-owned signals, 0: whole-block teams (x passes / line passes)
+    int spw, lpw;        // wave mode: complex slots per wave (x passes), lines per wave (line passes)
+    int bthreads;        // block mode: threads per block (x and y passes)
+    int bthreads_line;   // block mode: threads per block of the 2D line pass
     int N;               // nodes per case
     FftSched sx, sy, sz;
     const cplx_t<T> *twx, *twy, *twz;

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <numeric>
 
 #include "common.hpp"
@@ -34,25 +35,55 @@ void set_error(const char *fmt, ...) {
 }
 
 // ------------------------------------------------------------------ lengths
-bool factor_length(int L, std::vector<int> &radices) {
+// Radices the device code implements: basic 2, 3, 4, 5, 8 and register-composite
+// 6, 9, 10, 12, 15, 16 (two-level Cooley-Tukey inside a thread; kernels built for
+// radix <= 16 only instantiate these).
+static const int kRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+
+// Largest radix of the FP64 / FP32 schedules (measured: FP64 kernels keep more
+// occupancy with the basic radices, FP32 gains from fewer LDS stages).
+static int max_radix(bool fp32) {
+    const char *e = getenv(fp32 ? "MSB_MAX_RADIX32" : "MSB_MAX_RADIX");
+    if (!e) e = getenv("MSB_MAX_RADIX");
+    return e ? atoi(e) : (fp32 ? 16 : 8);
+}
+
+// Factor L into the fewest Stockham stages with radix <= rmax; ties go to the
+// factorisation whose smallest radix is largest (balanced stages).
+bool factor_length(int L, std::vector<int> &radices, int rmax_in) {
     radices.clear();
-    int n = L;
-    int c8 = 0, c4 = 0, c2 = 0, c3 = 0, c5 = 0;
-    while (n % 2 == 0) { n /= 2; ++c2; }
-    while (n % 3 == 0) { n /= 3; ++c3; }
-    while (n % 5 == 0) { n /= 5; ++c5; }
-    if (n != 1) return false;
-    c8 = c2 / 3;
-    c2 -= 3 * c8;
-    c4 = c2 / 2;
-    c2 -= 2 * c4;
-    // larger radices first: fewer LDS round trips
-    for (int i = 0; i < c8; ++i) radices.push_back(8);
-    for (int i = 0; i < c4; ++i) radices.push_back(4);
-    for (int i = 0; i < c5; ++i) radices.push_back(5);
-    for (int i = 0; i < c3; ++i) radices.push_back(3);
-    for (int i = 0; i < c2; ++i) radices.push_back(2);
-    if (radices.empty()) radices.push_back(1);
+    {
+        int n = L;
+        for (int p : {2, 3, 5})
+            while (n % p == 0) n /= p;
+        if (n != 1) return false;
+    }
+    if (L == 1) {
+        radices.push_back(1);
+        return true;
+    }
+    const int rmax = std::max(2, rmax_in);
+    // best[n] = (stages, -min radix) over factorisations of n
+    std::vector<int> st(L + 1, 1 << 20), mn(L + 1, 0), pick(L + 1, 0);
+    st[1] = 0;
+    mn[1] = 1 << 20;
+    for (int n = 2; n <= L; ++n) {
+        if (L % n) continue;
+        for (int r : kRadices) {
+            if (r > rmax || n % r) continue;
+            const int m = n / r;
+            if (st[m] >= (1 << 20)) continue;
+            const int s = st[m] + 1, lo = std::min(mn[m], r);
+            if (s < st[n] || (s == st[n] && lo > mn[n])) {
+                st[n] = s;
+                mn[n] = lo;
+                pick[n] = r;
+            }
+        }
+    }
+    if (st[L] >= (1 << 20)) return false;
+    for (int n = L; n > 1; n /= pick[n]) radices.push_back(pick[n]);
+    std::sort(radices.begin(), radices.end(), std::greater<int>());
     return true;
 }
 
@@ -106,12 +137,15 @@ static void unit_circle(int L, std::vector<long double> &c, std::vector<long dou
 }
 
 static msb_status make_axis(int L, FftAxis &ax) {
-    std::vector<int> r;
-    MSB_CHECK(factor_length(L, r), MSB_EINVAL, "FFT length %d is not 5-smooth", L);
-    MSB_CHECK((int)r.size() <= kMaxPasses, MSB_EINVAL, "FFT length %d too long", L);
+    std::vector<int> r, r32;
+    MSB_CHECK(factor_length(L, r, max_radix(false)) && factor_length(L, r32, max_radix(true)), MSB_EINVAL,
+              "FFT length %d is not 5-smooth", L);
+    MSB_CHECK((int)r.size() <= kMaxPasses && (int)r32.size() <= kMaxPasses, MSB_EINVAL, "FFT length %d too long", L);
     ax.L = L;
     ax.np = (L == 1) ? 0 : (int)r.size();
     for (int i = 0; i < ax.np; ++i) ax.radix[i] = r[i];
+    ax.np32 = (L == 1) ? 0 : (int)r32.size();
+    for (int i = 0; i < ax.np32; ++i) ax.radix32[i] = r32[i];
     std::vector<long double> c, s;
     unit_circle(L, c, s);
     std::vector<double2> t64(L);
