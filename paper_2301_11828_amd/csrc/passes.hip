@@ -70,7 +70,7 @@ __device__ __forceinline__ T2 *team_fft(T2 *a, T2 *b, int S, const FftSched &sc,
 
 // ---------------------------------------------------------------------------- x-forward
 // F grid rows per block; complex slot s packs real rows sig = 2s and 2s+1
-// (sig = c * nr + r: component c of grid row r0 + r).  Wave mode: one slot per wave.
+// (sig = c * nr + r: component c of grid row r0 + r).  Wave mode: each wave owns a.spw consecutive slots.
 template <typename T, bool BLOCK, int RMAX>
 __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
     using T2 = cplx_t<T>;
@@ -91,18 +91,35 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
     T2 *bufB = bufA + (size_t)Smax * Lx;
     if (e.case_done && e.case_done[b]) return;
 
-    T beta = T(0);
+    // fused CG step (single reduction per iteration, Chronopoulos-Gear form)
+    T alpha = T(0), beta = T(0);
+    bool upd = false, conv = false;
     if (e.pro == PRO_CG_P) {
-        // r.r of the current residual decides convergence (flag 1) or a
-        // non-finite residual (flag 3) before any work; beta = r.r / r_old.r_old
-        const double rn = block_sum_partials(e.beta_part + (size_t)b * e.nbeta, e.nbeta, red, threadIdx.x, blockDim.x);
-        if (e.thresh && !(rn > e.thresh[b])) {
-            if (r0 == 0 && threadIdx.x == 0) e.done_rw[b] = (rn == rn && rn <= 1e300) ? 1 : 3;
-            return;
-        }
-        if (e.beta_part_old) {
-            const double ro = block_sum_partials(e.beta_part_old + (size_t)b * e.nbeta, e.nbeta, red, threadIdx.x, blockDim.x);
-            beta = ro > 0.0 ? T(rn / ro) : T(0);
+        const int tid0 = threadIdx.x, ntb = blockDim.x;
+        if (!e.first) {
+            const size_t st3 = (size_t)gridDim.x;
+            const double rr = block_sum_partials(e.rr_prev + (size_t)b * tpc, tpc, red, tid0, ntb);
+            const double pq = block_sum_partials(e.cg3 + (size_t)b * tpc, tpc, red, tid0, ntb);
+            const double rq = block_sum_partials(e.cg3 + st3 + (size_t)b * tpc, tpc, red, tid0, ntb);
+            const double qq = block_sum_partials(e.cg3 + 2 * st3 + (size_t)b * tpc, tpc, red, tid0, ntb);
+            const double al = rr / pq;
+            if (!(pq > 0.0) || !(al == al) || al > 1e300) {   // K not positive definite on p
+                if (r0 == 0 && tid0 == 0) e.done_rw[b] = 2;
+                return;
+            }
+            const double rrn = rr - 2.0 * al * rq + al * al * qq;
+            if (!(rrn == rrn)) {
+                if (r0 == 0 && tid0 == 0) e.done_rw[b] = 3;
+                return;
+            }
+            alpha = T(al);
+            beta = T(rr > 0.0 ? rrn / rr : 0.0);
+            upd = true;
+            conv = e.update_only || (e.thresh && !(rrn > e.thresh[b]));
+        } else if (e.beta_num) {
+            const double num = block_sum_partials(e.beta_num + (size_t)b * e.n_num, e.n_num, red, tid0, ntb);
+            const double den = block_sum_partials(e.beta_den + (size_t)b * e.n_den, e.n_den, red, tid0, ntb);
+            beta = T(den > 0.0 ? num / den : 0.0);
         }
     }
     stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);
@@ -113,6 +130,7 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
     const T hdt2 = T(0.5 * e.dt * e.dt);
     const T dtt = T(e.dt);
     const size_t cbase = (size_t)b * a.d * a.N;
+    double rr_acc = 0.0;
     for (int s = s0; s < s0 + ns; ++s) {
         size_t rowaddr[2];
         int rowfix[2];
@@ -140,8 +158,16 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
                     if (e.pro == PRO_NONE) {
                         v = e.pio[addr];
                     } else if (e.pro == PRO_CG_P) {
-                        v = e.pr[addr] + beta * e.pio[addr];
-                        e.pio[addr] = v;
+                        const T pv = e.pio[addr];
+                        T rv = e.cr[addr];
+                        if (upd) {
+                            e.cx[addr] += alpha * pv;
+                            rv -= alpha * e.cq[addr];
+                            e.cr[addr] = rv;
+                        }
+                        rr_acc += (double)rv * (double)rv;
+                        v = conv ? T(0) : rv + beta * pv;
+                        if (!conv) e.pio[addr] = v;
                     } else {
                         const bool fx = a.fixed && a.fixed[rowfix[h2] + n];
                         if (fx) v = e.pg ? e.pg[addr] : T(0);
@@ -154,6 +180,18 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
             }
             dst[n] = z;
         }
+    }
+    if (e.pro == PRO_CG_P) {
+        double v[1] = {rr_acc};
+        block_sum<1>(v, red, threadIdx.x, blockDim.x);
+        if (threadIdx.x == 0) {
+            e.rr_out[tile] = v[0];
+            if (r0 == 0) {
+                if (upd) e.iters[b] += 1;
+                if (conv) e.done_rw[b] = e.update_only ? 5 : 1;
+            }
+        }
+        if (conv) return;
     }
     tm.sync();
     if (ns > 0) team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
@@ -404,7 +442,7 @@ __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
     stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);
     __syncthreads();
     int s0, ns;
-    tm.slots(S, 1, s0, ns);
+    tm.slots(S, a.spw_i, s0, ns);
 
     // full spectrum Z = Xa + i Xb of every slot with the Hermitian halves mirrored;
     // the whole block loads, consecutive threads on consecutive rows of one kx
@@ -508,7 +546,10 @@ __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
                     case EPI_CG_Q: {
                         const T q = fx ? T(0) : -f;
                         e.out[addr] = q;
-                        acc0 += (double)uin[addr] * (double)q;
+                        const double qd = (double)q;
+                        acc0 += (double)uin[addr] * qd;
+                        acc1 += (double)e.rhs[addr] * qd;
+                        acc2 += qd * qd;
                         break;
                     }
                     case EPI_RESID: {
@@ -644,6 +685,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     // wave mode: FP32 signals are cheap in registers, so a wave takes several (better
     // lane use per Stockham stage); FP64 keeps one slot / one line per wave
     a.spw = std::max(1, env_or("MSB_SLOTS_PER_WAVE", f32 ? 4 : 1));
+    a.spw_i = std::max(1, env_or("MSB_SLOTS_PER_WAVE_INV", a.spw));
     a.lpw = std::max(1, env_or("MSB_LINES_PER_WAVE", f32 ? 2 : 1));
     a.bthreads = std::max(64, std::min(1024, env_or("MSB_BLOCK_THREADS", 256)));
     // block mode line pass: one thread per ~4 points of the block's signals, 256..512
@@ -691,6 +733,7 @@ static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, hipStr
     const int tpc = (a.rows + a.F - 1) / a.F;
     const size_t lds_x = lds_x_bytes(a.d, a.F, a.sx.L, sizeof(T2));
     const int bx = B ? a.bthreads : 64 * ((waves_x(a.d, a.F) + a.spw - 1) / a.spw);
+    const int bxi = B ? a.bthreads : 64 * ((waves_x(a.d, a.F) + a.spw_i - 1) / a.spw_i);
     MSB_HIP(allow_lds(k_xfwd<T, B, RM>, lds_x));
     MSB_HIP(allow_lds(k_xinv<T, B, RM>, lds_x));
     MSB_HIP(mark());
@@ -739,7 +782,7 @@ static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, hipStr
         }
         MSB_HIP(mark());
     }
-    hipLaunchKernelGGL((k_xinv<T, B, RM>), dim3(a.B * tpc), dim3(bx), lds_x, st, a, e);
+    hipLaunchKernelGGL((k_xinv<T, B, RM>), dim3(a.B * tpc), dim3(bxi), lds_x, st, a, e);
     MSB_HIP(mark());
     MSB_HIP(hipGetLastError());
     return MSB_OK;

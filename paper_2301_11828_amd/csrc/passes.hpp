@@ -9,14 +9,14 @@ namespace msb {
 // What the x-forward pass does to its input rows before transforming them.
 enum Prologue : int {
     PRO_NONE = 0,   // transform u as given
-    PRO_CG_P = 1,   // p <- r + beta p (beta from partial sums), store p, transform p
+    PRO_CG_P = 1,   // fused CG step: x += alpha p, r -= alpha q, p <- r + beta p, transform p
     PRO_VV_U = 2,   // u <- u + dt v + dt^2 a / 2, u_C <- g_C, store u, transform u
 };
 
 // What the x-inverse pass does with f = A u after the corrections.
 enum Epilogue : int {
     EPI_APPLY = 0,  // out = sign * f, 0 on constrained DOFs
-    EPI_CG_Q = 1,   // out = q = -f (K p), 0 on constrained; partial p.q
+    EPI_CG_Q = 1,   // out = q = -f (K p), 0 on constrained; partials p.q, r.q, q.q
     EPI_RESID = 2,  // out = rhs + f, 0 on constrained; partial out.out
     EPI_VV = 3,     // a' = (f + b)/rho; v += dt (a + a')/2; a = a'; energy partials
     EPI_DOT = 4,    // no output; partial w.f over free DOFs
@@ -31,7 +31,7 @@ template <typename T> struct PassArgs {
     int F;               // rows per workgroup (x passes)
     int Fl;              // lines per workgroup (line passes)
     int wave_x, wave_l;  // 1: wave-owned signals, 0: whole-block teams (x passes / line passes)
-    int spw, lpw;        // wave mode: complex slots per wave (x passes), lines per wave (line passes)
+    int spw, spw_i, lpw; // wave mode: complex slots per wave (x-forward, x-inverse), lines per wave (line passes)
     int bthreads;        // block mode: threads per block (x and y passes)
     int bthreads_line;   // block mode: threads per block of the 2D line pass
     int N;               // nodes per case
@@ -64,9 +64,20 @@ template <typename T> struct EndArgs {
     const T *pr;         // PRO_CG_P: r;          PRO_VV_U: v
     const T *pa;         // PRO_VV_U: a
     const T *pg;         // PRO_VV_U: g or null
-    const double *beta_part;   // PRO_CG_P: partial sums rr_new [B][nbeta], rr_old [B][nbeta]
-    const double *beta_part_old;
-    int nbeta;
+    // PRO_CG_P (single-reduction CG): alpha = r.r / p.q, r'.r' = r.r - 2 alpha r.q +
+    // alpha^2 q.q, beta = r'.r' / r.r from the partial sums of the previous iteration
+    T *cx;                     // x (updated)
+    T *cr;                     // r (updated)
+    const T *cq;               // q = K p of the previous iteration
+    const double *cg3;         // previous x-inverse partials [3][B*tiles]: p.q, r.q, q.q
+    const double *rr_prev;     // previous true r.r partials [B][tiles]
+    double *rr_out;            // this iteration's true r.r partials [B][tiles]
+    const double *beta_num;    // first iteration of a continued run: beta = sum(num)/sum(den)
+    const double *beta_den;
+    int n_num, n_den;
+    int first;                 // no pending update (first iteration)
+    int update_only;           // apply the pending update and stop (no transform)
+    int *iters;                // [B] completed updates
     const int *case_done;      // [B] per-case stop flags (skip work) or null
     int *done_rw;              // PRO_CG_P: flags written when a case converges
     const double *thresh;      // PRO_CG_P: per-case stop threshold on r.r (or null)
@@ -74,7 +85,7 @@ template <typename T> struct EndArgs {
     // epilogue
     const T *uin;        // the vector that was transformed (for D^e, D^f, dots)
     T *out;              // EPI_APPLY/CG_Q/RESID output
-    const T *rhs;        // EPI_RESID rhs; EPI_VV b; EPI_DOT w
+    const T *rhs;        // EPI_RESID rhs; EPI_VV b; EPI_DOT w; EPI_CG_Q r
     T *ev;               // EPI_VV: v
     T *ea;               // EPI_VV: a
     double sign;         // EPI_APPLY sign

@@ -23,15 +23,15 @@ namespace msb {
 constexpr int kT = 256;
 
 // flags in SolverWs::done
-enum : int { RUNNING = 0, CONVERGED = 1, BREAKDOWN = 2, NONFINITE = 3, SKIPPED = 4 };
+enum : int { RUNNING = 0, CONVERGED = 1, BREAKDOWN = 2, NONFINITE = 3, SKIPPED = 4, CAPPED = 5 };
 
 struct SolverWs {
     size_t nvec = 0;                 // B * d * N
     double *v64[6] = {};             // FP64 vectors
     float *v32[5] = {};              // FP32 vectors
     double *part_x = nullptr;        // [3][B * rows] x-inverse epilogue partials
-    double *part_rr = nullptr;       // [2][B][P] r.r partials
-    double *part_aux = nullptr;      // [B][P] dot partials
+    double *part_rr = nullptr;       // [2][B][tiles] true r.r partials (by iteration parity)
+    double *part_aux = nullptr;      // [3][B][P] dot partials
     double *thresh = nullptr;        // [B]
     double *scal = nullptr;          // [16][B] per-case scalars
     double *energy = nullptr;        // energies (device)
@@ -79,7 +79,7 @@ static msb_status get_ws(msb_plan_s *p, SolverWs *&out) {
     for (auto &x : w->v64) MSB_HIP(hipMalloc(&x, sizeof(double) * w->nvec));
     for (auto &x : w->v32) MSB_HIP(hipMalloc(&x, sizeof(float) * w->nvec));
     MSB_HIP(hipMalloc(&w->part_x, sizeof(double) * 3 * (size_t)B * rows_total(p)));
-    MSB_HIP(hipMalloc(&w->part_rr, sizeof(double) * 2 * (size_t)B * w->P));
+    MSB_HIP(hipMalloc(&w->part_rr, sizeof(double) * 2 * (size_t)B * std::max<int64_t>(rows_total(p), w->P)));
     MSB_HIP(hipMalloc(&w->part_aux, sizeof(double) * 3 * (size_t)B * w->P));
     MSB_HIP(hipMalloc(&w->thresh, sizeof(double) * B));
     MSB_HIP(hipMalloc(&w->scal, sizeof(double) * 16 * B));
@@ -164,39 +164,6 @@ __global__ void k_cg_setup(const double *rr_part, int P, double tol2, double *th
     iters[b] = 0;
 }
 
-// x += alpha p ; r -= alpha q ; partial r.r.  alpha = (r.r)/(p.q) from partials.
-template <typename T>
-__global__ __launch_bounds__(kT) void k_cg_update(T *x, T *r, const T *p, const T *q,
-                                                  const double *pq_part, int npq,
-                                                  const double *rr_cur, double *rr_nxt, int P,
-                                                  int *done, int *iters, size_t dn) {
-    __shared__ double red[80];
-    const int b = blockIdx.x / P, blk = blockIdx.x - b * P;
-    if (done[b]) return;
-    const double pq = block_sum_partials(pq_part + (size_t)b * npq, npq, red, threadIdx.x, kT);
-    const double rr = block_sum_partials(rr_cur + (size_t)b * P, P, red, threadIdx.x, kT);
-    const double alpha = rr / pq;
-    if (!(pq > 0.0) || !std::isfinite(alpha)) {   // K p . p <= 0: not positive definite
-        if (blk == 0 && threadIdx.x == 0) done[b] = BREAKDOWN;
-        return;
-    }
-    const T a = T(alpha);
-    const size_t base = (size_t)b * dn;
-    double v[1] = {0.0};
-    for (size_t i = (size_t)blk * kT + threadIdx.x; i < dn; i += (size_t)P * kT) {
-        const size_t j = base + i;
-        x[j] += a * p[j];
-        const T rn = r[j] - a * q[j];
-        r[j] = rn;
-        v[0] += (double)rn * (double)rn;
-    }
-    block_sum<1>(v, red, threadIdx.x, kT);
-    if (threadIdx.x == 0) {
-        rr_nxt[blockIdx.x] = v[0];
-        if (blk == 0) iters[b] += 1;
-    }
-}
-
 // a = (a + b)/rho on free DOFs, 0 on constrained
 template <typename T>
 __global__ void k_vv_accel(T *a, const T *bf, const uint8_t *fixed, size_t n, size_t dn, double rho) {
@@ -261,33 +228,42 @@ template <typename T> struct Cg {
     const double *prev_rr;   // r.r partials before a residual replacement (first beta), or null
 };
 
-template <typename T> static msb_status cg_iteration(Cg<T> &c, int it) {
+// One CG iteration = one product chain.  The x-forward prologue applies the
+// previous iteration's update (x += alpha p, r -= alpha q, alpha and beta from the
+// previous partial sums) and forms p = r + beta p; the x-inverse epilogue forms
+// q = K p and the partials p.q, r.q, q.q.  No separate vector kernel.
+template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool update_only = false) {
     msb_plan_s *p = c.p;
     SolverWs *w = c.w;
-    const int B = p->B, P = w->P;
-    double *rr_cur = w->part_rr + (size_t)(it & 1) * B * P;
-    double *rr_nxt = w->part_rr + (size_t)((it + 1) & 1) * B * P;
+    const int B = p->B;
+    const size_t nt = (size_t)B * c.tpc;
     EndArgs<T> e = end_args<T>();
     e.pro = PRO_CG_P;
     e.pio = c.pv;
-    e.pr = c.r;
-    e.beta_part = rr_cur;
-    e.beta_part_old = it == 0 ? c.prev_rr : rr_nxt;
-    e.nbeta = P;
+    e.cx = c.x;
+    e.cr = c.r;
+    e.cq = c.q;
+    e.cg3 = w->part_x;
+    e.rr_prev = w->part_rr + (size_t)((it + 1) & 1) * nt;
+    e.rr_out = w->part_rr + (size_t)(it & 1) * nt;
+    e.first = it == 0;
+    e.update_only = update_only;
+    e.iters = w->iters;
+    if (it == 0 && c.prev_rr) {   // continuation after a residual replacement
+        e.beta_num = w->part_aux;
+        e.n_num = w->P;
+        e.beta_den = c.prev_rr;
+        e.n_den = c.tpc;
+    }
     e.case_done = w->done;
     e.done_rw = w->done;
     e.thresh = w->thresh;
     e.epi = EPI_CG_Q;
     e.uin = c.pv;
     e.out = c.q;
+    e.rhs = c.r;
     e.part = w->part_x;
-    MSB_TRY(launch_product<T>(c.pa, e, c.st));
-    const size_t dn = (size_t)p->dim * p->N;
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(B * P), dim3(kT), 0, c.st, c.x, c.r, (const T *)c.pv,
-                       (const T *)c.q, (const double *)w->part_x, c.tpc, (const double *)rr_cur, rr_nxt,
-                       P, w->done, w->iters, dn);
-    MSB_HIP(hipGetLastError());
-    return MSB_OK;
+    return launch_product<T>(c.pa, e, c.st);
 }
 
 static int env_int(const char *name, int dflt) {
@@ -332,6 +308,8 @@ template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_bl
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    // iteration cap: apply the pending update of the cases still running
+    if (st == MSB_OK) st = cg_iteration(c, it, true);
     *it_out = it;
     return st;
 }
@@ -357,9 +335,9 @@ static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, x, n, T(0));
     if (!prev_rr) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
     hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(n)), dim3(kT), 0, st, r, rhs, n);
-    hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * P), dim3(kT), 0, st, (const T *)r, (const T *)r, w->part_rr,
+    hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * P), dim3(kT), 0, st, (const T *)r, (const T *)r, w->part_aux,
                        (size_t)p->dim * p->N, P);
-    hipLaunchKernelGGL(k_cg_setup, dim3((B + 63) / 64), dim3(64), 0, st, (const double *)w->part_rr, P, tol * tol,
+    hipLaunchKernelGGL(k_cg_setup, dim3((B + 63) / 64), dim3(64), 0, st, (const double *)w->part_aux, P, tol * tol,
                        w->thresh, w->done, skip, w->iters, B);
     MSB_HIP(hipGetLastError());
     int it = 0;
@@ -545,7 +523,7 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
         }
         MSB_TRY(fetch_scal(w, st, 1, B));
         for (int c = 0; c < B; ++c) {
-            fl[c] = w->h_int[c];
+            fl[c] = w->h_int[c] == CAPPED ? RUNNING : w->h_int[c];
             inner[c] = w->h_int[B + c];
             outer[c] = 1;
         }
@@ -561,7 +539,8 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
         MSB_HIP(hipMalloc(&skip, sizeof(int) * B));
         float *r32 = w->v32[0], *d32 = w->v32[1], *p32 = w->v32[2];
         double *r64 = w->v64[2];
-        double *prev = w->part_aux + (size_t)B * w->P;
+        double *prev = nullptr;   // [B][tiles] r.r partials before the replacement
+        if (reliable) MSB_HIP(hipMalloc(&prev, sizeof(double) * (size_t)B * rows_total(p)));
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kT), 0, st, u, n, 0.0);
         hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(kT), 0, st, p32, n, 0.0f);
         hipLaunchKernelGGL((k_cast<double, double>), dim3(grid_for(n)), dim3(kT), 0, st, r64, (const double *)bp, n);
@@ -601,8 +580,11 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
                 mx = std::max(mx, w->h_int[B + c]);
             }
             used += mx;
-            if (reliable) hipLaunchKernelGGL(k_save_rr, dim3(B), dim3(64), 0, st, (const double *)w->part_rr,
-                                             (const int *)w->iters, w->P, B, prev);
+            if (reliable) {
+                const int tpc = x_tiles_per_case(p, pass_args<float>(p, p->op).F);
+                hipLaunchKernelGGL(k_save_rr, dim3(B), dim3(64), 0, st, (const double *)w->part_rr,
+                                   (const int *)w->iters, tpc, B, prev);
+            }
             hipLaunchKernelGGL(k_add_to<float>, dim3(grid_for(n)), dim3(kT), 0, st, u, (const float *)d32, n);
             MSB_TRY(true_residual(p, w, st, u, bp, r64, 0));
             MSB_TRY(fetch_scal(w, st, 1, B));
@@ -619,6 +601,7 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
             }
         }
         (void)hipFree(skip);
+        if (prev) (void)hipFree(prev);
         for (int c = 0; c < B; ++c)
             if (fl[c] == -1) fl[c] = RUNNING;   // reported as no convergence below
     }

@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 from paper_2301_11828_amd import workloads as W
-from helpers import gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
+from helpers import gpu_apply, gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +45,7 @@ def test_apply_fp64_matches_oracle(case):
     plan = gpu_plan(w)
     if crack:
         assert plan.n_bonds == len(oracle_bonds(w)) > 0
-    f = plan.apply(to_dev(w.b)).cpu().numpy()
+    f = gpu_apply(plan, to_dev(w.b)).cpu().numpy()
     import paper_2301_11828_amd as msb
     log("  HIP runtime(s): %s" % msb.loaded_hip_runtimes())
     assert len(msb.loaded_hip_runtimes()) == 1
@@ -64,7 +64,7 @@ def test_apply_fp32_error_bounded(case):
     import torch
     w = W.small(dim, n, M, seed=7, fixed=fixed, crack=crack, batch=batch)
     plan = gpu_plan(w)
-    f = plan.apply(to_dev(w.b, torch.float32)).double().cpu().numpy()
+    f = gpu_apply(plan, to_dev(w.b, torch.float32)).double().cpu().numpy()
     ref = _oracle_apply(w, w.b.astype(np.float32).astype(np.float64))
     for c in range(batch):
         err = rel_err(f[c], ref[c])
@@ -88,7 +88,7 @@ def test_exhaustive_unit_vectors_reproduce_dense_A(dim):
     cols = np.arange(D) if dim == 2 else np.random.default_rng(0).choice(D, 81 * 3, replace=False)
     U = np.zeros((len(cols), D))
     U[np.arange(len(cols)), cols] = 1.0
-    F = plan.apply(to_dev(U.reshape(len(cols), dim, w.N))).cpu().numpy().reshape(len(cols), D)
+    F = gpu_apply(plan, to_dev(U.reshape(len(cols), dim, w.N))).cpu().numpy().reshape(len(cols), D)
     ref = A[:, cols].T.copy()
     ref[:, fixed] = 0.0
     err = np.abs(F - ref).max() / np.abs(A).max()
@@ -112,8 +112,8 @@ def test_apply_deterministic():
     w = W.small(3, (12, 10, 9), 3, seed=5, fixed="bottom", batch=2)
     plan = gpu_plan(w)
     u = to_dev(w.b)
-    a = plan.apply(u).cpu().numpy()
-    b = plan.apply(u).cpu().numpy()
+    a = gpu_apply(plan, u).cpu().numpy()
+    b = gpu_apply(plan, u).cpu().numpy()
     assert np.array_equal(a, b)
 
 
@@ -124,11 +124,11 @@ def test_rigid_translation_and_rotation_on_gpu():
     plan = gpu_plan(w)
     x = oracle_problem(w).node_coords()
     u = np.stack([np.full(w.N, 0.3), np.full(w.N, -0.7)])[None]
-    f = plan.apply(to_dev(u)).cpu().numpy()
-    scale = np.abs(plan.apply(to_dev(np.stack([x[0], 0 * x[0]])[None])).cpu().numpy()).max()
+    f = gpu_apply(plan, to_dev(u)).cpu().numpy()
+    scale = np.abs(gpu_apply(plan, to_dev(np.stack([x[0], 0 * x[0]])[None])).cpu().numpy()).max()
     assert np.abs(f).max() <= 1e-12 * scale
     rot = (1e-2 * np.stack([-x[1], x[0]]))[None]
-    fr = plan.apply(to_dev(rot)).cpu().numpy()
+    fr = gpu_apply(plan, to_dev(rot)).cpu().numpy()
     assert np.abs(fr).max() <= 1e-12 * scale
 
 
@@ -139,7 +139,7 @@ def test_apply_at_benchmark_sizes(name):
     log("apply at %s" % name)
     plan = gpu_plan(w)
     u = np.random.default_rng(1).standard_normal((1, 2, w.N))
-    f = plan.apply(to_dev(u)).cpu().numpy()
+    f = gpu_apply(plan, to_dev(u)).cpu().numpy()
     ref = _oracle_apply(w, u)
     err = rel_err(f, ref)
     log("  %s rel err %.3e" % (name, err))
@@ -152,7 +152,7 @@ def test_apply_cube128_sampled_rows():
     w = W.cube128(batch=16)
     log("apply cube128 B=16")
     plan = gpu_plan(w)
-    f = plan.apply(to_dev(w.b)).cpu().numpy()
+    f = gpu_apply(plan, to_dev(w.b)).cpu().numpy()
     p = oracle_problem(w)
     rs = np.random.default_rng(3)
     for c in (0, 7, 15):
@@ -164,3 +164,47 @@ def test_apply_cube128_sampled_rows():
         err = rel_err(got, ref)
         log("  case %d sampled rel err %.3e" % (c, err))
         assert err <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("spw,spwi,lpw", [(1, 1, 1), (2, 1, 1), (1, 2, 2), (4, 2, 2), (3, 3, 3), (2, 4, 1)])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_wave_owned_signals_match_oracle(monkeypatch, prec, spw, spwi, lpw, dim):
+    """The wave-owned decomposition (several signals per wavefront, used for large
+    batches) forced on small ragged grids, both precisions, composite radices; the
+    forward and inverse x passes take their slots-per-wave independently."""
+    import torch
+    monkeypatch.setenv("MSB_TEAM", "wave")
+    monkeypatch.setenv("MSB_SLOTS_PER_WAVE", str(spw))
+    monkeypatch.setenv("MSB_SLOTS_PER_WAVE_INV", str(spwi))
+    monkeypatch.setenv("MSB_LINES_PER_WAVE", str(lpw))
+    if dim == 2:
+        w = W.small(2, (37, 30), 3, seed=61, fixed="left", crack=True, batch=2)
+    else:
+        w = W.small(3, (13, 11, 9), 2, seed=62, fixed="bottom", batch=2)
+    plan = gpu_plan(w)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u = w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64)
+    f = gpu_apply(plan, to_dev(w.b, dt)).double().cpu().numpy()
+    ref = _oracle_apply(w, u)
+    for c in range(2):
+        err = rel_err(f[c], ref[c])
+        log("wave %s spw=%d/%d lpw=%d %dD case %d rel err %.2e" % (prec, spw, spwi, lpw, dim, c, err))
+        assert err <= (FP64_TOL if prec == "fp64" else FP32_TOL)
+
+
+def test_apply_cube128_fp32_sampled_rows():
+    """FP32 product at the 128^3 x 16 size (wave-owned, several signals per wave)."""
+    import torch
+    w = W.cube128(batch=16)
+    plan = gpu_plan(w)
+    f = gpu_apply(plan, to_dev(w.b, torch.float32)).double().cpu().numpy()
+    p = oracle_problem(w)
+    rs = np.random.default_rng(4)
+    for c in (0, 9):
+        rows = np.sort(rs.choice(w.N, 2000, replace=False))
+        ref = O.force(p, w.b[c].astype(np.float32).astype(np.float64), rows=rows)
+        ref[w.fixed[:, rows]] = 0.0
+        err = rel_err(f[c][:, rows], ref)
+        log("cube128 fp32 case %d sampled rel err %.2e" % (c, err))
+        assert err <= FP32_TOL

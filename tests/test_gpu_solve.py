@@ -166,3 +166,22 @@ def test_maxit_reports_noconv():
     plan = gpu_plan(w)
     _, info = plan.solve(to_dev(w.b), precision="fp64", tol=1e-12, maxit=3, check=False)
     assert info[0].status == msb.MSB_ENOCONV and info[0].inner_iters == 3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
+def test_wave_owned_fused_cg_matches_cholesky(monkeypatch, prec):
+    """The fused CG prologue/epilogue under the wave-owned decomposition with several
+    slots per wave (the large-batch configuration), on a small cracked plate."""
+    monkeypatch.setenv("MSB_TEAM", "wave")
+    monkeypatch.setenv("MSB_SLOTS_PER_WAVE", "4")
+    monkeypatch.setenv("MSB_SLOTS_PER_WAVE_INV", "2")
+    monkeypatch.setenv("MSB_LINES_PER_WAVE", "2")
+    w = W.small(2, (31, 27), 3, seed=71, fixed="left", crack=True, batch=2)
+    plan = gpu_plan(w)
+    u, info = plan.solve(to_dev(w.b), precision=prec, tol=1e-13)
+    uu = u.cpu().numpy()
+    for c in range(2):
+        err = rel_err(uu[c], _dense(w, c))
+        log("wave-owned %s case %d: %d inner it, residual %.2e, rel err %.3e" % (prec, c, info[c].inner_iters,
+            info[c].rel_residual, err))
+        assert info[c].status == 0 and err <= 1e-10
