@@ -209,6 +209,69 @@ msb_status msb_profile_apply(msb_plan plan, msb_precision prec, const void *u, v
  * nodes N per case. */
 msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds);
 
+/*
+ * Launch configuration of the product's kernels, one per arithmetic precision
+ * (MSB_FP64 or MSB_FP32; the refined solve uses both).  It changes how the
+ * work is cut into workgroups and which Stockham radices are used, never the
+ * result beyond rounding order.  A plan starts with a size-based default.
+ *
+ *   x passes (forward and inverse transforms along x, with the prologue and
+ *   the D^e / D^f / epilogue work):
+ *     rows_per_wg   grid rows per workgroup, 1..16
+ *     team_x        0: the whole workgroup works on each Stockham stage
+ *                   (workgroup barriers); 1: every wavefront owns its own
+ *                   signals (no workgroup barrier inside the transform)
+ *     slots_fwd     team_x = 1: complex signals (two real rows each) per
+ *     slots_inv     wavefront in the forward / inverse x pass, 1..8
+ *     threads_x     team_x = 0: threads per workgroup, multiple of 64, 64..1024
+ *   line passes (2D: the y column transform with the block spectral product;
+ *   3D: the y transforms and the z transform with the block product):
+ *     lines_per_wg  lines per workgroup, 1..16
+ *     team_line     as team_x
+ *     lines_per_wave  team_line = 1: lines per wavefront, 1..8
+ *     threads_line  team_line = 0: threads per workgroup, multiple of 64, 64..1024
+ *   max_radix       largest Stockham radix of the schedules: 8 (radices 2, 3,
+ *                   4, 5, 8) or 16 (adds 6, 9, 10, 12, 15, 16)
+ *
+ * msb_plan_set_config validates (LDS per workgroup <= 160 KiB, threads <=
+ * 1024) and returns MSB_EINVAL without changing the plan otherwise.
+ */
+typedef struct {
+    int rows_per_wg, team_x, slots_fwd, slots_inv, threads_x;
+    int lines_per_wg, team_line, lines_per_wave, threads_line;
+    int max_radix;
+} msb_launch_config;
+
+msb_status msb_plan_get_config(msb_plan plan, msb_precision prec, msb_launch_config *cfg);
+msb_status msb_plan_set_config(msb_plan plan, msb_precision prec, const msb_launch_config *cfg);
+
+/*
+ * Change the zero-padded transform lengths.  The generating array G of Sec. 3.3
+ * (Alg. 3) and Sec. 4 (Alg. 4) is nonzero only for offsets |o_a| <= M, so any
+ * L_a >= N_a + M, not only the paper's 2 N_a, gives the exact product.  L: host [3]; L[a]
+ * for a >= dim is ignored; each must be >= N_a + M, <= 65535 and have no prime
+ * factor other than 2, 3, 5.  Rebuilds the spectra and the transform
+ * workspace; the launch configurations return to their defaults.  Synchronises
+ * the device.
+ */
+msb_status msb_plan_set_lengths(msb_plan plan, const int64_t *L);
+
+/*
+ * Autotuner: times candidate launch configurations of the product f = A u for
+ * `prec` (MSB_FP32_REFINED tunes both precisions) on `stream`, with every
+ * kernel of the chain timed by HIP events, and keeps the fastest in the plan.
+ * The search is coordinate-wise: x-pass settings (per kernel where the two x
+ * kernels can differ), then line-pass settings, then max_radix.  With
+ * lengths != 0 it also tries padded lengths up to 12.5% longer than the
+ * default, keeping the fastest (msb_plan_set_lengths).  effort: 0 = a small
+ * candidate set, 1 = full.  best: host, receives the chosen configuration of
+ * `prec` (of MSB_FP32 for the refined case) or may be null; best_ms: its
+ * product time in ms, or null.  Allocates two temporary product buffers on the
+ * device; synchronises the stream.
+ */
+msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int lengths,
+                             msb_launch_config *best, double *best_ms, void *stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *msb_last_error(void);
 

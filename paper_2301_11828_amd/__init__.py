@@ -28,7 +28,8 @@ _STATUS = {0: "MSB_OK", -1: "MSB_EINVAL", -2: "MSB_ENOMEM", -3: "MSB_EDEVICE", -
 EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "msb_plan_set_bonds",
            "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl",
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
-           "msb_profile_apply", "msb_last_error")
+           "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
+           "msb_plan_autotune", "msb_last_error")
 
 
 class MsbError(RuntimeError):
@@ -53,6 +54,14 @@ class _Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
+
+class _LaunchConfig(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int) for k in ("rows_per_wg", "team_x", "slots_fwd", "slots_inv", "threads_x",
+                                            "lines_per_wg", "team_line", "lines_per_wave", "threads_line",
+                                            "max_radix")]
+
+
+CONFIG_KEYS = tuple(k for k, _ in _LaunchConfig._fields_)
 
 _lib = None
 
@@ -90,6 +99,10 @@ def load_library(path: str = LIB_PATH):
         "msb_grad_infl": ([P, P, P, P, P], I),
         "msb_plan_info": ([P, P, P, P], I),
         "msb_profile_apply": ([P, I, P, P, I, P, P, P], I),
+        "msb_plan_get_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
+        "msb_plan_set_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
+        "msb_plan_set_lengths": ([P, P], I),
+        "msb_plan_autotune": ([P, I, I, I, ctypes.POINTER(_LaunchConfig), ctypes.POINTER(D), P], I),
         "msb_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -214,6 +227,37 @@ class Plan:
         nb = ctypes.c_int64()
         _check(_lib.msb_plan_info(self._ptr, None, None, ctypes.byref(nb)))
         return nb.value
+
+    def get_config(self, precision: str = "fp64") -> dict:
+        """Launch configuration of the product kernels for "fp64" or "fp32" (a dict
+        with the fields of msb_launch_config)."""
+        c = _LaunchConfig()
+        _check(_lib.msb_plan_get_config(self._ptr, _PREC[precision], ctypes.byref(c)))
+        return {k: getattr(c, k) for k in CONFIG_KEYS}
+
+    def set_config(self, precision: str = "fp64", **fields):
+        """Change some fields of the launch configuration (validated by the library)."""
+        c = _LaunchConfig()
+        _check(_lib.msb_plan_get_config(self._ptr, _PREC[precision], ctypes.byref(c)))
+        for k, v in fields.items():
+            if k not in CONFIG_KEYS:
+                raise KeyError("unknown launch configuration field %r" % k)
+            setattr(c, k, int(v))
+        _check(_lib.msb_plan_set_config(self._ptr, _PREC[precision], ctypes.byref(c)))
+
+    def set_lengths(self, L: Sequence[int]):
+        """New zero-padded transform lengths (each >= N + M, factors 2, 3, 5 only)."""
+        arr = (ctypes.c_int64 * 3)(*([int(x) for x in L] + [1] * (3 - len(L))))
+        _check(_lib.msb_plan_set_lengths(self._ptr, arr))
+
+    def autotune(self, precision: str = "fp64", effort: int = 1, lengths: bool = False):
+        """Time candidate launch configurations (and, with lengths=True, padded
+        lengths) and keep the fastest.  Returns (configuration dict, product ms)."""
+        c = _LaunchConfig()
+        ms = ctypes.c_double(0.0)
+        _check(_lib.msb_plan_autotune(self._ptr, _PREC[precision], int(effort), int(bool(lengths)),
+                                      ctypes.byref(c), ctypes.byref(ms), _stream()))
+        return {k: getattr(c, k) for k in CONFIG_KEYS}, ms.value
 
     def set_constraints(self, fixed: Optional[np.ndarray]):
         if fixed is None:

@@ -47,7 +47,8 @@ template <typename T> using cplx_t = typename cplx_of<T>::type;
 // ------------------------------------------------------------------ FFT schedule
 constexpr int kMaxPasses = 12;
 
-// One transform axis: length L = product of radix[0..np), each radix in {2,3,4,5,8}.
+// One transform axis: length L = product of radix[0..np); the radices are among
+// {2,3,4,5,8} and, with a radix cap of 16, {6,9,10,12,15,16}.
 // Twiddle table tw[t] = exp(-2 pi i t / L), t < L (device, both precisions).
 struct FftAxis {
     int L = 0;
@@ -149,8 +150,7 @@ struct msb_plan_s {
     int64_t L[3] = {1, 1, 1};
     int64_t H = 1;              // L[0]/2 + 1 (half spectrum along x)
     msb::FftAxis ax[3];
-    int rows_per_wg = 4;        // F: grid rows per workgroup in the x passes
-    int zlines_per_wg = 4;      // 3D: lines per workgroup in the y passes
+    msb_launch_config cfg[2];   // launch configuration of the product: [0] FP64, [1] FP32
 
     // stencil (host)
     int n_off = 0;
@@ -179,16 +179,8 @@ struct msb_plan_s {
     void *T1 = nullptr;         // complex [B][d][Nz][H][Ny] (largest precision)
     void *T2 = nullptr;         // 3D only: complex [B][d][H][Ly][Nz]
     size_t T1_bytes = 0, T2_bytes = 0;
-    double *partials = nullptr; // reduction scratch
-    size_t n_partials = 0;
-    int *state = nullptr;       // small int state (per-case flags/counters)
-    double *dstate = nullptr;   // small double state
-    double *vec64 = nullptr;    // solver vectors FP64 [k][B*d*N]
-    float *vec32 = nullptr;     // solver vectors FP32
-    int n_vec64 = 0, n_vec32 = 0;
-    double *host_partials = nullptr;  // pinned host mirror for reductions
 
-    // cached graphs etc. live in the solver translation unit
+    // solver vectors, partial sums and pinned mirrors (solver translation unit)
     void *solver_cache = nullptr;
 };
 
@@ -198,6 +190,15 @@ int64_t rows_total(const msb_plan_s *p);   // Ny * Nz grid rows per case
 size_t spectrum_len(const msb_plan_s *p);  // H * Ly * Lz reals per component
 size_t de_len(const msb_plan_s *p);        // ncomp * (M+1)^(2d) per slot
 size_t w_len(const msb_plan_s *p);         // ncomp * n_off per slot
+
+// Launch configurations (passes.hip): the size-based default, and the check that
+// a configuration fits the hardware limits and the schedules' index arithmetic.
+msb_launch_config default_config(const msb_plan_s *p, bool fp32);
+msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config &c);
+// Stockham schedules of every axis for one precision with radices <= max_radix (plan.cpp).
+msb_status set_schedules(msb_plan_s *p, bool fp32, int max_radix);
+// New padded lengths: rebuild twiddles, spectra and transform workspace (plan.cpp).
+msb_status relayout(msb_plan_s *p, const int64_t *L);
 
 msb_status alloc_operator(msb_plan_s *p, DeviceOp &op, int count);
 msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot);

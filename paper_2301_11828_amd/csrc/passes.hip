@@ -597,20 +597,6 @@ __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
 // ---------------------------------------------------------------------------- host side
 int x_tiles_per_case(const msb_plan_s *p, int F) { return (int)((rows_total(p) + F - 1) / F); }
 
-static int env_or(const char *name, int dflt) {
-    const char *e = getenv(name);
-    return e ? atoi(e) : dflt;
-}
-
-static size_t lds_budget() {
-    static size_t b = 0;
-    if (!b) {
-        const char *e = getenv("MSB_LDS_BUDGET");
-        b = e ? (size_t)atol(e) : (size_t)80 * 1024;
-    }
-    return b;
-}
-
 // LDS bytes: the shared twiddle table plus two buffers (ping-pong) of slots.
 static size_t lds_x_bytes(int d, int F, int64_t Lx, size_t cbytes) {
     return ((size_t)2 * ((d * F + 1) / 2) + 1) * Lx * cbytes;
@@ -620,42 +606,87 @@ static size_t lds_line_bytes(int d, int Fl, int64_t L, size_t cbytes) {
 }
 static int waves_x(int d, int F) { return (d * F + 1) / 2; }
 
-// Team choice: wave-owned signals once there are enough independent signals to give
-// every SIMD of the chip (256 CUs x 4) several of them; whole-block teams otherwise.
-static bool wave_mode(int64_t units) {
-    const char *env = getenv("MSB_TEAM");
-    if (env) return env[0] == 'w';
-    return units >= 4096;
-}
+// Dynamic LDS a workgroup may use (gfx950: 160 KiB per workgroup, less the
+// kernels' static reduction scratch), and the budget the default configuration
+// keeps to so that two workgroups fit on a CU.
+constexpr size_t kLdsMax = 160 * 1024 - 1024;
+constexpr size_t kLdsDefault = 80 * 1024;
 
-// Grid rows per block of the x passes.  Block teams: the largest power of two <= 8
-// that fits the LDS budget and leaves >= 1024 blocks (latency-bound small grids run
-// fastest with one row pair per block).  Wave teams: up to 16 waves
-// (slots) per block within the LDS budget.
-int rows_per_wg_for(const msb_plan_s *p, size_t cbytes) {
-    const char *env = getenv("MSB_ROWS_PER_WG");
-    if (env) return std::max(1, atoi(env));
+static int64_t x_units(const msb_plan_s *p) { return (int64_t)p->B * ((rows_total(p) * p->dim + 1) / 2); }
+static int64_t line_count(const msb_plan_s *p) { return p->dim == 2 ? p->H : p->H * p->n[2]; }
+static int64_t line_len(const msb_plan_s *p) { return p->dim == 2 ? p->L[1] : std::max(p->L[1], p->L[2]); }
+
+// Default configuration.  Team choice: wave-owned signals once there are enough
+// independent signals to give every SIMD of the chip (256 CUs x 4) several of them,
+// whole-workgroup teams otherwise.  x passes: the largest power of two <= 8 rows
+// per workgroup within the LDS budget (4 for FP32 wave teams, which own several
+// slots per wave), and >= 1024 workgroups for block teams (latency-bound small
+// grids run fastest with few rows per workgroup).  Line passes: up to 8 lines per
+// workgroup, >= 256 workgroups for block teams.
+msb_launch_config default_config(const msb_plan_s *p, bool fp32) {
+    msb_launch_config c;
+    const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
+    const int d = p->dim;
     const int64_t rows = rows_total(p);
-    const bool wm = wave_mode((int64_t)p->B * ((rows * p->dim + 1) / 2));
-    int F = 8;
-    while (F > 1 && (lds_x_bytes(p->dim, F, p->L[0], cbytes) > lds_budget() ||
-                     waves_x(p->dim, F) > 16 ||
-                     (!wm && (int64_t)p->B * ((rows + F - 1) / F) < 1024)))
+    c.team_x = x_units(p) >= 4096 ? 1 : 0;
+    int F = c.team_x && fp32 ? 4 : 8;
+    while (F > 1 && (lds_x_bytes(d, F, p->L[0], cb) > kLdsDefault || waves_x(d, F) > 16 ||
+                     (!c.team_x && (int64_t)p->B * ((rows + F - 1) / F) < 1024)))
         F /= 2;
-    return F;
+    c.rows_per_wg = F;
+    c.slots_fwd = c.team_x && fp32 ? 4 : 1;
+    c.slots_inv = c.team_x && fp32 ? 2 : 1;
+    c.threads_x = 256;
+    const int64_t nl = line_count(p), Ll = line_len(p);
+    c.team_line = (int64_t)p->B * nl >= 4096 ? 1 : 0;
+    int Fl = 8;
+    while (Fl > 1 && (lds_line_bytes(d, Fl, Ll, cb) > kLdsDefault ||
+                      (!c.team_line && (int64_t)p->B * ((nl + Fl - 1) / Fl) < 256)))
+        Fl /= 2;
+    c.lines_per_wg = Fl;
+    c.lines_per_wave = 1;
+    // 2D block teams: about one thread per 4 points of the workgroup's signals
+    c.threads_line = (d == 2 && (int64_t)Fl * d * Ll >= 2048) ? 512 : 256;
+    c.max_radix = fp32 ? 16 : 8;
+    return c;
 }
 
-// Lines per block of the line passes (block teams: >= 256 blocks; wave teams: one
-// line per wave, up to 8 per block).
-static int lines_per_wg_for(const msb_plan_s *p, size_t cbytes, int L, int64_t nlines) {
-    const char *env = getenv("MSB_LINES_PER_WG");
-    if (env) return std::max(1, atoi(env));
-    const bool wm = wave_mode((int64_t)p->B * nlines);
-    int F = 8;
-    while (F > 1 && (lds_line_bytes(p->dim, F, L, cbytes) > lds_budget() ||
-                     (!wm && (int64_t)p->B * ((nlines + F - 1) / F) < 256)))
-        F /= 2;
-    return F;
+// Exactness of the Stockham index split: fdiv(t, nb) with t < S * nb is exact while
+// S * nb^2 < 2^32 (S = signals a team transforms together).
+static bool split_exact(int64_t S, int64_t L) {
+    const int64_t nb = L / 2;   // largest butterfly count of any stage (radix >= 2)
+    return S * nb * nb < (int64_t(1) << 32);
+}
+
+msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config &c) {
+    const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
+    const int d = p->dim;
+    MSB_CHECK(c.rows_per_wg >= 1 && c.rows_per_wg <= 16, MSB_EINVAL, "rows_per_wg %d not in [1, 16]", c.rows_per_wg);
+    MSB_CHECK(c.lines_per_wg >= 1 && c.lines_per_wg <= 16, MSB_EINVAL, "lines_per_wg %d not in [1, 16]", c.lines_per_wg);
+    MSB_CHECK((c.team_x == 0 || c.team_x == 1) && (c.team_line == 0 || c.team_line == 1), MSB_EINVAL,
+              "team_x / team_line must be 0 or 1");
+    MSB_CHECK(c.slots_fwd >= 1 && c.slots_fwd <= 8 && c.slots_inv >= 1 && c.slots_inv <= 8, MSB_EINVAL,
+              "slots_fwd / slots_inv not in [1, 8]");
+    MSB_CHECK(c.lines_per_wave >= 1 && c.lines_per_wave <= 8, MSB_EINVAL, "lines_per_wave not in [1, 8]");
+    for (int t : {c.threads_x, c.threads_line})
+        MSB_CHECK(t >= 64 && t <= 1024 && t % 64 == 0, MSB_EINVAL, "thread count %d: need a multiple of 64 in [64, 1024]", t);
+    MSB_CHECK(c.max_radix == 8 || c.max_radix == 16, MSB_EINVAL, "max_radix must be 8 or 16");
+    const size_t lx = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb);
+    MSB_CHECK(lx <= kLdsMax, MSB_EINVAL, "x passes need %zu bytes of LDS per workgroup (max %zu)", lx, kLdsMax);
+    const size_t ll = lds_line_bytes(d, c.lines_per_wg, line_len(p), cb);
+    MSB_CHECK(ll <= kLdsMax, MSB_EINVAL, "line passes need %zu bytes of LDS per workgroup (max %zu)", ll, kLdsMax);
+    if (c.team_x) {
+        const int w = waves_x(d, c.rows_per_wg);
+        MSB_CHECK(64 * ((w + c.slots_fwd - 1) / c.slots_fwd) <= 1024 && 64 * ((w + c.slots_inv - 1) / c.slots_inv) <= 1024,
+                  MSB_EINVAL, "x passes: %d slots need more than 16 waves per workgroup", w);
+    }
+    MSB_CHECK(64 * ((c.lines_per_wg + c.lines_per_wave - 1) / c.lines_per_wave) <= 1024, MSB_EINVAL,
+              "line passes: too many waves per workgroup");
+    const int64_t sx = c.team_x ? std::max(c.slots_fwd, c.slots_inv) : waves_x(d, c.rows_per_wg);
+    const int64_t sl = c.team_line ? (int64_t)d * c.lines_per_wave : (int64_t)d * c.lines_per_wg;
+    MSB_CHECK(split_exact(sx, p->L[0]) && split_exact(sl, line_len(p)), MSB_EINVAL,
+              "too many signals per team for the transform length");
+    return MSB_OK;
 }
 
 template <typename T> static const T *sel(const double *a, const float *b);
@@ -676,23 +707,16 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.Ly = (int)p->L[1];
     a.Lz = (int)p->L[2];
     a.N = (int)p->N;
-    a.F = rows_per_wg_for(p, sizeof(cplx_t<T>));
-    const int64_t nl = p->dim == 2 ? p->H : p->H * p->n[2];
-    a.Fl = p->dim == 2 ? lines_per_wg_for(p, sizeof(cplx_t<T>), (int)p->L[1], nl)
-                       : lines_per_wg_for(p, sizeof(cplx_t<T>), (int)std::max(p->L[1], p->L[2]), nl);
-    a.wave_x = wave_mode((int64_t)p->B * ((rows_total(p) * p->dim + 1) / 2)) ? 1 : 0;
-    a.wave_l = wave_mode((int64_t)p->B * nl) ? 1 : 0;
-    // wave mode: FP32 signals are cheap in registers, so a wave takes several (better
-    // lane use per Stockham stage); FP64 keeps one slot / one line per wave
-    a.spw = std::max(1, env_or("MSB_SLOTS_PER_WAVE", f32 ? 4 : 1));
-    a.spw_i = std::max(1, env_or("MSB_SLOTS_PER_WAVE_INV", a.spw));
-    a.lpw = std::max(1, env_or("MSB_LINES_PER_WAVE", f32 ? 2 : 1));
-    a.bthreads = std::max(64, std::min(1024, env_or("MSB_BLOCK_THREADS", 256)));
-    // block mode line pass: one thread per ~4 points of the block's signals, 256..512
-    {
-        const int64_t pts = (int64_t)a.Fl * p->dim * (p->dim == 2 ? p->L[1] : p->L[2]);
-        a.bthreads_line = std::max(64, std::min(1024, env_or("MSB_BLOCK_THREADS_LINE", pts >= 2048 ? 512 : 256)));
-    }
+    const msb_launch_config &c = p->cfg[f32 ? 1 : 0];
+    a.F = c.rows_per_wg;
+    a.Fl = c.lines_per_wg;
+    a.wave_x = c.team_x;
+    a.wave_l = c.team_line;
+    a.spw = c.slots_fwd;
+    a.spw_i = c.slots_inv;
+    a.lpw = c.lines_per_wave;
+    a.bthreads = c.threads_x;
+    a.bthreads_line = c.threads_line;
     a.sx = sched_of(p->ax[0], f32);
     a.sy = sched_of(p->ax[1], f32);
     a.sz = sched_of(p->ax[2], f32);
@@ -758,7 +782,7 @@ static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, hipStr
         const int nlines = a.H * a.Ly;
         const int lpc = (nlines + a.Fl - 1) / a.Fl;
         const size_t lds_z = lds_line_bytes(a.d, a.Fl, a.sz.L, sizeof(T2));
-        const int by = wl ? 64 * ((a.Fl + a.lpw - 1) / a.lpw) : a.bthreads;
+        const int by = wl ? 64 * ((a.Fl + a.lpw - 1) / a.lpw) : a.bthreads_line;
         if (wl) {
             MSB_HIP(allow_lds(k_yfwd<T, false, RM>, lds_y));
             MSB_HIP(allow_lds(k_yinv<T, false, RM>, lds_y));

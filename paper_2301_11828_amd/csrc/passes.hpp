@@ -106,6 +106,5 @@ PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op);
 
 // tiles of the x passes per case (partial-sum slots per case)
 int x_tiles_per_case(const msb_plan_s *p, int F);
-int rows_per_wg_for(const msb_plan_s *p, size_t elem_bytes);
 
 }  // namespace msb

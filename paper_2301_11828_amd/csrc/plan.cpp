@@ -40,13 +40,9 @@ void set_error(const char *fmt, ...) {
 // radix <= 16 only instantiate these).
 static const int kRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
 
-// Largest radix of the FP64 / FP32 schedules (measured: FP64 kernels keep more
-// occupancy with the basic radices, FP32 gains from fewer LDS stages).
-static int max_radix(bool fp32) {
-    const char *e = getenv(fp32 ? "MSB_MAX_RADIX32" : "MSB_MAX_RADIX");
-    if (!e) e = getenv("MSB_MAX_RADIX");
-    return e ? atoi(e) : (fp32 ? 16 : 8);
-}
+// Default radix caps (measured: FP64 kernels keep more occupancy with the basic
+// radices, FP32 gains from fewer LDS stages); the launch configuration can change them.
+constexpr int kDefaultMaxRadix64 = 8, kDefaultMaxRadix32 = 16;
 
 // Factor L into the fewest Stockham stages with radix <= rmax; ties go to the
 // factorisation whose smallest radix is largest (balanced stages).
@@ -136,16 +132,26 @@ static void unit_circle(int L, std::vector<long double> &c, std::vector<long dou
     }
 }
 
+static msb_status axis_schedule(FftAxis &ax, bool fp32, int max_radix) {
+    std::vector<int> r;
+    MSB_CHECK(factor_length(ax.L, r, max_radix), MSB_EINVAL, "FFT length %d is not 5-smooth", ax.L);
+    MSB_CHECK((int)r.size() <= kMaxPasses, MSB_EINVAL, "FFT length %d needs too many stages", ax.L);
+    const int np = ax.L == 1 ? 0 : (int)r.size();
+    int *dst = fp32 ? ax.radix32 : ax.radix;
+    for (int i = 0; i < kMaxPasses; ++i) dst[i] = i < np ? r[i] : 0;
+    (fp32 ? ax.np32 : ax.np) = np;
+    return MSB_OK;
+}
+
+msb_status set_schedules(msb_plan_s *p, bool fp32, int max_radix) {
+    for (int a = 0; a < 3; ++a) MSB_TRY(axis_schedule(p->ax[a], fp32, max_radix));
+    return MSB_OK;
+}
+
 static msb_status make_axis(int L, FftAxis &ax) {
-    std::vector<int> r, r32;
-    MSB_CHECK(factor_length(L, r, max_radix(false)) && factor_length(L, r32, max_radix(true)), MSB_EINVAL,
-              "FFT length %d is not 5-smooth", L);
-    MSB_CHECK((int)r.size() <= kMaxPasses && (int)r32.size() <= kMaxPasses, MSB_EINVAL, "FFT length %d too long", L);
     ax.L = L;
-    ax.np = (L == 1) ? 0 : (int)r.size();
-    for (int i = 0; i < ax.np; ++i) ax.radix[i] = r[i];
-    ax.np32 = (L == 1) ? 0 : (int)r32.size();
-    for (int i = 0; i < ax.np32; ++i) ax.radix32[i] = r32[i];
+    MSB_TRY(axis_schedule(ax, false, kDefaultMaxRadix64));
+    MSB_TRY(axis_schedule(ax, true, kDefaultMaxRadix32));
     std::vector<long double> c, s;
     unit_circle(L, c, s);
     std::vector<double2> t64(L);
@@ -401,7 +407,9 @@ using namespace msb;
 
 extern "C" const char *msb_last_error(void) { return g_err.c_str(); }
 
-static msb_status plan_alloc_workspace(msb_plan_s *p) {
+// Transform workspace: T1 holds the x half spectra [B][d][Nz][H][Ny], T2 (3D) the
+// y spectra [B][d][H][Ly][Nz]; sized for complex FP64 and shared by FP32.
+static msb_status alloc_transform_ws(msb_plan_s *p) {
     const int d = p->dim;
     const size_t c16 = sizeof(double2);
     p->T1_bytes = (size_t)p->B * d * p->n[2] * p->H * p->n[1] * c16;
@@ -410,13 +418,69 @@ static msb_status plan_alloc_workspace(msb_plan_s *p) {
         p->T2_bytes = (size_t)p->B * d * p->H * p->L[1] * p->n[2] * c16;
         MSB_HIP(hipMalloc(&p->T2, p->T2_bytes));
     }
-    p->n_partials = (size_t)16 * 4096 + (size_t)p->B * 8192;
-    MSB_HIP(hipMalloc(&p->partials, sizeof(double) * p->n_partials));
-    MSB_HIP(hipMalloc(&p->state, sizeof(int) * (64 + 8 * (size_t)p->B)));
-    MSB_HIP(hipMalloc(&p->dstate, sizeof(double) * (64 + 16 * (size_t)p->B)));
-    MSB_HIP(hipMemset(p->state, 0, sizeof(int) * (64 + 8 * (size_t)p->B)));
-    MSB_HIP(hipHostMalloc(&p->host_partials, sizeof(double) * (64 + 16 * (size_t)p->B)));
     return MSB_OK;
+}
+
+static void free_axes(msb_plan_s *p) {
+    for (int a = 0; a < 3; ++a) {
+        if (p->ax[a].tw64) (void)hipFree(p->ax[a].tw64);
+        if (p->ax[a].tw32) (void)hipFree(p->ax[a].tw32);
+        p->ax[a] = FftAxis();
+    }
+}
+
+// Largest padded length per axis: the x pass stages up to three length-L signals
+// in LDS and the Stockham index split (fdiv) is exact while signals * (L/R)^2 < 2^32.
+constexpr int64_t kMaxLength = 16384;
+
+static msb_status check_lengths(const msb_plan_s *p, const int64_t *L) {
+    for (int a = 0; a < p->dim; ++a) {
+        MSB_CHECK(L[a] >= p->n[a] + p->M, MSB_EINVAL, "L[%d] = %lld < N + M = %lld", a, (long long)L[a],
+                  (long long)(p->n[a] + p->M));
+        MSB_CHECK(L[a] <= kMaxLength, MSB_EUNSUPPORTED, "L[%d] = %lld exceeds %lld", a, (long long)L[a],
+                  (long long)kMaxLength);
+        std::vector<int> r;
+        MSB_CHECK(factor_length((int)L[a], r, 16), MSB_EINVAL, "L[%d] = %lld has a prime factor above 5", a,
+                  (long long)L[a]);
+    }
+    return MSB_OK;
+}
+
+// Build the parts of the plan that depend on the padded lengths (p->L set).
+static msb_status build_layout(msb_plan_s *p) {
+    p->H = p->L[0] / 2 + 1;
+    for (int a = 0; a < 3; ++a) MSB_TRY(make_axis((int)p->L[a], p->ax[a]));
+    const int count = p->op.count > 0 ? p->op.count : 1;
+    MSB_TRY(alloc_operator(p, p->op, count));
+    for (int c = 0; c < count; ++c) {
+        std::vector<double> v = p->per_case ? std::vector<double>(p->infl_case.begin() + (size_t)c * p->n_infl,
+                                                                  p->infl_case.begin() + (size_t)(c + 1) * p->n_infl)
+                                            : p->infl;
+        MSB_TRY(fill_operator(p, v, p->op, c));
+    }
+    for (auto &o : p->dop) free_operator(o);
+    p->dop.clear();
+    MSB_TRY(alloc_transform_ws(p));
+    for (int f = 0; f < 2; ++f) {
+        p->cfg[f] = default_config(p, f == 1);
+        MSB_TRY(set_schedules(p, f == 1, p->cfg[f].max_radix));
+        MSB_CHECK(check_config(p, f == 1, p->cfg[f]) == MSB_OK, MSB_EUNSUPPORTED,
+                  "grid too large for the LDS-staged transforms (%s)", msb_last_error());
+    }
+    return MSB_OK;
+}
+
+msb_status msb::relayout(msb_plan_s *p, const int64_t *L) {
+    int64_t Ln[3] = {1, 1, 1};
+    for (int a = 0; a < p->dim; ++a) Ln[a] = L[a];
+    MSB_TRY(check_lengths(p, Ln));
+    MSB_HIP(hipDeviceSynchronize());
+    free_axes(p);
+    if (p->T1) (void)hipFree(p->T1);
+    if (p->T2) (void)hipFree(p->T2);
+    p->T1 = p->T2 = nullptr;
+    for (int a = 0; a < 3; ++a) p->L[a] = Ln[a];
+    return build_layout(p);
 }
 
 extern "C" msb_status msb_plan_create(const msb_problem_desc *desc, msb_plan *out) {
@@ -441,29 +505,12 @@ extern "C" msb_status msb_plan_create(const msb_problem_desc *desc, msb_plan *ou
     p->ncomp = desc->dim == 2 ? 3 : 6;
 
     // padded lengths: any L >= N + M gives the exact linear product (support +-M)
-    for (int a = 0; a < 3; ++a) {
-        if (a < p->dim) p->L[a] = next_smooth((int)(p->n[a] + p->M), false);
-        else p->L[a] = 1;
-    }
-    p->H = p->L[0] / 2 + 1;
+    for (int a = 0; a < 3; ++a) p->L[a] = a < p->dim ? next_smooth((int)(p->n[a] + p->M), false) : 1;
     p->de_stride = 1;
     for (int q = 0; q < 2 * p->dim; ++q) p->de_stride *= (p->M + 1);
-
-    msb_status st = MSB_OK;
-    for (int a = 0; a < 3 && st == MSB_OK; ++a) st = make_axis((int)p->L[a], p->ax[a]);
-    if (st == MSB_OK) {
-        build_offsets(p);
-        st = alloc_operator(p, p->op, 1);
-        if (st == MSB_OK) st = fill_operator(p, p->infl, p->op, 0);
-    }
-    if (st == MSB_OK) st = plan_alloc_workspace(p);
-    // rows per workgroup of the x passes: keep two LDS buffers within 64 KiB (FP64)
-    {
-        const int d = p->dim;
-        int F = 16;
-        while (F > 1 && (size_t)2 * ((d * F + 1) / 2) * p->L[0] * sizeof(double2) > 64 * 1024) F /= 2;
-        p->rows_per_wg = F;
-    }
+    build_offsets(p);
+    msb_status st = check_lengths(p, p->L);
+    if (st == MSB_OK) st = build_layout(p);
     if (st != MSB_OK) {
         msb_plan_destroy(p);
         return st;
@@ -475,17 +522,12 @@ extern "C" msb_status msb_plan_create(const msb_problem_desc *desc, msb_plan *ou
 extern "C" void msb_plan_destroy(msb_plan p) {
     if (!p) return;
     hipDeviceSynchronize();
-    for (int a = 0; a < 3; ++a) {
-        if (p->ax[a].tw64) hipFree(p->ax[a].tw64);
-        if (p->ax[a].tw32) hipFree(p->ax[a].tw32);
-    }
+    free_axes(p);
     free_operator(p->op);
     for (auto &o : p->dop) free_operator(o);
-    void *bufs[] = {p->fixed, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off,
-                    p->T1, p->T2, p->partials, p->state, p->dstate, p->vec64, p->vec32};
+    void *bufs[] = {p->fixed, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off, p->T1, p->T2};
     for (void *b : bufs)
         if (b) hipFree(b);
-    if (p->host_partials) hipHostFree(p->host_partials);
     solver_cache_free(p);
     delete p;
 }

@@ -266,10 +266,8 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
     return launch_product<T>(c.pa, e, c.st);
 }
 
-static int env_int(const char *name, int dflt) {
-    const char *e = getenv(name);
-    return e ? atoi(e) : dflt;
-}
+// Iterations between host checks of the per-case done flags when no graph is used.
+constexpr int kPollIterations = 32;
 
 // Run CG from the prepared state (x, r, p = 0, r.r partials in part_rr[0], thresholds
 // and flags set).  Stops when every case has a flag or after maxit iterations.
@@ -279,7 +277,7 @@ template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_bl
     int it = 0;
     MSB_TRY(cg_iteration(c, 0));
     it = 1;
-    const int poll = graph_block > 0 ? graph_block : std::max(2, env_int("MSB_CG_POLL", 32));
+    const int poll = graph_block > 0 ? graph_block : kPollIterations;
     const int block = poll + (poll & 1);   // even: keeps the partial-sum parity of replays fixed
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;

@@ -169,20 +169,18 @@ def test_apply_cube128_sampled_rows():
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("spw,spwi,lpw", [(1, 1, 1), (2, 1, 1), (1, 2, 2), (4, 2, 2), (3, 3, 3), (2, 4, 1)])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_wave_owned_signals_match_oracle(monkeypatch, prec, spw, spwi, lpw, dim):
+def test_wave_owned_signals_match_oracle(prec, spw, spwi, lpw, dim):
     """The wave-owned decomposition (several signals per wavefront, used for large
-    batches) forced on small ragged grids, both precisions, composite radices; the
-    forward and inverse x passes take their slots-per-wave independently."""
+    batches) on small ragged grids, both precisions, composite radices; the forward
+    and inverse x passes take their slots-per-wave independently."""
     import torch
-    monkeypatch.setenv("MSB_TEAM", "wave")
-    monkeypatch.setenv("MSB_SLOTS_PER_WAVE", str(spw))
-    monkeypatch.setenv("MSB_SLOTS_PER_WAVE_INV", str(spwi))
-    monkeypatch.setenv("MSB_LINES_PER_WAVE", str(lpw))
     if dim == 2:
         w = W.small(2, (37, 30), 3, seed=61, fixed="left", crack=True, batch=2)
     else:
         w = W.small(3, (13, 11, 9), 2, seed=62, fixed="bottom", batch=2)
     plan = gpu_plan(w)
+    plan.set_config(prec, rows_per_wg=8, team_x=1, slots_fwd=spw, slots_inv=spwi, team_line=1, lines_per_wg=4,
+                    lines_per_wave=lpw, max_radix=16)
     dt = torch.float64 if prec == "fp64" else torch.float32
     u = w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64)
     f = gpu_apply(plan, to_dev(w.b, dt)).double().cpu().numpy()

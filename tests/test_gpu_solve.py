@@ -169,15 +169,14 @@ def test_maxit_reports_noconv():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
-def test_wave_owned_fused_cg_matches_cholesky(monkeypatch, prec):
+def test_wave_owned_fused_cg_matches_cholesky(prec):
     """The fused CG prologue/epilogue under the wave-owned decomposition with several
     slots per wave (the large-batch configuration), on a small cracked plate."""
-    monkeypatch.setenv("MSB_TEAM", "wave")
-    monkeypatch.setenv("MSB_SLOTS_PER_WAVE", "4")
-    monkeypatch.setenv("MSB_SLOTS_PER_WAVE_INV", "2")
-    monkeypatch.setenv("MSB_LINES_PER_WAVE", "2")
     w = W.small(2, (31, 27), 3, seed=71, fixed="left", crack=True, batch=2)
     plan = gpu_plan(w)
+    for pr in ("fp64", "fp32"):
+        plan.set_config(pr, rows_per_wg=8, team_x=1, slots_fwd=4, slots_inv=2, team_line=1, lines_per_wg=4,
+                        lines_per_wave=2)
     u, info = plan.solve(to_dev(w.b), precision=prec, tol=1e-13)
     uu = u.cpu().numpy()
     for c in range(2):

@@ -1,0 +1,136 @@
+"""Launch configurations, padded lengths and the autotuner: none of them may change
+the product beyond rounding order, so every configuration the library accepts is
+checked against the oracle's bond-by-bond sum, eq. (mat:f1)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2301_11828_amd import workloads as W
+from helpers import gpu_apply, gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-6
+
+
+def _oracle_apply(w, u):
+    p = oracle_problem(w)
+    br = oracle_bonds(w)
+    return np.stack([O.apply(p, u[c], w.fixed, br) for c in range(u.shape[0])])
+
+
+def _check_apply(plan, w, prec, label):
+    import torch
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u = w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64)
+    f = gpu_apply(plan, to_dev(w.b, dt)).double().cpu().numpy()
+    ref = _oracle_apply(w, u)
+    err = max(rel_err(f[c], ref[c]) for c in range(w.batch))
+    log("%s %s rel err %.2e" % (label, prec, err))
+    assert err <= (FP64_TOL if prec == "fp64" else FP32_TOL)
+
+
+def _random_configs(rng, count):
+    out = []
+    for _ in range(count):
+        out.append(dict(rows_per_wg=int(rng.choice([1, 2, 3, 4, 5, 8, 16])), team_x=int(rng.integers(2)),
+                        slots_fwd=int(rng.integers(1, 9)), slots_inv=int(rng.integers(1, 9)),
+                        threads_x=64 * int(rng.integers(1, 17)), lines_per_wg=int(rng.choice([1, 2, 3, 5, 8, 16])),
+                        team_line=int(rng.integers(2)), lines_per_wave=int(rng.integers(1, 9)),
+                        threads_line=64 * int(rng.integers(1, 17)), max_radix=int(rng.choice([8, 16]))))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_random_launch_configs_match_oracle(prec, dim):
+    """Seeded random configurations (odd row/line counts, thread counts, slot counts,
+    radix caps); the ones the library accepts must all give the oracle's product."""
+    import paper_2301_11828_amd as msb
+    if dim == 2:
+        w = W.small(2, (45, 38), 3, seed=81, fixed="mixed", crack=True, batch=2)
+    else:
+        w = W.small(3, (14, 9, 11), 2, seed=82, fixed="bottom", batch=2)
+    plan = gpu_plan(w)
+    rng = np.random.default_rng(83 + dim)
+    accepted = 0
+    for cfg in _random_configs(rng, 24):
+        try:
+            plan.set_config(prec, **cfg)
+        except msb.MsbError as e:
+            assert e.status == msb.MSB_EINVAL
+            continue
+        assert plan.get_config(prec) == cfg
+        accepted += 1
+        _check_apply(plan, w, prec, "config %s" % cfg)
+    log("%d of 24 random configurations accepted" % accepted)
+    assert accepted >= 8
+
+
+def test_invalid_configs_rejected_and_plan_unchanged():
+    import paper_2301_11828_amd as msb
+    w = W.small(2, (30, 20), 3, seed=84, fixed="left")
+    plan = gpu_plan(w)
+    before = plan.get_config("fp64")
+    for bad in (dict(threads_x=100), dict(threads_line=2048), dict(max_radix=7), dict(rows_per_wg=0),
+                dict(rows_per_wg=17), dict(team_x=2), dict(slots_fwd=9), dict(lines_per_wave=0)):
+        with pytest.raises(msb.MsbError) as e:
+            plan.set_config("fp64", **bad)
+        assert e.value.status == msb.MSB_EINVAL
+        assert plan.get_config("fp64") == before
+    # too much LDS: 16 rows x 2 components of a long x axis in FP64
+    wl = W.small(2, (2000, 4), 3, seed=85)
+    pl = gpu_plan(wl)
+    with pytest.raises(msb.MsbError):
+        pl.set_config("fp64", rows_per_wg=16)
+    with pytest.raises(msb.MsbError):
+        plan.set_config("fp32_refined", rows_per_wg=2)
+    _check_apply(plan, w, "fp64", "after rejected configurations")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_set_lengths_matches_oracle(dim):
+    """Any padded length >= N + M gives the exact product, including the paper's 2N."""
+    import paper_2301_11828_amd as msb
+    if dim == 2:
+        w = W.small(2, (40, 27), 3, seed=86, fixed="left", crack=True)
+        Ls = [(80, 54), (45, 32), (48, 30)]
+    else:
+        w = W.small(3, (12, 10, 9), 2, seed=87, fixed="bottom")
+        Ls = [(24, 20, 18), (15, 12, 12), (16, 15, 20)]
+    plan = gpu_plan(w)
+    for L in Ls:
+        plan.set_lengths(L)
+        assert plan.padded_lengths == L
+        for prec in ("fp64", "fp32"):
+            _check_apply(plan, w, prec, "L=%s" % (L,))
+    for bad in ([w.n[0] + w.M - 1] + list(Ls[0][1:]), [7 * 11] + list(Ls[0][1:])):
+        with pytest.raises(msb.MsbError):
+            plan.set_lengths(bad)
+        assert plan.padded_lengths == Ls[-1]
+    u, info = plan.solve(to_dev(w.b), precision="fp64", tol=1e-13)
+    ref = O.solve_dense(oracle_problem(w), w.b[0], w.fixed, None, oracle_bonds(w))
+    err = rel_err(u.cpu().numpy()[0], ref)
+    log("solve after set_lengths rel err %.2e" % err)
+    assert err <= 1e-11
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_autotune_keeps_parity(dim):
+    if dim == 2:
+        w = W.small(2, (70, 52), 3, seed=88, fixed="left", crack=True, batch=2)
+    else:
+        w = W.small(3, (17, 13, 11), 3, seed=89, fixed="bottom", batch=2)
+    plan = gpu_plan(w)
+    cfg, ms = plan.autotune("fp32_refined", effort=0, lengths=True)
+    log("autotuned %dD: L=%s fp32 %s (%.4f ms), fp64 %s" % (dim, plan.padded_lengths, cfg, ms, plan.get_config("fp64")))
+    assert ms > 0 and cfg == plan.get_config("fp32")
+    for prec in ("fp64", "fp32"):
+        _check_apply(plan, w, prec, "autotuned")
+    u, info = plan.solve(to_dev(w.b), precision="fp32_refined", tol=1e-12)
+    for c in range(w.batch):
+        ref = O.solve_dense(oracle_problem(w), w.b[c], w.fixed, None, oracle_bonds(w))
+        err = rel_err(u.cpu().numpy()[c], ref)
+        log("refined solve after autotune case %d rel err %.2e" % (c, err))
+        assert info[c].status == 0 and err <= 1e-10
