@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-tolerance runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "0")))
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the plans' default launch configurations (skip the autotuner)")
     ap.add_argument("--workload", default="plate512",
                     choices=["plate512", "crack1024", "cube128", "plates64"],
                     help="plate512 is the headline line; the others measure the remaining workloads")
@@ -89,6 +91,17 @@ def main():
     w = W.plate512()
     plan = msb.Plan(w.n, w.h, w.M, w.alpha, batch=1)
     plan.set_constraints(w.fixed)
+    tuning = None
+    if not args.no_tune:
+        # launch configuration and padded lengths picked by the library's autotuner
+        # (untimed set-up, like the warm-up)
+        print("bench: autotune plate512", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        _, ms64 = plan.autotune("fp64", effort=1, lengths=True)
+        _, ms32 = plan.autotune("fp32", effort=1)
+        tuning = {"seconds": round(time.perf_counter() - t0, 2), "fp64": plan.get_config("fp64"),
+                  "fp32": plan.get_config("fp32"), "product_ms_fp64": round(ms64, 5),
+                  "product_ms_fp32": round(ms32, 5)}
     L = plan.padded_lengths
     dofs = w.dofs
     u64 = torch.from_numpy(W.rng(2, 1).standard_normal((1, 2, w.N))).cuda()
@@ -149,10 +162,41 @@ def main():
         "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kms)},
         "kernels_bytes": dict(zip(names, pb)),
         "chain": chain,
+        "tuning": tuning,
         "fp32": {"GDOF_s": round(dofs * args.steps / wall32 / 1e9, 3),
                  "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kms32)},
                  "chain_frac": round(sum(pb32) / (float(sum(kms32)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
+
+    # the same product on 16 load cases at once (one plan, shared spectra): the
+    # bandwidth regime, reported beside the single-case latency regime above
+    nb = 16
+    pb16 = msb.Plan(w.n, w.h, w.M, w.alpha, batch=nb)
+    pb16.set_constraints(w.fixed)
+    if not args.no_tune:
+        pb16.autotune("fp64", effort=1)
+    ub = torch.from_numpy(W.rng(3, 1).standard_normal((nb, 2, w.N))).cuda()
+    fb = torch.empty_like(ub)
+    for _ in range(5):
+        pb16.apply(ub, fb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        pb16.apply(ub, fb)
+    torch.cuda.synchronize()
+    sb = (time.perf_counter() - t0) / 50
+    kb = pb16.profile_apply(ub, fb, nrep=20)
+    Lb = pb16.padded_lengths
+    bb = [nb * x for x in pass_bytes(w.n, Lb, 2, 8)]
+    bb[1] -= (nb - 1) * 3 * (Lb[0] // 2 + 1) * Lb[1] * 8      # spectra are read once per launch
+    db = int(np.argmax(kb))
+    line["batch16_fp64"] = {"GDOF_s": round(nb * dofs / sb / 1e9, 3), "ms_per_matvec": round(1e3 * sb, 4),
+                            "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kb)},
+                            "dominant": names[db],
+                            "dominant_frac": round(bb[db] / (kb[db] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "chain_frac": round(sum(bb) / (float(sum(kb)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    pb16.close()
+    del ub, fb
 
     # calibration for the HBM byte counters: one plain 64 MiB device copy
     src = torch.empty(8 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -213,6 +257,7 @@ def bench_crack1024(args):
     w = W.crack1024(steps=1000)
     plan = msb.Plan(w.n, w.h, w.M, w.alpha, rho=w.rho)
     plan.set_bonds(msb.crack_to_bonds(w.n, w.h, w.M, w.cracks))
+    tuned = None if args.no_tune else plan.autotune("fp32", effort=1)[0]
     u = torch.zeros((1, 2, w.N), dtype=torch.float32, device="cuda")
     v = torch.zeros_like(u)
     bf = torch.from_numpy(w.b).float().cuda()
@@ -228,7 +273,7 @@ def bench_crack1024(args):
            "steps": w.steps, "seconds": round(dt, 4), "steps_per_s": round(w.steps / dt, 1),
            "GDOF_steps_per_s": round(w.dofs * w.steps / dt / 1e9, 3),
            "energy_first_last": [float(en[0]), float(en[-1])],
-           "n_bonds": plan.n_bonds}
+           "n_bonds": plan.n_bonds, "tuned_fp32": tuned}
     if not args.no_cpu:
         import oracle as O
         p = O.Problem(w.n, w.h, w.M, w.alpha, rho=w.rho)
@@ -251,10 +296,16 @@ def bench_cube128(args):
     w = W.cube128(batch=16)
     plan = msb.Plan(w.n, w.h, w.M, w.alpha, batch=16)
     plan.set_constraints(w.fixed)
+    tuning = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        plan.autotune("fp32_refined", effort=1)
+        tuning = {"seconds": round(time.perf_counter() - t0, 2), "fp64": plan.get_config("fp64"),
+                  "fp32": plan.get_config("fp32")}
     b = torch.from_numpy(w.b).cuda()
     dofs = w.dofs * 16
     out = {"workload": "cube128: 3D static, 128^3 x 16 cases (100663296 DOF), delta=3h, z=0 layer fixed",
-           "padded": list(plan.padded_lengths)}
+           "padded": list(plan.padded_lengths), "tuning": tuning}
     for dt in (torch.float64, torch.float32):
         u = b.to(dt)
         f = torch.empty_like(u)
@@ -299,6 +350,8 @@ def bench_plates64(args):
         w0 = g[0]
         pl = msb.Plan(w0.n, w0.h, w0.M, w0.alpha, infl=w0.infl, batch=len(g))
         pl.set_constraints(w0.fixed)
+        if not args.no_tune:
+            pl.autotune("fp32_refined", effort=0)
         plans[s] = pl
     Solve = msb.make_solve_function()
 
