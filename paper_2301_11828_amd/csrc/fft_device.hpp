@@ -167,7 +167,7 @@ struct FastDiv {
     bool exact;
     __device__ __forceinline__ FastDiv(uint32_t dd, uint32_t nmax) : d(dd) {
         exact = dd < 65536u && nmax < 65536u;
-        m = dd <= 1 ? 0u : (uint32_t)((0x100000000ull + dd - 1) / dd);
+        m = dd <= 1 ? 0u : 0xFFFFFFFFu / dd + 1u;   // ceil(2^32 / d), 32-bit arithmetic
     }
     __device__ __forceinline__ uint32_t div(uint32_t n) const { return exact ? fdiv(n, m) : n / d; }
 };

@@ -199,28 +199,33 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
     const T2 *res = (a.sx.np & 1) ? bufB : bufA;
 
     // unpack the two real transforms of each slot; x-spectrum k < H into
-    // [b][c][z][kx][y]; the whole block stores, consecutive threads on consecutive
-    // rows of one kx (the transposed layout's contiguous axis)
-    const FastDiv dv(nsig, nsig * a.H), dr(nr, nsig), dy(a.Ny, a.rows);
-    for (int idx = threadIdx.x; idx < nsig * a.H; idx += blockDim.x) {
-        const int kx = dv.div(idx);
-        const int sig = idx - kx * nsig;
-        const T2 *zs = res + (size_t)(sig >> 1) * Lx;
-        const T2 Z = zs[kx];
-        const T2 Zm = zs[kx == 0 ? 0 : Lx - kx];
-        T2 X;
-        if ((sig & 1) == 0) {
-            X.x = T(0.5) * (Z.x + Zm.x);
-            X.y = T(0.5) * (Z.y - Zm.y);
-        } else {
-            X.x = T(0.5) * (Z.y + Zm.y);
-            X.y = T(0.5) * (Zm.x - Z.x);
+    // [b][c][z][kx][y].  The whole block stores: thread t owns real row
+    // sig = t % nsig and the frequencies kx = t / nsig + j G (G = blockDim / nsig,
+    // nsig <= 48 < blockDim), so consecutive threads write consecutive rows of one
+    // kx (the transposed layout's contiguous axis) and the loop has no division.
+    {
+        const int G = blockDim.x / nsig;
+        const int sig = threadIdx.x % nsig, k0 = threadIdx.x / nsig;
+        if (k0 < G) {
+            const int c = sig / nr, row = r0 + sig - c * nr;
+            const int z = row / a.Ny, y = row - z * a.Ny;
+            T2 *dst = a.T1 + (((size_t)b * a.d + c) * a.Nz + z) * a.H * a.Ny + y;
+            const T2 *zs = res + (size_t)(sig >> 1) * Lx;
+            const bool odd = (sig & 1) != 0;
+            for (int kx = k0; kx < a.H; kx += G) {
+                const T2 Z = zs[kx];
+                const T2 Zm = zs[kx == 0 ? 0 : Lx - kx];
+                T2 X;
+                if (!odd) {
+                    X.x = T(0.5) * (Z.x + Zm.x);
+                    X.y = T(0.5) * (Z.y - Zm.y);
+                } else {
+                    X.x = T(0.5) * (Z.y + Zm.y);
+                    X.y = T(0.5) * (Zm.x - Z.x);
+                }
+                dst[kx * a.Ny] = X;
+            }
         }
-        const int c = dr.div(sig);
-        const int row = r0 + sig - c * nr;
-        const int z = dy.div(row);
-        const int y = row - z * a.Ny;
-        a.T1[((((size_t)b * a.d + c) * a.Nz + z) * a.H + kx) * a.Ny + y] = X;
     }
 }
 
@@ -272,9 +277,8 @@ __global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
     const T *spec = a.spec + (size_t)b * a.spec_slot;
     const size_t cstride = (size_t)nlines * L;
     const int lines_here = ns / d;
-    for (int idx = tm.tid; idx < lines_here * L; idx += tm.nt) {
-        const int lk = idx / L;
-        const int k = idx - lk * L;
+    for (int lk = 0; lk < lines_here; ++lk)
+    for (int k = tm.tid; k < L; k += tm.nt) {
         const int line = l0 + s0 / d + lk;
         const T *g0 = spec + (size_t)line * L + k;
         T2 *u = res + (size_t)lk * d * L + k;
@@ -357,14 +361,19 @@ __global__ __launch_bounds__(1024) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
     if (ns > 0) team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
     if (!BLOCK) __syncthreads();
     const T2 *res = (a.sy.np & 1) ? bufB : bufA;
-    // the whole block stores, consecutive threads on consecutive z (T2's contiguous axis)
-    const FastDiv dz(nz, nz * d * Ly), dd(d, d * Ly);
-    for (int idx = threadIdx.x; idx < nz * d * Ly; idx += blockDim.x) {
-        const int rest = dz.div(idx);
-        const int zl = idx - rest * nz;
-        const int ky = dd.div(rest);
-        const int c = rest - ky * d;
-        a.T2[((((size_t)b * d + c) * a.H + kx) * Ly + ky) * a.Nz + z0 + zl] = res[(size_t)(zl * d + c) * Ly + ky];
+    // the whole block stores: thread t owns z = z0 + t % nz and ky = t / nz + j G
+    // (G = blockDim / nz, nz <= 16 < blockDim), consecutive threads on consecutive z
+    // (T2's contiguous axis)
+    {
+        const int G = blockDim.x / nz;
+        const int zl = threadIdx.x % nz, k0 = threadIdx.x / nz;
+        if (k0 < G) {
+            for (int c = 0; c < d; ++c) {
+                T2 *dst = a.T2 + (((size_t)b * d + c) * a.H + kx) * Ly * a.Nz + z0 + zl;
+                const T2 *src = res + (size_t)(zl * d + c) * Ly;
+                for (int ky = k0; ky < Ly; ky += G) dst[ky * a.Nz] = src[ky];
+            }
+        }
     }
 }
 
@@ -392,14 +401,16 @@ __global__ __launch_bounds__(1024) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
     int s0, ns;
     tm.slots(nz * d, d * a.lpw, s0, ns);
     {
-        // the whole block loads, consecutive threads on consecutive z
-        const FastDiv dz(nz, nz * d * Ly), dd(d, d * Ly);
-        for (int idx = threadIdx.x; idx < nz * d * Ly; idx += blockDim.x) {
-            const int rest = dz.div(idx);
-            const int zl = idx - rest * nz;
-            const int ky = dd.div(rest);
-            const int c = rest - ky * d;
-            bufA[(size_t)(zl * d + c) * Ly + ky] = a.T2[((((size_t)b * d + c) * a.H + kx) * Ly + ky) * a.Nz + z0 + zl];
+        // the whole block loads: thread t owns z = z0 + t % nz and ky = t / nz + j G,
+        // consecutive threads on consecutive z
+        const int G = blockDim.x / nz;
+        const int zl = threadIdx.x % nz, k0 = threadIdx.x / nz;
+        if (k0 < G) {
+            for (int c = 0; c < d; ++c) {
+                const T2 *src = a.T2 + (((size_t)b * d + c) * a.H + kx) * Ly * a.Nz + z0 + zl;
+                T2 *dst = bufA + (size_t)(zl * d + c) * Ly;
+                for (int ky = k0; ky < Ly; ky += G) dst[ky] = src[ky * a.Nz];
+            }
         }
     }
     __syncthreads();
@@ -444,36 +455,41 @@ __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
     int s0, ns;
     tm.slots(S, a.spw_i, s0, ns);
 
-    // full spectrum Z = Xa + i Xb of every slot with the Hermitian halves mirrored;
-    // the whole block loads, consecutive threads on consecutive rows of one kx
+    // full spectrum Z = Xa + i Xb of every slot with the Hermitian halves mirrored.
+    // The whole block loads: thread t owns slot sl = t % S and the frequencies
+    // kx = t / S + j G (G = blockDim / S, S <= 24 < blockDim); consecutive threads
+    // read consecutive rows of one kx, no division in the loop.
     {
-        const FastDiv dv(S, S * a.H), dr(nr, nsig), dy(a.Ny, a.rows);
-        for (int idx = threadIdx.x; idx < S * a.H; idx += blockDim.x) {
-            const int kx = dv.div(idx);
-            const int sl = idx - kx * S;
-            T2 X[2];
+        const int G = blockDim.x / S;
+        const int sl = threadIdx.x % S, k0 = threadIdx.x / S;
+        if (k0 < G) {
+            const T2 *src[2] = {nullptr, nullptr};
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2) {
-                X[h2].x = T(0);
-                X[h2].y = T(0);
                 const int sig = 2 * sl + h2;
                 if (sig < nsig) {
-                    const int c = dr.div(sig), row = r0 + sig - c * nr;
-                    const int z = dy.div(row), y = row - z * a.Ny;
-                    X[h2] = a.T1[((((size_t)b * d + c) * a.Nz + z) * a.H + kx) * a.Ny + y];
+                    const int c = sig / nr, row = r0 + sig - c * nr;
+                    const int z = row / a.Ny, y = row - z * a.Ny;
+                    src[h2] = a.T1 + (((size_t)b * d + c) * a.Nz + z) * a.H * a.Ny + y;
                 }
             }
             T2 *zs = bufA + (size_t)sl * Lx;
-            T2 Z;
-            Z.x = X[0].x - X[1].y;
-            Z.y = X[0].y + X[1].x;
-            zs[kx] = Z;
-            const int m = Lx - kx;
-            if (kx >= 1 && m >= a.H) {
-                T2 Zm;
-                Zm.x = X[0].x + X[1].y;
-                Zm.y = -X[0].y + X[1].x;
-                zs[m] = Zm;
+            for (int kx = k0; kx < a.H; kx += G) {
+                T2 X0, X1;
+                X0.x = X0.y = X1.x = X1.y = T(0);
+                if (src[0]) X0 = src[0][kx * a.Ny];
+                if (src[1]) X1 = src[1][kx * a.Ny];
+                T2 Z;
+                Z.x = X0.x - X1.y;
+                Z.y = X0.y + X1.x;
+                zs[kx] = Z;
+                const int m = Lx - kx;
+                if (kx >= 1 && m >= a.H) {
+                    T2 Zm;
+                    Zm.x = X0.x + X1.y;
+                    Zm.y = -X0.y + X1.x;
+                    zs[m] = Zm;
+                }
             }
         }
     }
@@ -512,36 +528,83 @@ __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
             tm.sync();
         }
 
+        // incomplete horizon (eq. (tea:sc)): f += D^e u with D^e from the table indexed
+        // by the clamped distances to the faces.  Applied to the rows in LDS before the
+        // epilogue, as its own pass: an interior row needs it only on its first and
+        // last M columns, so those are gathered across all rows of the team in one
+        // flat loop (one memory round trip for the team instead of one per row).
         const T *de = a.de + (size_t)b * a.de_slot;
         const int M = a.M, M1 = a.M + 1;
-        const T dth = T(0.5 * e.dt);
-        const T rinv = T(1.0 / e.rho);
-        for (int sl = 0; sl < nsg; ++sl) {
+        // table index = (lx (M+1) + hx) (M+1)^(2d-2) + [y and z part, fixed per row]
+        const int M1p = d == 2 ? M1 * M1 : M1 * M1 * M1 * M1;
+        const bool narrow = a.Nx <= 2 * M;   // every column is within M of an x face
+        auto row_of = [&](int sl, int &c, int &row, int &rpart) -> bool {
             const int sig = 2 * s0 + sl;
-            const int c = sig / nr, row = r0 + sig - c * nr;
+            c = sig / nr;
+            row = r0 + sig - c * nr;
             const int z = row / a.Ny, y = row - z * a.Ny;
             const int ly = min(y, M), hy = min(a.Ny - 1 - y, M);
             const int lz = d == 3 ? min(z, M) : 0, hz = d == 3 ? min(a.Nz - 1 - z, M) : 0;
-            const bool row_interior = (ly == M) & (hy == M) & (d == 2 || ((lz == M) & (hz == M)));
+            rpart = ly * M1 + hy;
+            if (d == 3) rpart = (rpart * M1 + lz) * M1 + hz;
+            return (ly == M) & (hy == M) & (d == 2 || ((lz == M) & (hz == M)));   // interior row
+        };
+        auto apply_de = [&](int sl, int c, int row, int rpart, int n) {
+            const int lx = min(n, M), hx = min(a.Nx - 1 - n, M);
+            const int dx = (lx * M1 + hx) * M1p + rpart;
+            const T *urow = uin + cbase + (size_t)row * a.Nx + n;   // component cb at urow[cb N]
+            T *fr = Rr + 2 * ((size_t)(sl >> 1) * Lx + n) + (sl & 1);
+            T f = *fr;
+            for (int cb = 0; cb < d; ++cb) f += de[(size_t)comp_of(c, cb, d) * a.de_stride + dx] * urow[(size_t)cb * a.N];
+            *fr = f;
+        };
+        // (whole-workgroup teams apply D^e inline in the epilogue instead: there only
+        // the waves holding boundary columns wait for the table, with no extra barrier)
+        if (!BLOCK && !narrow) {
+            // interior rows: columns [0, M) and [Nx - M, Nx), flattened over the rows
+            const int per = 2 * M;
+            for (int jj = tm.tid; jj < nsg * per; jj += tm.nt) {
+                const int sl = jj / per, j = jj - sl * per;
+                int c, row, rpart;
+                if (!row_of(sl, c, row, rpart)) continue;
+                apply_de(sl, c, row, rpart, j < M ? j : a.Nx - per + j);
+            }
+        }
+        // rows within M of a y or z face (or every row of a narrow grid): all columns
+        for (int sl = 0; sl < nsg && !BLOCK; ++sl) {
+            int c, row, rpart;
+            if (row_of(sl, c, row, rpart) && !narrow) continue;
+#pragma unroll 4
+            for (int n = tm.tid; n < a.Nx; n += tm.nt) apply_de(sl, c, row, rpart, n);
+        }
+        if (!BLOCK) tm.sync();
+
+        const T dth = T(0.5 * e.dt);
+        const T rinv = T(1.0 / e.rho);
+        const T sign = T(e.sign);
+        for (int sl = 0; sl < nsg; ++sl) {
+            int c, row, rpart;
+            const bool rint = row_of(sl, c, row, rpart);
             const size_t rbase = cbase + (size_t)c * a.N + (size_t)row * a.Nx;
             const uint8_t *fxrow = a.fixed ? a.fixed + (size_t)c * a.N + (size_t)row * a.Nx : nullptr;
             const T *Rrow = Rr + 2 * (size_t)(sl >> 1) * Lx + (sl & 1);
+            const T *dec[3];
+            for (int cb = 0; cb < 3; ++cb) dec[cb] = de + (size_t)comp_of(c, cb < d ? cb : 0, d) * a.de_stride + rpart;
+            const T *urow = uin + cbase + (size_t)row * a.Nx;   // component cb at urow[cb N + n]
             for (int n = tm.tid; n < a.Nx; n += tm.nt) {
                 const size_t addr = rbase + n;
                 T f = Rrow[2 * n];
-                // incomplete horizon (eq. (tea:sc)): table by clamped distances to the faces
-                const int lx = min(n, M), hx = min(a.Nx - 1 - n, M);
-                if (!(row_interior & (lx == M) & (hx == M))) {
-                    int didx = ((lx * M1 + hx) * M1 + ly) * M1 + hy;
-                    if (d == 3) didx = (didx * M1 + lz) * M1 + hz;
-                    const size_t node = (size_t)row * a.Nx + n;
-                    for (int cb = 0; cb < d; ++cb)
-                        f += de[(size_t)comp_of(c, cb, d) * a.de_stride + didx] * uin[cbase + (size_t)cb * a.N + node];
+                if (BLOCK) {
+                    const int lx = min(n, M), hx = min(a.Nx - 1 - n, M);
+                    if (!(rint & (lx == M) & (hx == M))) {
+                        const int dx = (lx * M1 + hx) * M1p;
+                        for (int cb = 0; cb < d; ++cb) f += dec[cb][dx] * urow[cb * a.N + n];
+                    }
                 }
                 const bool fx = fxrow && fxrow[n];
                 switch (e.epi) {
                     case EPI_APPLY:
-                        e.out[addr] = fx ? T(0) : T(e.sign) * f;
+                        e.out[addr] = fx ? T(0) : sign * f;
                         break;
                     case EPI_CG_Q: {
                         const T q = fx ? T(0) : -f;
