@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "0")))
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plans' default launch configurations (skip the autotuner)")
+    ap.add_argument("--config", default=None,
+                    help="JSON file with a recorded tuning (the 'tuning' object of an earlier plate512 line) "
+                         "to apply instead of running the autotuner, e.g. for profiling runs")
     ap.add_argument("--workload", default="plate512",
                     choices=["plate512", "crack1024", "cube128", "plates64"],
                     help="plate512 is the headline line; the others measure the remaining workloads")
@@ -92,16 +95,22 @@ def main():
     plan = msb.Plan(w.n, w.h, w.M, w.alpha, batch=1)
     plan.set_constraints(w.fixed)
     tuning = None
-    if not args.no_tune:
+    recorded = json.load(open(args.config)) if args.config else None
+    if recorded:
+        plan.set_lengths(recorded["padded"])
+        plan.set_config("fp64", **recorded["fp64"])
+        plan.set_config("fp32", **recorded["fp32"])
+        tuning = dict(recorded, source=os.path.basename(args.config))
+    elif not args.no_tune:
         # launch configuration and padded lengths picked by the library's autotuner
         # (untimed set-up, like the warm-up)
         print("bench: autotune plate512", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         _, ms64 = plan.autotune("fp64", effort=1, lengths=True)
         _, ms32 = plan.autotune("fp32", effort=1)
-        tuning = {"seconds": round(time.perf_counter() - t0, 2), "fp64": plan.get_config("fp64"),
-                  "fp32": plan.get_config("fp32"), "product_ms_fp64": round(ms64, 5),
-                  "product_ms_fp32": round(ms32, 5)}
+        tuning = {"seconds": round(time.perf_counter() - t0, 2), "padded": list(plan.padded_lengths),
+                  "fp64": plan.get_config("fp64"), "fp32": plan.get_config("fp32"),
+                  "product_ms_fp64": round(ms64, 5), "product_ms_fp32": round(ms32, 5)}
     L = plan.padded_lengths
     dofs = w.dofs
     u64 = torch.from_numpy(W.rng(2, 1).standard_normal((1, 2, w.N))).cuda()
@@ -138,8 +147,14 @@ def main():
     pb32 = pass_bytes(w.n, L, 2, 4)
     dom = int(np.argmax(kms))
     achieved = pb[dom] / (kms[dom] * 1e-3) / 1e9
-    kname = {"x_forward": "k_xfwd<double>", "y_line_product": "k_line_prod<double>",
-             "x_inverse": "k_xinv<double>"}[names[dom]]
+    # the counter summary keys kernels by name and workgroup count (tells this plan's
+    # launches from the 16-case plan's)
+    c64 = plan.get_config("fp64")
+    wave = c64["team_line"] == 1 if names[dom] == "y_line_product" else c64["team_x"] == 1
+    ngroups = (-(-(L[0] // 2 + 1) // c64["lines_per_wg"]) if names[dom] == "y_line_product"
+               else -(-w.n[1] // c64["rows_per_wg"]))
+    kname = "%s<double%s>@%d" % ({"x_forward": "k_xfwd", "y_line_product": "k_line_prod",
+                                   "x_inverse": "k_xinv"}[names[dom]], ",wave" if wave else "", ngroups)
     traffic = load_traffic(os.path.join(ROOT, "profiles", "plate512_fp64_hbm_counters.txt"), kname)
     roofline = {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -173,8 +188,12 @@ def main():
     nb = 16
     pb16 = msb.Plan(w.n, w.h, w.M, w.alpha, batch=nb)
     pb16.set_constraints(w.fixed)
-    if not args.no_tune:
+    if recorded and "batch16_fp64" in recorded:
+        pb16.set_config("fp64", **recorded["batch16_fp64"])
+    elif not args.no_tune:
         pb16.autotune("fp64", effort=1)
+    if tuning is not None:
+        tuning["batch16_fp64"] = pb16.get_config("fp64")
     ub = torch.from_numpy(W.rng(3, 1).standard_normal((nb, 2, w.N))).cuda()
     fb = torch.empty_like(ub)
     for _ in range(5):

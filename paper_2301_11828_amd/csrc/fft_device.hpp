@@ -388,4 +388,29 @@ __device__ __forceinline__ double block_sum_partials(const double *__restrict__ 
     return s;
 }
 
+// Sums of K <= 4 arrays of n partials each by a whole block, all in one pass and one
+// tree (the same per-array order as block_sum_partials); results broadcast to all
+// threads.
+template <int K>
+__device__ __forceinline__ void block_sum_partials_k(const double *const (&p)[K], int n, double (&out)[K],
+                                                     double *red, int tid, int nt) {
+    static_assert(K >= 1 && K <= 4, "block_sum uses red[k * 16 + wave] and red[64 + k]");
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int i = tid; i < n; i += nt) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += p[k][i];
+    }
+    block_sum<K>(v, red, tid, nt);
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[64 + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = red[64 + k];
+    __syncthreads();
+}
+
 }  // namespace msb

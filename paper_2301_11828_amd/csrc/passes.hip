@@ -97,11 +97,19 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
     if (e.pro == PRO_CG_P) {
         const int tid0 = threadIdx.x, ntb = blockDim.x;
         if (!e.first) {
-            const size_t st3 = (size_t)gridDim.x;
-            const double rr = block_sum_partials(e.rr_prev + (size_t)b * tpc, tpc, red, tid0, ntb);
-            const double pq = block_sum_partials(e.cg3 + (size_t)b * tpc, tpc, red, tid0, ntb);
-            const double rq = block_sum_partials(e.cg3 + st3 + (size_t)b * tpc, tpc, red, tid0, ntb);
-            const double qq = block_sum_partials(e.cg3 + 2 * st3 + (size_t)b * tpc, tpc, red, tid0, ntb);
+            // case sums of r.r, p.q, r.q, q.q: from the per-case reduction when the
+            // solver ran one (many tiles per case), else reduced here from the tiles
+            double sums[4];
+            if (e.case4) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sums[k] = e.case4[(size_t)b * 4 + k];
+            } else {
+                const size_t st3 = (size_t)gridDim.x;
+                const double *const parts[4] = {e.rr_prev + (size_t)b * tpc, e.cg3 + (size_t)b * tpc,
+                                                e.cg3 + st3 + (size_t)b * tpc, e.cg3 + 2 * st3 + (size_t)b * tpc};
+                block_sum_partials_k<4>(parts, tpc, sums, red, tid0, ntb);
+            }
+            const double rr = sums[0], pq = sums[1], rq = sums[2], qq = sums[3];
             const double al = rr / pq;
             if (!(pq > 0.0) || !(al == al) || al > 1e300) {   // K not positive definite on p
                 if (r0 == 0 && tid0 == 0) e.done_rw[b] = 2;

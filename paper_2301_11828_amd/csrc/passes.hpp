@@ -72,6 +72,7 @@ template <typename T> struct EndArgs {
     const double *cg3;         // previous x-inverse partials [3][B*tiles]: p.q, r.q, q.q
     const double *rr_prev;     // previous true r.r partials [B][tiles]
     double *rr_out;            // this iteration's true r.r partials [B][tiles]
+    const double *case4;       // if set: [B][4] case sums of r.r, p.q, r.q, q.q already reduced
     const double *beta_num;    // first iteration of a continued run: beta = sum(num)/sum(den)
     const double *beta_den;
     int n_num, n_den;

@@ -32,6 +32,7 @@ struct SolverWs {
     double *part_x = nullptr;        // [3][B * rows] x-inverse epilogue partials
     double *part_rr = nullptr;       // [2][B][tiles] true r.r partials (by iteration parity)
     double *part_aux = nullptr;      // [3][B][P] dot partials
+    double *case4 = nullptr;         // [B][4] CG case sums (many tiles per case)
     double *thresh = nullptr;        // [B]
     double *scal = nullptr;          // [16][B] per-case scalars
     double *energy = nullptr;        // energies (device)
@@ -53,7 +54,7 @@ void solver_cache_free(msb_plan_s *p) {
         if (x) (void)hipFree(x);
     for (auto x : w->v32)
         if (x) (void)hipFree(x);
-    void *b[] = {w->part_x, w->part_rr, w->part_aux, w->thresh, w->scal, w->energy, w->done, w->iters, w->ecount};
+    void *b[] = {w->part_x, w->part_rr, w->part_aux, w->case4, w->thresh, w->scal, w->energy, w->done, w->iters, w->ecount};
     for (void *x : b)
         if (x) (void)hipFree(x);
     if (w->h_scal) (void)hipHostFree(w->h_scal);
@@ -81,6 +82,7 @@ static msb_status get_ws(msb_plan_s *p, SolverWs *&out) {
     MSB_HIP(hipMalloc(&w->part_x, sizeof(double) * 3 * (size_t)B * rows_total(p)));
     MSB_HIP(hipMalloc(&w->part_rr, sizeof(double) * 2 * (size_t)B * std::max<int64_t>(rows_total(p), w->P)));
     MSB_HIP(hipMalloc(&w->part_aux, sizeof(double) * 3 * (size_t)B * w->P));
+    MSB_HIP(hipMalloc(&w->case4, sizeof(double) * 4 * (size_t)B));
     MSB_HIP(hipMalloc(&w->thresh, sizeof(double) * B));
     MSB_HIP(hipMalloc(&w->scal, sizeof(double) * 16 * B));
     MSB_HIP(hipMalloc(&w->done, sizeof(int) * B));
@@ -228,6 +230,24 @@ template <typename T> struct Cg {
     const double *prev_rr;   // r.r partials before a residual replacement (first beta), or null
 };
 
+// Per-case sums of the tile partials the next CG iteration needs (r.r, p.q, r.q,
+// q.q), one block per case.  Used when a case has many tiles: every x-forward block
+// would otherwise re-reduce all of its case's partials.
+__global__ void k_cg_case4(const double *rr_prev, const double *cg3, size_t st3, int tpc, double *case4) {
+    __shared__ double red[80];
+    const int b = blockIdx.x;
+    const double *const parts[4] = {rr_prev + (size_t)b * tpc, cg3 + (size_t)b * tpc, cg3 + st3 + (size_t)b * tpc,
+                                    cg3 + 2 * st3 + (size_t)b * tpc};
+    double sums[4];
+    block_sum_partials_k<4>(parts, tpc, sums, red, threadIdx.x, blockDim.x);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 4; ++k) case4[(size_t)b * 4 + k] = sums[k];
+    }
+}
+
+// Tiles per case above which the per-case sums come from k_cg_case4.
+constexpr int kFusedReduceMaxTiles = 1024;
+
 // One CG iteration = one product chain.  The x-forward prologue applies the
 // previous iteration's update (x += alpha p, r -= alpha q, alpha and beta from the
 // previous partial sums) and forms p = r + beta p; the x-inverse epilogue forms
@@ -248,6 +268,11 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
     e.rr_out = w->part_rr + (size_t)(it & 1) * nt;
     e.first = it == 0;
     e.update_only = update_only;
+    if (it > 0 && c.tpc > kFusedReduceMaxTiles) {
+        hipLaunchKernelGGL(k_cg_case4, dim3(B), dim3(kT), 0, c.st, (const double *)e.rr_prev, (const double *)e.cg3,
+                           nt, c.tpc, w->case4);
+        e.case4 = w->case4;
+    }
     e.iters = w->iters;
     if (it == 0 && c.prev_rr) {   // continuation after a residual replacement
         e.beta_num = w->part_aux;

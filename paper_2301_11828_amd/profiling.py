@@ -36,16 +36,28 @@ def _short(name: str) -> str:
     return name[:60]
 
 
+def _key(r) -> str:
+    """Kernel short name @ number of workgroups (tells launches of different plans apart)."""
+    wg = 0
+    for g, w in (("Grid_Size", "Workgroup_Size"), ("Grid_Size_X", "Workgroup_Size_X")):
+        try:
+            wg = int(r[g]) // max(1, int(r[w]))
+            break
+        except (KeyError, ValueError):
+            continue
+    return "%s@%d" % (_short(r["Kernel_Name"]), wg)
+
+
 def trace(d: str):
     files = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
     durs = collections.defaultdict(list)
     for f in files:
         for r in csv.DictReader(open(f)):
-            durs[_short(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    print("kernel                                   calls    avg_us    med_us    min_us")
+            durs[_key(r)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    print("kernel@workgroups                            calls    avg_us    med_us    min_us")
     for k, v in sorted(durs.items(), key=lambda x: -sum(x[1])):
         v.sort()
-        print("%-40s %5d %9.2f %9.2f %9.2f" % (k, len(v), sum(v) / len(v) / 1e3, v[len(v) // 2] / 1e3, v[0] / 1e3))
+        print("%-44s %5d %9.2f %9.2f %9.2f" % (k, len(v), sum(v) / len(v) / 1e3, v[len(v) // 2] / 1e3, v[0] / 1e3))
     print("source_hash: %s" % source_hash())
 
 
@@ -55,7 +67,7 @@ def _counter(d: str, name: str):
     for f in files:
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] == name:
-                vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+                vals[(r["Kernel_Name"], _key(r))].append(float(r["Counter_Value"]))
     return vals
 
 
@@ -63,24 +75,24 @@ def counters(dfetch: str, dwrite: str, copy_bytes: float):
     fe, wr = _counter(dfetch, "FETCH_SIZE"), _counter(dwrite, "WRITE_SIZE")
 
     def copy_kernel(vals):
-        cands = {k: v for k, v in vals.items() if "copy" in k.lower() or "elementwise" in k.lower()}
+        cands = {k: v for k, v in vals.items() if "copy" in k[0].lower() or "elementwise" in k[0].lower()}
         return max(cands.items(), key=lambda kv: max(kv[1])) if cands else (None, None)
 
     ck, cf = copy_kernel(fe)
     _, cw = copy_kernel(wr)
     sf = (max(cf) * 1024.0 / copy_bytes) if cf else None
     sw = (max(cw) * 1024.0 / copy_bytes) if cw else None
-    print("calibration copy kernel: %s, %.0f bytes read+written per dispatch" % (ck, copy_bytes))
+    print("calibration copy kernel: %s, %.0f bytes read+written per dispatch" % (ck[0] if ck else None, copy_bytes))
     print("calibration: FETCH_SIZE reads %.4f x true bytes, WRITE_SIZE reads %.4f x" % (sf or float("nan"), sw or float("nan")))
-    print("kernel                                   fetch_KiB  write_KiB  traffic_bytes_per_launch(calibrated)")
+    print("kernel@workgroups                            fetch_KiB  write_KiB  traffic_bytes_per_launch(calibrated)")
     rows = {}
-    for k in sorted(set(fe) | set(wr)):
-        s = _short(k)
+    for k in sorted(set(fe) | set(wr), key=lambda kk: kk[1]):
+        s = k[1]
         f = sum(fe.get(k, [0])) / max(len(fe.get(k, [1])), 1)
         w = sum(wr.get(k, [0])) / max(len(wr.get(k, [1])), 1)
         t = (f * 1024 / sf if sf else f * 1024) + (w * 1024 / sw if sw else w * 1024)
         rows[s] = t
-        print("%-40s %10.1f %10.1f %14.0f" % (s, f, w, t))
+        print("%-44s %10.1f %10.1f %14.0f" % (s, f, w, t))
     for k, t in rows.items():
         if k.startswith("k_"):
             print("traffic %s %.0f" % (k, t))

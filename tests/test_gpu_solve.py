@@ -184,3 +184,27 @@ def test_wave_owned_fused_cg_matches_cholesky(prec):
         log("wave-owned %s case %d: %d inner it, residual %.2e, rel err %.3e" % (prec, c, info[c].inner_iters,
             info[c].rel_residual, err))
         assert info[c].status == 0 and err <= 1e-10
+
+
+def test_many_tiles_per_case_case_reduction():
+    """More than 1024 x-tiles per case (one grid row per workgroup on a 24 x 1100
+    plate) switches the CG case sums from the fused per-block reduction to the
+    per-case reduction kernel: the solve must match the fused path (8 rows per
+    workgroup, 138 tiles) and give the oracle's residual."""
+    w = W.small(2, (24, 1100), 3, seed=91, fixed="left", batch=2)
+    plan = gpu_plan(w)
+    plan.set_config("fp64", rows_per_wg=1, team_x=0)
+    u1, info1 = plan.solve(to_dev(w.b), precision="fp64", tol=1e-11, maxit=20000)
+    plan.set_config("fp64", rows_per_wg=8, team_x=0)
+    u2, info2 = plan.solve(to_dev(w.b), precision="fp64", tol=1e-11, maxit=20000)
+    a, bb = u1.cpu().numpy(), u2.cpu().numpy()
+    p = oracle_problem(w)
+    for c in range(2):
+        free = ~w.fixed
+        r = (w.b[c] + O.apply(p, a[c], w.fixed))[free]      # b_F - K_FF u_F with K = -A
+        rel = np.linalg.norm(r) / np.linalg.norm(w.b[c][free])
+        d = rel_err(a[c], bb[c])
+        log("1100 tiles/case: case %d %d vs %d it, oracle residual %.2e, vs fused path %.2e" %
+            (c, info1[c].inner_iters, info2[c].inner_iters, rel, d))
+        assert info1[c].status == 0 and info2[c].status == 0
+        assert rel <= 1e-10 and d <= 1e-8
