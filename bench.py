@@ -67,9 +67,12 @@ def main():
     ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "0")))
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plans' default launch configurations (skip the autotuner)")
-    ap.add_argument("--config", default=None,
-                    help="JSON file with a recorded tuning (the 'tuning' object of an earlier plate512 line) "
-                         "to apply instead of running the autotuner, e.g. for profiling runs")
+    ap.add_argument("--config", default=os.path.join(ROOT, "profiles", "plate512_tuning.json"),
+                    help="JSON file with a recorded plate512 tuning (padded lengths and launch configurations, "
+                         "as written by the autotuner) applied instead of tuning; default: the tuning the "
+                         "committed plate512 profiles were taken with")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner for plate512 instead of applying the recorded tuning")
     ap.add_argument("--workload", default="plate512",
                     choices=["plate512", "crack1024", "cube128", "plates64"],
                     help="plate512 is the headline line; the others measure the remaining workloads")
@@ -95,7 +98,8 @@ def main():
     plan = msb.Plan(w.n, w.h, w.M, w.alpha, batch=1)
     plan.set_constraints(w.fixed)
     tuning = None
-    recorded = json.load(open(args.config)) if args.config else None
+    recorded = (json.load(open(args.config)) if args.config and os.path.exists(args.config)
+                and not args.retune and not args.no_tune else None)
     if recorded:
         plan.set_lengths(recorded["padded"])
         plan.set_config("fp64", **recorded["fp64"])
