@@ -157,7 +157,7 @@ def main():
     wave = c64["team_line"] == 1 if names[dom] == "y_line_product" else c64["team_x"] == 1
     ngroups = (-(-(L[0] // 2 + 1) // c64["lines_per_wg"]) if names[dom] == "y_line_product"
                else -(-w.n[1] // c64["rows_per_wg"]))
-    kname = "%s<double%s>@%d" % ({"x_forward": "k_xfwd", "y_line_product": "k_line_prod",
+    kname = "%s<double%s>@%d" % ({"x_forward": "k_xfwd", "y_line_product": "k_line_y",
                                    "x_inverse": "k_xinv"}[names[dom]], ",wave" if wave else "", ngroups)
     traffic = load_traffic(os.path.join(ROOT, "profiles", "plate512_fp64_hbm_counters.txt"), kname)
     roofline = {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
@@ -358,8 +358,11 @@ def bench_cube128(args):
 
 
 def bench_plates64(args):
-    """64 plates of uneven size: forward FP32-refined solve, loss, hand-written adjoint
-    solve and influence-coefficient gradient, grouped into one batched plan per size."""
+    """64 plates of uneven size: target solve, forward FP32-refined solve, loss,
+    hand-written adjoint solve and influence-coefficient gradient.  The plates are
+    batched per size (one plan per size, per-case coefficients) and the five plans
+    run as one plan group: one launch per pass covers every plate.  The same work
+    done plan after plan is timed beside it."""
     import numpy as np
     import torch
     import paper_2301_11828_amd as msb
@@ -368,44 +371,66 @@ def bench_plates64(args):
     groups = {}
     for w in ws:
         groups.setdefault(w.n[0], []).append(w)
-    plans = {}
-    for s, g in groups.items():
-        w0 = g[0]
-        pl = msb.Plan(w0.n, w0.h, w0.M, w0.alpha, infl=w0.infl, batch=len(g))
+    sizes = sorted(groups)
+    plans = []
+    for s in sizes:
+        w0 = groups[s][0]
+        pl = msb.Plan(w0.n, w0.h, w0.M, w0.alpha, infl=w0.infl, batch=len(groups[s]))
         pl.set_constraints(w0.fixed)
         if not args.no_tune:
             pl.autotune("fp32_refined", effort=0)
-        plans[s] = pl
+        plans.append(pl)
+    grp = msb.PlanGroup(plans)
+    GSolve = msb.make_group_solve_function()
     Solve = msb.make_solve_function()
 
-    def run():
+    def inputs():
+        bs = [torch.from_numpy(np.concatenate([w.b for w in groups[s]])).cuda().requires_grad_(True) for s in sizes]
+        as_ = [torch.tensor(np.array([w.infl for w in groups[s]]), dtype=torch.float64, requires_grad=True)
+               for s in sizes]
+        targets = [np.array([w.extra["infl_target"] for w in groups[s]]) for s in sizes]
+        return bs, as_, targets
+
+    def run_group():
+        bs, as_, targets = inputs()
+        for pl, t in zip(plans, targets):
+            pl.set_infl(t, per_case=True)
+        uts, _ = grp.solve([b.detach() for b in bs], precision="fp32_refined", tol=1e-10)
+        us = GSolve.apply(grp, "fp32_refined", 1e-10, *bs, *as_)
+        loss = sum(((u - ut) ** 2).sum() for u, ut in zip(us, uts))
+        loss.backward()
+        torch.cuda.synchronize()
+        return loss.item(), [a.grad.numpy() for a in as_]
+
+    def run_sequential():
+        bs, as_, targets = inputs()
         total = 0.0
-        grads = []
-        for s, g in groups.items():
-            pl = plans[s]
-            b = torch.from_numpy(np.concatenate([w.b for w in g])).cuda().requires_grad_(True)
-            a = torch.tensor(np.array([w.infl for w in g]), dtype=torch.float64, requires_grad=True)
-            # target from the perturbed coefficients (no gradient)
-            pl.set_infl(np.array([w.extra["infl_target"] for w in g]), per_case=True)
+        for pl, b, a, t in zip(plans, bs, as_, targets):
+            pl.set_infl(t, per_case=True)
             ut, _ = pl.solve(b.detach(), precision="fp32_refined", tol=1e-10)
             u = Solve.apply(pl, b, a, "fp32_refined", 1e-10)
             loss = ((u - ut) ** 2).sum()
             loss.backward()
             total += loss.item()
-            grads.append(a.grad.numpy())
         torch.cuda.synchronize()
-        return total, grads
+        return total, [a.grad.numpy() for a in as_]
 
-    run()
+    run_group()
     t0 = time.perf_counter()
-    loss, grads = run()
+    loss, grads = run_group()
     dt = time.perf_counter() - t0
+    run_sequential()
+    t0 = time.perf_counter()
+    loss_s, grads_s = run_sequential()
+    dts = time.perf_counter() - t0
+    gdiff = max(float(np.max(np.abs(g - h)) / max(np.max(np.abs(h)), 1e-300)) for g, h in zip(grads, grads_s))
     dofs = sum(w.dofs for w in ws)
     return {"workload": "plates64: 64 plates, sizes %s, delta=3h, omega=sum_k a_k (r/delta)^k, "
-                        "target + forward + adjoint FP32-refined solves to 1e-10 and dL/da" %
-                        sorted({w.n[0] for w in ws}),
-            "plates": len(ws), "dofs_total": dofs, "seconds": round(dt, 3),
-            "solves": 3 * len(ws), "loss": loss,
+                        "target + forward + adjoint FP32-refined solves to 1e-10 and dL/da" % sizes,
+            "plates": len(ws), "dofs_total": dofs, "solves": 3 * len(ws),
+            "seconds": round(dt, 3), "mode": "plan group (one launch per pass for all plates)",
+            "seconds_plan_by_plan": round(dts, 3), "speedup_group": round(dts / dt, 2),
+            "loss": loss, "loss_plan_by_plan": loss_s, "grad_max_rel_diff_vs_plan_by_plan": gdiff,
             "plates_per_size": {int(k): len(v) for k, v in sorted(groups.items())}}
 
 

@@ -272,6 +272,40 @@ msb_status msb_plan_set_lengths(msb_plan plan, const int64_t *L);
 msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int lengths,
                              msb_launch_config *best, double *best_ms, void *stream);
 
+/*
+ * Plan groups: several plans of the same dimension (grids of different sizes, each
+ * with its own batch of cases, constraints, bonds and operator) whose products run
+ * as one launch per pass.  Every kernel's grid covers the tiles of all members; each
+ * workgroup finds its member in a table of tile offsets and reads that member's
+ * arguments from device memory.  The group's CG advances every case of every member
+ * in the same launches, with per-case stop flags, and hipGraph capture of blocks of
+ * iterations (graph_block) as for one plan.  For many small grids this replaces one
+ * latency-bound launch chain per grid by one chain for all of them.
+ *
+ * msb_group_create: plans: host [nplans] (1..4096), distinct, same dimension, same
+ *   device.  The group refers to the plans, which must outlive it and may still be
+ *   used on their own (not concurrently with group calls on the same stream).  The
+ *   common launch configuration is the largest member's when every member accepts
+ *   it, else one row / one line per workgroup (msb_group_set_config changes it).
+ * msb_group_apply: f_i = A_i u_i for every member i; u, f: host arrays [nplans] of
+ *   device pointers laid out as for msb_apply.  Synchronises `stream` first (the
+ *   group's argument arrays are rewritten).
+ * msb_group_solve_static: the static solve of msb_solve_static for every member at
+ *   once: b, u: host arrays [nplans] of device pointers; g: null or such an array
+ *   (entries may be null); info: host [total cases], member-major.  MSB_FP64,
+ *   MSB_FP32 or MSB_FP32_REFINED (restarted refinement; reliable_update must be 0).
+ */
+typedef struct msb_group_s *msb_group;
+msb_status msb_group_create(const msb_plan *plans, int nplans, msb_group *out);
+void msb_group_destroy(msb_group group);
+msb_status msb_group_get_config(msb_group group, msb_precision prec, msb_launch_config *cfg);
+msb_status msb_group_set_config(msb_group group, msb_precision prec, const msb_launch_config *cfg);
+msb_status msb_group_apply(msb_group group, msb_precision prec, const void *const *u, void *const *f,
+                           void *stream);
+msb_status msb_group_solve_static(msb_group group, msb_precision prec, const double *const *b,
+                                  const double *const *g, double *const *u, const msb_solve_opts *opts,
+                                  msb_solve_info *info, void *stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *msb_last_error(void);
 

@@ -29,7 +29,8 @@ EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "m
            "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl",
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
            "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
-           "msb_plan_autotune", "msb_last_error")
+           "msb_plan_autotune", "msb_group_create", "msb_group_destroy", "msb_group_get_config",
+           "msb_group_set_config", "msb_group_apply", "msb_group_solve_static", "msb_last_error")
 
 
 class MsbError(RuntimeError):
@@ -103,6 +104,12 @@ def load_library(path: str = LIB_PATH):
         "msb_plan_set_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
         "msb_plan_set_lengths": ([P, P], I),
         "msb_plan_autotune": ([P, I, I, I, ctypes.POINTER(_LaunchConfig), ctypes.POINTER(D), P], I),
+        "msb_group_create": ([P, I, ctypes.POINTER(P)], I),
+        "msb_group_destroy": ([P], None),
+        "msb_group_get_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
+        "msb_group_set_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
+        "msb_group_apply": ([P, I, P, P, P], I),
+        "msb_group_solve_static": ([P, I, P, P, P, ctypes.POINTER(_Opts), P, P], I),
         "msb_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -373,6 +380,86 @@ class Plan:
         return out
 
 
+class PlanGroup:
+    """Several plans of the same dimension run as one launch per pass (msb_group_*).
+
+    The plans stay usable on their own; the group holds references and must be closed
+    (or dropped) before them.  Vectors are passed as lists, one tensor per member, each
+    shaped as for that member's Plan."""
+
+    def __init__(self, plans):
+        lib = load_library()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._ptr.value for p in self.plans])
+        self._ptr = ctypes.c_void_p()
+        _check(lib.msb_group_create(arr, len(self.plans), ctypes.byref(self._ptr)))
+        self.total_cases = sum(p.batch for p in self.plans)
+
+    def close(self):
+        if self._ptr:
+            _lib.msb_group_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_config(self, precision: str = "fp64") -> dict:
+        c = _LaunchConfig()
+        _check(_lib.msb_group_get_config(self._ptr, _PREC[precision], ctypes.byref(c)))
+        return {k: getattr(c, k) for k in CONFIG_KEYS}
+
+    def set_config(self, precision: str = "fp64", **fields):
+        c = _LaunchConfig()
+        _check(_lib.msb_group_get_config(self._ptr, _PREC[precision], ctypes.byref(c)))
+        for k, v in fields.items():
+            if k not in CONFIG_KEYS:
+                raise KeyError("unknown launch configuration field %r" % k)
+            setattr(c, k, int(v))
+        _check(_lib.msb_group_set_config(self._ptr, _PREC[precision], ctypes.byref(c)))
+
+    def _ptrs(self, ts, dtype, name):
+        if len(ts) != len(self.plans):
+            raise ValueError("%s: one tensor per member (%d)" % (name, len(self.plans)))
+        return (ctypes.c_void_p * len(ts))(*[p._vec(t, dtype, "%s[%d]" % (name, i)).value
+                                             for i, (p, t) in enumerate(zip(self.plans, ts))])
+
+    def apply(self, us, outs=None):
+        """f_i = A_i u_i for every member (float64 -> FP64, float32 -> FP32)."""
+        torch = _torch()
+        dt = us[0].dtype
+        prec = FP64 if dt == torch.float64 else FP32
+        if outs is None:
+            outs = [torch.empty_like(u) for u in us]
+        _check(_lib.msb_group_apply(self._ptr, prec, self._ptrs(us, dt, "u"), self._ptrs(outs, dt, "f"), _stream()))
+        return outs
+
+    def solve(self, bs, gs=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
+              inner_tol: float = 0.0, graph_block: int = 0, outs=None, check: bool = True):
+        """Static solves of every member at once; returns (list of u, list of per-member info lists)."""
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty_like(b) for b in bs]
+        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), 0)
+        infos = (_Info * self.total_cases)()
+        gp = None
+        if gs is not None:
+            gp = (ctypes.c_void_p * len(gs))(*[(p._vec(g, torch.float64, "g").value if g is not None else None)
+                                               for p, g in zip(self.plans, gs)])
+        st = _lib.msb_group_solve_static(self._ptr, _PREC[precision], self._ptrs(bs, torch.float64, "b"), gp,
+                                         self._ptrs(outs, torch.float64, "u"), ctypes.byref(opts), infos, _stream())
+        flat = [SolveInfo(i.status, i.outer_iters, i.inner_iters, i.rel_residual, i.seconds) for i in infos]
+        res, k = [], 0
+        for p in self.plans:
+            res.append(flat[k:k + p.batch])
+            k += p.batch
+        if check:
+            _check(st)
+        return outs, res
+
+
 def make_solve_function():
     """torch.autograd.Function for u = K(a)^{-1} b with the hand-written adjoint.
 
@@ -400,3 +487,42 @@ def make_solve_function():
             return None, w, ga.to(ctx.infl_device), None, None
 
     return MSBFMSolve
+
+
+def make_group_solve_function():
+    """torch.autograd.Function for u_i = K_i(a_i)^{-1} b_i over a PlanGroup, with the
+    hand-written adjoint done as one group solve.
+
+    apply(group, precision, tol, b_0..b_{n-1}, a_0..a_{n-1}) -> (u_0, ..., u_{n-1});
+    backward: w_i = K_i^{-1} grad_u_i (all members in one group solve), grad_b_i = w_i,
+    grad_a_i[b, k] = w_i . (A_{i,k} u_i)_F."""
+    torch = _torch()
+
+    class MSBFMGroupSolve(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, group, precision, tol, *tensors):
+            n = len(group.plans)
+            bs, infls = tensors[:n], tensors[n:]
+            for p, a in zip(group.plans, infls):
+                p.set_infl(a.detach().cpu().numpy(), per_case=(a.dim() == 2))
+            us, _ = group.solve([b.contiguous() for b in bs], precision=precision, tol=tol)
+            ctx.group, ctx.precision, ctx.tol = group, precision, tol
+            ctx.per_case = [a.dim() == 2 for a in infls]
+            ctx.devs = [a.device for a in infls]
+            ctx.save_for_backward(*us)
+            return tuple(us)
+
+        @staticmethod
+        def backward(ctx, *grad_us):
+            us = ctx.saved_tensors
+            gus = [torch.zeros_like(u) if g is None else g.contiguous() for u, g in zip(us, grad_us)]
+            ws, _ = ctx.group.solve(gus, precision=ctx.precision, tol=ctx.tol)
+            gas = []
+            for p, u, w, pc, dev in zip(ctx.group.plans, us, ws, ctx.per_case, ctx.devs):
+                ga = torch.from_numpy(p.grad_infl(u, w))
+                if not pc:
+                    ga = ga.sum(0)
+                gas.append(ga.to(dev))
+            return (None, None, None, *ws, *gas)
+
+    return MSBFMGroupSolve

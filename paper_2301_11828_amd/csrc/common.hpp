@@ -197,6 +197,8 @@ msb_launch_config default_config(const msb_plan_s *p, bool fp32);
 msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config &c);
 // Stockham schedules of every axis for one precision with radices <= max_radix (plan.cpp).
 msb_status set_schedules(msb_plan_s *p, bool fp32, int max_radix);
+// The schedule of one axis for a given radix cap, leaving the plan's own unchanged.
+FftSched make_sched(const FftAxis &ax, bool fp32, int max_radix);
 // New padded lengths: rebuild twiddles, spectra and transform workspace (plan.cpp).
 msb_status relayout(msb_plan_s *p, const int64_t *L);
 

@@ -14,6 +14,8 @@
 //
 // Zero padding to L >= N + M makes the cyclic product equal the Toeplitz product
 // on the grid (the kernel's support is +-M), so only the N first outputs are kept.
+#include <cstring>
+
 #include "fft_device.hpp"
 #include "passes.hpp"
 
@@ -71,14 +73,15 @@ __device__ __forceinline__ T2 *team_fft(T2 *a, T2 *b, int S, const FftSched &sc,
 // ---------------------------------------------------------------------------- x-forward
 // F grid rows per block; complex slot s packs real rows sig = 2s and 2s+1
 // (sig = c * nr + r: component c of grid row r0 + r).  Wave mode: each wave owns a.spw consecutive slots.
+// tile: this block's tile of the plan's launch (XCD-remapped); ntiles: the plan's
+// tile count (the grid of a single-plan launch).
 template <typename T, bool BLOCK, int RMAX>
-__global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
+__device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[80];
     const Team<BLOCK> tm;
     const int tpc = (a.rows + a.F - 1) / a.F;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tpc;
     const int r0 = (tile - b * tpc) * a.F;
     const int nr = min(a.F, a.rows - r0);
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) sums[k] = e.case4[(size_t)b * 4 + k];
             } else {
-                const size_t st3 = (size_t)gridDim.x;
+                const size_t st3 = (size_t)ntiles;
                 const double *const parts[4] = {e.rr_prev + (size_t)b * tpc, e.cg3 + (size_t)b * tpc,
                                                 e.cg3 + st3 + (size_t)b * tpc, e.cg3 + 2 * st3 + (size_t)b * tpc};
                 block_sum_partials_k<4>(parts, tpc, sums, red, tid0, ntb);
@@ -242,15 +245,19 @@ __global__ __launch_bounds__(1024) void k_xfwd(PassArgs<T> a, EndArgs<T> e) {
 // block, slot = (line, component); wave mode: one line (d slots) per wave.  Each
 // line is zero-padded to L, transformed, multiplied by the real symmetric d x d
 // spectrum block spec[(comp*nlines + line)*L + k] and transformed back.
+// zpass = false: the 2D y lines of T1 (nlines = H, length Ny); true: the 3D z lines
+// of T2 (nlines = H Ly, length Nz).
 template <typename T, bool BLOCK, int RMAX>
-__global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
-                                                   cplx_t<T> *data, int nlines, int Nl,
-                                                   FftSched sl, const cplx_t<T> *twg) {
+__device__ __forceinline__ void line_body(const PassArgs<T> &a, const EndArgs<T> &e, bool zpass, int tile) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     const Team<BLOCK> tm;
+    T2 *data = zpass ? a.T2 : a.T1;
+    const int nlines = zpass ? a.H * a.Ly : a.H;
+    const int Nl = zpass ? a.Nz : a.Ny;
+    const FftSched &sl = zpass ? a.sz : a.sy;
+    const T2 *twg = zpass ? a.twz : a.twy;
     const int tpc = (nlines + a.Fl - 1) / a.Fl;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tpc;
     const int l0 = (tile - b * tpc) * a.Fl;
     const int nl = min(a.Fl, nlines - l0);
@@ -332,14 +339,13 @@ __global__ __launch_bounds__(1024) void k_line_prod(PassArgs<T> a, EndArgs<T> e,
 // y-forward: T1[b][c][z][kx][y<Ny] -> T2[b][c][kx][ky<Ly][z].  Block = Fl consecutive
 // z of one (b, kx); slot = (z, component); wave mode: one z-line (d slots) per wave.
 template <typename T, bool BLOCK, int RMAX>
-__global__ __launch_bounds__(1024) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
+__device__ __forceinline__ void yfwd_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     const Team<BLOCK> tm;
     const int d = a.d, Ly = a.sy.L;
     const int nzc = (a.Nz + a.Fl - 1) / a.Fl;
     const int tpc = a.H * nzc;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tpc;
     const int rem = tile - b * tpc;
     const int kx = rem / nzc;
@@ -387,14 +393,13 @@ __global__ __launch_bounds__(1024) void k_yfwd(PassArgs<T> a, EndArgs<T> e) {
 
 // y-inverse: T2[b][c][kx][ky][z] -> T1[b][c][z][kx][y<Ny]
 template <typename T, bool BLOCK, int RMAX>
-__global__ __launch_bounds__(1024) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
+__device__ __forceinline__ void yinv_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     const Team<BLOCK> tm;
     const int d = a.d, Ly = a.sy.L;
     const int nzc = (a.Nz + a.Fl - 1) / a.Fl;
     const int tpc = a.H * nzc;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tpc;
     const int rem = tile - b * tpc;
     const int kx = rem / nzc;
@@ -439,13 +444,12 @@ __global__ __launch_bounds__(1024) void k_yinv(PassArgs<T> a, EndArgs<T> e) {
 // correction of those rows, the incomplete-horizon diagonal, the constraint mask and
 // the fused epilogue are applied.
 template <typename T, bool BLOCK, int RMAX>
-__global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
+__device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[80];
     const Team<BLOCK> tm;
     const int tpc = (a.rows + a.F - 1) / a.F;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tpc;
     const int r0 = (tile - b * tpc) * a.F;
     const int nr = min(a.F, a.rows - r0);
@@ -657,13 +661,53 @@ __global__ __launch_bounds__(1024) void k_xinv(PassArgs<T> a, EndArgs<T> e) {
         double v[3] = {acc0, acc1, acc2};
         block_sum<3>(v, red, threadIdx.x, blockDim.x);
         if (threadIdx.x == 0) {
-            const size_t stride = (size_t)gridDim.x;
+            const size_t stride = (size_t)ntiles;
             e.part[tile] = v[0];
             e.part[stride + tile] = v[1];
             e.part[2 * stride + tile] = v[2];
         }
     }
 }
+
+// ---------------------------------------------------------------------------- kernels
+// Single-plan launches: the grid is the plan's tiles, remapped so that the blocks of
+// one XCD take a contiguous tile range.  Group launches: one grid over the tiles of
+// several plans; each block finds its plan in start[] (tile offsets, start[n] = the
+// total) after the same remap and takes that plan's arguments from device arrays.
+__device__ __forceinline__ int group_member(const int *__restrict__ start, int n, int g) {
+    int lo = 0, hi = n - 1;   // largest i with start[i] <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+#define MSB_PLAN_KERNEL(NAME, BODY, ...)                                                              \
+    template <typename T, bool BLOCK, int RMAX>                                                      \
+    __global__ __launch_bounds__(1024) void NAME(PassArgs<T> a, EndArgs<T> e) {                      \
+        const int tile = xcd_tile(blockIdx.x, gridDim.x), ntiles = gridDim.x;                        \
+        (void)ntiles;                                                                                \
+        BODY<T, BLOCK, RMAX>(a, e, __VA_ARGS__);                                                     \
+    }                                                                                                \
+    template <typename T, bool BLOCK, int RMAX>                                                      \
+    __global__ __launch_bounds__(1024) void NAME##_group(const PassArgs<T> *__restrict__ A,          \
+                                                         const EndArgs<T> *__restrict__ E,           \
+                                                         const int *__restrict__ start, int n) {    \
+        const int g = xcd_tile(blockIdx.x, gridDim.x);                                               \
+        const int m = group_member(start, n, g);                                                     \
+        const int tile = g - start[m], ntiles = start[m + 1] - start[m];                             \
+        (void)ntiles;                                                                                \
+        BODY<T, BLOCK, RMAX>(A[m], E[m], __VA_ARGS__);                                               \
+    }
+
+MSB_PLAN_KERNEL(k_xfwd, xfwd_body, tile, ntiles)
+MSB_PLAN_KERNEL(k_line_y, line_body, false, tile)
+MSB_PLAN_KERNEL(k_line_z, line_body, true, tile)
+MSB_PLAN_KERNEL(k_yfwd, yfwd_body, tile)
+MSB_PLAN_KERNEL(k_yinv, yinv_body, tile)
+MSB_PLAN_KERNEL(k_xinv, xinv_body, tile, ntiles)
 
 // ---------------------------------------------------------------------------- host side
 int x_tiles_per_case(const msb_plan_s *p, int F) { return (int)((rows_total(p) + F - 1) / F); }
@@ -764,7 +808,7 @@ template <typename T> static const T *sel(const double *a, const float *b);
 template <> const double *sel<double>(const double *a, const float *) { return a; }
 template <> const float *sel<float>(const double *, const float *b) { return b; }
 
-template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op) {
+template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op, const msb_launch_config *cfg) {
     PassArgs<T> a;
     const bool f32 = sizeof(T) == 4;
     a.d = p->dim;
@@ -778,7 +822,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.Ly = (int)p->L[1];
     a.Lz = (int)p->L[2];
     a.N = (int)p->N;
-    const msb_launch_config &c = p->cfg[f32 ? 1 : 0];
+    const msb_launch_config &c = cfg ? *cfg : p->cfg[f32 ? 1 : 0];
     a.F = c.rows_per_wg;
     a.Fl = c.lines_per_wg;
     a.wave_x = c.team_x;
@@ -788,9 +832,15 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.lpw = c.lines_per_wave;
     a.bthreads = c.threads_x;
     a.bthreads_line = c.threads_line;
-    a.sx = sched_of(p->ax[0], f32);
-    a.sy = sched_of(p->ax[1], f32);
-    a.sz = sched_of(p->ax[2], f32);
+    if (cfg) {   // the given configuration's radix cap, not the plan's
+        a.sx = make_sched(p->ax[0], f32, c.max_radix);
+        a.sy = make_sched(p->ax[1], f32, c.max_radix);
+        a.sz = make_sched(p->ax[2], f32, c.max_radix);
+    } else {
+        a.sx = sched_of(p->ax[0], f32);
+        a.sy = sched_of(p->ax[1], f32);
+        a.sz = sched_of(p->ax[2], f32);
+    }
     a.twx = tw_of<T>(p->ax[0]);
     a.twy = tw_of<T>(p->ax[1]);
     a.twz = tw_of<T>(p->ax[2]);
@@ -820,90 +870,138 @@ template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename T, bool B, int RM>
-static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev, bool wl) {
-    using T2 = cplx_t<T>;
+// Launch geometry of one plan's chain: tiles per case of each pass, threads per block
+// and dynamic LDS of each kernel.
+struct ChainGeom {
+    int tiles_x, tiles_l, tiles_y;   // x passes, line product (2D y / 3D z), 3D y passes
+    int bx, bxi, bl;                 // threads: x-forward, x-inverse, line passes
+    size_t lds_x, lds_l, lds_y;
+};
+
+template <typename T> static ChainGeom chain_geom(const PassArgs<T> &a) {
+    const size_t cb = sizeof(cplx_t<T>);
+    ChainGeom g;
+    g.tiles_x = (a.rows + a.F - 1) / a.F;
+    const int nzc = (a.Nz + a.Fl - 1) / a.Fl;
+    g.tiles_y = a.d == 3 ? a.H * nzc : 0;
+    g.tiles_l = ((a.d == 2 ? a.H : a.H * a.Ly) + a.Fl - 1) / a.Fl;
+    g.bx = a.wave_x ? 64 * ((waves_x(a.d, a.F) + a.spw - 1) / a.spw) : a.bthreads;
+    g.bxi = a.wave_x ? 64 * ((waves_x(a.d, a.F) + a.spw_i - 1) / a.spw_i) : a.bthreads;
+    g.bl = a.wave_l ? 64 * ((a.Fl + a.lpw - 1) / a.lpw) : a.bthreads_line;
+    g.lds_x = lds_x_bytes(a.d, a.F, a.sx.L, cb);
+    g.lds_l = lds_line_bytes(a.d, a.Fl, a.d == 2 ? a.sy.L : a.sz.L, cb);
+    g.lds_y = a.d == 3 ? lds_line_bytes(a.d, a.Fl, a.sy.L, cb) : 0;
+    return g;
+}
+
+template <typename T, bool BX, bool BL, int RM>
+static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, const ChainGeom &g, hipStream_t st,
+                               hipEvent_t *ev, const PassArgs<T> *dA, const EndArgs<T> *dE, const GroupGrid *gg) {
     int evi = 0;
     auto mark = [&]() -> hipError_t { return ev ? hipEventRecord(ev[evi++], st) : hipSuccess; };
-    const int tpc = (a.rows + a.F - 1) / a.F;
-    const size_t lds_x = lds_x_bytes(a.d, a.F, a.sx.L, sizeof(T2));
-    const int bx = B ? a.bthreads : 64 * ((waves_x(a.d, a.F) + a.spw - 1) / a.spw);
-    const int bxi = B ? a.bthreads : 64 * ((waves_x(a.d, a.F) + a.spw_i - 1) / a.spw_i);
-    MSB_HIP(allow_lds(k_xfwd<T, B, RM>, lds_x));
-    MSB_HIP(allow_lds(k_xinv<T, B, RM>, lds_x));
+    MSB_HIP((gg ? allow_lds(k_xfwd_group<T, BX, RM>, g.lds_x) : allow_lds(k_xfwd<T, BX, RM>, g.lds_x)));
+    MSB_HIP((gg ? allow_lds(k_xinv_group<T, BX, RM>, g.lds_x) : allow_lds(k_xinv<T, BX, RM>, g.lds_x)));
     MSB_HIP(mark());
-    hipLaunchKernelGGL((k_xfwd<T, B, RM>), dim3(a.B * tpc), dim3(bx), lds_x, st, a, e);
+    if (gg) hipLaunchKernelGGL((k_xfwd_group<T, BX, RM>), dim3(gg->total_x), dim3(g.bx), g.lds_x, st, dA, dE, gg->start_x, gg->n);
+    else hipLaunchKernelGGL((k_xfwd<T, BX, RM>), dim3(a.B * g.tiles_x), dim3(g.bx), g.lds_x, st, a, e);
     MSB_HIP(mark());
     if (a.d == 2) {
-        const int lpc = (a.H + a.Fl - 1) / a.Fl;
-        const size_t lds = lds_line_bytes(a.d, a.Fl, a.sy.L, sizeof(T2));
-        if (wl) {
-            MSB_HIP(allow_lds(k_line_prod<T, false, RM>, lds));
-            hipLaunchKernelGGL((k_line_prod<T, false, RM>), dim3(a.B * lpc), dim3(64 * ((a.Fl + a.lpw - 1) / a.lpw)), lds, st, a, e, a.T1,
-                               a.H, a.Ny, a.sy, a.twy);
-        } else {
-            MSB_HIP(allow_lds(k_line_prod<T, true, RM>, lds));
-            hipLaunchKernelGGL((k_line_prod<T, true, RM>), dim3(a.B * lpc), dim3(a.bthreads_line), lds, st, a, e, a.T1,
-                               a.H, a.Ny, a.sy, a.twy);
-        }
+        MSB_HIP((gg ? allow_lds(k_line_y_group<T, BL, RM>, g.lds_l) : allow_lds(k_line_y<T, BL, RM>, g.lds_l)));
+        if (gg) hipLaunchKernelGGL((k_line_y_group<T, BL, RM>), dim3(gg->total_l), dim3(g.bl), g.lds_l, st, dA, dE, gg->start_l, gg->n);
+        else hipLaunchKernelGGL((k_line_y<T, BL, RM>), dim3(a.B * g.tiles_l), dim3(g.bl), g.lds_l, st, a, e);
         MSB_HIP(mark());
     } else {
-        const int nzc = (a.Nz + a.Fl - 1) / a.Fl;
-        const size_t lds_y = lds_line_bytes(a.d, a.Fl, a.sy.L, sizeof(T2));
-        const int nlines = a.H * a.Ly;
-        const int lpc = (nlines + a.Fl - 1) / a.Fl;
-        const size_t lds_z = lds_line_bytes(a.d, a.Fl, a.sz.L, sizeof(T2));
-        const int by = wl ? 64 * ((a.Fl + a.lpw - 1) / a.lpw) : a.bthreads_line;
-        if (wl) {
-            MSB_HIP(allow_lds(k_yfwd<T, false, RM>, lds_y));
-            MSB_HIP(allow_lds(k_yinv<T, false, RM>, lds_y));
-            MSB_HIP(allow_lds(k_line_prod<T, false, RM>, lds_z));
-            hipLaunchKernelGGL((k_yfwd<T, false, RM>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
-            MSB_HIP(mark());
-            hipLaunchKernelGGL((k_line_prod<T, false, RM>), dim3(a.B * lpc), dim3(by), lds_z, st, a, e, a.T2,
-                               nlines, a.Nz, a.sz, a.twz);
-            MSB_HIP(mark());
-            hipLaunchKernelGGL((k_yinv<T, false, RM>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
-        } else {
-            MSB_HIP(allow_lds(k_yfwd<T, true, RM>, lds_y));
-            MSB_HIP(allow_lds(k_yinv<T, true, RM>, lds_y));
-            MSB_HIP(allow_lds(k_line_prod<T, true, RM>, lds_z));
-            hipLaunchKernelGGL((k_yfwd<T, true, RM>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
-            MSB_HIP(mark());
-            hipLaunchKernelGGL((k_line_prod<T, true, RM>), dim3(a.B * lpc), dim3(by), lds_z, st, a, e, a.T2,
-                               nlines, a.Nz, a.sz, a.twz);
-            MSB_HIP(mark());
-            hipLaunchKernelGGL((k_yinv<T, true, RM>), dim3(a.B * a.H * nzc), dim3(by), lds_y, st, a, e);
-        }
+        MSB_HIP((gg ? allow_lds(k_yfwd_group<T, BL, RM>, g.lds_y) : allow_lds(k_yfwd<T, BL, RM>, g.lds_y)));
+        MSB_HIP((gg ? allow_lds(k_yinv_group<T, BL, RM>, g.lds_y) : allow_lds(k_yinv<T, BL, RM>, g.lds_y)));
+        MSB_HIP((gg ? allow_lds(k_line_z_group<T, BL, RM>, g.lds_l) : allow_lds(k_line_z<T, BL, RM>, g.lds_l)));
+        if (gg) hipLaunchKernelGGL((k_yfwd_group<T, BL, RM>), dim3(gg->total_y), dim3(g.bl), g.lds_y, st, dA, dE, gg->start_y, gg->n);
+        else hipLaunchKernelGGL((k_yfwd<T, BL, RM>), dim3(a.B * g.tiles_y), dim3(g.bl), g.lds_y, st, a, e);
+        MSB_HIP(mark());
+        if (gg) hipLaunchKernelGGL((k_line_z_group<T, BL, RM>), dim3(gg->total_l), dim3(g.bl), g.lds_l, st, dA, dE, gg->start_l, gg->n);
+        else hipLaunchKernelGGL((k_line_z<T, BL, RM>), dim3(a.B * g.tiles_l), dim3(g.bl), g.lds_l, st, a, e);
+        MSB_HIP(mark());
+        if (gg) hipLaunchKernelGGL((k_yinv_group<T, BL, RM>), dim3(gg->total_y), dim3(g.bl), g.lds_y, st, dA, dE, gg->start_y, gg->n);
+        else hipLaunchKernelGGL((k_yinv<T, BL, RM>), dim3(a.B * g.tiles_y), dim3(g.bl), g.lds_y, st, a, e);
         MSB_HIP(mark());
     }
-    hipLaunchKernelGGL((k_xinv<T, B, RM>), dim3(a.B * tpc), dim3(bxi), lds_x, st, a, e);
+    if (gg) hipLaunchKernelGGL((k_xinv_group<T, BX, RM>), dim3(gg->total_x), dim3(g.bxi), g.lds_x, st, dA, dE, gg->start_x, gg->n);
+    else hipLaunchKernelGGL((k_xinv<T, BX, RM>), dim3(a.B * g.tiles_x), dim3(g.bxi), g.lds_x, st, a, e);
     MSB_HIP(mark());
     MSB_HIP(hipGetLastError());
     return MSB_OK;
 }
 
-template <typename T>
-msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev) {
-    // kernels built with RMAX = 8 only contain the basic radices 2, 3, 4, 5, 8
-    bool composite = false;
-    for (const FftSched *sc : {&a.sx, &a.sy, &a.sz})
+// kernels built with RMAX = 8 only contain the basic radices 2, 3, 4, 5, 8
+static bool needs_composite(const FftSched *const (&scheds)[3]) {
+    for (const FftSched *sc : scheds)
         for (int i = 0; i < sc->np; ++i) {
             const int r = sc->ps[i].R;
-            composite = composite || !(r == 2 || r == 3 || r == 4 || r == 5 || r == 8);
+            if (!(r == 2 || r == 3 || r == 4 || r == 5 || r == 8)) return true;
         }
-    const bool wl = a.wave_l != 0;
-    if (!composite) {
-        if (a.wave_x) return launch_chain<T, false, 8>(a, e, st, ev, wl);
-        return launch_chain<T, true, 8>(a, e, st, ev, wl);
-    }
-    if (a.wave_x) return launch_chain<T, false, 16>(a, e, st, ev, wl);
-    return launch_chain<T, true, 16>(a, e, st, ev, wl);
+    return false;
 }
 
-template PassArgs<double> pass_args<double>(const msb_plan_s *, const DeviceOp &);
-template PassArgs<float> pass_args<float>(const msb_plan_s *, const DeviceOp &);
+template <typename T>
+static msb_status dispatch_chain(const PassArgs<T> &a, const EndArgs<T> &e, const ChainGeom &g, bool composite,
+                                 hipStream_t st, hipEvent_t *ev, const PassArgs<T> *dA, const EndArgs<T> *dE,
+                                 const GroupGrid *gg) {
+    const int sel = (a.wave_x ? 1 : 0) | (a.wave_l ? 2 : 0) | (composite ? 4 : 0);
+    switch (sel) {
+        case 0: return launch_chain<T, true, true, 8>(a, e, g, st, ev, dA, dE, gg);
+        case 1: return launch_chain<T, false, true, 8>(a, e, g, st, ev, dA, dE, gg);
+        case 2: return launch_chain<T, true, false, 8>(a, e, g, st, ev, dA, dE, gg);
+        case 3: return launch_chain<T, false, false, 8>(a, e, g, st, ev, dA, dE, gg);
+        case 4: return launch_chain<T, true, true, 16>(a, e, g, st, ev, dA, dE, gg);
+        case 5: return launch_chain<T, false, true, 16>(a, e, g, st, ev, dA, dE, gg);
+        case 6: return launch_chain<T, true, false, 16>(a, e, g, st, ev, dA, dE, gg);
+        default: return launch_chain<T, false, false, 16>(a, e, g, st, ev, dA, dE, gg);
+    }
+}
+
+template <typename T>
+msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev) {
+    const FftSched *const sc[3] = {&a.sx, &a.sy, &a.sz};
+    return dispatch_chain<T>(a, e, chain_geom(a), needs_composite(sc), st, ev, nullptr, nullptr, nullptr);
+}
+
+template <typename T>
+msb_status launch_group(const PassArgs<T> &a, const GroupGrid &gg, const PassArgs<T> *dA, const EndArgs<T> *dE,
+                        bool composite, hipStream_t st) {
+    ChainGeom g = chain_geom(a);
+    g.lds_x = gg.lds_x;
+    g.lds_l = gg.lds_l;
+    g.lds_y = gg.lds_y;
+    EndArgs<T> e;
+    memset(&e, 0, sizeof(e));
+    return dispatch_chain<T>(a, e, g, composite, st, nullptr, dA, dE, &gg);
+}
+
+void pass_tiles(const msb_plan_s *p, const msb_launch_config &c, bool fp32, int tiles[3], size_t lds[3]) {
+    const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
+    const int d = p->dim;
+    const int H = (int)p->H, Ly = (int)p->L[1], Lz = (int)p->L[2], Nz = (int)p->n[2];
+    tiles[0] = (int)((rows_total(p) + c.rows_per_wg - 1) / c.rows_per_wg);
+    tiles[1] = ((d == 2 ? H : H * Ly) + c.lines_per_wg - 1) / c.lines_per_wg;
+    tiles[2] = d == 3 ? H * ((Nz + c.lines_per_wg - 1) / c.lines_per_wg) : 0;
+    lds[0] = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb);
+    lds[1] = lds_line_bytes(d, c.lines_per_wg, d == 2 ? Ly : Lz, cb);
+    lds[2] = d == 3 ? lds_line_bytes(d, c.lines_per_wg, Ly, cb) : 0;
+}
+
+bool plan_needs_composite(const msb_plan_s *p, bool fp32, int max_radix) {
+    const FftSched s0 = make_sched(p->ax[0], fp32, max_radix), s1 = make_sched(p->ax[1], fp32, max_radix),
+                   s2 = make_sched(p->ax[2], fp32, max_radix);
+    const FftSched *const sc[3] = {&s0, &s1, &s2};
+    return needs_composite(sc);
+}
+
+template PassArgs<double> pass_args<double>(const msb_plan_s *, const DeviceOp &, const msb_launch_config *);
+template PassArgs<float> pass_args<float>(const msb_plan_s *, const DeviceOp &, const msb_launch_config *);
 template msb_status launch_product<double>(const PassArgs<double> &, const EndArgs<double> &, hipStream_t, hipEvent_t *);
 template msb_status launch_product<float>(const PassArgs<float> &, const EndArgs<float> &, hipStream_t, hipEvent_t *);
+template msb_status launch_group<double>(const PassArgs<double> &, const GroupGrid &, const PassArgs<double> *,
+                                         const EndArgs<double> *, bool, hipStream_t);
+template msb_status launch_group<float>(const PassArgs<float> &, const GroupGrid &, const PassArgs<float> *,
+                                        const EndArgs<float> *, bool, hipStream_t);
 
 }  // namespace msb

@@ -102,8 +102,30 @@ msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t
                           hipEvent_t *ev = nullptr);
 inline int n_passes(int dim) { return dim == 2 ? 3 : 5; }
 
+// Arguments of the product passes for plan p and operator op, with the plan's launch
+// configuration for T's precision, or cfg (and its radix cap) when given.
 template <typename T>
-PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op);
+PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op, const msb_launch_config *cfg = nullptr);
+
+// Group launch: one grid per pass over the tiles of n plans that share the dimension
+// and the launch configuration.  start_*: device [n + 1] tile offsets of each pass
+// (start[n] = total); lds_*: the largest member's dynamic LDS per pass.
+struct GroupGrid {
+    int n = 0;
+    const int *start_x = nullptr, *start_l = nullptr, *start_y = nullptr;
+    int total_x = 0, total_l = 0, total_y = 0;
+    size_t lds_x = 0, lds_l = 0, lds_y = 0;
+};
+// a: any member's host arguments (for the common geometry); dA/dE: device arrays of the
+// members' arguments; composite: some member's schedules use a composite radix.
+template <typename T>
+msb_status launch_group(const PassArgs<T> &a, const GroupGrid &gg, const PassArgs<T> *dA, const EndArgs<T> *dE,
+                        bool composite, hipStream_t st);
+// Per-case tile counts of a plan's passes under a configuration: x passes, line
+// product (2D y / 3D z), 3D y passes; and their dynamic LDS bytes.
+void pass_tiles(const msb_plan_s *p, const msb_launch_config &c, bool fp32, int tiles[3], size_t lds[3]);
+// Whether a plan's schedules at radix cap max_radix use a composite radix.
+bool plan_needs_composite(const msb_plan_s *p, bool fp32, int max_radix);
 
 // tiles of the x passes per case (partial-sum slots per case)
 int x_tiles_per_case(const msb_plan_s *p, int F);

@@ -143,6 +143,12 @@ static msb_status axis_schedule(FftAxis &ax, bool fp32, int max_radix) {
     return MSB_OK;
 }
 
+FftSched make_sched(const FftAxis &ax, bool fp32, int max_radix) {
+    FftAxis t = ax;
+    if (axis_schedule(t, fp32, max_radix) != MSB_OK) return sched_of(ax, fp32);
+    return sched_of(t, fp32);
+}
+
 msb_status set_schedules(msb_plan_s *p, bool fp32, int max_radix) {
     for (int a = 0; a < 3; ++a) MSB_TRY(axis_schedule(p->ax[a], fp32, max_radix));
     return MSB_OK;

@@ -154,14 +154,15 @@ __global__ __launch_bounds__(kT) void k_case_sums(const double *part, int n, siz
     if (threadIdx.x == 0) out[blockIdx.x] = scale * s;
 }
 
-// CG start: thresh[b] = tol2 * (r.r)[b]; done[b] = SKIPPED when skip[b] != 0 (or r.r == 0)
-__global__ void k_cg_setup(const double *rr_part, int P, double tol2, double *thresh, int *done,
-                           const int *skip, int *iters, int B) {
+// CG start: thresh[b] = tol2 * (r.r)[b] (tol2_case[b] instead of tol2 when given);
+// done[b] = SKIPPED when skip[b] != 0 (or r.r == 0)
+__global__ void k_cg_setup(const double *rr_part, int P, double tol2, const double *tol2_case, double *thresh,
+                           int *done, const int *skip, int *iters, int B) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     double s = 0.0;
     for (int i = 0; i < P; ++i) s += rr_part[(size_t)b * P + i];
-    thresh[b] = tol2 * s;
+    thresh[b] = (tol2_case ? tol2_case[b] : tol2) * s;
     done[b] = (skip && skip[b]) ? SKIPPED : (s == 0.0 ? CONVERGED : RUNNING);
     iters[b] = 0;
 }
@@ -350,7 +351,8 @@ __global__ void k_save_rr(const double *part_rr, const int *iters, int P, int B,
 template <typename T>
 static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *rhs, T *x, T *r, T *pv,
                            T *q, double tol, int maxit, int graph_block, const int *skip,
-                           const double *prev_rr = nullptr, int *iters_out = nullptr) {
+                           const double *prev_rr = nullptr, int *iters_out = nullptr,
+                           const double *tol2_case = nullptr) {
     const size_t n = w->nvec;
     const int B = p->B, P = w->P;
     Cg<T> c{p, w, st, x, r, pv, q, pass_args<T>(p, p->op), 0, prev_rr};
@@ -361,7 +363,7 @@ static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *
     hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * P), dim3(kT), 0, st, (const T *)r, (const T *)r, w->part_aux,
                        (size_t)p->dim * p->N, P);
     hipLaunchKernelGGL(k_cg_setup, dim3((B + 63) / 64), dim3(64), 0, st, (const double *)w->part_aux, P, tol * tol,
-                       w->thresh, w->done, skip, w->iters, B);
+                       tol2_case, w->thresh, w->done, skip, w->iters, B);
     MSB_HIP(hipGetLastError());
     int it = 0;
     msb_status r0 = run_cg(c, maxit, graph_block, &it);
@@ -582,15 +584,21 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
                 all = all && hskip[c];
             }
             if (all || used >= opts->maxit) break;
-            // inner target: reduce by itol, but not below what the outer tolerance needs
-            double ratio = itol;
-            for (int c = 0; c < B; ++c)
+            // inner target per case: reduce by itol, but not below what the outer
+            // tolerance needs for that case
+            std::vector<double> t2(B, itol * itol);
+            for (int c = 0; c < B; ++c) {
+                double ratio = itol;
                 if (!hskip[c] && rr[c] > 0) ratio = std::max(ratio, 0.5 * opts->tol * std::sqrt(bb[c] / rr[c]));
-            ratio = std::min(ratio, 0.5);
+                ratio = std::min(ratio, 0.5);
+                t2[c] = ratio * ratio;
+            }
+            double *t2d = w->scal + 15 * (size_t)B;
+            MSB_HIP(hipMemcpyAsync(t2d, t2.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
             MSB_HIP(hipMemcpyAsync(skip, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
             hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kT), 0, st, r32, (const double *)r64, n);
-            MSB_TRY(cg_solve<float>(p, w, st, r32, d32, p32, w->v32[3], w->v32[4], ratio, opts->maxit - used, gb,
-                                    skip, (reliable && !first) ? prev : nullptr));
+            MSB_TRY(cg_solve<float>(p, w, st, r32, d32, p32, w->v32[3], w->v32[4], itol, opts->maxit - used, gb,
+                                    skip, (reliable && !first) ? prev : nullptr, nullptr, t2d));
             first = false;
             MSB_TRY(fetch_scal(w, st, 0, B));
             int mx = 0;
@@ -764,4 +772,656 @@ extern "C" msb_status msb_grad_infl(msb_plan p, const double *u, const double *w
     for (int b = 0; b < B; ++b)
         for (int k = 0; k < K; ++k) dL_da[(size_t)b * K + k] = w->h_scal[(size_t)k * B + b];
     return MSB_OK;
+}
+
+// ---------------------------------------------------------------------------- plan groups
+// Several plans (grids of different sizes, each with its own cases) whose products run
+// as one launch per pass: the grid of every kernel covers the tiles of all members, and
+// each block takes its member's arguments from device arrays.  The group CG keeps its
+// per-case state (flags, counts, thresholds, tile partials) in contiguous arrays over
+// all members' cases, so one host check covers the whole group.
+struct msb_group_s {
+    std::vector<msb_plan_s *> m;
+    int dim = 2, n = 0, Btot = 0, device = 0;
+    std::vector<int> case_off;                 // [n + 1]
+    msb_launch_config cfg[2];                  // common launch configuration per precision
+    std::vector<int> start[2][3];              // host tile offsets per pass [n + 1]
+    size_t lds[2][3] = {};
+    bool composite[2] = {};
+    int *dstart[2] = {};                       // device copies [3][n + 1]
+    void *dA[2] = {};                          // device PassArgs<T>[n]
+    void *dE[2] = {};                          // device EndArgs<T>[kSlots][n]
+    double *part_x = nullptr, *part_rr = nullptr;   // [3][tiles], [2][tiles] (largest precision)
+    double *thresh = nullptr, *scal = nullptr;      // [Btot], [16][Btot]
+    int *done = nullptr, *iters = nullptr, *skip = nullptr;   // [Btot]
+    double *h_scal = nullptr;                  // pinned [16][Btot]
+    int *h_int = nullptr;                      // pinned [2][Btot]
+    hipStream_t st = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace msb {
+namespace {
+
+// argument slots of a group: CG iterations (first; even and odd partial-sum parity;
+// the final update-only iteration of each parity) and one-off products
+enum GroupSlot { G_FIRST, G_EVEN, G_ODD, G_UPD_EVEN, G_UPD_ODD, G_LIFT, G_RESID, G_CERT, kSlots };
+
+msb_status group_geometry(msb_group_s *g, int f) {
+    const bool f32 = f == 1;
+    for (int k = 0; k < 3; ++k) g->start[f][k].assign(g->n + 1, 0);
+    g->composite[f] = false;
+    for (int k = 0; k < 3; ++k) g->lds[f][k] = 0;
+    for (int i = 0; i < g->n; ++i) {
+        int t[3];
+        size_t l[3];
+        pass_tiles(g->m[i], g->cfg[f], f32, t, l);
+        for (int k = 0; k < 3; ++k) {
+            g->start[f][k][i + 1] = g->start[f][k][i] + g->m[i]->B * t[k];
+            g->lds[f][k] = std::max(g->lds[f][k], l[k]);
+        }
+        g->composite[f] = g->composite[f] || plan_needs_composite(g->m[i], f32, g->cfg[f].max_radix);
+    }
+    std::vector<int> h;
+    for (int k = 0; k < 3; ++k) h.insert(h.end(), g->start[f][k].begin(), g->start[f][k].end());
+    MSB_HIP(hipMemcpy(g->dstart[f], h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
+    return MSB_OK;
+}
+
+// common configuration: the largest member's, if every member accepts it, else a
+// conservative one (one row / one line per workgroup, whole-workgroup teams)
+msb_status group_config(msb_group_s *g, int f, const msb_launch_config *want) {
+    const bool f32 = f == 1;
+    msb_launch_config c;
+    if (want) {
+        c = *want;
+    } else {
+        int big = 0;
+        for (int i = 1; i < g->n; ++i)
+            if (g->m[i]->N * g->m[i]->B > g->m[big]->N * g->m[big]->B) big = i;
+        c = g->m[big]->cfg[f];
+    }
+    bool ok = true;
+    for (int i = 0; i < g->n && ok; ++i) ok = check_config(g->m[i], f32, c) == MSB_OK;
+    if (!ok && !want) {
+        c = msb_launch_config{1, 0, 1, 1, 256, 1, 0, 1, 256, 8};
+        ok = true;
+        for (int i = 0; i < g->n && ok; ++i) ok = check_config(g->m[i], f32, c) == MSB_OK;
+    }
+    MSB_CHECK(ok, want ? MSB_EINVAL : MSB_EUNSUPPORTED, "launch configuration not valid for every member: %s",
+              msb_last_error());
+    g->cfg[f] = c;
+    return group_geometry(g, f);
+}
+
+template <typename T> constexpr int prec_index() { return sizeof(T) == 4 ? 1 : 0; }
+
+// Upload the members' pass arguments (refreshed: operators, constraints and bonds may
+// have changed since the last call) and the given end arguments into one slot.
+template <typename T> msb_status group_upload_args(msb_group_s *g, std::vector<PassArgs<T>> &A) {
+    const int f = prec_index<T>();
+    A.resize(g->n);
+    for (int i = 0; i < g->n; ++i) A[i] = pass_args<T>(g->m[i], g->m[i]->op, &g->cfg[f]);
+    MSB_HIP(hipMemcpy(g->dA[f], A.data(), sizeof(PassArgs<T>) * g->n, hipMemcpyHostToDevice));
+    return MSB_OK;
+}
+template <typename T> msb_status group_upload_end(msb_group_s *g, int slot, const std::vector<EndArgs<T>> &E) {
+    const int f = prec_index<T>();
+    EndArgs<T> *dst = static_cast<EndArgs<T> *>(g->dE[f]) + (size_t)slot * g->n;
+    MSB_HIP(hipMemcpy(dst, E.data(), sizeof(EndArgs<T>) * g->n, hipMemcpyHostToDevice));
+    return MSB_OK;
+}
+// The members a launch covers: n of them, tile totals per pass; their arguments and
+// tile tables are what the device arrays currently hold (all members, or the active
+// ones during a group CG).
+struct GroupView {
+    int n = 0;
+    int total[3] = {0, 0, 0};
+};
+
+template <typename T> GroupView full_view(const msb_group_s *g) {
+    const int f = prec_index<T>();
+    GroupView v;
+    v.n = g->n;
+    for (int k = 0; k < 3; ++k) v.total[k] = g->start[f][k][g->n];
+    return v;
+}
+
+template <typename T>
+msb_status group_launch(msb_group_s *g, const std::vector<PassArgs<T>> &A, int slot, hipStream_t st,
+                        const GroupView *view = nullptr) {
+    const int f = prec_index<T>();
+    const GroupView v = view ? *view : full_view<T>(g);
+    GroupGrid gg;
+    gg.n = v.n;
+    gg.start_x = g->dstart[f];
+    gg.start_l = g->dstart[f] + (v.n + 1);
+    gg.start_y = g->dstart[f] + 2 * (v.n + 1);
+    gg.total_x = v.total[0];
+    gg.total_l = v.total[1];
+    gg.total_y = v.total[2];
+    gg.lds_x = g->lds[f][0];
+    gg.lds_l = g->lds[f][1];
+    gg.lds_y = g->lds[f][2];
+    const EndArgs<T> *dE = static_cast<const EndArgs<T> *>(g->dE[f]) + (size_t)slot * g->n;
+    return launch_group<T>(A[0], gg, static_cast<const PassArgs<T> *>(g->dA[f]), dE, g->composite[f], st);
+}
+
+// Load the device arrays with the members in `act` (argument arrays, the CG slots'
+// end arguments and the tile tables); returns the matching view.
+template <typename T>
+msb_status group_load_members(msb_group_s *g, const std::vector<int> &act, const std::vector<PassArgs<T>> &A,
+                              const std::vector<std::vector<EndArgs<T>>> &Eslots, GroupView &v) {
+    const int f = prec_index<T>();
+    const int na = (int)act.size();
+    std::vector<PassArgs<T>> Aa(na);
+    std::vector<int> st3(3 * (na + 1), 0);
+    v.n = na;
+    for (int k = 0; k < 3; ++k) v.total[k] = 0;
+    for (int j = 0; j < na; ++j) {
+        const int i = act[j];
+        Aa[j] = A[i];
+        for (int k = 0; k < 3; ++k) {
+            st3[k * (na + 1) + j + 1] = st3[k * (na + 1) + j] + (g->start[f][k][i + 1] - g->start[f][k][i]);
+        }
+    }
+    for (int k = 0; k < 3; ++k) v.total[k] = st3[k * (na + 1) + na];
+    MSB_HIP(hipMemcpy(g->dA[f], Aa.data(), sizeof(PassArgs<T>) * na, hipMemcpyHostToDevice));
+    MSB_HIP(hipMemcpy(g->dstart[f], st3.data(), sizeof(int) * st3.size(), hipMemcpyHostToDevice));
+    for (size_t slot = 0; slot < Eslots.size(); ++slot) {
+        std::vector<EndArgs<T>> Ea(na);
+        for (int j = 0; j < na; ++j) Ea[j] = Eslots[slot][act[j]];
+        EndArgs<T> *dst = static_cast<EndArgs<T> *>(g->dE[f]) + slot * g->n;
+        MSB_HIP(hipMemcpy(dst, Ea.data(), sizeof(EndArgs<T>) * na, hipMemcpyHostToDevice));
+    }
+    return MSB_OK;
+}
+
+// pending kernels of earlier calls may still read the argument arrays
+msb_status group_quiesce(msb_group_s *g, hipStream_t user) {
+    MSB_HIP(hipStreamSynchronize(user));
+    MSB_HIP(hipStreamSynchronize(g->st));
+    return MSB_OK;
+}
+
+// Group CG on K d_i = rhs_i for every member, x0 = 0 (restart), like cg_solve.
+template <typename T>
+msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std::vector<const T *> &rhs,
+                    const std::vector<T *> &x, const std::vector<T *> &r, const std::vector<T *> &pv,
+                    const std::vector<T *> &q, double tol, int maxit, int graph_block, const int *skip,
+                    const double *tol2_case = nullptr) {
+    const int f = prec_index<T>();
+    hipStream_t st = g->st;
+    for (int i = 0; i < g->n; ++i) {
+        msb_plan_s *p = g->m[i];
+        SolverWs *w = nullptr;
+        MSB_TRY(get_ws(p, w));
+        const size_t nv = w->nvec;
+        hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kT), 0, st, x[i], nv, T(0));
+        hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kT), 0, st, pv[i], nv, T(0));
+        hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(nv)), dim3(kT), 0, st, r[i], rhs[i], nv);
+        hipLaunchKernelGGL(k_dot_parts<T>, dim3(p->B * w->P), dim3(kT), 0, st, (const T *)r[i], (const T *)r[i],
+                           w->part_aux, (size_t)p->dim * p->N, w->P);
+        const int co = g->case_off[i];
+        hipLaunchKernelGGL(k_cg_setup, dim3((p->B + 63) / 64), dim3(64), 0, st, (const double *)w->part_aux, w->P,
+                           tol * tol, tol2_case ? tol2_case + co : nullptr, g->thresh + co, g->done + co,
+                           skip ? skip + co : nullptr, g->iters + co, p->B);
+    }
+    MSB_HIP(hipGetLastError());
+    // end arguments of the iteration slots (no kernel of an earlier solve still reads them)
+    MSB_HIP(hipStreamSynchronize(st));
+    std::vector<std::vector<EndArgs<T>>> Eslots(G_UPD_ODD + 1, std::vector<EndArgs<T>>(g->n));
+    for (int slot = G_FIRST; slot <= G_UPD_ODD; ++slot) {
+        const int parity = (slot == G_ODD || slot == G_UPD_ODD) ? 1 : 0;
+        for (int i = 0; i < g->n; ++i) {
+            const int sx = g->start[f][0][i], nt = g->start[f][0][i + 1] - sx;
+            const int co = g->case_off[i];
+            EndArgs<T> e = end_args<T>();
+            e.pro = PRO_CG_P;
+            e.pio = pv[i];
+            e.cx = x[i];
+            e.cr = r[i];
+            e.cq = q[i];
+            e.cg3 = g->part_x + 3 * (size_t)sx;
+            e.rr_prev = g->part_rr + 2 * (size_t)sx + (size_t)((parity + 1) & 1) * nt;
+            e.rr_out = g->part_rr + 2 * (size_t)sx + (size_t)parity * nt;
+            e.first = slot == G_FIRST;
+            e.update_only = slot == G_UPD_EVEN || slot == G_UPD_ODD;
+            e.iters = g->iters + co;
+            e.case_done = g->done + co;
+            e.done_rw = g->done + co;
+            e.thresh = g->thresh + co;
+            e.epi = EPI_CG_Q;
+            e.uin = pv[i];
+            e.out = q[i];
+            e.rhs = r[i];
+            e.part = g->part_x + 3 * (size_t)sx;
+            Eslots[slot][i] = e;
+        }
+    }
+    // work list: members with a running case (converged or skipped members leave the
+    // launches at the next check of the flags, so their tiles cost nothing afterwards)
+    std::vector<int> act(g->n);
+    for (int i = 0; i < g->n; ++i) act[i] = i;
+    GroupView view;
+    MSB_TRY(group_load_members<T>(g, act, A, Eslots, view));
+    auto iteration = [&](int it, bool upd) {
+        const int slot = upd ? ((it & 1) ? G_UPD_ODD : G_UPD_EVEN) : (it == 0 ? G_FIRST : ((it & 1) ? G_ODD : G_EVEN));
+        return group_launch<T>(g, A, slot, st, &view);
+    };
+    MSB_TRY(iteration(0, false));
+    int it = 1;
+    const int poll = graph_block > 0 ? graph_block : kPollIterations;
+    const int block = poll + (poll & 1);   // even: keeps the partial-sum parity of replays fixed
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    msb_status s = MSB_OK;
+    while (it < maxit && s == MSB_OK) {
+        MSB_HIP(hipMemcpyAsync(g->h_int, g->done, sizeof(int) * g->Btot, hipMemcpyDeviceToHost, st));
+        MSB_HIP(hipStreamSynchronize(st));
+        std::vector<int> now;
+        for (int i = 0; i < g->n; ++i) {
+            bool running = false;
+            for (int c = g->case_off[i]; c < g->case_off[i + 1]; ++c) running = running || g->h_int[c] == RUNNING;
+            if (running) now.push_back(i);
+        }
+        if (now.empty()) break;
+        if (now != act) {   // the stream is idle here (synchronised above)
+            act = now;
+            MSB_TRY(group_load_members<T>(g, act, A, Eslots, view));
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+        }
+        const int k = std::min(block, maxit - it);
+        if (graph_block > 0 && k == block) {
+            if (!exec) {
+                MSB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                for (int j = 0; j < block && s == MSB_OK; ++j) s = iteration(it + j, false);
+                hipError_t e1 = hipStreamEndCapture(st, &graph);
+                if (s != MSB_OK) break;
+                MSB_HIP(e1);
+                MSB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            }
+            MSB_HIP(hipGraphLaunch(exec, st));
+        } else {
+            for (int j = 0; j < k && s == MSB_OK; ++j) s = iteration(it + j, false);
+        }
+        it += k;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (s == MSB_OK) s = iteration(it, true);   // iteration cap: pending update of running cases
+    // all members again for the next launches
+    MSB_HIP(hipStreamSynchronize(st));
+    std::vector<int> all(g->n);
+    for (int i = 0; i < g->n; ++i) all[i] = i;
+    if (s == MSB_OK) s = group_load_members<T>(g, all, A, Eslots, view);
+    return s;
+}
+
+// per-case ||rhs_i + A x_i||^2 on free DOFs into g->scal[slot*Btot + case], residual into out_i
+msb_status group_residual(msb_group_s *g, const std::vector<PassArgs<double>> &A, int argslot,
+                          const std::vector<double *> &x, const std::vector<const double *> &rhs,
+                          const std::vector<double *> &out, int slot) {
+    std::vector<EndArgs<double>> E(g->n);
+    for (int i = 0; i < g->n; ++i) {
+        EndArgs<double> e = end_args<double>();
+        e.pro = PRO_NONE;
+        e.pio = x[i];
+        e.uin = x[i];
+        e.epi = EPI_RESID;
+        e.rhs = rhs[i];
+        e.out = out[i];
+        e.part = g->part_x + 3 * (size_t)g->start[0][0][i];
+        E[i] = e;
+    }
+    MSB_TRY(group_quiesce(g, g->st));
+    MSB_TRY(group_upload_end<double>(g, argslot, E));
+    MSB_TRY(group_launch<double>(g, A, argslot, g->st));
+    for (int i = 0; i < g->n; ++i) {
+        const int tpc = (g->start[0][0][i + 1] - g->start[0][0][i]) / g->m[i]->B;
+        hipLaunchKernelGGL(k_case_sums, dim3(g->m[i]->B), dim3(kT), 0, g->st,
+                           (const double *)(g->part_x + 3 * (size_t)g->start[0][0][i]), tpc, (size_t)tpc,
+                           g->scal + (size_t)slot * g->Btot + g->case_off[i], 1.0);
+    }
+    MSB_HIP(hipGetLastError());
+    return MSB_OK;
+}
+
+msb_status group_fetch(msb_group_s *g, int nslots) {
+    MSB_HIP(hipMemcpyAsync(g->h_scal, g->scal, sizeof(double) * nslots * g->Btot, hipMemcpyDeviceToHost, g->st));
+    MSB_HIP(hipMemcpyAsync(g->h_int, g->done, sizeof(int) * g->Btot, hipMemcpyDeviceToHost, g->st));
+    MSB_HIP(hipMemcpyAsync(g->h_int + g->Btot, g->iters, sizeof(int) * g->Btot, hipMemcpyDeviceToHost, g->st));
+    MSB_HIP(hipStreamSynchronize(g->st));
+    return MSB_OK;
+}
+
+void group_free(msb_group_s *g) {
+    for (int f = 0; f < 2; ++f) {
+        if (g->dstart[f]) (void)hipFree(g->dstart[f]);
+        if (g->dA[f]) (void)hipFree(g->dA[f]);
+        if (g->dE[f]) (void)hipFree(g->dE[f]);
+    }
+    void *b[] = {g->part_x, g->part_rr, g->thresh, g->scal, g->done, g->iters, g->skip};
+    for (void *x : b)
+        if (x) (void)hipFree(x);
+    if (g->h_scal) (void)hipHostFree(g->h_scal);
+    if (g->h_int) (void)hipHostFree(g->h_int);
+    if (g->ev_in) (void)hipEventDestroy(g->ev_in);
+    if (g->ev_out) (void)hipEventDestroy(g->ev_out);
+    if (g->st) (void)hipStreamDestroy(g->st);
+    delete g;
+}
+
+}  // namespace
+}  // namespace msb
+
+extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_group *out) {
+    MSB_CHECK(out, MSB_EINVAL, "null output pointer");
+    *out = nullptr;
+    MSB_CHECK(plans && nplans >= 1 && nplans <= 4096, MSB_EINVAL, "need 1..4096 plans");
+    int dev = -1;
+    MSB_HIP(hipGetDevice(&dev));
+    for (int i = 0; i < nplans; ++i) {
+        MSB_CHECK(plans[i], MSB_EINVAL, "plan %d is null", i);
+        MSB_CHECK(plans[i]->dim == plans[0]->dim, MSB_EINVAL, "plan %d: every member must have the same dimension", i);
+        MSB_CHECK(plans[i]->device == dev, MSB_EINVAL, "plan %d was created on another device", i);
+        for (int j = 0; j < i; ++j) MSB_CHECK(plans[j] != plans[i], MSB_EINVAL, "plan %d is listed twice", i);
+    }
+    msb_group_s *g = new (std::nothrow) msb_group_s();
+    MSB_CHECK(g, MSB_ENOMEM, "host allocation failed");
+    g->m.assign(plans, plans + nplans);
+    g->n = nplans;
+    g->dim = plans[0]->dim;
+    g->device = dev;
+    g->case_off.assign(nplans + 1, 0);
+    for (int i = 0; i < nplans; ++i) g->case_off[i + 1] = g->case_off[i] + plans[i]->B;
+    g->Btot = g->case_off[nplans];
+    auto fail = [&](msb_status s) {
+        group_free(g);
+        return s;
+    };
+    const size_t nb = (size_t)g->Btot;
+    size_t tiles_max = 0;
+    for (int f = 0; f < 2; ++f) {
+        if (hipMalloc(&g->dstart[f], sizeof(int) * 3 * (nplans + 1)) != hipSuccess) return fail(MSB_ENOMEM);
+        const size_t pa = f ? sizeof(PassArgs<float>) : sizeof(PassArgs<double>);
+        const size_t ea = f ? sizeof(EndArgs<float>) : sizeof(EndArgs<double>);
+        if (hipMalloc(&g->dA[f], pa * nplans) != hipSuccess) return fail(MSB_ENOMEM);
+        if (hipMalloc(&g->dE[f], ea * kSlots * nplans) != hipSuccess) return fail(MSB_ENOMEM);
+        msb_status s = group_config(g, f, nullptr);
+        if (s != MSB_OK) return fail(s);
+    }
+    // tile partials sized for any configuration: at most one x tile per grid row
+    for (int i = 0; i < nplans; ++i) tiles_max += (size_t)plans[i]->B * rows_total(plans[i]);
+    if (hipMalloc(&g->part_x, sizeof(double) * 3 * tiles_max) != hipSuccess ||
+        hipMalloc(&g->part_rr, sizeof(double) * 2 * tiles_max) != hipSuccess ||
+        hipMalloc(&g->thresh, sizeof(double) * nb) != hipSuccess ||
+        hipMalloc(&g->scal, sizeof(double) * 16 * nb) != hipSuccess ||
+        hipMalloc(&g->done, sizeof(int) * nb) != hipSuccess || hipMalloc(&g->iters, sizeof(int) * nb) != hipSuccess ||
+        hipMalloc(&g->skip, sizeof(int) * nb) != hipSuccess ||
+        hipHostMalloc(&g->h_scal, sizeof(double) * 16 * nb) != hipSuccess ||
+        hipHostMalloc(&g->h_int, sizeof(int) * 2 * nb) != hipSuccess ||
+        hipStreamCreateWithFlags(&g->st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming) != hipSuccess) {
+        set_error("group allocation failed");
+        return fail(MSB_ENOMEM);
+    }
+    *out = g;
+    return MSB_OK;
+}
+
+extern "C" void msb_group_destroy(msb_group g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    group_free(g);
+}
+
+extern "C" msb_status msb_group_get_config(msb_group g, msb_precision prec, msb_launch_config *cfg) {
+    MSB_CHECK(g && cfg, MSB_EINVAL, "null argument");
+    MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
+    *cfg = g->cfg[prec == MSB_FP32 ? 1 : 0];
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_group_set_config(msb_group g, msb_precision prec, const msb_launch_config *cfg) {
+    MSB_CHECK(g && cfg, MSB_EINVAL, "null argument");
+    MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
+    const int f = prec == MSB_FP32 ? 1 : 0;
+    const msb_launch_config keep = g->cfg[f];
+    MSB_HIP(hipDeviceSynchronize());
+    msb_status s = group_config(g, f, cfg);
+    if (s != MSB_OK) {
+        g->cfg[f] = keep;
+        (void)group_geometry(g, f);
+    }
+    return s;
+}
+
+template <typename T>
+static msb_status group_apply_t(msb_group_s *g, const void *const *u, void *const *f, hipStream_t user) {
+    for (int i = 0; i < g->n; ++i) {
+        MSB_CHECK(u[i] && f[i] && u[i] != f[i], MSB_EINVAL, "member %d: null or aliased vectors", i);
+    }
+    MSB_TRY(group_quiesce(g, user));
+    std::vector<PassArgs<T>> A;
+    MSB_TRY(group_upload_args<T>(g, A));
+    std::vector<EndArgs<T>> E(g->n);
+    for (int i = 0; i < g->n; ++i) {
+        EndArgs<T> e = end_args<T>();
+        e.pro = PRO_NONE;
+        e.pio = (T *)u[i];
+        e.uin = (const T *)u[i];
+        e.epi = EPI_APPLY;
+        e.out = (T *)f[i];
+        E[i] = e;
+    }
+    MSB_TRY(group_upload_end<T>(g, G_LIFT, E));
+    return group_launch<T>(g, A, G_LIFT, user);
+}
+
+extern "C" msb_status msb_group_apply(msb_group g, msb_precision prec, const void *const *u, void *const *f,
+                                      void *stream) {
+    MSB_CHECK(g && u && f, MSB_EINVAL, "null argument");
+    int dev = -1;
+    MSB_HIP(hipGetDevice(&dev));
+    MSB_CHECK(dev == g->device, MSB_EINVAL, "group was created on device %d, current is %d", g->device, dev);
+    if (prec == MSB_FP64) return group_apply_t<double>(g, u, f, (hipStream_t)stream);
+    MSB_CHECK(prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
+    return group_apply_t<float>(g, u, f, (hipStream_t)stream);
+}
+
+extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, const double *const *b,
+                                             const double *const *gv, double *const *u, const msb_solve_opts *opts,
+                                             msb_solve_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    MSB_CHECK(g && b && u && opts && info, MSB_EINVAL, "null argument");
+    MSB_CHECK(opts->tol > 0 && opts->tol < 1 && opts->maxit > 0, MSB_EINVAL, "need 0 < tol < 1 and maxit > 0");
+    MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32 || prec == MSB_FP32_REFINED, MSB_EINVAL, "bad precision");
+    MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
+    MSB_CHECK(opts->reliable_update == 0, MSB_EUNSUPPORTED, "groups refine by restarts only (reliable_update = 0)");
+    int dev = -1;
+    MSB_HIP(hipGetDevice(&dev));
+    MSB_CHECK(dev == g->device, MSB_EINVAL, "group was created on device %d, current is %d", g->device, dev);
+    const int n = g->n, Bt = g->Btot;
+    for (int i = 0; i < n; ++i)
+        MSB_CHECK(b[i] && u[i] && b[i] != u[i] && (!gv || gv[i] != u[i]), MSB_EINVAL,
+                  "member %d: null or aliased vectors", i);
+    hipStream_t user = (hipStream_t)stream;
+    MSB_TRY(group_quiesce(g, user));
+    hipStream_t st = g->st;
+    std::vector<SolverWs *> w(n);
+    for (int i = 0; i < n; ++i) MSB_TRY(get_ws(g->m[i], w[i]));
+    std::vector<PassArgs<double>> A64;
+    std::vector<PassArgs<float>> A32;
+    MSB_TRY(group_upload_args<double>(g, A64));
+    if (prec != MSB_FP64) MSB_TRY(group_upload_args<float>(g, A32));
+    const int gb = opts->graph_block;
+
+    // lifted right-hand sides b'_i (per member, as msb_solve_static) and their norms
+    std::vector<double *> bp(n), tmp(n);
+    for (int i = 0; i < n; ++i) {
+        msb_plan_s *p = g->m[i];
+        const size_t nv = w[i]->nvec, dn = (size_t)p->dim * p->N;
+        bp[i] = w[i]->v64[0];
+        tmp[i] = w[i]->v64[1];
+        const double *gi = gv ? gv[i] : nullptr;
+        if (gi && p->fixed) {
+            hipLaunchKernelGGL(k_mask_copy<double>, dim3(grid_for(nv)), dim3(kT), 0, st, tmp[i], gi, (const uint8_t *)p->fixed, nv, dn, 1);
+            EndArgs<double> e = end_args<double>();
+            e.epi = EPI_RESID;
+            e.rhs = b[i];
+            e.out = bp[i];
+            MSB_TRY(product<double>(p, p->op, tmp[i], e, st));
+        } else {
+            hipLaunchKernelGGL(k_mask_copy<double>, dim3(grid_for(nv)), dim3(kT), 0, st, bp[i], b[i], (const uint8_t *)p->fixed, nv, dn, 0);
+        }
+        hipLaunchKernelGGL(k_dot_parts<double>, dim3(p->B * w[i]->P), dim3(kT), 0, st, (const double *)bp[i],
+                           (const double *)bp[i], w[i]->part_aux, dn, w[i]->P);
+        hipLaunchKernelGGL(k_case_sums, dim3(p->B), dim3(kT), 0, st, (const double *)w[i]->part_aux, w[i]->P,
+                           (size_t)w[i]->P, g->scal + g->case_off[i], 1.0);
+    }
+    MSB_HIP(hipGetLastError());
+    MSB_TRY(group_fetch(g, 1));
+    std::vector<double> bb(g->h_scal, g->h_scal + Bt);
+    for (int c = 0; c < Bt; ++c)
+        MSB_CHECK(std::isfinite(bb[c]), MSB_EINVAL, "case %d: right-hand side (or lift) is not finite", c);
+
+    std::vector<int> outer(Bt, 0), inner(Bt, 0), fl(Bt, RUNNING);
+    std::vector<double> rel(Bt, 0.0);
+    std::vector<const double *> cbp(bp.begin(), bp.end());
+    if (prec == MSB_FP64) {
+        std::vector<double *> r(n), pv(n), q(n), x(u, u + n);
+        for (int i = 0; i < n; ++i) r[i] = w[i]->v64[2], pv[i] = w[i]->v64[3], q[i] = w[i]->v64[4];
+        MSB_TRY(group_cg<double>(g, A64, cbp, x, r, pv, q, opts->tol, opts->maxit, gb, nullptr));
+        MSB_TRY(group_fetch(g, 1));
+        for (int c = 0; c < Bt; ++c) {
+            fl[c] = g->h_int[c] == CAPPED ? RUNNING : g->h_int[c];
+            inner[c] = g->h_int[Bt + c];
+            outer[c] = 1;
+        }
+    } else if (prec == MSB_FP32) {
+        std::vector<const float *> b32(n);
+        std::vector<float *> x32(n), r(n), pv(n), q(n);
+        for (int i = 0; i < n; ++i) {
+            const size_t nv = w[i]->nvec;
+            hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(nv)), dim3(kT), 0, st, w[i]->v32[0], (const double *)bp[i], nv);
+            b32[i] = w[i]->v32[0];
+            x32[i] = w[i]->v32[1], r[i] = w[i]->v32[2], pv[i] = w[i]->v32[3], q[i] = w[i]->v32[4];
+        }
+        MSB_TRY(group_cg<float>(g, A32, b32, x32, r, pv, q, opts->tol, opts->maxit, gb, nullptr));
+        for (int i = 0; i < n; ++i)
+            hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for(w[i]->nvec)), dim3(kT), 0, st, u[i], (const float *)x32[i], w[i]->nvec);
+        MSB_TRY(group_fetch(g, 1));
+        for (int c = 0; c < Bt; ++c) {
+            fl[c] = g->h_int[c] == CAPPED ? RUNNING : g->h_int[c];
+            inner[c] = g->h_int[Bt + c];
+            outer[c] = 1;
+        }
+    } else {
+        // restarted iterative refinement, as msb_solve_static: FP32 CG on K d = r to a
+        // reduction of inner_tol, u += d in FP64, r = b' - K u with the FP64 product
+        const double itol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
+        std::vector<const float *> r32c(n);
+        std::vector<float *> r32(n), d32(n), p32(n), q32(n), rr32(n);
+        std::vector<double *> r64(n), uu(u, u + n);
+        for (int i = 0; i < n; ++i) {
+            const size_t nv = w[i]->nvec;
+            r32[i] = w[i]->v32[0], d32[i] = w[i]->v32[1], p32[i] = w[i]->v32[2], rr32[i] = w[i]->v32[3], q32[i] = w[i]->v32[4];
+            r32c[i] = r32[i];
+            r64[i] = w[i]->v64[2];
+            hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(nv)), dim3(kT), 0, st, u[i], nv, 0.0);
+            hipLaunchKernelGGL((k_cast<double, double>), dim3(grid_for(nv)), dim3(kT), 0, st, r64[i], (const double *)bp[i], nv);
+        }
+        std::vector<double> rr(bb), best(bb);
+        std::vector<int> stall(Bt, 0), hskip(Bt, 0);
+        int used = 0;
+        for (int j = 0; j < 1000; ++j) {
+            bool all = true;
+            for (int c = 0; c < Bt; ++c) {
+                rel[c] = bb[c] > 0 ? std::sqrt(rr[c] / bb[c]) : 0.0;
+                if (!std::isfinite(rel[c])) fl[c] = NONFINITE;
+                if (fl[c] == RUNNING && rel[c] <= opts->tol) fl[c] = CONVERGED;
+                hskip[c] = fl[c] != RUNNING;
+                all = all && hskip[c];
+            }
+            if (all || used >= opts->maxit) break;
+            std::vector<double> t2(Bt, itol * itol);   // per-case inner target, as for one plan
+            for (int c = 0; c < Bt; ++c) {
+                double ratio = itol;
+                if (!hskip[c] && rr[c] > 0) ratio = std::max(ratio, 0.5 * opts->tol * std::sqrt(bb[c] / rr[c]));
+                ratio = std::min(ratio, 0.5);
+                t2[c] = ratio * ratio;
+            }
+            double *t2d = g->scal + 15 * (size_t)Bt;
+            MSB_HIP(hipMemcpyAsync(t2d, t2.data(), sizeof(double) * Bt, hipMemcpyHostToDevice, st));
+            MSB_HIP(hipMemcpyAsync(g->skip, hskip.data(), sizeof(int) * Bt, hipMemcpyHostToDevice, st));
+            for (int i = 0; i < n; ++i)
+                hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(w[i]->nvec)), dim3(kT), 0, st, r32[i], (const double *)r64[i], w[i]->nvec);
+            MSB_TRY(group_cg<float>(g, A32, r32c, d32, rr32, p32, q32, itol, opts->maxit - used, gb, g->skip, t2d));
+            MSB_TRY(group_fetch(g, 0));
+            int mx = 0;
+            for (int c = 0; c < Bt; ++c) {
+                if (!hskip[c]) {
+                    inner[c] += g->h_int[Bt + c];
+                    outer[c] += 1;
+                    if (g->h_int[c] == BREAKDOWN || g->h_int[c] == NONFINITE) fl[c] = g->h_int[c];
+                }
+                mx = std::max(mx, g->h_int[Bt + c]);
+            }
+            used += mx;
+            for (int i = 0; i < n; ++i)
+                hipLaunchKernelGGL(k_add_to<float>, dim3(grid_for(w[i]->nvec)), dim3(kT), 0, st, u[i], (const float *)d32[i], w[i]->nvec);
+            MSB_TRY(group_residual(g, A64, G_RESID, uu, cbp, r64, 0));
+            MSB_TRY(group_fetch(g, 1));
+            for (int c = 0; c < Bt; ++c) {
+                if (hskip[c]) continue;
+                rr[c] = g->h_scal[c];
+                if (rr[c] < 0.81 * best[c]) {
+                    best[c] = rr[c];
+                    stall[c] = 0;
+                } else if (++stall[c] >= 3 && fl[c] == RUNNING) {
+                    fl[c] = -1;
+                }
+            }
+        }
+        for (int c = 0; c < Bt; ++c)
+            if (fl[c] == -1) fl[c] = RUNNING;
+    }
+
+    // certify: FP64 residual of the final u on free DOFs; u_C = g
+    std::vector<double *> uu(u, u + n);
+    MSB_TRY(group_residual(g, A64, G_CERT, uu, cbp, tmp, 0));
+    for (int i = 0; i < n; ++i) {
+        msb_plan_s *p = g->m[i];
+        if (p->fixed)
+            hipLaunchKernelGGL(k_set_fixed<double>, dim3(grid_for(w[i]->nvec)), dim3(kT), 0, st, u[i],
+                               gv ? gv[i] : nullptr, (const uint8_t *)p->fixed, w[i]->nvec, (size_t)p->dim * p->N);
+    }
+    MSB_TRY(group_fetch(g, 1));
+    MSB_HIP(hipEventRecord(g->ev_out, st));
+    MSB_HIP(hipStreamWaitEvent(user, g->ev_out, 0));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    msb_status result = MSB_OK;
+    for (int c = 0; c < Bt; ++c) {
+        rel[c] = bb[c] > 0 ? std::sqrt(g->h_scal[c] / bb[c]) : 0.0;
+        msb_status s = flag_status(fl[c]);
+        if (s == MSB_OK && !(rel[c] <= opts->tol * 10)) s = MSB_ENOCONV;
+        if (fl[c] == RUNNING) s = rel[c] <= opts->tol ? MSB_OK : MSB_ENOCONV;
+        info[c].status = s;
+        info[c].outer_iters = outer[c];
+        info[c].inner_iters = inner[c];
+        info[c].rel_residual = rel[c];
+        info[c].seconds = secs;
+        if (s != MSB_OK && result == MSB_OK) {
+            result = s;
+            set_error("case %d of the group: %s (relative residual %.3e after %d iterations)", c,
+                      s == MSB_ENOTSPD ? "CG breakdown: operator not positive definite on the free DOFs"
+                                       : "no convergence", rel[c], inner[c]);
+        }
+    }
+    return result;
 }

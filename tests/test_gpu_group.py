@@ -1,0 +1,152 @@
+"""Plan groups: the products and static solves of several plans of different sizes in
+one launch per pass, against each member's own product and the oracle (eq. (mat:f1)
+bond sums, dense Cholesky of eq. (mat:e2))."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2301_11828_amd import workloads as W
+from helpers import gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-6
+
+
+def _members_2d():
+    return [W.small(2, (37, 30), 3, seed=101, fixed="left", crack=True, batch=2),
+            W.small(2, (20, 17), 3, seed=102, fixed="all", batch=1, infl=(0.4, 0.3, 0.2)),
+            W.small(2, (64, 50), 3, seed=103, fixed="mixed", batch=3),
+            W.small(2, (9, 41), 3, seed=104, fixed="all", batch=1)]
+
+
+def _members_3d():
+    return [W.small(3, (13, 11, 9), 2, seed=105, fixed="bottom", batch=2),
+            W.small(3, (7, 8, 6), 2, seed=106, fixed="all", batch=1),
+            W.small(3, (16, 12, 10), 2, seed=107, fixed="bottom", batch=1)]
+
+
+def _oracle_apply(w, u):
+    p = oracle_problem(w)
+    br = oracle_bonds(w)
+    return np.stack([O.apply(p, u[c], w.fixed, br) for c in range(u.shape[0])])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_group_apply_matches_members_and_oracle(prec, dim):
+    import torch
+    import paper_2301_11828_amd as msb
+    ws = _members_2d() if dim == 2 else _members_3d()
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    cfg = grp.get_config(prec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    us = [to_dev(w.b, dt) for w in ws]
+    outs = [torch.full_like(u, float("nan")) for u in us]
+    fs = [f.double().cpu().numpy() for f in grp.apply(us, outs)]
+    for i, (w, p) in enumerate(zip(ws, plans)):
+        p.set_config(prec, **cfg)   # the member alone, same configuration: identical arithmetic
+        own = p.apply(us[i], torch.full_like(us[i], float("nan"))).double().cpu().numpy()
+        assert np.array_equal(fs[i], own), "member %d differs from its own product" % i
+        u = w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64)
+        err = rel_err(fs[i], _oracle_apply(w, u))
+        log("group %dD %s member %d (%s x%d) rel err %.2e" % (dim, prec, i, "x".join(map(str, w.n)), w.batch, err))
+        assert err <= (FP64_TOL if prec == "fp64" else FP32_TOL)
+
+
+def test_group_config_change_keeps_parity():
+    import torch
+    import paper_2301_11828_amd as msb
+    ws = _members_2d()
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    for cfg in (dict(rows_per_wg=4, team_x=1, slots_fwd=2, slots_inv=1, team_line=1, lines_per_wg=4, lines_per_wave=2,
+                     max_radix=16),
+                dict(rows_per_wg=2, team_x=0, threads_x=128, team_line=0, lines_per_wg=2, threads_line=192,
+                     max_radix=8)):
+        grp.set_config("fp64", **cfg)
+        fs = grp.apply([to_dev(w.b) for w in ws])
+        for i, w in enumerate(ws):
+            err = rel_err(fs[i].cpu().numpy(), _oracle_apply(w, w.b))
+            log("group config %s member %d rel err %.2e" % (cfg, i, err))
+            assert err <= FP64_TOL
+    with pytest.raises(msb.MsbError):
+        grp.set_config("fp64", threads_x=100)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
+def test_group_solve_matches_cholesky(prec):
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (25, 22), 3, seed=111, fixed="left", crack=True, batch=2),
+          W.small(2, (14, 18), 3, seed=112, fixed="all", batch=1, infl=(0.5, 0.2)),
+          W.small(2, (31, 12), 3, seed=113, fixed="left", batch=2)]
+    rng = np.random.default_rng(114)
+    gs = [np.where(w.fixed[None], 1e-2 * rng.standard_normal((w.batch, 2, w.N)), 0.0) for w in ws]
+    gs[1] = None
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    us, infos = grp.solve([to_dev(w.b) for w in ws], [None if g is None else to_dev(g) for g in gs],
+                          precision=prec, tol=1e-13)
+    for i, w in enumerate(ws):
+        uu = us[i].cpu().numpy()
+        for c in range(w.batch):
+            ref = O.solve_dense(oracle_problem(w), w.b[c], w.fixed, None if gs[i] is None else gs[i][c], oracle_bonds(w))
+            err = rel_err(uu[c], ref)
+            log("group solve %s member %d case %d: %d outer %d inner, residual %.2e, rel err %.2e" %
+                (prec, i, c, infos[i][c].outer_iters, infos[i][c].inner_iters, infos[i][c].rel_residual, err))
+            assert infos[i][c].status == 0
+            assert err <= (1e-11 if prec == "fp64" else 1e-10)
+
+
+def test_group_graph_blocks_equal_plain():
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (40, 33), 3, seed=121, fixed="left", batch=2), W.small(2, (17, 26), 3, seed=122, fixed="all")]
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    bs = [to_dev(w.b) for w in ws]
+    a, ia = grp.solve(bs, precision="fp64", tol=1e-12)
+    b, ib = grp.solve(bs, precision="fp64", tol=1e-12, graph_block=8)
+    for i in range(2):
+        assert np.array_equal(a[i].cpu().numpy(), b[i].cpu().numpy())
+        assert [x.inner_iters for x in ia[i]] == [x.inner_iters for x in ib[i]]
+
+
+def test_group_rejects_invalid_members():
+    import paper_2301_11828_amd as msb
+    p2 = gpu_plan(W.small(2, (12, 10), 2, seed=131))
+    p3 = gpu_plan(W.small(3, (6, 5, 4), 2, seed=132))
+    with pytest.raises(msb.MsbError):
+        msb.PlanGroup([p2, p3])
+    with pytest.raises(msb.MsbError):
+        msb.PlanGroup([p2, p2])
+
+
+def test_group_adjoint_gradient_matches_oracle():
+    """dL/db and dL/da through the group solve and its adjoint (one group solve for all
+    members' adjoints) against the oracle's exact dense gradient of each member."""
+    import torch
+    import paper_2301_11828_amd as msb
+    rng = np.random.default_rng(141)
+    ws, uts, refs = [], [], []
+    for i, (n, crack) in enumerate((((20, 17), True), ((15, 12), False), ((24, 9), False))):
+        a = tuple(rng.uniform(0.2, 1.0, size=4))
+        w = W.small(2, n, 3, seed=142 + i, fixed="all", crack=crack, infl=a)
+        ut = np.where(w.fixed, 0.0, 1e-3 * rng.standard_normal((2, w.N)))
+        refs.append(O.grad_dense(oracle_problem(w), w.b[0], ut, w.fixed, None, oracle_bonds(w)))
+        ws.append(w)
+        uts.append(ut)
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    GSolve = msb.make_group_solve_function()
+    bs = [to_dev(w.b).requires_grad_(True) for w in ws]
+    infls = [torch.tensor(w.infl, dtype=torch.float64, requires_grad=True) for w in ws]
+    us = GSolve.apply(grp, "fp64", 1e-13, *bs, *infls)
+    loss = sum(((u - to_dev(ut[None])) ** 2).sum() for u, ut in zip(us, uts))
+    loss.backward()
+    for i, (L, uref, gb_ref, ga_ref) in enumerate(refs):
+        eb = rel_err(bs[i].grad.cpu().numpy()[0], gb_ref)
+        ea = rel_err(infls[i].grad.numpy(), ga_ref)
+        log("group adjoint member %d: rel err dL/db %.2e, dL/da %.2e" % (i, eb, ea))
+        assert eb <= 1e-9 and ea <= 1e-9
