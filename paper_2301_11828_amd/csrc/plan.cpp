@@ -229,6 +229,25 @@ static void bond_weights(const msb_plan_s *p, const std::vector<double> &infl,
 // G_hat = sign * sum_o K(o) prod_axis phi_axis(2 pi k o / L) with phi = cos on even
 // axes, sin on odd axes and sign = -1 for a != b: real.  Evaluated axis by axis.
 // Output layout [comp][kx < H][ky < Ly][kz < Lz], scaled by 1/(Lx Ly Lz).
+// Rows of the exact unit circle for offsets m = -Mo..Mo along one axis:
+// row[(m + Mo) * L + k] = cos (or sin when odd) of 2 pi k m / L, rounded to double.
+static void offset_rows(int L, int Mo, bool odd, const std::vector<long double> &c,
+                        const std::vector<long double> &sn, std::vector<double> &row) {
+    row.resize((size_t)(2 * Mo + 1) * L);
+    for (int m = -Mo; m <= Mo; ++m)
+        for (int k = 0; k < L; ++k) {
+            long long t = ((long long)k * m) % L;
+            if (t < 0) t += L;
+            row[(size_t)(m + Mo) * L + k] = (double)(odd ? sn[t] : c[t]);
+        }
+}
+
+// Real spectra of the generating arrays (Sec. 3.3 and Sec. 4): G^{ab} is the stencil
+// K^{ab}(o) placed at o mod L, so its DFT is the separable sum over the (2M+1)^d box
+// of K(o) e^{-2 pi i k.o / L}.  K is even in every coordinate for a = b and odd in
+// x_a and x_b for a != b, so each axis contributes a cosine or a sine (the product of
+// the two sines of an odd pair gives the factor -1).  Computed axis by axis in double
+// from the exact unit circle; scaled by 1 / prod(L) (the inverse transform's factor).
 static void build_spectrum(const msb_plan_s *p, const std::vector<long double> &W,
                            std::vector<double> &spec) {
     const int d = p->dim, M = p->M, nc = p->ncomp;
@@ -239,64 +258,69 @@ static void build_spectrum(const msb_plan_s *p, const std::vector<long double> &
     unit_circle(Lx, cx, sx);
     unit_circle(Ly, cy, sy);
     unit_circle(Lz, cz, sz);
-    const long double scale = 1.0L / ((long double)Lx * Ly * Lz);
+    std::vector<double> rx[2], ry[2], rz[2];   // [even, odd]
+    for (int o = 0; o < 2; ++o) {
+        offset_rows(Lx, M, o == 1, cx, sx, rx[o]);
+        offset_rows(Ly, M, o == 1, cy, sy, ry[o]);
+        offset_rows(Lz, Mz, o == 1, cz, sz, rz[o]);
+    }
+    const double scale = (double)(1.0L / ((long double)Lx * Ly * Lz));
     spec.assign((size_t)nc * H * Ly * Lz, 0.0);
 
-    std::vector<long double> K((size_t)Bz * By * Bx);
-    std::vector<long double> S1((size_t)Bz * By * H), S2((size_t)Bz * H * Ly);
+    std::vector<double> K((size_t)Bz * By * Bx);
+    std::vector<double> S1((size_t)Bz * By * H), S2((size_t)Bz * H * Ly);
     for (int a = 0; a < d; ++a)
         for (int b = a; b < d; ++b) {
             const int c = comp_index(a, b, d);
-            std::fill(K.begin(), K.end(), 0.0L);
+            std::fill(K.begin(), K.end(), 0.0);
             long double centre = 0.0L;
             for (int i = 0; i < p->n_off; ++i) {
                 const int *o = &p->off[3 * i];
-                long double w = W[(size_t)c * p->n_off + i];
-                K[((size_t)(o[2] + Mz) * By + (o[1] + M)) * Bx + (o[0] + M)] = w;
+                const long double w = W[(size_t)c * p->n_off + i];
+                K[((size_t)(o[2] + Mz) * By + (o[1] + M)) * Bx + (o[0] + M)] = (double)w;
                 centre -= w;
             }
-            K[((size_t)Mz * By + M) * Bx + M] = centre;   // eq. (frb:e4)
-            const bool oddx = (a != b) && (a == 0 || b == 0);
-            const bool oddy = (a != b) && (a == 1 || b == 1);
-            const bool oddz = (a != b) && (a == 2 || b == 2);
-            const long double sign = (a != b) ? -1.0L : 1.0L;
-            // stage x
+            K[((size_t)Mz * By + M) * Bx + M] = (double)centre;   // eq. (frb:e4)
+            const int oddx = (a != b) && (a == 0 || b == 0);
+            const int oddy = (a != b) && (a == 1 || b == 1);
+            const int oddz = (a != b) && (a == 2 || b == 2);
+            const double sign = (a != b) ? -1.0 : 1.0;
+            // stage x: S1[z][y][kx] = sum_x K[z][y][x] row_x[x][kx]
+            std::fill(S1.begin(), S1.end(), 0.0);
             for (int z = 0; z < Bz; ++z)
-                for (int y = 0; y < By; ++y)
-                    for (int kx = 0; kx < H; ++kx) {
-                        long double acc = 0.0L;
-                        for (int x = 0; x < Bx; ++x) {
-                            long long t = ((long long)kx * (x - M)) % Lx;
-                            if (t < 0) t += Lx;
-                            acc += K[((size_t)z * By + y) * Bx + x] * (oddx ? sx[t] : cx[t]);
-                        }
-                        S1[((size_t)z * By + y) * H + kx] = acc;
+                for (int y = 0; y < By; ++y) {
+                    double *dst = &S1[((size_t)z * By + y) * H];
+                    for (int x = 0; x < Bx; ++x) {
+                        const double k = K[((size_t)z * By + y) * Bx + x];
+                        if (k == 0.0) continue;
+                        const double *row = &rx[oddx][(size_t)x * Lx];
+                        for (int kx = 0; kx < H; ++kx) dst[kx] += k * row[kx];
                     }
-            // stage y
+                }
+            // stage y: S2[z][kx][ky] = sum_y S1[z][y][kx] row_y[y][ky]
+            std::fill(S2.begin(), S2.end(), 0.0);
             for (int z = 0; z < Bz; ++z)
-                for (int kx = 0; kx < H; ++kx)
-                    for (int ky = 0; ky < Ly; ++ky) {
-                        long double acc = 0.0L;
-                        for (int y = 0; y < By; ++y) {
-                            long long t = ((long long)ky * (y - M)) % Ly;
-                            if (t < 0) t += Ly;
-                            acc += S1[((size_t)z * By + y) * H + kx] * (oddy ? sy[t] : cy[t]);
-                        }
-                        S2[((size_t)z * H + kx) * Ly + ky] = acc;
+                for (int kx = 0; kx < H; ++kx) {
+                    double *dst = &S2[((size_t)z * H + kx) * Ly];
+                    for (int y = 0; y < By; ++y) {
+                        const double s1 = S1[((size_t)z * By + y) * H + kx];
+                        if (s1 == 0.0) continue;
+                        const double *row = &ry[oddy][(size_t)y * Ly];
+                        for (int ky = 0; ky < Ly; ++ky) dst[ky] += s1 * row[ky];
                     }
-            // stage z
+                }
+            // stage z: out[kx][ky][kz] = sign scale sum_z S2[z][kx][ky] row_z[z][kz]
             double *out = spec.data() + (size_t)c * H * Ly * Lz;
             for (int kx = 0; kx < H; ++kx)
-                for (int ky = 0; ky < Ly; ++ky)
-                    for (int kz = 0; kz < Lz; ++kz) {
-                        long double acc = 0.0L;
-                        for (int z = 0; z < Bz; ++z) {
-                            long long t = ((long long)kz * (z - Mz)) % Lz;
-                            if (t < 0) t += Lz;
-                            acc += S2[((size_t)z * H + kx) * Ly + ky] * (oddz ? sz[t] : cz[t]);
-                        }
-                        out[((size_t)kx * Ly + ky) * Lz + kz] = (double)(sign * acc * scale);
+                for (int ky = 0; ky < Ly; ++ky) {
+                    double *dst = out + ((size_t)kx * Ly + ky) * Lz;
+                    for (int z = 0; z < Bz; ++z) {
+                        const double s2 = S2[((size_t)z * H + kx) * Ly + ky];
+                        const double *row = &rz[oddz][(size_t)z * Lz];
+                        for (int kz = 0; kz < Lz; ++kz) dst[kz] += s2 * row[kz];
                     }
+                    for (int kz = 0; kz < Lz; ++kz) dst[kz] *= sign * scale;
+                }
         }
 }
 
