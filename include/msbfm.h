@@ -138,6 +138,19 @@ msb_status msb_apply(msb_plan plan, msb_precision prec, const void *u, void *f, 
  */
 msb_status msb_apply_dinfl(msb_plan plan, int k, const double *u, double *f, void *stream);
 
+/*
+ * The preconditioner of the preconditioned solver (msb_solve_opts.precond), applied
+ * on its own: z = Pi_F E^T C^{-1} E r, where E zero-pads [d][N] to the plan's padded
+ * lengths L (msb_plan_info), C = Khat + s I is the L-periodic operator with the
+ * stiffness generating array (diagonal in Fourier space: per frequency the d x d block
+ * Khat(k) = -Ghat(k) of the Toeplitz part of Sec. 3.2 / 4), s = 1e-3 x max over k of
+ * the largest row sum of |Khat(k)|, and Pi_F zeroes constrained DOFs of the output.
+ * r is read as given on constrained DOFs (the solver passes residuals that are 0
+ * there).  r, z: device [B][d][N], double (MSB_FP64) or float (MSB_FP32), no overlap.
+ * Cases with per-case influence coefficients use their own C.  Builds C on first use.
+ */
+msb_status msb_apply_precond(msb_plan plan, msb_precision prec, const void *r, void *z, void *stream);
+
 typedef struct {
     double tol;             /* stop when ||b' - K u||_2 <= tol ||b'||_2 on free DOFs (FP64 apply) */
     int maxit;              /* cap on CG iterations (inner iterations for FP32_REFINED), > 0 */
@@ -147,6 +160,16 @@ typedef struct {
     int reliable_update;    /* FP32_REFINED: 0 = restart CG after each FP64 residual update
                                (iterative refinement); 1 = keep the search direction and
                                replace the residual by the FP64 one (reliable updates) */
+    int precond;            /* 0 = plain CG; 1 = CG preconditioned by the circulant inverse
+                               of the periodic operator on the padded grid (prior fast
+                               methods cited in the introduction): per frequency the d x d
+                               block (Khat(k) + s I)^{-1}, Khat = -Ghat, s = 1e-3 x a bound on
+                               the largest block eigenvalue; applied by the same FFT chain
+                               without the D^e / D^f corrections and masked to the free DOFs.
+                               Built on first use (host work like the operator's spectra),
+                               freed when the influence coefficients change.  Two product
+                               chains per iteration.  Not with reliable_update or groups
+                               (MSB_EUNSUPPORTED). */
 } msb_solve_opts;
 
 typedef struct {
@@ -230,8 +253,9 @@ msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds
  *     team_line     as team_x
  *     lines_per_wave  team_line = 1: lines per wavefront, 1..8
  *     threads_line  team_line = 0: threads per workgroup, multiple of 64, 64..1024
- *   max_radix       largest Stockham radix of the schedules: 8 (radices 2, 3,
- *                   4, 5, 8) or 16 (adds 6, 9, 10, 12, 15, 16)
+ *   max_radix       largest Stockham radix of the schedules: 4 (radices 2, 3,
+ *                   4; with 5 where the length needs it), 8 (adds 8; 5 always) or
+ *                   16 (adds 6, 9, 10, 12, 15, 16)
  *
  * msb_plan_set_config validates (LDS per workgroup <= 160 KiB, threads <=
  * 1024) and returns MSB_EINVAL without changing the plan otherwise.
@@ -261,7 +285,7 @@ msb_status msb_plan_set_lengths(msb_plan plan, const int64_t *L);
  * `prec` (MSB_FP32_REFINED tunes both precisions) on `stream`, with every
  * kernel of the chain timed by HIP events, and keeps the fastest in the plan.
  * The search is coordinate-wise: x-pass settings (per kernel where the two x
- * kernels can differ), then line-pass settings, then max_radix.  With
+ * kernels can differ), then line-pass settings, then max_radix (4, 8, 16).  With
  * lengths != 0 it also tries padded lengths up to 12.5% longer than the
  * default, keeping the fastest (msb_plan_set_lengths).  effort: 0 = a small
  * candidate set, 1 = full.  best: host, receives the chosen configuration of

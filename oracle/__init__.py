@@ -5,4 +5,5 @@ this package.  The product library never does, and the two share no code.
 """
 from .oracle import (Problem, alpha_2d, alpha_3d, apply, assemble_dense, broken_csr,  # noqa: F401
                      build_oracle, crack_to_bonds, energy, force, grad_dense, lifted_rhs,
-                     solve_cg, solve_dense, vv)
+                     generating_blocks, periodic_apply, precond_apply, precond_apply_periodic,
+                     precond_symbol, solve_cg, solve_dense, vv)

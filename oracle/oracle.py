@@ -24,6 +24,15 @@ eqs. (matrix)/(mae:e1), and the model equations built on it:
                               and the influence coefficients a_k (omega = sum_k a_k (r/delta)^k).
 * ``crack_to_bonds``       -- broken set of eq. (mu) for a pre-crack: a bond is broken
                               iff its segment properly crosses a crack segment.
+* ``generating_blocks``    -- the d x d blocks G(o) of the Toeplitz generating array
+                              (Sec. 3.2 / 4), read off the bond-sum force of a unit
+                              displacement at the centre of a (2M+1)^d grid.
+* ``periodic_apply``       -- the L-periodic operator with that generating array, by
+                              direct convolution (for pins).
+* ``precond_apply``        -- the circulant preconditioner of the preconditioned solver
+                              (prior fast methods cited in Sec. 1; not part of MSBFM):
+                              z = Pi_F E^T (K_per + s I)^{-1} E r, K_per = -A_per,
+                              inverted per frequency with numpy's FFT.
 
 Parity of the paper's own displacement results is unpinned (they are figures
 only and are absent from the text); the tests pin this oracle with
@@ -395,3 +404,102 @@ def crack_to_bonds(prob: Problem, segments) -> np.ndarray:
     pairs = np.concatenate(out)
     order = np.lexsort((pairs[:, 1], pairs[:, 0]))
     return np.ascontiguousarray(pairs[order])
+
+
+# ---------------------------------------------------------------- circulant preconditioner
+def generating_blocks(prob: Problem) -> np.ndarray:
+    """G(o) for every offset o in [-M, M]^d: the block A_{p,q} with p - q = o of the
+    unbroken operator (translation invariant away from the boundary, eqs. (matrix),
+    (mae:e1)).  Read off f = A e_c for a unit displacement e_c in component c at the
+    centre of a (2M+1)^d grid, whose horizon lies inside the grid: G(o)[a, c] =
+    f[a, centre + o].  Returns [d][d][2M+1]...[2M+1] (axes z, y, x reversed like the
+    node ids: index [a][c][oz+M][oy+M][ox+M])."""
+    d, M = prob.dim, prob.M
+    m = 2 * M + 1
+    small = Problem(tuple([m] * d), prob.h, M, prob.alpha, tuple(prob.infl), prob.rho)
+    centre = sum(M * m ** a for a in range(d))
+    G = np.zeros((d, d) + (m,) * d)
+    for c in range(d):
+        u = np.zeros((d, small.N))
+        u[c, centre] = 1.0
+        f = force(small, u)
+        for a in range(d):
+            G[a, c] = f[a].reshape((m,) * d)
+    return G
+
+
+def _grid_shape(n):
+    return tuple(int(x) for x in reversed(list(n)))
+
+
+def periodic_apply(prob: Problem, L: Sequence[int], v: np.ndarray, G: Optional[np.ndarray] = None) -> np.ndarray:
+    """A_per v on the L-periodic grid: (A_per v)_p = sum_o G(o) v_{p - o} (indices mod L),
+    by direct summation over the offsets.  v: [d][prod L] (node id x fastest)."""
+    d, M = prob.dim, prob.M
+    if G is None:
+        G = generating_blocks(prob)
+    shp = _grid_shape(L)
+    v = np.asarray(v, dtype=np.float64).reshape((d,) + shp)
+    out = np.zeros_like(v)
+    rng = range(-M, M + 1)
+    offs = [(o,) for o in rng] if d == 1 else (
+        [(oy, ox) for oy in rng for ox in rng] if d == 2 else [(oz, oy, ox) for oz in rng for oy in rng for ox in rng])
+    for o in offs:
+        blk = G[(slice(None), slice(None)) + tuple(x + M for x in o)]
+        if not blk.any():
+            continue
+        shifted = np.roll(v, shift=o, axis=tuple(range(1, d + 1)))   # shifted_p = v_{p - o}
+        out += np.einsum("ac,c...->a...", blk, shifted)
+    return out.reshape(d, -1)
+
+
+def precond_symbol(prob: Problem, L: Sequence[int], G: Optional[np.ndarray] = None):
+    """Khat(k) = -sum_o G(o) exp(-2 pi i k.o / L) for every frequency of the L grid (real:
+    G(o) = G(-o)), and the shift s = 1e-3 * max over k of the largest row sum of
+    |Khat(k)| (1e-3 if that is 0).  Returns (Khat [d][d][shape L reversed], s)."""
+    d, M = prob.dim, prob.M
+    if G is None:
+        G = generating_blocks(prob)
+    shp = _grid_shape(L)
+    arr = np.zeros((d, d) + shp)
+    rng = range(-M, M + 1)
+    idx = np.stack(np.meshgrid(*([np.arange(-M, M + 1)] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    for o in idx:
+        arr[(slice(None), slice(None)) + tuple(int(x) % l for x, l in zip(o, shp))] += \
+            G[(slice(None), slice(None)) + tuple(int(x) + M for x in o)]
+    Gh = np.fft.fftn(arr, axes=tuple(range(2, d + 2)))
+    Kh = -Gh.real
+    bound = np.abs(Kh).sum(axis=1).max()
+    s = 1e-3 * (bound if bound > 0 else 1.0)
+    return Kh, s
+
+
+def precond_apply(prob: Problem, r: np.ndarray, L: Sequence[int], fixed=None) -> np.ndarray:
+    """z = Pi_F E^T (K_per + s I)^{-1} E r: zero-pad r ([d][N]) to the L grid, solve the
+    d x d system of every frequency, transform back, keep the N-grid, zero constrained
+    DOFs.  Returns [d][N]."""
+    d, N = prob.dim, prob.N
+    Kh, s = precond_symbol(prob, L)
+    shp = _grid_shape(L)
+    nshp = _grid_shape(prob.n)
+    full = np.zeros((d,) + shp)
+    full[(slice(None),) + tuple(slice(0, m) for m in nshp)] = np.asarray(r, dtype=np.float64).reshape((d,) + nshp)
+    rh = np.fft.fftn(full, axes=tuple(range(1, d + 1)))
+    C = np.moveaxis(Kh, (0, 1), (-2, -1)) + s * np.eye(d)
+    zh = np.linalg.solve(C, np.moveaxis(rh, 0, -1)[..., None])[..., 0]
+    zf = np.fft.ifftn(np.moveaxis(zh, -1, 0), axes=tuple(range(1, d + 1))).real
+    z = zf[(slice(None),) + tuple(slice(0, m) for m in nshp)].reshape(d, N).copy()
+    if fixed is not None:
+        z[np.asarray(fixed, dtype=bool).reshape(d, N)] = 0.0
+    return z
+
+
+def precond_apply_periodic(prob: Problem, L: Sequence[int], v: np.ndarray) -> np.ndarray:
+    """(K_per + s I)^{-1} v on the whole L-periodic grid (for pins).  v: [d][prod L]."""
+    d = prob.dim
+    Kh, s = precond_symbol(prob, L)
+    shp = _grid_shape(L)
+    vh = np.fft.fftn(np.asarray(v, dtype=np.float64).reshape((d,) + shp), axes=tuple(range(1, d + 1)))
+    C = np.moveaxis(Kh, (0, 1), (-2, -1)) + s * np.eye(d)
+    zh = np.linalg.solve(C, np.moveaxis(vh, 0, -1)[..., None])[..., 0]
+    return np.fft.ifftn(np.moveaxis(zh, -1, 0), axes=tuple(range(1, d + 1))).real.reshape(d, -1)

@@ -26,7 +26,7 @@ _STATUS = {0: "MSB_OK", -1: "MSB_EINVAL", -2: "MSB_ENOMEM", -3: "MSB_EDEVICE", -
 
 # every symbol include/msbfm.h declares
 EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "msb_plan_set_bonds",
-           "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl",
+           "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl", "msb_apply_precond",
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
            "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
            "msb_plan_autotune", "msb_group_create", "msb_group_destroy", "msb_group_get_config",
@@ -48,7 +48,7 @@ class _Desc(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("graph_block", ctypes.c_int), ("reliable_update", ctypes.c_int)]
+                ("graph_block", ctypes.c_int), ("reliable_update", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "msb_plan_set_infl": ([P, P, I, I], I),
         "msb_apply": ([P, I, P, P, P], I),
         "msb_apply_dinfl": ([P, I, P, P, P], I),
+        "msb_apply_precond": ([P, I, P, P, P], I),
         "msb_solve_static": ([P, I, P, P, P, ctypes.POINTER(_Opts), P, P], I),
         "msb_vv_init": ([P, I, P, P, P, P], I),
         "msb_vv_run": ([P, I, D, I64, P, P, P, P, P, P, I, P], I),
@@ -320,14 +321,25 @@ class Plan:
                                     self._vec(out, torch.float64, "out"), _stream()))
         return out
 
+    def apply_precond(self, r, out=None):
+        """z = C^{-1} r of the preconditioned solver (masked to free DOFs); fp64 or fp32 by r's dtype."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(r)
+        prec = FP64 if r.dtype == torch.float64 else FP32
+        _check(_lib.msb_apply_precond(self._ptr, prec, self._vec(r, r.dtype, "r"), self._vec(out, r.dtype, "out"),
+                                      _stream()))
+        return out
+
     def solve(self, b, g=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
               inner_tol: float = 0.0, graph_block: int = 0, reliable_update: int = 0, out=None,
-              check: bool = True):
-        """Static model: K u = b on free DOFs, u = g on constrained (K = -A).  Returns (u, infos)."""
+              check: bool = True, precond: bool = False):
+        """Static model: K u = b on free DOFs, u = g on constrained (K = -A).  Returns (u, infos).
+        precond: CG preconditioned by the circulant inverse of the periodic operator."""
         torch = _torch()
         if out is None:
             out = torch.empty_like(b)
-        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), int(reliable_update))
+        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), int(reliable_update), int(bool(precond)))
         infos = (_Info * self.batch)()
         gp = self._vec(g, torch.float64, "g") if g is not None else None
         st = _lib.msb_solve_static(self._ptr, _PREC[precision], self._vec(b, torch.float64, "b"), gp,
@@ -442,7 +454,7 @@ class PlanGroup:
         torch = _torch()
         if outs is None:
             outs = [torch.empty_like(b) for b in bs]
-        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), 0)
+        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), 0, 0)
         infos = (_Info * self.total_cases)()
         gp = None
         if gs is not None:

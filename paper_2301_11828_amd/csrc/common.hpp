@@ -161,6 +161,7 @@ struct msb_plan_s {
     // per_case); dop[k] = derivative operator for omega = (r/delta)^k (built lazily)
     msb::DeviceOp op;
     std::vector<msb::DeviceOp> dop;
+    msb::DeviceOp pre;          // circulant preconditioner spectra (built on first use)
 
     // constraints
     uint8_t *fixed = nullptr;   // device [d][N] or null
@@ -203,6 +204,7 @@ FftSched make_sched(const FftAxis &ax, bool fp32, int max_radix);
 msb_status relayout(msb_plan_s *p, const int64_t *L);
 
 msb_status alloc_operator(msb_plan_s *p, DeviceOp &op, int count);
+msb_status build_preconditioner(msb_plan_s *p, DeviceOp &pre);
 msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot);
 void free_operator(DeviceOp &op);
 void solver_cache_free(msb_plan_s *p);

@@ -349,7 +349,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
 
 // Block-wide sum of up to 4 FP64 values per thread in a fixed order (deterministic):
 // wave64 butterfly shuffles, then the waves' results added in wave order by thread 0.
-// red: LDS scratch of >= 4 * (blockDim/64) doubles.  Result valid in thread 0.
+// red: LDS scratch of >= 16 K doubles (up to 16 waves).  Result valid in thread 0.
 template <int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double *red, int tid, int nt) {
 #pragma unroll
@@ -388,13 +388,13 @@ __device__ __forceinline__ double block_sum_partials(const double *__restrict__ 
     return s;
 }
 
-// Sums of K <= 4 arrays of n partials each by a whole block, all in one pass and one
+// Sums of K <= 5 arrays of n partials each by a whole block, all in one pass and one
 // tree (the same per-array order as block_sum_partials); results broadcast to all
-// threads.
+// threads.  red: >= 96 doubles.
 template <int K>
 __device__ __forceinline__ void block_sum_partials_k(const double *const (&p)[K], int n, double (&out)[K],
                                                      double *red, int tid, int nt) {
-    static_assert(K >= 1 && K <= 4, "block_sum uses red[k * 16 + wave] and red[64 + k]");
+    static_assert(K >= 1 && K <= 5, "block_sum uses red[k * 16 + wave] and red[80 + k]");
     double v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = 0.0;
@@ -405,11 +405,11 @@ __device__ __forceinline__ void block_sum_partials_k(const double *const (&p)[K]
     block_sum<K>(v, red, tid, nt);
     if (tid == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) red[64 + k] = v[k];
+        for (int k = 0; k < K; ++k) red[80 + k] = v[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = red[64 + k];
+    for (int k = 0; k < K; ++k) out[k] = red[80 + k];
     __syncthreads();
 }
 

@@ -79,7 +79,7 @@ template <typename T, bool BLOCK, int RMAX>
 __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[80];
+    __shared__ double red[96];
     const Team<BLOCK> tm;
     const int tpc = (a.rows + a.F - 1) / a.F;
     const int b = tile / tpc;
@@ -92,7 +92,14 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
     T2 *twl = reinterpret_cast<T2 *>(smem);
     T2 *bufA = twl + Lx;
     T2 *bufB = bufA + (size_t)Smax * Lx;
-    if (e.case_done && e.case_done[b]) return;
+    if (e.done_prev) {
+        if (e.done_prev[b]) {   // stopped before this iteration: carry the flag over
+            if (r0 == 0 && threadIdx.x == 0) e.done_rw[b] = e.done_prev[b];
+            return;
+        }
+    } else if (e.case_done && e.case_done[b]) {
+        return;
+    }
 
     // fused CG step (single reduction per iteration, Chronopoulos-Gear form)
     T alpha = T(0), beta = T(0);
@@ -132,6 +139,46 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
             const double den = block_sum_partials(e.beta_den + (size_t)b * e.n_den, e.n_den, red, tid0, ntb);
             beta = T(den > 0.0 ? num / den : 0.0);
         }
+    } else if (e.pro == PRO_PCG_R && !e.first) {
+        // preconditioned CG: alpha = r.z / p.q; the new r.r = r.r - 2 alpha r.q + alpha^2 q.q
+        const int tid0 = threadIdx.x, ntb = blockDim.x;
+        double sums[5];
+        if (e.case4) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sums[k] = e.case4[(size_t)b * 5 + k];
+        } else {
+            const size_t st3 = (size_t)ntiles;
+            const double *const parts[5] = {e.rr_prev + (size_t)b * tpc, e.rz_k + (size_t)b * tpc,
+                                            e.cg3 + (size_t)b * tpc, e.cg3 + st3 + (size_t)b * tpc,
+                                            e.cg3 + 2 * st3 + (size_t)b * tpc};
+            block_sum_partials_k<5>(parts, tpc, sums, red, tid0, ntb);
+        }
+        const double rr = sums[0], rz = sums[1], pq = sums[2], rq = sums[3], qq = sums[4];
+        const double al = rz / pq;
+        if (!(pq > 0.0) || !(rz >= 0.0) || !(al == al) || al > 1e300) {   // K or the preconditioner not SPD
+            if (r0 == 0 && tid0 == 0) e.done_rw[b] = 2;
+            return;
+        }
+        const double rrn = rr - 2.0 * al * rq + al * al * qq;
+        if (!(rrn == rrn)) {
+            if (r0 == 0 && tid0 == 0) e.done_rw[b] = 3;
+            return;
+        }
+        alpha = T(al);
+        upd = true;
+        conv = e.update_only || (e.thresh && !(rrn > e.thresh[b]));
+    } else if (e.pro == PRO_PCG_P && !e.first) {
+        // beta = (r.z) / (r.z of the previous iteration)
+        const int tid0 = threadIdx.x, ntb = blockDim.x;
+        double sums[2];
+        if (e.case4) {
+            sums[0] = e.case4[(size_t)b * 2];
+            sums[1] = e.case4[(size_t)b * 2 + 1];
+        } else {
+            const double *const parts[2] = {e.rz_k + (size_t)b * tpc, e.rz_km1 + (size_t)b * tpc};
+            block_sum_partials_k<2>(parts, tpc, sums, red, tid0, ntb);
+        }
+        beta = T(sums[1] > 0.0 ? sums[0] / sums[1] : 0.0);
     }
     stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);
     __syncthreads();
@@ -179,6 +226,18 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
                         rr_acc += (double)rv * (double)rv;
                         v = conv ? T(0) : rv + beta * pv;
                         if (!conv) e.pio[addr] = v;
+                    } else if (e.pro == PRO_PCG_R) {
+                        T rv = e.cr[addr];
+                        if (upd) {
+                            e.cx[addr] += alpha * e.pr[addr];
+                            rv -= alpha * e.cq[addr];
+                            e.cr[addr] = rv;
+                        }
+                        rr_acc += (double)rv * (double)rv;
+                        v = conv ? T(0) : rv;
+                    } else if (e.pro == PRO_PCG_P) {
+                        v = e.pr[addr] + beta * e.pio[addr];
+                        e.pio[addr] = v;
                     } else {
                         const bool fx = a.fixed && a.fixed[rowfix[h2] + n];
                         if (fx) v = e.pg ? e.pg[addr] : T(0);
@@ -192,7 +251,7 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
             dst[n] = z;
         }
     }
-    if (e.pro == PRO_CG_P) {
+    if (e.pro == PRO_CG_P || e.pro == PRO_PCG_R) {
         double v[1] = {rr_acc};
         block_sum<1>(v, red, threadIdx.x, blockDim.x);
         if (threadIdx.x == 0) {
@@ -200,6 +259,7 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
             if (r0 == 0) {
                 if (upd) e.iters[b] += 1;
                 if (conv) e.done_rw[b] = e.update_only ? 5 : 1;
+                else if (e.done_prev) e.done_rw[b] = 0;
             }
         }
         if (conv) return;
@@ -447,7 +507,7 @@ template <typename T, bool BLOCK, int RMAX>
 __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
     using T2 = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[80];
+    __shared__ double red[96];
     const Team<BLOCK> tm;
     const int tpc = (a.rows + a.F - 1) / a.F;
     const int b = tile / tpc;
@@ -515,7 +575,7 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
         T *Rr = reinterpret_cast<T *>(R);   // real row sl of this team at Rr[2 ((sl>>1) Lx + n) + (sl&1)]
 
         // broken bonds (eq. (tea:fr)): f_p += sum_{q in v_p} W(q - p) (u_p - u_q)
-        if (a.br_row_ptr) {
+        if (a.br_row_ptr && a.corr) {
             const T *wt = a.w + (size_t)b * a.w_slot;
             for (int sl = 0; sl < nsg; ++sl) {
                 const int sig = 2 * s0 + sl;
@@ -572,7 +632,7 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
         };
         // (whole-workgroup teams apply D^e inline in the epilogue instead: there only
         // the waves holding boundary columns wait for the table, with no extra barrier)
-        if (!BLOCK && !narrow) {
+        if (!BLOCK && !narrow && a.corr) {
             // interior rows: columns [0, M) and [Nx - M, Nx), flattened over the rows
             const int per = 2 * M;
             for (int jj = tm.tid; jj < nsg * per; jj += tm.nt) {
@@ -583,7 +643,7 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
             }
         }
         // rows within M of a y or z face (or every row of a narrow grid): all columns
-        for (int sl = 0; sl < nsg && !BLOCK; ++sl) {
+        for (int sl = 0; sl < nsg && !BLOCK && a.corr; ++sl) {
             int c, row, rpart;
             if (row_of(sl, c, row, rpart) && !narrow) continue;
 #pragma unroll 4
@@ -606,7 +666,7 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
             for (int n = tm.tid; n < a.Nx; n += tm.nt) {
                 const size_t addr = rbase + n;
                 T f = Rrow[2 * n];
-                if (BLOCK) {
+                if (BLOCK && a.corr) {
                     const int lx = min(n, M), hx = min(a.Nx - 1 - n, M);
                     if (!(rint & (lx == M) & (hx == M))) {
                         const int dx = (lx * M1 + hx) * M1p;
@@ -625,6 +685,12 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
                         acc0 += (double)uin[addr] * qd;
                         acc1 += (double)e.rhs[addr] * qd;
                         acc2 += qd * qd;
+                        break;
+                    }
+                    case EPI_PCG_Z: {
+                        const T z = fx ? T(0) : sign * f;
+                        e.out[addr] = z;
+                        acc0 += (double)uin[addr] * (double)z;
                         break;
                     }
                     case EPI_RESID: {
@@ -785,7 +851,7 @@ msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config 
     MSB_CHECK(c.lines_per_wave >= 1 && c.lines_per_wave <= 8, MSB_EINVAL, "lines_per_wave not in [1, 8]");
     for (int t : {c.threads_x, c.threads_line})
         MSB_CHECK(t >= 64 && t <= 1024 && t % 64 == 0, MSB_EINVAL, "thread count %d: need a multiple of 64 in [64, 1024]", t);
-    MSB_CHECK(c.max_radix == 8 || c.max_radix == 16, MSB_EINVAL, "max_radix must be 8 or 16");
+    MSB_CHECK(c.max_radix == 4 || c.max_radix == 8 || c.max_radix == 16, MSB_EINVAL, "max_radix must be 4, 8 or 16");
     const size_t lx = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb);
     MSB_CHECK(lx <= kLdsMax, MSB_EINVAL, "x passes need %zu bytes of LDS per workgroup (max %zu)", lx, kLdsMax);
     const size_t ll = lds_line_bytes(d, c.lines_per_wg, line_len(p), cb);
@@ -822,6 +888,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.Ly = (int)p->L[1];
     a.Lz = (int)p->L[2];
     a.N = (int)p->N;
+    a.corr = 1;
     const msb_launch_config &c = cfg ? *cfg : p->cfg[f32 ? 1 : 0];
     a.F = c.rows_per_wg;
     a.Fl = c.lines_per_wg;

@@ -11,6 +11,8 @@ enum Prologue : int {
     PRO_NONE = 0,   // transform u as given
     PRO_CG_P = 1,   // fused CG step: x += alpha p, r -= alpha q, p <- r + beta p, transform p
     PRO_VV_U = 2,   // u <- u + dt v + dt^2 a / 2, u_C <- g_C, store u, transform u
+    PRO_PCG_R = 3,  // preconditioned CG, preconditioner chain: x += alpha p, r -= alpha q, transform r
+    PRO_PCG_P = 4,  // preconditioned CG, stiffness chain: p <- z + beta p, transform p
 };
 
 // What the x-inverse pass does with f = A u after the corrections.
@@ -20,6 +22,7 @@ enum Epilogue : int {
     EPI_RESID = 2,  // out = rhs + f, 0 on constrained; partial out.out
     EPI_VV = 3,     // a' = (f + b)/rho; v += dt (a + a')/2; a = a'; energy partials
     EPI_DOT = 4,    // no output; partial w.f over free DOFs
+    EPI_PCG_Z = 5,  // out = z = sign * f (the preconditioned residual), 0 on constrained; partial r.z
 };
 
 template <typename T> struct PassArgs {
@@ -35,6 +38,7 @@ template <typename T> struct PassArgs {
     int bthreads;        // block mode: threads per block (x and y passes)
     int bthreads_line;   // block mode: threads per block of the 2D line pass
     int N;               // nodes per case
+    int corr;            // 1: add the corrections D^e and D^f (0 for the preconditioner's spectral operator)
     FftSched sx, sy, sz;
     const cplx_t<T> *twx, *twy, *twz;
     cplx_t<T> *T1, *T2;
@@ -60,8 +64,8 @@ template <typename T> struct PassArgs {
 template <typename T> struct EndArgs {
     int pro, epi;
     // prologue
-    T *pio;              // PRO_CG_P: p (in/out); PRO_VV_U: u (in/out)
-    const T *pr;         // PRO_CG_P: r;          PRO_VV_U: v
+    T *pio;              // PRO_CG_P, PRO_PCG_P: p (in/out); PRO_VV_U: u (in/out)
+    const T *pr;         // PRO_CG_P: r;          PRO_VV_U: v;  PRO_PCG_R: p;  PRO_PCG_P: z
     const T *pa;         // PRO_VV_U: a
     const T *pg;         // PRO_VV_U: g or null
     // PRO_CG_P (single-reduction CG): alpha = r.r / p.q, r'.r' = r.r - 2 alpha r.q +
@@ -72,7 +76,11 @@ template <typename T> struct EndArgs {
     const double *cg3;         // previous x-inverse partials [3][B*tiles]: p.q, r.q, q.q
     const double *rr_prev;     // previous true r.r partials [B][tiles]
     double *rr_out;            // this iteration's true r.r partials [B][tiles]
-    const double *case4;       // if set: [B][4] case sums of r.r, p.q, r.q, q.q already reduced
+    const double *case4;       // if set: [B][K] case sums already reduced (K and order as the
+                               // prologue reduces them: CG_P r.r p.q r.q q.q; PCG_R r.r r.z p.q
+                               // r.q q.q; PCG_P r.z r.z_prev)
+    // PRO_PCG_R / PRO_PCG_P: r.z partials [B][tiles] of this and the previous iteration
+    const double *rz_k, *rz_km1;
     const double *beta_num;    // first iteration of a continued run: beta = sum(num)/sum(den)
     const double *beta_den;
     int n_num, n_den;
@@ -80,7 +88,13 @@ template <typename T> struct EndArgs {
     int update_only;           // apply the pending update and stop (no transform)
     int *iters;                // [B] completed updates
     const int *case_done;      // [B] per-case stop flags (skip work) or null
-    int *done_rw;              // PRO_CG_P: flags written when a case converges
+    // CG chains keep the flags in two arrays by iteration parity: the x-forward stops on
+    // done_prev (the flags before this iteration) and writes every case's new flag into
+    // done_rw, which the later passes read as case_done.  A block that starts after
+    // another block of its case has flagged convergence in the same launch therefore
+    // still applies its share of the final update.
+    const int *done_prev;      // flags before this iteration, or null (stop on case_done)
+    int *done_rw;              // PRO_CG_P, PRO_PCG_R: the new flags
     const double *thresh;      // PRO_CG_P: per-case stop threshold on r.r (or null)
     double dt;
     // epilogue

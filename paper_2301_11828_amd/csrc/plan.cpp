@@ -66,7 +66,7 @@ bool factor_length(int L, std::vector<int> &radices, int rmax_in) {
     for (int n = 2; n <= L; ++n) {
         if (L % n) continue;
         for (int r : kRadices) {
-            if (r > rmax || n % r) continue;
+            if ((r > rmax && r != 5) || n % r) continue;   // 5 is a basic radix under every cap
             const int m = n / r;
             if (st[m] >= (1 << 20)) continue;
             const int s = st[m] + 1, lo = std::min(mn[m], r);
@@ -384,6 +384,72 @@ template <typename T> static msb_status put(T *dst, const std::vector<double> &v
     return MSB_OK;
 }
 
+// Circulant preconditioner of K = -A: on the padded grid, the periodic operator with
+// the same generating array is diagonal in Fourier space with the d x d real symmetric
+// blocks Khat(k) = -Ghat(k).  Its shifted inverse (Khat(k) + s I)^{-1}, s = 1e-3 times
+// the largest block eigenvalue bound (which also removes the rigid-motion nullspace at
+// k = 0), is stored like the spectra (components xx xy yy / xx xy xz yy yz zz, scaled
+// by 1 / prod(L)), so the same product chain applies it.
+msb_status build_preconditioner(msb_plan_s *p, DeviceOp &pre) {
+    const int count = p->op.count > 0 ? p->op.count : 1;
+    const int d = p->dim, nc = p->ncomp;
+    const size_t ns = spectrum_len(p);
+    free_operator(pre);
+    MSB_HIP(hipMalloc(&pre.spec64, sizeof(double) * nc * ns * count));
+    MSB_HIP(hipMalloc(&pre.spec32, sizeof(float) * nc * ns * count));
+    const double vol = (double)p->L[0] * (double)p->L[1] * (double)p->L[2];
+    for (int c = 0; c < count; ++c) {
+        const std::vector<double> infl = p->per_case ? std::vector<double>(p->infl_case.begin() + (size_t)c * p->n_infl,
+                                                                           p->infl_case.begin() + (size_t)(c + 1) * p->n_infl)
+                                                     : p->infl;
+        std::vector<long double> W;
+        bond_weights(p, infl, W);
+        std::vector<double> spec, out((size_t)nc * ns);
+        build_spectrum(p, W, spec);
+        // Khat = -spec * vol per frequency; largest eigenvalue bound by the row sums
+        double lmax = 0.0;
+        for (size_t k = 0; k < ns; ++k) {
+            double Kb[3][3];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) Kb[a][b] = -spec[(size_t)comp_index(a, b, d) * ns + k] * vol;
+            for (int a = 0; a < d; ++a) {
+                double r = 0.0;
+                for (int b = 0; b < d; ++b) r += std::fabs(Kb[a][b]);
+                lmax = std::max(lmax, r);
+            }
+        }
+        const double shift = 1e-3 * (lmax > 0.0 ? lmax : 1.0);
+        for (size_t k = 0; k < ns; ++k) {
+            double Kb[3][3], I[3][3];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) Kb[a][b] = -spec[(size_t)comp_index(a, b, d) * ns + k] * vol + (a == b ? shift : 0.0);
+            if (d == 2) {
+                const double det = Kb[0][0] * Kb[1][1] - Kb[0][1] * Kb[1][0];
+                I[0][0] = Kb[1][1] / det;
+                I[1][1] = Kb[0][0] / det;
+                I[0][1] = I[1][0] = -Kb[0][1] / det;
+            } else {
+                const double c00 = Kb[1][1] * Kb[2][2] - Kb[1][2] * Kb[2][1];
+                const double c01 = Kb[1][2] * Kb[2][0] - Kb[1][0] * Kb[2][2];
+                const double c02 = Kb[1][0] * Kb[2][1] - Kb[1][1] * Kb[2][0];
+                const double det = Kb[0][0] * c00 + Kb[0][1] * c01 + Kb[0][2] * c02;
+                I[0][0] = c00 / det;
+                I[0][1] = I[1][0] = c01 / det;
+                I[0][2] = I[2][0] = c02 / det;
+                I[1][1] = (Kb[0][0] * Kb[2][2] - Kb[0][2] * Kb[2][0]) / det;
+                I[1][2] = I[2][1] = (Kb[0][2] * Kb[1][0] - Kb[0][0] * Kb[1][2]) / det;
+                I[2][2] = (Kb[0][0] * Kb[1][1] - Kb[0][1] * Kb[1][0]) / det;
+            }
+            for (int a = 0; a < d; ++a)
+                for (int b = a; b < d; ++b) out[(size_t)comp_index(a, b, d) * ns + k] = I[a][b] / vol;
+        }
+        MSB_TRY(put(pre.spec64 + (size_t)nc * ns * c, out));
+        MSB_TRY(put(pre.spec32 + (size_t)nc * ns * c, out));
+    }
+    pre.count = count;   // built (a failed build leaves count 0: rebuilt on next use)
+    return MSB_OK;
+}
+
 // Fill one slot of an operator for the given influence coefficients.
 msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot) {
     std::vector<long double> W;
@@ -490,6 +556,7 @@ static msb_status build_layout(msb_plan_s *p) {
     }
     for (auto &o : p->dop) free_operator(o);
     p->dop.clear();
+    free_operator(p->pre);
     MSB_TRY(alloc_transform_ws(p));
     for (int f = 0; f < 2; ++f) {
         p->cfg[f] = default_config(p, f == 1);
@@ -554,6 +621,7 @@ extern "C" void msb_plan_destroy(msb_plan p) {
     hipDeviceSynchronize();
     free_axes(p);
     free_operator(p->op);
+    free_operator(p->pre);
     for (auto &o : p->dop) free_operator(o);
     void *bufs[] = {p->fixed, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off, p->T1, p->T2};
     for (void *b : bufs)
@@ -763,6 +831,7 @@ extern "C" msb_status msb_plan_set_infl(msb_plan p, const double *infl, int n_in
         for (auto &o : p->dop) free_operator(o);
         p->dop.clear();
     }
+    free_operator(p->pre);   // rebuilt from the new coefficients on the next preconditioned solve
     p->n_infl = n_infl;
     return MSB_OK;
 }

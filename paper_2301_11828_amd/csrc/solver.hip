@@ -28,16 +28,17 @@ enum : int { RUNNING = 0, CONVERGED = 1, BREAKDOWN = 2, NONFINITE = 3, SKIPPED =
 struct SolverWs {
     size_t nvec = 0;                 // B * d * N
     double *v64[6] = {};             // FP64 vectors
-    float *v32[5] = {};              // FP32 vectors
+    float *v32[6] = {};              // FP32 vectors
     double *part_x = nullptr;        // [3][B * rows] x-inverse epilogue partials
     double *part_rr = nullptr;       // [2][B][tiles] true r.r partials (by iteration parity)
     double *part_aux = nullptr;      // [3][B][P] dot partials
-    double *case4 = nullptr;         // [B][4] CG case sums (many tiles per case)
+    double *case4 = nullptr;         // [B][5] CG case sums (many tiles per case)
+    double *part_rz = nullptr;       // [2][3][B * rows] preconditioned CG: r.z partials by parity
     double *thresh = nullptr;        // [B]
     double *scal = nullptr;          // [16][B] per-case scalars
     double *energy = nullptr;        // energies (device)
     size_t energy_cap = 0;
-    int *done = nullptr;             // [B]
+    int *done = nullptr;             // [2][B] flags by CG iteration parity; [0] is the final state
     int *iters = nullptr;            // [B]
     int *ecount = nullptr;           // energy counter
     double *h_scal = nullptr;        // pinned [16][B]
@@ -54,7 +55,8 @@ void solver_cache_free(msb_plan_s *p) {
         if (x) (void)hipFree(x);
     for (auto x : w->v32)
         if (x) (void)hipFree(x);
-    void *b[] = {w->part_x, w->part_rr, w->part_aux, w->case4, w->thresh, w->scal, w->energy, w->done, w->iters, w->ecount};
+    void *b[] = {w->part_x, w->part_rr, w->part_aux, w->case4, w->part_rz, w->thresh, w->scal, w->energy, w->done,
+                 w->iters, w->ecount};
     for (void *x : b)
         if (x) (void)hipFree(x);
     if (w->h_scal) (void)hipHostFree(w->h_scal);
@@ -82,10 +84,11 @@ static msb_status get_ws(msb_plan_s *p, SolverWs *&out) {
     MSB_HIP(hipMalloc(&w->part_x, sizeof(double) * 3 * (size_t)B * rows_total(p)));
     MSB_HIP(hipMalloc(&w->part_rr, sizeof(double) * 2 * (size_t)B * std::max<int64_t>(rows_total(p), w->P)));
     MSB_HIP(hipMalloc(&w->part_aux, sizeof(double) * 3 * (size_t)B * w->P));
-    MSB_HIP(hipMalloc(&w->case4, sizeof(double) * 4 * (size_t)B));
+    MSB_HIP(hipMalloc(&w->case4, sizeof(double) * 5 * (size_t)B));
+    MSB_HIP(hipMalloc(&w->part_rz, sizeof(double) * 6 * (size_t)B * rows_total(p)));
     MSB_HIP(hipMalloc(&w->thresh, sizeof(double) * B));
     MSB_HIP(hipMalloc(&w->scal, sizeof(double) * 16 * B));
-    MSB_HIP(hipMalloc(&w->done, sizeof(int) * B));
+    MSB_HIP(hipMalloc(&w->done, sizeof(int) * 2 * B));
     MSB_HIP(hipMalloc(&w->iters, sizeof(int) * B));
     MSB_HIP(hipMalloc(&w->ecount, sizeof(int)));
     MSB_HIP(hipHostMalloc(&w->h_scal, sizeof(double) * 16 * B));
@@ -138,7 +141,7 @@ template <typename S> __global__ void k_add_to(double *x, const S *d, size_t n) 
 // per-case partial dot products x.y: grid B*P blocks, part[b*P + blk]
 template <typename T>
 __global__ __launch_bounds__(kT) void k_dot_parts(const T *x, const T *y, double *part, size_t dn, int P) {
-    __shared__ double red[80];
+    __shared__ double red[96];
     const int b = blockIdx.x / P, blk = blockIdx.x - b * P;
     const T *xb = x + (size_t)b * dn, *yb = y + (size_t)b * dn;
     double v[1] = {0.0};
@@ -149,21 +152,24 @@ __global__ __launch_bounds__(kT) void k_dot_parts(const T *x, const T *y, double
 
 // out[b] = scale * sum of part[b*stride .. b*stride + n)  (one block per case)
 __global__ __launch_bounds__(kT) void k_case_sums(const double *part, int n, size_t stride, double *out, double scale) {
-    __shared__ double red[80];
+    __shared__ double red[96];
     const double s = block_sum_partials(part + (size_t)blockIdx.x * stride, n, red, threadIdx.x, kT);
     if (threadIdx.x == 0) out[blockIdx.x] = scale * s;
 }
 
 // CG start: thresh[b] = tol2 * (r.r)[b] (tol2_case[b] instead of tol2 when given);
-// done[b] = SKIPPED when skip[b] != 0 (or r.r == 0)
+// both parity slots of the flags (done[b], done[b + stride]): SKIPPED when skip[b] != 0,
+// CONVERGED when r.r == 0, else RUNNING
 __global__ void k_cg_setup(const double *rr_part, int P, double tol2, const double *tol2_case, double *thresh,
-                           int *done, const int *skip, int *iters, int B) {
+                           int *done, size_t stride, const int *skip, int *iters, int B) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     double s = 0.0;
     for (int i = 0; i < P; ++i) s += rr_part[(size_t)b * P + i];
     thresh[b] = (tol2_case ? tol2_case[b] : tol2) * s;
-    done[b] = (skip && skip[b]) ? SKIPPED : (s == 0.0 ? CONVERGED : RUNNING);
+    const int f = (skip && skip[b]) ? SKIPPED : (s == 0.0 ? CONVERGED : RUNNING);
+    done[b] = f;
+    done[b + stride] = f;
     iters[b] = 0;
 }
 
@@ -179,7 +185,7 @@ __global__ void k_vv_accel(T *a, const T *bf, const uint8_t *fixed, size_t n, si
 
 // H = rho V/2 sum v^2 - V/2 sum u.f - V sum b.u over all tiles of all cases
 __global__ __launch_bounds__(kT) void k_energy(const double *part, int n, double rho, double V, double *energy, int *count) {
-    __shared__ double red[80];
+    __shared__ double red[96];
     const double uf = block_sum_partials(part, n, red, threadIdx.x, kT);
     const double vv = block_sum_partials(part + n, n, red, threadIdx.x, kT);
     const double bu = block_sum_partials(part + 2 * (size_t)n, n, red, threadIdx.x, kT);
@@ -231,18 +237,23 @@ template <typename T> struct Cg {
     const double *prev_rr;   // r.r partials before a residual replacement (first beta), or null
 };
 
-// Per-case sums of the tile partials the next CG iteration needs (r.r, p.q, r.q,
-// q.q), one block per case.  Used when a case has many tiles: every x-forward block
-// would otherwise re-reduce all of its case's partials.
-__global__ void k_cg_case4(const double *rr_prev, const double *cg3, size_t st3, int tpc, double *case4) {
-    __shared__ double red[80];
+// Per-case sums of the tile partials the next CG step needs, one block per case
+// (src[k] + b tiles: the K arrays in the order the prologue reduces them).  Used when a
+// case has many tiles: every x-forward block would otherwise re-reduce all of its
+// case's partials.
+struct SumSrc {
+    const double *p[5];
+};
+template <int K> __global__ void k_cg_sums(SumSrc src, int tpc, double *out) {
+    __shared__ double red[96];
     const int b = blockIdx.x;
-    const double *const parts[4] = {rr_prev + (size_t)b * tpc, cg3 + (size_t)b * tpc, cg3 + st3 + (size_t)b * tpc,
-                                    cg3 + 2 * st3 + (size_t)b * tpc};
-    double sums[4];
-    block_sum_partials_k<4>(parts, tpc, sums, red, threadIdx.x, blockDim.x);
+    const double *parts[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) parts[k] = src.p[k] + (size_t)b * tpc;
+    double sums[K];
+    block_sum_partials_k<K>(parts, tpc, sums, red, threadIdx.x, blockDim.x);
     if (threadIdx.x == 0) {
-        for (int k = 0; k < 4; ++k) case4[(size_t)b * 4 + k] = sums[k];
+        for (int k = 0; k < K; ++k) out[(size_t)b * K + k] = sums[k];
     }
 }
 
@@ -270,8 +281,8 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
     e.first = it == 0;
     e.update_only = update_only;
     if (it > 0 && c.tpc > kFusedReduceMaxTiles) {
-        hipLaunchKernelGGL(k_cg_case4, dim3(B), dim3(kT), 0, c.st, (const double *)e.rr_prev, (const double *)e.cg3,
-                           nt, c.tpc, w->case4);
+        const SumSrc src{{e.rr_prev, e.cg3, e.cg3 + nt, e.cg3 + 2 * nt, nullptr}};
+        hipLaunchKernelGGL(k_cg_sums<4>, dim3(B), dim3(kT), 0, c.st, src, c.tpc, w->case4);
         e.case4 = w->case4;
     }
     e.iters = w->iters;
@@ -281,8 +292,9 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
         e.beta_den = c.prev_rr;
         e.n_den = c.tpc;
     }
-    e.case_done = w->done;
-    e.done_rw = w->done;
+    e.done_prev = w->done + (size_t)((it + 1) & 1) * B;
+    e.case_done = w->done + (size_t)(it & 1) * B;
+    e.done_rw = w->done + (size_t)(it & 1) * B;
     e.thresh = w->thresh;
     e.epi = EPI_CG_Q;
     e.uin = c.pv;
@@ -295,47 +307,56 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
 // Iterations between host checks of the per-case done flags when no graph is used.
 constexpr int kPollIterations = 32;
 
-// Run CG from the prepared state (x, r, p = 0, r.r partials in part_rr[0], thresholds
-// and flags set).  Stops when every case has a flag or after maxit iterations.
-template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_block, int *it_out) {
-    SolverWs *w = c.w;
-    const int B = c.p->B;
+// Run CG iterations iter(it, update_only) from the prepared state (vectors, partials,
+// thresholds and both parity slots of the flags set).  Stops when every case has a
+// flag or after maxit iterations; the final flags end in slot 0.
+template <typename It>
+static msb_status run_iterations(SolverWs *w, int B, hipStream_t st, It iter, int maxit, int graph_block,
+                                 int *it_out) {
     int it = 0;
-    MSB_TRY(cg_iteration(c, 0));
+    MSB_TRY(iter(0, false));
     it = 1;
     const int poll = graph_block > 0 ? graph_block : kPollIterations;
     const int block = poll + (poll & 1);   // even: keeps the partial-sum parity of replays fixed
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    msb_status st = MSB_OK;
-    while (it < maxit && st == MSB_OK) {
-        MSB_HIP(hipMemcpyAsync(w->h_int, w->done, sizeof(int) * B, hipMemcpyDeviceToHost, c.st));
-        MSB_HIP(hipStreamSynchronize(c.st));
+    msb_status s = MSB_OK;
+    while (it < maxit && s == MSB_OK) {
+        MSB_HIP(hipMemcpyAsync(w->h_int, w->done + (size_t)((it - 1) & 1) * B, sizeof(int) * B,
+                               hipMemcpyDeviceToHost, st));
+        MSB_HIP(hipStreamSynchronize(st));
         bool all = true;
         for (int b = 0; b < B; ++b) all = all && w->h_int[b] != RUNNING;
         if (all) break;
         const int k = std::min(block, maxit - it);
         if (graph_block > 0 && k == block) {
             if (!exec) {
-                MSB_HIP(hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal));
-                for (int j = 0; j < block && st == MSB_OK; ++j) st = cg_iteration(c, it + j);
-                hipError_t e1 = hipStreamEndCapture(c.st, &graph);
-                if (st != MSB_OK) break;
+                MSB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                for (int j = 0; j < block && s == MSB_OK; ++j) s = iter(it + j, false);
+                hipError_t e1 = hipStreamEndCapture(st, &graph);
+                if (s != MSB_OK) break;
                 MSB_HIP(e1);
                 MSB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             }
-            MSB_HIP(hipGraphLaunch(exec, c.st));
+            MSB_HIP(hipGraphLaunch(exec, st));
         } else {
-            for (int j = 0; j < k && st == MSB_OK; ++j) st = cg_iteration(c, it + j);
+            for (int j = 0; j < k && s == MSB_OK; ++j) s = iter(it + j, false);
         }
         it += k;
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     // iteration cap: apply the pending update of the cases still running
-    if (st == MSB_OK) st = cg_iteration(c, it, true);
+    if (s == MSB_OK) s = iter(it, true);
+    if (s == MSB_OK && (it & 1))   // the final flags into slot 0
+        MSB_HIP(hipMemcpyAsync(w->done, w->done + B, sizeof(int) * B, hipMemcpyDeviceToDevice, st));
     *it_out = it;
-    return st;
+    return s;
+}
+
+template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_block, int *it_out) {
+    auto iter = [&c](int it, bool upd) { return cg_iteration(c, it, upd); };
+    return run_iterations(c.w, c.p->B, c.st, iter, maxit, graph_block, it_out);
 }
 
 // per case: dst[b][.] = latest r.r partials, part_rr[iters[b] & 1][b][.]
@@ -363,10 +384,126 @@ static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *
     hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * P), dim3(kT), 0, st, (const T *)r, (const T *)r, w->part_aux,
                        (size_t)p->dim * p->N, P);
     hipLaunchKernelGGL(k_cg_setup, dim3((B + 63) / 64), dim3(64), 0, st, (const double *)w->part_aux, P, tol * tol,
-                       tol2_case, w->thresh, w->done, skip, w->iters, B);
+                       tol2_case, w->thresh, w->done, (size_t)B, skip, w->iters, B);
     MSB_HIP(hipGetLastError());
     int it = 0;
     msb_status r0 = run_cg(c, maxit, graph_block, &it);
+    if (iters_out) *iters_out = it;
+    return r0;
+}
+
+// ------------------------------------------------------------------ preconditioned CG
+// A circulant preconditioner (the introduction cites preconditioned fast Toeplitz
+// methods as prior work; it is not part of MSBFM itself): C^{-1} with symbol
+// (Khat(k) + s I)^{-1} per frequency of the padded grid, applied by the same product
+// chain without the boundary corrections, so z = Pi_F E^T C^{-1} E Pi_F r (E: zero
+// padding to the transform lengths) is symmetric positive definite on the free DOFs.
+// Built on first use, dropped with the operator.
+static msb_status ensure_pre(msb_plan_s *p) {
+    if (p->pre.count > 0) return MSB_OK;
+    return build_preconditioner(p, p->pre);
+}
+
+template <typename T> struct Pcg {
+    msb_plan_s *p;
+    SolverWs *w;
+    hipStream_t st;
+    T *x, *r, *pv, *q, *z;
+    PassArgs<T> pa;   // stiffness product
+    PassArgs<T> pp;   // preconditioner product (spectral symbol only)
+    int tpc;
+};
+
+// One preconditioned CG iteration = two product chains.
+//   P chain: the x-forward applies the previous update (x += alpha p, r -= alpha q with
+//            alpha = r.z / p.q) and transforms r; the x-inverse forms z = C^{-1} r and
+//            the partials r.z.
+//   A chain: the x-forward forms p = z + beta p (beta = r.z / previous r.z) and
+//            transforms p; the x-inverse forms q = K p and the partials p.q, r.q, q.q.
+// Convergence is tested on the true r.r (summed in the P chain's x-forward) against the
+// same threshold as plain CG.
+template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool update_only) {
+    msb_plan_s *p = c.p;
+    SolverWs *w = c.w;
+    const int B = p->B;
+    const size_t nt = (size_t)B * c.tpc;
+    const int cur = it & 1, prv = (it + 1) & 1;
+    const bool reduce = it > 0 && c.tpc > kFusedReduceMaxTiles;
+    {
+        EndArgs<T> e = end_args<T>();
+        e.pro = PRO_PCG_R;
+        e.pr = c.pv;
+        e.cx = c.x;
+        e.cr = c.r;
+        e.cq = c.q;
+        e.cg3 = w->part_x;
+        e.rr_prev = w->part_rr + (size_t)prv * nt;
+        e.rr_out = w->part_rr + (size_t)cur * nt;
+        e.rz_k = w->part_rz + (size_t)prv * 3 * nt;
+        e.first = it == 0;
+        e.update_only = update_only;
+        if (reduce) {
+            const SumSrc src{{e.rr_prev, e.rz_k, e.cg3, e.cg3 + nt, e.cg3 + 2 * nt}};
+            hipLaunchKernelGGL(k_cg_sums<5>, dim3(B), dim3(kT), 0, c.st, src, c.tpc, w->case4);
+            e.case4 = w->case4;
+        }
+        e.iters = w->iters;
+        e.done_prev = w->done + (size_t)prv * B;
+        e.case_done = w->done + (size_t)cur * B;
+        e.done_rw = w->done + (size_t)cur * B;
+        e.thresh = w->thresh;
+        e.epi = EPI_PCG_Z;
+        e.uin = c.r;
+        e.out = c.z;
+        e.sign = 1.0;
+        e.part = w->part_rz + (size_t)cur * 3 * nt;
+        MSB_TRY(launch_product<T>(c.pp, e, c.st));
+    }
+    if (update_only) return MSB_OK;
+    EndArgs<T> e = end_args<T>();
+    e.pro = PRO_PCG_P;
+    e.pr = c.z;
+    e.pio = c.pv;
+    e.rz_k = w->part_rz + (size_t)cur * 3 * nt;
+    e.rz_km1 = w->part_rz + (size_t)prv * 3 * nt;
+    e.first = it == 0;
+    if (reduce) {
+        const SumSrc src{{e.rz_k, e.rz_km1, nullptr, nullptr, nullptr}};
+        hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kT), 0, c.st, src, c.tpc, w->case4);
+        e.case4 = w->case4;
+    }
+    e.case_done = w->done + (size_t)cur * B;
+    e.epi = EPI_CG_Q;
+    e.uin = c.pv;
+    e.out = c.q;
+    e.rhs = c.r;
+    e.part = w->part_x;
+    return launch_product<T>(c.pa, e, c.st);
+}
+
+// Preconditioned CG on K d = rhs (rhs already masked), x0 = 0, with the same flags,
+// thresholds and iteration counters as cg_solve.
+template <typename T>
+static msb_status pcg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *rhs, T *x, T *r, T *pv, T *q,
+                            T *z, double tol, int maxit, int graph_block, const int *skip, int *iters_out = nullptr,
+                            const double *tol2_case = nullptr) {
+    MSB_TRY(ensure_pre(p));
+    const size_t n = w->nvec;
+    const int B = p->B, P = w->P;
+    Pcg<T> c{p, w, st, x, r, pv, q, z, pass_args<T>(p, p->op), pass_args<T>(p, p->pre), 0};
+    c.pp.corr = 0;
+    c.tpc = x_tiles_per_case(p, c.pa.F);
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, x, n, T(0));
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
+    hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(n)), dim3(kT), 0, st, r, rhs, n);
+    hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * P), dim3(kT), 0, st, (const T *)r, (const T *)r, w->part_aux,
+                       (size_t)p->dim * p->N, P);
+    hipLaunchKernelGGL(k_cg_setup, dim3((B + 63) / 64), dim3(64), 0, st, (const double *)w->part_aux, P, tol * tol,
+                       tol2_case, w->thresh, w->done, (size_t)B, skip, w->iters, B);
+    MSB_HIP(hipGetLastError());
+    int it = 0;
+    auto iter = [&c](int k, bool upd) { return pcg_iteration(c, k, upd); };
+    msb_status r0 = run_iterations(w, B, st, iter, maxit, graph_block, &it);
     if (iters_out) *iters_out = it;
     return r0;
 }
@@ -426,6 +563,28 @@ extern "C" msb_status msb_apply(msb_plan p, msb_precision prec, const void *u, v
     e.epi = EPI_APPLY;
     e.out = (float *)f;
     return product<float>(p, p->op, (const float *)u, e, st);
+}
+
+template <typename T> static msb_status apply_pre_t(msb_plan_s *p, const T *r, T *z, hipStream_t st) {
+    MSB_TRY(ensure_pre(p));
+    PassArgs<T> a = pass_args<T>(p, p->pre);
+    a.corr = 0;
+    EndArgs<T> e = end_args<T>();
+    e.epi = EPI_APPLY;
+    e.pio = const_cast<T *>(r);
+    e.uin = r;
+    e.out = z;
+    return launch_product<T>(a, e, st);
+}
+
+extern "C" msb_status msb_apply_precond(msb_plan p, msb_precision prec, const void *r, void *z, void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(r && z, MSB_EINVAL, "null vector");
+    MSB_CHECK(r != z, MSB_EINVAL, "r and z must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == MSB_FP64) return apply_pre_t<double>(p, (const double *)r, (double *)z, st);
+    MSB_CHECK(prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
+    return apply_pre_t<float>(p, (const float *)r, (float *)z, st);
 }
 
 static msb_status ensure_dop(msb_plan_s *p, int k) {
@@ -502,6 +661,10 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
     MSB_CHECK(opts->tol > 0 && opts->tol < 1 && opts->maxit > 0, MSB_EINVAL, "need 0 < tol < 1 and maxit > 0");
     MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32 || prec == MSB_FP32_REFINED, MSB_EINVAL, "bad precision");
     MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
+    MSB_CHECK(opts->precond == 0 || opts->precond == 1, MSB_EINVAL, "precond must be 0 or 1");
+    MSB_CHECK(!(opts->precond && opts->reliable_update), MSB_EUNSUPPORTED,
+              "the preconditioned solver refines by restarts only (reliable_update = 0)");
+    const bool pre = opts->precond != 0;
     SolverWs *w = nullptr;
     MSB_TRY(get_ws(p, w));
     const int B = p->B;
@@ -539,11 +702,21 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
 
     if (prec == MSB_FP64 || prec == MSB_FP32) {
         if (prec == MSB_FP64) {
-            MSB_TRY(cg_solve<double>(p, w, st, bp, u, w->v64[2], w->v64[3], w->v64[4], opts->tol, opts->maxit, gb, nullptr));
+            if (pre)
+                MSB_TRY(pcg_solve<double>(p, w, st, bp, u, w->v64[2], w->v64[3], w->v64[4], w->v64[5], opts->tol,
+                                          opts->maxit, gb, nullptr));
+            else
+                MSB_TRY(cg_solve<double>(p, w, st, bp, u, w->v64[2], w->v64[3], w->v64[4], opts->tol, opts->maxit, gb,
+                                         nullptr));
         } else {
             float *b32 = w->v32[0], *x32 = w->v32[1];
             hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kT), 0, st, b32, (const double *)bp, n);
-            MSB_TRY(cg_solve<float>(p, w, st, b32, x32, w->v32[2], w->v32[3], w->v32[4], opts->tol, opts->maxit, gb, nullptr));
+            if (pre)
+                MSB_TRY(pcg_solve<float>(p, w, st, b32, x32, w->v32[2], w->v32[3], w->v32[4], w->v32[5], opts->tol,
+                                         opts->maxit, gb, nullptr));
+            else
+                MSB_TRY(cg_solve<float>(p, w, st, b32, x32, w->v32[2], w->v32[3], w->v32[4], opts->tol, opts->maxit,
+                                        gb, nullptr));
             hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for(n)), dim3(kT), 0, st, u, (const float *)x32, n);
         }
         MSB_TRY(fetch_scal(w, st, 1, B));
@@ -597,8 +770,12 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
             MSB_HIP(hipMemcpyAsync(t2d, t2.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
             MSB_HIP(hipMemcpyAsync(skip, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
             hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kT), 0, st, r32, (const double *)r64, n);
-            MSB_TRY(cg_solve<float>(p, w, st, r32, d32, p32, w->v32[3], w->v32[4], itol, opts->maxit - used, gb,
-                                    skip, (reliable && !first) ? prev : nullptr, nullptr, t2d));
+            if (pre)
+                MSB_TRY(pcg_solve<float>(p, w, st, r32, d32, p32, w->v32[3], w->v32[4], w->v32[5], itol,
+                                         opts->maxit - used, gb, skip, nullptr, t2d));
+            else
+                MSB_TRY(cg_solve<float>(p, w, st, r32, d32, p32, w->v32[3], w->v32[4], itol, opts->maxit - used, gb,
+                                        skip, (reliable && !first) ? prev : nullptr, nullptr, t2d));
             first = false;
             MSB_TRY(fetch_scal(w, st, 0, B));
             int mx = 0;
@@ -964,7 +1141,7 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
                            w->part_aux, (size_t)p->dim * p->N, w->P);
         const int co = g->case_off[i];
         hipLaunchKernelGGL(k_cg_setup, dim3((p->B + 63) / 64), dim3(64), 0, st, (const double *)w->part_aux, w->P,
-                           tol * tol, tol2_case ? tol2_case + co : nullptr, g->thresh + co, g->done + co,
+                           tol * tol, tol2_case ? tol2_case + co : nullptr, g->thresh + co, g->done + co, (size_t)g->Btot,
                            skip ? skip + co : nullptr, g->iters + co, p->B);
     }
     MSB_HIP(hipGetLastError());
@@ -988,8 +1165,9 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
             e.first = slot == G_FIRST;
             e.update_only = slot == G_UPD_EVEN || slot == G_UPD_ODD;
             e.iters = g->iters + co;
-            e.case_done = g->done + co;
-            e.done_rw = g->done + co;
+            e.done_prev = g->done + (size_t)((parity + 1) & 1) * g->Btot + co;
+            e.case_done = g->done + (size_t)parity * g->Btot + co;
+            e.done_rw = g->done + (size_t)parity * g->Btot + co;
             e.thresh = g->thresh + co;
             e.epi = EPI_CG_Q;
             e.uin = pv[i];
@@ -1017,7 +1195,8 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     hipGraph_t graph = nullptr;
     msb_status s = MSB_OK;
     while (it < maxit && s == MSB_OK) {
-        MSB_HIP(hipMemcpyAsync(g->h_int, g->done, sizeof(int) * g->Btot, hipMemcpyDeviceToHost, st));
+        MSB_HIP(hipMemcpyAsync(g->h_int, g->done + (size_t)((it - 1) & 1) * g->Btot, sizeof(int) * g->Btot,
+                               hipMemcpyDeviceToHost, st));
         MSB_HIP(hipStreamSynchronize(st));
         std::vector<int> now;
         for (int i = 0; i < g->n; ++i) {
@@ -1053,6 +1232,8 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (s == MSB_OK) s = iteration(it, true);   // iteration cap: pending update of running cases
+    if (s == MSB_OK && (it & 1))                  // the final flags into slot 0
+        MSB_HIP(hipMemcpyAsync(g->done, g->done + g->Btot, sizeof(int) * g->Btot, hipMemcpyDeviceToDevice, st));
     // all members again for the next launches
     MSB_HIP(hipStreamSynchronize(st));
     std::vector<int> all(g->n);
@@ -1160,7 +1341,7 @@ extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_gr
         hipMalloc(&g->part_rr, sizeof(double) * 2 * tiles_max) != hipSuccess ||
         hipMalloc(&g->thresh, sizeof(double) * nb) != hipSuccess ||
         hipMalloc(&g->scal, sizeof(double) * 16 * nb) != hipSuccess ||
-        hipMalloc(&g->done, sizeof(int) * nb) != hipSuccess || hipMalloc(&g->iters, sizeof(int) * nb) != hipSuccess ||
+        hipMalloc(&g->done, sizeof(int) * 2 * nb) != hipSuccess || hipMalloc(&g->iters, sizeof(int) * nb) != hipSuccess ||
         hipMalloc(&g->skip, sizeof(int) * nb) != hipSuccess ||
         hipHostMalloc(&g->h_scal, sizeof(double) * 16 * nb) != hipSuccess ||
         hipHostMalloc(&g->h_int, sizeof(int) * 2 * nb) != hipSuccess ||
@@ -1243,6 +1424,7 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32 || prec == MSB_FP32_REFINED, MSB_EINVAL, "bad precision");
     MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
     MSB_CHECK(opts->reliable_update == 0, MSB_EUNSUPPORTED, "groups refine by restarts only (reliable_update = 0)");
+    MSB_CHECK(opts->precond == 0, MSB_EUNSUPPORTED, "groups solve without the preconditioner (precond = 0)");
     int dev = -1;
     MSB_HIP(hipGetDevice(&dev));
     MSB_CHECK(dev == g->device, MSB_EINVAL, "group was created on device %d, current is %d", g->device, dev);

@@ -219,7 +219,7 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
         msb_launch_config best = cur;
         MSB_TRY(bn.run(cur, err) ? MSB_OK : err);
         double bt = bn.total();
-        for (int r : {8, 16}) {
+        for (int r : {4, 8, 16}) {
             if (r == cur.max_radix) continue;
             msb_launch_config c = cur;
             c.max_radix = r;

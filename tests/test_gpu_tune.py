@@ -38,7 +38,7 @@ def _random_configs(rng, count):
                         slots_fwd=int(rng.integers(1, 9)), slots_inv=int(rng.integers(1, 9)),
                         threads_x=64 * int(rng.integers(1, 17)), lines_per_wg=int(rng.choice([1, 2, 3, 5, 8, 16])),
                         team_line=int(rng.integers(2)), lines_per_wave=int(rng.integers(1, 9)),
-                        threads_line=64 * int(rng.integers(1, 17)), max_radix=int(rng.choice([8, 16]))))
+                        threads_line=64 * int(rng.integers(1, 17)), max_radix=int(rng.choice([4, 8, 16]))))
     return out
 
 

@@ -469,3 +469,128 @@ def test_lift_equals_dense_block():
     got = O.lifted_rhs(p, b, fixed, g).reshape(-1)
     assert np.allclose(got[F], ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
     assert np.all(got[C] == 0)
+
+
+# ---------------------------------------------------------------- circulant preconditioner
+
+def test_generating_blocks_match_golden_stencil():
+    """G(o) read off the unit-displacement force equals the hand-worked entries of
+    eq. (frb:e1) (A_{p, p+o} = G(-o) = G(o))."""
+    M = 3
+    p = O.Problem((7, 7), 1.0, M, 1.0)
+    G = O.generating_blocks(p)
+    comp = {"xx": (0, 0), "yy": (1, 1), "xy": (0, 1)}
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "stencil_M3_2d.txt"))
+            if l.strip() and not l.startswith("#")]
+    for ox, oy, cname, val in rows:
+        a, b = comp[cname]
+        for sgn in (1, -1):
+            got = G[a, b, M + sgn * int(oy), M + sgn * int(ox)]
+            assert got == pytest.approx(float(val), rel=1e-14, abs=1e-15), (ox, oy, cname)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_generating_blocks_symmetries(dim):
+    """Sum over o of G(o) = 0 (rigid translation), G(o) = G(-o), symmetric blocks, and
+    G(o) = 0 outside the horizon |o| > M."""
+    p = _prob2(9, 9, 3) if dim == 2 else _prob3(5, 5, 5, 2)
+    G = O.generating_blocks(p)
+    M = p.M
+    scale = np.abs(G).max()
+    assert np.abs(G.sum(axis=tuple(range(2, dim + 2)))).max() <= 1e-13 * scale
+    flip = G[(slice(None), slice(None)) + (slice(None, None, -1),) * dim]
+    assert np.abs(G - flip).max() <= 1e-15 * scale
+    assert np.array_equal(G, np.swapaxes(G, 0, 1))
+    o = np.stack(np.meshgrid(*([np.arange(-M, M + 1)] * dim), indexing="ij"))
+    outside = (o ** 2).sum(axis=0) > M * M
+    assert np.all(G[:, :, outside] == 0.0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_periodic_apply_equals_bounded_apply_in_interior(dim):
+    """For u on the N grid zero-padded to L >= N + M, the periodic operator agrees with the
+    bond sum of eq. (mat:f1) on every node whose horizon lies inside the domain."""
+    rng = np.random.default_rng(31 + dim)
+    if dim == 2:
+        p, L = _prob2(14, 11, 3), (18, 15)
+    else:
+        p, L = _prob3(8, 7, 6, 2), (11, 9, 8)
+    M, d = p.M, dim
+    u = rng.standard_normal((d, p.N))
+    nshp = tuple(reversed(p.n))
+    full = np.zeros((d,) + tuple(reversed(L)))
+    full[(slice(None),) + tuple(slice(0, m) for m in nshp)] = u.reshape((d,) + nshp)
+    ap = O.periodic_apply(p, L, full.reshape(d, -1)).reshape(full.shape)
+    ap = ap[(slice(None),) + tuple(slice(0, m) for m in nshp)]
+    ab = O.force(p, u).reshape((d,) + nshp)
+    inner = (slice(None),) + (slice(M, -M),) * d
+    assert np.abs(ap[inner] - ab[inner]).max() <= 1e-12 * np.abs(ab).max()
+    # the boundary rows differ (incomplete horizons: the D^e correction)
+    assert np.abs(ap - ab).max() > 1e-3 * np.abs(ab).max()
+
+
+def _dense_periodic(p, L):
+    n = int(np.prod(L)) * p.dim
+    C = np.empty((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        C[:, j] = -O.periodic_apply(p, L, e.reshape(p.dim, -1)).reshape(-1)
+    return C
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_precond_equals_dense_inverse(dim):
+    """Brute force on tiny grids: z = Pi_F E^T (K_per + s I)^{-1} E r with K_per assembled
+    column by column from the direct convolution and inverted densely; s = 1e-3 x the
+    largest absolute row sum over the frequency blocks."""
+    rng = np.random.default_rng(41 + dim)
+    if dim == 2:
+        p, L = _prob2(5, 4, 2), (8, 7)
+    else:
+        p, L = _prob3(3, 3, 2, 2), (6, 5, 5)
+    d = p.dim
+    K = _dense_periodic(p, L)
+    assert np.abs(K - K.T).max() <= 1e-12 * np.abs(K).max()
+    ev = np.linalg.eigvalsh(K)
+    assert ev.min() >= -1e-12 * ev.max()            # positive semi-definite, translations in the kernel
+    Kh, s = O.precond_symbol(p, L)
+    # the Gershgorin bound of every block is at least its largest eigenvalue
+    assert 1e-3 * ev.max() <= s * (1 + 1e-12)
+    Cinv = np.linalg.inv(K + s * np.eye(K.shape[0]))
+    fixed = np.zeros((d, p.N), dtype=bool)
+    fixed[:, :p.n[0]] = True                          # first grid row constrained
+    r = rng.standard_normal((d, p.N))
+    # explicit padding: node id i + nx (j + ny k) -> i + Lx (j + Ly k)
+    ids = np.arange(p.N)
+    coords = []
+    rem = ids.copy()
+    for m in p.n:
+        coords.append(rem % m)
+        rem //= m
+    pid = np.zeros(p.N, dtype=np.int64)
+    for a in reversed(range(d)):
+        pid = pid * L[a] + coords[a]
+    nL = int(np.prod(L))
+    E = np.zeros((d * nL, d * p.N))
+    for c in range(d):
+        E[c * nL + pid, c * p.N + ids] = 1.0
+    ref = (E.T @ Cinv @ E @ r.reshape(-1)).reshape(d, p.N)
+    ref[fixed] = 0.0
+    got = O.precond_apply(p, r, L, fixed)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    # constant fields are the k = 0 mode: (K_per + s I)^{-1} c = c / s
+    const = np.ones((d, nL)) * np.arange(1, d + 1)[:, None]
+    assert np.allclose(O.precond_apply_periodic(p, L, const), const / s, rtol=1e-12)
+
+
+def test_precond_is_spd_on_free_dofs():
+    rng = np.random.default_rng(51)
+    p, L = _prob2(20, 17, 3), (24, 20)
+    fixed = np.zeros((2, p.N), dtype=bool)
+    fixed[:, ::20] = True                              # left column
+    r1 = np.where(fixed, 0.0, rng.standard_normal((2, p.N)))
+    r2 = np.where(fixed, 0.0, rng.standard_normal((2, p.N)))
+    z1, z2 = O.precond_apply(p, r1, L, fixed), O.precond_apply(p, r2, L, fixed)
+    assert abs((r1 * z2).sum() - (r2 * z1).sum()) <= 1e-13 * abs((r1 * z1).sum())
+    assert (r1 * z1).sum() > 0 and (r2 * z2).sum() > 0
