@@ -330,6 +330,26 @@ msb_status msb_group_solve_static(msb_group group, msb_precision prec, const dou
                                   const double *const *g, double *const *u, const msb_solve_opts *opts,
                                   msb_solve_info *info, void *stream);
 
+/*
+ * Crack propagation, the history-dependent factor mu of eq. (mu): every bond {p, q} not
+ * yet broken whose stretch s = (|x_q + u_q - x_p - u_p| - |x_q - x_p|) / |x_q - x_p|
+ * (eq. (fra:s1), FP64 from u) satisfies s >= s0 breaks and joins the plan's broken set,
+ * whose stiffness the D^f correction (eq. (df)) removes from every later product (the
+ * paper's Phase III, Sec. 5.2).  Bonds never heal.  u: device [1][d][N], double
+ * (MSB_FP64) or float (MSB_FP32).  s0 > 0 (e.g. sqrt(4 pi G0 / (9 E delta)), plane
+ * stress, eq. (fra:s1)).  *n_new: bonds broken by this call.  Single-case plans only
+ * (MSB_EUNSUPPORTED for batch > 1: the broken set is shared by the cases).
+ * Synchronises the stream.
+ */
+msb_status msb_crack_update(msb_plan plan, msb_precision prec, const void *u, double s0, int64_t *n_new,
+                            void *stream);
+
+/*
+ * The broken set: *count = number of broken bonds; the first min(cap, count) pairs
+ * (p < q, sorted by p then q) go to pairs [cap][2] (host; may be NULL when cap = 0).
+ */
+msb_status msb_plan_get_bonds(msb_plan plan, int64_t *pairs, int64_t cap, int64_t *count);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *msb_last_error(void);
 

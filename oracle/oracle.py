@@ -24,6 +24,9 @@ eqs. (matrix)/(mae:e1), and the model equations built on it:
                               and the influence coefficients a_k (omega = sum_k a_k (r/delta)^k).
 * ``crack_to_bonds``       -- broken set of eq. (mu) for a pre-crack: a bond is broken
                               iff its segment properly crosses a crack segment.
+* ``bond_stretch``         -- s of eq. (fra:s1) for given bonds, from node coordinates.
+* ``crack_update``         -- the new broken set of eq. (mu): every unbroken bond with
+                              s >= s0, brute force over every bond of the horizon.
 * ``generating_blocks``    -- the d x d blocks G(o) of the Toeplitz generating array
                               (Sec. 3.2 / 4), read off the bond-sum force of a unit
                               displacement at the centre of a (2M+1)^d grid.
@@ -503,3 +506,56 @@ def precond_apply_periodic(prob: Problem, L: Sequence[int], v: np.ndarray) -> np
     C = np.moveaxis(Kh, (0, 1), (-2, -1)) + s * np.eye(d)
     zh = np.linalg.solve(C, np.moveaxis(vh, 0, -1)[..., None])[..., 0]
     return np.fft.ifftn(np.moveaxis(zh, -1, 0), axes=tuple(range(1, d + 1))).real.reshape(d, -1)
+
+
+# ---------------------------------------------------------------- crack propagation
+def all_bonds(prob: Problem) -> np.ndarray:
+    """Every bond {p, q} of the discrete horizon (integer offsets 0 < |o|^2 <= M^2, q inside
+    the grid), as [n][2] pairs p < q sorted by (p, q)."""
+    d, M = prob.dim, prob.M
+    n = list(prob.n)
+    ids = np.arange(prob.N).reshape(tuple(reversed(n)))
+    out = []
+    rng = range(-M, M + 1)
+    offs = [(ox, oy, 0) for oy in rng for ox in rng] if d == 2 else \
+        [(ox, oy, oz) for oz in rng for oy in rng for ox in rng]
+    for o in offs:
+        o = o[:d]
+        s2 = sum(x * x for x in o)
+        if s2 == 0 or s2 > M * M:
+            continue
+        src = tuple(slice(max(0, -x), m - max(0, x)) for x, m in zip(reversed(o), reversed(n)))
+        dst = tuple(slice(max(0, x), m - max(0, -x)) for x, m in zip(reversed(o), reversed(n)))
+        P, Q = ids[src].reshape(-1), ids[dst].reshape(-1)
+        keep = P < Q
+        out.append(np.stack([P[keep], Q[keep]], axis=1))
+    pairs = np.concatenate(out) if out else np.zeros((0, 2), dtype=np.int64)
+    order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    return np.ascontiguousarray(pairs[order].astype(np.int64))
+
+
+def bond_stretch(prob: Problem, u: np.ndarray, pairs: np.ndarray) -> np.ndarray:
+    """s = (|x_q + u_q - x_p - u_p| - |x_q - x_p|) / |x_q - x_p|, eq. (fra:s1), FP64."""
+    d = prob.dim
+    x = prob.node_coords()
+    u = np.asarray(u, dtype=np.float64).reshape(d, prob.N)
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    P, Q = pairs[:, 0], pairs[:, 1]
+    xi = x[:, Q] - x[:, P]
+    eta = u[:, Q] - u[:, P]
+    ref = np.sqrt((xi * xi).sum(axis=0))
+    cur = np.sqrt(((xi + eta) ** 2).sum(axis=0))
+    return (cur - ref) / ref
+
+
+def crack_update(prob: Problem, u: np.ndarray, s0: float, broken=None):
+    """Eq. (mu): mu drops to 0 for good once s >= s0.  Returns (new [k][2] pairs p < q sorted,
+    the updated broken set [n][2] sorted, the stretches of every bond of all_bonds)."""
+    bonds = all_bonds(prob)
+    s = bond_stretch(prob, u, bonds)
+    old = set() if broken is None or len(broken) == 0 else \
+        {(int(a), int(b)) for a, b in np.asarray(broken, dtype=np.int64).reshape(-1, 2)}
+    new = [(int(a), int(b)) for (a, b), si in zip(bonds, s) if si >= s0 and (int(a), int(b)) not in old]
+    allb = sorted(old | set(new))
+    as_arr = lambda v: np.array(v, dtype=np.int64).reshape(-1, 2)
+    return as_arr(new), as_arr(allb), s

@@ -27,6 +27,7 @@ _STATUS = {0: "MSB_OK", -1: "MSB_EINVAL", -2: "MSB_ENOMEM", -3: "MSB_EDEVICE", -
 # every symbol include/msbfm.h declares
 EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "msb_plan_set_bonds",
            "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl", "msb_apply_precond",
+           "msb_crack_update", "msb_plan_get_bonds",
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
            "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
            "msb_plan_autotune", "msb_group_create", "msb_group_destroy", "msb_group_get_config",
@@ -95,6 +96,8 @@ def load_library(path: str = LIB_PATH):
         "msb_apply": ([P, I, P, P, P], I),
         "msb_apply_dinfl": ([P, I, P, P, P], I),
         "msb_apply_precond": ([P, I, P, P, P], I),
+        "msb_crack_update": ([P, I, P, D, ctypes.POINTER(I64), P], I),
+        "msb_plan_get_bonds": ([P, P, I64, ctypes.POINTER(I64)], I),
         "msb_solve_static": ([P, I, P, P, P, ctypes.POINTER(_Opts), P, P], I),
         "msb_vv_init": ([P, I, P, P, P, P], I),
         "msb_vv_run": ([P, I, D, I64, P, P, P, P, P, P, I, P], I),
@@ -278,6 +281,24 @@ class Plan:
         p = np.ascontiguousarray(np.asarray(pairs if pairs is not None else np.zeros((0, 2)),
                                             dtype=np.int64).reshape(-1, 2))
         _check(_lib.msb_plan_set_bonds(self._ptr, p.ctypes.data if len(p) else None, len(p)))
+
+    def bonds(self) -> np.ndarray:
+        """The broken set as [n][2] int64 pairs (p < q), sorted."""
+        cnt = ctypes.c_int64()
+        _check(_lib.msb_plan_get_bonds(self._ptr, None, 0, ctypes.byref(cnt)))
+        out = np.zeros((cnt.value, 2), dtype=np.int64)
+        if cnt.value:
+            _check(_lib.msb_plan_get_bonds(self._ptr, out.ctypes.data, cnt.value, ctypes.byref(cnt)))
+        return out
+
+    def crack_update(self, u, s0: float) -> int:
+        """Break every bond whose stretch (eq. (fra:s1)) reaches s0; returns the number of new breaks."""
+        torch = _torch()
+        prec = FP64 if u.dtype == torch.float64 else FP32
+        n = ctypes.c_int64()
+        _check(_lib.msb_crack_update(self._ptr, prec, self._vec(u, u.dtype, "u"), float(s0), ctypes.byref(n),
+                                     _stream()))
+        return n.value
 
     def set_infl(self, infl, per_case: bool = False):
         a = np.ascontiguousarray(np.asarray(infl, dtype=np.float64))

@@ -175,6 +175,15 @@ struct msb_plan_s {
     int32_t *br_q = nullptr;         // [ndir] neighbour node id
     int32_t *br_off = nullptr;       // [ndir] stencil offset id
     int64_t n_br_nodes = 0;
+    std::vector<int64_t> bonds_host; // [n_pairs][2] the broken set, p < q, sorted
+
+    // crack propagation (crack.hip): broken-bond bit mask over the half stencil
+    // (offsets o with p + o > p), one bit per bond {p, p + o}; rebuilt from bonds_host
+    // when stale
+    uint64_t *mu_mask = nullptr;     // [N][mu_words]
+    int mu_words = 0;
+    bool mu_valid = false;
+    void *crack_ws = nullptr;        // crack.hip workspace
 
     // workspace (device)
     void *T1 = nullptr;         // complex [B][d][Nz][H][Ny] (largest precision)
@@ -208,5 +217,8 @@ msb_status build_preconditioner(msb_plan_s *p, DeviceOp &pre);
 msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot);
 void free_operator(DeviceOp &op);
 void solver_cache_free(msb_plan_s *p);
+// Replace the broken set by pairs[nb][2] (validated), rebuild the D^f lists (plan.cpp).
+msb_status set_bonds_impl(msb_plan_s *p, const int64_t *pairs, int64_t nb);
+void crack_free(msb_plan_s *p);   // crack.hip
 
 }  // namespace msb

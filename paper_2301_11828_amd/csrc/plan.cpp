@@ -627,6 +627,7 @@ extern "C" void msb_plan_destroy(msb_plan p) {
     for (void *b : bufs)
         if (b) hipFree(b);
     solver_cache_free(p);
+    crack_free(p);
     delete p;
 }
 
@@ -662,6 +663,24 @@ extern "C" msb_status msb_plan_set_constraints(msb_plan p, const uint8_t *fixed)
 
 extern "C" msb_status msb_plan_set_bonds(msb_plan p, const int64_t *pairs, int64_t nb) {
     MSB_CHECK(p, MSB_EINVAL, "null plan");
+    MSB_TRY(msb::set_bonds_impl(p, pairs, nb));
+    p->mu_valid = false;
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_plan_get_bonds(msb_plan p, int64_t *pairs, int64_t cap, int64_t *count) {
+    MSB_CHECK(p, MSB_EINVAL, "null plan");
+    MSB_CHECK(count, MSB_EINVAL, "null count");
+    *count = p->n_pairs;
+    MSB_CHECK(cap >= 0, MSB_EINVAL, "negative capacity");
+    if (pairs && cap > 0) {
+        const int64_t n = std::min<int64_t>(cap, p->n_pairs);
+        std::memcpy(pairs, p->bonds_host.data(), sizeof(int64_t) * 2 * n);
+    }
+    return MSB_OK;
+}
+
+msb_status msb::set_bonds_impl(msb_plan_s *p, const int64_t *pairs, int64_t nb) {
     MSB_CHECK(nb >= 0, MSB_EINVAL, "negative bond count");
     MSB_CHECK(nb == 0 || pairs, MSB_EINVAL, "null bond list");
     const int d = p->dim, M = p->M, B = 2 * M + 1;
@@ -727,6 +746,14 @@ extern "C" msb_status msb_plan_set_bonds(msb_plan p, const int64_t *pairs, int64
     MSB_TRY(upload(&p->br_off, off));
     p->n_pairs = nb;
     p->n_br_nodes = (int64_t)node_i.size();
+    std::vector<int64_t> hb;
+    hb.reserve(2 * (size_t)nb);
+    for (const Dir &e : dir)
+        if (e.p < e.q) {
+            hb.push_back(e.p);
+            hb.push_back(e.q);
+        }
+    p->bonds_host.swap(hb);   // sorted by (p, q): dir is
     return MSB_OK;
 }
 

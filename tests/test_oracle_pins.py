@@ -594,3 +594,71 @@ def test_precond_is_spd_on_free_dofs():
     z1, z2 = O.precond_apply(p, r1, L, fixed), O.precond_apply(p, r2, L, fixed)
     assert abs((r1 * z2).sum() - (r2 * z1).sum()) <= 1e-13 * abs((r1 * z1).sum())
     assert (r1 * z1).sum() > 0 and (r2 * z2).sum() > 0
+
+
+# ---------------------------------------------------------------- crack propagation (eq. (mu))
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_all_bonds_equals_pair_double_loop(dim):
+    p = _prob2(9, 7, 3) if dim == 2 else _prob3(5, 4, 4, 2)
+    got = {tuple(b) for b in O.all_bonds(p)}
+    n = list(p.n)
+    coords = [np.unravel_index(i, tuple(reversed(n)))[::-1] for i in range(p.N)]
+    want = set()
+    for a in range(p.N):
+        for b in range(a + 1, p.N):
+            if sum((x - y) ** 2 for x, y in zip(coords[a], coords[b])) <= p.M ** 2:
+                want.add((a, b))
+    assert got == want
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_stretch_zero_under_rigid_motion(dim):
+    """Translations and finite rotations leave every bond length unchanged (eq. (fra:s1)
+    is the nonlinear stretch), so nothing breaks at any s0 > 1e-12."""
+    p = _prob2(12, 10, 3) if dim == 2 else _prob3(6, 5, 5, 2)
+    x = p.node_coords()
+    t = 0.7
+    if dim == 2:
+        R = np.array([[math.cos(t), -math.sin(t)], [math.sin(t), math.cos(t)]])
+    else:
+        R = np.array([[1, 0, 0], [0, math.cos(t), -math.sin(t)], [0, math.sin(t), math.cos(t)]])
+    for u in (np.ones((dim, p.N)) * np.arange(1, dim + 1)[:, None], R @ x - x):
+        s = O.bond_stretch(p, u, O.all_bonds(p))
+        assert np.abs(s).max() <= 1e-13
+        new, allb, _ = O.crack_update(p, u, 1e-12)
+        assert len(new) == 0 and len(allb) == 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_uniform_stretch_breaks_the_closed_form_set(dim):
+    """u = eps x_1 e_1: a bond at angle theta to e_1 has s = sqrt((1+eps)^2 cos^2 + sin^2) - 1,
+    so it breaks iff cos^2(theta) >= ((1+s0)^2 - 1) / ((1+eps)^2 - 1); the number of broken
+    bonds is the sum over those offsets o of prod_a (n_a - |o_a|)."""
+    p = _prob2(14, 11, 3) if dim == 2 else _prob3(7, 6, 5, 2)
+    eps, s0 = 0.05, 0.03
+    x = p.node_coords()
+    u = np.zeros_like(x)
+    u[0] = eps * x[0]
+    thresh = ((1 + s0) ** 2 - 1) / ((1 + eps) ** 2 - 1)
+    M = p.M
+    want = 0
+    for o in np.ndindex(*([2 * M + 1] * dim)):
+        o = np.array(o) - M
+        s2 = int((o * o).sum())
+        if s2 == 0 or s2 > M * M:
+            continue
+        lex = next((v for v in o[::-1] if v != 0), 0)   # count each bond once: o > 0 in (z, y, x) order
+        if lex < 0:
+            continue
+        c2 = o[0] ** 2 / s2
+        assert abs(c2 - thresh) > 1e-6                  # no direction at the threshold
+        if c2 >= thresh:
+            want += int(np.prod([m - abs(v) for m, v in zip(p.n, o)]))
+    new, allb, s = O.crack_update(p, u, s0)
+    assert len(new) == want and want > 0
+    # history: bonds already broken are not reported again, the union is kept
+    half = new[: len(new) // 2]
+    new2, allb2, _ = O.crack_update(p, u, s0, half)
+    assert len(new2) == want - len(half)
+    assert np.array_equal(allb2, allb)
