@@ -306,6 +306,29 @@ def bench_crack1024(args):
            "GDOF_steps_per_s": round(w.dofs * w.steps / dt / 1e9, 3),
            "energy_first_last": [float(en[0]), float(en[-1])],
            "n_bonds": plan.n_bonds, "tuned_fp32": tuned}
+    # crack propagation (eq. (mu)): the stretch pass over all 2.1M x 24 half-stencil bonds
+    # plus the count read-back, at a critical stretch no bond reaches (cost of the check);
+    # then Verlet with the check after every step
+    s0 = 1.0
+    plan.crack_update(u, s0)                                             # mask upload, warm
+    torch.cuda.synchronize()
+    reps = 50
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.crack_update(u, s0)
+    per_call = (time.perf_counter() - t0) / reps
+    nsteps = 200
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        plan.vv_run(w.dt, 1, u, v, a, bf)
+        plan.crack_update(u, s0)
+    torch.cuda.synchronize()
+    dtc = time.perf_counter() - t0
+    half = 24   # bonds per node in the half stencil at delta = 4h
+    out["crack_update"] = {"s0": s0, "us_per_call": round(1e6 * per_call, 2),
+                           "bonds_checked": half * w.N, "Gbond_per_s": round(half * w.N / per_call / 1e9, 2),
+                           "verlet_plus_check_steps_per_s": round(nsteps / dtc, 1),
+                           "bytes_per_call": 2 * w.N * 4 + 2 * w.N * 8 + w.N * 4}
     if not args.no_cpu:
         import oracle as O
         p = O.Problem(w.n, w.h, w.M, w.alpha, rho=w.rho)

@@ -331,6 +331,27 @@ msb_status msb_group_solve_static(msb_group group, msb_precision prec, const dou
                                   msb_solve_info *info, void *stream);
 
 /*
+ * Surface correction (Remark 3, eq. (scr)): on the rows of nodes p whose horizon leaves
+ * the grid (Omega_e: within M of a face) every bond {p, q} is scaled by
+ * v_pq = (nu_p + nu_q) / 2, so f_p = sum_q mu_pq v_pq A_pq (u_q - u_p) there; other rows
+ * are unchanged.  The paper leaves v_pq to the cited surface-correction method; per-node
+ * factors averaged over the bond are the form taken here.  nu: host [N] factors (finite,
+ * > 0, shared by the cases), copied; NULL switches the correction off.  Applied as a
+ * banded O(|Omega_e| (2M+1)^d) term in the product's last pass, so msb_apply, the Verlet
+ * run, plan groups' products and the derivative operators of msb_apply_dinfl include
+ * it.  The corrected A is not symmetric: msb_solve_static and msb_group_solve_static
+ * return MSB_EUNSUPPORTED while it is on.
+ */
+msb_status msb_plan_set_surface(msb_plan plan, const double *nu);
+
+/*
+ * Volume factors for msb_plan_set_surface: nu_p = sum over the full discrete horizon of
+ * lambda(o) / the same sum over the neighbours inside the grid, lambda the partial-volume
+ * factor of eq. (fac:e1); 1 on nodes with a complete horizon.  nu: host [N] output.
+ */
+msb_status msb_surface_volume_factors(msb_plan plan, double *nu);
+
+/*
  * Crack propagation, the history-dependent factor mu of eq. (mu): every bond {p, q} not
  * yet broken whose stretch s = (|x_q + u_q - x_p - u_p| - |x_q - x_p|) / |x_q - x_p|
  * (eq. (fra:s1), FP64 from u) satisfies s >= s0 breaks and joins the plan's broken set,

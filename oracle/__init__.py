@@ -7,4 +7,4 @@ from .oracle import (Problem, all_bonds, alpha_2d, alpha_3d, apply, assemble_den
                      broken_csr, crack_update,
                      build_oracle, crack_to_bonds, energy, force, grad_dense, lifted_rhs,
                      generating_blocks, periodic_apply, precond_apply, precond_apply_periodic,
-                     precond_symbol, solve_cg, solve_dense, vv)
+                     precond_symbol, solve_cg, solve_dense, surface_volume_factors, vv)

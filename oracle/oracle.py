@@ -10,7 +10,10 @@ evaluated bond by bond (``oracle_core.c``), the dense stiffness matrix of
 eqs. (matrix)/(mae:e1), and the model equations built on it:
 
 * ``force``/``apply``      -- f = A u, eq. (mat:f1); constrained rows reported as 0
-                              (their content is arbitrary, Remark 1).
+                              (their content is arbitrary, Remark 1); optionally with
+                              the surface correction of Remark 3 / eq. (scr).
+* ``surface_volume_factors`` -- per-node factors nu_p = (full-horizon volume) / (volume
+                              of the horizon inside the grid), partial volumes lambda.
 * ``assemble_dense``       -- A, eq. (matrix); used at small sizes only.
 * ``solve_dense``          -- static model eq. (mat:e2): K = -A, K_FF u_F =
                               b_F - K_FC g_C, u_C = g_C (Sec. 3.4, eq. (up));
@@ -77,7 +80,7 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_force_rows.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_int, P, P, P, P, P,
-                                          ctypes.c_int64, P]
+                                          ctypes.c_int64, P, P]
         lib.oracle_force_rows.restype = None
         lib.oracle_assemble_dense.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
                                               ctypes.c_double, ctypes.c_int, P, P, P, P]
@@ -157,9 +160,12 @@ def _infl_arr(prob: Problem):
     return a, len(a)
 
 
-def force(prob: Problem, u: np.ndarray, broken=None, rows: Optional[np.ndarray] = None) -> np.ndarray:
+def force(prob: Problem, u: np.ndarray, broken=None, rows: Optional[np.ndarray] = None,
+          nu: Optional[np.ndarray] = None) -> np.ndarray:
     """f = A u evaluated bond by bond, eq. (mat:f1), on every row (or on ``rows``).
 
+    nu: per-node surface-correction factors [N] (Remark 3, eq. (scr)): rows of nodes
+    within M of a face scale each bond by (nu_p + nu_q) / 2.
     u: [dim][N] (or flat).  Returns [dim][N] (or [dim][len(rows)])."""
     lib = _load()
     d, N = prob.dim, prob.N
@@ -173,15 +179,17 @@ def force(prob: Problem, u: np.ndarray, broken=None, rows: Optional[np.ndarray] 
     else:
         nr = N
     f = np.empty((d, nr), dtype=np.float64)
+    nuv = None if nu is None else np.ascontiguousarray(np.asarray(nu, dtype=np.float64).reshape(N))
     lib.oracle_force_rows(d, _ptr(n), prob.h, prob.M, prob.alpha, ni,
                           _ptr(infl) if ni else None, _ptr(u), _ptr(ptr), _ptr(idx),
-                          _ptr(rows), nr, _ptr(f))
+                          _ptr(rows), nr, _ptr(nuv), _ptr(f))
     return f
 
 
-def apply(prob: Problem, u: np.ndarray, fixed: Optional[np.ndarray] = None, broken=None) -> np.ndarray:
+def apply(prob: Problem, u: np.ndarray, fixed: Optional[np.ndarray] = None, broken=None,
+          nu: Optional[np.ndarray] = None) -> np.ndarray:
     """f = A u with rows of constrained DOFs reported as 0 (Remark 1)."""
-    f = force(prob, u, broken)
+    f = force(prob, u, broken, nu=nu)
     if fixed is not None:
         f[np.asarray(fixed, dtype=bool).reshape(f.shape)] = 0.0
     return f
@@ -280,7 +288,7 @@ def solve_cg(prob: Problem, b, fixed=None, g=None, broken=None, tol: float = 1e-
 
 
 def vv(prob: Problem, u0, v0, b, dt: float, nsteps: int, fixed=None, g=None, broken=None,
-       energy_every: int = 0):
+       energy_every: int = 0, nu=None):
     """Velocity Verlet, Alg. 2, with acceleration a = (A u + b)/rho (eq. (mat:e1)).
 
     Constrained DOFs are overwritten with g after each displacement update
@@ -298,7 +306,7 @@ def vv(prob: Problem, u0, v0, b, dt: float, nsteps: int, fixed=None, g=None, bro
     v[fx] = 0.0
 
     def accel(uu):
-        a = (force(prob, uu, broken) + b) / prob.rho
+        a = (force(prob, uu, broken, nu=nu) + b) / prob.rho
         a[fx] = 0.0
         return a
 
@@ -559,3 +567,32 @@ def crack_update(prob: Problem, u: np.ndarray, s0: float, broken=None):
     allb = sorted(old | set(new))
     as_arr = lambda v: np.array(v, dtype=np.int64).reshape(-1, 2)
     return as_arr(new), as_arr(allb), s
+
+
+# ---------------------------------------------------------------- surface correction
+def surface_volume_factors(prob: Problem) -> np.ndarray:
+    """nu_p = sum over the full discrete horizon of lambda(o) V / the same sum over the
+    neighbours inside the grid (the volume reading of the surface-correction factor,
+    Remark 3); 1 on nodes with a complete horizon.  lambda as in eq. (fac:e1):
+    1 for |o|^2 <= M^2 - M, else M + 1/2 - |o|."""
+    d, M = prob.dim, prob.M
+    n = list(prob.n)
+    shp = tuple(reversed(n))
+    full = 0.0
+    inside = np.zeros(shp)
+    for o in np.ndindex(*([2 * M + 1] * d)):
+        o = np.array(o) - M
+        s2 = int((o * o).sum())
+        if s2 == 0 or s2 > M * M:
+            continue
+        lam = 1.0 if s2 <= M * M - M else M + 0.5 - math.sqrt(s2)
+        full += lam
+        ok = np.ones(shp, dtype=bool)
+        for a in range(d):   # axis a of the node grid is array axis d - 1 - a
+            idx = np.arange(n[a]) + o[a]
+            good = (idx >= 0) & (idx < n[a])
+            sh = [1] * d
+            sh[d - 1 - a] = n[a]
+            ok &= good.reshape(sh)
+        inside += lam * ok
+    return (full / inside).reshape(-1)

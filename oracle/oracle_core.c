@@ -30,6 +30,12 @@
  * The loop visits, for each node p, the offsets with |o_i| <= M per axis: the
  * block-banded-block bound of eq. (band).  Nothing is precomputed per offset;
  * every bond weight is evaluated from the node coordinates.
+ *
+ * Surface correction (Remark 3, eq. (scr)), when per-node factors nu are given:
+ * on the rows of Omega_e (nodes whose horizon leaves the grid: within M of a
+ * face) every bond is scaled by v_pq = (nu_p + nu_q) / 2; other rows unchanged.
+ * The paper leaves v_pq to the cited surface-correction method; the average of
+ * per-node factors is the reading taken here.
  */
 #include <math.h>
 #include <stdint.h>
@@ -111,7 +117,7 @@ static void node_index(int64_t p, const int64_t n[3], int64_t ip[3])
 void oracle_force_rows(int dim, const int64_t *n, double h, int M, double alpha,
                        int n_infl, const double *infl, const double *u,
                        const int64_t *br_ptr, const int64_t *br_idx,
-                       const int64_t *rows, int64_t nrows, double *f)
+                       const int64_t *rows, int64_t nrows, const double *nu, double *f)
 {
     int64_t nn[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
     int64_t N = nn[0] * nn[1] * nn[2];
@@ -124,6 +130,9 @@ void oracle_force_rows(int dim, const int64_t *n, double h, int M, double alpha,
         int64_t ip[3], iq[3];
         node_index(p, nn, ip);
         double acc[3] = {0, 0, 0};
+        int on_e = 0;   /* p in Omega_e: within M of a face of the grid */
+        for (int a = 0; a < dim; ++a)
+            if (ip[a] < M || ip[a] >= nn[a] - M) on_e = 1;
         for (int64_t oz = -Mz; oz <= Mz; ++oz)
             for (int64_t oy = -M; oy <= M; ++oy)
                 for (int64_t ox = -M; ox <= M; ++ox) {
@@ -134,9 +143,10 @@ void oracle_force_rows(int dim, const int64_t *n, double h, int M, double alpha,
                     if (!bond_tensor(dim, ip, iq, h, M, alpha, n_infl, infl, W)) continue;
                     int64_t q = (iq[2] * nn[1] + iq[1]) * nn[0] + iq[0];
                     if (bond_broken(p, q, br_ptr, br_idx)) continue;  /* mu = 0 */
+                    const double v = (nu && on_e) ? 0.5 * (nu[p] + nu[q]) : 1.0;
                     for (int a = 0; a < dim; ++a)
                         for (int b = 0; b < dim; ++b)
-                            acc[a] += W[a][b] * (u[b * N + q] - u[b * N + p]);
+                            acc[a] += v * W[a][b] * (u[b * N + q] - u[b * N + p]);
                 }
         for (int a = 0; a < dim; ++a) f[a * nrows + r] = acc[a];
     }

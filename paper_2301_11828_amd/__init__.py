@@ -27,7 +27,7 @@ _STATUS = {0: "MSB_OK", -1: "MSB_EINVAL", -2: "MSB_ENOMEM", -3: "MSB_EDEVICE", -
 # every symbol include/msbfm.h declares
 EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "msb_plan_set_bonds",
            "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl", "msb_apply_precond",
-           "msb_crack_update", "msb_plan_get_bonds",
+           "msb_crack_update", "msb_plan_get_bonds", "msb_plan_set_surface", "msb_surface_volume_factors",
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
            "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
            "msb_plan_autotune", "msb_group_create", "msb_group_destroy", "msb_group_get_config",
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH):
         "msb_apply_precond": ([P, I, P, P, P], I),
         "msb_crack_update": ([P, I, P, D, ctypes.POINTER(I64), P], I),
         "msb_plan_get_bonds": ([P, P, I64, ctypes.POINTER(I64)], I),
+        "msb_plan_set_surface": ([P, P], I),
+        "msb_surface_volume_factors": ([P, P], I),
         "msb_solve_static": ([P, I, P, P, P, ctypes.POINTER(_Opts), P, P], I),
         "msb_vv_init": ([P, I, P, P, P, P], I),
         "msb_vv_run": ([P, I, D, I64, P, P, P, P, P, P, I, P], I),
@@ -281,6 +283,21 @@ class Plan:
         p = np.ascontiguousarray(np.asarray(pairs if pairs is not None else np.zeros((0, 2)),
                                             dtype=np.int64).reshape(-1, 2))
         _check(_lib.msb_plan_set_bonds(self._ptr, p.ctypes.data if len(p) else None, len(p)))
+
+    def set_surface(self, nu: Optional[np.ndarray]):
+        """Surface-correction factors per node ([N], or None to switch the correction off)."""
+        if nu is None:
+            _check(_lib.msb_plan_set_surface(self._ptr, None))
+            return
+        a = np.ascontiguousarray(np.asarray(nu, dtype=np.float64).reshape(-1))
+        if a.size != self.N:
+            raise ValueError("nu must hold N = %d values" % self.N)
+        _check(_lib.msb_plan_set_surface(self._ptr, a.ctypes.data))
+
+    def surface_volume_factors(self) -> np.ndarray:
+        out = np.empty(self.N, dtype=np.float64)
+        _check(_lib.msb_surface_volume_factors(self._ptr, out.ctypes.data))
+        return out
 
     def bonds(self) -> np.ndarray:
         """The broken set as [n][2] int64 pairs (p < q), sorted."""

@@ -163,6 +163,12 @@ struct msb_plan_s {
     std::vector<msb::DeviceOp> dop;
     msb::DeviceOp pre;          // circulant preconditioner spectra (built on first use)
 
+    // surface correction (Remark 3, eq. (scr)): per-node factors nu, device [N] in both
+    // precisions, or null; stencil offsets on the device for the correction pass
+    double *nu64 = nullptr;
+    float *nu32 = nullptr;
+    int32_t *off_dev = nullptr;      // [n_off][3]
+
     // constraints
     uint8_t *fixed = nullptr;   // device [d][N] or null
     int64_t n_fixed = 0;

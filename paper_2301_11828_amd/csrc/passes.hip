@@ -574,25 +574,35 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
         T2 *R = team_fft<T, T2, 1, BLOCK, RMAX>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
         T *Rr = reinterpret_cast<T *>(R);   // real row sl of this team at Rr[2 ((sl>>1) Lx + n) + (sl&1)]
 
-        // broken bonds (eq. (tea:fr)): f_p += sum_{q in v_p} W(q - p) (u_p - u_q)
+        const int M = a.M, M1 = a.M + 1;
+        const bool narrow = a.Nx <= 2 * M;   // every column is within M of an x face
+        // broken bonds (eq. (tea:fr)): f_p += sum_{q in v_p} W(q - p) (u_p - u_q); with
+        // the surface correction a bond of a row of Omega_e carries v_pq W, so v_pq W
+        // is removed
         if (a.br_row_ptr && a.corr) {
             const T *wt = a.w + (size_t)b * a.w_slot;
             for (int sl = 0; sl < nsg; ++sl) {
                 const int sig = 2 * s0 + sl;
                 const int c = sig / nr, row = r0 + sig - c * nr;
+                const int z = row / a.Ny, y = row - z * a.Ny;
+                const bool row_e = y < M || y >= a.Ny - M || (d == 3 && (z < M || z >= a.Nz - M));
                 const int e0 = a.br_row_ptr[row], e1 = a.br_row_ptr[row + 1];
                 for (int ei = e0 + tm.tid; ei < e1; ei += tm.nt) {
                     const int node = a.br_node_i[ei];
                     const int n = node - row * a.Nx;
+                    const bool on_e = a.nu && (row_e || n < M || n >= a.Nx - M);
+                    const double nup = on_e ? (double)a.nu[node] : 0.0;
                     double accb = 0.0;
                     for (int t = a.br_bond_ptr[ei]; t < a.br_bond_ptr[ei + 1]; ++t) {
                         const int q = a.br_q[t];
                         const int o = a.br_off[t];
+                        double wb = 0.0;
                         for (int cb = 0; cb < d; ++cb) {
                             const double du = (double)uin[cbase + (size_t)cb * a.N + node] -
                                               (double)uin[cbase + (size_t)cb * a.N + q];
-                            accb += (double)wt[(size_t)comp_of(c, cb, d) * a.n_off + o] * du;
+                            wb += (double)wt[(size_t)comp_of(c, cb, d) * a.n_off + o] * du;
                         }
+                        accb += on_e ? 0.5 * (nup + (double)a.nu[q]) * wb : wb;
                     }
                     Rr[2 * ((size_t)(sl >> 1) * Lx + n) + (sl & 1)] += T(accb);
                 }
@@ -606,10 +616,8 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
         // last M columns, so those are gathered across all rows of the team in one
         // flat loop (one memory round trip for the team instead of one per row).
         const T *de = a.de + (size_t)b * a.de_slot;
-        const int M = a.M, M1 = a.M + 1;
         // table index = (lx (M+1) + hx) (M+1)^(2d-2) + [y and z part, fixed per row]
         const int M1p = d == 2 ? M1 * M1 : M1 * M1 * M1 * M1;
-        const bool narrow = a.Nx <= 2 * M;   // every column is within M of an x face
         auto row_of = [&](int sl, int &c, int &row, int &rpart) -> bool {
             const int sig = 2 * s0 + sl;
             c = sig / nr;
@@ -630,6 +638,40 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
             for (int cb = 0; cb < d; ++cb) f += de[(size_t)comp_of(c, cb, d) * a.de_stride + dx] * urow[(size_t)cb * a.N];
             *fr = f;
         };
+        // surface correction (Remark 3, eq. (scr)): on the nodes of Omega_e (within M of
+        // a face) every bond is scaled by v_pq = (nu_p + nu_q) / 2, i.e. f_p +=
+        // sum_o (v_pq - 1) W(o) (u_{p+o} - u_p) over the neighbours inside the grid
+        // (broken ones included: the D^f term above removed v_pq W for those)
+        if (a.nu && a.corr) {
+            const T *wt = a.w + (size_t)b * a.w_slot;
+            for (int sl = 0; sl < nsg; ++sl) {
+                int c, row, rpart;
+                const bool edge_cols = row_of(sl, c, row, rpart) && !narrow;   // interior row
+                const int z = row / a.Ny, y = row - z * a.Ny;
+                const int ncol = edge_cols ? 2 * M : a.Nx;
+                for (int jj = tm.tid; jj < ncol; jj += tm.nt) {
+                    const int n = edge_cols ? (jj < M ? jj : a.Nx - 2 * M + jj) : jj;
+                    const int node = row * a.Nx + n;
+                    const double nup = (double)a.nu[node];
+                    double acc = 0.0;
+                    for (int o = 0; o < a.n_off; ++o) {
+                        const int ox = a.offs[3 * o], oy = a.offs[3 * o + 1], oz = a.offs[3 * o + 2];
+                        const int xx = n + ox, yy = y + oy, zz = z + oz;
+                        if (xx < 0 || xx >= a.Nx || yy < 0 || yy >= a.Ny || zz < 0 || zz >= a.Nz) continue;
+                        const int q = node + (oz * a.Ny + oy) * a.Nx + ox;
+                        double wb = 0.0;
+                        for (int cb = 0; cb < d; ++cb) {
+                            const double du = (double)uin[cbase + (size_t)cb * a.N + q] -
+                                              (double)uin[cbase + (size_t)cb * a.N + node];
+                            wb += (double)wt[(size_t)comp_of(c, cb, d) * a.n_off + o] * du;
+                        }
+                        acc += (0.5 * (nup + (double)a.nu[q]) - 1.0) * wb;
+                    }
+                    Rr[2 * ((size_t)(sl >> 1) * Lx + n) + (sl & 1)] += T(acc);
+                }
+            }
+            tm.sync();
+        }
         // (whole-workgroup teams apply D^e inline in the epilogue instead: there only
         // the waves holding boundary columns wait for the table, with no extra barrier)
         if (!BLOCK && !narrow && a.corr) {
@@ -923,6 +965,8 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.de_stride = p->de_stride;
     a.n_off = p->n_off;
     a.fixed = p->fixed;
+    a.nu = sel<T>(p->nu64, p->nu32);
+    a.offs = p->off_dev;
     a.br_row_ptr = p->n_pairs ? p->br_row_ptr : nullptr;
     a.br_node_i = p->br_node_i;
     a.br_bond_ptr = p->br_bond_ptr;

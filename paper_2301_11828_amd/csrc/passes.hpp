@@ -51,6 +51,10 @@ template <typename T> struct PassArgs {
     size_t w_slot;
     int de_stride;       // (M+1)^(2d)
     int n_off;
+    // surface correction: per-node factors [N] (null: off) and the stencil offsets
+    // [n_off][3] in the order of the weight table w
+    const T *nu;
+    const int32_t *offs;
     // constraints and bonds
     const uint8_t *fixed;          // [d][N] or null
     const int32_t *br_row_ptr;     // [rows+1] or null

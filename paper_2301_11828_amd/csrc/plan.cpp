@@ -607,6 +607,7 @@ extern "C" msb_status msb_plan_create(const msb_problem_desc *desc, msb_plan *ou
     for (int q = 0; q < 2 * p->dim; ++q) p->de_stride *= (p->M + 1);
     build_offsets(p);
     msb_status st = check_lengths(p, p->L);
+    if (st == MSB_OK) st = upload(&p->off_dev, std::vector<int32_t>(p->off.begin(), p->off.end()));
     if (st == MSB_OK) st = build_layout(p);
     if (st != MSB_OK) {
         msb_plan_destroy(p);
@@ -623,7 +624,8 @@ extern "C" void msb_plan_destroy(msb_plan p) {
     free_operator(p->op);
     free_operator(p->pre);
     for (auto &o : p->dop) free_operator(o);
-    void *bufs[] = {p->fixed, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off, p->T1, p->T2};
+    void *bufs[] = {p->fixed, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off, p->T1, p->T2,
+                    p->nu64, p->nu32, p->off_dev};
     for (void *b : bufs)
         if (b) hipFree(b);
     solver_cache_free(p);
@@ -665,6 +667,54 @@ extern "C" msb_status msb_plan_set_bonds(msb_plan p, const int64_t *pairs, int64
     MSB_CHECK(p, MSB_EINVAL, "null plan");
     MSB_TRY(msb::set_bonds_impl(p, pairs, nb));
     p->mu_valid = false;
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_plan_set_surface(msb_plan p, const double *nu) {
+    MSB_CHECK(p, MSB_EINVAL, "null plan");
+    if (!nu) {
+        if (p->nu64) hipFree(p->nu64);
+        if (p->nu32) hipFree(p->nu32);
+        p->nu64 = nullptr;
+        p->nu32 = nullptr;
+        return MSB_OK;
+    }
+    std::vector<double> v(nu, nu + p->N);
+    for (int64_t i = 0; i < p->N; ++i)
+        MSB_CHECK(std::isfinite(v[i]) && v[i] > 0.0, MSB_EINVAL, "surface factor %lld must be finite and > 0",
+                  (long long)i);
+    MSB_TRY(upload(&p->nu64, v));
+    MSB_TRY(upload(&p->nu32, std::vector<float>(v.begin(), v.end())));
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_surface_volume_factors(msb_plan p, double *nu) {
+    MSB_CHECK(p && nu, MSB_EINVAL, "null argument");
+    const int d = p->dim, M = p->M;
+    std::vector<double> lam(p->n_off);
+    double full = 0.0;
+    for (int i = 0; i < p->n_off; ++i) {
+        const int *o = &p->off[3 * i];
+        const long long s2 = (long long)o[0] * o[0] + (long long)o[1] * o[1] + (long long)o[2] * o[2];
+        lam[i] = s2 <= (long long)M * M - M ? 1.0 : M + 0.5 - std::sqrt((double)s2);
+        full += lam[i];
+    }
+    const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const bool inner = i >= M && i < nx - M && j >= M && j < ny - M && (d == 2 || (k >= M && k < nz - M));
+                double in = full;
+                if (!inner) {
+                    in = 0.0;
+                    for (int t = 0; t < p->n_off; ++t) {
+                        const int *o = &p->off[3 * t];
+                        const int64_t x = i + o[0], y = j + o[1], z = k + o[2];
+                        if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) in += lam[t];
+                    }
+                }
+                nu[(k * ny + j) * nx + i] = full / in;
+            }
     return MSB_OK;
 }
 

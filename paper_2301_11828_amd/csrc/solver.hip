@@ -662,6 +662,7 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
     MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32 || prec == MSB_FP32_REFINED, MSB_EINVAL, "bad precision");
     MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
     MSB_CHECK(opts->precond == 0 || opts->precond == 1, MSB_EINVAL, "precond must be 0 or 1");
+    MSB_CHECK(!p->nu64, MSB_EUNSUPPORTED, "the surface-corrected operator is not symmetric: no CG solve");
     MSB_CHECK(!(opts->precond && opts->reliable_update), MSB_EUNSUPPORTED,
               "the preconditioned solver refines by restarts only (reliable_update = 0)");
     const bool pre = opts->precond != 0;
@@ -1425,6 +1426,8 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
     MSB_CHECK(opts->reliable_update == 0, MSB_EUNSUPPORTED, "groups refine by restarts only (reliable_update = 0)");
     MSB_CHECK(opts->precond == 0, MSB_EUNSUPPORTED, "groups solve without the preconditioner (precond = 0)");
+    for (int i = 0; i < g->n; ++i)
+        MSB_CHECK(!g->m[i]->nu64, MSB_EUNSUPPORTED, "member %d: the surface-corrected operator is not symmetric", i);
     int dev = -1;
     MSB_HIP(hipGetDevice(&dev));
     MSB_CHECK(dev == g->device, MSB_EINVAL, "group was created on device %d, current is %d", g->device, dev);

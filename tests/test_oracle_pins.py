@@ -662,3 +662,60 @@ def test_uniform_stretch_breaks_the_closed_form_set(dim):
     new2, allb2, _ = O.crack_update(p, u, s0, half)
     assert len(new2) == want - len(half)
     assert np.array_equal(allb2, allb)
+
+
+# ---------------------------------------------------------------- surface correction (Remark 3)
+
+def _omega_e(p):
+    """Nodes within M of a face (incomplete horizon)."""
+    n = list(p.n)
+    coords = np.stack(np.unravel_index(np.arange(p.N), tuple(reversed(n)))[::-1])
+    on = np.zeros(p.N, dtype=bool)
+    for a in range(p.dim):
+        on |= (coords[a] < p.M) | (coords[a] >= n[a] - p.M)
+    return on
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_surface_constant_factor_scales_edge_rows(dim):
+    """nu = c everywhere: v_pq = c on the rows of Omega_e, so those rows are c f and every
+    other row is f; nu = 1 is the plain sum."""
+    rng = np.random.default_rng(61 + dim)
+    p = _prob2(13, 11, 3) if dim == 2 else _prob3(8, 7, 7, 2)
+    br = _random_bonds(p, 15, 62)
+    u = rng.standard_normal((dim, p.N))
+    f = O.force(p, u, br)
+    assert np.array_equal(O.force(p, u, br, nu=np.ones(p.N)), f)
+    fc = O.force(p, u, br, nu=np.full(p.N, 1.7))
+    on = _omega_e(p)
+    assert np.allclose(fc[:, on], 1.7 * f[:, on], rtol=1e-13, atol=1e-13 * np.abs(f).max())
+    assert np.array_equal(fc[:, ~on], f[:, ~on])
+    assert on.any() and (~on).any()
+
+
+def test_surface_rigid_translation_and_interior_rows():
+    """Any factors: a translation still gives zero force (each bond term has u_q - u_p),
+    and rows off Omega_e are untouched."""
+    rng = np.random.default_rng(63)
+    p = _prob2(14, 12, 3)
+    nu = rng.uniform(0.5, 2.0, p.N)
+    t = np.ones((2, p.N)) * np.array([[0.3], [-1.1]])
+    assert np.abs(O.force(p, t, nu=nu)).max() <= 1e-12 * np.abs(O.force(p, rng.standard_normal((2, p.N)))).max()
+    u = rng.standard_normal((2, p.N))
+    on = _omega_e(p)
+    assert np.array_equal(O.force(p, u, nu=nu)[:, ~on], O.force(p, u)[:, ~on])
+
+
+def test_surface_volume_factors_closed_form():
+    """M = 1 (4 neighbours, lambda = 1/2 each): corner 4/2 = 2, edge 4/3, interior 1.
+    M = 3: a node at distance 2 from one face lacks only the offset (-3, 0) of weight 1/2."""
+    p = _prob2(5, 4, 1)
+    nu = O.surface_volume_factors(p).reshape(4, 5)
+    assert nu[0, 0] == 2.0 and nu[3, 4] == 2.0 and nu[0, 2] == pytest.approx(4 / 3, abs=1e-15)
+    assert nu[1, 2] == 1.0
+    p3 = _prob2(12, 12, 3)
+    nu3 = O.surface_volume_factors(p3).reshape(12, 12)
+    lam = [1.0 if s2 <= 6 else 3.5 - math.sqrt(s2)
+           for s2 in (ox * ox + oy * oy for oy in range(-3, 4) for ox in range(-3, 4)) if 0 < s2 <= 9]
+    full = sum(lam)
+    assert nu3[5, 2] == pytest.approx(full / (full - 0.5), rel=1e-14)
