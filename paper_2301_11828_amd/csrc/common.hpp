@@ -186,7 +186,7 @@ struct msb_plan_s {
     // crack propagation (crack.hip): broken-bond bit mask over the half stencil
     // (offsets o with p + o > p), one bit per bond {p, p + o}; rebuilt from bonds_host
     // when stale
-    uint64_t *mu_mask = nullptr;     // [N][mu_words]
+    uint32_t *mu_mask = nullptr;     // [N][mu_words]
     int mu_words = 0;
     bool mu_valid = false;
     void *crack_ws = nullptr;        // crack.hip workspace

@@ -4,8 +4,9 @@
 // correction D^f (eq. (df)).  The paper's Phase III (Sec. 5.2) evaluates s for every
 // bond each step; here that is one data-parallel pass over the nodes (each thread a
 // node p and the half stencil, bonds to q = p + o > p), reading the broken set as a
-// bit mask, followed by a deterministic compaction of the new breaks (per-block counts,
-// one scan, then every block writes its nodes' breaks in node and offset order).  The
+// bit mask, followed by a deterministic compaction of the new breaks (per-node counts,
+// one scan of the block totals, then every block writes its nodes' breaks in node and
+// offset order).  The
 // new pairs are merged into the plan's broken list, which rebuilds the D^f lists.
 #include <algorithm>
 #include <array>
@@ -18,19 +19,23 @@
 namespace msb {
 namespace {
 
-constexpr int kCT = 256;   // threads per block of the stretch and emit passes
+constexpr int kCT = 256;        // threads per block of the stretch and emit passes
+constexpr int kScanT = 1024;    // threads of the one-block scan
+constexpr int kMaxWords = 8;    // mask words per node: half stencils of up to 256 bonds
 
 struct CrackWs {
     int nh = 0;                 // half-stencil offsets
     int *hoff = nullptr;        // [nh][3]
-    double *hlen = nullptr;     // [nh] |o| h
-    uint64_t *fresh = nullptr;  // [N][words] bonds that break in this update
-    int *count = nullptr;       // [N] new breaks per node
+    double *thr2 = nullptr;     // [nh] ((1 + s0) |o| h)^2 of the current call
+    uint8_t *count = nullptr;   // [N] new breaks per node
     int64_t *blk = nullptr;     // [nblk + 1] per-block counts, then their exclusive scan
     int64_t *pairs = nullptr;   // [cap][2]
     int64_t cap = 0;
     int64_t *h_total = nullptr; // pinned
+    double *h_thr2 = nullptr;   // pinned [nh]
+    double s0 = -1.0;           // critical stretch thr2 holds (uploaded again when it changes)
     std::vector<int> hoff_host; // [nh][3]
+    std::vector<double> len;    // [nh] |o| h
 };
 
 // Half stencil: offsets o of the plan's stencil with node id p + o > p, i.e. o > 0 in
@@ -57,39 +62,41 @@ msb_status get_crack_ws(msb_plan_s *p, CrackWs *&out) {
         out = static_cast<CrackWs *>(p->crack_ws);
         return MSB_OK;
     }
+    std::vector<int> hoff = half_stencil(p);
+    const int nh = (int)hoff.size() / 3;
+    // per-node counts are bytes: at most 255 bonds per node in the half stencil
+    MSB_CHECK(nh <= 255, MSB_EUNSUPPORTED, "crack propagation supports up to 255 bonds per node "
+              "in the half stencil (this horizon has %d)", nh);
     CrackWs *w = new CrackWs();
     p->crack_ws = w;
-    w->hoff_host = half_stencil(p);
-    w->nh = (int)w->hoff_host.size() / 3;
-    std::vector<double> len(w->nh);
-    for (int k = 0; k < w->nh; ++k) {
+    w->hoff_host = hoff;
+    w->nh = nh;
+    w->len.resize(nh);
+    for (int k = 0; k < nh; ++k) {
         double s2 = 0.0;
         for (int c = 0; c < 3; ++c) {
-            const double x = w->hoff_host[3 * k + c] * p->h;
+            const double x = hoff[3 * k + c] * p->h;
             s2 += x * x;
         }
-        len[k] = std::sqrt(s2);
+        w->len[k] = std::sqrt(s2);
     }
-    p->mu_words = std::max(1, (w->nh + 63) / 64);
+    p->mu_words = std::max(1, (nh + 31) / 32);
     const size_t N = (size_t)p->N;
     const size_t nblk = (N + kCT - 1) / kCT;
-    MSB_HIP(hipMalloc(&w->hoff, sizeof(int) * std::max<size_t>(1, w->hoff_host.size())));
-    MSB_HIP(hipMalloc(&w->hlen, sizeof(double) * std::max(1, w->nh)));
-    if (w->nh) {
-        MSB_HIP(hipMemcpy(w->hoff, w->hoff_host.data(), sizeof(int) * w->hoff_host.size(), hipMemcpyHostToDevice));
-        MSB_HIP(hipMemcpy(w->hlen, len.data(), sizeof(double) * w->nh, hipMemcpyHostToDevice));
-    }
-    MSB_HIP(hipMalloc(&p->mu_mask, sizeof(uint64_t) * N * p->mu_words));
-    MSB_HIP(hipMalloc(&w->fresh, sizeof(uint64_t) * N * p->mu_words));
-    MSB_HIP(hipMalloc(&w->count, sizeof(int) * N));
+    MSB_HIP(hipMalloc(&w->hoff, sizeof(int) * std::max<size_t>(1, hoff.size())));
+    MSB_HIP(hipMalloc(&w->thr2, sizeof(double) * std::max(1, nh)));
+    if (nh) MSB_HIP(hipMemcpy(w->hoff, hoff.data(), sizeof(int) * hoff.size(), hipMemcpyHostToDevice));
+    MSB_HIP(hipMalloc(&p->mu_mask, sizeof(uint32_t) * N * p->mu_words));
+    MSB_HIP(hipMalloc(&w->count, N));
     MSB_HIP(hipMalloc(&w->blk, sizeof(int64_t) * (nblk + 1)));
     MSB_HIP(hipHostMalloc(&w->h_total, sizeof(int64_t)));
+    MSB_HIP(hipHostMalloc(&w->h_thr2, sizeof(double) * std::max(1, nh)));
     p->mu_valid = false;
     out = w;
     return MSB_OK;
 }
 
-// Bit k of mask word (p, k / 64) <-> bond {p, p + half[k]} broken, from the host list.
+// Bit k of mask word (p, k / 32) <-> bond {p, p + half[k]} broken, from the host list.
 msb_status upload_mask(msb_plan_s *p, CrackWs *w) {
     const int64_t nx = p->n[0], ny = p->n[1];
     const int M = p->M, S = 2 * M + 1;
@@ -98,7 +105,7 @@ msb_status upload_mask(msb_plan_s *p, CrackWs *w) {
         const int *o = &w->hoff_host[3 * k];
         lut[((size_t)(o[2] + M) * S + (o[1] + M)) * S + (o[0] + M)] = k;
     }
-    std::vector<uint64_t> mask((size_t)p->N * p->mu_words, 0);
+    std::vector<uint32_t> mask((size_t)p->N * p->mu_words, 0);
     for (int64_t e = 0; e < p->n_pairs; ++e) {
         const int64_t a = p->bonds_host[2 * e], b = p->bonds_host[2 * e + 1];   // a < b
         const int64_t ia[3] = {a % nx, (a / nx) % ny, a / (nx * ny)};
@@ -106,60 +113,100 @@ msb_status upload_mask(msb_plan_s *p, CrackWs *w) {
         const int k = lut[((size_t)(ib[2] - ia[2] + M) * S + (ib[1] - ia[1] + M)) * S + (ib[0] - ia[0] + M)];
         MSB_CHECK(k >= 0, MSB_EINVAL, "broken bond (%lld, %lld) is not in the half stencil", (long long)a,
                   (long long)b);
-        mask[(size_t)a * p->mu_words + (k >> 6)] |= 1ull << (k & 63);
+        mask[(size_t)a * p->mu_words + (k >> 5)] |= 1u << (k & 31);
     }
-    MSB_HIP(hipMemcpy(p->mu_mask, mask.data(), sizeof(uint64_t) * mask.size(), hipMemcpyHostToDevice));
+    MSB_HIP(hipMemcpy(p->mu_mask, mask.data(), sizeof(uint32_t) * mask.size(), hipMemcpyHostToDevice));
     p->mu_valid = true;
     return MSB_OK;
 }
 
 struct Grid {
     int d, nx, ny, nz, N, nh, words;
-    double h, s0;
 };
 
-// One thread per node p: the stretch of every unbroken bond {p, p + o} of the half
-// stencil (FP64 from the given displacements); fresh = bonds with s >= s0, count =
-// their number, blk = the block's total.
-template <typename T>
+// The bonds {p, p + o} of the half stencil that are unbroken and break now: with
+// l = |o| h and l' = |o h + u_{p+o} - u_p| (FP64 from the given displacements), the
+// stretch s = (l' - l) / l of eq. (fra:s1) reaches s0 exactly when l'^2 >= ((1 + s0) l)^2
+// (thr2, one value per offset), so neither a square root nor a division is needed.
+// Branch-free over the offsets (a bond outside the grid or already broken reads node p
+// itself and is masked out), so the loads of several bonds are in flight at once.
+// nw: the new bits per mask word; returns their number.
+template <typename T, int D>
+__device__ __forceinline__ int node_breaks(const Grid &g, const T *__restrict__ u, const int *__restrict__ hoff,
+                                           const double *__restrict__ thr2, const uint32_t *__restrict__ mu,
+                                           int p, uint32_t (&nw)[kMaxWords], double h) {
+    const int i = p % g.nx, j = (p / g.nx) % g.ny, k = p / (g.nx * g.ny);
+    double up[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) up[c] = (double)u[(size_t)c * g.N + p];
+    int cnt = 0;
+    for (int wd = 0; wd < g.words; ++wd) {
+        const uint32_t old = mu[(size_t)p * g.words + wd];
+        uint32_t bits = 0;
+        const int kend = min(g.nh, 32 * (wd + 1));
+#pragma unroll 4
+        for (int b = 32 * wd; b < kend; ++b) {
+            const int ox = hoff[3 * b], oy = hoff[3 * b + 1], oz = hoff[3 * b + 2];
+            const bool ok = !((old >> (b & 31)) & 1u) && (unsigned)(i + ox) < (unsigned)g.nx &&
+                            (unsigned)(j + oy) < (unsigned)g.ny && (unsigned)(k + oz) < (unsigned)g.nz;
+            const int q = ok ? p + (oz * g.ny + oy) * g.nx + ox : p;
+            const int o3[3] = {ox, oy, oz};
+            double s2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const double e = o3[c] * h + ((double)u[(size_t)c * g.N + q] - up[c]);
+                s2 += e * e;
+            }
+            if (ok && s2 >= thr2[b]) {
+                bits |= 1u << (b & 31);
+                ++cnt;
+            }
+        }
+        nw[wd] = bits;
+    }
+    return cnt;
+}
+
+// Exclusive block scan of one value per thread (blockDim a multiple of 64, <= 1024):
+// wave shuffles, then the wave totals scanned by wave 0.  *total = the block's sum.
+__device__ __forceinline__ long long block_exclusive_scan(long long x, long long *wsum, long long *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    long long inc = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    if (wv == 0) {
+        const long long t = lane < nw ? wsum[lane] : 0;
+        long long it = t;
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long y = __shfl_up(it, off, 64);
+            if (lane >= off) it += y;
+        }
+        if (lane < nw) wsum[lane] = it - t;
+        if (lane == nw - 1) wsum[16] = it;
+    }
+    __syncthreads();
+    *total = wsum[16];
+    return wsum[wv] + inc - x;
+}
+
+// One thread per node: count of the bonds that break now (fresh bits are not stored:
+// the emit pass recomputes them for the few nodes with a break); block totals to blk.
+template <typename T, int D>
 __global__ __launch_bounds__(kCT) void k_stretch(Grid g, const T *__restrict__ u, const int *__restrict__ hoff,
-                                                 const double *__restrict__ hlen, const uint64_t *__restrict__ mu,
-                                                 uint64_t *__restrict__ fresh, int *__restrict__ count,
-                                                 int64_t *__restrict__ blk) {
+                                                 const double *__restrict__ thr2, const uint32_t *__restrict__ mu,
+                                                 uint8_t *__restrict__ count, int64_t *__restrict__ blk, double h) {
     __shared__ int red[kCT / 64];
     const int p = blockIdx.x * kCT + threadIdx.x;
     int cnt = 0;
     if (p < g.N) {
-        const int i = p % g.nx, j = (p / g.nx) % g.ny, k = p / (g.nx * g.ny);
-        double up[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < g.d; ++c) up[c] = (double)u[(size_t)c * g.N + p];
-        for (int wd = 0; wd < g.words; ++wd) {
-            const uint64_t old = mu[(size_t)p * g.words + wd];
-            uint64_t nw = 0;
-            const int kend = min(g.nh, 64 * (wd + 1));
-            for (int b = 64 * wd; b < kend; ++b) {
-                if ((old >> (b & 63)) & 1ull) continue;
-                const int ox = hoff[3 * b], oy = hoff[3 * b + 1], oz = hoff[3 * b + 2];
-                const int ii = i + ox, jj = j + oy, kk = k + oz;
-                if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) continue;
-                const int q = p + (oz * g.ny + oy) * g.nx + ox;
-                const int o3[3] = {ox, oy, oz};
-                double s2 = 0.0;
-                for (int c = 0; c < g.d; ++c) {
-                    const double e = o3[c] * g.h + ((double)u[(size_t)c * g.N + q] - up[c]);
-                    s2 += e * e;
-                }
-                const double s = (sqrt(s2) - hlen[b]) / hlen[b];
-                if (s >= g.s0) {
-                    nw |= 1ull << (b & 63);
-                    ++cnt;
-                }
-            }
-            fresh[(size_t)p * g.words + wd] = nw;
-        }
-        count[p] = cnt;
+        uint32_t nw[kMaxWords];
+        cnt = node_breaks<T, D>(g, u, hoff, thr2, mu, p, nw, h);
+        count[p] = (uint8_t)cnt;
     }
-    // block total (the wave sums, then wave 0 adds them)
     int v = cnt;
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -171,63 +218,58 @@ __global__ __launch_bounds__(kCT) void k_stretch(Grid g, const T *__restrict__ u
     }
 }
 
-// Exclusive scan of blk[0..n) in place, blk[n] = total; one block of kCT threads,
-// chunks of kCT with a running carry.
-__global__ __launch_bounds__(kCT) void k_scan(int64_t *blk, int n) {
-    __shared__ int64_t s[kCT];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < n; base += kCT) {
-        const int i = base + threadIdx.x;
-        const int64_t x = i < n ? blk[i] : 0;
-        s[threadIdx.x] = x;
-        __syncthreads();
-        for (int off = 1; off < kCT; off <<= 1) {   // Hillis-Steele inclusive scan
-            const int64_t y = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-            __syncthreads();
-            s[threadIdx.x] += y;
-            __syncthreads();
-        }
-        const int64_t c0 = carry;
-        if (i < n) blk[i] = c0 + s[threadIdx.x] - x;
-        __syncthreads();
-        if (threadIdx.x == kCT - 1) carry = c0 + s[kCT - 1];
-        __syncthreads();
+// Exclusive scan of blk[0..n) in place, blk[n] = total; one block, each thread a
+// contiguous run of ceil(n / kScanT) values.
+__global__ __launch_bounds__(kScanT) void k_scan(int64_t *blk, int n) {
+    __shared__ long long wsum[17];
+    const int per = (n + kScanT - 1) / kScanT;
+    const int b0 = min(n, threadIdx.x * per), b1 = min(n, b0 + per);
+    long long s = 0;
+    for (int i = b0; i < b1; ++i) s += blk[i];
+    long long total = 0;
+    long long run = block_exclusive_scan(s, wsum, &total);
+    for (int i = b0; i < b1; ++i) {
+        const long long x = blk[i];
+        blk[i] = run;
+        run += x;
     }
-    if (threadIdx.x == 0) blk[n] = carry;
+    if (threadIdx.x == 0) blk[n] = total;
 }
 
 // Every block writes its nodes' new breaks (p, p + o) from offset blk[block] on, in
-// node order and, per node, in half-stencil order; and marks them broken in mu.
-__global__ __launch_bounds__(kCT) void k_emit(Grid g, const int *__restrict__ hoff, const int *__restrict__ count,
-                                              const uint64_t *__restrict__ fresh, uint64_t *__restrict__ mu,
-                                              const int64_t *__restrict__ blk, int64_t *__restrict__ pairs) {
-    __shared__ int s[kCT];
+// node order and, per node, in half-stencil order, and marks them broken in mu.  A node
+// writes exactly count[p] entries (fewer found would leave (-1, -1), which the host
+// rejects), so the writes stay inside the scanned range.
+template <typename T, int D>
+__global__ __launch_bounds__(kCT) void k_emit(Grid g, const T *__restrict__ u, const int *__restrict__ hoff,
+                                              const double *__restrict__ thr2, uint32_t *__restrict__ mu,
+                                              const uint8_t *__restrict__ count, const int64_t *__restrict__ blk,
+                                              int64_t *__restrict__ pairs, double h) {
+    __shared__ long long wsum[17];
     const int p = blockIdx.x * kCT + threadIdx.x;
     const int c = p < g.N ? count[p] : 0;
-    s[threadIdx.x] = c;
-    __syncthreads();
-    for (int off = 1; off < kCT; off <<= 1) {
-        const int y = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-        __syncthreads();
-        s[threadIdx.x] += y;
-        __syncthreads();
-    }
-    if (p >= g.N || c == 0) return;
-    int64_t at = blk[blockIdx.x] + s[threadIdx.x] - c;
+    long long total = 0;
+    const long long off = block_exclusive_scan(c, wsum, &total);
+    if (c == 0) return;
+    uint32_t nw[kMaxWords];
+    node_breaks<T, D>(g, u, hoff, thr2, mu, p, nw, h);
+    int64_t at = blk[blockIdx.x] + off;
+    const int64_t end = at + c;
     for (int wd = 0; wd < g.words; ++wd) {
-        const uint64_t nw = fresh[(size_t)p * g.words + wd];
-        if (!nw) continue;
-        mu[(size_t)p * g.words + wd] |= nw;
-        for (int b = 0; b < 64; ++b) {
-            if (!((nw >> b) & 1ull)) continue;
-            const int kk = 64 * wd + b;
-            const int q = p + (hoff[3 * kk + 2] * g.ny + hoff[3 * kk + 1]) * g.nx + hoff[3 * kk];
+        const uint32_t bits = nw[wd];
+        if (!bits) continue;
+        mu[(size_t)p * g.words + wd] |= bits;
+        for (int b = 0; b < 32 && at < end; ++b) {
+            if (!((bits >> b) & 1u)) continue;
+            const int kk = 32 * wd + b;
             pairs[2 * at] = p;
-            pairs[2 * at + 1] = q;
+            pairs[2 * at + 1] = p + (hoff[3 * kk + 2] * g.ny + hoff[3 * kk + 1]) * g.nx + hoff[3 * kk];
             ++at;
         }
+    }
+    for (; at < end; ++at) {
+        pairs[2 * at] = -1;
+        pairs[2 * at + 1] = -1;
     }
 }
 
@@ -238,11 +280,23 @@ msb_status crack_update_t(msb_plan_s *p, const T *u, double s0, int64_t *n_new, 
     if (!p->mu_valid) MSB_TRY(upload_mask(p, w));
     *n_new = 0;
     if (w->nh == 0) return MSB_OK;
-    const Grid g{p->dim, (int)p->n[0], (int)p->n[1], (int)p->n[2], (int)p->N, w->nh, p->mu_words, p->h, s0};
+    if (s0 != w->s0) {
+        for (int k = 0; k < w->nh; ++k) {
+            const double l = (1.0 + s0) * w->len[k];
+            w->h_thr2[k] = l * l;
+        }
+        MSB_HIP(hipMemcpyAsync(w->thr2, w->h_thr2, sizeof(double) * w->nh, hipMemcpyHostToDevice, st));
+        w->s0 = s0;
+    }
+    const Grid g{p->dim, (int)p->n[0], (int)p->n[1], (int)p->n[2], (int)p->N, w->nh, p->mu_words};
     const int nblk = (int)((p->N + kCT - 1) / kCT);
-    hipLaunchKernelGGL(k_stretch<T>, dim3(nblk), dim3(kCT), 0, st, g, u, (const int *)w->hoff,
-                       (const double *)w->hlen, (const uint64_t *)p->mu_mask, w->fresh, w->count, w->blk);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kCT), 0, st, w->blk, nblk);
+    if (p->dim == 2)
+        hipLaunchKernelGGL((k_stretch<T, 2>), dim3(nblk), dim3(kCT), 0, st, g, u, (const int *)w->hoff,
+                           (const double *)w->thr2, (const uint32_t *)p->mu_mask, w->count, w->blk, p->h);
+    else
+        hipLaunchKernelGGL((k_stretch<T, 3>), dim3(nblk), dim3(kCT), 0, st, g, u, (const int *)w->hoff,
+                           (const double *)w->thr2, (const uint32_t *)p->mu_mask, w->count, w->blk, p->h);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanT), 0, st, w->blk, nblk);
     MSB_HIP(hipGetLastError());
     MSB_HIP(hipMemcpyAsync(w->h_total, w->blk + nblk, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     MSB_HIP(hipStreamSynchronize(st));
@@ -255,15 +309,27 @@ msb_status crack_update_t(msb_plan_s *p, const T *u, double s0, int64_t *n_new, 
         MSB_HIP(hipMalloc(&w->pairs, sizeof(int64_t) * 2 * total));
         w->cap = total;
     }
-    hipLaunchKernelGGL(k_emit, dim3(nblk), dim3(kCT), 0, st, g, (const int *)w->hoff, (const int *)w->count,
-                       (const uint64_t *)w->fresh, p->mu_mask, (const int64_t *)w->blk, w->pairs);
+    if (p->dim == 2)
+        hipLaunchKernelGGL((k_emit<T, 2>), dim3(nblk), dim3(kCT), 0, st, g, u, (const int *)w->hoff,
+                           (const double *)w->thr2, p->mu_mask, (const uint8_t *)w->count, (const int64_t *)w->blk,
+                           w->pairs, p->h);
+    else
+        hipLaunchKernelGGL((k_emit<T, 3>), dim3(nblk), dim3(kCT), 0, st, g, u, (const int *)w->hoff,
+                           (const double *)w->thr2, p->mu_mask, (const uint8_t *)w->count, (const int64_t *)w->blk,
+                           w->pairs, p->h);
     MSB_HIP(hipGetLastError());
     std::vector<int64_t> fresh((size_t)2 * total);
     MSB_HIP(hipMemcpyAsync(fresh.data(), w->pairs, sizeof(int64_t) * 2 * total, hipMemcpyDeviceToHost, st));
     MSB_HIP(hipStreamSynchronize(st));
     // merge into the sorted broken list (both sorted by (p, q) after sorting the new ones)
     std::vector<std::pair<int64_t, int64_t>> nv((size_t)total);
-    for (int64_t e = 0; e < total; ++e) nv[e] = {fresh[2 * e], fresh[2 * e + 1]};
+    for (int64_t e = 0; e < total; ++e) {
+        nv[e] = {fresh[2 * e], fresh[2 * e + 1]};
+        if (nv[e].first < 0) {
+            p->mu_valid = false;
+            MSB_CHECK(false, MSB_EDEVICE, "crack update: the emit pass disagreed with the count pass");
+        }
+    }
     std::sort(nv.begin(), nv.end());
     const std::vector<int64_t> &old = p->bonds_host;
     std::vector<int64_t> merged;
@@ -297,10 +363,11 @@ msb_status crack_update_t(msb_plan_s *p, const T *u, double s0, int64_t *n_new, 
 void crack_free(msb_plan_s *p) {
     CrackWs *w = static_cast<CrackWs *>(p->crack_ws);
     if (w) {
-        void *b[] = {w->hoff, w->hlen, w->fresh, w->count, w->blk, w->pairs};
+        void *b[] = {w->hoff, w->thr2, w->count, w->blk, w->pairs};
         for (void *x : b)
             if (x) (void)hipFree(x);
         if (w->h_total) (void)hipHostFree(w->h_total);
+        if (w->h_thr2) (void)hipHostFree(w->h_thr2);
         delete w;
         p->crack_ws = nullptr;
     }

@@ -29,7 +29,8 @@ def source_hash() -> str:
 
 
 def _short(name: str) -> str:
-    for k in ("k_xfwd", "k_line_y", "k_line_z", "k_xinv", "k_yfwd", "k_yinv", "k_cg_case4", "k_dot_parts"):
+    for k in ("k_xfwd", "k_line_y", "k_line_z", "k_xinv", "k_yfwd", "k_yinv", "k_cg_sums", "k_dot_parts",
+              "k_stretch", "k_scan", "k_emit"):
         if k in name:
             prec = "double" if "<double" in name else ("float" if "<float" in name else "")
             return "%s<%s%s>" % (k, prec, ",wave" if "false" in name.split(k)[1][:40] else "")
