@@ -219,11 +219,12 @@ msb_status msb_grad_infl(msb_plan plan, const double *u, const double *w, double
                          void *stream);
 
 /*
- * Measurement helper: enqueues nrep products f = A u (as msb_apply) with HIP events
- * recorded on `stream` between the kernels of the chain, and returns in ms[i] the
- * mean duration in milliseconds of kernel i: 2D x-forward, y line product,
- * x-inverse (*npass = 3); 3D x-forward, y-forward, z line product, y-inverse,
- * x-inverse (*npass = 5).  ms: host, capacity >= 5.  Synchronises the stream.
+ * Measurement helper: launches every kernel of the product chain nrep times back to
+ * back on `stream`, with HIP events recorded between the kernels, and returns in ms[i]
+ * the mean duration in milliseconds of one launch of kernel i: 2D x-forward, y line
+ * product, x-inverse (*npass = 3); 3D x-forward, y-forward, z line product, y-inverse,
+ * x-inverse (*npass = 5).  Then computes f = A u once (as msb_apply), so f holds the
+ * product on return.  ms: host, capacity >= 5.  Synchronises the stream.
  */
 msb_status msb_profile_apply(msb_plan plan, msb_precision prec, const void *u, void *f, int nrep,
                              double *ms, int *npass, void *stream);

@@ -1005,38 +1005,54 @@ template <typename T> static ChainGeom chain_geom(const PassArgs<T> &a) {
     return g;
 }
 
+// reps > 1 (single plans, measurement only): every pass is launched reps times back to
+// back between the events, so an event interval is reps kernel durations without the
+// dispatch gaps of a lone launch.
 template <typename T, bool BX, bool BL, int RM>
 static msb_status launch_chain(const PassArgs<T> &a, const EndArgs<T> &e, const ChainGeom &g, hipStream_t st,
-                               hipEvent_t *ev, const PassArgs<T> *dA, const EndArgs<T> *dE, const GroupGrid *gg) {
+                               hipEvent_t *ev, const PassArgs<T> *dA, const EndArgs<T> *dE, const GroupGrid *gg,
+                               int reps = 1) {
     int evi = 0;
     auto mark = [&]() -> hipError_t { return ev ? hipEventRecord(ev[evi++], st) : hipSuccess; };
     MSB_HIP((gg ? allow_lds(k_xfwd_group<T, BX, RM>, g.lds_x) : allow_lds(k_xfwd<T, BX, RM>, g.lds_x)));
     MSB_HIP((gg ? allow_lds(k_xinv_group<T, BX, RM>, g.lds_x) : allow_lds(k_xinv<T, BX, RM>, g.lds_x)));
     MSB_HIP(mark());
     if (gg) hipLaunchKernelGGL((k_xfwd_group<T, BX, RM>), dim3(gg->total_x), dim3(g.bx), g.lds_x, st, dA, dE, gg->start_x, gg->n);
-    else hipLaunchKernelGGL((k_xfwd<T, BX, RM>), dim3(a.B * g.tiles_x), dim3(g.bx), g.lds_x, st, a, e);
+    else
+        for (int k = 0; k < reps; ++k)
+            hipLaunchKernelGGL((k_xfwd<T, BX, RM>), dim3(a.B * g.tiles_x), dim3(g.bx), g.lds_x, st, a, e);
     MSB_HIP(mark());
     if (a.d == 2) {
         MSB_HIP((gg ? allow_lds(k_line_y_group<T, BL, RM>, g.lds_l) : allow_lds(k_line_y<T, BL, RM>, g.lds_l)));
         if (gg) hipLaunchKernelGGL((k_line_y_group<T, BL, RM>), dim3(gg->total_l), dim3(g.bl), g.lds_l, st, dA, dE, gg->start_l, gg->n);
-        else hipLaunchKernelGGL((k_line_y<T, BL, RM>), dim3(a.B * g.tiles_l), dim3(g.bl), g.lds_l, st, a, e);
+        else
+            for (int k = 0; k < reps; ++k)
+                hipLaunchKernelGGL((k_line_y<T, BL, RM>), dim3(a.B * g.tiles_l), dim3(g.bl), g.lds_l, st, a, e);
         MSB_HIP(mark());
     } else {
         MSB_HIP((gg ? allow_lds(k_yfwd_group<T, BL, RM>, g.lds_y) : allow_lds(k_yfwd<T, BL, RM>, g.lds_y)));
         MSB_HIP((gg ? allow_lds(k_yinv_group<T, BL, RM>, g.lds_y) : allow_lds(k_yinv<T, BL, RM>, g.lds_y)));
         MSB_HIP((gg ? allow_lds(k_line_z_group<T, BL, RM>, g.lds_l) : allow_lds(k_line_z<T, BL, RM>, g.lds_l)));
         if (gg) hipLaunchKernelGGL((k_yfwd_group<T, BL, RM>), dim3(gg->total_y), dim3(g.bl), g.lds_y, st, dA, dE, gg->start_y, gg->n);
-        else hipLaunchKernelGGL((k_yfwd<T, BL, RM>), dim3(a.B * g.tiles_y), dim3(g.bl), g.lds_y, st, a, e);
+        else
+            for (int k = 0; k < reps; ++k)
+                hipLaunchKernelGGL((k_yfwd<T, BL, RM>), dim3(a.B * g.tiles_y), dim3(g.bl), g.lds_y, st, a, e);
         MSB_HIP(mark());
         if (gg) hipLaunchKernelGGL((k_line_z_group<T, BL, RM>), dim3(gg->total_l), dim3(g.bl), g.lds_l, st, dA, dE, gg->start_l, gg->n);
-        else hipLaunchKernelGGL((k_line_z<T, BL, RM>), dim3(a.B * g.tiles_l), dim3(g.bl), g.lds_l, st, a, e);
+        else
+            for (int k = 0; k < reps; ++k)
+                hipLaunchKernelGGL((k_line_z<T, BL, RM>), dim3(a.B * g.tiles_l), dim3(g.bl), g.lds_l, st, a, e);
         MSB_HIP(mark());
         if (gg) hipLaunchKernelGGL((k_yinv_group<T, BL, RM>), dim3(gg->total_y), dim3(g.bl), g.lds_y, st, dA, dE, gg->start_y, gg->n);
-        else hipLaunchKernelGGL((k_yinv<T, BL, RM>), dim3(a.B * g.tiles_y), dim3(g.bl), g.lds_y, st, a, e);
+        else
+            for (int k = 0; k < reps; ++k)
+                hipLaunchKernelGGL((k_yinv<T, BL, RM>), dim3(a.B * g.tiles_y), dim3(g.bl), g.lds_y, st, a, e);
         MSB_HIP(mark());
     }
     if (gg) hipLaunchKernelGGL((k_xinv_group<T, BX, RM>), dim3(gg->total_x), dim3(g.bxi), g.lds_x, st, dA, dE, gg->start_x, gg->n);
-    else hipLaunchKernelGGL((k_xinv<T, BX, RM>), dim3(a.B * g.tiles_x), dim3(g.bxi), g.lds_x, st, a, e);
+    else
+        for (int k = 0; k < reps; ++k)
+            hipLaunchKernelGGL((k_xinv<T, BX, RM>), dim3(a.B * g.tiles_x), dim3(g.bxi), g.lds_x, st, a, e);
     MSB_HIP(mark());
     MSB_HIP(hipGetLastError());
     return MSB_OK;
@@ -1055,24 +1071,24 @@ static bool needs_composite(const FftSched *const (&scheds)[3]) {
 template <typename T>
 static msb_status dispatch_chain(const PassArgs<T> &a, const EndArgs<T> &e, const ChainGeom &g, bool composite,
                                  hipStream_t st, hipEvent_t *ev, const PassArgs<T> *dA, const EndArgs<T> *dE,
-                                 const GroupGrid *gg) {
+                                 const GroupGrid *gg, int reps = 1) {
     const int sel = (a.wave_x ? 1 : 0) | (a.wave_l ? 2 : 0) | (composite ? 4 : 0);
     switch (sel) {
-        case 0: return launch_chain<T, true, true, 8>(a, e, g, st, ev, dA, dE, gg);
-        case 1: return launch_chain<T, false, true, 8>(a, e, g, st, ev, dA, dE, gg);
-        case 2: return launch_chain<T, true, false, 8>(a, e, g, st, ev, dA, dE, gg);
-        case 3: return launch_chain<T, false, false, 8>(a, e, g, st, ev, dA, dE, gg);
-        case 4: return launch_chain<T, true, true, 16>(a, e, g, st, ev, dA, dE, gg);
-        case 5: return launch_chain<T, false, true, 16>(a, e, g, st, ev, dA, dE, gg);
-        case 6: return launch_chain<T, true, false, 16>(a, e, g, st, ev, dA, dE, gg);
-        default: return launch_chain<T, false, false, 16>(a, e, g, st, ev, dA, dE, gg);
+        case 0: return launch_chain<T, true, true, 8>(a, e, g, st, ev, dA, dE, gg, reps);
+        case 1: return launch_chain<T, false, true, 8>(a, e, g, st, ev, dA, dE, gg, reps);
+        case 2: return launch_chain<T, true, false, 8>(a, e, g, st, ev, dA, dE, gg, reps);
+        case 3: return launch_chain<T, false, false, 8>(a, e, g, st, ev, dA, dE, gg, reps);
+        case 4: return launch_chain<T, true, true, 16>(a, e, g, st, ev, dA, dE, gg, reps);
+        case 5: return launch_chain<T, false, true, 16>(a, e, g, st, ev, dA, dE, gg, reps);
+        case 6: return launch_chain<T, true, false, 16>(a, e, g, st, ev, dA, dE, gg, reps);
+        default: return launch_chain<T, false, false, 16>(a, e, g, st, ev, dA, dE, gg, reps);
     }
 }
 
 template <typename T>
-msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev) {
+msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t st, hipEvent_t *ev, int reps) {
     const FftSched *const sc[3] = {&a.sx, &a.sy, &a.sz};
-    return dispatch_chain<T>(a, e, chain_geom(a), needs_composite(sc), st, ev, nullptr, nullptr, nullptr);
+    return dispatch_chain<T>(a, e, chain_geom(a), needs_composite(sc), st, ev, nullptr, nullptr, nullptr, reps);
 }
 
 template <typename T>
@@ -1108,8 +1124,10 @@ bool plan_needs_composite(const msb_plan_s *p, bool fp32, int max_radix) {
 
 template PassArgs<double> pass_args<double>(const msb_plan_s *, const DeviceOp &, const msb_launch_config *);
 template PassArgs<float> pass_args<float>(const msb_plan_s *, const DeviceOp &, const msb_launch_config *);
-template msb_status launch_product<double>(const PassArgs<double> &, const EndArgs<double> &, hipStream_t, hipEvent_t *);
-template msb_status launch_product<float>(const PassArgs<float> &, const EndArgs<float> &, hipStream_t, hipEvent_t *);
+template msb_status launch_product<double>(const PassArgs<double> &, const EndArgs<double> &, hipStream_t, hipEvent_t *,
+                                          int);
+template msb_status launch_product<float>(const PassArgs<float> &, const EndArgs<float> &, hipStream_t, hipEvent_t *,
+                                         int);
 template msb_status launch_group<double>(const PassArgs<double> &, const GroupGrid &, const PassArgs<double> *,
                                          const EndArgs<double> *, bool, hipStream_t);
 template msb_status launch_group<float>(const PassArgs<float> &, const GroupGrid &, const PassArgs<float> *,

@@ -114,10 +114,12 @@ template <typename T> struct EndArgs {
 };
 
 // Launch the pass chain on stream s.  ev (optional, npasses+1 events) is recorded
-// before the first kernel and after each kernel (measurement only).
+// before the first kernel and after each kernel (measurement only); with reps > 1 each
+// kernel is launched reps times back to back between its events (measurement only: the
+// outputs of repeated in-place passes are not the product).
 template <typename T>
 msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t s,
-                          hipEvent_t *ev = nullptr);
+                          hipEvent_t *ev = nullptr, int reps = 1);
 inline int n_passes(int dim) { return dim == 2 ? 3 : 5; }
 
 // Arguments of the product passes for plan p and operator op, with the plan's launch

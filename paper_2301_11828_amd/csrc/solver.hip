@@ -610,8 +610,10 @@ extern "C" msb_status msb_apply_dinfl(msb_plan p, int k, const double *u, double
 
 template <typename T>
 static msb_status profile_t(msb_plan_s *p, const T *u, T *f, int nrep, double *ms, int *npass, hipStream_t st) {
+    // each pass launched nrep times back to back between two events: the mean kernel
+    // duration of a launch in a stream of launches; then one plain product for f
     const int np = n_passes(p->dim);
-    std::vector<hipEvent_t> ev((size_t)(np + 1) * nrep, nullptr);
+    std::vector<hipEvent_t> ev((size_t)(np + 1), nullptr);
     msb_status s = MSB_OK;
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) s = MSB_EDEVICE;
@@ -621,17 +623,13 @@ static msb_status profile_t(msb_plan_s *p, const T *u, T *f, int nrep, double *m
     PassArgs<T> a = pass_args<T>(p, p->op);
     e.pio = const_cast<T *>(u);
     e.uin = u;
-    for (int r = 0; r < nrep && s == MSB_OK; ++r) s = launch_product<T>(a, e, st, ev.data() + (size_t)r * (np + 1));
+    if (s == MSB_OK) s = launch_product<T>(a, e, st, ev.data(), nrep);
+    if (s == MSB_OK) s = launch_product<T>(a, e, st);
     if (s == MSB_OK && hipStreamSynchronize(st) != hipSuccess) s = MSB_EDEVICE;
     for (int i = 0; i < np && s == MSB_OK; ++i) {
-        double acc = 0.0;
-        for (int r = 0; r < nrep; ++r) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, ev[(size_t)r * (np + 1) + i], ev[(size_t)r * (np + 1) + i + 1]) != hipSuccess)
-                s = MSB_EDEVICE;
-            acc += t;
-        }
-        ms[i] = acc / nrep;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) s = MSB_EDEVICE;
+        ms[i] = (double)t / nrep;
     }
     for (auto &x : ev)
         if (x) (void)hipEventDestroy(x);

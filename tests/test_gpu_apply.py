@@ -206,3 +206,21 @@ def test_apply_cube128_fp32_sampled_rows():
         err = rel_err(f[c][:, rows], ref)
         log("cube128 fp32 case %d sampled rel err %.2e" % (c, err))
         assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_profile_apply_times_every_pass_and_leaves_the_product(dim):
+    """The measurement helper repeats each pass back to back, then computes f = A u once:
+    f must equal the plain product bit for bit."""
+    import torch
+    if dim == 2:
+        w = W.small(2, (40, 33), 3, seed=95, fixed="left", crack=True)
+    else:
+        w = W.small(3, (12, 9, 8), 2, seed=96, fixed="bottom")
+    plan = gpu_plan(w)
+    u = to_dev(w.b)
+    f = torch.full_like(u, float("nan"))
+    ks = plan.profile_apply(u, f, nrep=7)
+    log("profile_apply %dD: %s ms" % (dim, ["%.4f" % k for k in ks]))
+    assert len(ks) == (3 if dim == 2 else 5) and all(k > 0 for k in ks)
+    assert np.array_equal(f.cpu().numpy(), gpu_apply(plan, u).cpu().numpy())
