@@ -209,6 +209,26 @@ msb_status msb_vv_run(msb_plan plan, msb_precision prec, double dt, int64_t nste
                       void *stream);
 
 /*
+ * Quasi-static model by adaptive dynamic relaxation (Sec. 2.2, eq. (ADR:e1), Alg. 1 CDEI,
+ * time step 1):
+ *   v^{1/2} = D^{-1} F^0 / 2,  v^{n+1/2} = ((2 - c^n) v^{n-1/2} + 2 D^{-1} F^n) / (2 + c^n),
+ *   u^{n+1} = u^n + v^{n+1/2},  F = A u + b on free DOFs (0 on constrained ones, u_C = g).
+ * The fictitious density D and the damping c^n are those of the ADR method the paper
+ * cites: D_ii = 1/4 sum_j |K_ij| (a Gershgorin bound of K = -A as the product applies it,
+ * broken bonds and surface factors included), c^n = 2 sqrt(u^T K1 u / u^T u) over the free
+ * DOFs with K1_ii = -(F^n_i - F^{n-1}_i) / (D_ii v^{n-1/2}_i) (0 where v = 0), c^n = 0 when
+ * the quotient is not positive.  The fixed point is the static solution of eq. (mat:e2).
+ * restart != 0: start from u (u_C set to g), build D, evaluate F^0 and take nsteps
+ * updates.  restart = 0: continue from (u, v, F) with the damping sums the previous call
+ * on this plan left in its workspace (same precision; MSB_EINVAL otherwise).
+ * u, v (= v^{n-1/2}), F (= F(u^n) on return): device [B][d][N] in/out; b: device, constant;
+ * g: device or NULL (= 0); all double (MSB_FP64) or float (MSB_FP32).  res: host [B] or
+ * NULL: ||F||_2 of the final state per case (synchronises the stream).
+ */
+msb_status msb_adr_run(msb_plan plan, msb_precision prec, int64_t nsteps, int restart, void *u, void *v,
+                       void *F, const void *b, const void *g, double *res, void *stream);
+
+/*
  * Adjoint gradient of a loss of a static solution u (Sec. 2.1 kernel with
  * omega = sum_k a_k (r/delta)^k): K symmetric, so with w = K_FF^{-1} dL/du_F
  * (w from msb_solve_static on dL/du) the gradient is dL/db_F = w and

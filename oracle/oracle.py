@@ -23,6 +23,10 @@ eqs. (matrix)/(mae:e1), and the model equations built on it:
 * ``vv``                   -- velocity Verlet, Alg. 2, with a = (A u + b)/rho and
                               constrained DOFs overwritten after each update (eq. (up)).
 * ``energy``               -- kinetic + elastic - external work of the discrete system.
+* ``adr_step``/``adr``     -- the quasi-static model by adaptive dynamic relaxation (Sec. 2.2,
+                              eq. (ADR:e1), Alg. 1, CDEI) with the fictitious density and the
+                              adaptive damping of the cited ADR method (Kilic and Madenci):
+                              one update, and a run of updates.
 * ``grad_dense``           -- exact gradient of ||u - u_t||^2 w.r.t. the body force
                               and the influence coefficients a_k (omega = sum_k a_k (r/delta)^k).
 * ``crack_to_bonds``       -- broken set of eq. (mu) for a pre-crack: a bond is broken
@@ -596,3 +600,70 @@ def surface_volume_factors(prob: Problem) -> np.ndarray:
             ok &= good.reshape(sh)
         inside += lam * ok
     return (full / inside).reshape(-1)
+
+
+# ---------------------------------------------------------------- adaptive dynamic relaxation
+def adr_density(prob: Problem, broken=None) -> np.ndarray:
+    """Fictitious diagonal density of the cited ADR method: D_ii = 1/4 sum_j |K_ij| (a
+    Gershgorin bound, time step 1), K = -A assembled densely (every row and column, broken
+    bonds removed).  Returns [dim][N]."""
+    K = -assemble_dense(prob, broken)
+    return (0.25 * np.abs(K).sum(axis=1)).reshape(prob.dim, prob.N)
+
+
+def adr_step(prob: Problem, u, v, F, Fprev, b, D, fixed=None, g=None, broken=None):
+    """One update of Alg. 1 (time step 1) from u^n with F = F(u^n), the velocity v^{n-1/2}
+    and F^{n-1} (Fprev None: the first update, v^{1/2} = D^{-1} F^0 / 2):
+
+        c^n        = 2 sqrt(u^T K1 u / u^T u) over the free DOFs, K1_ii = -(F^n_i - F^{n-1}_i) /
+                     (D_ii v^{n-1/2}_i) (0 where v = 0); c^n = 0 when the quotient is not positive
+        v^{n+1/2}  = ((2 - c^n) v^{n-1/2} + 2 D^{-1} F^n) / (2 + c^n)
+        u^{n+1}    = u^n + v^{n+1/2}
+
+    F = A u + b on free DOFs, 0 on constrained ones (u held at g there).  Returns
+    (u^{n+1}, v^{n+1/2}, F(u^{n+1}), c^n or None for the first update)."""
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed).reshape(d, N)
+    free = ~fx
+    b = np.asarray(b, dtype=np.float64).reshape(d, N)
+    u = np.asarray(u, dtype=np.float64).reshape(d, N)
+    F = np.asarray(F, dtype=np.float64).reshape(d, N)
+    c = None
+    if Fprev is None:
+        vn = np.where(free, 0.5 * F / D, 0.0)
+    else:
+        v = np.asarray(v, dtype=np.float64).reshape(d, N)
+        Fp = np.asarray(Fprev, dtype=np.float64).reshape(d, N)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            k1 = np.where(free & (v != 0.0), -(F - Fp) / (D * v), 0.0)
+        num = float((u[free] * k1[free] * u[free]).sum())
+        den = float((u[free] * u[free]).sum())
+        c = 2.0 * math.sqrt(num / den) if den > 0 and num > 0 else 0.0
+        vn = np.where(free, ((2.0 - c) * v + 2.0 * F / D) / (2.0 + c), 0.0)
+    un = u + vn
+    if g is not None:
+        un[fx] = np.asarray(g, dtype=np.float64).reshape(d, N)[fx]
+    Fn = force(prob, un, broken) + b
+    Fn[fx] = 0.0
+    return un, vn, Fn, c
+
+
+def adr(prob: Problem, u0, b, nsteps: int, fixed=None, g=None, broken=None):
+    """Alg. 1 (CDEI) for D u'' + c D u' = f + b (eq. (ADR:e1)): nsteps updates of
+    ``adr_step`` from u0 (u held at g on constrained DOFs), D from ``adr_density``.
+    Returns (u, the last velocity, F(u), list of c^n)."""
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed).reshape(d, N)
+    D = adr_density(prob, broken)
+    b = np.asarray(b, dtype=np.float64).reshape(d, N)
+    u = np.asarray(u0, dtype=np.float64).reshape(d, N).copy()
+    u[fx] = 0.0 if g is None else np.asarray(g, dtype=np.float64).reshape(d, N)[fx]
+    F = force(prob, u, broken) + b
+    F[fx] = 0.0
+    v, Fprev, cs = np.zeros((d, N)), None, []
+    for _ in range(nsteps):
+        un, v, Fn, c = adr_step(prob, u, v, F, Fprev, b, D, fixed, g, broken)
+        if c is not None:
+            cs.append(c)
+        u, Fprev, F = un, F, Fn
+    return u, v, F, cs

@@ -28,6 +28,7 @@ _STATUS = {0: "MSB_OK", -1: "MSB_EINVAL", -2: "MSB_ENOMEM", -3: "MSB_EDEVICE", -
 EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "msb_plan_set_bonds",
            "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl", "msb_apply_precond",
            "msb_crack_update", "msb_plan_get_bonds", "msb_plan_set_surface", "msb_surface_volume_factors",
+           "msb_adr_run",
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
            "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
            "msb_plan_autotune", "msb_group_create", "msb_group_destroy", "msb_group_get_config",
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "msb_crack_update": ([P, I, P, D, ctypes.POINTER(I64), P], I),
         "msb_plan_get_bonds": ([P, P, I64, ctypes.POINTER(I64)], I),
         "msb_plan_set_surface": ([P, P], I),
+        "msb_adr_run": ([P, I, I64, I, P, P, P, P, P, P, P], I),
         "msb_surface_volume_factors": ([P, P], I),
         "msb_solve_static": ([P, I, P, P, P, ctypes.POINTER(_Opts), P, P], I),
         "msb_vv_init": ([P, I, P, P, P, P], I),
@@ -386,6 +388,19 @@ class Plan:
         if check:
             _check(st)
         return out, res
+
+    def adr_run(self, nsteps: int, u, v, F, b, g=None, restart: bool = True, residual: bool = False):
+        """Adaptive dynamic relaxation (Alg. 1): nsteps updates of u (in place), velocity v and
+        force F = A u + b; restart starts from u, else continues.  Returns ||F|| per case when
+        residual is set."""
+        torch = _torch()
+        prec = FP64 if u.dtype == torch.float64 else FP32
+        res = np.zeros(self.batch, dtype=np.float64) if residual else None
+        gp = self._vec(g, u.dtype, "g") if g is not None else None
+        _check(_lib.msb_adr_run(self._ptr, prec, int(nsteps), int(bool(restart)), self._vec(u, u.dtype, "u"),
+                                self._vec(v, u.dtype, "v"), self._vec(F, u.dtype, "F"), self._vec(b, u.dtype, "b"),
+                                gp, res.ctypes.data if res is not None else None, _stream()))
+        return res
 
     def vv_init(self, u, b, a=None):
         torch = _torch()

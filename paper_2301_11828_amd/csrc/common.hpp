@@ -167,6 +167,7 @@ struct msb_plan_s {
     // precisions, or null; stencil offsets on the device for the correction pass
     double *nu64 = nullptr;
     float *nu32 = nullptr;
+    std::vector<double> nu_host;     // [N] or empty
     int32_t *off_dev = nullptr;      // [n_off][3]
 
     // constraints
@@ -220,6 +221,9 @@ msb_status relayout(msb_plan_s *p, const int64_t *L);
 
 msb_status alloc_operator(msb_plan_s *p, DeviceOp &op, int count);
 msb_status build_preconditioner(msb_plan_s *p, DeviceOp &pre);
+// Fictitious density of dynamic relaxation, D_ii = 1/4 sum_j |K_ij| for every DOF of
+// every operator slot ([slots][d][N]; slots = per-case operators or 1) (plan.cpp).
+void build_adr_density(const msb_plan_s *p, std::vector<double> &D, int &slots);
 msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot);
 void free_operator(DeviceOp &op);
 void solver_cache_free(msb_plan_s *p);

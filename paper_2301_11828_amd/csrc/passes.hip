@@ -167,6 +167,22 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
         alpha = T(al);
         upd = true;
         conv = e.update_only || (e.thresh && !(rrn > e.thresh[b]));
+    } else if (e.pro == PRO_ADR_U && !e.first) {
+        // adaptive damping c = 2 sqrt(u.K1.u / u.u) from the previous epilogue's partials;
+        // alpha = 2 - c, beta = 1 / (2 + c)
+        const int tid0 = threadIdx.x, ntb = blockDim.x;
+        double sums[2];
+        if (e.case4) {
+            sums[0] = e.case4[(size_t)b * 2];
+            sums[1] = e.case4[(size_t)b * 2 + 1];
+        } else {
+            const double *const parts[2] = {e.cg3 + (size_t)b * tpc, e.cg3 + (size_t)ntiles + (size_t)b * tpc};
+            block_sum_partials_k<2>(parts, tpc, sums, red, tid0, ntb);
+        }
+        const double q = sums[1] > 0.0 ? sums[0] / sums[1] : 0.0;
+        const double c = q > 0.0 ? 2.0 * sqrt(q) : 0.0;
+        alpha = T(2.0 - c);
+        beta = T(1.0 / (2.0 + c));
     } else if (e.pro == PRO_PCG_P && !e.first) {
         // beta = (r.z) / (r.z of the previous iteration)
         const int tid0 = threadIdx.x, ntb = blockDim.x;
@@ -237,6 +253,18 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
                         v = conv ? T(0) : rv;
                     } else if (e.pro == PRO_PCG_P) {
                         v = e.pr[addr] + beta * e.pio[addr];
+                        e.pio[addr] = v;
+                    } else if (e.pro == PRO_ADR_U) {
+                        const bool fx = a.fixed && a.fixed[rowfix[h2] + n];
+                        T vn = T(0);
+                        if (fx) {
+                            v = e.pg ? e.pg[addr] : T(0);
+                        } else {
+                            const T fd = e.cq[addr] / e.pa[addr - cbase + (size_t)b * e.pa_stride];
+                            vn = e.first ? T(0.5) * fd : (alpha * e.cx[addr] + T(2) * fd) * beta;
+                            v = e.pio[addr] + vn;
+                        }
+                        e.cx[addr] = vn;
                         e.pio[addr] = v;
                     } else {
                         const bool fx = a.fixed && a.fixed[rowfix[h2] + n];
@@ -733,6 +761,26 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
                         const T z = fx ? T(0) : sign * f;
                         e.out[addr] = z;
                         acc0 += (double)uin[addr] * (double)z;
+                        break;
+                    }
+                    case EPI_ADR: {
+                        // F = f + b; K1 = -(F - F_prev) / (D v) where v != 0 (the local
+                        // stiffness of the adaptive damping); sums u.K1.u and u.u
+                        if (fx) {
+                            e.out[addr] = T(0);
+                            break;
+                        }
+                        const T Fn = f + e.rhs[addr];
+                        if (e.part) {   // no partials on the first evaluation (no previous F)
+                            const double uu = (double)uin[addr];
+                            const double vv = (double)e.ev[addr];
+                            if (vv != 0.0) {
+                                const double Dd = (double)e.pa[addr - cbase + (size_t)b * e.pa_stride];
+                                acc0 += uu * uu * (-((double)Fn - (double)e.out[addr]) / (Dd * vv));
+                            }
+                            acc1 += uu * uu;
+                        }
+                        e.out[addr] = Fn;
                         break;
                     }
                     case EPI_RESID: {

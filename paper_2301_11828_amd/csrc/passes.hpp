@@ -13,6 +13,7 @@ enum Prologue : int {
     PRO_VV_U = 2,   // u <- u + dt v + dt^2 a / 2, u_C <- g_C, store u, transform u
     PRO_PCG_R = 3,  // preconditioned CG, preconditioner chain: x += alpha p, r -= alpha q, transform r
     PRO_PCG_P = 4,  // preconditioned CG, stiffness chain: p <- z + beta p, transform p
+    PRO_ADR_U = 5,  // dynamic relaxation (Alg. 1): v <- ((2 - c) v + 2 F/D)/(2 + c), u <- u + v, transform u
 };
 
 // What the x-inverse pass does with f = A u after the corrections.
@@ -23,6 +24,7 @@ enum Epilogue : int {
     EPI_VV = 3,     // a' = (f + b)/rho; v += dt (a + a')/2; a = a'; energy partials
     EPI_DOT = 4,    // no output; partial w.f over free DOFs
     EPI_PCG_Z = 5,  // out = z = sign * f (the preconditioned residual), 0 on constrained; partial r.z
+    EPI_ADR = 6,    // out = F = f + b (0 on constrained); partials u.K1.u, u.u of the adaptive damping
 };
 
 template <typename T> struct PassArgs {
@@ -68,15 +70,16 @@ template <typename T> struct PassArgs {
 template <typename T> struct EndArgs {
     int pro, epi;
     // prologue
-    T *pio;              // PRO_CG_P, PRO_PCG_P: p (in/out); PRO_VV_U: u (in/out)
+    T *pio;              // PRO_CG_P, PRO_PCG_P: p (in/out); PRO_VV_U, PRO_ADR_U: u (in/out)
     const T *pr;         // PRO_CG_P: r;          PRO_VV_U: v;  PRO_PCG_R: p;  PRO_PCG_P: z
-    const T *pa;         // PRO_VV_U: a
+    const T *pa;         // PRO_VV_U: a;  PRO_ADR_U, EPI_ADR: the fictitious density D
+    size_t pa_stride;    // PRO_ADR_U, EPI_ADR: stride of D between cases (0: shared)
     const T *pg;         // PRO_VV_U: g or null
     // PRO_CG_P (single-reduction CG): alpha = r.r / p.q, r'.r' = r.r - 2 alpha r.q +
     // alpha^2 q.q, beta = r'.r' / r.r from the partial sums of the previous iteration
-    T *cx;                     // x (updated)
+    T *cx;                     // x (updated); PRO_ADR_U: the velocity (updated)
     T *cr;                     // r (updated)
-    const T *cq;               // q = K p of the previous iteration
+    const T *cq;               // q = K p of the previous iteration; PRO_ADR_U: F of the current u
     const double *cg3;         // previous x-inverse partials [3][B*tiles]: p.q, r.q, q.q
     const double *rr_prev;     // previous true r.r partials [B][tiles]
     double *rr_out;            // this iteration's true r.r partials [B][tiles]

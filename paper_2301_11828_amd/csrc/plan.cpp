@@ -450,6 +450,73 @@ msb_status build_preconditioner(msb_plan_s *p, DeviceOp &pre) {
     return MSB_OK;
 }
 
+// Fictitious density of the dynamic-relaxation solver (the cited ADR method): a Gershgorin
+// bound per row, D_ii = 1/4 sum_j |K_ij| with K = -A as the products apply it (in-grid
+// neighbours, broken bonds removed, surface factors on Omega_e rows): off-diagonal blocks
+// |W(o)| per neighbour, the diagonal block |sum_o W(o)|.
+void build_adr_density(const msb_plan_s *p, std::vector<double> &D, int &slots) {
+    const int d = p->dim, M = p->M;
+    slots = p->op.count > 1 ? p->op.count : 1;
+    const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2], N = p->N;
+    // broken neighbours per node (CSR from the sorted pair list)
+    std::vector<int64_t> ptr(N + 1, 0), nb;
+    const int64_t np_ = p->n_pairs;
+    for (int64_t e = 0; e < np_; ++e) {
+        ptr[p->bonds_host[2 * e] + 1]++;
+        ptr[p->bonds_host[2 * e + 1] + 1]++;
+    }
+    for (int64_t i = 0; i < N; ++i) ptr[i + 1] += ptr[i];
+    nb.assign(ptr[N], 0);
+    {
+        std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t e = 0; e < np_; ++e) {
+            const int64_t a = p->bonds_host[2 * e], b = p->bonds_host[2 * e + 1];
+            nb[fill[a]++] = b;
+            nb[fill[b]++] = a;
+        }
+    }
+    const bool surf = !p->nu_host.empty();
+    D.assign((size_t)slots * d * N, 0.0);
+    for (int sl = 0; sl < slots; ++sl) {
+        const std::vector<double> infl = p->per_case ? std::vector<double>(p->infl_case.begin() + (size_t)sl * p->n_infl,
+                                                                           p->infl_case.begin() + (size_t)(sl + 1) * p->n_infl)
+                                                     : p->infl;
+        std::vector<long double> Wl;
+        bond_weights(p, infl, Wl);
+        std::vector<double> W(Wl.begin(), Wl.end());   // [comp][n_off]
+        double *Ds = D.data() + (size_t)sl * d * N;
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
+                for (int64_t i = 0; i < nx; ++i) {
+                    const int64_t pn = (k * ny + j) * nx + i;
+                    const bool on_e = surf && (i < M || i >= nx - M || j < M || j >= ny - M ||
+                                               (d == 3 && (k < M || k >= nz - M)));
+                    double off[3] = {0, 0, 0}, diag[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                    for (int o = 0; o < p->n_off; ++o) {
+                        const int *of = &p->off[3 * o];
+                        const int64_t x = i + of[0], y = j + of[1], z = k + of[2];
+                        if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) continue;
+                        const int64_t q = (z * ny + y) * nx + x;
+                        bool broken = false;
+                        for (int64_t t = ptr[pn]; t < ptr[pn + 1] && !broken; ++t) broken = nb[t] == q;
+                        if (broken) continue;
+                        const double v = on_e ? 0.5 * (p->nu_host[pn] + p->nu_host[q]) : 1.0;
+                        for (int a = 0; a < d; ++a)
+                            for (int c = 0; c < d; ++c) {
+                                const double wv = v * W[(size_t)comp_index(a, c, d) * p->n_off + o];
+                                off[a] += std::fabs(wv);
+                                diag[a][c] += wv;
+                            }
+                    }
+                    for (int a = 0; a < d; ++a) {
+                        double r = off[a];
+                        for (int c = 0; c < d; ++c) r += std::fabs(diag[a][c]);
+                        Ds[(size_t)a * N + pn] = 0.25 * r;
+                    }
+                }
+    }
+}
+
 // Fill one slot of an operator for the given influence coefficients.
 msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot) {
     std::vector<long double> W;
@@ -677,6 +744,7 @@ extern "C" msb_status msb_plan_set_surface(msb_plan p, const double *nu) {
         if (p->nu32) hipFree(p->nu32);
         p->nu64 = nullptr;
         p->nu32 = nullptr;
+        p->nu_host.clear();
         return MSB_OK;
     }
     std::vector<double> v(nu, nu + p->N);
@@ -685,6 +753,7 @@ extern "C" msb_status msb_plan_set_surface(msb_plan p, const double *nu) {
                   (long long)i);
     MSB_TRY(upload(&p->nu64, v));
     MSB_TRY(upload(&p->nu32, std::vector<float>(v.begin(), v.end())));
+    p->nu_host = v;
     return MSB_OK;
 }
 

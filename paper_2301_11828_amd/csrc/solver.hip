@@ -34,6 +34,13 @@ struct SolverWs {
     double *part_aux = nullptr;      // [3][B][P] dot partials
     double *case4 = nullptr;         // [B][5] CG case sums (many tiles per case)
     double *part_rz = nullptr;       // [2][3][B * rows] preconditioned CG: r.z partials by parity
+    double *part_adr = nullptr;      // [3][B * rows] dynamic relaxation: damping partials of the last force
+    double *adr_D64 = nullptr;       // [slots][d][N] fictitious density
+    float *adr_D32 = nullptr;
+    int adr_slots = 0;
+    int adr_prec = -1;               // precision of the last relaxation run (its partials), -1 none
+    int adr_tiles = 0;               // x tiles per case its partials were written with
+    bool adr_pending = false;        // restarted without an update: the next update is the first
     double *thresh = nullptr;        // [B]
     double *scal = nullptr;          // [16][B] per-case scalars
     double *energy = nullptr;        // energies (device)
@@ -55,8 +62,8 @@ void solver_cache_free(msb_plan_s *p) {
         if (x) (void)hipFree(x);
     for (auto x : w->v32)
         if (x) (void)hipFree(x);
-    void *b[] = {w->part_x, w->part_rr, w->part_aux, w->case4, w->part_rz, w->thresh, w->scal, w->energy, w->done,
-                 w->iters, w->ecount};
+    void *b[] = {w->part_x, w->part_rr, w->part_aux, w->case4, w->part_rz, w->part_adr, w->adr_D64, w->adr_D32,
+                 w->thresh, w->scal, w->energy, w->done, w->iters, w->ecount};
     for (void *x : b)
         if (x) (void)hipFree(x);
     if (w->h_scal) (void)hipHostFree(w->h_scal);
@@ -903,6 +910,115 @@ static msb_status vv_run_t(msb_plan_s *p, double dt, int64_t nsteps, T *u, T *v,
         MSB_HIP(hipStreamSynchronize(st));
     }
     return MSB_OK;
+}
+
+// ---------------------------------------------------------------------------- relaxation
+// Dynamic relaxation (Alg. 1, CDEI, time step 1): each step is one product chain whose
+// x-forward applies the velocity and displacement update with the damping of the
+// previous force evaluation, and whose x-inverse forms F = A u + b and the damping
+// partials u.K1.u and u.u.
+template <typename T>
+static msb_status adr_run_t(msb_plan_s *p, msb_precision prec, int64_t nsteps, int restart, T *u, T *v, T *F,
+                            const T *bf, const T *g, double *res, hipStream_t st) {
+    SolverWs *w = nullptr;
+    MSB_TRY(get_ws(p, w));
+    const int B = p->B;
+    const size_t n = w->nvec, dn = (size_t)p->dim * p->N;
+    if (restart) {
+        std::vector<double> D;
+        int slots = 0;
+        build_adr_density(p, D, slots);
+        if (w->adr_D64) (void)hipFree(w->adr_D64);
+        if (w->adr_D32) (void)hipFree(w->adr_D32);
+        w->adr_D64 = nullptr;
+        w->adr_D32 = nullptr;
+        w->adr_prec = -1;
+        MSB_HIP(hipMalloc(&w->adr_D64, sizeof(double) * D.size()));
+        MSB_HIP(hipMalloc(&w->adr_D32, sizeof(float) * D.size()));
+        std::vector<float> D32(D.begin(), D.end());
+        MSB_HIP(hipMemcpy(w->adr_D64, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice));
+        MSB_HIP(hipMemcpy(w->adr_D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice));
+        w->adr_slots = slots;
+        if (!w->part_adr) MSB_HIP(hipMalloc(&w->part_adr, sizeof(double) * 3 * (size_t)B * rows_total(p)));
+    } else {
+        MSB_CHECK(w->adr_prec == (int)prec, MSB_EINVAL,
+                  "continuing a relaxation needs an earlier msb_adr_run on this plan in the same precision");
+    }
+    const T *D = sizeof(T) == 8 ? (const T *)(const void *)w->adr_D64 : (const T *)(const void *)w->adr_D32;
+    const size_t dstride = w->adr_slots > 1 ? dn : 0;
+    PassArgs<T> pa = pass_args<T>(p, p->op);
+    const int tpc = x_tiles_per_case(p, pa.F);
+    MSB_CHECK(restart || w->adr_tiles == tpc, MSB_EINVAL,
+              "continuing a relaxation needs the launch configuration of the run it continues");
+    const size_t nt = (size_t)B * tpc;
+    if (restart) {
+        if (p->fixed)
+            hipLaunchKernelGGL(k_set_fixed<T>, dim3(grid_for(n)), dim3(kT), 0, st, u, g, (const uint8_t *)p->fixed, n, dn);
+        EndArgs<T> e = end_args<T>();
+        e.pio = u;
+        e.epi = EPI_ADR;
+        e.uin = u;
+        e.rhs = bf;
+        e.out = F;
+        e.pa = D;
+        e.pa_stride = dstride;
+        MSB_TRY(launch_product<T>(pa, e, st));
+    }
+    const bool first_pending = restart || w->adr_pending;
+    for (int64_t k = 1; k <= nsteps; ++k) {
+        const bool first = first_pending && k == 1;
+        EndArgs<T> e = end_args<T>();
+        e.pro = PRO_ADR_U;
+        e.first = first;
+        e.pio = u;
+        e.cx = v;
+        e.cq = F;
+        e.pa = D;
+        e.pa_stride = dstride;
+        e.pg = g;
+        e.cg3 = w->part_adr;
+        if (!first && tpc > kFusedReduceMaxTiles) {
+            const SumSrc src{{w->part_adr, w->part_adr + nt, nullptr, nullptr, nullptr}};
+            hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kT), 0, st, src, tpc, w->case4);
+            e.case4 = w->case4;
+        }
+        e.epi = EPI_ADR;
+        e.uin = u;
+        e.rhs = bf;
+        e.ev = v;
+        e.out = F;
+        e.part = w->part_adr;
+        MSB_TRY(launch_product<T>(pa, e, st));
+    }
+    MSB_HIP(hipGetLastError());
+    w->adr_prec = (int)prec;
+    w->adr_tiles = tpc;
+    w->adr_pending = first_pending && nsteps == 0;
+    if (res) {
+        hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * w->P), dim3(kT), 0, st, (const T *)F, (const T *)F, w->part_aux,
+                           dn, w->P);
+        hipLaunchKernelGGL(k_case_sums, dim3(B), dim3(kT), 0, st, (const double *)w->part_aux, w->P, (size_t)w->P,
+                           w->scal, 1.0);
+        MSB_HIP(hipGetLastError());
+        MSB_TRY(fetch_scal(w, st, 1, B));
+        for (int b = 0; b < B; ++b) res[b] = std::sqrt(w->h_scal[b]);
+    }
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_adr_run(msb_plan p, msb_precision prec, int64_t nsteps, int restart, void *u, void *v,
+                                  void *F, const void *b, const void *g, double *res, void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(u && v && F && b, MSB_EINVAL, "null vector");
+    MSB_CHECK(nsteps >= 0, MSB_EINVAL, "negative step count");
+    MSB_CHECK(u != v && u != F && v != F && b != u && b != v && b != F, MSB_EINVAL, "vectors must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == MSB_FP64)
+        return adr_run_t<double>(p, prec, nsteps, restart, (double *)u, (double *)v, (double *)F, (const double *)b,
+                                 (const double *)g, res, st);
+    MSB_CHECK(prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
+    return adr_run_t<float>(p, prec, nsteps, restart, (float *)u, (float *)v, (float *)F, (const float *)b,
+                            (const float *)g, res, st);
 }
 
 extern "C" msb_status msb_vv_run(msb_plan p, msb_precision prec, double dt, int64_t nsteps, void *u, void *v,

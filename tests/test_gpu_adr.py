@@ -1,0 +1,148 @@
+"""Quasi-static model by adaptive dynamic relaxation (Alg. 1, CDEI, with the fictitious
+density and damping of the cited ADR method): every GPU update against the oracle's one-step
+map, and the fixed point against the dense Cholesky solve of eq. (mat:e2)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2301_11828_amd import workloads as W
+from helpers import gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(plan, w, nsteps, g=None, dt=None, chunks=None):
+    import torch
+    dt = dt or torch.float64
+    u = torch.zeros((w.batch, w.dim, w.N), dtype=dt, device="cuda")
+    v = torch.full_like(u, float("nan"))
+    F = torch.full_like(u, float("nan"))
+    b = to_dev(w.b, dt)
+    gd = None if g is None else to_dev(g, dt)
+    res = None
+    for i, k in enumerate(chunks or [nsteps]):
+        res = plan.adr_run(k, u, v, F, b, gd, restart=(i == 0), residual=True)
+    return u.double().cpu().numpy(), v.double().cpu().numpy(), F.double().cpu().numpy(), res
+
+
+def _stepwise(plan, w, nsteps, g=None, infl=None):
+    """Takes nsteps updates one call at a time (a restart with the first update, then
+    continuations) and checks every update against the oracle's one-step map from the GPU's
+    previous state.  The adaptive damping makes whole trajectories ill-conditioned (a 1e-15
+    perturbation of b moves the oracle's own u by 1e-4 after 20 updates), so parity is per
+    update, plus the fixed point."""
+    import torch
+    u = torch.zeros((w.batch, w.dim, w.N), dtype=torch.float64, device="cuda")
+    v = torch.full_like(u, float("nan"))
+    F = torch.full_like(u, float("nan"))
+    b = to_dev(w.b)
+    gd = None if g is None else to_dev(g)
+    plan.adr_run(0, u, v, F, b, gd, restart=True)          # u_C = g and F(u^0)
+    hist = [(u.cpu().numpy(), None, F.cpu().numpy())]
+    for k in range(nsteps):
+        plan.adr_run(1, u, v, F, b, gd, restart=False)
+        hist.append((u.cpu().numpy(), v.cpu().numpy(), F.cpu().numpy()))
+    worst = 0.0
+    for c in range(w.batch):
+        p = oracle_problem(w, infl=None if infl is None else tuple(infl[c]))
+        D = O.adr_density(p, oracle_bonds(w))
+        for k in range(1, nsteps + 1):
+            u0, v0, F0 = hist[k - 1]
+            Fp = hist[k - 2][2][c] if k >= 2 else None
+            uo, vo, Fo, _ = O.adr_step(p, u0[c], None if v0 is None else v0[c], F0[c], Fp, w.b[c], D, w.fixed,
+                                       None if g is None else g[c], oracle_bonds(w))
+            u1, v1, F1 = hist[k]
+            worst = max(worst, rel_err(u1[c], uo), rel_err(v1[c], vo), rel_err(F1[c], Fo))
+    return worst, hist
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adr_fp64_updates_match_oracle(dim):
+    if dim == 2:
+        w = W.small(2, (24, 20), 3, seed=501, fixed="left", crack=True)
+    else:
+        w = W.small(3, (10, 9, 8), 2, seed=502, fixed="bottom")
+    g = np.where(w.fixed[None], 1e-3 * np.random.default_rng(503).standard_normal((1, w.dim, w.N)), 0.0)
+    plan = gpu_plan(w)
+    worst, hist = _stepwise(plan, w, 40, g)
+    log("ADR %dD: 40 updates, worst per-update rel err vs the oracle's step %.2e" % (dim, worst))
+    assert worst <= 1e-12
+    assert np.array_equal(hist[-1][0][0][w.fixed], g[0][w.fixed])
+    # the first updates as one run agree with the oracle's run (before rounding is amplified)
+    u, v, F, _ = _run(plan, w, 2, g)
+    uo, vo, Fo, _ = O.adr(oracle_problem(w), np.zeros((w.dim, w.N)), w.b[0], 2, w.fixed, g[0], oracle_bonds(w))
+    assert rel_err(u[0], uo) <= 1e-13 and rel_err(F[0], Fo) <= 1e-12
+    # a run in chunks gives the same trajectory as one run, bit for bit
+    u1, v1, F1, _ = _run(plan, w, 100, g)
+    u2, v2, F2, _ = _run(plan, w, 100, g, chunks=[40, 1, 59])
+    assert np.array_equal(u1, u2) and np.array_equal(v1, v2) and np.array_equal(F1, F2)
+
+
+def test_adr_converges_to_cholesky():
+    w = W.small(2, (20, 16), 3, seed=504, fixed="all", crack=True, batch=2)
+    g = np.where(w.fixed[None], 1e-2 * np.random.default_rng(505).standard_normal((2, w.dim, w.N)), 0.0)
+    plan = gpu_plan(w)
+    u, v, F, res = _run(plan, w, 300, g)
+    for c in range(2):
+        ref = O.solve_dense(oracle_problem(w), w.b[c], w.fixed, g[c], oracle_bonds(w))
+        err = rel_err(u[c], ref)
+        log("ADR 300 steps case %d: |F| %.2e, rel err vs Cholesky %.2e" % (c, res[c], err))
+        assert err <= 1e-11
+
+
+def test_adr_fp32_error_stated():
+    import torch
+    w = W.small(2, (32, 28), 3, seed=506, fixed="all")
+    plan = gpu_plan(w)
+    u, v, F, res = _run(plan, w, 300, dt=torch.float32)
+    ref = O.solve_dense(oracle_problem(w), w.b[0], w.fixed)
+    err = rel_err(u[0], ref)
+    log("ADR FP32 300 steps: rel err vs FP64 Cholesky %.2e" % err)
+    assert err <= 1e-5
+
+
+def test_adr_per_case_operators():
+    """Per-case influence coefficients: every case relaxes with its own operator and its own D."""
+    w = W.small(2, (18, 15), 3, seed=507, fixed="left", batch=3)
+    plan = gpu_plan(w)
+    infl = np.array([[1.0, 0.0], [0.4, 0.9], [0.7, -0.3]])
+    plan.set_infl(infl, per_case=True)
+    worst, _ = _stepwise(plan, w, 20, infl=infl)
+    log("ADR per-case operators: 20 updates, worst per-update rel err %.2e" % worst)
+    assert worst <= 1e-12
+    u, v, F, res = _run(plan, w, 3000)
+    for c in range(3):
+        ref = O.solve_dense(oracle_problem(w, infl=tuple(infl[c])), w.b[c], w.fixed)
+        err = rel_err(u[c], ref)
+        log("ADR per-case operator, case %d after 3000 updates: |F| %.2e, rel err vs Cholesky %.2e" % (c, res[c], err))
+        assert err <= 1e-9
+
+
+def test_adr_many_tiles_per_case_and_continuation_checks():
+    """More than 1024 x-tiles per case: the damping sums come from the per-case reduction
+    kernel; the trajectory equals the fused-reduction configuration's."""
+    import torch
+    import paper_2301_11828_amd as msb
+    w = W.small(2, (24, 1100), 3, seed=508, fixed="left")
+    plan = gpu_plan(w)
+    plan.set_config("fp64", rows_per_wg=1, team_x=0)
+    u1, _, F1, _ = _run(plan, w, 2)          # the second update uses the first damping sums
+    plan.set_config("fp64", rows_per_wg=8, team_x=0)
+    u2, _, F2, _ = _run(plan, w, 2)
+    d = rel_err(u1[0], u2[0])
+    log("ADR 1100 tiles/case vs fused sums: rel diff u %.2e" % d)
+    assert d <= 1e-13
+    # a changed launch configuration (tiling of the damping sums) cannot continue a run
+    import torch as _t
+    u = _t.zeros((1, w.dim, w.N), dtype=_t.float64, device="cuda")
+    v, F = _t.zeros_like(u), _t.zeros_like(u)
+    plan.adr_run(3, u, v, F, to_dev(w.b))
+    plan.set_config("fp64", rows_per_wg=1, team_x=0)
+    with pytest.raises(msb.MsbError) as e:
+        plan.adr_run(1, u, v, F, to_dev(w.b), restart=False)
+    assert e.value.status == msb.MSB_EINVAL
+    # continuing in the other precision is rejected
+    u = torch.zeros((1, w.dim, w.N), dtype=torch.float32, device="cuda")
+    with pytest.raises(msb.MsbError) as e:
+        plan.adr_run(5, u, torch.zeros_like(u), torch.zeros_like(u), to_dev(w.b, torch.float32), restart=False)
+    assert e.value.status == msb.MSB_EINVAL

@@ -719,3 +719,44 @@ def test_surface_volume_factors_closed_form():
            for s2 in (ox * ox + oy * oy for oy in range(-3, 4) for ox in range(-3, 4)) if 0 < s2 <= 9]
     full = sum(lam)
     assert nu3[5, 2] == pytest.approx(full / (full - 0.5), rel=1e-14)
+
+
+# ---------------------------------------------------------------- adaptive dynamic relaxation (Alg. 1)
+
+def test_adr_converges_to_the_dense_solution():
+    """The damped relaxation of eq. (ADR:e1) has the static solution of eq. (mat:e2) as its
+    fixed point: clamped plate with a crack and prescribed displacements, and a cantilever."""
+    from paper_2301_11828_amd import workloads as W
+    for (n, fixed, crack, steps, tol) in (((20, 16), "all", True, 200, 1e-12), ((16, 12), "left", False, 500, 1e-10)):
+        w = W.small(2, n, 3, seed=71, fixed=fixed, crack=crack)
+        p = O.Problem(w.n, w.h, w.M, w.alpha)
+        br = None if w.cracks is None else O.crack_to_bonds(p, w.cracks)
+        g = np.where(w.fixed, 0.01 * np.random.default_rng(72).standard_normal((2, p.N)), 0.0)
+        ref = O.solve_dense(p, w.b[0], w.fixed, g, br)
+        u, v, F, cs = O.adr(p, np.zeros((2, p.N)), w.b[0], steps, w.fixed, g, br)
+        err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+        assert err <= tol, (fixed, err)
+        assert np.array_equal(u[w.fixed], g[w.fixed])
+        assert all(c >= 0 for c in cs)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adr_density_bounds_the_spectrum_and_interior_closed_form(dim):
+    """D = 1/4 Gershgorin: the eigenvalues of D^-1 K lie in [0, 4]; on a node with a full
+    horizon D_aa = 1/4 (sum_b |sum_o G_ab(o)| over the diagonal block + sum_o sum_b |G_ab(o)|)
+    with the generating blocks G read off the unit-displacement force."""
+    p = _prob2(9, 8, 2) if dim == 2 else _prob3(6, 5, 5, 1)
+    K = -O.assemble_dense(p)
+    D = O.adr_density(p)
+    ev = np.linalg.eigvals(K / D.reshape(-1)[:, None]).real
+    assert ev.min() >= -1e-12 and ev.max() <= 4.0 + 1e-12
+    G = O.generating_blocks(p)
+    M = p.M
+    ctr = tuple([M] * dim)
+    off = G.copy()
+    off[(slice(None), slice(None)) + ctr] = 0.0
+    diag = -G[(slice(None), slice(None)) + ctr]       # K_pp = -A_pp
+    node = sum((M + 1) * int(np.prod(p.n[:a])) for a in range(dim))   # index (M+1, ..., M+1): full horizon
+    for a in range(dim):
+        want = 0.25 * (np.abs(diag[a]).sum() + np.abs(off[a]).sum())
+        assert D[a, node] == pytest.approx(want, rel=1e-13)
