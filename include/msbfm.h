@@ -267,19 +267,19 @@ msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds
  *                   signals (no workgroup barrier inside the transform)
  *     slots_fwd     team_x = 1: complex signals (two real rows each) per
  *     slots_inv     wavefront in the forward / inverse x pass, 1..8
- *     threads_x     team_x = 0: threads per workgroup, multiple of 64, 64..1024
+ *     threads_x     team_x = 0: threads per workgroup, multiple of 64, 64..512
  *   line passes (2D: the y column transform with the block spectral product;
  *   3D: the y transforms and the z transform with the block product):
  *     lines_per_wg  lines per workgroup, 1..16
  *     team_line     as team_x
  *     lines_per_wave  team_line = 1: lines per wavefront, 1..8
- *     threads_line  team_line = 0: threads per workgroup, multiple of 64, 64..1024
+ *     threads_line  team_line = 0: threads per workgroup, multiple of 64, 64..512
  *   max_radix       largest Stockham radix of the schedules: 4 (radices 2, 3,
  *                   4; with 5 where the length needs it), 8 (adds 8; 5 always) or
  *                   16 (adds 6, 9, 10, 12, 15, 16)
  *
  * msb_plan_set_config validates (LDS per workgroup <= 160 KiB, threads <=
- * 1024) and returns MSB_EINVAL without changing the plan otherwise.
+ * 512) and returns MSB_EINVAL without changing the plan otherwise.
  */
 typedef struct {
     int rows_per_wg, team_x, slots_fwd, slots_inv, threads_x;

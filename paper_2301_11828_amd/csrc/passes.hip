@@ -197,7 +197,9 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
         beta = T(sums[1] > 0.0 ? sums[0] / sums[1] : 0.0);
     }
     stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);
-    __syncthreads();
+    // whole-workgroup teams: the barrier before the transform also publishes the
+    // twiddles, so their loads overlap the data loads; wave teams need it here
+    if (!BLOCK) __syncthreads();
     int s0, ns;
     tm.slots(S, a.spw, s0, ns);
 
@@ -356,7 +358,7 @@ __device__ __forceinline__ void line_body(const PassArgs<T> &a, const EndArgs<T>
     T2 *bufB = bufA + (size_t)a.Fl * d * L;
     if (e.case_done && e.case_done[b]) return;
     stage_twiddles(tws, twg, L, threadIdx.x, blockDim.x);
-    __syncthreads();
+    if (!BLOCK) __syncthreads();   // whole-workgroup teams: published by the barrier before the transform
     int s0, ns;
     tm.slots(nl * d, d * a.lpw, s0, ns);
     if (ns <= 0) return;
@@ -373,14 +375,61 @@ __device__ __forceinline__ void line_body(const PassArgs<T> &a, const EndArgs<T>
             dst[t] = v;
         }
     }
+    const T *spec = a.spec + (size_t)b * a.spec_slot;
+    const size_t cstride = (size_t)nlines * L;
+    const int lines_here = ns / d;
+    // a whole-workgroup team on one line with at most kPf frequencies per thread loads
+    // its spectra into registers before the forward transform (their latency hides
+    // behind it) instead of between the two transforms
+    constexpr int kPf = 2;
+    const bool pf = BLOCK && lines_here == 1 && L <= kPf * tm.nt;
+    T gpf[kPf][6];
+    if (pf) {
+        const T *g0 = spec + (size_t)(l0 + s0 / d) * L;
+#pragma unroll
+        for (int j = 0; j < kPf; ++j) {
+            const int k = tm.tid + j * tm.nt;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) gpf[j][q] = (k < L && q < (d == 2 ? 3 : 6)) ? g0[q * cstride + k] : T(0);
+        }
+    }
     tm.sync();
     T2 *res = team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * L, bufB + (size_t)s0 * L, ns, sl, tws, tm);
     T2 *oth = (res == bufA + (size_t)s0 * L) ? bufB + (size_t)s0 * L : bufA + (size_t)s0 * L;
 
-    const T *spec = a.spec + (size_t)b * a.spec_slot;
-    const size_t cstride = (size_t)nlines * L;
-    const int lines_here = ns / d;
-    for (int lk = 0; lk < lines_here; ++lk)
+    if (pf) {
+#pragma unroll
+        for (int j = 0; j < kPf; ++j) {
+            const int k = tm.tid + j * tm.nt;
+            if (k >= L) break;
+            T2 *u = res + k;
+            if (d == 2) {
+                const T gxx = gpf[j][0], gxy = gpf[j][1], gyy = gpf[j][2];
+                const T2 ux = u[0], uy = u[L];
+                T2 fx, fy;
+                fx.x = gxx * ux.x + gxy * uy.x;
+                fx.y = gxx * ux.y + gxy * uy.y;
+                fy.x = gxy * ux.x + gyy * uy.x;
+                fy.y = gxy * ux.y + gyy * uy.y;
+                u[0] = fx;
+                u[L] = fy;
+            } else {
+                const T *g = gpf[j];
+                const T2 ux = u[0], uy = u[L], uz = u[2 * L];
+                T2 fx, fy, fz;
+                fx.x = g[0] * ux.x + g[1] * uy.x + g[2] * uz.x;
+                fx.y = g[0] * ux.y + g[1] * uy.y + g[2] * uz.y;
+                fy.x = g[1] * ux.x + g[3] * uy.x + g[4] * uz.x;
+                fy.y = g[1] * ux.y + g[3] * uy.y + g[4] * uz.y;
+                fz.x = g[2] * ux.x + g[4] * uy.x + g[5] * uz.x;
+                fz.y = g[2] * ux.y + g[4] * uy.y + g[5] * uz.y;
+                u[0] = fx;
+                u[L] = fy;
+                u[2 * L] = fz;
+            }
+        }
+    }
+    for (int lk = 0; lk < lines_here && !pf; ++lk)
     for (int k = tm.tid; k < L; k += tm.nt) {
         const int line = l0 + s0 / d + lk;
         const T *g0 = spec + (size_t)line * L + k;
@@ -444,7 +493,7 @@ __device__ __forceinline__ void yfwd_body(const PassArgs<T> &a, const EndArgs<T>
     T2 *bufB = bufA + (size_t)a.Fl * d * Ly;
     if (e.case_done && e.case_done[b]) return;
     stage_twiddles(twl, a.twy, Ly, threadIdx.x, blockDim.x);
-    __syncthreads();
+    if (!BLOCK) __syncthreads();   // whole-workgroup teams: published by the barrier before the transform
     int s0, ns;
     tm.slots(nz * d, d * a.lpw, s0, ns);
     for (int s = s0; s < s0 + ns; ++s) {
@@ -497,8 +546,7 @@ __device__ __forceinline__ void yinv_body(const PassArgs<T> &a, const EndArgs<T>
     T2 *bufA = twl + Ly;
     T2 *bufB = bufA + (size_t)a.Fl * d * Ly;
     if (e.case_done && e.case_done[b]) return;
-    stage_twiddles(twl, a.twy, Ly, threadIdx.x, blockDim.x);
-    __syncthreads();
+    stage_twiddles(twl, a.twy, Ly, threadIdx.x, blockDim.x);   // published by the barrier after the gather
     int s0, ns;
     tm.slots(nz * d, d * a.lpw, s0, ns);
     {
@@ -550,8 +598,7 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
     T2 *bufA = twl + Lx;
     T2 *bufB = bufA + (size_t)Smax * Lx;
     if (e.case_done && e.case_done[b]) return;
-    stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);
-    __syncthreads();
+    stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);   // published by the barrier after the gather
     int s0, ns;
     tm.slots(S, a.spw_i, s0, ns);
 
@@ -842,13 +889,13 @@ __device__ __forceinline__ int group_member(const int *__restrict__ start, int n
 
 #define MSB_PLAN_KERNEL(NAME, BODY, ...)                                                              \
     template <typename T, bool BLOCK, int RMAX>                                                      \
-    __global__ __launch_bounds__(1024) void NAME(PassArgs<T> a, EndArgs<T> e) {                      \
+    __global__ __launch_bounds__(kMaxBlock) void NAME(PassArgs<T> a, EndArgs<T> e) {                      \
         const int tile = xcd_tile(blockIdx.x, gridDim.x), ntiles = gridDim.x;                        \
         (void)ntiles;                                                                                \
         BODY<T, BLOCK, RMAX>(a, e, __VA_ARGS__);                                                     \
     }                                                                                                \
     template <typename T, bool BLOCK, int RMAX>                                                      \
-    __global__ __launch_bounds__(1024) void NAME##_group(const PassArgs<T> *__restrict__ A,          \
+    __global__ __launch_bounds__(kMaxBlock) void NAME##_group(const PassArgs<T> *__restrict__ A,          \
                                                          const EndArgs<T> *__restrict__ E,           \
                                                          const int *__restrict__ start, int n) {    \
         const int g = xcd_tile(blockIdx.x, gridDim.x);                                               \
@@ -901,7 +948,8 @@ msb_launch_config default_config(const msb_plan_s *p, bool fp32) {
     const int64_t rows = rows_total(p);
     c.team_x = x_units(p) >= 4096 ? 1 : 0;
     int F = c.team_x && fp32 ? 4 : 8;
-    while (F > 1 && (lds_x_bytes(d, F, p->L[0], cb) > kLdsDefault || waves_x(d, F) > 16 ||
+    const int wslots = c.team_x && fp32 ? 2 : 1;   // the smaller of the two slot counts below
+    while (F > 1 && (lds_x_bytes(d, F, p->L[0], cb) > kLdsDefault || waves_x(d, F) > (kMaxBlock / 64) * wslots ||
                      (!c.team_x && (int64_t)p->B * ((rows + F - 1) / F) < 1024)))
         F /= 2;
     c.rows_per_wg = F;
@@ -940,7 +988,8 @@ msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config 
               "slots_fwd / slots_inv not in [1, 8]");
     MSB_CHECK(c.lines_per_wave >= 1 && c.lines_per_wave <= 8, MSB_EINVAL, "lines_per_wave not in [1, 8]");
     for (int t : {c.threads_x, c.threads_line})
-        MSB_CHECK(t >= 64 && t <= 1024 && t % 64 == 0, MSB_EINVAL, "thread count %d: need a multiple of 64 in [64, 1024]", t);
+        MSB_CHECK(t >= 64 && t <= kMaxBlock && t % 64 == 0, MSB_EINVAL, "thread count %d: need a multiple of 64 in [64, %d]",
+                  t, kMaxBlock);
     MSB_CHECK(c.max_radix == 4 || c.max_radix == 8 || c.max_radix == 16, MSB_EINVAL, "max_radix must be 4, 8 or 16");
     const size_t lx = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb);
     MSB_CHECK(lx <= kLdsMax, MSB_EINVAL, "x passes need %zu bytes of LDS per workgroup (max %zu)", lx, kLdsMax);
@@ -948,10 +997,11 @@ msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config 
     MSB_CHECK(ll <= kLdsMax, MSB_EINVAL, "line passes need %zu bytes of LDS per workgroup (max %zu)", ll, kLdsMax);
     if (c.team_x) {
         const int w = waves_x(d, c.rows_per_wg);
-        MSB_CHECK(64 * ((w + c.slots_fwd - 1) / c.slots_fwd) <= 1024 && 64 * ((w + c.slots_inv - 1) / c.slots_inv) <= 1024,
-                  MSB_EINVAL, "x passes: %d slots need more than 16 waves per workgroup", w);
+        MSB_CHECK(64 * ((w + c.slots_fwd - 1) / c.slots_fwd) <= kMaxBlock &&
+                      64 * ((w + c.slots_inv - 1) / c.slots_inv) <= kMaxBlock,
+                  MSB_EINVAL, "x passes: %d slots need more than %d waves per workgroup", w, kMaxBlock / 64);
     }
-    MSB_CHECK(64 * ((c.lines_per_wg + c.lines_per_wave - 1) / c.lines_per_wave) <= 1024, MSB_EINVAL,
+    MSB_CHECK(64 * ((c.lines_per_wg + c.lines_per_wave - 1) / c.lines_per_wave) <= kMaxBlock, MSB_EINVAL,
               "line passes: too many waves per workgroup");
     const int64_t sx = c.team_x ? std::max(c.slots_fwd, c.slots_inv) : waves_x(d, c.rows_per_wg);
     const int64_t sl = c.team_line ? (int64_t)d * c.lines_per_wave : (int64_t)d * c.lines_per_wg;

@@ -6,6 +6,10 @@
 
 namespace msb {
 
+// Largest workgroup of the product kernels (their launch bound): 512 threads leave the
+// compiler 256 VGPRs per lane, which the FP64 radix-16 passes need without spilling.
+constexpr int kMaxBlock = 512;
+
 // What the x-forward pass does to its input rows before transforming them.
 enum Prologue : int {
     PRO_NONE = 0,   // transform u as given

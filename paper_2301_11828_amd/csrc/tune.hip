@@ -134,7 +134,7 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
     bn.nrep = std::max(3, std::min(kMaxRep, (int)std::ceil(2.0 / std::max(bn.total(), 1e-3))));
 
     const std::vector<int> Fs = {1, 2, 4, 8, 16};
-    const std::vector<int> ths = effort ? std::vector<int>{64, 128, 256, 512, 1024} : std::vector<int>{128, 256, 512};
+    const std::vector<int> ths = effort ? std::vector<int>{64, 128, 256, 384, 512} : std::vector<int>{128, 256, 512};
     const std::vector<int> sls = effort ? std::vector<int>{1, 2, 3, 4, 6, 8} : std::vector<int>{1, 2, 4};
     const std::vector<int> lpws = effort ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{1, 2};
 

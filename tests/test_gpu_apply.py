@@ -179,8 +179,9 @@ def test_wave_owned_signals_match_oracle(prec, spw, spwi, lpw, dim):
     else:
         w = W.small(3, (13, 11, 9), 2, seed=62, fixed="bottom", batch=2)
     plan = gpu_plan(w)
-    plan.set_config(prec, rows_per_wg=8, team_x=1, slots_fwd=spw, slots_inv=spwi, team_line=1, lines_per_wg=4,
-                    lines_per_wave=lpw, max_radix=16)
+    # at most 8 waves per workgroup: 3D rows of 3 components take 5 rows (8 slots) per workgroup
+    plan.set_config(prec, rows_per_wg=8 if dim == 2 else 5, team_x=1, slots_fwd=spw, slots_inv=spwi, team_line=1,
+                    lines_per_wg=4, lines_per_wave=lpw, max_radix=16)
     dt = torch.float64 if prec == "fp64" else torch.float32
     u = w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64)
     f = gpu_apply(plan, to_dev(w.b, dt)).double().cpu().numpy()

@@ -36,9 +36,9 @@ def _random_configs(rng, count):
     for _ in range(count):
         out.append(dict(rows_per_wg=int(rng.choice([1, 2, 3, 4, 5, 8, 16])), team_x=int(rng.integers(2)),
                         slots_fwd=int(rng.integers(1, 9)), slots_inv=int(rng.integers(1, 9)),
-                        threads_x=64 * int(rng.integers(1, 17)), lines_per_wg=int(rng.choice([1, 2, 3, 5, 8, 16])),
+                        threads_x=64 * int(rng.integers(1, 9)), lines_per_wg=int(rng.choice([1, 2, 3, 5, 8, 16])),
                         team_line=int(rng.integers(2)), lines_per_wave=int(rng.integers(1, 9)),
-                        threads_line=64 * int(rng.integers(1, 17)), max_radix=int(rng.choice([4, 8, 16]))))
+                        threads_line=64 * int(rng.integers(1, 9)), max_radix=int(rng.choice([4, 8, 16]))))
     return out
 
 
@@ -73,7 +73,7 @@ def test_invalid_configs_rejected_and_plan_unchanged():
     w = W.small(2, (30, 20), 3, seed=84, fixed="left")
     plan = gpu_plan(w)
     before = plan.get_config("fp64")
-    for bad in (dict(threads_x=100), dict(threads_line=2048), dict(max_radix=7), dict(rows_per_wg=0),
+    for bad in (dict(threads_x=100), dict(threads_line=2048), dict(threads_x=1024), dict(max_radix=7), dict(rows_per_wg=0),
                 dict(rows_per_wg=17), dict(team_x=2), dict(slots_fwd=9), dict(lines_per_wave=0)):
         with pytest.raises(msb.MsbError) as e:
             plan.set_config("fp64", **bad)
