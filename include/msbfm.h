@@ -220,7 +220,11 @@ msb_status msb_vv_run(msb_plan plan, msb_precision prec, double dt, int64_t nste
  * the quotient is not positive.  The fixed point is the static solution of eq. (mat:e2).
  * restart != 0: start from u (u_C set to g), build D, evaluate F^0 and take nsteps
  * updates.  restart = 0: continue from (u, v, F) with the damping sums the previous call
- * on this plan left in its workspace (same precision; MSB_EINVAL otherwise).
+ * on this plan left in its workspace (same precision and launch configuration;
+ * MSB_EINVAL otherwise); if the operator changed in between (coefficients, broken bonds
+ * -- crack updates included --, surface factors, constraints) D is rebuilt for it; the
+ * next update still uses the F given and the damping sums formed with it (the force and
+ * the density before the change).
  * u, v (= v^{n-1/2}), F (= F(u^n) on return): device [B][d][N] in/out; b: device, constant;
  * g: device or NULL (= 0); all double (MSB_FP64) or float (MSB_FP32).  res: host [B] or
  * NULL: ||F||_2 of the final state per case (synchronises the stream).

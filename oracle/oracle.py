@@ -611,7 +611,7 @@ def adr_density(prob: Problem, broken=None) -> np.ndarray:
     return (0.25 * np.abs(K).sum(axis=1)).reshape(prob.dim, prob.N)
 
 
-def adr_step(prob: Problem, u, v, F, Fprev, b, D, fixed=None, g=None, broken=None):
+def adr_step(prob: Problem, u, v, F, Fprev, b, D, fixed=None, g=None, broken=None, Dc=None):
     """One update of Alg. 1 (time step 1) from u^n with F = F(u^n), the velocity v^{n-1/2}
     and F^{n-1} (Fprev None: the first update, v^{1/2} = D^{-1} F^0 / 2):
 
@@ -620,8 +620,10 @@ def adr_step(prob: Problem, u, v, F, Fprev, b, D, fixed=None, g=None, broken=Non
         v^{n+1/2}  = ((2 - c^n) v^{n-1/2} + 2 D^{-1} F^n) / (2 + c^n)
         u^{n+1}    = u^n + v^{n+1/2}
 
-    F = A u + b on free DOFs, 0 on constrained ones (u held at g there).  Returns
-    (u^{n+1}, v^{n+1/2}, F(u^{n+1}), c^n or None for the first update)."""
+    F = A u + b on free DOFs, 0 on constrained ones (u held at g there).  Dc: the density in
+    K1 when it differs from D (the one in force when F^n was evaluated, for a step right
+    after the operator changed).  Returns (u^{n+1}, v^{n+1/2}, F(u^{n+1}), c^n or None for the
+    first update)."""
     d, N = prob.dim, prob.N
     fx = _split(prob, fixed).reshape(d, N)
     free = ~fx
@@ -635,7 +637,7 @@ def adr_step(prob: Problem, u, v, F, Fprev, b, D, fixed=None, g=None, broken=Non
         v = np.asarray(v, dtype=np.float64).reshape(d, N)
         Fp = np.asarray(Fprev, dtype=np.float64).reshape(d, N)
         with np.errstate(divide="ignore", invalid="ignore"):
-            k1 = np.where(free & (v != 0.0), -(F - Fp) / (D * v), 0.0)
+            k1 = np.where(free & (v != 0.0), -(F - Fp) / ((D if Dc is None else Dc) * v), 0.0)
         num = float((u[free] * k1[free] * u[free]).sum())
         den = float((u[free] * u[free]).sum())
         c = 2.0 * math.sqrt(num / den) if den > 0 and num > 0 else 0.0

@@ -199,6 +199,8 @@ struct msb_plan_s {
 
     // solver vectors, partial sums and pinned mirrors (solver translation unit)
     void *solver_cache = nullptr;
+    // incremented whenever A changes (coefficients, bonds, surface factors, constraints)
+    int64_t op_version = 0;
 };
 
 namespace msb {

@@ -57,6 +57,8 @@ std::vector<int> half_stencil(const msb_plan_s *p) {
     return out;
 }
 
+msb_status alloc_crack_ws(msb_plan_s *p, CrackWs *w, const std::vector<int> &hoff);
+
 msb_status get_crack_ws(msb_plan_s *p, CrackWs *&out) {
     if (p->crack_ws) {
         out = static_cast<CrackWs *>(p->crack_ws);
@@ -69,6 +71,17 @@ msb_status get_crack_ws(msb_plan_s *p, CrackWs *&out) {
               "in the half stencil (this horizon has %d)", nh);
     CrackWs *w = new CrackWs();
     p->crack_ws = w;
+    const msb_status s = alloc_crack_ws(p, w, hoff);
+    if (s != MSB_OK) {
+        crack_free(p);   // a partial workspace is never reused
+        return s;
+    }
+    out = w;
+    return MSB_OK;
+}
+
+msb_status alloc_crack_ws(msb_plan_s *p, CrackWs *w, const std::vector<int> &hoff) {
+    const int nh = (int)hoff.size() / 3;
     w->hoff_host = hoff;
     w->nh = nh;
     w->len.resize(nh);
@@ -92,7 +105,6 @@ msb_status get_crack_ws(msb_plan_s *p, CrackWs *&out) {
     MSB_HIP(hipHostMalloc(&w->h_total, sizeof(int64_t)));
     MSB_HIP(hipHostMalloc(&w->h_thr2, sizeof(double) * std::max(1, nh)));
     p->mu_valid = false;
-    out = w;
     return MSB_OK;
 }
 

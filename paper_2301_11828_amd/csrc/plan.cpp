@@ -711,6 +711,7 @@ extern "C" msb_status msb_plan_info(msb_plan p, int64_t *L, int64_t *N, int64_t 
 
 extern "C" msb_status msb_plan_set_constraints(msb_plan p, const uint8_t *fixed) {
     MSB_CHECK(p, MSB_EINVAL, "null plan");
+    ++p->op_version;
     const size_t n = (size_t)p->dim * p->N;
     if (!fixed) {
         if (p->fixed) hipFree(p->fixed);
@@ -739,6 +740,7 @@ extern "C" msb_status msb_plan_set_bonds(msb_plan p, const int64_t *pairs, int64
 
 extern "C" msb_status msb_plan_set_surface(msb_plan p, const double *nu) {
     MSB_CHECK(p, MSB_EINVAL, "null plan");
+    ++p->op_version;
     if (!nu) {
         if (p->nu64) hipFree(p->nu64);
         if (p->nu32) hipFree(p->nu32);
@@ -800,6 +802,7 @@ extern "C" msb_status msb_plan_get_bonds(msb_plan p, int64_t *pairs, int64_t cap
 }
 
 msb_status msb::set_bonds_impl(msb_plan_s *p, const int64_t *pairs, int64_t nb) {
+    ++p->op_version;
     MSB_CHECK(nb >= 0, MSB_EINVAL, "negative bond count");
     MSB_CHECK(nb == 0 || pairs, MSB_EINVAL, "null bond list");
     const int d = p->dim, M = p->M, B = 2 * M + 1;
@@ -952,6 +955,7 @@ extern "C" msb_status msb_crack_to_bonds(const msb_problem_desc *desc, const dou
 }
 
 extern "C" msb_status msb_plan_set_infl(msb_plan p, const double *infl, int n_infl, int per_case) {
+    if (p) ++p->op_version;
     MSB_CHECK(p, MSB_EINVAL, "null plan");
     MSB_CHECK(n_infl >= 0 && n_infl <= 8, MSB_EINVAL, "n_infl must be in [0, 8]");
     MSB_CHECK(n_infl == 0 || infl, MSB_EINVAL, "null coefficients");

@@ -41,6 +41,7 @@ struct SolverWs {
     int adr_prec = -1;               // precision of the last relaxation run (its partials), -1 none
     int adr_tiles = 0;               // x tiles per case its partials were written with
     bool adr_pending = false;        // restarted without an update: the next update is the first
+    int64_t adr_version = -1;        // operator version D was built for
     double *thresh = nullptr;        // [B]
     double *scal = nullptr;          // [16][B] per-case scalars
     double *energy = nullptr;        // energies (device)
@@ -75,6 +76,10 @@ void solver_cache_free(msb_plan_s *p) {
     p->solver_cache = nullptr;
 }
 
+static msb_status alloc_ws(msb_plan_s *p, SolverWs *w);
+
+// The plan's solver workspace, allocated on first use; a failed allocation frees the
+// partial workspace (the next call starts over).
 static msb_status get_ws(msb_plan_s *p, SolverWs *&out) {
     if (p->solver_cache) {
         out = static_cast<SolverWs *>(p->solver_cache);
@@ -82,6 +87,16 @@ static msb_status get_ws(msb_plan_s *p, SolverWs *&out) {
     }
     SolverWs *w = new SolverWs();
     p->solver_cache = w;
+    const msb_status s = alloc_ws(p, w);
+    if (s != MSB_OK) {
+        solver_cache_free(p);
+        return s;
+    }
+    out = w;
+    return MSB_OK;
+}
+
+static msb_status alloc_ws(msb_plan_s *p, SolverWs *w) {
     const int B = p->B;
     w->nvec = (size_t)B * p->dim * p->N;
     const size_t dn = (size_t)p->dim * p->N;
@@ -103,9 +118,16 @@ static msb_status get_ws(msb_plan_s *p, SolverWs *&out) {
     MSB_HIP(hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking));
     MSB_HIP(hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming));
     MSB_HIP(hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming));
-    out = w;
     return MSB_OK;
 }
+
+// Device buffer owned for the duration of a call (freed on every return path).
+struct CallBuf {
+    void *p = nullptr;
+    ~CallBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
 
 // ------------------------------------------------------------------ vector kernels
 template <typename T> __global__ void k_fill(T *x, size_t n, T v) {
@@ -739,12 +761,13 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
         // or restarts from the new residual (plain iterative refinement).
         const bool reliable = opts->reliable_update != 0;
         const double itol = opts->inner_tol > 0 ? opts->inner_tol : (reliable ? 0.1 : 1e-4);
-        int *skip = nullptr;
-        MSB_HIP(hipMalloc(&skip, sizeof(int) * B));
+        CallBuf skip_buf, prev_buf;
+        MSB_HIP(hipMalloc(&skip_buf.p, sizeof(int) * B));
+        int *skip = static_cast<int *>(skip_buf.p);
         float *r32 = w->v32[0], *d32 = w->v32[1], *p32 = w->v32[2];
         double *r64 = w->v64[2];
-        double *prev = nullptr;   // [B][tiles] r.r partials before the replacement
-        if (reliable) MSB_HIP(hipMalloc(&prev, sizeof(double) * (size_t)B * rows_total(p)));
+        if (reliable) MSB_HIP(hipMalloc(&prev_buf.p, sizeof(double) * (size_t)B * rows_total(p)));
+        double *prev = static_cast<double *>(prev_buf.p);   // [B][tiles] r.r partials before the replacement
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kT), 0, st, u, n, 0.0);
         hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(kT), 0, st, p32, n, 0.0f);
         hipLaunchKernelGGL((k_cast<double, double>), dim3(grid_for(n)), dim3(kT), 0, st, r64, (const double *)bp, n);
@@ -814,8 +837,6 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
                 }
             }
         }
-        (void)hipFree(skip);
-        if (prev) (void)hipFree(prev);
         for (int c = 0; c < B; ++c)
             if (fl[c] == -1) fl[c] = RUNNING;   // reported as no convergence below
     }
@@ -924,7 +945,10 @@ static msb_status adr_run_t(msb_plan_s *p, msb_precision prec, int64_t nsteps, i
     MSB_TRY(get_ws(p, w));
     const int B = p->B;
     const size_t n = w->nvec, dn = (size_t)p->dim * p->N;
-    if (restart) {
+    if (!restart)
+        MSB_CHECK(w->adr_prec == (int)prec, MSB_EINVAL,
+                  "continuing a relaxation needs an earlier msb_adr_run on this plan in the same precision");
+    if (restart || w->adr_version != p->op_version) {   // D for the current operator
         std::vector<double> D;
         int slots = 0;
         build_adr_density(p, D, slots);
@@ -932,17 +956,16 @@ static msb_status adr_run_t(msb_plan_s *p, msb_precision prec, int64_t nsteps, i
         if (w->adr_D32) (void)hipFree(w->adr_D32);
         w->adr_D64 = nullptr;
         w->adr_D32 = nullptr;
-        w->adr_prec = -1;
+        w->adr_prec = -1;          // no continuation unless this rebuild completes
+        w->adr_version = -1;
         MSB_HIP(hipMalloc(&w->adr_D64, sizeof(double) * D.size()));
         MSB_HIP(hipMalloc(&w->adr_D32, sizeof(float) * D.size()));
         std::vector<float> D32(D.begin(), D.end());
         MSB_HIP(hipMemcpy(w->adr_D64, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice));
         MSB_HIP(hipMemcpy(w->adr_D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice));
         w->adr_slots = slots;
+        w->adr_version = p->op_version;
         if (!w->part_adr) MSB_HIP(hipMalloc(&w->part_adr, sizeof(double) * 3 * (size_t)B * rows_total(p)));
-    } else {
-        MSB_CHECK(w->adr_prec == (int)prec, MSB_EINVAL,
-                  "continuing a relaxation needs an earlier msb_adr_run on this plan in the same precision");
     }
     const T *D = sizeof(T) == 8 ? (const T *)(const void *)w->adr_D64 : (const T *)(const void *)w->adr_D32;
     const size_t dstride = w->adr_slots > 1 ? dn : 0;

@@ -146,3 +146,34 @@ def test_adr_many_tiles_per_case_and_continuation_checks():
     with pytest.raises(msb.MsbError) as e:
         plan.adr_run(5, u, torch.zeros_like(u), torch.zeros_like(u), to_dev(w.b, torch.float32), restart=False)
     assert e.value.status == msb.MSB_EINVAL
+
+
+def test_adr_continues_across_a_crack_update():
+    """Quasi-static crack growth: relax, break bonds, continue.  The continuation rebuilds D
+    for the new broken set; the next update matches the oracle's step from the GPU state
+    with the new operator (the forces before the change drive the damping and the update)."""
+    import torch
+    w = W.small(2, (26, 22), 3, seed=509, fixed="left")
+    plan = gpu_plan(w)
+    p = oracle_problem(w)
+    u = torch.zeros((1, w.dim, w.N), dtype=torch.float64, device="cuda")
+    v, F = torch.zeros_like(u), torch.zeros_like(u)
+    b = to_dev(w.b)
+    plan.adr_run(29, u, v, F, b)
+    F29 = F.cpu().numpy()[0]
+    plan.adr_run(1, u, v, F, b, restart=False)
+    u30, v30, F30 = u.cpu().numpy()[0], v.cpu().numpy()[0], F.cpu().numpy()[0]
+    s = np.sort(O.bond_stretch(p, u30, O.all_bonds(p)))
+    i = int(0.9 * len(s))
+    s0 = 0.5 * (s[i - 1] + s[i])
+    assert s0 > 0 and np.abs(s - s0).min() > 1e-9 * s0
+    nnew = plan.crack_update(u, s0)
+    broken = plan.bonds()
+    assert nnew > 0
+    plan.adr_run(1, u, v, F, b, restart=False)
+    D = O.adr_density(p, broken)
+    D_before = O.adr_density(p, None)   # the damping sums were formed with F^30, before the breaks
+    uo, vo, Fo, _ = O.adr_step(p, u30, v30, F30, F29, w.b[0], D, w.fixed, None, broken, Dc=D_before)
+    e = max(rel_err(u.cpu().numpy()[0], uo), rel_err(v.cpu().numpy()[0], vo), rel_err(F.cpu().numpy()[0], Fo))
+    log("ADR continuation across a crack update (%d new breaks): rel err %.2e" % (nnew, e))
+    assert e <= 1e-12
