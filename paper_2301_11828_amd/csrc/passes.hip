@@ -206,6 +206,7 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
     const T hdt2 = T(0.5 * e.dt * e.dt);
     const T dtt = T(e.dt);
     const size_t cbase = (size_t)b * a.d * a.N;
+    const FastDiv by_nr((uint32_t)nr, (uint32_t)(2 * S));   // signal -> component (uniform, no division loop)
     double rr_acc = 0.0;
     for (int s = s0; s < s0 + ns; ++s) {
         size_t rowaddr[2];
@@ -215,7 +216,7 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
         for (int h2 = 0; h2 < 2; ++h2) {
             const int sig = 2 * s + h2;
             has[h2] = sig < nsig;
-            const int c = has[h2] ? sig / nr : 0;
+            const int c = has[h2] ? (int)by_nr.div((uint32_t)sig) : 0;
             const int r = has[h2] ? sig - c * nr : 0;
             rowaddr[h2] = cbase + (size_t)c * a.N + (size_t)(r0 + r) * a.Nx;
             rowfix[h2] = c * a.N + (r0 + r) * a.Nx;
@@ -598,6 +599,10 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
     T2 *bufA = twl + Lx;
     T2 *bufB = bufA + (size_t)Smax * Lx;
     if (e.case_done && e.case_done[b]) return;
+    // uniform splits signal -> (component, row) and row -> (z, y) by multiply-high: the
+    // per-slot loops below would otherwise run a scalar division sequence each time
+    const FastDiv by_nr((uint32_t)nr, (uint32_t)(2 * S));
+    const FastDiv by_ny((uint32_t)a.Ny, (uint32_t)a.rows);
     stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);   // published by the barrier after the gather
     int s0, ns;
     tm.slots(S, a.spw_i, s0, ns);
@@ -658,8 +663,8 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
             const T *wt = a.w + (size_t)b * a.w_slot;
             for (int sl = 0; sl < nsg; ++sl) {
                 const int sig = 2 * s0 + sl;
-                const int c = sig / nr, row = r0 + sig - c * nr;
-                const int z = row / a.Ny, y = row - z * a.Ny;
+                const int c = (int)by_nr.div((uint32_t)sig), row = r0 + sig - c * nr;
+                const int z = (int)by_ny.div((uint32_t)row), y = row - z * a.Ny;
                 const bool row_e = y < M || y >= a.Ny - M || (d == 3 && (z < M || z >= a.Nz - M));
                 const int e0 = a.br_row_ptr[row], e1 = a.br_row_ptr[row + 1];
                 for (int ei = e0 + tm.tid; ei < e1; ei += tm.nt) {
@@ -695,9 +700,9 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
         const int M1p = d == 2 ? M1 * M1 : M1 * M1 * M1 * M1;
         auto row_of = [&](int sl, int &c, int &row, int &rpart) -> bool {
             const int sig = 2 * s0 + sl;
-            c = sig / nr;
+            c = (int)by_nr.div((uint32_t)sig);
             row = r0 + sig - c * nr;
-            const int z = row / a.Ny, y = row - z * a.Ny;
+            const int z = (int)by_ny.div((uint32_t)row), y = row - z * a.Ny;
             const int ly = min(y, M), hy = min(a.Ny - 1 - y, M);
             const int lz = d == 3 ? min(z, M) : 0, hz = d == 3 ? min(a.Nz - 1 - z, M) : 0;
             rpart = ly * M1 + hy;
@@ -722,7 +727,7 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
             for (int sl = 0; sl < nsg; ++sl) {
                 int c, row, rpart;
                 const bool edge_cols = row_of(sl, c, row, rpart) && !narrow;   // interior row
-                const int z = row / a.Ny, y = row - z * a.Ny;
+                const int z = (int)by_ny.div((uint32_t)row), y = row - z * a.Ny;
                 const int ncol = edge_cols ? 2 * M : a.Nx;
                 for (int jj = tm.tid; jj < ncol; jj += tm.nt) {
                     const int n = edge_cols ? (jj < M ? jj : a.Nx - 2 * M + jj) : jj;
