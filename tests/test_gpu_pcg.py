@@ -156,3 +156,25 @@ def test_pcg_rejects_reliable_update():
     with pytest.raises(msb.MsbError) as e:
         plan.solve(to_dev(w.b), precision="fp32_refined", reliable_update=1, precond=True)
     assert e.value.status == msb.MSB_EUNSUPPORTED
+
+
+def test_plate512_pcg_at_the_benchmark_tuning_certified_by_oracle():
+    """Full size, the bench's recorded tuning: FP64 and FP32-refined preconditioned solves to
+    1e-10, each certified by the oracle's bond-sum residual."""
+    import json
+    import os
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                                      "plate512_tuning.json")))
+    w = W.plate512()
+    plan = gpu_plan(w)
+    plan.set_lengths(rec["padded"])
+    plan.set_config("fp64", **rec["fp64"])
+    plan.set_config("fp32", **rec["fp32"])
+    p = oracle_problem(w)
+    bp = O.lifted_rhs(p, w.b[0], w.fixed).reshape(-1)
+    for prec in ("fp64", "fp32_refined"):
+        u, info = plan.solve(to_dev(w.b), precision=prec, tol=1e-10, maxit=200000, precond=True)
+        r = bp + O.apply(p, u.cpu().numpy()[0], w.fixed).reshape(-1)
+        res = np.linalg.norm(r) / np.linalg.norm(bp)
+        log("plate512 PCG %s: %d it, oracle residual %.2e" % (prec, info[0].inner_iters, res))
+        assert info[0].status == 0 and res <= 1.05e-10
