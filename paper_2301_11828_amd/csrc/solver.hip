@@ -286,7 +286,7 @@ template <int K> __global__ void k_cg_sums(SumSrc src, int tpc, double *out) {
     }
 }
 
-// Tiles per case above which the per-case sums come from k_cg_case4.
+// Tiles per case above which the per-case sums come from k_cg_sums.
 constexpr int kFusedReduceMaxTiles = 1024;
 
 // One CG iteration = one product chain.  The x-forward prologue applies the
