@@ -498,6 +498,11 @@ def bench_plates64(args):
         return time.perf_counter() - t0, r
 
     dt, (loss, grads) = timed(run_group)
+    # the same with every member's CG preconditioned by its circulant inverse (each
+    # preconditioner is rebuilt when the member's coefficients change: inside the timing)
+    grp.precond = True
+    dtc, (loss_c, grads_c) = timed(run_group)
+    grp.precond = False
     dtp, (loss_p, grads_p) = timed(run_plans)
     dts, (loss_s, grads_s) = timed(run_sizes)
 
@@ -509,6 +514,8 @@ def bench_plates64(args):
                         "target + forward + adjoint FP32-refined solves to 1e-10 and dL/da" % sizes,
             "plates": len(ws), "dofs_total": dofs, "solves": 3 * len(ws),
             "seconds": round(dt, 3), "mode": "64 plans in one plan group (one launch per pass)",
+            "seconds_group_pcg": round(dtc, 3), "speedup_group_pcg_vs_group": round(dt / dtc, 2),
+            "grad_max_rel_diff_pcg_vs_cg": gdiff(grads_c, grads),
             "seconds_64_plans_one_after_another": round(dtp, 3),
             "seconds_batched_per_size_one_after_another": round(dts, 3),
             "speedup_group_vs_plans": round(dtp / dt, 2), "speedup_group_vs_batched_sizes": round(dts / dt, 2),

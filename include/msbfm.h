@@ -168,7 +168,9 @@ typedef struct {
                                without the D^e / D^f corrections and masked to the free DOFs.
                                Built on first use (host work like the operator's spectra),
                                freed when the influence coefficients change.  Two product
-                               chains per iteration.  Not with reliable_update or groups
+                               chains per iteration (for a plan group, two group launches:
+                               every member's preconditioner chain, then every member's
+                               stiffness chain).  Not with reliable_update
                                (MSB_EUNSUPPORTED). */
 } msb_solve_opts;
 
@@ -343,6 +345,9 @@ msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int 
  *   once: b, u: host arrays [nplans] of device pointers; g: null or such an array
  *   (entries may be null); info: host [total cases], member-major.  MSB_FP64,
  *   MSB_FP32 or MSB_FP32_REFINED (restarted refinement; reliable_update must be 0).
+ *   opts->precond = 1 preconditions every member by its own circulant inverse (each
+ *   built on first use, as for one plan).  A member with the surface correction set
+ *   is rejected (MSB_EUNSUPPORTED: that operator is not symmetric).
  */
 typedef struct msb_group_s *msb_group;
 msb_status msb_group_create(const msb_plan *plans, int nplans, msb_group *out);

@@ -452,13 +452,14 @@ class PlanGroup:
     (or dropped) before them.  Vectors are passed as lists, one tensor per member, each
     shaped as for that member's Plan."""
 
-    def __init__(self, plans):
+    def __init__(self, plans, precond: bool = False):
         lib = load_library()
         self.plans = list(plans)
         arr = (ctypes.c_void_p * len(self.plans))(*[p._ptr.value for p in self.plans])
         self._ptr = ctypes.c_void_p()
         _check(lib.msb_group_create(arr, len(self.plans), ctypes.byref(self._ptr)))
         self.total_cases = sum(p.batch for p in self.plans)
+        self.precond = bool(precond)   # default of solve(): circulant-preconditioned CG
 
     def close(self):
         if self._ptr:
@@ -502,12 +503,15 @@ class PlanGroup:
         return outs
 
     def solve(self, bs, gs=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
-              inner_tol: float = 0.0, graph_block: int = 0, outs=None, check: bool = True):
-        """Static solves of every member at once; returns (list of u, list of per-member info lists)."""
+              inner_tol: float = 0.0, graph_block: int = 0, outs=None, check: bool = True, precond=None):
+        """Static solves of every member at once; returns (list of u, list of per-member info lists).
+        precond: each member's CG preconditioned by its circulant inverse (None: the
+        group's `precond` attribute, which the autograd function's solves also use)."""
         torch = _torch()
         if outs is None:
             outs = [torch.empty_like(b) for b in bs]
-        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), 0, 0)
+        pre = self.precond if precond is None else bool(precond)
+        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), 0, int(pre))
         infos = (_Info * self.total_cases)()
         gp = None
         if gs is not None:

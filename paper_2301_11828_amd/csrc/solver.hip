@@ -1105,8 +1105,11 @@ struct msb_group_s {
     bool composite[2] = {};
     int *dstart[2] = {};                       // device copies [3][n + 1]
     void *dA[2] = {};                          // device PassArgs<T>[n]
+    void *dAp[2] = {};                         // device PassArgs<T>[n] of the preconditioners
     void *dE[2] = {};                          // device EndArgs<T>[kSlots][n]
     double *part_x = nullptr, *part_rr = nullptr;   // [3][tiles], [2][tiles] (largest precision)
+    double *part_rz = nullptr;                      // [2][3][tiles]: r.z partials by iteration parity
+    size_t tiles_max = 0;                           // x tiles of every member at one row per tile
     double *thresh = nullptr, *scal = nullptr;      // [Btot], [16][Btot]
     int *done = nullptr, *iters = nullptr, *skip = nullptr;   // [Btot]
     double *h_scal = nullptr;                  // pinned [16][Btot]
@@ -1119,8 +1122,12 @@ namespace msb {
 namespace {
 
 // argument slots of a group: CG iterations (first; even and odd partial-sum parity;
-// the final update-only iteration of each parity) and one-off products
-enum GroupSlot { G_FIRST, G_EVEN, G_ODD, G_UPD_EVEN, G_UPD_ODD, G_LIFT, G_RESID, G_CERT, kSlots };
+// the final update-only iteration of each parity; with the preconditioner these are
+// the slots of the preconditioner chain and G_PA_* those of the stiffness chain) and
+// one-off products
+enum GroupSlot {
+    G_FIRST, G_EVEN, G_ODD, G_UPD_EVEN, G_UPD_ODD, G_PA_FIRST, G_PA_EVEN, G_PA_ODD, G_LIFT, G_RESID, G_CERT, kSlots
+};
 
 msb_status group_geometry(msb_group_s *g, int f) {
     const bool f32 = f == 1;
@@ -1204,7 +1211,7 @@ template <typename T> GroupView full_view(const msb_group_s *g) {
 
 template <typename T>
 msb_status group_launch(msb_group_s *g, const std::vector<PassArgs<T>> &A, int slot, hipStream_t st,
-                        const GroupView *view = nullptr) {
+                        const GroupView *view = nullptr, bool pre = false) {
     const int f = prec_index<T>();
     const GroupView v = view ? *view : full_view<T>(g);
     GroupGrid gg;
@@ -1219,29 +1226,33 @@ msb_status group_launch(msb_group_s *g, const std::vector<PassArgs<T>> &A, int s
     gg.lds_l = g->lds[f][1];
     gg.lds_y = g->lds[f][2];
     const EndArgs<T> *dE = static_cast<const EndArgs<T> *>(g->dE[f]) + (size_t)slot * g->n;
-    return launch_group<T>(A[0], gg, static_cast<const PassArgs<T> *>(g->dA[f]), dE, g->composite[f], st);
+    return launch_group<T>(A[0], gg, static_cast<const PassArgs<T> *>(pre ? g->dAp[f] : g->dA[f]), dE,
+                           g->composite[f], st);
 }
 
 // Load the device arrays with the members in `act` (argument arrays, the CG slots'
 // end arguments and the tile tables); returns the matching view.
 template <typename T>
 msb_status group_load_members(msb_group_s *g, const std::vector<int> &act, const std::vector<PassArgs<T>> &A,
-                              const std::vector<std::vector<EndArgs<T>>> &Eslots, GroupView &v) {
+                              const std::vector<std::vector<EndArgs<T>>> &Eslots, GroupView &v,
+                              const std::vector<PassArgs<T>> *Ap = nullptr) {
     const int f = prec_index<T>();
     const int na = (int)act.size();
-    std::vector<PassArgs<T>> Aa(na);
+    std::vector<PassArgs<T>> Aa(na), Apa(Ap ? na : 0);
     std::vector<int> st3(3 * (na + 1), 0);
     v.n = na;
     for (int k = 0; k < 3; ++k) v.total[k] = 0;
     for (int j = 0; j < na; ++j) {
         const int i = act[j];
         Aa[j] = A[i];
+        if (Ap) Apa[j] = (*Ap)[i];
         for (int k = 0; k < 3; ++k) {
             st3[k * (na + 1) + j + 1] = st3[k * (na + 1) + j] + (g->start[f][k][i + 1] - g->start[f][k][i]);
         }
     }
     for (int k = 0; k < 3; ++k) v.total[k] = st3[k * (na + 1) + na];
     MSB_HIP(hipMemcpy(g->dA[f], Aa.data(), sizeof(PassArgs<T>) * na, hipMemcpyHostToDevice));
+    if (Ap) MSB_HIP(hipMemcpy(g->dAp[f], Apa.data(), sizeof(PassArgs<T>) * na, hipMemcpyHostToDevice));
     MSB_HIP(hipMemcpy(g->dstart[f], st3.data(), sizeof(int) * st3.size(), hipMemcpyHostToDevice));
     for (size_t slot = 0; slot < Eslots.size(); ++slot) {
         std::vector<EndArgs<T>> Ea(na);
@@ -1259,14 +1270,19 @@ msb_status group_quiesce(msb_group_s *g, hipStream_t user) {
     return MSB_OK;
 }
 
-// Group CG on K d_i = rhs_i for every member, x0 = 0 (restart), like cg_solve.
+// Group CG on K d_i = rhs_i for every member, x0 = 0 (restart), like cg_solve; with the
+// preconditioners' arguments Ap and the vectors z, preconditioned CG like pcg_solve (two
+// group launches per iteration: the preconditioner chain, then the stiffness chain).
 template <typename T>
 msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std::vector<const T *> &rhs,
                     const std::vector<T *> &x, const std::vector<T *> &r, const std::vector<T *> &pv,
                     const std::vector<T *> &q, double tol, int maxit, int graph_block, const int *skip,
-                    const double *tol2_case = nullptr) {
+                    const double *tol2_case = nullptr, const std::vector<PassArgs<T>> *Ap = nullptr,
+                    const std::vector<T *> *z = nullptr) {
     const int f = prec_index<T>();
     hipStream_t st = g->st;
+    const bool pcg = Ap != nullptr;
+    if (pcg && !z) return MSB_EINVAL;
     for (int i = 0; i < g->n; ++i) {
         msb_plan_s *p = g->m[i];
         SolverWs *w = nullptr;
@@ -1285,28 +1301,62 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     MSB_HIP(hipGetLastError());
     // end arguments of the iteration slots (no kernel of an earlier solve still reads them)
     MSB_HIP(hipStreamSynchronize(st));
-    std::vector<std::vector<EndArgs<T>>> Eslots(G_UPD_ODD + 1, std::vector<EndArgs<T>>(g->n));
+    std::vector<std::vector<EndArgs<T>>> Eslots((pcg ? G_PA_ODD : G_UPD_ODD) + 1, std::vector<EndArgs<T>>(g->n));
     for (int slot = G_FIRST; slot <= G_UPD_ODD; ++slot) {
         const int parity = (slot == G_ODD || slot == G_UPD_ODD) ? 1 : 0;
+        const int prv = (parity + 1) & 1;
         for (int i = 0; i < g->n; ++i) {
             const int sx = g->start[f][0][i], nt = g->start[f][0][i + 1] - sx;
             const int co = g->case_off[i];
             EndArgs<T> e = end_args<T>();
-            e.pro = PRO_CG_P;
-            e.pio = pv[i];
+            e.pro = pcg ? PRO_PCG_R : PRO_CG_P;
+            if (pcg) e.pr = pv[i];
+            else e.pio = pv[i];
             e.cx = x[i];
             e.cr = r[i];
             e.cq = q[i];
             e.cg3 = g->part_x + 3 * (size_t)sx;
-            e.rr_prev = g->part_rr + 2 * (size_t)sx + (size_t)((parity + 1) & 1) * nt;
+            e.rr_prev = g->part_rr + 2 * (size_t)sx + (size_t)prv * nt;
             e.rr_out = g->part_rr + 2 * (size_t)sx + (size_t)parity * nt;
+            if (pcg) e.rz_k = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * (size_t)sx;
             e.first = slot == G_FIRST;
             e.update_only = slot == G_UPD_EVEN || slot == G_UPD_ODD;
             e.iters = g->iters + co;
-            e.done_prev = g->done + (size_t)((parity + 1) & 1) * g->Btot + co;
+            e.done_prev = g->done + (size_t)prv * g->Btot + co;
             e.case_done = g->done + (size_t)parity * g->Btot + co;
             e.done_rw = g->done + (size_t)parity * g->Btot + co;
             e.thresh = g->thresh + co;
+            if (pcg) {   // z = C^-1 r and the partials r.z
+                e.epi = EPI_PCG_Z;
+                e.uin = r[i];
+                e.out = (*z)[i];
+                e.sign = 1.0;
+                e.part = g->part_rz + (size_t)parity * 3 * g->tiles_max + 3 * (size_t)sx;
+            } else {
+                e.epi = EPI_CG_Q;
+                e.uin = pv[i];
+                e.out = q[i];
+                e.rhs = r[i];
+                e.part = g->part_x + 3 * (size_t)sx;
+            }
+            Eslots[slot][i] = e;
+        }
+    }
+    for (int slot = G_PA_FIRST; pcg && slot <= G_PA_ODD; ++slot) {
+        // stiffness chain: p = z + beta p (beta = r.z / previous r.z), q = K p and the
+        // partials p.q, r.q, q.q
+        const int parity = slot == G_PA_ODD ? 1 : 0;
+        const int prv = (parity + 1) & 1;
+        for (int i = 0; i < g->n; ++i) {
+            const int sx = g->start[f][0][i];
+            EndArgs<T> e = end_args<T>();
+            e.pro = PRO_PCG_P;
+            e.pr = (*z)[i];
+            e.pio = pv[i];
+            e.rz_k = g->part_rz + (size_t)parity * 3 * g->tiles_max + 3 * (size_t)sx;
+            e.rz_km1 = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * (size_t)sx;
+            e.first = slot == G_PA_FIRST;
+            e.case_done = g->done + (size_t)parity * g->Btot + g->case_off[i];
             e.epi = EPI_CG_Q;
             e.uin = pv[i];
             e.out = q[i];
@@ -1320,10 +1370,12 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     std::vector<int> act(g->n);
     for (int i = 0; i < g->n; ++i) act[i] = i;
     GroupView view;
-    MSB_TRY(group_load_members<T>(g, act, A, Eslots, view));
-    auto iteration = [&](int it, bool upd) {
+    MSB_TRY(group_load_members<T>(g, act, A, Eslots, view, Ap));
+    auto iteration = [&](int it, bool upd) -> msb_status {
         const int slot = upd ? ((it & 1) ? G_UPD_ODD : G_UPD_EVEN) : (it == 0 ? G_FIRST : ((it & 1) ? G_ODD : G_EVEN));
-        return group_launch<T>(g, A, slot, st, &view);
+        MSB_TRY(group_launch<T>(g, A, slot, st, &view, pcg));
+        if (!pcg || upd) return MSB_OK;
+        return group_launch<T>(g, A, it == 0 ? G_PA_FIRST : ((it & 1) ? G_PA_ODD : G_PA_EVEN), st, &view);
     };
     MSB_TRY(iteration(0, false));
     int it = 1;
@@ -1345,7 +1397,7 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
         if (now.empty()) break;
         if (now != act) {   // the stream is idle here (synchronised above)
             act = now;
-            MSB_TRY(group_load_members<T>(g, act, A, Eslots, view));
+            MSB_TRY(group_load_members<T>(g, act, A, Eslots, view, Ap));
             if (exec) (void)hipGraphExecDestroy(exec);
             if (graph) (void)hipGraphDestroy(graph);
             exec = nullptr;
@@ -1376,7 +1428,7 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     MSB_HIP(hipStreamSynchronize(st));
     std::vector<int> all(g->n);
     for (int i = 0; i < g->n; ++i) all[i] = i;
-    if (s == MSB_OK) s = group_load_members<T>(g, all, A, Eslots, view);
+    if (s == MSB_OK) s = group_load_members<T>(g, all, A, Eslots, view, Ap);
     return s;
 }
 
@@ -1421,9 +1473,10 @@ void group_free(msb_group_s *g) {
     for (int f = 0; f < 2; ++f) {
         if (g->dstart[f]) (void)hipFree(g->dstart[f]);
         if (g->dA[f]) (void)hipFree(g->dA[f]);
+        if (g->dAp[f]) (void)hipFree(g->dAp[f]);
         if (g->dE[f]) (void)hipFree(g->dE[f]);
     }
-    void *b[] = {g->part_x, g->part_rr, g->thresh, g->scal, g->done, g->iters, g->skip};
+    void *b[] = {g->part_x, g->part_rr, g->part_rz, g->thresh, g->scal, g->done, g->iters, g->skip};
     for (void *x : b)
         if (x) (void)hipFree(x);
     if (g->h_scal) (void)hipHostFree(g->h_scal);
@@ -1469,14 +1522,17 @@ extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_gr
         const size_t pa = f ? sizeof(PassArgs<float>) : sizeof(PassArgs<double>);
         const size_t ea = f ? sizeof(EndArgs<float>) : sizeof(EndArgs<double>);
         if (hipMalloc(&g->dA[f], pa * nplans) != hipSuccess) return fail(MSB_ENOMEM);
+        if (hipMalloc(&g->dAp[f], pa * nplans) != hipSuccess) return fail(MSB_ENOMEM);
         if (hipMalloc(&g->dE[f], ea * kSlots * nplans) != hipSuccess) return fail(MSB_ENOMEM);
         msb_status s = group_config(g, f, nullptr);
         if (s != MSB_OK) return fail(s);
     }
     // tile partials sized for any configuration: at most one x tile per grid row
     for (int i = 0; i < nplans; ++i) tiles_max += (size_t)plans[i]->B * rows_total(plans[i]);
+    g->tiles_max = tiles_max;
     if (hipMalloc(&g->part_x, sizeof(double) * 3 * tiles_max) != hipSuccess ||
         hipMalloc(&g->part_rr, sizeof(double) * 2 * tiles_max) != hipSuccess ||
+        hipMalloc(&g->part_rz, sizeof(double) * 6 * tiles_max) != hipSuccess ||
         hipMalloc(&g->thresh, sizeof(double) * nb) != hipSuccess ||
         hipMalloc(&g->scal, sizeof(double) * 16 * nb) != hipSuccess ||
         hipMalloc(&g->done, sizeof(int) * 2 * nb) != hipSuccess || hipMalloc(&g->iters, sizeof(int) * nb) != hipSuccess ||
@@ -1562,7 +1618,7 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32 || prec == MSB_FP32_REFINED, MSB_EINVAL, "bad precision");
     MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
     MSB_CHECK(opts->reliable_update == 0, MSB_EUNSUPPORTED, "groups refine by restarts only (reliable_update = 0)");
-    MSB_CHECK(opts->precond == 0, MSB_EUNSUPPORTED, "groups solve without the preconditioner (precond = 0)");
+    MSB_CHECK(opts->precond == 0 || opts->precond == 1, MSB_EINVAL, "precond must be 0 or 1");
     for (int i = 0; i < g->n; ++i)
         MSB_CHECK(!g->m[i]->nu64, MSB_EUNSUPPORTED, "member %d: the surface-corrected operator is not symmetric", i);
     int dev = -1;
@@ -1582,6 +1638,32 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     MSB_TRY(group_upload_args<double>(g, A64));
     if (prec != MSB_FP64) MSB_TRY(group_upload_args<float>(g, A32));
     const int gb = opts->graph_block;
+    // circulant preconditioners of the members (built on first use), their chains
+    // without the corrections
+    const bool pre = opts->precond == 1;
+    std::vector<PassArgs<double>> P64;
+    std::vector<PassArgs<float>> P32;
+    std::vector<double *> z64(n);
+    std::vector<float *> z32(n);
+    if (pre) {
+        for (int i = 0; i < n; ++i) {
+            msb_plan_s *p = g->m[i];
+            MSB_TRY(ensure_pre(p));
+            if (prec == MSB_FP64) {
+                P64.push_back(pass_args<double>(p, p->pre, &g->cfg[0]));
+                P64.back().corr = 0;
+            } else {
+                P32.push_back(pass_args<float>(p, p->pre, &g->cfg[1]));
+                P32.back().corr = 0;
+            }
+            z64[i] = w[i]->v64[5];
+            z32[i] = w[i]->v32[5];
+        }
+    }
+    const std::vector<PassArgs<double>> *ap64 = pre ? &P64 : nullptr;
+    const std::vector<PassArgs<float>> *ap32 = pre ? &P32 : nullptr;
+    const std::vector<double *> *zz64 = pre ? &z64 : nullptr;
+    const std::vector<float *> *zz32 = pre ? &z32 : nullptr;
 
     // lifted right-hand sides b'_i (per member, as msb_solve_static) and their norms
     std::vector<double *> bp(n), tmp(n);
@@ -1618,7 +1700,7 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     if (prec == MSB_FP64) {
         std::vector<double *> r(n), pv(n), q(n), x(u, u + n);
         for (int i = 0; i < n; ++i) r[i] = w[i]->v64[2], pv[i] = w[i]->v64[3], q[i] = w[i]->v64[4];
-        MSB_TRY(group_cg<double>(g, A64, cbp, x, r, pv, q, opts->tol, opts->maxit, gb, nullptr));
+        MSB_TRY(group_cg<double>(g, A64, cbp, x, r, pv, q, opts->tol, opts->maxit, gb, nullptr, nullptr, ap64, zz64));
         MSB_TRY(group_fetch(g, 1));
         for (int c = 0; c < Bt; ++c) {
             fl[c] = g->h_int[c] == CAPPED ? RUNNING : g->h_int[c];
@@ -1634,7 +1716,7 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
             b32[i] = w[i]->v32[0];
             x32[i] = w[i]->v32[1], r[i] = w[i]->v32[2], pv[i] = w[i]->v32[3], q[i] = w[i]->v32[4];
         }
-        MSB_TRY(group_cg<float>(g, A32, b32, x32, r, pv, q, opts->tol, opts->maxit, gb, nullptr));
+        MSB_TRY(group_cg<float>(g, A32, b32, x32, r, pv, q, opts->tol, opts->maxit, gb, nullptr, nullptr, ap32, zz32));
         for (int i = 0; i < n; ++i)
             hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for(w[i]->nvec)), dim3(kT), 0, st, u[i], (const float *)x32[i], w[i]->nvec);
         MSB_TRY(group_fetch(g, 1));
@@ -1683,7 +1765,8 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
             MSB_HIP(hipMemcpyAsync(g->skip, hskip.data(), sizeof(int) * Bt, hipMemcpyHostToDevice, st));
             for (int i = 0; i < n; ++i)
                 hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(w[i]->nvec)), dim3(kT), 0, st, r32[i], (const double *)r64[i], w[i]->nvec);
-            MSB_TRY(group_cg<float>(g, A32, r32c, d32, rr32, p32, q32, itol, opts->maxit - used, gb, g->skip, t2d));
+            MSB_TRY(group_cg<float>(g, A32, r32c, d32, rr32, p32, q32, itol, opts->maxit - used, gb, g->skip, t2d, ap32,
+                                    zz32));
             MSB_TRY(group_fetch(g, 0));
             int mx = 0;
             for (int c = 0; c < Bt; ++c) {

@@ -123,9 +123,88 @@ def test_group_rejects_invalid_members():
         msb.PlanGroup([p2, p2])
 
 
-def test_group_adjoint_gradient_matches_oracle():
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_group_pcg_matches_cholesky(prec, dim):
+    """Circulant-preconditioned CG of every member in the same launches (a crack member,
+    per-case influence coefficients, lifts) against each member's dense Cholesky solve."""
+    import paper_2301_11828_amd as msb
+    if dim == 2:
+        ws = [W.small(2, (25, 22), 3, seed=151, fixed="left", crack=True, batch=2),
+              W.small(2, (14, 18), 3, seed=152, fixed="all", batch=3),
+              W.small(2, (31, 12), 3, seed=153, fixed="left", batch=1)]
+    else:
+        ws = [W.small(3, (11, 9, 8), 2, seed=154, fixed="bottom", batch=2),
+              W.small(3, (7, 8, 6), 2, seed=155, fixed="all", batch=1)]
+    rng = np.random.default_rng(156)
+    gs = [np.where(w.fixed[None], 1e-2 * rng.standard_normal((w.batch, dim, w.N)), 0.0) for w in ws]
+    gs[-1] = None
+    plans = [gpu_plan(w) for w in ws]
+    infl = None
+    if dim == 2:
+        infl = np.array([[1.0, 0.0], [0.4, 0.7], [0.8, -0.2]])
+        plans[1].set_infl(infl, per_case=True)
+    grp = msb.PlanGroup(plans)
+    us, infos = grp.solve([to_dev(w.b) for w in ws], [None if g is None else to_dev(g) for g in gs],
+                          precision=prec, tol=1e-13, precond=True)
+    for i, w in enumerate(ws):
+        uu = us[i].cpu().numpy()
+        for c in range(w.batch):
+            p = oracle_problem(w, infl=tuple(infl[c]) if (infl is not None and i == 1) else None)
+            ref = O.solve_dense(p, w.b[c], w.fixed, None if gs[i] is None else gs[i][c], oracle_bonds(w))
+            err = rel_err(uu[c], ref)
+            log("group pcg %dD %s member %d case %d: %d outer %d inner, residual %.2e, rel err %.2e" %
+                (dim, prec, i, c, infos[i][c].outer_iters, infos[i][c].inner_iters, infos[i][c].rel_residual, err))
+            assert infos[i][c].status == 0
+            assert err <= (1e-11 if prec == "fp64" else 1e-10)
+            if gs[i] is not None:
+                assert np.array_equal(uu[c][w.fixed], gs[i][c][w.fixed])
+
+
+def test_group_pcg_equals_members_and_graph_blocks():
+    """At the group's launch configuration each member's own preconditioned solve does the
+    same arithmetic: equal results and iteration counts; hipGraph blocks change neither."""
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (40, 33), 3, seed=161, fixed="left", crack=True, batch=2),
+          W.small(2, (17, 26), 3, seed=162, fixed="all"),
+          W.small(2, (64, 20), 3, seed=163, fixed="left", batch=2)]
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans, precond=True)
+    bs = [to_dev(w.b) for w in ws]
+    a, ia = grp.solve(bs, precision="fp64", tol=1e-12)
+    b, ib = grp.solve(bs, precision="fp64", tol=1e-12, graph_block=8)
+    c0, ic = grp.solve(bs, precision="fp64", tol=1e-12, precond=False)
+    cfg = grp.get_config("fp64")
+    for i, (w, p) in enumerate(zip(ws, plans)):
+        p.set_config("fp64", **cfg)
+        own, io = p.solve(bs[i], precision="fp64", tol=1e-12, precond=True)
+        log("group pcg member %d: iterations %s (own %s, graph %s, plain CG %s)" %
+            (i, [x.inner_iters for x in ia[i]], [x.inner_iters for x in io], [x.inner_iters for x in ib[i]],
+             [x.inner_iters for x in ic[i]]))
+        assert np.array_equal(a[i].cpu().numpy(), own.cpu().numpy())
+        assert [x.inner_iters for x in ia[i]] == [x.inner_iters for x in io]
+        assert np.array_equal(a[i].cpu().numpy(), b[i].cpu().numpy())
+        assert [x.inner_iters for x in ia[i]] == [x.inner_iters for x in ib[i]]
+        assert sum(x.inner_iters for x in ia[i]) < sum(y.inner_iters for y in ic[i])
+        assert rel_err(a[i].cpu().numpy(), c0[i].cpu().numpy()) <= 1e-9
+
+
+def test_group_pcg_rejects_surface_members():
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (14, 12), 3, seed=171, fixed="left"), W.small(2, (10, 16), 3, seed=172, fixed="left")]
+    plans = [gpu_plan(w) for w in ws]
+    plans[1].set_surface(plans[1].surface_volume_factors())
+    grp = msb.PlanGroup(plans)
+    with pytest.raises(msb.MsbError) as e:
+        grp.solve([to_dev(w.b) for w in ws], precision="fp64", precond=True)
+    assert e.value.status == msb.MSB_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_group_adjoint_gradient_matches_oracle(precond):
     """dL/db and dL/da through the group solve and its adjoint (one group solve for all
-    members' adjoints) against the oracle's exact dense gradient of each member."""
+    members' adjoints, plain or preconditioned CG) against the oracle's exact dense
+    gradient of each member."""
     import torch
     import paper_2301_11828_amd as msb
     rng = np.random.default_rng(141)
@@ -138,7 +217,7 @@ def test_group_adjoint_gradient_matches_oracle():
         ws.append(w)
         uts.append(ut)
     plans = [gpu_plan(w) for w in ws]
-    grp = msb.PlanGroup(plans)
+    grp = msb.PlanGroup(plans, precond=precond)
     GSolve = msb.make_group_solve_function()
     bs = [to_dev(w.b).requires_grad_(True) for w in ws]
     infls = [torch.tensor(w.infl, dtype=torch.float64, requires_grad=True) for w in ws]
