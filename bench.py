@@ -64,7 +64,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-tolerance runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "0")))
+    ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "32")),
+                    help="CG iterations per hipGraph launch in the solves (0: plain launches)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the plans' default launch configurations (skip the autotuner)")
     ap.add_argument("--config", default=os.path.join(ROOT, "profiles", "plate512_tuning.json"),
@@ -72,7 +73,7 @@ def main():
                          "as written by the autotuner) applied instead of tuning; default: the tuning the "
                          "committed plate512 profiles were taken with")
     ap.add_argument("--retune", action="store_true",
-                    help="run the autotuner for plate512 instead of applying the recorded tuning")
+                    help="run the autotuner instead of applying the recorded tunings (profiles/<workload>_tuning.json)")
     ap.add_argument("--workload", default="plate512",
                     choices=["plate512", "crack1024", "cube128", "plates64"],
                     help="plate512 is the headline line; the others measure the remaining workloads")
@@ -295,6 +296,15 @@ def _cpu_cores():
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
 
 
+def recorded_tuning(args, name):
+    """The tuning recorded for a workload (padded lengths and launch configurations as the
+    autotuner chose them; the parity tests run the same), or None to tune at run time."""
+    path = os.path.join(ROOT, "profiles", "%s_tuning.json" % name)
+    if args.retune or args.no_tune or not os.path.exists(path):
+        return None
+    return json.load(open(path))
+
+
 def bench_crack1024(args):
     """Dynamic pre-crack plate, 1024^2 (2.1M DOF), delta = 4h, 12,654 broken bonds:
     velocity Verlet in FP32 with the FP64 energy every 10 steps; steps/s."""
@@ -305,7 +315,13 @@ def bench_crack1024(args):
     w = W.crack1024(steps=1000)
     plan = msb.Plan(w.n, w.h, w.M, w.alpha, rho=w.rho)
     plan.set_bonds(msb.crack_to_bonds(w.n, w.h, w.M, w.cracks))
-    tuned = None if args.no_tune else plan.autotune("fp32", effort=1)[0]
+    rec = recorded_tuning(args, "crack1024")
+    if rec:
+        plan.set_lengths(rec["padded"])
+        plan.set_config("fp32", **rec["fp32"])
+        tuned = dict(rec["fp32"], source="crack1024_tuning.json")
+    else:
+        tuned = None if args.no_tune else plan.autotune("fp32", effort=1)[0]
     u = torch.zeros((1, 2, w.N), dtype=torch.float32, device="cuda")
     v = torch.zeros_like(u)
     bf = torch.from_numpy(w.b).float().cuda()
@@ -368,7 +384,13 @@ def bench_cube128(args):
     plan = msb.Plan(w.n, w.h, w.M, w.alpha, batch=16)
     plan.set_constraints(w.fixed)
     tuning = None
-    if not args.no_tune:
+    rec = recorded_tuning(args, "cube128")
+    if rec:
+        plan.set_lengths(rec["padded"])
+        plan.set_config("fp64", **rec["fp64"])
+        plan.set_config("fp32", **rec["fp32"])
+        tuning = {"fp64": rec["fp64"], "fp32": rec["fp32"], "source": "cube128_tuning.json"}
+    elif not args.no_tune:
         t0 = time.perf_counter()
         plan.autotune("fp32_refined", effort=1)
         tuning = {"seconds": round(time.perf_counter() - t0, 2), "fp64": plan.get_config("fp64"),

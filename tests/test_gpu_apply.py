@@ -147,13 +147,26 @@ def test_apply_at_benchmark_sizes(name):
     assert err <= FP64_TOL
 
 
+def _cube128_products(w, dt, prec):
+    """f = A u of the 128^3 x 16 plan in its default launch configuration and in the one the
+    benchmark applies (the recorded tuning)."""
+    plan = gpu_plan(w)
+    out = {"default": gpu_apply(plan, to_dev(w.b, dt)).double().cpu().numpy()}
+    rec = _recorded_tuning("cube128")
+    plan.set_lengths(rec["padded"])
+    plan.set_config(prec, **rec[prec])
+    out["recorded %s" % rec[prec]] = gpu_apply(plan, to_dev(w.b, dt)).double().cpu().numpy()
+    return out
+
+
 def test_apply_cube128_sampled_rows():
     """3D 128^3 batch of 16: compare 3000 sampled nodes per case on 3 cases with the
-    oracle's row-by-row sum (all components)."""
+    oracle's row-by-row sum (all components), in the default and the benchmark's launch
+    configuration."""
+    import torch
     w = W.cube128(batch=16)
     log("apply cube128 B=16")
-    plan = gpu_plan(w)
-    f = gpu_apply(plan, to_dev(w.b)).cpu().numpy()
+    fs = _cube128_products(w, torch.float64, "fp64")
     p = oracle_problem(w)
     rs = np.random.default_rng(3)
     for c in (0, 7, 15):
@@ -161,10 +174,10 @@ def test_apply_cube128_sampled_rows():
         rows = np.concatenate([rows, [0, w.N - 1, 128 * 128 * 64 + 64 * 128 + 64]])
         ref = O.force(p, w.b[c], rows=rows)
         ref[w.fixed[:, rows]] = 0.0
-        got = f[c][:, rows]
-        err = rel_err(got, ref)
-        log("  case %d sampled rel err %.3e" % (c, err))
-        assert err <= FP64_TOL
+        for name, f in fs.items():
+            err = rel_err(f[c][:, rows], ref)
+            log("  case %d %s sampled rel err %.3e" % (c, name, err))
+            assert err <= FP64_TOL
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -194,20 +207,21 @@ def test_wave_owned_signals_match_oracle(prec, spw, spwi, lpw, dim):
 
 
 def test_apply_cube128_fp32_sampled_rows():
-    """FP32 product at the 128^3 x 16 size (wave-owned, several signals per wave)."""
+    """FP32 product at the 128^3 x 16 size (wave-owned, several signals per wave), in the
+    default and the benchmark's launch configuration."""
     import torch
     w = W.cube128(batch=16)
-    plan = gpu_plan(w)
-    f = gpu_apply(plan, to_dev(w.b, torch.float32)).double().cpu().numpy()
+    fs = _cube128_products(w, torch.float32, "fp32")
     p = oracle_problem(w)
     rs = np.random.default_rng(4)
     for c in (0, 9):
         rows = np.sort(rs.choice(w.N, 2000, replace=False))
         ref = O.force(p, w.b[c].astype(np.float32).astype(np.float64), rows=rows)
         ref[w.fixed[:, rows]] = 0.0
-        err = rel_err(f[c][:, rows], ref)
-        log("cube128 fp32 case %d sampled rel err %.2e" % (c, err))
-        assert err <= FP32_TOL
+        for name, f in fs.items():
+            err = rel_err(f[c][:, rows], ref)
+            log("cube128 fp32 case %d %s sampled rel err %.2e" % (c, name, err))
+            assert err <= FP32_TOL
 
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -228,10 +242,11 @@ def test_profile_apply_times_every_pass_and_leaves_the_product(dim):
     assert np.array_equal(f.cpu().numpy(), gpu_apply(plan, u).cpu().numpy())
 
 
-def _recorded_tuning():
+def _recorded_tuning(name="plate512"):
     import json
     import os
-    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles", "plate512_tuning.json")
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                        "%s_tuning.json" % name)
     return json.load(open(path))
 
 

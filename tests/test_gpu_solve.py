@@ -137,6 +137,37 @@ def test_plate512_both_precisions_certified_by_oracle():
     assert d <= 1e-4
 
 
+def test_cube128_batch16_solves_at_the_benchmark_tuning_certified_by_oracle():
+    """The 128^3 x 16 solves the benchmark times, in its recorded launch configuration and
+    hipGraph blocks: FP32-refined CG and preconditioned CG to 1e-8; the FP64 residual of two
+    cases, recomputed with the oracle's bond sum, is below the tolerance."""
+    import json
+    import os
+    import torch
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                                      "cube128_tuning.json")))
+    w = W.cube128(batch=16)
+    plan = gpu_plan(w)
+    plan.set_lengths(rec["padded"])
+    plan.set_config("fp64", **rec["fp64"])
+    plan.set_config("fp32", **rec["fp32"])
+    p = oracle_problem(w)
+    b = to_dev(w.b)
+    for pre in (False, True):
+        u, info = plan.solve(b, precision="fp32_refined", tol=1e-8, maxit=100000, graph_block=32, precond=pre)
+        assert all(i.status == 0 for i in info)
+        uu = u.cpu().numpy()
+        del u
+        torch.cuda.empty_cache()
+        for c in (0, 15):
+            bp = O.lifted_rhs(p, w.b[c], w.fixed).reshape(-1)
+            r = bp + O.apply(p, uu[c], w.fixed).reshape(-1)
+            res = np.linalg.norm(r) / np.linalg.norm(bp)
+            log("cube128 x16 refined precond=%d case %d: %d outer %d inner, lib residual %.2e, oracle residual %.2e"
+                % (pre, c, info[c].outer_iters, info[c].inner_iters, info[c].rel_residual, res))
+            assert res <= 1.05e-8
+
+
 def test_nan_rhs_is_einval():
     import paper_2301_11828_amd as msb
     w = W.plate32()

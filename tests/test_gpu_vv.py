@@ -66,19 +66,29 @@ def test_vv_fp32_error_stated():
 
 
 def test_crack1024_fp32_short_run_vs_oracle():
-    """Benchmark shape (1024^2, delta = 4h, pre-crack, opposing edge loads) for 20 steps:
-    FP32 state against the FP64 oracle trajectory; error stated."""
+    """Benchmark shape (1024^2, delta = 4h, pre-crack, opposing edge loads) for 20 steps, in
+    the default launch configuration and in the benchmark's (the recorded tuning): FP32 state
+    against the FP64 oracle trajectory; error stated."""
+    import json
+    import os
     import torch
     w = W.crack1024(steps=20)
     plan = gpu_plan(w)
     assert plan.n_bonds == 12654
-    u = torch.zeros((1, 2, w.N), dtype=torch.float32, device="cuda")
-    v = torch.zeros_like(u)
-    b = to_dev(w.b, torch.float32)
-    a = plan.vv_init(u, b)
-    plan.vv_run(w.dt, w.steps, u, v, a, b)
     p = oracle_problem(w)
     uo, vo, _, _ = O.vv(p, np.zeros((2, w.N)), np.zeros((2, w.N)), w.b[0], w.dt, w.steps, None, None, oracle_bonds(w))
-    eu, ev = rel_err(u.double().cpu().numpy()[0], uo), rel_err(v.double().cpu().numpy()[0], vo)
-    log("crack1024 FP32 VV %d steps vs FP64 oracle: rel err u %.2e v %.2e" % (w.steps, eu, ev))
-    assert eu <= 1e-4 and ev <= 1e-4
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                                      "crack1024_tuning.json")))
+    for name in ("default", "recorded"):
+        if name == "recorded":
+            plan.set_lengths(rec["padded"])
+            plan.set_config("fp32", **rec["fp32"])
+        u = torch.zeros((1, 2, w.N), dtype=torch.float32, device="cuda")
+        v = torch.zeros_like(u)
+        b = to_dev(w.b, torch.float32)
+        a = plan.vv_init(u, b)
+        plan.vv_run(w.dt, w.steps, u, v, a, b)
+        eu, ev = rel_err(u.double().cpu().numpy()[0], uo), rel_err(v.double().cpu().numpy()[0], vo)
+        log("crack1024 FP32 VV %d steps (%s configuration) vs FP64 oracle: rel err u %.2e v %.2e" %
+            (w.steps, name, eu, ev))
+        assert eu <= 1e-4 and ev <= 1e-4
