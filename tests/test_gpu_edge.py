@@ -97,3 +97,58 @@ def test_adr_degenerate_shapes(case):
     ea = rel_err(u.cpu().numpy()[0], ref)
     log("%s: ADR 3000 updates, rel err vs Cholesky %.2e" % (_ids(case), ea))
     assert ea <= 1e-9
+
+
+# the largest padded lengths a workgroup's LDS holds in FP64 (x pass: twiddles and two
+# buffers of one complex row, 48 L bytes; 2D line pass: twiddles and two buffers of the
+# two components of one line, 80 L bytes; both within 159 KiB): L_x = 3375 and L_y = 2025
+MAX_SHAPES = [((3300, 6), 3375), ((6, 2022), 2025)]
+
+
+@pytest.mark.parametrize("n,L", MAX_SHAPES, ids=["x3375", "y2025"])
+def test_largest_lengths_the_lds_holds(n, L):
+    import torch
+    w = W.small(2, n, 3, seed=611, fixed="left")
+    plan = gpu_plan(w)
+    assert max(plan.padded_lengths) == L
+    p = oracle_problem(w)
+    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 2e-6)):
+        u = w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64)
+        f = gpu_apply(plan, to_dev(w.b, dt)).double().cpu().numpy()[0]
+        err = rel_err(f, O.apply(p, u[0], w.fixed))
+        log("grid %s, padded %s, %s product rel err %.2e" % (n, plan.padded_lengths, prec, err))
+        assert err <= tol
+
+
+@pytest.mark.parametrize("n", [(3400, 6), (6, 2040)], ids=["x3456", "y2048"])
+def test_lengths_beyond_lds_are_rejected(n):
+    """One 5-smooth length further (3456, 2048) no longer fits: plan creation fails with
+    MSB_EUNSUPPORTED instead of a launch failing later."""
+    import paper_2301_11828_amd as msb
+    w = W.small(2, n, 3, seed=612)
+    with pytest.raises(msb.MsbError) as e:
+        gpu_plan(w)
+    assert e.value.status == msb.MSB_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_single_node_grid(dim):
+    """One node and no bonds: the product is zero (up to the rounding of the transform's
+    centre term against D^e, which cancel exactly in exact arithmetic), the crack update
+    finds nothing, and the preconditioner is the oracle's (the shifted periodic symbol)."""
+    w = W.small(dim, (1,) * dim, 1, seed=621, batch=2)
+    plan = gpu_plan(w)
+    p = oracle_problem(w)
+    assert np.array_equal(O.apply(p, w.b[0], w.fixed), np.zeros((dim, 1)))
+    f = gpu_apply(plan, to_dev(w.b)).cpu().numpy()
+    scale = np.abs(w.b).max() * max(1.0, w.alpha * w.h ** dim)   # |u| x the stencil's weight scale
+    log("%dD single node: |f| %.2e (scale %.2e)" % (dim, np.abs(f).max(), scale))
+    assert np.abs(f).max() <= 1e-13 * scale
+    z = plan.apply_precond(to_dev(w.b)).cpu().numpy()
+    for c in range(2):
+        ez = rel_err(z[c], O.precond_apply(p, w.b[c], plan.padded_lengths, w.fixed))
+        log("%dD single node: preconditioner case %d rel err %.2e" % (dim, c, ez))
+        assert ez <= 1e-12
+    if dim == 2:   # the crack update takes single-case plans
+        p1 = gpu_plan(w, batch=1)
+        assert p1.crack_update(to_dev(w.b[:1]), 1e-3) == 0 and len(p1.bonds()) == 0
