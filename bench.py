@@ -122,27 +122,52 @@ def main():
     f64 = torch.empty_like(u64)
     u32, f32 = u64.float(), torch.empty_like(u64, dtype=torch.float32)
 
-    def timed(u, f, steps, warmup):
-        for _ in range(warmup):
-            plan.apply(u, f)
+    def timed(u, f, steps, warmup, graph=0):
+        """`steps` products after `warmup` untimed ones: one launch chain per product, or
+        (graph > 0, dividing steps) replays of a hipGraph that holds `graph` products."""
+        g = None
+        if graph:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(graph):
+                    plan.apply(u, f)
+            torch.cuda.synchronize()
+        per = graph if g is not None else 1
+
+        def run():
+            if g is not None:
+                g.replay()
+            else:
+                plan.apply(u, f)
+        for _ in range(-(-warmup // per)):
+            run()
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         ev0.record()
-        for _ in range(steps):
-            plan.apply(u, f)
+        for _ in range(steps // per):
+            run()
         ev1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return wall, ev0.elapsed_time(ev1) / steps
 
-    print("bench: plate512 FP64 product, %d warmup + %d steps" % (args.warmup, args.steps),
+    # the timed steps replay a hipGraph of G products (the launch gaps between the three
+    # kernels of consecutive products shrink); the same steps as plain launches beside it
+    G = 10 if args.steps % 10 == 0 else 0
+    print("bench: plate512 FP64 product, %d warmup + %d steps (graphs of %d)" % (args.warmup, args.steps, G),
           file=sys.stderr, flush=True)
-    wall, ev_ms = timed(u64, f64, args.steps, args.warmup)
+    wall, ev_ms = timed(u64, f64, args.steps, args.warmup, G)
     ms_step = 1e3 * wall / args.steps
     value = dofs * args.steps / wall / 1e9
+    eager = torch.empty_like(f64)
+    plan.apply(u64, eager)
+    graph_eq = bool(torch.equal(eager, f64))          # the replayed products are the eager one
+    wall_plain, ev_plain = timed(u64, f64, args.steps, args.warmup)
 
-    wall32, ev_ms32 = timed(u32, f32, args.steps, args.warmup)
+    wall32, ev_ms32 = timed(u32, f32, args.steps, args.warmup, G)
 
     # per-kernel durations (HIP events recorded between the kernels on this stream)
     names = ["x_forward", "y_line_product", "x_inverse"]
@@ -179,6 +204,10 @@ def main():
                                "delta=3h, left layer constrained, FP64 FFT-BTTB product",
                    "grid": list(w.n), "M": w.M, "dofs": dofs, "padded": list(L)},
         "roofline": roofline,
+        "timing": {"graph_products": G, "graph_equals_eager": graph_eq,
+                   "plain_launches": {"GDOF_s": round(dofs * args.steps / wall_plain / 1e9, 3),
+                                      "ms_per_step": round(1e3 * wall_plain / args.steps, 5),
+                                      "event_ms_per_matvec": round(ev_plain, 5)}},
         "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kms)},
         "kernels_bytes": dict(zip(names, pb)),
         "chain": chain,

@@ -289,3 +289,38 @@ def test_plate512_batch16_at_the_benchmark_tuning():
         err = rel_err(f[c][:, rows], ref)
         log("plate512 x16 at the recorded tuning, case %d sampled rel err %.2e" % (c, err))
         assert err <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_products_captured_in_a_hipgraph_replay_exactly(prec, dim):
+    """Products captured in a hipGraph on a side stream (as the benchmark times them): every
+    replay, with eager products and synchronisations between replays, equals the eager
+    product bit for bit."""
+    import torch
+    if dim == 2:
+        w = W.small(2, (45, 38), 3, seed=97, fixed="left", crack=True, batch=2)
+    else:
+        w = W.small(3, (12, 9, 8), 2, seed=98, fixed="bottom", batch=2)
+    plan = gpu_plan(w)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u = to_dev(w.b, dt)
+    eager = gpu_apply(plan, u).clone()
+    f = torch.full_like(u, float("nan"))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(3):
+            plan.apply(u, f)
+    torch.cuda.synchronize()
+    for r in range(4):
+        f.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(f, eager), "replay %d differs from the eager product" % r
+        other = gpu_apply(plan, u.flip(-1).contiguous())   # eager work between replays
+        torch.cuda.synchronize()
+        assert not torch.equal(other, eager)
+    ref = _oracle_apply(w, w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64))
+    assert rel_err(f.double().cpu().numpy(), ref) <= (FP64_TOL if prec == "fp64" else FP32_TOL)
