@@ -462,6 +462,21 @@ def bench_cube128(args):
     cg["speedup_fp64_pcg_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp64_pcg"]["seconds"], 3)
     cg["speedup_fp32_refined_pcg_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp32_refined_pcg"]["seconds"], 3)
     out["cg_to_1e-8"] = cg
+    if not args.no_cpu:
+        # the oracle's bond-by-bond FP64 product on one case (3 runs), and the CG time it
+        # implies: per-case product time x 16 cases x the GPU's FP64 iteration count
+        # (extrapolated: the oracle's own CG at this size would take about that long)
+        import oracle as O
+        p = O.Problem(w.n, w.h, w.M, w.alpha)
+        u0 = w.b[0]
+        O.apply(p, u0, w.fixed)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            O.apply(p, u0, w.fixed)
+        per = (time.perf_counter() - t0) / 3
+        out["cpu_baseline"] = {"value": round(w.dofs / per / 1e9, 5), "unit": "GDOF/s", "cores": _cpu_cores(),
+                               "kind": "oracle", "sample": "3 FP64 bond-by-bond products of one 128^3 case",
+                               "cg_fp64_seconds_extrapolated": round(per * 16 * cg["fp64"]["iterations_max"], 1)}
     return out
 
 

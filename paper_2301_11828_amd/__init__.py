@@ -532,16 +532,17 @@ class PlanGroup:
 def make_solve_function():
     """torch.autograd.Function for u = K(a)^{-1} b with the hand-written adjoint.
 
-    forward(plan, b, infl) -> u; backward: w = K^{-1} grad_u (K symmetric, same solve),
+    forward(plan, b, infl[, precision, tol, precond]) -> u; backward: w = K^{-1} grad_u (K
+    symmetric, same solve, same preconditioning),
     grad_b = w, grad_infl[b, k] = w . (A_k u)_F."""
     torch = _torch()
 
     class MSBFMSolve(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, plan, b, infl, precision="fp32_refined", tol=1e-10):
+        def forward(ctx, plan, b, infl, precision="fp32_refined", tol=1e-10, precond=False):
             plan.set_infl(infl.detach().cpu().numpy(), per_case=(infl.dim() == 2))
-            u, _ = plan.solve(b.contiguous(), precision=precision, tol=tol)
-            ctx.plan, ctx.precision, ctx.tol = plan, precision, tol
+            u, _ = plan.solve(b.contiguous(), precision=precision, tol=tol, precond=precond)
+            ctx.plan, ctx.precision, ctx.tol, ctx.precond = plan, precision, tol, precond
             ctx.per_case, ctx.infl_device = infl.dim() == 2, infl.device
             ctx.save_for_backward(u)
             return u
@@ -549,11 +550,11 @@ def make_solve_function():
         @staticmethod
         def backward(ctx, grad_u):
             (u,) = ctx.saved_tensors
-            w, _ = ctx.plan.solve(grad_u.contiguous(), precision=ctx.precision, tol=ctx.tol)
+            w, _ = ctx.plan.solve(grad_u.contiguous(), precision=ctx.precision, tol=ctx.tol, precond=ctx.precond)
             ga = torch.from_numpy(ctx.plan.grad_infl(u, w))
             if not ctx.per_case:
                 ga = ga.sum(0)          # one coefficient set shared by every case
-            return None, w, ga.to(ctx.infl_device), None, None
+            return None, w, ga.to(ctx.infl_device), None, None, None
 
     return MSBFMSolve
 

@@ -24,8 +24,9 @@ def test_apply_dinfl_matches_oracle():
         assert err <= 1e-12
 
 
+@pytest.mark.parametrize("precond", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
-def test_adjoint_gradient_matches_oracle(prec):
+def test_adjoint_gradient_matches_oracle(prec, precond):
     rng = np.random.default_rng(42)
     a = tuple(rng.uniform(0.2, 1.0, size=5))
     w = W.small(2, (20, 17), 3, seed=43, fixed="all", crack=True, infl=a)
@@ -37,12 +38,13 @@ def test_adjoint_gradient_matches_oracle(prec):
     Solve = msb.make_solve_function()
     b = to_dev(w.b).requires_grad_(True)
     infl = torch.tensor(a, dtype=torch.float64, requires_grad=True)
-    u = Solve.apply(plan, b, infl, prec, 1e-13)
+    u = Solve.apply(plan, b, infl, prec, 1e-13, precond)
     loss = ((u - to_dev(ut[None])) ** 2).sum()
     loss.backward()
     eb = rel_err(b.grad.cpu().numpy()[0], gb_ref)
     ea = rel_err(infl.grad.numpy(), ga_ref)
-    log("adjoint %s: loss %.6e (oracle %.6e), rel err dL/db %.2e, dL/da %.2e" % (prec, loss.item(), L, eb, ea))
+    log("adjoint %s precond=%d: loss %.6e (oracle %.6e), rel err dL/db %.2e, dL/da %.2e" %
+        (prec, precond, loss.item(), L, eb, ea))
     assert abs(loss.item() - L) <= 1e-8 * L
     assert eb <= 1e-9 and ea <= 1e-9
 
