@@ -79,7 +79,7 @@ def main():
                     help="plate512 is the headline line; the others measure the remaining workloads")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
     if args.workload != "plate512":

@@ -49,7 +49,7 @@ typedef enum {
     MSB_EDEVICE = -3,       /* a HIP runtime call failed */
     MSB_ENOCONV = -4,       /* iteration limit reached or refinement stagnated */
     MSB_ENOTSPD = -5,       /* CG breakdown: p.Kp <= 0 or non-finite (singular/unconstrained problem) */
-    MSB_EUNSUPPORTED = -6   /* valid request this build does not support */
+    MSB_EUNSUPPORTED = -6   /* valid request the library does not support */
 } msb_status;
 
 typedef enum {

@@ -75,8 +75,8 @@ def load_library(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError("libmsbfm.so not built (expected at %s); run __graft_entry__.build() "
-                          "or python -m paper_2301_11828_amd.build" % path)
+        raise ImportError("libmsbfm.so not built (expected at %s); run python -m paper_2301_11828_amd.build"
+                          % path)
     # One HIP runtime per process: let PyTorch load (and initialise) its runtime first so
     # that the library's libamdhip64.so.7 dependency binds to that same copy.
     try:
