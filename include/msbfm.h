@@ -283,6 +283,14 @@ msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds
  *   max_radix       largest Stockham radix of the schedules: 4 (radices 2, 3,
  *                   4; with 5 where the length needs it), 8 (adds 8; 5 always) or
  *                   16 (adds 6, 9, 10, 12, 15, 16)
+ *   lds_inplace     bit 0: x passes, bit 1: line passes; a set bit runs every
+ *                   Stockham stage in place (each thread reads its butterflies
+ *                   into registers, a barrier, then it writes them back into the
+ *                   same buffer): half the signal LDS per workgroup, one more
+ *                   barrier per stage.  Valid with max_radix 16 when a schedule
+ *                   uses a composite radix (6, 9, 10, 12, 15 or 16), and while no
+ *                   thread owns more than max(1, 16 / R) butterflies of a
+ *                   radix-R stage.
  *
  * msb_plan_set_config validates (LDS per workgroup <= 160 KiB, threads <=
  * 512) and returns MSB_EINVAL without changing the plan otherwise.
@@ -291,6 +299,7 @@ typedef struct {
     int rows_per_wg, team_x, slots_fwd, slots_inv, threads_x;
     int lines_per_wg, team_line, lines_per_wave, threads_line;
     int max_radix;
+    int lds_inplace;
 } msb_launch_config;
 
 msb_status msb_plan_get_config(msb_plan plan, msb_precision prec, msb_launch_config *cfg);

@@ -253,6 +253,97 @@ __device__ __forceinline__ void stockham_pass(const T2 *__restrict__ in, T2 *__r
     }
 }
 
+// Ordering point between Stockham stages of signals owned by a single wavefront:
+// LDS traffic of one wave is processed in order, so a wave-scope fence plus a
+// scheduling barrier is all that is needed (no block-wide s_barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Butterflies of one in-place stage a thread may own: they stay in registers between
+// the stage's reads and writes, at most as many values as one radix-RMAX butterfly.
+__host__ __device__ constexpr int inplace_batch(int R, int RMAX) { return RMAX / R > 1 ? RMAX / R : 1; }
+
+// The same stage in place: every thread reads and transforms all its butterflies (at
+// most inplace_batch(R, RMAX) of them; the host checks S nb <= that many per thread),
+// the team synchronises (BLOCK: workgroup barrier, else wave scope), then every
+// thread writes its outputs into the buffer it read.
+template <typename T, typename T2, int R, int DIR, int RMAX, bool BLOCK>
+__device__ __forceinline__ void stockham_pass_ip(T2 *buf, int S, int L, const FftPass &ps,
+                                                 const T2 *__restrict__ tw, int tid, int nt) {
+    constexpr int KB = inplace_batch(R, RMAX);
+    const int nb = ps.nb;
+    const int Ns = ps.Ns;
+    const int total = S * nb;
+    T2 v[KB][R];
+    int ob[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        const int t = tid + i * nt;
+        ob[i] = -1;
+        if (t < total) {
+            const int s = (int)fdiv((uint32_t)t, ps.m_nb);
+            const int j = t - s * nb;
+            const T2 *x = buf + s * L;
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[i][m] = x[j + m * nb];
+            const int jq = (int)fdiv((uint32_t)j, ps.m_Ns);
+            const int k = j - jq * Ns;
+            if (Ns > 1) {
+                const int step = k * ps.twstep;
+#pragma unroll
+                for (int m = 1; m < R; ++m) {
+                    T2 w = tw[m * step];
+                    if (DIR > 0) w.y = -w.y;
+                    v[i][m] = c_mul(v[i][m], w);
+                }
+            }
+            Dft<T, T2, R, DIR>::run(v[i], tw, L / R);
+            ob[i] = s * L + jq * Ns * R + k;
+        }
+    }
+    if (BLOCK) __syncthreads();
+    else wave_sync();
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        if (ob[i] < 0) continue;
+        T2 *y = buf + ob[i];
+#pragma unroll
+        for (int m = 0; m < R; ++m) y[m * Ns] = v[i][m];
+    }
+}
+
+template <typename T, typename T2, int DIR, int RMAX, bool BLOCK>
+__device__ void fft_inplace(T2 *a, int S, const FftSched &sc, const T2 *__restrict__ tw, int tid, int nt) {
+    const int L = sc.L;
+    for (int p = 0; p < sc.np; ++p) {
+        const FftPass &ps = sc.ps[p];
+        switch (ps.R) {
+            case 2: stockham_pass_ip<T, T2, 2, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+            case 3: stockham_pass_ip<T, T2, 3, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+            case 4: stockham_pass_ip<T, T2, 4, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+            case 5: stockham_pass_ip<T, T2, 5, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+            case 8: stockham_pass_ip<T, T2, 8, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+            default:
+                if constexpr (RMAX >= 16) {
+                    switch (ps.R) {
+                        case 6: stockham_pass_ip<T, T2, 6, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+                        case 9: stockham_pass_ip<T, T2, 9, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+                        case 10: stockham_pass_ip<T, T2, 10, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+                        case 12: stockham_pass_ip<T, T2, 12, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+                        case 15: stockham_pass_ip<T, T2, 15, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+                        default: stockham_pass_ip<T, T2, 16, DIR, RMAX, BLOCK>(a, S, L, ps, tw, tid, nt); break;
+                    }
+                }
+                break;
+        }
+        if (BLOCK) __syncthreads();
+        else wave_sync();
+    }
+}
+
 // Full transform of S signals in LDS buffer a (scratch b); tw: the length-L twiddle
 // table staged in LDS.  Returns the buffer that holds the result.  Every thread of
 // the block must call it (it synchronises).
@@ -287,15 +378,6 @@ __device__ T2 *fft_lds(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__rest
         b = t;
     }
     return a;
-}
-
-// Ordering point between Stockham stages of signals owned by a single wavefront:
-// LDS traffic of one wave is processed in order, so a wave-scope fence plus a
-// scheduling barrier is all that is needed (no block-wide s_barrier).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Transform of S signals owned by one wavefront (lane = 0..63) in its private LDS

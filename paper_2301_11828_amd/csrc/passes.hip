@@ -65,7 +65,16 @@ template <bool BLOCK> struct Team {
 };
 
 template <typename T, typename T2, int DIR, bool BLOCK, int RMAX>
-__device__ __forceinline__ T2 *team_fft(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *tw, const Team<BLOCK> &tm) {
+__device__ __forceinline__ T2 *team_fft(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *tw, const Team<BLOCK> &tm,
+                                       bool in_place) {
+    // in-place stages (b is not touched and need not exist); only in the kernels with the
+    // composite radices, whose register budget already holds 16 values per thread
+    if constexpr (RMAX >= 16) {
+        if (in_place) {
+            fft_inplace<T, T2, DIR, RMAX, BLOCK>(a, S, sc, tw, tm.tid, tm.nt);
+            return a;
+        }
+    }
     if (BLOCK) return fft_lds<T, T2, DIR, RMAX>(a, b, S, sc, tw, tm.tid, tm.nt);
     return fft_wave<T, T2, DIR, RMAX>(a, b, S, sc, tw, tm.tid);
 }
@@ -296,9 +305,9 @@ __device__ __forceinline__ void xfwd_body(const PassArgs<T> &a, const EndArgs<T>
         if (conv) return;
     }
     tm.sync();
-    if (ns > 0) team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
+    if (ns > 0) team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm, a.ip_x);
     if (!BLOCK) __syncthreads();
-    const T2 *res = (a.sx.np & 1) ? bufB : bufA;
+    const T2 *res = (!a.ip_x && (a.sx.np & 1)) ? bufB : bufA;
 
     // unpack the two real transforms of each slot; x-spectrum k < H into
     // [b][c][z][kx][y].  The whole block stores: thread t owns real row
@@ -395,7 +404,7 @@ __device__ __forceinline__ void line_body(const PassArgs<T> &a, const EndArgs<T>
         }
     }
     tm.sync();
-    T2 *res = team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * L, bufB + (size_t)s0 * L, ns, sl, tws, tm);
+    T2 *res = team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * L, bufB + (size_t)s0 * L, ns, sl, tws, tm, a.ip_l);
     T2 *oth = (res == bufA + (size_t)s0 * L) ? bufB + (size_t)s0 * L : bufA + (size_t)s0 * L;
 
     if (pf) {
@@ -463,7 +472,7 @@ __device__ __forceinline__ void line_body(const PassArgs<T> &a, const EndArgs<T>
         }
     }
     tm.sync();
-    T2 *out = team_fft<T, T2, 1, BLOCK, RMAX>(res, oth, ns, sl, tws, tm);
+    T2 *out = team_fft<T, T2, 1, BLOCK, RMAX>(res, oth, ns, sl, tws, tm, a.ip_l);
     for (int s = 0; s < ns; ++s) {
         const int sg = s0 + s;
         const int li = sg / d, c = sg - li * d;
@@ -510,9 +519,9 @@ __device__ __forceinline__ void yfwd_body(const PassArgs<T> &a, const EndArgs<T>
         }
     }
     tm.sync();
-    if (ns > 0) team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
+    if (ns > 0) team_fft<T, T2, -1, BLOCK, RMAX>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm, a.ip_l);
     if (!BLOCK) __syncthreads();
-    const T2 *res = (a.sy.np & 1) ? bufB : bufA;
+    const T2 *res = (!a.ip_l && (a.sy.np & 1)) ? bufB : bufA;
     // the whole block stores: thread t owns z = z0 + t % nz and ky = t / nz + j G
     // (G = blockDim / nz, nz <= 16 < blockDim), consecutive threads on consecutive z
     // (T2's contiguous axis)
@@ -565,7 +574,7 @@ __device__ __forceinline__ void yinv_body(const PassArgs<T> &a, const EndArgs<T>
     }
     __syncthreads();
     if (ns <= 0) return;
-    T2 *res = team_fft<T, T2, 1, BLOCK, RMAX>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm);
+    T2 *res = team_fft<T, T2, 1, BLOCK, RMAX>(bufA + (size_t)s0 * Ly, bufB + (size_t)s0 * Ly, ns, a.sy, twl, tm, a.ip_l);
     for (int s = 0; s < ns; ++s) {
         const int sg = s0 + s;
         const int zl = sg / d, c = sg - zl * d;
@@ -651,7 +660,7 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
         const int nsg = min(2 * ns, nsig - 2 * s0);   // real rows of this team
         const size_t cbase = (size_t)b * d * a.N;
         const T *uin = e.uin;
-        T2 *R = team_fft<T, T2, 1, BLOCK, RMAX>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm);
+        T2 *R = team_fft<T, T2, 1, BLOCK, RMAX>(bufA + (size_t)s0 * Lx, bufB + (size_t)s0 * Lx, ns, a.sx, twl, tm, a.ip_x);
         T *Rr = reinterpret_cast<T *>(R);   // real row sl of this team at Rr[2 ((sl>>1) Lx + n) + (sl&1)]
 
         const int M = a.M, M1 = a.M + 1;
@@ -921,11 +930,12 @@ MSB_PLAN_KERNEL(k_xinv, xinv_body, tile, ntiles)
 int x_tiles_per_case(const msb_plan_s *p, int F) { return (int)((rows_total(p) + F - 1) / F); }
 
 // LDS bytes: the shared twiddle table plus two buffers (ping-pong) of slots.
-static size_t lds_x_bytes(int d, int F, int64_t Lx, size_t cbytes) {
-    return ((size_t)2 * ((d * F + 1) / 2) + 1) * Lx * cbytes;
+// twiddles plus two signal buffers (one with in-place stages)
+static size_t lds_x_bytes(int d, int F, int64_t Lx, size_t cbytes, bool in_place = false) {
+    return ((size_t)(in_place ? 1 : 2) * ((d * F + 1) / 2) + 1) * Lx * cbytes;
 }
-static size_t lds_line_bytes(int d, int Fl, int64_t L, size_t cbytes) {
-    return ((size_t)2 * Fl * d + 1) * L * cbytes;
+static size_t lds_line_bytes(int d, int Fl, int64_t L, size_t cbytes, bool in_place = false) {
+    return ((size_t)(in_place ? 1 : 2) * Fl * d + 1) * L * cbytes;
 }
 static int waves_x(int d, int F) { return (d * F + 1) / 2; }
 
@@ -972,7 +982,18 @@ msb_launch_config default_config(const msb_plan_s *p, bool fp32) {
     // 2D block teams: about one thread per 4 points of the workgroup's signals
     c.threads_line = (d == 2 && (int64_t)Fl * d * Ll >= 2048) ? 512 : 256;
     c.max_radix = fp32 ? 16 : 8;
+    c.lds_inplace = 0;
     return c;
+}
+
+// In-place stages keep all of a thread's butterflies of a stage in registers: for S
+// signals on nt threads, at most inplace_batch(R, RMAX) per thread in every stage
+// (RMAX of the kernel the plan's schedules select: 16 with composite radices, else 8;
+// a group may run the plan in a 16 kernel, whose bound is not smaller).
+static bool inplace_fits(const FftSched &s, int64_t S, int64_t nt, int rmax) {
+    for (int i = 0; i < s.np; ++i)
+        if ((S * s.ps[i].nb + nt - 1) / nt > inplace_batch(s.ps[i].R, rmax)) return false;
+    return true;
 }
 
 // Exactness of the Stockham index split: fdiv(t, nb) with t < S * nb is exact while
@@ -996,9 +1017,26 @@ msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config 
         MSB_CHECK(t >= 64 && t <= kMaxBlock && t % 64 == 0, MSB_EINVAL, "thread count %d: need a multiple of 64 in [64, %d]",
                   t, kMaxBlock);
     MSB_CHECK(c.max_radix == 4 || c.max_radix == 8 || c.max_radix == 16, MSB_EINVAL, "max_radix must be 4, 8 or 16");
-    const size_t lx = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb);
+    MSB_CHECK(c.lds_inplace >= 0 && c.lds_inplace <= 3, MSB_EINVAL, "lds_inplace must be in [0, 3]");
+    const bool ipx = (c.lds_inplace & 1) != 0, ipl = (c.lds_inplace & 2) != 0;
+    if (ipx || ipl) {
+        const FftSched sx = make_sched(p->ax[0], fp32, c.max_radix), sy = make_sched(p->ax[1], fp32, c.max_radix),
+                       sz = make_sched(p->ax[2], fp32, c.max_radix);
+        const int rk = plan_needs_composite(p, fp32, c.max_radix) ? 16 : 8;
+        MSB_CHECK(rk == 16, MSB_EINVAL, "lds_inplace needs a schedule with a composite radix (max_radix 16 and "
+                  "a length that uses one)");
+        const int64_t Sx = c.team_x ? std::max(c.slots_fwd, c.slots_inv) : waves_x(d, c.rows_per_wg);
+        const int64_t ntx = c.team_x ? 64 : c.threads_x;
+        const int64_t Sl = (int64_t)d * (c.team_line ? c.lines_per_wave : c.lines_per_wg);
+        const int64_t ntl = c.team_line ? 64 : c.threads_line;
+        MSB_CHECK(!ipx || inplace_fits(sx, Sx, ntx, rk), MSB_EINVAL,
+                  "lds_inplace: an x-pass thread would own more butterflies of a stage than it holds in registers");
+        MSB_CHECK(!ipl || (d == 2 ? inplace_fits(sy, Sl, ntl, rk) : inplace_fits(sz, Sl, ntl, rk) && inplace_fits(sy, Sl, ntl, rk)),
+                  MSB_EINVAL, "lds_inplace: a line-pass thread would own more butterflies of a stage than it holds in registers");
+    }
+    const size_t lx = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb, ipx);
     MSB_CHECK(lx <= kLdsMax, MSB_EINVAL, "x passes need %zu bytes of LDS per workgroup (max %zu)", lx, kLdsMax);
-    const size_t ll = lds_line_bytes(d, c.lines_per_wg, line_len(p), cb);
+    const size_t ll = lds_line_bytes(d, c.lines_per_wg, line_len(p), cb, ipl);
     MSB_CHECK(ll <= kLdsMax, MSB_EINVAL, "line passes need %zu bytes of LDS per workgroup (max %zu)", ll, kLdsMax);
     if (c.team_x) {
         const int w = waves_x(d, c.rows_per_wg);
@@ -1042,6 +1080,8 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.spw = c.slots_fwd;
     a.spw_i = c.slots_inv;
     a.lpw = c.lines_per_wave;
+    a.ip_x = c.lds_inplace & 1;
+    a.ip_l = (c.lds_inplace >> 1) & 1;
     a.bthreads = c.threads_x;
     a.bthreads_line = c.threads_line;
     if (cfg) {   // the given configuration's radix cap, not the plan's
@@ -1102,9 +1142,9 @@ template <typename T> static ChainGeom chain_geom(const PassArgs<T> &a) {
     g.bx = a.wave_x ? 64 * ((waves_x(a.d, a.F) + a.spw - 1) / a.spw) : a.bthreads;
     g.bxi = a.wave_x ? 64 * ((waves_x(a.d, a.F) + a.spw_i - 1) / a.spw_i) : a.bthreads;
     g.bl = a.wave_l ? 64 * ((a.Fl + a.lpw - 1) / a.lpw) : a.bthreads_line;
-    g.lds_x = lds_x_bytes(a.d, a.F, a.sx.L, cb);
-    g.lds_l = lds_line_bytes(a.d, a.Fl, a.d == 2 ? a.sy.L : a.sz.L, cb);
-    g.lds_y = a.d == 3 ? lds_line_bytes(a.d, a.Fl, a.sy.L, cb) : 0;
+    g.lds_x = lds_x_bytes(a.d, a.F, a.sx.L, cb, a.ip_x);
+    g.lds_l = lds_line_bytes(a.d, a.Fl, a.d == 2 ? a.sy.L : a.sz.L, cb, a.ip_l);
+    g.lds_y = a.d == 3 ? lds_line_bytes(a.d, a.Fl, a.sy.L, cb, a.ip_l) : 0;
     return g;
 }
 
@@ -1213,9 +1253,9 @@ void pass_tiles(const msb_plan_s *p, const msb_launch_config &c, bool fp32, int 
     tiles[0] = (int)((rows_total(p) + c.rows_per_wg - 1) / c.rows_per_wg);
     tiles[1] = ((d == 2 ? H : H * Ly) + c.lines_per_wg - 1) / c.lines_per_wg;
     tiles[2] = d == 3 ? H * ((Nz + c.lines_per_wg - 1) / c.lines_per_wg) : 0;
-    lds[0] = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb);
-    lds[1] = lds_line_bytes(d, c.lines_per_wg, d == 2 ? Ly : Lz, cb);
-    lds[2] = d == 3 ? lds_line_bytes(d, c.lines_per_wg, Ly, cb) : 0;
+    lds[0] = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb, c.lds_inplace & 1);
+    lds[1] = lds_line_bytes(d, c.lines_per_wg, d == 2 ? Ly : Lz, cb, c.lds_inplace & 2);
+    lds[2] = d == 3 ? lds_line_bytes(d, c.lines_per_wg, Ly, cb, c.lds_inplace & 2) : 0;
 }
 
 bool plan_needs_composite(const msb_plan_s *p, bool fp32, int max_radix) {

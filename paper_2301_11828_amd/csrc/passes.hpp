@@ -41,6 +41,7 @@ template <typename T> struct PassArgs {
     int Fl;              // lines per workgroup (line passes)
     int wave_x, wave_l;  // 1: wave-owned signals, 0: whole-block teams (x passes / line passes)
     int spw, spw_i, lpw; // wave mode: complex slots per wave (x-forward, x-inverse), lines per wave (line passes)
+    int ip_x, ip_l;      // 1: in-place Stockham stages (one LDS signal buffer) in the x / line passes
     int bthreads;        // block mode: threads per block (x and y passes)
     int bthreads_line;   // block mode: threads per block of the 2D line pass
     int N;               // nodes per case

@@ -1166,7 +1166,7 @@ msb_status group_config(msb_group_s *g, int f, const msb_launch_config *want) {
     bool ok = true;
     for (int i = 0; i < g->n && ok; ++i) ok = check_config(g->m[i], f32, c) == MSB_OK;
     if (!ok && !want) {
-        c = msb_launch_config{1, 0, 1, 1, 256, 1, 0, 1, 256, 8};
+        c = msb_launch_config{1, 0, 1, 1, 256, 1, 0, 1, 256, 8, 0};
         ok = true;
         for (int i = 0; i < g->n && ok; ++i) ok = check_config(g->m[i], f32, c) == MSB_OK;
     }

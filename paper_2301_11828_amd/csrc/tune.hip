@@ -139,17 +139,20 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
     const std::vector<int> lpws = effort ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{1, 2};
 
     // x passes: (team, rows per workgroup) groups; wave teams pick the forward and
-    // inverse slot counts separately from their own kernel times
-    {
+    // inverse slot counts separately from their own kernel times.  ip: the x-pass bit of
+    // lds_inplace the candidates take.
+    auto scan_x = [&](int ip) -> msb_status {
         msb_launch_config best = cur;
         MSB_TRY(bn.run(cur, err) ? MSB_OK : err);
         double bt = bn.x_time();
+        const int ipm = (cur.lds_inplace & ~1) | ip;
         for (int F : Fs) {
             for (int th : ths) {
                 msb_launch_config c = cur;
                 c.team_x = 0;
                 c.rows_per_wg = F;
                 c.threads_x = th;
+                c.lds_inplace = ipm;
                 if (bn.run(c, err) && bn.x_time() < bt) {
                     bt = bn.x_time();
                     best = c;
@@ -158,14 +161,15 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
             }
             double tf = kInf, ti = kInf;
             int sf = 1, si = 1;
-            for (int s : sls) {
+            for (int sl : sls) {
                 msb_launch_config c = cur;
                 c.team_x = 1;
                 c.rows_per_wg = F;
-                c.slots_fwd = c.slots_inv = s;
+                c.slots_fwd = c.slots_inv = sl;
+                c.lds_inplace = ipm;
                 if (bn.run(c, err)) {
-                    if (bn.ms[0] < tf) tf = bn.ms[0], sf = s;
-                    if (bn.ms[bn.np - 1] < ti) ti = bn.ms[bn.np - 1], si = s;
+                    if (bn.ms[0] < tf) tf = bn.ms[0], sf = sl;
+                    if (bn.ms[bn.np - 1] < ti) ti = bn.ms[bn.np - 1], si = sl;
                 }
                 MSB_TRY(err);
             }
@@ -175,6 +179,7 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
                 c.rows_per_wg = F;
                 c.slots_fwd = sf;
                 c.slots_inv = si;
+                c.lds_inplace = ipm;
                 if (check_config(p, f32, c) == MSB_OK) {
                     bt = tf + ti;
                     best = c;
@@ -182,18 +187,21 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
             }
         }
         cur = best;
-    }
-    // line passes, with the x passes fixed
-    {
+        return MSB_OK;
+    };
+    // line passes, with the x passes fixed; ip: the line-pass bit of lds_inplace
+    auto scan_lines = [&](int ip) -> msb_status {
         msb_launch_config best = cur;
         MSB_TRY(bn.run(cur, err) ? MSB_OK : err);
         double bt = bn.line_time();
+        const int ipm = (cur.lds_inplace & ~2) | (ip << 1);
         for (int Fl : Fs) {
             for (int th : ths) {
                 msb_launch_config c = cur;
                 c.team_line = 0;
                 c.lines_per_wg = Fl;
                 c.threads_line = th;
+                c.lds_inplace = ipm;
                 if (bn.run(c, err) && bn.line_time() < bt) {
                     bt = bn.line_time();
                     best = c;
@@ -205,6 +213,7 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
                 c.team_line = 1;
                 c.lines_per_wg = Fl;
                 c.lines_per_wave = lp;
+                c.lds_inplace = ipm;
                 if (bn.run(c, err) && bn.line_time() < bt) {
                     bt = bn.line_time();
                     best = c;
@@ -213,7 +222,10 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
             }
         }
         cur = best;
-    }
+        return MSB_OK;
+    };
+    MSB_TRY(scan_x(0));
+    MSB_TRY(scan_lines(0));
     // radix cap of the schedules (changes every kernel)
     {
         msb_launch_config best = cur;
@@ -230,6 +242,12 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
             MSB_TRY(err);
         }
         cur = best;
+    }
+    // in-place stages (half the LDS per workgroup: more resident workgroups, or more rows
+    // or lines per workgroup), kept where they are faster; invalid candidates are skipped
+    if (effort) {
+        MSB_TRY(scan_x(1));
+        MSB_TRY(scan_lines(1));
     }
     bn.nrep = std::max(bn.nrep, 5);
     MSB_CHECK(bn.run(cur, err), err != MSB_OK ? err : MSB_EINVAL, "tuned configuration rejected");

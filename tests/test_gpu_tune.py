@@ -38,7 +38,8 @@ def _random_configs(rng, count):
                         slots_fwd=int(rng.integers(1, 9)), slots_inv=int(rng.integers(1, 9)),
                         threads_x=64 * int(rng.integers(1, 9)), lines_per_wg=int(rng.choice([1, 2, 3, 5, 8, 16])),
                         team_line=int(rng.integers(2)), lines_per_wave=int(rng.integers(1, 9)),
-                        threads_line=64 * int(rng.integers(1, 9)), max_radix=int(rng.choice([4, 8, 16]))))
+                        threads_line=64 * int(rng.integers(1, 9)), max_radix=int(rng.choice([4, 8, 16])),
+                        lds_inplace=int(rng.choice([0, 0, 1, 2, 3]))))
     return out
 
 
@@ -74,7 +75,8 @@ def test_invalid_configs_rejected_and_plan_unchanged():
     plan = gpu_plan(w)
     before = plan.get_config("fp64")
     for bad in (dict(threads_x=100), dict(threads_line=2048), dict(threads_x=1024), dict(max_radix=7), dict(rows_per_wg=0),
-                dict(rows_per_wg=17), dict(team_x=2), dict(slots_fwd=9), dict(lines_per_wave=0)):
+                dict(rows_per_wg=17), dict(team_x=2), dict(slots_fwd=9), dict(lines_per_wave=0), dict(lds_inplace=4),
+                dict(lds_inplace=3, max_radix=4)):
         with pytest.raises(msb.MsbError) as e:
             plan.set_config("fp64", **bad)
         assert e.value.status == msb.MSB_EINVAL
@@ -134,3 +136,46 @@ def test_autotune_keeps_parity(dim):
         err = rel_err(u.cpu().numpy()[c], ref)
         log("refined solve after autotune case %d rel err %.2e" % (c, err))
         assert info[c].status == 0 and err <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("team", ["block", "wave"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_inplace_stages_equal_two_buffer_stages(prec, team, dim):
+    """In-place Stockham stages do the arithmetic of the two-buffer stages in the same order
+    (the compiler may contract the two code paths into different fused multiply-adds):
+    equal products up to that rounding (x passes, line passes, both), and the oracle's."""
+    import torch
+    import paper_2301_11828_amd as msb
+    if dim == 2:
+        w = W.small(2, (45, 38), 3, seed=91, fixed="left", crack=True, batch=2)
+    else:
+        w = W.small(3, (13, 11, 9), 2, seed=92, fixed="bottom", batch=2)
+    plan = gpu_plan(w)
+    if team == "block":
+        base = dict(team_x=0, rows_per_wg=4 if dim == 2 else 3, threads_x=192, team_line=0, lines_per_wg=2,
+                    threads_line=128, max_radix=16)
+    else:
+        base = dict(team_x=1, rows_per_wg=8 if dim == 2 else 5, slots_fwd=2, slots_inv=1, team_line=1,
+                    lines_per_wg=4, lines_per_wave=2, max_radix=16)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u = to_dev(w.b, dt)
+    plan.set_config(prec, lds_inplace=0, **base)
+    ref = gpu_apply(plan, u).double().cpu().numpy()
+    for ip in (1, 2, 3):
+        plan.set_config(prec, lds_inplace=ip, **base)
+        f = gpu_apply(plan, u).double().cpu().numpy()
+        d = rel_err(f, ref)
+        log("in-place %d %dD %s %s: rel diff to two-buffer stages %.2e" % (ip, dim, team, prec, d))
+        assert d <= (1e-15 if prec == "fp64" else 1e-6)
+    _check_apply(plan, w, prec, "in-place %s" % team)
+
+
+def test_autotune_with_inplace_stages_keeps_parity():
+    """The full search (effort 1, with the in-place stages) on a 16-case plan whose x rows
+    are LDS-heavy; the chosen configuration gives the oracle's product."""
+    w = W.small(2, (60, 200), 3, seed=93, fixed="left", batch=16)
+    plan = gpu_plan(w)
+    cfg, ms = plan.autotune("fp64", effort=1)
+    log("autotuned with in-place stages: %s (%.4f ms)" % (cfg, ms))
+    _check_apply(plan, w, "fp64", "autotuned (effort 1)")
