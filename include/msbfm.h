@@ -321,7 +321,9 @@ msb_status msb_plan_set_lengths(msb_plan plan, const int64_t *L);
  * `prec` (MSB_FP32_REFINED tunes both precisions) on `stream`, with every
  * kernel of the chain timed by HIP events, and keeps the fastest in the plan.
  * The search is coordinate-wise: x-pass settings (per kernel where the two x
- * kernels can differ), then line-pass settings, then max_radix (4, 8, 16).  With
+ * kernels can differ), then line-pass settings, then max_radix (4, 8, 16), then
+ * (effort 1) the x-pass and line-pass settings again with in-place stages
+ * (lds_inplace), kept where they are faster.  With
  * lengths != 0 it also tries padded lengths up to 12.5% longer than the
  * default, keeping the fastest (msb_plan_set_lengths).  effort: 0 = a small
  * candidate set, 1 = full.  best: host, receives the chosen configuration of
