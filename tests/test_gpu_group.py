@@ -229,3 +229,33 @@ def test_group_adjoint_gradient_matches_oracle(precond):
         ea = rel_err(infls[i].grad.numpy(), ga_ref)
         log("group adjoint member %d: rel err dL/db %.2e, dL/da %.2e" % (i, eb, ea))
         assert eb <= 1e-9 and ea <= 1e-9
+
+
+def test_group_inplace_stages_match_oracle():
+    """A group configuration with in-place stages: every member's schedules use a composite
+    radix (lengths 27, 36, 45, 48), the products match the oracle; adding a member whose
+    lengths factor into basic radices only (40 = 8 x 5, 32 = 8 x 4) makes that configuration
+    invalid."""
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (33, 40), 3, seed=181, fixed="left", crack=True, batch=2),
+          W.small(2, (24, 42), 3, seed=182, fixed="all"),
+          W.small(2, (45, 30), 3, seed=183, fixed="left", batch=2)]
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    cfg = dict(rows_per_wg=4, team_x=1, slots_fwd=2, slots_inv=1, team_line=1, lines_per_wg=4, lines_per_wave=2,
+               max_radix=16, lds_inplace=3)
+    for prec, tol in (("fp64", FP64_TOL), ("fp32", FP32_TOL)):
+        import torch
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        grp.set_config(prec, **cfg)
+        fs = grp.apply([to_dev(w.b, dt) for w in ws])
+        for i, w in enumerate(ws):
+            u = w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64)
+            err = rel_err(fs[i].double().cpu().numpy(), _oracle_apply(w, u))
+            log("group in-place %s member %d rel err %.2e" % (prec, i, err))
+            assert err <= tol
+    extra = W.small(2, (37, 29), 3, seed=184, fixed="left")
+    g2 = msb.PlanGroup(plans + [gpu_plan(extra)])
+    with pytest.raises(msb.MsbError) as e:
+        g2.set_config("fp64", **cfg)
+    assert e.value.status == msb.MSB_EINVAL
