@@ -518,8 +518,7 @@ def bench_plates64(args):
 
     def run_group():
         bs, as_ = inputs()
-        for pl, w in zip(plans, ws):
-            pl.set_infl(np.asarray(w.extra["infl_target"]))
+        grp.set_infl([np.asarray(w.extra["infl_target"]) for w in ws])
         uts, _ = grp.solve([b.detach() for b in bs], precision="fp32_refined", tol=1e-10)
         us = GSolve.apply(grp, "fp32_refined", 1e-10, *bs, *as_)
         loss = sum(((u - ut) ** 2).sum() for u, ut in zip(us, uts))

@@ -357,7 +357,13 @@ msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int 
  *   (entries may be null); info: host [total cases], member-major.  MSB_FP64,
  *   MSB_FP32 or MSB_FP32_REFINED (restarted refinement; reliable_update must be 0).
  *   opts->precond = 1 preconditions every member by its own circulant inverse (each
- *   built on first use, as for one plan).  A member with the surface correction set
+ *   built on first use, as for one plan; the host work of the missing ones runs on
+ *   parallel host threads).
+ * msb_group_set_infl: msb_plan_set_infl for every member i: infl[i] holds n_infl
+ *   values, or B_i x n_infl when per_case (host [nplans], or null: all shared) has
+ *   per_case[i] != 0.  The members' host work (bond weights, spectra, D^e tables)
+ *   runs on parallel host threads, the uploads follow in member order.  Validates
+ *   every member before changing any; synchronises the device.  A member with the surface correction set
  *   is rejected (MSB_EUNSUPPORTED: that operator is not symmetric).
  */
 typedef struct msb_group_s *msb_group;
@@ -367,6 +373,7 @@ msb_status msb_group_get_config(msb_group group, msb_precision prec, msb_launch_
 msb_status msb_group_set_config(msb_group group, msb_precision prec, const msb_launch_config *cfg);
 msb_status msb_group_apply(msb_group group, msb_precision prec, const void *const *u, void *const *f,
                            void *stream);
+msb_status msb_group_set_infl(msb_group group, const double *const *infl, int n_infl, const int *per_case);
 msb_status msb_group_solve_static(msb_group group, msb_precision prec, const double *const *b,
                                   const double *const *g, double *const *u, const msb_solve_opts *opts,
                                   msb_solve_info *info, void *stream);

@@ -32,7 +32,8 @@ EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "m
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
            "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
            "msb_plan_autotune", "msb_group_create", "msb_group_destroy", "msb_group_get_config",
-           "msb_group_set_config", "msb_group_apply", "msb_group_solve_static", "msb_last_error")
+           "msb_group_set_config", "msb_group_apply", "msb_group_set_infl", "msb_group_solve_static",
+           "msb_last_error")
 
 
 class MsbError(RuntimeError):
@@ -117,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         "msb_group_get_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
         "msb_group_set_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
         "msb_group_apply": ([P, I, P, P, P], I),
+        "msb_group_set_infl": ([P, P, I, P], I),
         "msb_group_solve_static": ([P, I, P, P, P, ctypes.POINTER(_Opts), P, P], I),
         "msb_last_error": ([], ctypes.c_char_p),
     }
@@ -502,6 +504,28 @@ class PlanGroup:
         _check(_lib.msb_group_apply(self._ptr, prec, self._ptrs(us, dt, "u"), self._ptrs(outs, dt, "f"), _stream()))
         return outs
 
+    def set_infl(self, infls, per_case=None):
+        """New influence coefficients for every member in one call (msb_group_set_infl):
+        infls[i] of shape (k,), or (B_i, k) where per_case[i] is true; the members' host
+        work runs on parallel host threads."""
+        n = len(self.plans)
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in infls]
+        if len(arrs) != n:
+            raise ValueError("one coefficient array per member (%d)" % n)
+        pc = [bool(x) for x in (per_case if per_case is not None else [False] * n)]
+        ks = {a.shape[-1] if a.ndim else 0 for a in arrs}
+        if len(ks) != 1:
+            raise ValueError("every member needs the same number of coefficients")
+        k = ks.pop()
+        for i, (a, p, c) in enumerate(zip(arrs, self.plans, pc)):
+            if a.size != (p.batch if c else 1) * k:
+                raise ValueError("member %d: expected %d coefficients" % (i, (p.batch if c else 1) * k))
+        ptrs = (ctypes.c_void_p * n)(*[a.ctypes.data for a in arrs])
+        flags = (ctypes.c_int * n)(*[int(c) for c in pc])
+        _check(_lib.msb_group_set_infl(self._ptr, ptrs, int(k), flags))
+        for p in self.plans:
+            p.n_infl = int(k)
+
     def solve(self, bs, gs=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
               inner_tol: float = 0.0, graph_block: int = 0, outs=None, check: bool = True, precond=None):
         """Static solves of every member at once; returns (list of u, list of per-member info lists).
@@ -573,8 +597,7 @@ def make_group_solve_function():
         def forward(ctx, group, precision, tol, *tensors):
             n = len(group.plans)
             bs, infls = tensors[:n], tensors[n:]
-            for p, a in zip(group.plans, infls):
-                p.set_infl(a.detach().cpu().numpy(), per_case=(a.dim() == 2))
+            group.set_infl([a.detach().cpu().numpy() for a in infls], per_case=[a.dim() == 2 for a in infls])
             us, _ = group.solve([b.contiguous() for b in bs], precision=precision, tol=tol)
             ctx.group, ctx.precision, ctx.tol = group, precision, tol
             ctx.per_case = [a.dim() == 2 for a in infls]

@@ -222,7 +222,9 @@ FftSched make_sched(const FftAxis &ax, bool fp32, int max_radix);
 msb_status relayout(msb_plan_s *p, const int64_t *L);
 
 msb_status alloc_operator(msb_plan_s *p, DeviceOp &op, int count);
-msb_status build_preconditioner(msb_plan_s *p, DeviceOp &pre);
+msb_status build_preconditioner(msb_plan_s *p);   // (re)builds p->pre
+msb_status build_preconditioners(msb_plan_s *const *ps, int n);   // parallel host work, plans without one
+msb_status set_infl_many(msb_plan_s *const *ps, int n, const double *const *infl, int n_infl, const int *per_case);
 // Fictitious density of dynamic relaxation, D_ii = 1/4 sum_j |K_ij| for every DOF of
 // every operator slot ([slots][d][N]; slots = per-case operators or 1) (plan.cpp).
 void build_adr_density(const msb_plan_s *p, std::vector<double> &D, int &slots);

@@ -15,7 +15,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <functional>
+#include <thread>
 #include <numeric>
 
 #include "common.hpp"
@@ -384,70 +386,132 @@ template <typename T> static msb_status put(T *dst, const std::vector<double> &v
     return MSB_OK;
 }
 
+// Coefficients of operator slot c (shared, or case c's with per-case coefficients).
+static std::vector<double> slot_infl(const msb_plan_s *p, int c) {
+    if (!p->per_case) return p->infl;
+    return std::vector<double>(p->infl_case.begin() + (size_t)c * p->n_infl,
+                               p->infl_case.begin() + (size_t)(c + 1) * p->n_infl);
+}
+
 // Circulant preconditioner of K = -A: on the padded grid, the periodic operator with
 // the same generating array is diagonal in Fourier space with the d x d real symmetric
 // blocks Khat(k) = -Ghat(k).  Its shifted inverse (Khat(k) + s I)^{-1}, s = 1e-3 times
 // the largest block eigenvalue bound (which also removes the rigid-motion nullspace at
 // k = 0), is stored like the spectra (components xx xy yy / xx xy xz yy yz zz, scaled
 // by 1 / prod(L)), so the same product chain applies it.
-msb_status build_preconditioner(msb_plan_s *p, DeviceOp &pre) {
-    const int count = p->op.count > 0 ? p->op.count : 1;
+// Host part of one slot of the preconditioner (reads only the plan's geometry: several
+// plans may run it on parallel threads).
+static void precond_symbol(const msb_plan_s *p, const std::vector<double> &infl, std::vector<double> &out) {
     const int d = p->dim, nc = p->ncomp;
     const size_t ns = spectrum_len(p);
-    free_operator(pre);
-    MSB_HIP(hipMalloc(&pre.spec64, sizeof(double) * nc * ns * count));
-    MSB_HIP(hipMalloc(&pre.spec32, sizeof(float) * nc * ns * count));
     const double vol = (double)p->L[0] * (double)p->L[1] * (double)p->L[2];
-    for (int c = 0; c < count; ++c) {
-        const std::vector<double> infl = p->per_case ? std::vector<double>(p->infl_case.begin() + (size_t)c * p->n_infl,
-                                                                           p->infl_case.begin() + (size_t)(c + 1) * p->n_infl)
-                                                     : p->infl;
-        std::vector<long double> W;
-        bond_weights(p, infl, W);
-        std::vector<double> spec, out((size_t)nc * ns);
-        build_spectrum(p, W, spec);
-        // Khat = -spec * vol per frequency; largest eigenvalue bound by the row sums
-        double lmax = 0.0;
-        for (size_t k = 0; k < ns; ++k) {
-            double Kb[3][3];
-            for (int a = 0; a < d; ++a)
-                for (int b = 0; b < d; ++b) Kb[a][b] = -spec[(size_t)comp_index(a, b, d) * ns + k] * vol;
-            for (int a = 0; a < d; ++a) {
-                double r = 0.0;
-                for (int b = 0; b < d; ++b) r += std::fabs(Kb[a][b]);
-                lmax = std::max(lmax, r);
-            }
+    std::vector<long double> W;
+    bond_weights(p, infl, W);
+    std::vector<double> spec;
+    build_spectrum(p, W, spec);
+    out.assign((size_t)nc * ns, 0.0);
+    // Khat = -spec * vol per frequency; largest eigenvalue bound by the row sums
+    double lmax = 0.0;
+    for (size_t k = 0; k < ns; ++k) {
+        double Kb[3][3];
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) Kb[a][b] = -spec[(size_t)comp_index(a, b, d) * ns + k] * vol;
+        for (int a = 0; a < d; ++a) {
+            double r = 0.0;
+            for (int b = 0; b < d; ++b) r += std::fabs(Kb[a][b]);
+            lmax = std::max(lmax, r);
         }
-        const double shift = 1e-3 * (lmax > 0.0 ? lmax : 1.0);
-        for (size_t k = 0; k < ns; ++k) {
-            double Kb[3][3], I[3][3];
-            for (int a = 0; a < d; ++a)
-                for (int b = 0; b < d; ++b) Kb[a][b] = -spec[(size_t)comp_index(a, b, d) * ns + k] * vol + (a == b ? shift : 0.0);
-            if (d == 2) {
-                const double det = Kb[0][0] * Kb[1][1] - Kb[0][1] * Kb[1][0];
-                I[0][0] = Kb[1][1] / det;
-                I[1][1] = Kb[0][0] / det;
-                I[0][1] = I[1][0] = -Kb[0][1] / det;
-            } else {
-                const double c00 = Kb[1][1] * Kb[2][2] - Kb[1][2] * Kb[2][1];
-                const double c01 = Kb[1][2] * Kb[2][0] - Kb[1][0] * Kb[2][2];
-                const double c02 = Kb[1][0] * Kb[2][1] - Kb[1][1] * Kb[2][0];
-                const double det = Kb[0][0] * c00 + Kb[0][1] * c01 + Kb[0][2] * c02;
-                I[0][0] = c00 / det;
-                I[0][1] = I[1][0] = c01 / det;
-                I[0][2] = I[2][0] = c02 / det;
-                I[1][1] = (Kb[0][0] * Kb[2][2] - Kb[0][2] * Kb[2][0]) / det;
-                I[1][2] = I[2][1] = (Kb[0][2] * Kb[1][0] - Kb[0][0] * Kb[1][2]) / det;
-                I[2][2] = (Kb[0][0] * Kb[1][1] - Kb[0][1] * Kb[1][0]) / det;
-            }
-            for (int a = 0; a < d; ++a)
-                for (int b = a; b < d; ++b) out[(size_t)comp_index(a, b, d) * ns + k] = I[a][b] / vol;
-        }
-        MSB_TRY(put(pre.spec64 + (size_t)nc * ns * c, out));
-        MSB_TRY(put(pre.spec32 + (size_t)nc * ns * c, out));
     }
-    pre.count = count;   // built (a failed build leaves count 0: rebuilt on next use)
+    const double shift = 1e-3 * (lmax > 0.0 ? lmax : 1.0);
+    for (size_t k = 0; k < ns; ++k) {
+        double Kb[3][3], I[3][3];
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) Kb[a][b] = -spec[(size_t)comp_index(a, b, d) * ns + k] * vol + (a == b ? shift : 0.0);
+        if (d == 2) {
+            const double det = Kb[0][0] * Kb[1][1] - Kb[0][1] * Kb[1][0];
+            I[0][0] = Kb[1][1] / det;
+            I[1][1] = Kb[0][0] / det;
+            I[0][1] = I[1][0] = -Kb[0][1] / det;
+        } else {
+            const double c00 = Kb[1][1] * Kb[2][2] - Kb[1][2] * Kb[2][1];
+            const double c01 = Kb[1][2] * Kb[2][0] - Kb[1][0] * Kb[2][2];
+            const double c02 = Kb[1][0] * Kb[2][1] - Kb[1][1] * Kb[2][0];
+            const double det = Kb[0][0] * c00 + Kb[0][1] * c01 + Kb[0][2] * c02;
+            I[0][0] = c00 / det;
+            I[0][1] = I[1][0] = c01 / det;
+            I[0][2] = I[2][0] = c02 / det;
+            I[1][1] = (Kb[0][0] * Kb[2][2] - Kb[0][2] * Kb[2][0]) / det;
+            I[1][2] = I[2][1] = (Kb[0][2] * Kb[1][0] - Kb[0][0] * Kb[1][2]) / det;
+            I[2][2] = (Kb[0][0] * Kb[1][1] - Kb[0][1] * Kb[1][0]) / det;
+        }
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b) out[(size_t)comp_index(a, b, d) * ns + k] = I[a][b] / vol;
+    }
+}
+
+// Runs body(i) for i in [0, n) on up to 16 host threads (the plans' host preparation
+// work; each i touches only its own outputs).  Returns false if a thread failed.
+static bool parallel_for(int n, const std::function<void(int)> &body) {
+    const int nt = std::max(1, std::min({n, 16, (int)std::max(1u, std::thread::hardware_concurrency())}));
+    std::atomic<int> next{0};
+    std::atomic<bool> ok{true};
+    auto work = [&]() {
+        for (int i = next++; i < n; i = next++) {
+            try {
+                body(i);
+            } catch (...) {
+                ok = false;
+            }
+        }
+    };
+    if (nt <= 1) {
+        work();
+        return ok;
+    }
+    std::vector<std::thread> th;
+    try {
+        for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    } catch (...) {   // fewer threads than asked: the remaining ones share the work
+    }
+    work();
+    for (auto &t : th) t.join();
+    return ok;
+}
+
+// Preconditioners of every listed plan that has none: the symbols on parallel host
+// threads, then the uploads in plan order.
+msb_status build_preconditioners(msb_plan_s *const *ps, int n) {
+    std::vector<int> todo;
+    for (int i = 0; i < n; ++i)
+        if (ps[i]->pre.count <= 0) todo.push_back(i);
+    std::vector<std::vector<std::vector<double>>> sym(todo.size());
+    const bool ok = parallel_for((int)todo.size(), [&](int k) {
+        const msb_plan_s *p = ps[todo[k]];
+        const int count = p->op.count > 0 ? p->op.count : 1;
+        sym[k].resize(count);
+        for (int c = 0; c < count; ++c) precond_symbol(p, slot_infl(p, c), sym[k][c]);
+    });
+    MSB_CHECK(ok, MSB_ENOMEM, "host allocation failed while building preconditioners");
+    for (size_t k = 0; k < todo.size(); ++k) {
+        msb_plan_s *p = ps[todo[k]];
+        DeviceOp &pre = p->pre;
+        const int count = (int)sym[k].size();
+        const size_t all = (size_t)p->ncomp * spectrum_len(p);
+        free_operator(pre);
+        MSB_HIP(hipMalloc(&pre.spec64, sizeof(double) * all * count));
+        MSB_HIP(hipMalloc(&pre.spec32, sizeof(float) * all * count));
+        for (int c = 0; c < count; ++c) {
+            MSB_TRY(put(pre.spec64 + all * c, sym[k][c]));
+            MSB_TRY(put(pre.spec32 + all * c, sym[k][c]));
+        }
+        pre.count = count;   // built (a failed build leaves count 0: rebuilt on next use)
+    }
     return MSB_OK;
+}
+
+msb_status build_preconditioner(msb_plan_s *p) {
+    free_operator(p->pre);
+    return build_preconditioners(&p, 1);
 }
 
 // Fictitious density of the dynamic-relaxation solver (the cited ADR method): a Gershgorin
@@ -518,21 +582,34 @@ void build_adr_density(const msb_plan_s *p, std::vector<double> &D, int &slots) 
 }
 
 // Fill one slot of an operator for the given influence coefficients.
-msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot) {
+// Host part of one operator slot: spectra, D^e table and bond weights (reads only the
+// plan's geometry: several plans may run it on parallel threads).
+struct OperatorHost {
+    std::vector<double> spec, de, w;
+};
+static void operator_host(const msb_plan_s *p, const std::vector<double> &infl, OperatorHost &h) {
     std::vector<long double> W;
     bond_weights(p, infl, W);
-    std::vector<double> spec, de;
-    build_spectrum(p, W, spec);
-    build_de_table(p, W, de);
-    std::vector<double> w64(W.begin(), W.end());
+    build_spectrum(p, W, h.spec);
+    build_de_table(p, W, h.de);
+    h.w.assign(W.begin(), W.end());
+}
+
+static msb_status upload_operator(msb_plan_s *p, const OperatorHost &h, DeviceOp &op, int slot) {
     const size_t ns = (size_t)p->ncomp * spectrum_len(p), nd = de_len(p), nw = w_len(p);
-    MSB_TRY(put(op.spec64 + ns * slot, spec));
-    MSB_TRY(put(op.spec32 + ns * slot, spec));
-    MSB_TRY(put(op.de64 + nd * slot, de));
-    MSB_TRY(put(op.de32 + nd * slot, de));
-    MSB_TRY(put(op.w64 + nw * slot, w64));
-    MSB_TRY(put(op.w32 + nw * slot, w64));
+    MSB_TRY(put(op.spec64 + ns * slot, h.spec));
+    MSB_TRY(put(op.spec32 + ns * slot, h.spec));
+    MSB_TRY(put(op.de64 + nd * slot, h.de));
+    MSB_TRY(put(op.de32 + nd * slot, h.de));
+    MSB_TRY(put(op.w64 + nw * slot, h.w));
+    MSB_TRY(put(op.w32 + nw * slot, h.w));
     return MSB_OK;
+}
+
+msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot) {
+    OperatorHost h;
+    operator_host(p, infl, h);
+    return upload_operator(p, h, op, slot);
 }
 
 void free_operator(DeviceOp &op) {
@@ -954,34 +1031,61 @@ extern "C" msb_status msb_crack_to_bonds(const msb_problem_desc *desc, const dou
     return MSB_OK;
 }
 
-extern "C" msb_status msb_plan_set_infl(msb_plan p, const double *infl, int n_infl, int per_case) {
-    if (p) ++p->op_version;
-    MSB_CHECK(p, MSB_EINVAL, "null plan");
+// New influence coefficients for several plans: validation, the host work of every
+// plan on parallel threads, then per plan the uploads and the bookkeeping (derivative
+// operators dropped when the coefficient count changes, the preconditioner rebuilt on
+// its next use, operator version bumped).  infl[i]: n_infl values, or B_i x n_infl
+// with per_case[i] != 0 (per_case may be null).
+msb_status msb::set_infl_many(msb_plan_s *const *ps, int n, const double *const *infl, int n_infl,
+                              const int *per_case) {
     MSB_CHECK(n_infl >= 0 && n_infl <= 8, MSB_EINVAL, "n_infl must be in [0, 8]");
-    MSB_CHECK(n_infl == 0 || infl, MSB_EINVAL, "null coefficients");
-    const int nset = per_case ? p->B : 1;
-    for (int64_t i = 0; i < (int64_t)nset * n_infl; ++i)
-        MSB_CHECK(std::isfinite(infl[i]), MSB_EINVAL, "coefficient %lld not finite", (long long)i);
-    hipDeviceSynchronize();
-    const int count = per_case ? p->B : 1;
-    if (p->op.count != count) MSB_TRY(alloc_operator(p, p->op, count));
-    for (int c = 0; c < count; ++c) {
-        std::vector<double> v(infl + (size_t)c * n_infl, infl + (size_t)(c + 1) * n_infl);
-        MSB_TRY(fill_operator(p, v, p->op, c));
+    for (int i = 0; i < n; ++i) {
+        MSB_CHECK(ps[i], MSB_EINVAL, "null plan");
+        MSB_CHECK(n_infl == 0 || infl[i], MSB_EINVAL, "null coefficients (plan %d)", i);
+        const int64_t nset = (per_case && per_case[i]) ? ps[i]->B : 1;
+        for (int64_t k = 0; k < nset * n_infl; ++k)
+            MSB_CHECK(std::isfinite(infl[i][k]), MSB_EINVAL, "plan %d: coefficient %lld not finite", i, (long long)k);
     }
-    p->per_case = per_case != 0;
-    if (per_case) {
-        p->infl_case.assign(infl, infl + (size_t)p->B * n_infl);
-        p->infl.clear();
-    } else {
-        p->infl.assign(infl, infl + n_infl);
-        p->infl_case.clear();
+    MSB_HIP(hipDeviceSynchronize());
+    std::vector<std::vector<OperatorHost>> host(n);
+    const bool ok = parallel_for(n, [&](int i) {
+        const msb_plan_s *p = ps[i];
+        const int count = (per_case && per_case[i]) ? p->B : 1;
+        host[i].resize(count);
+        for (int c = 0; c < count; ++c) {
+            const double *v = n_infl ? infl[i] + (size_t)c * n_infl : nullptr;
+            operator_host(p, std::vector<double>(v, v + n_infl), host[i][c]);
+        }
+    });
+    MSB_CHECK(ok, MSB_ENOMEM, "host allocation failed while building the operators");
+    for (int i = 0; i < n; ++i) {
+        msb_plan_s *p = ps[i];
+        ++p->op_version;
+        const bool pc = per_case && per_case[i];
+        const int count = pc ? p->B : 1;
+        if (p->op.count != count) MSB_TRY(alloc_operator(p, p->op, count));
+        for (int c = 0; c < count; ++c) MSB_TRY(upload_operator(p, host[i][c], p->op, c));
+        p->per_case = pc;
+        const double *src = n_infl ? infl[i] : nullptr;
+        if (pc) {
+            p->infl_case.assign(src, src + (size_t)p->B * n_infl);
+            p->infl.clear();
+        } else {
+            p->infl.assign(src, src + n_infl);
+            p->infl_case.clear();
+        }
+        if (n_infl != p->n_infl) {
+            for (auto &o : p->dop) free_operator(o);
+            p->dop.clear();
+        }
+        free_operator(p->pre);   // rebuilt from the new coefficients on the next preconditioned solve
+        p->n_infl = n_infl;
     }
-    if (n_infl != p->n_infl) {
-        for (auto &o : p->dop) free_operator(o);
-        p->dop.clear();
-    }
-    free_operator(p->pre);   // rebuilt from the new coefficients on the next preconditioned solve
-    p->n_infl = n_infl;
     return MSB_OK;
+}
+
+extern "C" msb_status msb_plan_set_infl(msb_plan p, const double *infl, int n_infl, int per_case) {
+    MSB_CHECK(p, MSB_EINVAL, "null plan");
+    MSB_CHECK(n_infl == 0 || infl, MSB_EINVAL, "null coefficients");
+    return set_infl_many(&p, 1, &infl, n_infl, &per_case);
 }

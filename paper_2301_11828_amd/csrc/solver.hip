@@ -430,7 +430,7 @@ static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *
 // Built on first use, dropped with the operator.
 static msb_status ensure_pre(msb_plan_s *p) {
     if (p->pre.count > 0) return MSB_OK;
-    return build_preconditioner(p, p->pre);
+    return build_preconditioner(p);
 }
 
 template <typename T> struct Pcg {
@@ -1549,6 +1549,12 @@ extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_gr
     return MSB_OK;
 }
 
+extern "C" msb_status msb_group_set_infl(msb_group g, const double *const *infl, int n_infl, const int *per_case) {
+    MSB_CHECK(g, MSB_EINVAL, "null group");
+    MSB_CHECK(n_infl == 0 || infl, MSB_EINVAL, "null coefficient array");
+    return set_infl_many(g->m.data(), g->n, infl, n_infl, per_case);
+}
+
 extern "C" void msb_group_destroy(msb_group g) {
     if (!g) return;
     (void)hipDeviceSynchronize();
@@ -1646,6 +1652,7 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     std::vector<double *> z64(n);
     std::vector<float *> z32(n);
     if (pre) {
+        MSB_TRY(build_preconditioners(g->m.data(), n));   // the missing ones, host work in parallel
         for (int i = 0; i < n; ++i) {
             msb_plan_s *p = g->m[i];
             MSB_TRY(ensure_pre(p));

@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 from paper_2301_11828_amd import workloads as W
-from helpers import gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
+from helpers import gpu_apply, gpu_plan, log, oracle_bonds, oracle_problem, rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -259,3 +259,42 @@ def test_group_inplace_stages_match_oracle():
     with pytest.raises(msb.MsbError) as e:
         g2.set_config("fp64", **cfg)
     assert e.value.status == msb.MSB_EINVAL
+
+
+def test_group_set_infl_equals_member_calls_and_validates_first():
+    """One msb_group_set_infl call (members' host work on parallel threads) leaves every
+    member's operator as its own msb_plan_set_infl would: equal products, the oracle's; a
+    non-finite coefficient in any member is rejected before any member changes."""
+    import torch
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (25, 22), 3, seed=191, fixed="left", crack=True, batch=2),
+          W.small(2, (14, 18), 3, seed=192, fixed="all"),
+          W.small(2, (31, 12), 3, seed=193, fixed="left", batch=3)]
+    rng = np.random.default_rng(194)
+    coeffs = [rng.uniform(0.2, 1.0, (2, 4)), rng.uniform(0.2, 1.0, 4), rng.uniform(0.2, 1.0, (3, 4))]
+    per_case = [True, False, True]
+    pa = [gpu_plan(w) for w in ws]
+    pb = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(pa)
+    grp.set_infl(coeffs, per_case=per_case)
+    for p, c, pc in zip(pb, coeffs, per_case):
+        p.set_infl(c, per_case=pc)
+    us = [to_dev(w.b) for w in ws]
+    fa = [f.cpu().numpy() for f in grp.apply(us)]
+    for i, (w, p) in enumerate(zip(ws, pb)):
+        p.set_config("fp64", **grp.get_config("fp64"))
+        fb = gpu_apply(p, us[i]).cpu().numpy()
+        assert np.array_equal(fa[i], fb), "member %d differs from its own set_infl" % i
+        for c in range(w.batch):
+            a = tuple(coeffs[i][c]) if per_case[i] else tuple(coeffs[i])
+            ref = O.apply(oracle_problem(w, infl=a), w.b[c], w.fixed, oracle_bonds(w))
+            err = rel_err(fa[i][c], ref)
+            log("group set_infl member %d case %d rel err %.2e" % (i, c, err))
+            assert err <= FP64_TOL
+    bad = [c.copy() for c in coeffs]
+    bad[2][1, 3] = float("nan")
+    with pytest.raises(msb.MsbError) as e:
+        grp.set_infl([np.ones(4), np.ones(4), bad[2]], per_case=[False, False, True])
+    assert e.value.status == msb.MSB_EINVAL
+    again = [f.cpu().numpy() for f in grp.apply(us)]
+    assert all(np.array_equal(x, y) for x, y in zip(again, fa))
