@@ -498,6 +498,13 @@ def bench_plates64(args):
         pl.set_constraints(w.fixed)
         plans.append(pl)
     grp = msb.PlanGroup(plans)
+    tuning = None
+    if not args.no_tune:
+        # the group's launch configuration picked by the group autotuner (untimed set-up)
+        t0 = time.perf_counter()
+        grp.autotune("fp32_refined", effort=1)
+        tuning = {"seconds": round(time.perf_counter() - t0, 2), "fp64": grp.get_config("fp64"),
+                  "fp32": grp.get_config("fp32")}
     GSolve = msb.make_group_solve_function()
     Solve = msb.make_solve_function()
     by_size = {}
@@ -586,7 +593,7 @@ def bench_plates64(args):
             "speedup_group_vs_plans": round(dtp / dt, 2), "speedup_group_vs_batched_sizes": round(dts / dt, 2),
             "loss": loss, "grad_max_rel_diff_vs_plans": gdiff(grads, grads_p),
             "grad_max_rel_diff_vs_batched_sizes": gdiff(grads, grads_s),
-            "plates_per_size": {int(k): len(v) for k, v in sorted(by_size.items())}}
+            "plates_per_size": {int(k): len(v) for k, v in sorted(by_size.items())}, "group_tuning": tuning}
 
 
 if __name__ == "__main__":

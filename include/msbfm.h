@@ -363,7 +363,13 @@ msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int 
  *   values, or B_i x n_infl when per_case (host [nplans], or null: all shared) has
  *   per_case[i] != 0.  The members' host work (bond weights, spectra, D^e tables)
  *   runs on parallel host threads, the uploads follow in member order.  Validates
- *   every member before changing any; synchronises the device.  A member with the surface correction set
+ *   every member before changing any; synchronises the device.
+ * msb_group_autotune: the coordinate search of msb_plan_autotune (x passes and line
+ *   passes, each with two-buffer and in-place stages, then max_radix) over
+ *   configurations every member accepts, each timed as whole group products of all
+ *   members; keeps the fastest in the group (both precisions for
+ *   MSB_FP32_REFINED).  best / best_ms as for msb_plan_autotune.  Allocates one input
+ *   and one output vector per member for the timing; synchronises the device.  A member with the surface correction set
  *   is rejected (MSB_EUNSUPPORTED: that operator is not symmetric).
  */
 typedef struct msb_group_s *msb_group;
@@ -374,6 +380,8 @@ msb_status msb_group_set_config(msb_group group, msb_precision prec, const msb_l
 msb_status msb_group_apply(msb_group group, msb_precision prec, const void *const *u, void *const *f,
                            void *stream);
 msb_status msb_group_set_infl(msb_group group, const double *const *infl, int n_infl, const int *per_case);
+msb_status msb_group_autotune(msb_group group, msb_precision prec, int effort, msb_launch_config *best,
+                              double *best_ms);
 msb_status msb_group_solve_static(msb_group group, msb_precision prec, const double *const *b,
                                   const double *const *g, double *const *u, const msb_solve_opts *opts,
                                   msb_solve_info *info, void *stream);

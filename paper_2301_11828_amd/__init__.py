@@ -32,7 +32,8 @@ EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "m
            "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
            "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
            "msb_plan_autotune", "msb_group_create", "msb_group_destroy", "msb_group_get_config",
-           "msb_group_set_config", "msb_group_apply", "msb_group_set_infl", "msb_group_solve_static",
+           "msb_group_set_config", "msb_group_apply", "msb_group_set_infl", "msb_group_autotune",
+           "msb_group_solve_static",
            "msb_last_error")
 
 
@@ -119,6 +120,7 @@ def load_library(path: str = LIB_PATH):
         "msb_group_set_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
         "msb_group_apply": ([P, I, P, P, P], I),
         "msb_group_set_infl": ([P, P, I, P], I),
+        "msb_group_autotune": ([P, I, I, ctypes.POINTER(_LaunchConfig), ctypes.POINTER(D)], I),
         "msb_group_solve_static": ([P, I, P, P, P, ctypes.POINTER(_Opts), P, P], I),
         "msb_last_error": ([], ctypes.c_char_p),
     }
@@ -503,6 +505,14 @@ class PlanGroup:
             outs = [torch.empty_like(u) for u in us]
         _check(_lib.msb_group_apply(self._ptr, prec, self._ptrs(us, dt, "u"), self._ptrs(outs, dt, "f"), _stream()))
         return outs
+
+    def autotune(self, precision: str = "fp64", effort: int = 1):
+        """Time candidate group configurations (every member's products in one launch per
+        pass) and keep the fastest.  Returns (configuration dict, group product ms)."""
+        c = _LaunchConfig()
+        ms = ctypes.c_double(0.0)
+        _check(_lib.msb_group_autotune(self._ptr, _PREC[precision], int(effort), ctypes.byref(c), ctypes.byref(ms)))
+        return {k: getattr(c, k) for k in CONFIG_KEYS}, ms.value
 
     def set_infl(self, infls, per_case=None):
         """New influence coefficients for every member in one call (msb_group_set_infl):

@@ -1604,6 +1604,138 @@ static msb_status group_apply_t(msb_group_s *g, const void *const *u, void *cons
     return group_launch<T>(g, A, G_LIFT, user);
 }
 
+// Group autotuner: the plan autotuner's coordinate search (x passes, line passes, each
+// with two-buffer and in-place stages; then the radix cap) over configurations every
+// member accepts, each timed as whole group products (HIP events around nrep launches of
+// f_i = A_i u_i on the group's stream).  Leaves the fastest in the group.
+template <typename T> static msb_status group_tune_t(msb_group_s *g, int effort, double *best_ms) {
+    const int f = prec_index<T>();
+    const int n = g->n;
+    hipStream_t st = g->st;
+    std::vector<T *> u(n, nullptr), y(n, nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct Cleanup {
+        std::vector<T *> &u, &y;
+        hipEvent_t &e0, &e1;
+        ~Cleanup() {
+            for (T *x : u)
+                if (x) (void)hipFree(x);
+            for (T *x : y)
+                if (x) (void)hipFree(x);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } cleanup{u, y, e0, e1};
+    for (int i = 0; i < n; ++i) {
+        const size_t nv = (size_t)g->m[i]->B * g->m[i]->dim * g->m[i]->N;
+        MSB_HIP(hipMalloc(&u[i], sizeof(T) * nv));
+        MSB_HIP(hipMalloc(&y[i], sizeof(T) * nv));
+        hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kT), 0, st, u[i], nv, T(1));
+    }
+    MSB_HIP(hipGetLastError());
+    MSB_HIP(hipEventCreate(&e0));
+    MSB_HIP(hipEventCreate(&e1));
+    int nrep = 3;
+    auto time_now = [&](double &ms) -> msb_status {
+        std::vector<PassArgs<T>> A;
+        MSB_TRY(group_upload_args<T>(g, A));
+        std::vector<EndArgs<T>> E(n);
+        for (int i = 0; i < n; ++i) {
+            EndArgs<T> e = end_args<T>();
+            e.pro = PRO_NONE;
+            e.pio = u[i];
+            e.uin = u[i];
+            e.epi = EPI_APPLY;
+            e.out = y[i];
+            E[i] = e;
+        }
+        MSB_TRY(group_upload_end<T>(g, G_LIFT, E));
+        MSB_TRY(group_launch<T>(g, A, G_LIFT, st));
+        MSB_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < nrep; ++r) MSB_TRY(group_launch<T>(g, A, G_LIFT, st));
+        MSB_HIP(hipEventRecord(e1, st));
+        MSB_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        MSB_HIP(hipEventElapsedTime(&t, e0, e1));
+        ms = (double)t / nrep;
+        return MSB_OK;
+    };
+    msb_launch_config best = g->cfg[f];
+    double bt = 0.0;
+    MSB_TRY(time_now(bt));
+    nrep = std::max(3, std::min(40, (int)std::ceil(2.0 / std::max(bt, 1e-3))));   // about 2 ms per candidate
+    MSB_TRY(time_now(bt));
+    msb_status err = MSB_OK;
+    auto consider = [&](const msb_launch_config &c) {
+        if (err != MSB_OK || group_config(g, f, &c) != MSB_OK) return;   // not valid for every member
+        double ms = 0.0;
+        err = time_now(ms);
+        if (err == MSB_OK && ms < bt) {
+            bt = ms;
+            best = c;
+        }
+    };
+    const std::vector<int> Fs = {1, 2, 4, 8, 16};
+    const std::vector<int> ths = effort ? std::vector<int>{128, 256, 512} : std::vector<int>{256};
+    const std::vector<int> sls = effort ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2};
+    const std::vector<int> lps = effort ? std::vector<int>{1, 2, 4} : std::vector<int>{1};
+    for (int ip = 0; ip < 2; ++ip)
+        for (int F : Fs) {
+            for (int th : ths) {
+                msb_launch_config c = best;
+                c.team_x = 0, c.rows_per_wg = F, c.threads_x = th, c.lds_inplace = (best.lds_inplace & ~1) | ip;
+                consider(c);
+            }
+            for (int sl : sls) {
+                msb_launch_config c = best;
+                c.team_x = 1, c.rows_per_wg = F, c.slots_fwd = c.slots_inv = sl;
+                c.lds_inplace = (best.lds_inplace & ~1) | ip;
+                consider(c);
+            }
+        }
+    for (int ip = 0; ip < 2; ++ip)
+        for (int Fl : Fs) {
+            for (int th : ths) {
+                msb_launch_config c = best;
+                c.team_line = 0, c.lines_per_wg = Fl, c.threads_line = th;
+                c.lds_inplace = (best.lds_inplace & ~2) | (ip << 1);
+                consider(c);
+            }
+            for (int lp : lps) {
+                msb_launch_config c = best;
+                c.team_line = 1, c.lines_per_wg = Fl, c.lines_per_wave = lp;
+                c.lds_inplace = (best.lds_inplace & ~2) | (ip << 1);
+                consider(c);
+            }
+        }
+    for (int r : {4, 8, 16}) {
+        msb_launch_config c = best;
+        c.max_radix = r;
+        consider(c);
+    }
+    MSB_TRY(err);
+    MSB_TRY(group_config(g, f, &best));
+    if (best_ms) *best_ms = bt;
+    return MSB_OK;
+}
+
+extern "C" msb_status msb_group_autotune(msb_group g, msb_precision prec, int effort, msb_launch_config *best,
+                                         double *best_ms) {
+    MSB_CHECK(g, MSB_EINVAL, "null group");
+    MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32 || prec == MSB_FP32_REFINED, MSB_EINVAL, "bad precision");
+    MSB_CHECK(effort == 0 || effort == 1, MSB_EINVAL, "effort must be 0 or 1");
+    int dev = -1;
+    MSB_HIP(hipGetDevice(&dev));
+    MSB_CHECK(dev == g->device, MSB_EINVAL, "group was created on device %d, current is %d", g->device, dev);
+    MSB_HIP(hipDeviceSynchronize());
+    double t64 = 0.0, t32 = 0.0;
+    if (prec != MSB_FP32) MSB_TRY(group_tune_t<double>(g, effort, &t64));
+    if (prec != MSB_FP64) MSB_TRY(group_tune_t<float>(g, effort, &t32));
+    if (best) *best = g->cfg[prec == MSB_FP64 ? 0 : 1];
+    if (best_ms) *best_ms = prec == MSB_FP64 ? t64 : t32;
+    return MSB_OK;
+}
+
 extern "C" msb_status msb_group_apply(msb_group g, msb_precision prec, const void *const *u, void *const *f,
                                       void *stream) {
     MSB_CHECK(g && u && f, MSB_EINVAL, "null argument");

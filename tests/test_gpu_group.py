@@ -298,3 +298,30 @@ def test_group_set_infl_equals_member_calls_and_validates_first():
     assert e.value.status == msb.MSB_EINVAL
     again = [f.cpu().numpy() for f in grp.apply(us)]
     assert all(np.array_equal(x, y) for x, y in zip(again, fa))
+
+
+def test_group_autotune_keeps_parity():
+    """The group autotuner (whole-group products timed per candidate) leaves a configuration
+    every member accepts: products match the oracle, refined solves the Cholesky solution."""
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (25, 22), 3, seed=195, fixed="left", crack=True, batch=2),
+          W.small(2, (14, 18), 3, seed=196, fixed="all"),
+          W.small(2, (31, 12), 3, seed=197, fixed="left", batch=2)]
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    cfg, ms = grp.autotune("fp32_refined", effort=1)
+    log("group autotune: fp32 %s (%.4f ms), fp64 %s" % (cfg, ms, grp.get_config("fp64")))
+    assert ms > 0 and cfg == grp.get_config("fp32")
+    import torch
+    for prec, tol in (("fp64", FP64_TOL), ("fp32", FP32_TOL)):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        fs = grp.apply([to_dev(w.b, dt) for w in ws])
+        for i, w in enumerate(ws):
+            u = w.b if prec == "fp64" else w.b.astype(np.float32).astype(np.float64)
+            assert rel_err(fs[i].double().cpu().numpy(), _oracle_apply(w, u)) <= tol
+    us, infos = grp.solve([to_dev(w.b) for w in ws], precision="fp32_refined", tol=1e-12, precond=True)
+    for i, w in enumerate(ws):
+        for c in range(w.batch):
+            err = rel_err(us[i].cpu().numpy()[c], O.solve_dense(oracle_problem(w), w.b[c], w.fixed, None, oracle_bonds(w)))
+            log("tuned group refined PCG member %d case %d rel err %.2e" % (i, c, err))
+            assert infos[i][c].status == 0 and err <= 1e-10
