@@ -325,3 +325,21 @@ def test_group_autotune_keeps_parity():
             err = rel_err(us[i].cpu().numpy()[c], O.solve_dense(oracle_problem(w), w.b[c], w.fixed, None, oracle_bonds(w)))
             log("tuned group refined PCG member %d case %d rel err %.2e" % (i, c, err))
             assert infos[i][c].status == 0 and err <= 1e-10
+
+
+def test_group_set_infl_back_to_constant_micromodulus():
+    """Empty coefficient arrays (omega = 1) through the group call give the product of plans
+    created without influence coefficients."""
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (20, 17), 3, seed=198, fixed="left", infl=(0.3, 0.5)),
+          W.small(2, (15, 22), 3, seed=199, fixed="all", infl=(0.9, -0.2), batch=2)]
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    grp.set_infl([np.zeros(0), np.zeros(0)])
+    fs = grp.apply([to_dev(w.b) for w in ws])
+    for i, w in enumerate(ws):
+        import dataclasses
+        ref = _oracle_apply(dataclasses.replace(w, infl=()), w.b)
+        err = rel_err(fs[i].cpu().numpy(), ref)
+        log("group set_infl to omega = 1, member %d rel err %.2e" % (i, err))
+        assert err <= FP64_TOL and plans[i].n_infl == 0
