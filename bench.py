@@ -258,6 +258,22 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+    # the bandwidth a plain device copy reaches on this GPU (1 GiB read + 1 GiB written per
+    # copy, far beyond the 256 MB Infinity Cache), beside the 8 TB/s peak the fractions use
+    src = torch.empty(128 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_s = ev0.elapsed_time(ev1) / 10 * 1e-3
+    line["hbm_copy"] = {"GB_s": round(2 * src.numel() * 8 / copy_s / 1e9, 1), "bytes_per_copy": 2 * src.numel() * 8,
+                        "frac_of_peak": round(2 * src.numel() * 8 / copy_s / 1e9 / HBM_PEAK_GBS, 4)}
+    del src, dst
 
     if not args.no_cg:
         b = torch.from_numpy(w.b).cuda()
