@@ -721,6 +721,49 @@ def test_surface_volume_factors_closed_form():
     assert nu3[5, 2] == pytest.approx(full / (full - 0.5), rel=1e-14)
 
 
+def _surface_entry(p, nu, pi, qi, a, b):
+    """A[a p, b q] of the surface-corrected operator, read off the force of a unit
+    displacement of DOF (b, q) at row p."""
+    e = np.zeros((p.dim, p.N))
+    e[b, qi] = 1.0
+    return O.force(p, e, nu=nu, rows=np.array([pi]))[a, 0]
+
+
+def test_surface_golden_rows():
+    """Hand-worked rows (tests/golden/surface_rows_M2_2d.txt): one bond coefficient
+    v_pq = (nu_p + nu_q)/2 per bond on the rows of Omega_e, with non-constant nu, so a
+    factor taken from p alone (or from q alone) changes the entries."""
+    n, M = 7, 2
+    p = O.Problem((n, n), 1.0, M, 1.0)
+    ix = np.arange(p.N) % n
+    nu = 1.0 + ix / 10.0
+    comp = {"xx": (0, 0), "yy": (1, 1), "xy": (0, 1)}
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "surface_rows_M2_2d.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 15
+    for px, py, qx, qy, cname, val in rows:
+        a, b = comp[cname]
+        got = _surface_entry(p, nu, int(py) * n + int(px), int(qy) * n + int(qx), a, b)
+        assert got == pytest.approx(float(val), rel=1e-14, abs=1e-15), (px, py, qx, qy, cname)
+
+
+def test_surface_block_symmetric_on_omega_e():
+    """A bond's micromodulus belongs to the pair, so the scaled block is symmetric
+    between two rows of Omega_e (A_pq = A_qp for p, q both in Omega_e); across the edge of
+    Omega_e it is not (the row of the node off Omega_e is unscaled)."""
+    rng = np.random.default_rng(64)
+    p = _prob2(9, 8, 3)
+    nu = rng.uniform(0.6, 1.8, p.N)
+    on = _omega_e(p)
+    A = np.stack([O.force(p, np.eye(2 * p.N)[j].reshape(2, p.N), nu=nu).reshape(-1) for j in range(2 * p.N)], 1)
+    idx = np.concatenate([np.flatnonzero(on), p.N + np.flatnonzero(on)])
+    Ae = A[np.ix_(idx, idx)]
+    assert np.allclose(Ae, Ae.T, rtol=0, atol=1e-13 * np.abs(Ae).max())
+    off = np.concatenate([np.flatnonzero(~on), p.N + np.flatnonzero(~on)])
+    cross = A[np.ix_(idx, off)]
+    assert np.abs(cross - A[np.ix_(off, idx)].T).max() > 1e-3 * np.abs(Ae).max()
+
+
 # ---------------------------------------------------------------- adaptive dynamic relaxation (Alg. 1)
 
 def test_adr_converges_to_the_dense_solution():
