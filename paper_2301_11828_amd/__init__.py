@@ -222,6 +222,12 @@ class Plan:
         self._ptr = ctypes.c_void_p()
         _check(lib.msb_plan_create(ctypes.byref(d), ctypes.byref(self._ptr)))
         del keep
+        # what the operator was last built from, so that an adjoint solve can check it
+        # still applies the operator of its forward solve: the coefficients (restored
+        # when they differ) and a count of the other operator changes (constraints,
+        # broken bonds, surface factors), which it cannot restore
+        self._infl_state = (np.array(infl, dtype=np.float64), False)
+        self._struct_version = 0
 
     def close(self):
         if self._ptr:
@@ -281,17 +287,21 @@ class Plan:
     def set_constraints(self, fixed: Optional[np.ndarray]):
         if fixed is None:
             _check(_lib.msb_plan_set_constraints(self._ptr, None))
+            self._struct_version += 1
             return
         f = np.ascontiguousarray(np.asarray(fixed).reshape(self.dim, self.N).astype(np.uint8))
         _check(_lib.msb_plan_set_constraints(self._ptr, f.ctypes.data))
+        self._struct_version += 1
 
     def set_bonds(self, pairs: Optional[np.ndarray]):
         p = np.ascontiguousarray(np.asarray(pairs if pairs is not None else np.zeros((0, 2)),
                                             dtype=np.int64).reshape(-1, 2))
         _check(_lib.msb_plan_set_bonds(self._ptr, p.ctypes.data if len(p) else None, len(p)))
+        self._struct_version += 1
 
     def set_surface(self, nu: Optional[np.ndarray]):
         """Surface-correction factors per node ([N], or None to switch the correction off)."""
+        self._struct_version += 1
         if nu is None:
             _check(_lib.msb_plan_set_surface(self._ptr, None))
             return
@@ -321,6 +331,8 @@ class Plan:
         n = ctypes.c_int64()
         _check(_lib.msb_crack_update(self._ptr, prec, self._vec(u, u.dtype, "u"), float(s0), ctypes.byref(n),
                                      _stream()))
+        if n.value:
+            self._struct_version += 1
         return n.value
 
     def set_infl(self, infl, per_case: bool = False):
@@ -328,6 +340,26 @@ class Plan:
         k = a.shape[-1] if a.ndim else 0
         _check(_lib.msb_plan_set_infl(self._ptr, a.ctypes.data, int(k), int(per_case)))
         self.n_infl = int(k)
+        self._infl_state = (a.copy(), bool(per_case))
+
+    def _operator_state(self):
+        return (self._infl_state[0].copy(), self._infl_state[1], self._struct_version)
+
+    def _restore_operator(self, state):
+        """Make the plan apply the operator recorded by _operator_state() again: the
+        coefficients are re-applied when they differ; any other operator change since
+        then cannot be undone and raises.  Returns the state to restore afterwards, or
+        None when nothing changed."""
+        infl, per_case, version = state
+        if version != self._struct_version:
+            raise RuntimeError("the plan's constraints, broken bonds or surface factors changed between the "
+                               "forward solve and its adjoint")
+        cur = self._infl_state
+        if cur[1] == per_case and cur[0].shape == infl.shape and np.array_equal(cur[0], infl):
+            return None
+        before = self._operator_state()
+        self.set_infl(infl, per_case=per_case)
+        return before
 
     # ------------------------------------------------------------ tensors
     def _vec(self, t, dtype=None, name="vector"):
@@ -533,8 +565,9 @@ class PlanGroup:
         ptrs = (ctypes.c_void_p * n)(*[a.ctypes.data for a in arrs])
         flags = (ctypes.c_int * n)(*[int(c) for c in pc])
         _check(_lib.msb_group_set_infl(self._ptr, ptrs, int(k), flags))
-        for p in self.plans:
+        for p, a, c in zip(self.plans, arrs, pc):
             p.n_infl = int(k)
+            p._infl_state = (a.copy(), c)
 
     def solve(self, bs, gs=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
               inner_tol: float = 0.0, graph_block: int = 0, outs=None, check: bool = True, precond=None):
@@ -578,14 +611,21 @@ def make_solve_function():
             u, _ = plan.solve(b.contiguous(), precision=precision, tol=tol, precond=precond)
             ctx.plan, ctx.precision, ctx.tol, ctx.precond = plan, precision, tol, precond
             ctx.per_case, ctx.infl_device = infl.dim() == 2, infl.device
+            ctx.state = plan._operator_state()      # the operator this forward solve used
             ctx.save_for_backward(u)
             return u
 
         @staticmethod
         def backward(ctx, grad_u):
             (u,) = ctx.saved_tensors
-            w, _ = ctx.plan.solve(grad_u.contiguous(), precision=ctx.precision, tol=ctx.tol, precond=ctx.precond)
-            ga = torch.from_numpy(ctx.plan.grad_infl(u, w))
+            back = ctx.plan._restore_operator(ctx.state)
+            try:
+                w, _ = ctx.plan.solve(grad_u.contiguous(), precision=ctx.precision, tol=ctx.tol,
+                                      precond=ctx.precond)
+                ga = torch.from_numpy(ctx.plan.grad_infl(u, w))
+            finally:
+                if back is not None:
+                    ctx.plan.set_infl(back[0], per_case=back[1])
             if not ctx.per_case:
                 ga = ga.sum(0)          # one coefficient set shared by every case
             return None, w, ga.to(ctx.infl_device), None, None, None
@@ -612,6 +652,7 @@ def make_group_solve_function():
             ctx.group, ctx.precision, ctx.tol = group, precision, tol
             ctx.per_case = [a.dim() == 2 for a in infls]
             ctx.devs = [a.device for a in infls]
+            ctx.states = [p._operator_state() for p in group.plans]
             ctx.save_for_backward(*us)
             return tuple(us)
 
@@ -619,13 +660,27 @@ def make_group_solve_function():
         def backward(ctx, *grad_us):
             us = ctx.saved_tensors
             gus = [torch.zeros_like(u) if g is None else g.contiguous() for u, g in zip(us, grad_us)]
-            ws, _ = ctx.group.solve(gus, precision=ctx.precision, tol=ctx.tol)
-            gas = []
-            for p, u, w, pc, dev in zip(ctx.group.plans, us, ws, ctx.per_case, ctx.devs):
-                ga = torch.from_numpy(p.grad_infl(u, w))
-                if not pc:
-                    ga = ga.sum(0)
-                gas.append(ga.to(dev))
+            plans = ctx.group.plans
+            for p, st in zip(plans, ctx.states):
+                if st[2] != p._struct_version:
+                    raise RuntimeError("a member's constraints, broken bonds or surface factors changed between "
+                                       "the forward solve and its adjoint")
+            changed = any(not (p._infl_state[1] == st[1] and p._infl_state[0].shape == st[0].shape
+                               and np.array_equal(p._infl_state[0], st[0])) for p, st in zip(plans, ctx.states))
+            back = [p._operator_state() for p in plans] if changed else None
+            try:
+                if changed:
+                    ctx.group.set_infl([st[0] for st in ctx.states], per_case=[st[1] for st in ctx.states])
+                ws, _ = ctx.group.solve(gus, precision=ctx.precision, tol=ctx.tol)
+                gas = []
+                for p, u, w, pc, dev in zip(plans, us, ws, ctx.per_case, ctx.devs):
+                    ga = torch.from_numpy(p.grad_infl(u, w))
+                    if not pc:
+                        ga = ga.sum(0)
+                    gas.append(ga.to(dev))
+            finally:
+                if back is not None:
+                    ctx.group.set_infl([st[0] for st in back], per_case=[st[1] for st in back])
             return (None, None, None, *ws, *gas)
 
     return MSBFMGroupSolve

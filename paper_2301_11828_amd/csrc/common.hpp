@@ -201,6 +201,8 @@ struct msb_plan_s {
     void *solver_cache = nullptr;
     // incremented whenever A changes (coefficients, bonds, surface factors, constraints)
     int64_t op_version = 0;
+    // incremented whenever the padded lengths (and with them the transform layout) change
+    int64_t layout_version = 0;
 };
 
 namespace msb {

@@ -688,6 +688,7 @@ static msb_status check_lengths(const msb_plan_s *p, const int64_t *L) {
 
 // Build the parts of the plan that depend on the padded lengths (p->L set).
 static msb_status build_layout(msb_plan_s *p) {
+    ++p->layout_version;
     p->H = p->L[0] / 2 + 1;
     for (int a = 0; a < 3; ++a) MSB_TRY(make_axis((int)p->L[a], p->ax[a]));
     const int count = p->op.count > 0 ? p->op.count : 1;
@@ -879,7 +880,6 @@ extern "C" msb_status msb_plan_get_bonds(msb_plan p, int64_t *pairs, int64_t cap
 }
 
 msb_status msb::set_bonds_impl(msb_plan_s *p, const int64_t *pairs, int64_t nb) {
-    ++p->op_version;
     MSB_CHECK(nb >= 0, MSB_EINVAL, "negative bond count");
     MSB_CHECK(nb == 0 || pairs, MSB_EINVAL, "null bond list");
     const int d = p->dim, M = p->M, B = 2 * M + 1;
@@ -938,11 +938,24 @@ msb_status msb::set_bonds_impl(msb_plan_s *p, const int64_t *pairs, int64_t nb) 
     bond_ptr.push_back((int32_t)q.size());
     for (int64_t r = 0; r < rows; ++r) row_ptr[r + 1] += row_ptr[r];
 
-    MSB_TRY(upload(&p->br_row_ptr, nb ? row_ptr : std::vector<int32_t>()));
-    MSB_TRY(upload(&p->br_node_i, node_i));
-    MSB_TRY(upload(&p->br_bond_ptr, nb ? bond_ptr : std::vector<int32_t>()));
-    MSB_TRY(upload(&p->br_q, q));
-    MSB_TRY(upload(&p->br_off, off));
+    // the five device lists are built first and replace the plan's only when every upload
+    // succeeded: a failure leaves the previous broken set complete
+    int32_t *nl[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const std::vector<int32_t> empty;
+    const std::vector<int32_t> *src[5] = {nb ? &row_ptr : &empty, &node_i, nb ? &bond_ptr : &empty, &q, &off};
+    msb_status us = MSB_OK;
+    for (int k = 0; k < 5 && us == MSB_OK; ++k) us = upload(&nl[k], *src[k]);
+    if (us != MSB_OK) {
+        for (int32_t *b : nl)
+            if (b) (void)hipFree(b);
+        return us;
+    }
+    int32_t **cur[5] = {&p->br_row_ptr, &p->br_node_i, &p->br_bond_ptr, &p->br_q, &p->br_off};
+    for (int k = 0; k < 5; ++k) {
+        if (*cur[k]) (void)hipFree(*cur[k]);
+        *cur[k] = nl[k];
+    }
+    ++p->op_version;
     p->n_pairs = nb;
     p->n_br_nodes = (int64_t)node_i.size();
     std::vector<int64_t> hb;

@@ -335,6 +335,9 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
 
 // Iterations between host checks of the per-case done flags when no graph is used.
 constexpr int kPollIterations = 32;
+// FP64 solves: restarts of CG from the FP64 residual when the recurrence met the
+// tolerance but the residual b' - K u does not.
+constexpr int kPolish = 4;
 
 // Run CG iterations iter(it, update_only) from the prepared state (vectors, partials,
 // thresholds and both parity slots of the flags set).  Stops when every case has a
@@ -753,6 +756,55 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
             inner[c] = w->h_int[B + c];
             outer[c] = 1;
         }
+        if (prec == MSB_FP64) {
+            // The CG recurrence residual drifts from b' - K u.  A case whose recurrence met
+            // tol but whose FP64 residual does not restarts CG on that residual (residual
+            // replacement), aiming at half the missing factor, up to kPolish times.
+            CallBuf skip_buf;
+            MSB_HIP(hipMalloc(&skip_buf.p, sizeof(int) * B));
+            int *skip = static_cast<int *>(skip_buf.p);
+            double *r64 = w->v64[2], *d64 = tmp;
+            std::vector<int> hskip(B, 0);
+            std::vector<double> t2(B, 0.0);
+            int used = 0;
+            for (int c = 0; c < B; ++c) used = std::max(used, inner[c]);
+            for (int j = 0; j < kPolish && used < opts->maxit; ++j) {
+                MSB_TRY(true_residual(p, w, st, u, bp, r64, 0));
+                MSB_TRY(fetch_scal(w, st, 1, B));
+                bool any = false;
+                for (int c = 0; c < B; ++c) {
+                    const double rr = w->h_scal[c];
+                    const double relc = bb[c] > 0 ? std::sqrt(rr / bb[c]) : 0.0;
+                    hskip[c] = !(fl[c] == CONVERGED && relc > opts->tol);
+                    const double ratio = hskip[c] ? 0.5 : std::min(0.5, 0.5 * opts->tol * std::sqrt(bb[c] / rr));
+                    t2[c] = ratio * ratio;
+                    any = any || !hskip[c];
+                }
+                if (!any) break;
+                double *t2d = w->scal + 15 * (size_t)B;
+                MSB_HIP(hipMemcpyAsync(t2d, t2.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+                MSB_HIP(hipMemcpyAsync(skip, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+                // rhs = r64 is copied into the CG residual vector r64 itself (same index)
+                if (pre)
+                    MSB_TRY(pcg_solve<double>(p, w, st, r64, d64, r64, w->v64[3], w->v64[4], w->v64[5], opts->tol,
+                                              opts->maxit - used, gb, skip, nullptr, t2d));
+                else
+                    MSB_TRY(cg_solve<double>(p, w, st, r64, d64, r64, w->v64[3], w->v64[4], opts->tol,
+                                             opts->maxit - used, gb, skip, nullptr, nullptr, t2d));
+                MSB_TRY(fetch_scal(w, st, 0, B));
+                int mx = 0;
+                for (int c = 0; c < B; ++c) {
+                    if (hskip[c]) continue;
+                    inner[c] += w->h_int[B + c];
+                    outer[c] += 1;
+                    const int f = w->h_int[c] == CAPPED ? RUNNING : w->h_int[c];
+                    if (f != CONVERGED) fl[c] = f;
+                    mx = std::max(mx, w->h_int[B + c]);
+                }
+                used += mx;
+                hipLaunchKernelGGL(k_add_to<double>, dim3(grid_for(n)), dim3(kT), 0, st, u, (const double *)d64, n);
+            }
+        }
     } else {
         // FP32 inner CG inside FP64 refinement.  Each inner run reduces the FP32
         // residual by inner_tol (default 0.1 with reliable updates, 1e-4 restarted);
@@ -851,7 +903,7 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
     for (int c = 0; c < B; ++c) {
         rel[c] = bb[c] > 0 ? std::sqrt(w->h_scal[c] / bb[c]) : 0.0;
         msb_status s = flag_status(fl[c]);
-        if (s == MSB_OK && !(rel[c] <= opts->tol * 10)) s = MSB_ENOCONV;   // certified residual
+        if (s == MSB_OK && !(rel[c] <= opts->tol)) s = MSB_ENOCONV;   // certified residual
         if (fl[c] == RUNNING) s = rel[c] <= opts->tol ? MSB_OK : MSB_ENOCONV;
         info[c].status = s;
         info[c].outer_iters = outer[c];
@@ -1114,6 +1166,7 @@ struct msb_group_s {
     int *done = nullptr, *iters = nullptr, *skip = nullptr;   // [Btot]
     double *h_scal = nullptr;                  // pinned [16][Btot]
     int *h_int = nullptr;                      // pinned [2][Btot]
+    std::vector<int64_t> layout_seen;          // members' layout versions the tile tables were built for
     hipStream_t st = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
@@ -1177,6 +1230,24 @@ msb_status group_config(msb_group_s *g, int f, const msb_launch_config *want) {
 }
 
 template <typename T> constexpr int prec_index() { return sizeof(T) == 4 ? 1 : 0; }
+
+// A member's padded lengths may change after the group was built (msb_plan_set_lengths,
+// msb_plan_autotune with lengths): its tile counts and LDS sizes change with them.
+// Rebuild the tile tables for the current layouts before any group launch; a
+// configuration a member no longer accepts falls back to the default group choice.
+msb_status group_refresh(msb_group_s *g) {
+    bool stale = (int)g->layout_seen.size() != g->n;
+    for (int i = 0; i < g->n && !stale; ++i) stale = g->layout_seen[i] != g->m[i]->layout_version;
+    if (!stale) return MSB_OK;
+    MSB_HIP(hipDeviceSynchronize());
+    for (int f = 0; f < 2; ++f) {
+        const msb_launch_config keep = g->cfg[f];
+        if (group_config(g, f, &keep) != MSB_OK) MSB_TRY(group_config(g, f, nullptr));
+    }
+    g->layout_seen.resize(g->n);
+    for (int i = 0; i < g->n; ++i) g->layout_seen[i] = g->m[i]->layout_version;
+    return MSB_OK;
+}
 
 // Upload the members' pass arguments (refreshed: operators, constraints and bonds may
 // have changed since the last call) and the given end arguments into one slot.
@@ -1530,6 +1601,8 @@ extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_gr
     // tile partials sized for any configuration: at most one x tile per grid row
     for (int i = 0; i < nplans; ++i) tiles_max += (size_t)plans[i]->B * rows_total(plans[i]);
     g->tiles_max = tiles_max;
+    g->layout_seen.resize(nplans);
+    for (int i = 0; i < nplans; ++i) g->layout_seen[i] = plans[i]->layout_version;
     if (hipMalloc(&g->part_x, sizeof(double) * 3 * tiles_max) != hipSuccess ||
         hipMalloc(&g->part_rr, sizeof(double) * 2 * tiles_max) != hipSuccess ||
         hipMalloc(&g->part_rz, sizeof(double) * 6 * tiles_max) != hipSuccess ||
@@ -1572,6 +1645,7 @@ extern "C" msb_status msb_group_set_config(msb_group g, msb_precision prec, cons
     MSB_CHECK(g && cfg, MSB_EINVAL, "null argument");
     MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
     const int f = prec == MSB_FP32 ? 1 : 0;
+    MSB_TRY(group_refresh(g));
     const msb_launch_config keep = g->cfg[f];
     MSB_HIP(hipDeviceSynchronize());
     msb_status s = group_config(g, f, cfg);
@@ -1727,6 +1801,7 @@ extern "C" msb_status msb_group_autotune(msb_group g, msb_precision prec, int ef
     int dev = -1;
     MSB_HIP(hipGetDevice(&dev));
     MSB_CHECK(dev == g->device, MSB_EINVAL, "group was created on device %d, current is %d", g->device, dev);
+    MSB_TRY(group_refresh(g));
     MSB_HIP(hipDeviceSynchronize());
     double t64 = 0.0, t32 = 0.0;
     if (prec != MSB_FP32) MSB_TRY(group_tune_t<double>(g, effort, &t64));
@@ -1742,6 +1817,7 @@ extern "C" msb_status msb_group_apply(msb_group g, msb_precision prec, const voi
     int dev = -1;
     MSB_HIP(hipGetDevice(&dev));
     MSB_CHECK(dev == g->device, MSB_EINVAL, "group was created on device %d, current is %d", g->device, dev);
+    MSB_TRY(group_refresh(g));
     if (prec == MSB_FP64) return group_apply_t<double>(g, u, f, (hipStream_t)stream);
     MSB_CHECK(prec == MSB_FP32, MSB_EINVAL, "precision must be MSB_FP64 or MSB_FP32");
     return group_apply_t<float>(g, u, f, (hipStream_t)stream);
@@ -1762,6 +1838,7 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     int dev = -1;
     MSB_HIP(hipGetDevice(&dev));
     MSB_CHECK(dev == g->device, MSB_EINVAL, "group was created on device %d, current is %d", g->device, dev);
+    MSB_TRY(group_refresh(g));
     const int n = g->n, Bt = g->Btot;
     for (int i = 0; i < n; ++i)
         MSB_CHECK(b[i] && u[i] && b[i] != u[i] && (!gv || gv[i] != u[i]), MSB_EINVAL,
@@ -1845,6 +1922,46 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
             fl[c] = g->h_int[c] == CAPPED ? RUNNING : g->h_int[c];
             inner[c] = g->h_int[Bt + c];
             outer[c] = 1;
+        }
+        // residual replacement for cases whose recurrence met tol but whose FP64 residual
+        // does not (as msb_solve_static)
+        std::vector<const double *> rc(r.begin(), r.end());
+        std::vector<int> hskip(Bt, 0);
+        std::vector<double> t2(Bt, 0.0);
+        int used = 0;
+        for (int c = 0; c < Bt; ++c) used = std::max(used, inner[c]);
+        for (int j = 0; j < kPolish && used < opts->maxit; ++j) {
+            MSB_TRY(group_residual(g, A64, G_RESID, x, cbp, r, 0));
+            MSB_TRY(group_fetch(g, 1));
+            bool any = false;
+            for (int c = 0; c < Bt; ++c) {
+                const double rr = g->h_scal[c];
+                const double relc = bb[c] > 0 ? std::sqrt(rr / bb[c]) : 0.0;
+                hskip[c] = !(fl[c] == CONVERGED && relc > opts->tol);
+                const double ratio = hskip[c] ? 0.5 : std::min(0.5, 0.5 * opts->tol * std::sqrt(bb[c] / rr));
+                t2[c] = ratio * ratio;
+                any = any || !hskip[c];
+            }
+            if (!any) break;
+            double *t2d = g->scal + 15 * (size_t)Bt;
+            MSB_HIP(hipMemcpyAsync(t2d, t2.data(), sizeof(double) * Bt, hipMemcpyHostToDevice, st));
+            MSB_HIP(hipMemcpyAsync(g->skip, hskip.data(), sizeof(int) * Bt, hipMemcpyHostToDevice, st));
+            MSB_TRY(group_cg<double>(g, A64, rc, tmp, r, pv, q, opts->tol, opts->maxit - used, gb, g->skip, t2d, ap64,
+                                     zz64));
+            MSB_TRY(group_fetch(g, 0));
+            int mx = 0;
+            for (int c = 0; c < Bt; ++c) {
+                if (hskip[c]) continue;
+                inner[c] += g->h_int[Bt + c];
+                outer[c] += 1;
+                const int f = g->h_int[c] == CAPPED ? RUNNING : g->h_int[c];
+                if (f != CONVERGED) fl[c] = f;
+                mx = std::max(mx, g->h_int[Bt + c]);
+            }
+            used += mx;
+            for (int i = 0; i < n; ++i)
+                hipLaunchKernelGGL(k_add_to<double>, dim3(grid_for(w[i]->nvec)), dim3(kT), 0, st, u[i],
+                                   (const double *)tmp[i], w[i]->nvec);
         }
     } else if (prec == MSB_FP32) {
         std::vector<const float *> b32(n);
@@ -1953,7 +2070,7 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     for (int c = 0; c < Bt; ++c) {
         rel[c] = bb[c] > 0 ? std::sqrt(g->h_scal[c] / bb[c]) : 0.0;
         msb_status s = flag_status(fl[c]);
-        if (s == MSB_OK && !(rel[c] <= opts->tol * 10)) s = MSB_ENOCONV;
+        if (s == MSB_OK && !(rel[c] <= opts->tol)) s = MSB_ENOCONV;   // certified residual
         if (fl[c] == RUNNING) s = rel[c] <= opts->tol ? MSB_OK : MSB_ENOCONV;
         info[c].status = s;
         info[c].outer_iters = outer[c];
