@@ -283,6 +283,24 @@ msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds
  *   max_radix       largest Stockham radix of the schedules: 4 (radices 2, 3,
  *                   4; with 5 where the length needs it), 8 (adds 8; 5 always) or
  *                   16 (adds 6, 9, 10, 12, 15, 16)
+ *   tile            2D only.  0: the global chain above (x-forward, line product,
+ *                   x-inverse).  > 0: the tiled single-pass product with frame
+ *                   length tile (5-smooth, 8..64 in FP64, 8..96 in FP32; tile - 2M
+ *                   >= 4).  The Toeplitz part is a correlation with a kernel of
+ *                   support +-M, so the output on a block of T = tile - 2M nodes per
+ *                   axis needs u only on that block grown by M (zero outside the
+ *                   grid, the embedding of Sec. 3.3): one workgroup loads that
+ *                   tile x tile patch, transforms it in LDS (rows, then columns),
+ *                   multiplies by the spectra of the generating array wrapped to
+ *                   tile x tile (Alg. 3 on the patch; both displacement components in
+ *                   one complex transform), transforms back and keeps the inner
+ *                   T x T block, whose D^e / D^f corrections, mask and epilogue it
+ *                   applies before the one store.  One read of u, one write of f,
+ *                   one launch.  A fused solver update runs first as its own
+ *                   elementwise pass (the patches overlap).  The preconditioner of
+ *                   the solvers and plan groups always use the global chain.
+ *   threads_tile    threads per workgroup of the tiled product, multiple of 64,
+ *                   64..512
  *   lds_inplace     bit 0: x passes, bit 1: line passes; a set bit runs every
  *                   Stockham stage in place (each thread reads its butterflies
  *                   into registers, a barrier, then it writes them back into the
@@ -300,6 +318,7 @@ typedef struct {
     int lines_per_wg, team_line, lines_per_wave, threads_line;
     int max_radix;
     int lds_inplace;
+    int tile, threads_tile;
 } msb_launch_config;
 
 msb_status msb_plan_get_config(msb_plan plan, msb_precision prec, msb_launch_config *cfg);

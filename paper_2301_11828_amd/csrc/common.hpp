@@ -117,6 +117,15 @@ int next_smooth(int nmin, bool even_only);
 // Device data of the operator A for one or more sets of influence coefficients,
 // stored as `count` back-to-back slots (slot = batch case when every case has its
 // own coefficients, else a single shared slot).
+// Spectra of the generating array wrapped to a tl x tl frame (tiled 2D product), one
+// set per frame length in use: [count][3][tl][tl] = (Gxx+Gyy)/2, (Gxx-Gyy)/2, Gxy,
+// scaled by 1/tl^2.
+struct TileSpec {
+    int tl = 0;
+    double *s64 = nullptr;
+    float *s32 = nullptr;
+};
+
 struct DeviceOp {
     int count = 0;
     double *spec64 = nullptr;   // [count][ncomp][H][Ly][Lz] real spectra, scaled by 1/prod(L)
@@ -125,6 +134,8 @@ struct DeviceOp {
     float *de32 = nullptr;
     double *w64 = nullptr;      // [count][ncomp][n_off] bond weights (broken-bond correction)
     float *w32 = nullptr;
+    std::vector<TileSpec> tiles;   // frame spectra for the tiled product (2D), built on demand
+    std::vector<std::vector<double>> infl_slots;   // the coefficients of every slot (tile spectra rebuilds)
 };
 
 }  // namespace msb
@@ -150,6 +161,7 @@ struct msb_plan_s {
     int64_t L[3] = {1, 1, 1};
     int64_t H = 1;              // L[0]/2 + 1 (half spectrum along x)
     msb::FftAxis ax[3];
+    std::vector<msb::FftAxis> tax;   // frame axes (twiddles) of the tiled product, per length in use
     msb_launch_config cfg[2];   // launch configuration of the product: [0] FP64, [1] FP32
 
     // stencil (host)
@@ -232,6 +244,12 @@ msb_status set_infl_many(msb_plan_s *const *ps, int n, const double *const *infl
 void build_adr_density(const msb_plan_s *p, std::vector<double> &D, int &slots);
 msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot);
 void free_operator(DeviceOp &op);
+// Frame spectra of every operator of the plan (op and the derivative operators) and the
+// frame axis for the tile lengths of both launch configurations and `extra` (if > 0);
+// host work and uploads, so never during graph capture (plan.cpp).
+msb_status ensure_tiles(msb_plan_s *p, int extra = 0);
+const TileSpec *find_tile_spec(const DeviceOp &op, int tl);
+const FftAxis *find_tile_axis(const msb_plan_s *p, int tl);
 void solver_cache_free(msb_plan_s *p);
 // Replace the broken set by pairs[nb][2] (validated), rebuild the D^f lists (plan.cpp).
 msb_status set_bonds_impl(msb_plan_s *p, const int64_t *pairs, int64_t nb);

@@ -414,6 +414,80 @@ __device__ T2 *fft_wave(T2 *a, T2 *b, int S, const FftSched &sc, const T2 *__res
     return a;
 }
 
+// One Stockham stage over S signals of length L held in a 2D LDS array: element m of
+// signal s at s * ss + m * es (rows of a frame: ss = row pitch, es = 1; columns: ss = 1,
+// es = row pitch).  Consecutive threads take the same butterfly of consecutive signals,
+// so with an odd row pitch a wavefront's accesses fall on distinct LDS banks in both
+// directions.  mS = ceil(2^32 / S) (0 for S = 1).
+template <typename T, typename T2, int R, int DIR>
+__device__ __forceinline__ void stockham_pass_2d(const T2 *__restrict__ in, T2 *__restrict__ out, int S, uint32_t mS,
+                                                 int L, int ss, int es, const FftPass &ps,
+                                                 const T2 *__restrict__ tw, int tid, int nt) {
+    const int nb = ps.nb;
+    const int Ns = ps.Ns;
+    const int total = S * nb;
+    for (int t = tid; t < total; t += nt) {
+        const int j = (int)fdiv((uint32_t)t, mS);
+        const int s = t - j * S;
+        const T2 *x = in + s * ss + j * es;
+        T2 v[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = x[m * nb * es];
+        const int jq = (int)fdiv((uint32_t)j, ps.m_Ns);
+        const int k = j - jq * Ns;
+        if (Ns > 1) {
+            const int step = k * ps.twstep;
+#pragma unroll
+            for (int m = 1; m < R; ++m) {
+                T2 w = tw[m * step];
+                if (DIR > 0) w.y = -w.y;
+                v[m] = c_mul(v[m], w);
+            }
+        }
+        Dft<T, T2, R, DIR>::run(v, tw, L / R);
+        T2 *y = out + s * ss + (jq * Ns * R + k) * es;
+#pragma unroll
+        for (int m = 0; m < R; ++m) y[m * Ns * es] = v[m];
+    }
+}
+
+// All stages of the length-L transform of S signals of a 2D LDS array (layout as for
+// stockham_pass_2d), ping-pong between a and b with a block barrier after each stage;
+// returns the buffer that holds the result.  Every thread of the block must call it.
+template <typename T, typename T2, int DIR, int RMAX>
+__device__ T2 *fft_lds_2d(T2 *a, T2 *b, int S, int ss, int es, const FftSched &sc, const T2 *__restrict__ tw,
+                          int tid, int nt) {
+    const int L = sc.L;
+    const uint32_t mS = S <= 1 ? 0u : 0xFFFFFFFFu / (uint32_t)S + 1u;   // ceil(2^32 / S)
+    for (int p = 0; p < sc.np; ++p) {
+        const FftPass &ps = sc.ps[p];
+        switch (ps.R) {
+            case 2: stockham_pass_2d<T, T2, 2, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+            case 3: stockham_pass_2d<T, T2, 3, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+            case 4: stockham_pass_2d<T, T2, 4, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+            case 5: stockham_pass_2d<T, T2, 5, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+            case 8: stockham_pass_2d<T, T2, 8, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+            default:
+                if constexpr (RMAX >= 16) {
+                    switch (ps.R) {
+                        case 6: stockham_pass_2d<T, T2, 6, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+                        case 9: stockham_pass_2d<T, T2, 9, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+                        case 10: stockham_pass_2d<T, T2, 10, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+                        case 12: stockham_pass_2d<T, T2, 12, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+                        case 15: stockham_pass_2d<T, T2, 15, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+                        default: stockham_pass_2d<T, T2, 16, DIR>(a, b, S, mS, L, ss, es, ps, tw, tid, nt); break;
+                    }
+                }
+                break;
+        }
+        __syncthreads();
+        T2 *t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
 // Copy a length-L twiddle table into LDS (caller synchronises before use).
 template <typename T2>
 __device__ __forceinline__ void stage_twiddles(T2 *dst, const T2 *__restrict__ src, int L, int tid, int nt) {
@@ -473,16 +547,23 @@ __device__ __forceinline__ double block_sum_partials(const double *__restrict__ 
 // Sums of K <= 5 arrays of n partials each by a whole block, all in one pass and one
 // tree (the same per-array order as block_sum_partials); results broadcast to all
 // threads.  red: >= 96 doubles.
+// Array k holds n[k] partials (the arrays of one chain may come from passes with
+// different tile counts); with equal counts the order is that of a single count.
 template <int K>
-__device__ __forceinline__ void block_sum_partials_k(const double *const (&p)[K], int n, double (&out)[K],
+__device__ __forceinline__ void block_sum_partials_k(const double *const (&p)[K], const int (&n)[K], double (&out)[K],
                                                      double *red, int tid, int nt) {
     static_assert(K >= 1 && K <= 5, "block_sum uses red[k * 16 + wave] and red[80 + k]");
     double v[K];
+    int nmax = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0;
-    for (int i = tid; i < n; i += nt) {
+    for (int k = 0; k < K; ++k) {
+        v[k] = 0.0;
+        nmax = n[k] > nmax ? n[k] : nmax;
+    }
+    for (int i = tid; i < nmax; i += nt) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += p[k][i];
+        for (int k = 0; k < K; ++k)
+            if (i < n[k]) v[k] += p[k][i];
     }
     block_sum<K>(v, red, tid, nt);
     if (tid == 0) {

@@ -69,6 +69,18 @@ template <typename T> struct PassArgs {
     const int32_t *br_bond_ptr;
     const int32_t *br_q;
     const int32_t *br_off;
+    // Tiled single-pass product (2D): frame length tl per axis (0: the global chain of
+    // passes), tiles per case along x and y, threads per workgroup, the frame's Stockham
+    // schedule and twiddles, and the frame spectra [slots][3][tl][tl] ((Gxx+Gyy)/2,
+    // (Gxx-Gyy)/2, Gxy of the generating array wrapped to tl x tl, scaled by 1/tl^2)
+    int tl, ttx, tty, tthreads;
+    FftSched stl;
+    const cplx_t<T> *twt;
+    const T *tspec;
+    size_t tspec_slot;
+    // slots per case of the epilogue partial sums: the x-inverse tiles of the chain, or
+    // the tiles of the tiled product
+    int ept;
 };
 
 // Per-call data of the prologue/epilogue.
@@ -98,6 +110,13 @@ template <typename T> struct EndArgs {
     int n_num, n_den;
     int first;                 // no pending update (first iteration)
     int update_only;           // apply the pending update and stop (no transform)
+    int no_transform;          // apply the prologue (update, store, partials, flags) only: the
+                               // tiled product transforms the stored vector afterwards
+    // slots per case (n_cg3) and stride between the arrays (s_cg3) of the epilogue partials
+    // cg3 the prologue reduces (they come from the previous product's epilogue, whose
+    // tiles may differ from the x tiles of this launch); 0: this launch's x tiles
+    int n_cg3;
+    size_t s_cg3;
     int *iters;                // [B] completed updates
     const int *case_done;      // [B] per-case stop flags (skip work) or null
     // CG chains keep the flags in two arrays by iteration parity: the x-forward stops on
@@ -129,6 +148,12 @@ template <typename T>
 msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t s,
                           hipEvent_t *ev = nullptr, int reps = 1);
 inline int n_passes(int dim) { return dim == 2 ? 3 : 5; }
+// Kernels a product launch times: the chain's passes, or the one tiled kernel.
+template <typename T> inline int n_passes(const PassArgs<T> &a) { return a.tl > 0 ? 1 : n_passes(a.d); }
+// Tiles per case of the tiled product for frame length tl (0 when tl is 0).
+int tile_count(const msb_plan_s *p, int tl);
+// Slots per case every epilogue partial array needs under any valid configuration.
+int64_t partial_slots(const msb_plan_s *p);
 
 // Arguments of the product passes for plan p and operator op, with the plan's launch
 // configuration for T's precision, or cfg (and its radix cap) when given.

@@ -355,6 +355,45 @@ static void build_de_table(const msb_plan_s *p, const std::vector<long double> &
     }
 }
 
+// Spectra of the generating array wrapped to a tl x tl frame (the tiled 2D product):
+// Ghat(k) = sum_o K(o) exp(-2 pi i k.o / tl) over the (2M+1)^2 box; K is even in o for
+// every component, so the sum is real, sum_o K(o) cos(2 pi k.o / tl), each cosine taken
+// from the exact unit circle at (k.o mod tl).  Stored as the three reals the product
+// uses per frequency, (Gxx + Gyy)/2, (Gxx - Gyy)/2 and Gxy, scaled by 1/tl^2 (the
+// inverse transform's factor): out[c][ky][kx].
+static void tile_spectrum(const msb_plan_s *p, const std::vector<long double> &W, int tl, std::vector<double> &out) {
+    std::vector<long double> cs, sn;
+    unit_circle(tl, cs, sn);
+    const int n2 = tl * tl;
+    std::vector<long double> g((size_t)3 * n2, 0.0L);
+    long double centre[3] = {0.0L, 0.0L, 0.0L};
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < p->n_off; ++i) centre[c] -= W[(size_t)c * p->n_off + i];   // eq. (frb:e4)
+    for (int ky = 0; ky < tl; ++ky)
+        for (int kx = 0; kx < tl; ++kx) {
+            long double acc[3] = {centre[0], centre[1], centre[2]};
+            for (int i = 0; i < p->n_off; ++i) {
+                const int *o = &p->off[3 * i];
+                long long t = ((long long)kx * o[0] + (long long)ky * o[1]) % tl;
+                if (t < 0) t += tl;
+                const long double cv = cs[t];
+                for (int c = 0; c < 3; ++c) acc[c] += W[(size_t)c * p->n_off + i] * cv;
+            }
+            const size_t k = (size_t)ky * tl + kx;
+            g[k] = acc[0];
+            g[n2 + k] = acc[1];
+            g[2 * (size_t)n2 + k] = acc[2];
+        }
+    const long double sc = 1.0L / ((long double)tl * tl);
+    out.assign((size_t)3 * n2, 0.0);
+    for (int k = 0; k < n2; ++k) {
+        const long double gxx = g[k], gxy = g[n2 + k], gyy = g[2 * (size_t)n2 + k];
+        out[k] = (double)(0.5L * (gxx + gyy) * sc);
+        out[n2 + k] = (double)(0.5L * (gxx - gyy) * sc);
+        out[2 * (size_t)n2 + k] = (double)(gxy * sc);
+    }
+}
+
 template <typename T> static msb_status upload(T **dst, const std::vector<T> &v) {
     if (*dst) { hipFree(*dst); *dst = nullptr; }
     if (v.empty()) return MSB_OK;
@@ -595,8 +634,20 @@ static void operator_host(const msb_plan_s *p, const std::vector<double> &infl, 
     h.w.assign(W.begin(), W.end());
 }
 
-static msb_status upload_operator(msb_plan_s *p, const OperatorHost &h, DeviceOp &op, int slot) {
+static void free_tiles(DeviceOp &op) {
+    for (TileSpec &t : op.tiles) {
+        if (t.s64) (void)hipFree(t.s64);
+        if (t.s32) (void)hipFree(t.s32);
+    }
+    op.tiles.clear();
+}
+
+static msb_status upload_operator(msb_plan_s *p, const OperatorHost &h, DeviceOp &op, int slot,
+                                  const std::vector<double> &infl) {
     const size_t ns = (size_t)p->ncomp * spectrum_len(p), nd = de_len(p), nw = w_len(p);
+    free_tiles(op);   // frame spectra of the old coefficients (rebuilt by ensure_tiles)
+    if ((int)op.infl_slots.size() < op.count) op.infl_slots.resize(op.count);
+    op.infl_slots[slot] = infl;
     MSB_TRY(put(op.spec64 + ns * slot, h.spec));
     MSB_TRY(put(op.spec32 + ns * slot, h.spec));
     MSB_TRY(put(op.de64 + nd * slot, h.de));
@@ -609,14 +660,67 @@ static msb_status upload_operator(msb_plan_s *p, const OperatorHost &h, DeviceOp
 msb_status fill_operator(msb_plan_s *p, const std::vector<double> &infl, DeviceOp &op, int slot) {
     OperatorHost h;
     operator_host(p, infl, h);
-    return upload_operator(p, h, op, slot);
+    return upload_operator(p, h, op, slot, infl);
 }
 
 void free_operator(DeviceOp &op) {
     void *b[] = {op.spec64, op.spec32, op.de64, op.de32, op.w64, op.w32};
     for (void *x : b)
         if (x) hipFree(x);
+    free_tiles(op);
     op = DeviceOp();
+}
+
+const TileSpec *find_tile_spec(const DeviceOp &op, int tl) {
+    for (const TileSpec &t : op.tiles)
+        if (t.tl == tl) return &t;
+    return nullptr;
+}
+
+const FftAxis *find_tile_axis(const msb_plan_s *p, int tl) {
+    for (const FftAxis &a : p->tax)
+        if (a.L == tl) return &a;
+    return nullptr;
+}
+
+// Frame spectra of one operator for length tl (all its slots, both precisions).
+static msb_status build_tile_spec(msb_plan_s *p, DeviceOp &op, int tl) {
+    const size_t n = (size_t)3 * tl * tl;
+    std::vector<double> all(n * op.count);
+    for (int c = 0; c < op.count; ++c) {
+        std::vector<long double> W;
+        bond_weights(p, c < (int)op.infl_slots.size() ? op.infl_slots[c] : p->infl, W);
+        std::vector<double> v;
+        tile_spectrum(p, W, tl, v);
+        std::copy(v.begin(), v.end(), all.begin() + n * c);
+    }
+    TileSpec t;
+    t.tl = tl;
+    MSB_TRY(upload(&t.s64, all));
+    msb_status st = upload(&t.s32, std::vector<float>(all.begin(), all.end()));
+    if (st != MSB_OK) {
+        (void)hipFree(t.s64);
+        return st;
+    }
+    op.tiles.push_back(t);
+    return MSB_OK;
+}
+
+msb_status ensure_tiles(msb_plan_s *p, int extra) {
+    if (p->dim != 2) return MSB_OK;
+    const int want[3] = {p->cfg[0].tile, p->cfg[1].tile, extra};
+    for (int tl : want) {
+        if (tl <= 0) continue;
+        if (!find_tile_axis(p, tl)) {
+            FftAxis ax;
+            MSB_TRY(make_axis(tl, ax));
+            p->tax.push_back(ax);
+        }
+        if (p->op.count > 0 && !find_tile_spec(p->op, tl)) MSB_TRY(build_tile_spec(p, p->op, tl));
+        for (DeviceOp &d : p->dop)
+            if (d.count > 0 && !find_tile_spec(d, tl)) MSB_TRY(build_tile_spec(p, d, tl));
+    }
+    return MSB_OK;
 }
 
 static msb_status validate_desc(const msb_problem_desc *d) {
@@ -667,6 +771,11 @@ static void free_axes(msb_plan_s *p) {
         if (p->ax[a].tw32) (void)hipFree(p->ax[a].tw32);
         p->ax[a] = FftAxis();
     }
+    for (FftAxis &t : p->tax) {
+        if (t.tw64) (void)hipFree(t.tw64);
+        if (t.tw32) (void)hipFree(t.tw32);
+    }
+    p->tax.clear();
 }
 
 // Largest padded length per axis: the x pass stages up to three length-L signals
@@ -709,7 +818,7 @@ static msb_status build_layout(msb_plan_s *p) {
         MSB_CHECK(check_config(p, f == 1, p->cfg[f]) == MSB_OK, MSB_EUNSUPPORTED,
                   "grid too large for the LDS-staged transforms (%s)", msb_last_error());
     }
-    return MSB_OK;
+    return ensure_tiles(p);
 }
 
 msb_status msb::relayout(msb_plan_s *p, const int64_t *L) {
@@ -1077,7 +1186,10 @@ msb_status msb::set_infl_many(msb_plan_s *const *ps, int n, const double *const 
         const bool pc = per_case && per_case[i];
         const int count = pc ? p->B : 1;
         if (p->op.count != count) MSB_TRY(alloc_operator(p, p->op, count));
-        for (int c = 0; c < count; ++c) MSB_TRY(upload_operator(p, host[i][c], p->op, c));
+        for (int c = 0; c < count; ++c) {
+            const double *v = n_infl ? infl[i] + (size_t)c * n_infl : nullptr;
+            MSB_TRY(upload_operator(p, host[i][c], p->op, c, std::vector<double>(v, v + n_infl)));
+        }
         p->per_case = pc;
         const double *src = n_infl ? infl[i] : nullptr;
         if (pc) {
@@ -1093,6 +1205,7 @@ msb_status msb::set_infl_many(msb_plan_s *const *ps, int n, const double *const 
         }
         free_operator(p->pre);   // rebuilt from the new coefficients on the next preconditioned solve
         p->n_infl = n_infl;
+        MSB_TRY(ensure_tiles(p));
     }
     return MSB_OK;
 }

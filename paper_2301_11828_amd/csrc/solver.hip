@@ -103,7 +103,7 @@ static msb_status alloc_ws(msb_plan_s *p, SolverWs *w) {
     w->P = (int)std::max<size_t>(1, std::min<size_t>(256, (dn + 4095) / 4096));
     for (auto &x : w->v64) MSB_HIP(hipMalloc(&x, sizeof(double) * w->nvec));
     for (auto &x : w->v32) MSB_HIP(hipMalloc(&x, sizeof(float) * w->nvec));
-    MSB_HIP(hipMalloc(&w->part_x, sizeof(double) * 3 * (size_t)B * rows_total(p)));
+    MSB_HIP(hipMalloc(&w->part_x, sizeof(double) * 3 * (size_t)B * partial_slots(p)));
     MSB_HIP(hipMalloc(&w->part_rr, sizeof(double) * 2 * (size_t)B * std::max<int64_t>(rows_total(p), w->P)));
     MSB_HIP(hipMalloc(&w->part_aux, sizeof(double) * 3 * (size_t)B * w->P));
     MSB_HIP(hipMalloc(&w->case4, sizeof(double) * 5 * (size_t)B));
@@ -272,15 +272,20 @@ template <typename T> struct Cg {
 // case's partials.
 struct SumSrc {
     const double *p[5];
+    int n[5];   // partials per case of each array
 };
-template <int K> __global__ void k_cg_sums(SumSrc src, int tpc, double *out) {
+template <int K> __global__ void k_cg_sums(SumSrc src, double *out) {
     __shared__ double red[96];
     const int b = blockIdx.x;
     const double *parts[K];
+    int cnt[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) parts[k] = src.p[k] + (size_t)b * tpc;
+    for (int k = 0; k < K; ++k) {
+        parts[k] = src.p[k] + (size_t)b * src.n[k];
+        cnt[k] = src.n[k];
+    }
     double sums[K];
-    block_sum_partials_k<K>(parts, tpc, sums, red, threadIdx.x, blockDim.x);
+    block_sum_partials_k<K>(parts, cnt, sums, red, threadIdx.x, blockDim.x);
     if (threadIdx.x == 0) {
         for (int k = 0; k < K; ++k) out[(size_t)b * K + k] = sums[k];
     }
@@ -298,6 +303,8 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
     SolverWs *w = c.w;
     const int B = p->B;
     const size_t nt = (size_t)B * c.tpc;
+    const int ept = c.pa.ept;                 // epilogue partials per case (x-inverse or tiles)
+    const size_t ne = (size_t)B * ept;
     EndArgs<T> e = end_args<T>();
     e.pro = PRO_CG_P;
     e.pio = c.pv;
@@ -305,13 +312,15 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
     e.cr = c.r;
     e.cq = c.q;
     e.cg3 = w->part_x;
+    e.n_cg3 = ept;
+    e.s_cg3 = ne;
     e.rr_prev = w->part_rr + (size_t)((it + 1) & 1) * nt;
     e.rr_out = w->part_rr + (size_t)(it & 1) * nt;
     e.first = it == 0;
     e.update_only = update_only;
-    if (it > 0 && c.tpc > kFusedReduceMaxTiles) {
-        const SumSrc src{{e.rr_prev, e.cg3, e.cg3 + nt, e.cg3 + 2 * nt, nullptr}};
-        hipLaunchKernelGGL(k_cg_sums<4>, dim3(B), dim3(kT), 0, c.st, src, c.tpc, w->case4);
+    if (it > 0 && std::max(c.tpc, ept) > kFusedReduceMaxTiles) {
+        const SumSrc src{{e.rr_prev, e.cg3, e.cg3 + ne, e.cg3 + 2 * ne, nullptr}, {c.tpc, ept, ept, ept, 0}};
+        hipLaunchKernelGGL(k_cg_sums<4>, dim3(B), dim3(kT), 0, c.st, src, w->case4);
         e.case4 = w->case4;
     }
     e.iters = w->iters;
@@ -459,8 +468,10 @@ template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool up
     SolverWs *w = c.w;
     const int B = p->B;
     const size_t nt = (size_t)B * c.tpc;
+    const int ept = c.pa.ept;                 // the stiffness chain's epilogue partials per case
+    const size_t ne = (size_t)B * ept;
     const int cur = it & 1, prv = (it + 1) & 1;
-    const bool reduce = it > 0 && c.tpc > kFusedReduceMaxTiles;
+    const bool reduce = it > 0 && std::max(c.tpc, ept) > kFusedReduceMaxTiles;
     {
         EndArgs<T> e = end_args<T>();
         e.pro = PRO_PCG_R;
@@ -469,14 +480,16 @@ template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool up
         e.cr = c.r;
         e.cq = c.q;
         e.cg3 = w->part_x;
+        e.n_cg3 = ept;
+        e.s_cg3 = ne;
         e.rr_prev = w->part_rr + (size_t)prv * nt;
         e.rr_out = w->part_rr + (size_t)cur * nt;
         e.rz_k = w->part_rz + (size_t)prv * 3 * nt;
         e.first = it == 0;
         e.update_only = update_only;
         if (reduce) {
-            const SumSrc src{{e.rr_prev, e.rz_k, e.cg3, e.cg3 + nt, e.cg3 + 2 * nt}};
-            hipLaunchKernelGGL(k_cg_sums<5>, dim3(B), dim3(kT), 0, c.st, src, c.tpc, w->case4);
+            const SumSrc src{{e.rr_prev, e.rz_k, e.cg3, e.cg3 + ne, e.cg3 + 2 * ne}, {c.tpc, c.tpc, ept, ept, ept}};
+            hipLaunchKernelGGL(k_cg_sums<5>, dim3(B), dim3(kT), 0, c.st, src, w->case4);
             e.case4 = w->case4;
         }
         e.iters = w->iters;
@@ -500,8 +513,8 @@ template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool up
     e.rz_km1 = w->part_rz + (size_t)prv * 3 * nt;
     e.first = it == 0;
     if (reduce) {
-        const SumSrc src{{e.rz_k, e.rz_km1, nullptr, nullptr, nullptr}};
-        hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kT), 0, c.st, src, c.tpc, w->case4);
+        const SumSrc src{{e.rz_k, e.rz_km1, nullptr, nullptr, nullptr}, {c.tpc, c.tpc, 0, 0, 0}};
+        hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kT), 0, c.st, src, w->case4);
         e.case4 = w->case4;
     }
     e.case_done = w->done + (size_t)cur * B;
@@ -549,9 +562,8 @@ static msb_status true_residual(msb_plan_s *p, SolverWs *w, hipStream_t st, cons
     e.out = out;
     e.part = w->part_x;
     MSB_TRY(product<double>(p, p->op, x, e, st));
-    PassArgs<double> a = pass_args<double>(p, p->op);
-    const int tpc = x_tiles_per_case(p, a.F);
-    hipLaunchKernelGGL(k_case_sums, dim3(p->B), dim3(kT), 0, st, (const double *)w->part_x, tpc, (size_t)tpc,
+    const int ept = pass_args<double>(p, p->op).ept;
+    hipLaunchKernelGGL(k_case_sums, dim3(p->B), dim3(kT), 0, st, (const double *)w->part_x, ept, (size_t)ept,
                        w->scal + (size_t)slot * p->B, 1.0);
     MSB_HIP(hipGetLastError());
     return MSB_OK;
@@ -626,7 +638,8 @@ static msb_status ensure_dop(msb_plan_s *p, int k) {
     std::vector<double> e(k + 1, 0.0);
     e[k] = 1.0;
     MSB_TRY(alloc_operator(p, op, 1));
-    return fill_operator(p, e, op, 0);
+    MSB_TRY(fill_operator(p, e, op, 0));
+    return ensure_tiles(p);
 }
 
 extern "C" msb_status msb_apply_dinfl(msb_plan p, int k, const double *u, double *f, void *stream) {
@@ -644,7 +657,7 @@ template <typename T>
 static msb_status profile_t(msb_plan_s *p, const T *u, T *f, int nrep, double *ms, int *npass, hipStream_t st) {
     // each pass launched nrep times back to back between two events: the mean kernel
     // duration of a launch in a stream of launches; then one plain product for f
-    const int np = n_passes(p->dim);
+    const int np = n_passes(pass_args<T>(p, p->op));
     std::vector<hipEvent_t> ev((size_t)(np + 1), nullptr);
     msb_status s = MSB_OK;
     for (auto &e : ev)
@@ -954,7 +967,7 @@ static msb_status vv_run_t(msb_plan_s *p, double dt, int64_t nsteps, T *u, T *v,
     }
     if (ne > 0) hipLaunchKernelGGL(k_fill_int<int>, dim3(1), dim3(64), 0, st, w->ecount, 1, 0);
     PassArgs<T> pa = pass_args<T>(p, p->op);
-    const int tiles = p->B * x_tiles_per_case(p, pa.F);
+    const int tiles = p->B * pa.ept;   // epilogue partials of the whole batch
     double V = 1.0;
     for (int q = 0; q < p->dim; ++q) V *= p->h;
     for (int64_t s = 1; s <= nsteps; ++s) {
@@ -1017,12 +1030,12 @@ static msb_status adr_run_t(msb_plan_s *p, msb_precision prec, int64_t nsteps, i
         MSB_HIP(hipMemcpy(w->adr_D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice));
         w->adr_slots = slots;
         w->adr_version = p->op_version;
-        if (!w->part_adr) MSB_HIP(hipMalloc(&w->part_adr, sizeof(double) * 3 * (size_t)B * rows_total(p)));
+        if (!w->part_adr) MSB_HIP(hipMalloc(&w->part_adr, sizeof(double) * 3 * (size_t)B * partial_slots(p)));
     }
     const T *D = sizeof(T) == 8 ? (const T *)(const void *)w->adr_D64 : (const T *)(const void *)w->adr_D32;
     const size_t dstride = w->adr_slots > 1 ? dn : 0;
     PassArgs<T> pa = pass_args<T>(p, p->op);
-    const int tpc = x_tiles_per_case(p, pa.F);
+    const int tpc = pa.ept;   // damping partials per case (written by the product's epilogue)
     MSB_CHECK(restart || w->adr_tiles == tpc, MSB_EINVAL,
               "continuing a relaxation needs the launch configuration of the run it continues");
     const size_t nt = (size_t)B * tpc;
@@ -1052,9 +1065,11 @@ static msb_status adr_run_t(msb_plan_s *p, msb_precision prec, int64_t nsteps, i
         e.pa_stride = dstride;
         e.pg = g;
         e.cg3 = w->part_adr;
+        e.n_cg3 = tpc;
+        e.s_cg3 = nt;
         if (!first && tpc > kFusedReduceMaxTiles) {
-            const SumSrc src{{w->part_adr, w->part_adr + nt, nullptr, nullptr, nullptr}};
-            hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kT), 0, st, src, tpc, w->case4);
+            const SumSrc src{{w->part_adr, w->part_adr + nt, nullptr, nullptr, nullptr}, {tpc, tpc, 0, 0, 0}};
+            hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kT), 0, st, src, w->case4);
             e.case4 = w->case4;
         }
         e.epi = EPI_ADR;
@@ -1120,10 +1135,9 @@ extern "C" msb_status msb_grad_infl(msb_plan p, const double *u, const double *w
     MSB_TRY(get_ws(p, w));
     hipStream_t st = (hipStream_t)stream;
     const int B = p->B, K = p->n_infl;
-    PassArgs<double> pa = pass_args<double>(p, p->op);
-    const int tpc = x_tiles_per_case(p, pa.F);
     for (int k = 0; k < K; ++k) {
         MSB_TRY(ensure_dop(p, k));
+        const int tpc = pass_args<double>(p, p->dop[k]).ept;   // epilogue partials per case
         // dL/da_k = w . (A_k u)_F
         EndArgs<double> e = end_args<double>();
         e.epi = EPI_DOT;
@@ -1209,6 +1223,7 @@ msb_status group_config(msb_group_s *g, int f, const msb_launch_config *want) {
     const bool f32 = f == 1;
     msb_launch_config c;
     if (want) {
+        MSB_CHECK(want->tile == 0, MSB_EINVAL, "plan groups run the chain of passes (tile must be 0)");
         c = *want;
     } else {
         int big = 0;
@@ -1216,10 +1231,11 @@ msb_status group_config(msb_group_s *g, int f, const msb_launch_config *want) {
             if (g->m[i]->N * g->m[i]->B > g->m[big]->N * g->m[big]->B) big = i;
         c = g->m[big]->cfg[f];
     }
+    c.tile = 0;   // group launches run the chain of passes: a member's tiled configuration does not carry over
     bool ok = true;
     for (int i = 0; i < g->n && ok; ++i) ok = check_config(g->m[i], f32, c) == MSB_OK;
     if (!ok && !want) {
-        c = msb_launch_config{1, 0, 1, 1, 256, 1, 0, 1, 256, 8, 0};
+        c = msb_launch_config{1, 0, 1, 1, 256, 1, 0, 1, 256, 8, 0, 0, 256};
         ok = true;
         for (int i = 0; i < g->n && ok; ++i) ok = check_config(g->m[i], f32, c) == MSB_OK;
     }

@@ -44,7 +44,7 @@ template <typename T> struct Bench {
     std::vector<double> ms;
 
     msb_status init(int max_rep) {
-        np = n_passes(p->dim);
+        np = n_passes(p->dim);   // the chain; a tiled candidate times one kernel (ms[0])
         const size_t n = (size_t)p->B * p->dim * p->N;
         MSB_HIP(hipMalloc(&u, sizeof(T) * n));
         MSB_HIP(hipMalloc(&f, sizeof(T) * n));
@@ -70,6 +70,7 @@ template <typename T> struct Bench {
         const msb_launch_config keep = p->cfg[f32];
         p->cfg[f32] = c;
         err = set_schedules(p, f32, c.max_radix);
+        if (err == MSB_OK) err = ensure_tiles(p);
         if (err == MSB_OK) err = time_now();
         if (err != MSB_OK) {
             p->cfg[f32] = keep;
@@ -81,6 +82,7 @@ template <typename T> struct Bench {
 
     msb_status time_now() {
         PassArgs<T> a = pass_args<T>(p, p->op);
+        const int npa = n_passes(a);
         EndArgs<T> e;
         memset(&e, 0, sizeof(e));
         e.pro = PRO_NONE;
@@ -95,7 +97,7 @@ template <typename T> struct Bench {
         MSB_HIP(hipStreamSynchronize(st));
         for (int i = 0; i < np; ++i) {
             double acc = 0.0;
-            for (int r = 0; r < nrep; ++r) {
+            for (int r = 0; r < nrep && i < npa; ++r) {
                 float t = 0.f;
                 MSB_HIP(hipEventElapsedTime(&t, ev[(size_t)r * (np + 1) + i], ev[(size_t)r * (np + 1) + i + 1]));
                 acc += t;
@@ -129,6 +131,7 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
     MSB_TRY(bn.init(kMaxRep));
     msb_status err = MSB_OK;
     msb_launch_config cur = p->cfg[f32];
+    cur.tile = 0;   // the chain's settings are searched on the chain; the tiled product last
     MSB_CHECK(bn.run(cur, err), err != MSB_OK ? err : MSB_EINVAL, "current configuration is not valid");
     // about 2 ms of kernels per candidate, 3..40 products
     bn.nrep = std::max(3, std::min(kMaxRep, (int)std::ceil(2.0 / std::max(bn.total(), 1e-3))));
@@ -249,6 +252,30 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
         MSB_TRY(scan_x(1));
         MSB_TRY(scan_lines(1));
     }
+    // the tiled single-pass product (2D): frame lengths, threads per workgroup and radix
+    // caps, kept when one launch beats the tuned chain (the chain's settings stay for the
+    // preconditioner and the fused solver prologues)
+    if (p->dim == 2) {
+        msb_launch_config best = cur;
+        MSB_TRY(bn.run(cur, err) ? MSB_OK : err);
+        double bt = bn.total();
+        const std::vector<int> tls = effort ? std::vector<int>{16, 20, 24, 30, 32, 36, 40, 48, 60, 64, 72, 80, 96}
+                                            : std::vector<int>{24, 32, 40, 48, 64};
+        for (int tl : tls)
+            for (int th : effort ? std::vector<int>{128, 256, 512} : std::vector<int>{256})
+                for (int r : {8, 16}) {
+                    msb_launch_config c = cur;
+                    c.tile = tl;
+                    c.threads_tile = th;
+                    c.max_radix = r;
+                    if (bn.run(c, err) && bn.total() < bt) {
+                        bt = bn.total();
+                        best = c;
+                    }
+                    MSB_TRY(err);
+                }
+        cur = best;
+    }
     bn.nrep = std::max(bn.nrep, 5);
     MSB_CHECK(bn.run(cur, err), err != MSB_OK ? err : MSB_EINVAL, "tuned configuration rejected");
     *best_ms = bn.total();
@@ -302,6 +329,7 @@ extern "C" msb_status msb_plan_set_config(msb_plan p, msb_precision prec, const 
     const bool f32 = prec == MSB_FP32;
     MSB_TRY(check_config(p, f32, *cfg));
     msb_status s = set_schedules(p, f32, cfg->max_radix);
+    if (s == MSB_OK) s = ensure_tiles(p, cfg->tile);
     if (s != MSB_OK) {
         (void)set_schedules(p, f32, p->cfg[f32].max_radix);
         return s;

@@ -31,7 +31,7 @@ def _check_apply(plan, w, prec, label):
     assert err <= (FP64_TOL if prec == "fp64" else FP32_TOL)
 
 
-def _random_configs(rng, count):
+def _random_configs(rng, count, dim=2):
     out = []
     for _ in range(count):
         out.append(dict(rows_per_wg=int(rng.choice([1, 2, 3, 4, 5, 8, 16])), team_x=int(rng.integers(2)),
@@ -39,7 +39,9 @@ def _random_configs(rng, count):
                         threads_x=64 * int(rng.integers(1, 9)), lines_per_wg=int(rng.choice([1, 2, 3, 5, 8, 16])),
                         team_line=int(rng.integers(2)), lines_per_wave=int(rng.integers(1, 9)),
                         threads_line=64 * int(rng.integers(1, 9)), max_radix=int(rng.choice([4, 8, 16])),
-                        lds_inplace=int(rng.choice([0, 0, 1, 2, 3]))))
+                        lds_inplace=int(rng.choice([0, 0, 1, 2, 3])),
+                        tile=int(rng.choice([0, 0, 16, 24, 40])) if dim == 2 else 0,
+                        threads_tile=64 * int(rng.integers(1, 9))))
     return out
 
 
@@ -56,7 +58,7 @@ def test_random_launch_configs_match_oracle(prec, dim):
     plan = gpu_plan(w)
     rng = np.random.default_rng(83 + dim)
     accepted = 0
-    for cfg in _random_configs(rng, 24):
+    for cfg in _random_configs(rng, 24, dim):
         try:
             plan.set_config(prec, **cfg)
         except msb.MsbError as e:
