@@ -39,6 +39,62 @@ def pass_bytes(n, L, d, s):
     return [d * N * s + half, 2 * half + 3 * H * Ly * s, half + d * N * s]
 
 
+def tile_bytes(n, d, s, tl, nb=1):
+    """Algorithmic HBM bytes of one launch of the tiled single-pass product over nb cases:
+    read u and write f (d N reals each per case), the constraint mask (d N bytes, shared),
+    the frame spectra (3 tl^2 reals, shared).  Halo re-reads of neighbouring blocks are
+    not algorithmic (they come from L2 when neighbouring blocks run on one XCD)."""
+    N = n[0] * n[1]
+    return nb * 2 * d * N * s + d * N + 3 * tl * tl * s
+
+
+def model_c_bytes_per_dof(n, M, d, s):
+    """Bytes per DOF that a global-embedding FFT product (three HBM passes in 2D) must
+    move: s (2 d N + 3 H Ly + 16 H Ny) / (d N) with L the smallest 5-smooth length
+    >= N + M per axis and H = Lx / 2 + 1; the reference figure for the primary
+    roofline fraction GDOF/s x bytes per DOF / peak."""
+    def smooth(x):
+        while True:
+            m = x
+            for q in (2, 3, 5):
+                while m % q == 0:
+                    m //= q
+            if m == 1:
+                return x
+            x += 1
+    Lx, Ly = smooth(n[0] + M), smooth(n[1] + M)
+    H = Lx // 2 + 1
+    N = n[0] * n[1]
+    return s * (2 * d * N + 3 * H * Ly + 16 * H * n[1]) / (d * N)
+
+
+def product_kernels(plan, prec, n, L, d, s, nb=1):
+    """Names and algorithmic bytes per launch of the kernels of one product at the plan's
+    configuration: the tiled single-pass kernel, or the three passes of the chain."""
+    c = plan.get_config(prec)
+    if c["tile"] > 0:
+        return ["tile_product"], [tile_bytes(n, d, s, c["tile"], nb)]
+    pb = [nb * x for x in pass_bytes(n, L, d, s)]
+    pb[1] -= (nb - 1) * 3 * (L[0] // 2 + 1) * L[1] * s      # spectra are read once per launch
+    return ["x_forward", "y_line_product", "x_inverse"], pb
+
+
+def kernel_key(plan, prec, name, n, M, nb=1):
+    """The counter summary's key of a product kernel: short name @ workgroups."""
+    c = plan.get_config(prec)
+    t = "double" if prec == "fp64" else "float"
+    if name == "tile_product":
+        inner = c["tile"] - 2 * M
+        tiles = nb * (-(-n[0] // inner)) * (-(-n[1] // inner))
+        return "%s<%s>@%d" % ("k_tile_reg" if c["tile_regs"] else "k_tile", t, tiles)
+    L = plan.padded_lengths
+    wave = c["team_line"] == 1 if name == "y_line_product" else c["team_x"] == 1
+    ngroups = (-(-(L[0] // 2 + 1) // c["lines_per_wg"]) if name == "y_line_product"
+               else -(-n[1] // c["rows_per_wg"]))
+    return "%s<%s%s>@%d" % ({"x_forward": "k_xfwd", "y_line_product": "k_line_y", "x_inverse": "k_xinv"}[name],
+                            t, ",wave" if wave else "", nb * ngroups)
+
+
 def load_traffic(path, kernel):
     """HBM traffic per launch (bytes) of `kernel` from a committed rocprofv3 counter
     summary, or None when absent or taken on a different kernel source."""
@@ -63,6 +119,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-tolerance runs")
+    ap.add_argument("--no-copy-bw", action="store_true",
+                    help="skip the 1 GiB copy-bandwidth measurement (counter runs: the 64 MiB copy alone "
+                         "calibrates FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "32")),
                     help="CG iterations per hipGraph launch in the solves (0: plain launches)")
@@ -169,32 +228,34 @@ def main():
 
     wall32, ev_ms32 = timed(u32, f32, args.steps, args.warmup, G)
 
-    # per-kernel durations (HIP events recorded between the kernels on this stream)
-    names = ["x_forward", "y_line_product", "x_inverse"]
+    # per-kernel durations (HIP events recorded around the kernels on this stream)
+    names, pb = product_kernels(plan, "fp64", w.n, L, 2, 8)
+    names32, pb32 = product_kernels(plan, "fp32", w.n, L, 2, 4)
     kms = plan.profile_apply(u64, f64, nrep=max(50, args.steps // 2))
     kms32 = plan.profile_apply(u32, f32, nrep=max(50, args.steps // 2))
-    pb = pass_bytes(w.n, L, 2, 8)
-    pb32 = pass_bytes(w.n, L, 2, 4)
     dom = int(np.argmax(kms))
     achieved = pb[dom] / (kms[dom] * 1e-3) / 1e9
     # the counter summary keys kernels by name and workgroup count (tells this plan's
     # launches from the 16-case plan's)
-    c64 = plan.get_config("fp64")
-    wave = c64["team_line"] == 1 if names[dom] == "y_line_product" else c64["team_x"] == 1
-    ngroups = (-(-(L[0] // 2 + 1) // c64["lines_per_wg"]) if names[dom] == "y_line_product"
-               else -(-w.n[1] // c64["rows_per_wg"]))
-    kname = "%s<double%s>@%d" % ({"x_forward": "k_xfwd", "y_line_product": "k_line_y",
-                                   "x_inverse": "k_xinv"}[names[dom]], ",wave" if wave else "", ngroups)
+    kname = kernel_key(plan, "fp64", names[dom], w.n, w.M)
     traffic = load_traffic(os.path.join(ROOT, "profiles", "plate512_fp64_hbm_counters.txt"), kname)
+    bpd_c = model_c_bytes_per_dof(w.n, w.M, 2, 8)
     roofline = {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "bytes_per_launch": pb[dom], "ms_per_launch": round(kms[dom], 5)}
+                "traffic": traffic, "traffic_kind": "L2-fabric bytes per launch (rocprofv3 FETCH_SIZE + "
+                                                    "WRITE_SIZE, calibrated with a plain copy)",
+                "bytes_per_launch": pb[dom], "ms_per_launch": round(kms[dom], 5), "counter_key": kname,
+                "bytes_model": ("read u + write f + frame spectra + constraint mask" if names[dom] == "tile_product"
+                                else "the pass's reads and writes of the global-embedding chain"),
+                "primary_frac_model_c": {"B_per_DOF": round(bpd_c, 2),
+                                         "frac": None}}
     chain_ms = float(sum(kms))
     chain = {"bytes_per_matvec": sum(pb), "kernel_ms_sum": round(chain_ms, 5),
              "achieved_GBs": round(sum(pb) / (chain_ms * 1e-3) / 1e9, 1),
              "frac": round(sum(pb) / (chain_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "event_ms_per_matvec": round(ev_ms, 5)}
 
+    roofline["primary_frac_model_c"]["frac"] = round(value * bpd_c / HBM_PEAK_GBS, 4)
     line = {
         "metric": "BTTB PD matvec GDOF/s (%HBM roofline); CG time-to-1e-10, FP32-refined vs FP64",
         "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
@@ -213,7 +274,7 @@ def main():
         "chain": chain,
         "tuning": tuning,
         "fp32": {"GDOF_s": round(dofs * args.steps / wall32 / 1e9, 3),
-                 "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kms32)},
+                 "kernels_ms": {n: round(float(t), 5) for n, t in zip(names32, kms32)},
                  "chain_frac": round(sum(pb32) / (float(sum(kms32)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
 
@@ -239,13 +300,12 @@ def main():
     torch.cuda.synchronize()
     sb = (time.perf_counter() - t0) / 50
     kb = pb16.profile_apply(ub, fb, nrep=20)
-    Lb = pb16.padded_lengths
-    bb = [nb * x for x in pass_bytes(w.n, Lb, 2, 8)]
-    bb[1] -= (nb - 1) * 3 * (Lb[0] // 2 + 1) * Lb[1] * 8      # spectra are read once per launch
+    names16, bb = product_kernels(pb16, "fp64", w.n, pb16.padded_lengths, 2, 8, nb)
     db = int(np.argmax(kb))
     line["batch16_fp64"] = {"GDOF_s": round(nb * dofs / sb / 1e9, 3), "ms_per_matvec": round(1e3 * sb, 4),
-                            "kernels_ms": {n: round(float(t), 5) for n, t in zip(names, kb)},
-                            "dominant": names[db],
+                            "kernels_ms": {n: round(float(t), 5) for n, t in zip(names16, kb)},
+                            "counter_key": kernel_key(pb16, "fp64", names16[db], w.n, w.M, nb),
+                            "dominant": names16[db],
                             "dominant_frac": round(bb[db] / (kb[db] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                             "chain_frac": round(sum(bb) / (float(sum(kb)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     pb16.close()
@@ -260,20 +320,22 @@ def main():
     del src, dst
     # the bandwidth a plain device copy reaches on this GPU (1 GiB read + 1 GiB written per
     # copy, far beyond the 256 MB Infinity Cache), beside the 8 TB/s peak the fractions use
-    src = torch.empty(128 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(10):
+    if not args.no_copy_bw:
+        src = torch.empty(128 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
         dst.copy_(src)
-    ev1.record()
-    torch.cuda.synchronize()
-    copy_s = ev0.elapsed_time(ev1) / 10 * 1e-3
-    line["hbm_copy"] = {"GB_s": round(2 * src.numel() * 8 / copy_s / 1e9, 1), "bytes_per_copy": 2 * src.numel() * 8,
-                        "frac_of_peak": round(2 * src.numel() * 8 / copy_s / 1e9 / HBM_PEAK_GBS, 4)}
-    del src, dst
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        copy_s = ev0.elapsed_time(ev1) / 10 * 1e-3
+        line["hbm_copy"] = {"GB_s": round(2 * src.numel() * 8 / copy_s / 1e9, 1),
+                            "bytes_per_copy": 2 * src.numel() * 8,
+                            "frac_of_peak": round(2 * src.numel() * 8 / copy_s / 1e9 / HBM_PEAK_GBS, 4)}
+        del src, dst
 
     if not args.no_cg:
         b = torch.from_numpy(w.b).cuda()

@@ -301,6 +301,12 @@ msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds
  *                   the solvers and plan groups always use the global chain.
  *   threads_tile    threads per workgroup of the tiled product, multiple of 64,
  *                   64..512
+ *   tile_regs       0: the tiled product's frame transforms run as LDS Stockham
+ *                   stages (any tile above); 1: tile 16, 32 or 64 only, each thread
+ *                   keeps R points of a line in registers (tile = R S: 4 x 4, 8 x 4,
+ *                   8 x 8) and a 1D transform is a radix-R butterfly, one LDS exchange
+ *                   and R / S radix-S butterflies; the workgroup has S tile threads
+ *                   (threads_tile is not used)
  *   lds_inplace     bit 0: x passes, bit 1: line passes; a set bit runs every
  *                   Stockham stage in place (each thread reads its butterflies
  *                   into registers, a barrier, then it writes them back into the
@@ -319,6 +325,7 @@ typedef struct {
     int max_radix;
     int lds_inplace;
     int tile, threads_tile;
+    int tile_regs;
 } msb_launch_config;
 
 msb_status msb_plan_get_config(msb_plan plan, msb_precision prec, msb_launch_config *cfg);

@@ -15,7 +15,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libmsbfm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "passes.hip", "solver.hip", "tune.hip", "crack.hip"]
+SOURCES = ["plan.cpp", "passes.hip", "tile.hip", "solver.hip", "tune.hip", "crack.hip"]
 
 # gfx950 only; packed-FP32 instructions disabled (they are generated from plain float code
 # otherwise).

@@ -1,0 +1,84 @@
+// The fused solver epilogue of the product kernels (shared by the x-inverse pass of
+// the chain and the tiled single-pass product).
+#pragma once
+
+#include "passes.hpp"
+
+namespace msb {
+
+// The fused epilogue at one DOF: f = (A u) at addr (corrections applied), fx = the DOF
+// is constrained; pa_idx indexes the per-case array e.pa (the ADR density).
+template <typename T>
+__device__ __forceinline__ void epilogue_at(const EndArgs<T> &e, const T *__restrict__ uin, size_t addr, size_t pa_idx,
+                                            T f, bool fx, T sign, T rinv, T dth, double &acc0, double &acc1,
+                                            double &acc2) {
+    switch (e.epi) {
+        case EPI_APPLY:
+            e.out[addr] = fx ? T(0) : sign * f;
+            break;
+        case EPI_CG_Q: {
+            const T q = fx ? T(0) : -f;
+            e.out[addr] = q;
+            const double qd = (double)q;
+            acc0 += (double)uin[addr] * qd;
+            acc1 += (double)e.rhs[addr] * qd;
+            acc2 += qd * qd;
+            break;
+        }
+        case EPI_PCG_Z: {
+            const T z = fx ? T(0) : sign * f;
+            e.out[addr] = z;
+            acc0 += (double)uin[addr] * (double)z;
+            break;
+        }
+        case EPI_ADR: {
+            // F = f + b; K1 = -(F - F_prev) / (D v) where v != 0 (the local
+            // stiffness of the adaptive damping); sums u.K1.u and u.u
+            if (fx) {
+                e.out[addr] = T(0);
+                break;
+            }
+            const T Fn = f + e.rhs[addr];
+            if (e.part) {   // no partials on the first evaluation (no previous F)
+                const double uu = (double)uin[addr];
+                const double vv = (double)e.ev[addr];
+                if (vv != 0.0) {
+                    const double Dd = (double)e.pa[pa_idx];
+                    acc0 += uu * uu * (-((double)Fn - (double)e.out[addr]) / (Dd * vv));
+                }
+                acc1 += uu * uu;
+            }
+            e.out[addr] = Fn;
+            break;
+        }
+        case EPI_RESID: {
+            const T v = fx ? T(0) : e.rhs[addr] + f;
+            e.out[addr] = v;
+            acc0 += (double)v * (double)v;
+            break;
+        }
+        case EPI_VV: {
+            T an = T(0), vn = T(0);
+            const T bb = e.rhs[addr];
+            if (!fx) {
+                an = (f + bb) * rinv;
+                vn = e.ev[addr] + dth * (e.ea[addr] + an);
+                if (e.energy) {
+                    const double uu = (double)uin[addr];
+                    acc0 += uu * (double)f;
+                    acc1 += (double)vn * (double)vn;
+                    acc2 += (double)bb * uu;
+                }
+            }
+            e.ea[addr] = an;
+            e.ev[addr] = vn;
+            break;
+        }
+        default:  // EPI_DOT
+            if (!fx) acc0 += (double)e.rhs[addr] * (double)f;
+            break;
+    }
+}
+
+
+}  // namespace msb

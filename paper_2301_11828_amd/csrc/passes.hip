@@ -16,6 +16,7 @@
 // on the grid (the kernel's support is +-M), so only the N first outputs are kept.
 #include <cstring>
 
+#include "epilogue.hpp"
 #include "fft_device.hpp"
 #include "passes.hpp"
 
@@ -592,80 +593,6 @@ __device__ __forceinline__ void yinv_body(const PassArgs<T> &a, const EndArgs<T>
     }
 }
 
-// The fused epilogue at one DOF: f = (A u) at addr (corrections applied), fx = the DOF
-// is constrained; pa_idx indexes the per-case array e.pa (the ADR density).
-template <typename T>
-__device__ __forceinline__ void epilogue_at(const EndArgs<T> &e, const T *__restrict__ uin, size_t addr, size_t pa_idx,
-                                            T f, bool fx, T sign, T rinv, T dth, double &acc0, double &acc1,
-                                            double &acc2) {
-    switch (e.epi) {
-        case EPI_APPLY:
-            e.out[addr] = fx ? T(0) : sign * f;
-            break;
-        case EPI_CG_Q: {
-            const T q = fx ? T(0) : -f;
-            e.out[addr] = q;
-            const double qd = (double)q;
-            acc0 += (double)uin[addr] * qd;
-            acc1 += (double)e.rhs[addr] * qd;
-            acc2 += qd * qd;
-            break;
-        }
-        case EPI_PCG_Z: {
-            const T z = fx ? T(0) : sign * f;
-            e.out[addr] = z;
-            acc0 += (double)uin[addr] * (double)z;
-            break;
-        }
-        case EPI_ADR: {
-            // F = f + b; K1 = -(F - F_prev) / (D v) where v != 0 (the local
-            // stiffness of the adaptive damping); sums u.K1.u and u.u
-            if (fx) {
-                e.out[addr] = T(0);
-                break;
-            }
-            const T Fn = f + e.rhs[addr];
-            if (e.part) {   // no partials on the first evaluation (no previous F)
-                const double uu = (double)uin[addr];
-                const double vv = (double)e.ev[addr];
-                if (vv != 0.0) {
-                    const double Dd = (double)e.pa[pa_idx];
-                    acc0 += uu * uu * (-((double)Fn - (double)e.out[addr]) / (Dd * vv));
-                }
-                acc1 += uu * uu;
-            }
-            e.out[addr] = Fn;
-            break;
-        }
-        case EPI_RESID: {
-            const T v = fx ? T(0) : e.rhs[addr] + f;
-            e.out[addr] = v;
-            acc0 += (double)v * (double)v;
-            break;
-        }
-        case EPI_VV: {
-            T an = T(0), vn = T(0);
-            const T bb = e.rhs[addr];
-            if (!fx) {
-                an = (f + bb) * rinv;
-                vn = e.ev[addr] + dth * (e.ea[addr] + an);
-                if (e.energy) {
-                    const double uu = (double)uin[addr];
-                    acc0 += uu * (double)f;
-                    acc1 += (double)vn * (double)vn;
-                    acc2 += (double)bb * uu;
-                }
-            }
-            e.ea[addr] = an;
-            e.ev[addr] = vn;
-            break;
-        }
-        default:  // EPI_DOT
-            if (!fx) acc0 += (double)e.rhs[addr] * (double)f;
-            break;
-    }
-}
-
 // ---------------------------------------------------------------------------- x-inverse
 // Slots as in the x-forward pass.  Each slot's full x-spectrum is rebuilt from the
 // half spectra of its two real rows, transformed back, then the broken-bond
@@ -919,195 +846,6 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
     }
 }
 
-// ---------------------------------------------------------------------------- tiled product (2D)
-// Overlap-save form of the Toeplitz product: A_hat u at node p is the correlation
-// sum_o K(o) u(p + o) over |o_a| <= M, u = 0 outside the grid (the zero embedding of
-// Sec. 3.3).  A block of T x T nodes (T = tl - 2M) therefore needs u only on that block
-// grown by M on every side: a tl x tl patch.  Its cyclic product with the generating
-// array wrapped to tl x tl (Alg. 3 on the patch) differs from the linear one only where
-// the kernel wraps around, within M of the patch edge; the inner T x T outputs are exact.
-//
-// The two displacement components go into one complex signal z = u_x + i u_y.  With
-// Z = FFT(z), Ux = (Z(k) + conj Z(-k)) / 2 and Uy = (Z(k) - conj Z(-k)) / 2i, and the real
-// even spectra Gxx, Gxy, Gyy, the block product written back as one complex signal
-// w = f_x + i f_y is
-//     W(k) = (Gxx + Gyy)/2 Z(k) + ((Gxx - Gyy)/2 + i Gxy) conj Z(-k),
-// so a patch costs one forward and one inverse complex 2D transform in LDS (rows, then
-// columns; the inverse only for the T inner rows at the end).  Then D^f, the surface
-// correction and D^e are added on the inner block in LDS, and the mask and fused
-// epilogue write the outputs: u is read once (plus the halo, from L2) and f written once.
-template <typename T, int RMAX>
-__device__ __forceinline__ void tile_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
-    using T2 = cplx_t<T>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[96];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int Lt = a.tl, M = a.M, Tt = Lt - 2 * M;
-    const int P = Lt | 1;                      // odd row pitch: conflict-free row and column stages
-    const int tpc = a.ttx * a.tty;
-    const int b = tile / tpc;
-    const int rem = tile - b * tpc;
-    const int ty = rem / a.ttx, tx = rem - ty * a.ttx;
-    const int x0 = tx * Tt, y0 = ty * Tt;      // first inner node of the block
-    const int nx = min(Tt, a.Nx - x0), ny = min(Tt, a.Ny - y0);   // inner nodes inside the grid
-    T2 *tw = reinterpret_cast<T2 *>(smem);
-    T2 *bufA = tw + Lt;
-    T2 *bufB = bufA + (size_t)Lt * P;
-    if (e.case_done && e.case_done[b]) return;
-    stage_twiddles(tw, a.twt, Lt, tid, nt);
-    const int N = a.N, Nx = a.Nx, Ny = a.Ny;
-    const size_t cbase = (size_t)b * 2 * N;
-    const T *uin = e.uin;
-    {
-        // patch node (lx, ly) = grid node (x0 - M + lx, y0 - M + ly); consecutive threads on
-        // consecutive lx (contiguous in u and in LDS)
-        const uint32_t mL = 0xFFFFFFFFu / (uint32_t)Lt + 1u;
-        const T *ux = uin + cbase, *uy = ux + N;
-        for (int i = tid; i < Lt * Lt; i += nt) {
-            const int ly = (int)fdiv((uint32_t)i, mL), lx = i - ly * Lt;
-            const int gx = x0 - M + lx, gy = y0 - M + ly;
-            T2 z;
-            z.x = T(0);
-            z.y = T(0);
-            if (gx >= 0 && gx < Nx && gy >= 0 && gy < Ny) {
-                const size_t q = (size_t)gy * Nx + gx;
-                z.x = ux[q];
-                z.y = uy[q];
-            }
-            bufA[ly * P + lx] = z;
-        }
-    }
-    __syncthreads();
-    // forward: rows (signals P apart, elements adjacent), then columns
-    T2 *r = fft_lds_2d<T, T2, -1, RMAX>(bufA, bufB, Lt, P, 1, a.stl, tw, tid, nt);
-    T2 *o = r == bufA ? bufB : bufA;
-    r = fft_lds_2d<T, T2, -1, RMAX>(r, o, Lt, 1, P, a.stl, tw, tid, nt);
-    o = r == bufA ? bufB : bufA;
-    {
-        const T *g = a.tspec + (size_t)b * a.tspec_slot;
-        const size_t n2 = (size_t)Lt * Lt;
-        const uint32_t mL = 0xFFFFFFFFu / (uint32_t)Lt + 1u;
-        for (int i = tid; i < Lt * Lt; i += nt) {
-            const int ky = (int)fdiv((uint32_t)i, mL), kx = i - ky * Lt;
-            const int mky = ky ? Lt - ky : 0, mkx = kx ? Lt - kx : 0;
-            const T2 Z = r[ky * P + kx], Zm = r[mky * P + mkx];
-            const T ga = g[i], gr = g[n2 + i], gi = g[2 * n2 + i];
-            T2 W;
-            W.x = ga * Z.x + gr * Zm.x + gi * Zm.y;
-            W.y = ga * Z.y + gi * Zm.x - gr * Zm.y;
-            o[ky * P + kx] = W;
-        }
-    }
-    __syncthreads();
-    // inverse: columns, then only the inner rows M .. M + T - 1
-    r = fft_lds_2d<T, T2, 1, RMAX>(o, r, Lt, 1, P, a.stl, tw, tid, nt);
-    o = r == bufA ? bufB : bufA;
-    r = fft_lds_2d<T, T2, 1, RMAX>(r + M * P, o + M * P, Tt, P, 1, a.stl, tw, tid, nt);
-    T2 *res = r + M;   // r starts at patch row M: inner node (jx, jy) at res[jy * P + jx], f_x + i f_y
-    const T *wt = a.w + (size_t)b * a.w_slot;
-    // broken bonds (eq. (tea:fr)): the Omega_br nodes of the block's rows are contiguous in
-    // the per-row lists; f_p += sum_q W(q - p) (u_p - u_q) (with the surface correction a
-    // bond of an Omega_e row carries v_pq W)
-    if (a.br_row_ptr && ny > 0) {
-        const int e0 = a.br_row_ptr[y0], e1 = a.br_row_ptr[y0 + ny];
-        for (int ei = e0 + tid; ei < e1; ei += nt) {
-            const int node = a.br_node_i[ei];
-            const int gy = node / Nx, gx = node - gy * Nx;
-            if (gx < x0 || gx >= x0 + nx) continue;
-            const bool on_e = a.nu && (gx < M || gx >= Nx - M || gy < M || gy >= Ny - M);
-            const double nup = on_e ? (double)a.nu[node] : 0.0;
-            const double upx = (double)uin[cbase + node], upy = (double)uin[cbase + N + node];
-            double fxa = 0.0, fya = 0.0;
-            for (int t0 = a.br_bond_ptr[ei], t1 = a.br_bond_ptr[ei + 1]; t0 < t1; ++t0) {
-                const int q = a.br_q[t0], oi = a.br_off[t0];
-                const double dx = upx - (double)uin[cbase + q], dy = upy - (double)uin[cbase + N + q];
-                const double wxx = (double)wt[oi], wxy = (double)wt[a.n_off + oi], wyy = (double)wt[2 * a.n_off + oi];
-                const double v = on_e ? 0.5 * (nup + (double)a.nu[q]) : 1.0;
-                fxa += v * (wxx * dx + wxy * dy);
-                fya += v * (wxy * dx + wyy * dy);
-            }
-            T2 &f = res[(gy - y0) * P + (gx - x0)];
-            f.x += T(fxa);
-            f.y += T(fya);
-        }
-        __syncthreads();
-    }
-    // nodes within M of a face (Omega_e): the surface correction (Remark 3, eq. (scr)) and
-    // the incomplete-horizon diagonal D^e (eq. (tea:sc), table by clamped face distances)
-    const bool edge = x0 < M || x0 + nx > Nx - M || y0 < M || y0 + ny > Ny - M;
-    if (edge) {
-        const T *de = a.de + (size_t)b * a.de_slot;
-        const int M1 = M + 1;
-        const uint32_t mT = 0xFFFFFFFFu / (uint32_t)Tt + 1u;
-        for (int i = tid; i < Tt * Tt; i += nt) {
-            const int jy = (int)fdiv((uint32_t)i, mT), jx = i - jy * Tt;
-            if (jx >= nx || jy >= ny) continue;
-            const int gx = x0 + jx, gy = y0 + jy;
-            const int lx = min(gx, M), hx = min(Nx - 1 - gx, M), ly = min(gy, M), hy = min(Ny - 1 - gy, M);
-            if ((lx == M) & (hx == M) & (ly == M) & (hy == M)) continue;   // full horizon
-            const int node = gy * Nx + gx;
-            const T upx = uin[cbase + node], upy = uin[cbase + N + node];
-            T2 &f = res[jy * P + jx];
-            if (a.nu) {
-                const double nup = (double)a.nu[node];
-                double ax = 0.0, ay = 0.0;
-                for (int oi = 0; oi < a.n_off; ++oi) {
-                    const int ox = a.offs[3 * oi], oy = a.offs[3 * oi + 1];
-                    const int xx = gx + ox, yy = gy + oy;
-                    if (xx < 0 || xx >= Nx || yy < 0 || yy >= Ny) continue;
-                    const int q = node + oy * Nx + ox;
-                    const double dx = (double)uin[cbase + q] - (double)upx, dy = (double)uin[cbase + N + q] - (double)upy;
-                    const double vm = 0.5 * (nup + (double)a.nu[q]) - 1.0;
-                    ax += vm * ((double)wt[oi] * dx + (double)wt[a.n_off + oi] * dy);
-                    ay += vm * ((double)wt[a.n_off + oi] * dx + (double)wt[2 * a.n_off + oi] * dy);
-                }
-                f.x += T(ax);
-                f.y += T(ay);
-            }
-            const int dx = ((lx * M1 + hx) * M1 + ly) * M1 + hy;
-            const T dxx = de[dx], dxy = de[a.de_stride + dx], dyy = de[2 * a.de_stride + dx];
-            f.x += dxx * upx + dxy * upy;
-            f.y += dxy * upx + dyy * upy;
-        }
-        __syncthreads();
-    }
-    // mask and fused epilogue: both components of a node in one thread
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    {
-        const T dth = T(0.5 * e.dt);
-        const T rinv = T(1.0 / e.rho);
-        const T sign = T(e.sign);
-        const uint32_t mT = 0xFFFFFFFFu / (uint32_t)Tt + 1u;
-        for (int i = tid; i < Tt * Tt; i += nt) {
-            const int jy = (int)fdiv((uint32_t)i, mT), jx = i - jy * Tt;
-            if (jx >= nx || jy >= ny) continue;
-            const size_t node = (size_t)(y0 + jy) * Nx + (x0 + jx);
-            const T2 f = res[jy * P + jx];
-            const size_t ax = cbase + node, ay = ax + N;
-            const bool fxx = a.fixed && a.fixed[node], fxy = a.fixed && a.fixed[N + node];
-            epilogue_at<T>(e, uin, ax, ax - cbase + (size_t)b * e.pa_stride, f.x, fxx, sign, rinv, dth, acc0, acc1,
-                           acc2);
-            epilogue_at<T>(e, uin, ay, ay - cbase + (size_t)b * e.pa_stride, f.y, fxy, sign, rinv, dth, acc0, acc1,
-                           acc2);
-        }
-    }
-    if (e.part) {
-        double v[3] = {acc0, acc1, acc2};
-        block_sum<3>(v, red, tid, nt);
-        if (tid == 0) {
-            const size_t stride = (size_t)ntiles;
-            e.part[tile] = v[0];
-            e.part[stride + tile] = v[1];
-            e.part[2 * stride + tile] = v[2];
-        }
-    }
-}
-
-template <typename T, int RMAX>
-__global__ __launch_bounds__(kMaxBlock) void k_tile(PassArgs<T> a, EndArgs<T> e) {
-    tile_body<T, RMAX>(a, e, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
-}
-
 // ---------------------------------------------------------------------------- kernels
 // Single-plan launches: the grid is the plan's tiles, remapped so that the blocks of
 // one XCD take a contiguous tile range.  Group launches: one grid over the tiles of
@@ -1211,6 +949,7 @@ msb_launch_config default_config(const msb_plan_s *p, bool fp32) {
     c.lds_inplace = 0;
     c.tile = 0;
     c.threads_tile = 256;
+    c.tile_regs = 0;
     return c;
 }
 
@@ -1291,6 +1030,9 @@ msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config 
         const size_t lt = lds_tile_bytes(c.tile, cb);
         MSB_CHECK(lt <= kLdsMax, MSB_EINVAL, "tile %d needs %zu bytes of LDS per workgroup (max %zu)", c.tile, lt, kLdsMax);
     }
+    MSB_CHECK(c.tile_regs == 0 || c.tile_regs == 1, MSB_EINVAL, "tile_regs %d: need 0 or 1", c.tile_regs);
+    MSB_CHECK(!c.tile_regs || c.tile == 16 || c.tile == 32 || c.tile == 64, MSB_EINVAL,
+              "tile_regs = 1 needs tile 16, 32 or 64 (got %d)", c.tile);
     return MSB_OK;
 }
 
@@ -1373,6 +1115,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.br_off = p->br_off;
     a.ept = (a.rows + a.F - 1) / a.F;
     a.tl = a.ttx = a.tty = 0;
+    a.treg = 0;
     a.tthreads = c.threads_tile;
     a.twt = nullptr;
     a.tspec = nullptr;
@@ -1393,6 +1136,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
             a.tspec = sel<T>(ts->s64, ts->s32);
             a.tspec_slot = multi ? (size_t)3 * c.tile * c.tile : 0;
             a.ept = a.ttx * a.tty;
+            a.treg = c.tile_regs;
         }
     }
     return a;
@@ -1515,14 +1259,7 @@ static msb_status launch_tiled(const PassArgs<T> &a, const EndArgs<T> &e, hipStr
         else launch_prologue<T, true>(a, e, st);
     }
     if (ev) MSB_HIP(hipEventRecord(ev[0], st));
-    const dim3 grid(a.B * a.ttx * a.tty), block(a.tthreads);
-    if (comp) {
-        MSB_HIP(allow_lds(k_tile<T, 16>, lds));
-        for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile<T, 16>), grid, block, lds, st, a, e);
-    } else {
-        MSB_HIP(allow_lds(k_tile<T, 8>, lds));
-        for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile<T, 8>), grid, block, lds, st, a, e);
-    }
+    MSB_HIP(launch_tile_kernel<T>(a, e, lds, comp, reps, st));
     if (ev) MSB_HIP(hipEventRecord(ev[1], st));
     MSB_HIP(hipGetLastError());
     return MSB_OK;

@@ -74,6 +74,7 @@ template <typename T> struct PassArgs {
     // schedule and twiddles, and the frame spectra [slots][3][tl][tl] ((Gxx+Gyy)/2,
     // (Gxx-Gyy)/2, Gxy of the generating array wrapped to tl x tl, scaled by 1/tl^2)
     int tl, ttx, tty, tthreads;
+    int treg;            // 1: the register-resident frame kernel (tl = 16, 32 or 64)
     FftSched stl;
     const cplx_t<T> *twt;
     const T *tspec;
@@ -147,6 +148,12 @@ template <typename T> struct EndArgs {
 template <typename T>
 msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t s,
                           hipEvent_t *ev = nullptr, int reps = 1);
+// The tiled single-pass 2D product kernel over B x ttx x tty tiles (tile.hip): lds
+// dynamic bytes per workgroup, composite: the frame schedule uses a composite radix;
+// launched reps times back to back (reps > 1: measurement only).
+template <typename T>
+hipError_t launch_tile_kernel(const PassArgs<T> &a, const EndArgs<T> &e, size_t lds, bool composite, int reps,
+                              hipStream_t st);
 inline int n_passes(int dim) { return dim == 2 ? 3 : 5; }
 // Kernels a product launch times: the chain's passes, or the one tiled kernel.
 template <typename T> inline int n_passes(const PassArgs<T> &a) { return a.tl > 0 ? 1 : n_passes(a.d); }

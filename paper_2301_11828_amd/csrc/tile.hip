@@ -1,0 +1,513 @@
+// The tiled single-pass 2D product: one launch computes f = A u = A_hat u + D^e u +
+// D^f u on blocks of the grid, each from an LDS-resident patch of u (the overlap-save
+// form of Alg. 3), with the corrections, the constraint mask and the fused solver
+// epilogues applied before the one store of f.
+#include "epilogue.hpp"
+#include "fft_device.hpp"
+#include "passes.hpp"
+
+namespace msb {
+
+// Overlap-save form of the Toeplitz product: A_hat u at node p is the correlation
+// sum_o K(o) u(p + o) over |o_a| <= M, u = 0 outside the grid (the zero embedding of
+// Sec. 3.3).  A block of T x T nodes (T = tl - 2M) therefore needs u only on that block
+// grown by M on every side: a tl x tl patch.  Its cyclic product with the generating
+// array wrapped to tl x tl (Alg. 3 on the patch) differs from the linear one only where
+// the kernel wraps around, within M of the patch edge; the inner T x T outputs are exact.
+//
+// The two displacement components go into one complex signal z = u_x + i u_y.  With
+// Z = FFT(z), Ux = (Z(k) + conj Z(-k)) / 2 and Uy = (Z(k) - conj Z(-k)) / 2i, and the real
+// even spectra Gxx, Gxy, Gyy, the block product written back as one complex signal
+// w = f_x + i f_y is
+//     W(k) = (Gxx + Gyy)/2 Z(k) + ((Gxx - Gyy)/2 + i Gxy) conj Z(-k),
+// so a patch costs one forward and one inverse complex 2D transform in LDS (rows, then
+// columns; the inverse only for the T inner rows at the end).  Then D^f, the surface
+// correction and D^e are added on the inner block in LDS, and the mask and fused
+// epilogue write the outputs: u is read once (plus the halo, from L2) and f written once.
+template <typename T, int RMAX>
+__device__ __forceinline__ void tile_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
+    using T2 = cplx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[96];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int Lt = a.tl, M = a.M, Tt = Lt - 2 * M;
+    const int P = Lt | 1;                      // odd row pitch: conflict-free row and column stages
+    const int tpc = a.ttx * a.tty;
+    const int b = tile / tpc;
+    const int rem = tile - b * tpc;
+    const int ty = rem / a.ttx, tx = rem - ty * a.ttx;
+    const int x0 = tx * Tt, y0 = ty * Tt;      // first inner node of the block
+    const int nx = min(Tt, a.Nx - x0), ny = min(Tt, a.Ny - y0);   // inner nodes inside the grid
+    T2 *tw = reinterpret_cast<T2 *>(smem);
+    T2 *bufA = tw + Lt;
+    T2 *bufB = bufA + (size_t)Lt * P;
+    if (e.case_done && e.case_done[b]) return;
+    stage_twiddles(tw, a.twt, Lt, tid, nt);
+    const int N = a.N, Nx = a.Nx, Ny = a.Ny;
+    const size_t cbase = (size_t)b * 2 * N;
+    const T *uin = e.uin;
+    {
+        // patch node (lx, ly) = grid node (x0 - M + lx, y0 - M + ly); consecutive threads on
+        // consecutive lx (contiguous in u and in LDS)
+        const uint32_t mL = 0xFFFFFFFFu / (uint32_t)Lt + 1u;
+        const T *ux = uin + cbase, *uy = ux + N;
+        for (int i = tid; i < Lt * Lt; i += nt) {
+            const int ly = (int)fdiv((uint32_t)i, mL), lx = i - ly * Lt;
+            const int gx = x0 - M + lx, gy = y0 - M + ly;
+            T2 z;
+            z.x = T(0);
+            z.y = T(0);
+            if (gx >= 0 && gx < Nx && gy >= 0 && gy < Ny) {
+                const size_t q = (size_t)gy * Nx + gx;
+                z.x = ux[q];
+                z.y = uy[q];
+            }
+            bufA[ly * P + lx] = z;
+        }
+    }
+    __syncthreads();
+    // forward: rows (signals P apart, elements adjacent), then columns
+    T2 *r = fft_lds_2d<T, T2, -1, RMAX>(bufA, bufB, Lt, P, 1, a.stl, tw, tid, nt);
+    T2 *o = r == bufA ? bufB : bufA;
+    r = fft_lds_2d<T, T2, -1, RMAX>(r, o, Lt, 1, P, a.stl, tw, tid, nt);
+    o = r == bufA ? bufB : bufA;
+    {
+        const T *g = a.tspec + (size_t)b * a.tspec_slot;
+        const size_t n2 = (size_t)Lt * Lt;
+        const uint32_t mL = 0xFFFFFFFFu / (uint32_t)Lt + 1u;
+        for (int i = tid; i < Lt * Lt; i += nt) {
+            const int ky = (int)fdiv((uint32_t)i, mL), kx = i - ky * Lt;
+            const int mky = ky ? Lt - ky : 0, mkx = kx ? Lt - kx : 0;
+            const T2 Z = r[ky * P + kx], Zm = r[mky * P + mkx];
+            const T ga = g[i], gr = g[n2 + i], gi = g[2 * n2 + i];
+            T2 W;
+            W.x = ga * Z.x + gr * Zm.x + gi * Zm.y;
+            W.y = ga * Z.y + gi * Zm.x - gr * Zm.y;
+            o[ky * P + kx] = W;
+        }
+    }
+    __syncthreads();
+    // inverse: columns, then only the inner rows M .. M + T - 1
+    r = fft_lds_2d<T, T2, 1, RMAX>(o, r, Lt, 1, P, a.stl, tw, tid, nt);
+    o = r == bufA ? bufB : bufA;
+    r = fft_lds_2d<T, T2, 1, RMAX>(r + M * P, o + M * P, Tt, P, 1, a.stl, tw, tid, nt);
+    T2 *res = r + M;   // r starts at patch row M: inner node (jx, jy) at res[jy * P + jx], f_x + i f_y
+    const T *wt = a.w + (size_t)b * a.w_slot;
+    // broken bonds (eq. (tea:fr)): the Omega_br nodes of the block's rows are contiguous in
+    // the per-row lists; f_p += sum_q W(q - p) (u_p - u_q) (with the surface correction a
+    // bond of an Omega_e row carries v_pq W)
+    if (a.br_row_ptr && ny > 0) {
+        const int e0 = a.br_row_ptr[y0], e1 = a.br_row_ptr[y0 + ny];
+        for (int ei = e0 + tid; ei < e1; ei += nt) {
+            const int node = a.br_node_i[ei];
+            const int gy = node / Nx, gx = node - gy * Nx;
+            if (gx < x0 || gx >= x0 + nx) continue;
+            const bool on_e = a.nu && (gx < M || gx >= Nx - M || gy < M || gy >= Ny - M);
+            const double nup = on_e ? (double)a.nu[node] : 0.0;
+            const double upx = (double)uin[cbase + node], upy = (double)uin[cbase + N + node];
+            double fxa = 0.0, fya = 0.0;
+            for (int t0 = a.br_bond_ptr[ei], t1 = a.br_bond_ptr[ei + 1]; t0 < t1; ++t0) {
+                const int q = a.br_q[t0], oi = a.br_off[t0];
+                const double dx = upx - (double)uin[cbase + q], dy = upy - (double)uin[cbase + N + q];
+                const double wxx = (double)wt[oi], wxy = (double)wt[a.n_off + oi], wyy = (double)wt[2 * a.n_off + oi];
+                const double v = on_e ? 0.5 * (nup + (double)a.nu[q]) : 1.0;
+                fxa += v * (wxx * dx + wxy * dy);
+                fya += v * (wxy * dx + wyy * dy);
+            }
+            T2 &f = res[(gy - y0) * P + (gx - x0)];
+            f.x += T(fxa);
+            f.y += T(fya);
+        }
+        __syncthreads();
+    }
+    // nodes within M of a face (Omega_e): the surface correction (Remark 3, eq. (scr)) and
+    // the incomplete-horizon diagonal D^e (eq. (tea:sc), table by clamped face distances)
+    const bool edge = x0 < M || x0 + nx > Nx - M || y0 < M || y0 + ny > Ny - M;
+    if (edge) {
+        const T *de = a.de + (size_t)b * a.de_slot;
+        const int M1 = M + 1;
+        const uint32_t mT = 0xFFFFFFFFu / (uint32_t)Tt + 1u;
+        for (int i = tid; i < Tt * Tt; i += nt) {
+            const int jy = (int)fdiv((uint32_t)i, mT), jx = i - jy * Tt;
+            if (jx >= nx || jy >= ny) continue;
+            const int gx = x0 + jx, gy = y0 + jy;
+            const int lx = min(gx, M), hx = min(Nx - 1 - gx, M), ly = min(gy, M), hy = min(Ny - 1 - gy, M);
+            if ((lx == M) & (hx == M) & (ly == M) & (hy == M)) continue;   // full horizon
+            const int node = gy * Nx + gx;
+            const T upx = uin[cbase + node], upy = uin[cbase + N + node];
+            T2 &f = res[jy * P + jx];
+            if (a.nu) {
+                const double nup = (double)a.nu[node];
+                double ax = 0.0, ay = 0.0;
+                for (int oi = 0; oi < a.n_off; ++oi) {
+                    const int ox = a.offs[3 * oi], oy = a.offs[3 * oi + 1];
+                    const int xx = gx + ox, yy = gy + oy;
+                    if (xx < 0 || xx >= Nx || yy < 0 || yy >= Ny) continue;
+                    const int q = node + oy * Nx + ox;
+                    const double dx = (double)uin[cbase + q] - (double)upx, dy = (double)uin[cbase + N + q] - (double)upy;
+                    const double vm = 0.5 * (nup + (double)a.nu[q]) - 1.0;
+                    ax += vm * ((double)wt[oi] * dx + (double)wt[a.n_off + oi] * dy);
+                    ay += vm * ((double)wt[a.n_off + oi] * dx + (double)wt[2 * a.n_off + oi] * dy);
+                }
+                f.x += T(ax);
+                f.y += T(ay);
+            }
+            const int dx = ((lx * M1 + hx) * M1 + ly) * M1 + hy;
+            const T dxx = de[dx], dxy = de[a.de_stride + dx], dyy = de[2 * a.de_stride + dx];
+            f.x += dxx * upx + dxy * upy;
+            f.y += dxy * upx + dyy * upy;
+        }
+        __syncthreads();
+    }
+    // mask and fused epilogue: both components of a node in one thread
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    {
+        const T dth = T(0.5 * e.dt);
+        const T rinv = T(1.0 / e.rho);
+        const T sign = T(e.sign);
+        const uint32_t mT = 0xFFFFFFFFu / (uint32_t)Tt + 1u;
+        for (int i = tid; i < Tt * Tt; i += nt) {
+            const int jy = (int)fdiv((uint32_t)i, mT), jx = i - jy * Tt;
+            if (jx >= nx || jy >= ny) continue;
+            const size_t node = (size_t)(y0 + jy) * Nx + (x0 + jx);
+            const T2 f = res[jy * P + jx];
+            const size_t ax = cbase + node, ay = ax + N;
+            const bool fxx = a.fixed && a.fixed[node], fxy = a.fixed && a.fixed[N + node];
+            epilogue_at<T>(e, uin, ax, ax - cbase + (size_t)b * e.pa_stride, f.x, fxx, sign, rinv, dth, acc0, acc1,
+                           acc2);
+            epilogue_at<T>(e, uin, ay, ay - cbase + (size_t)b * e.pa_stride, f.y, fxy, sign, rinv, dth, acc0, acc1,
+                           acc2);
+        }
+    }
+    if (e.part) {
+        double v[3] = {acc0, acc1, acc2};
+        block_sum<3>(v, red, tid, nt);
+        if (tid == 0) {
+            const size_t stride = (size_t)ntiles;
+            e.part[tile] = v[0];
+            e.part[stride + tile] = v[1];
+            e.part[2 * stride + tile] = v[2];
+        }
+    }
+}
+
+template <typename T, int RMAX>
+__global__ __launch_bounds__(kMaxBlock) void k_tile(PassArgs<T> a, EndArgs<T> e) {
+    tile_body<T, RMAX>(a, e, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// ---------------------------------------------------------------------------- register-resident frames
+// The same product with the frame transforms held in registers.  A frame length
+// TL = R S (16 = 4 x 4, 32 = 8 x 4, 64 = 8 x 8) is cut into two Stockham stages: a thread
+// owns R points of one line at positions p + S i (i < R), which are exactly the inputs of
+// the first stage's radix-R butterfly p; after one exchange through LDS the thread computes
+// R / S radix-S butterflies of the second stage (twiddles w_TL^(j m), held in registers),
+// whose outputs land again at positions p + S i.  A 2D transform is a column transform,
+// a transpose through LDS and a row transform, so each 1D transform costs one LDS
+// round trip instead of one per stage, and the radix-R/S butterflies use compile-time
+// constants.  The workgroup has S TL threads: thread t owns line t mod TL, part t div TL.
+//
+//   load     : column layout, thread (c, p) holds u at patch (row p + S i, column c)
+//   forward  : column transform, transpose, row transform -> Z(ky = line, kx = p + S i)
+//   product  : Z(-k) through one exchange; W = (Gxx + Gyy)/2 Z + ((Gxx - Gyy)/2 + i Gxy) conj Z(-k)
+//   inverse  : row transform, transpose, column transform -> f at (row p + S i, column c),
+//              the positions whose u the thread loaded (D^e u computed at load time)
+//
+// Exchanges alternate between two LDS frames, so one barrier per exchange suffices: a
+// frame is written again only two exchanges later, after every thread has passed the
+// barrier that follows its last read.
+template <int TL> struct RegShape;
+template <> struct RegShape<16> { static constexpr int R = 4, S = 4; };
+template <> struct RegShape<32> { static constexpr int R = 8, S = 4; };
+template <> struct RegShape<64> { static constexpr int R = 8, S = 8; };
+
+template <typename T, int TL, int DIR>
+struct RegLine {
+    using T2 = cplx_t<T>;
+    static constexpr int R = RegShape<TL>::R, S = RegShape<TL>::S, RA = R / S;
+    // 1D transform of the thread's line: v holds positions p + S i; element q of the line
+    // lives at buf[q * es] (buf already offset to the line).  tw[a][m] = w_TL^((p + S a) m)
+    // for the forward direction (conjugated here for the inverse).
+    __device__ __forceinline__ static void run(T2 (&v)[R], T2 *buf, int es, int p, const T2 (&tw)[RA][S]) {
+        Dft<T, T2, R, DIR>::run(v);
+#pragma unroll
+        for (int m = 0; m < R; ++m) buf[(p * R + m) * es] = v[m];
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < RA; ++a) {
+            const int j = p + S * a;
+            T2 t[S];
+#pragma unroll
+            for (int m = 0; m < S; ++m) t[m] = buf[(j + R * m) * es];
+#pragma unroll
+            for (int m = 1; m < S; ++m) {
+                T2 w = tw[a][m];
+                if (DIR > 0) w.y = -w.y;
+                t[m] = c_mul(t[m], w);
+            }
+            Dft<T, T2, S, DIR>::run(t);
+#pragma unroll
+            for (int m = 0; m < S; ++m) v[a + RA * m] = t[m];
+        }
+    }
+};
+
+template <typename T, int TL>
+__device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
+    using T2 = cplx_t<T>;
+    constexpr int R = RegShape<TL>::R, S = RegShape<TL>::S, RA = R / S, P = TL + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[96];
+    const int tid = threadIdx.x;
+    const int ln = tid % TL, p = tid / TL;    // line and part
+    const int M = a.M, Tt = TL - 2 * M;
+    const int tpc = a.ttx * a.tty;
+    const int b = tile / tpc;
+    const int rem = tile - b * tpc;
+    const int ty = rem / a.ttx, tx = rem - ty * a.ttx;
+    const int x0 = tx * Tt, y0 = ty * Tt;      // first inner node of the block
+    const int nx = min(Tt, a.Nx - x0), ny = min(Tt, a.Ny - y0);
+    T2 *buf0 = reinterpret_cast<T2 *>(smem);
+    T2 *buf1 = buf0 + TL * P;
+    if (e.case_done && e.case_done[b]) return;
+    const int N = a.N, Nx = a.Nx, Ny = a.Ny;
+    const size_t cbase = (size_t)b * 2 * N;
+    const T *uin = e.uin;
+    const bool edge = x0 < M || x0 + nx > Nx - M || y0 < M || y0 + ny > Ny - M;
+    // second-stage twiddles of this thread's butterflies (same in both axes)
+    T2 tw[RA][S];
+#pragma unroll
+    for (int q = 0; q < RA; ++q)
+#pragma unroll
+        for (int m = 0; m < S; ++m) tw[q][m] = a.twt[(p + S * q) * m];
+    // frame spectra of Z(ky = ln, kx = p + S i)
+    const T *g = a.tspec + (size_t)b * a.tspec_slot + ln * TL + p;
+    T ga[R], gr[R], gi[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        ga[i] = g[S * i];
+        gr[i] = g[TL * TL + S * i];
+        gi[i] = g[2 * TL * TL + S * i];
+    }
+    // load: column layout, patch (row p + S i, column ln) = grid (x0 - M + ln, y0 - M + p + S i);
+    // the D^e block of inner nodes within M of a face applied to u at load time, and the
+    // constraint bits of the inner nodes
+    T2 v[R], dcor[R];
+    uint32_t fixbits = 0;
+    const int gx = x0 - M + ln;
+    const bool col_in = gx >= 0 && gx < Nx;
+    const bool col_inner = ln >= M && ln < M + nx;
+    const T *de = a.de + (size_t)b * a.de_slot;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int ly = p + S * i, gy = y0 - M + ly;
+        v[i].x = T(0);
+        v[i].y = T(0);
+        dcor[i].x = T(0);
+        dcor[i].y = T(0);
+        if (col_in && gy >= 0 && gy < Ny) {
+            const size_t q = (size_t)gy * Nx + gx;
+            v[i].x = uin[cbase + q];
+            v[i].y = uin[cbase + N + q];
+            if (col_inner && ly >= M && ly < M + ny) {
+                if (a.fixed) fixbits |= ((uint32_t)a.fixed[q] | ((uint32_t)a.fixed[N + q] << 1)) << (2 * i);
+                if (edge) {
+                    const int M1 = M + 1;
+                    const int lx = min(gx, M), hx = min(Nx - 1 - gx, M), lo = min(gy, M), hy = min(Ny - 1 - gy, M);
+                    if (!((lx == M) & (hx == M) & (lo == M) & (hy == M))) {
+                        const int di = ((lx * M1 + hx) * M1 + lo) * M1 + hy;
+                        const T dxx = de[di], dxy = de[a.de_stride + di], dyy = de[2 * a.de_stride + di];
+                        dcor[i].x = dxx * v[i].x + dxy * v[i].y;
+                        dcor[i].y = dxy * v[i].x + dyy * v[i].y;
+                    }
+                }
+            }
+        }
+    }
+    // forward: columns (line ln, element q at buf[q P + ln]), transpose, rows
+    RegLine<T, TL, -1>::run(v, buf0 + ln, P, p, tw);
+#pragma unroll
+    for (int i = 0; i < R; ++i) buf1[(p + S * i) * P + ln] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = buf1[ln * P + p + S * i];
+    RegLine<T, TL, -1>::run(v, buf0 + ln * P, 1, p, tw);
+    // block product with Z(-k) from the other frame
+#pragma unroll
+    for (int i = 0; i < R; ++i) buf1[ln * P + p + S * i] = v[i];
+    __syncthreads();
+    {
+        const int mky = ln ? TL - ln : 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int kx = p + S * i, mkx = kx ? TL - kx : 0;
+            const T2 Z = v[i], Zm = buf1[mky * P + mkx];
+            T2 W;
+            W.x = ga[i] * Z.x + gr[i] * Zm.x + gi[i] * Zm.y;
+            W.y = ga[i] * Z.y + gi[i] * Zm.x - gr[i] * Zm.y;
+            v[i] = W;
+        }
+    }
+    // inverse: rows, transpose, columns
+    RegLine<T, TL, 1>::run(v, buf0 + ln * P, 1, p, tw);
+#pragma unroll
+    for (int i = 0; i < R; ++i) buf1[ln * P + p + S * i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = buf1[(p + S * i) * P + ln];
+    RegLine<T, TL, 1>::run(v, buf0 + ln, P, p, tw);
+    // broken bonds (eq. (tea:fr)) and the surface correction (Remark 3, eq. (scr)) of the
+    // inner nodes, gathered into the free frame (zeroed first) by the nodes' threads of
+    // the generic form, then read back by the owners
+    const bool bonds = a.br_row_ptr && ny > 0 && a.br_row_ptr[y0] < a.br_row_ptr[y0 + ny];
+    const bool surf = a.nu && edge;
+    if (bonds || surf) {
+        const int nt = S * TL;
+        T2 *cor = buf1;
+        for (int i = tid; i < TL * P; i += nt) {
+            cor[i].x = T(0);
+            cor[i].y = T(0);
+        }
+        __syncthreads();
+        const T *wt = a.w + (size_t)b * a.w_slot;
+        if (bonds) {
+            const int e0 = a.br_row_ptr[y0], e1 = a.br_row_ptr[y0 + ny];
+            for (int ei = e0 + tid; ei < e1; ei += nt) {
+                const int node = a.br_node_i[ei];
+                const int qy = node / Nx, qx = node - qy * Nx;
+                if (qx < x0 || qx >= x0 + nx) continue;
+                const bool on_e = a.nu && (qx < M || qx >= Nx - M || qy < M || qy >= Ny - M);
+                const double nup = on_e ? (double)a.nu[node] : 0.0;
+                const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
+                double fxa = 0.0, fya = 0.0;
+                for (int t0 = a.br_bond_ptr[ei], t1 = a.br_bond_ptr[ei + 1]; t0 < t1; ++t0) {
+                    const int q = a.br_q[t0], oi = a.br_off[t0];
+                    const double dx = px - (double)uin[cbase + q], dy = py - (double)uin[cbase + N + q];
+                    const double wxx = (double)wt[oi], wxy = (double)wt[a.n_off + oi],
+                                 wyy = (double)wt[2 * a.n_off + oi];
+                    const double vf = on_e ? 0.5 * (nup + (double)a.nu[q]) : 1.0;
+                    fxa += vf * (wxx * dx + wxy * dy);
+                    fya += vf * (wxy * dx + wyy * dy);
+                }
+                T2 &c = cor[(qy - y0 + M) * P + (qx - x0 + M)];
+                c.x += T(fxa);
+                c.y += T(fya);
+            }
+        }
+        __syncthreads();
+        if (surf) {
+            for (int i = tid; i < Tt * Tt; i += nt) {
+                const int jy = i / Tt, jx = i - jy * Tt;
+                if (jx >= nx || jy >= ny) continue;
+                const int qx = x0 + jx, qy = y0 + jy;
+                if (qx >= M && qx < Nx - M && qy >= M && qy < Ny - M) continue;
+                const int node = qy * Nx + qx;
+                const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
+                const double nup = (double)a.nu[node];
+                double ax = 0.0, ay = 0.0;
+                for (int oi = 0; oi < a.n_off; ++oi) {
+                    const int ox = a.offs[3 * oi], oy = a.offs[3 * oi + 1];
+                    const int xx = qx + ox, yy = qy + oy;
+                    if (xx < 0 || xx >= Nx || yy < 0 || yy >= Ny) continue;
+                    const int q = node + oy * Nx + ox;
+                    const double dx = (double)uin[cbase + q] - px, dy = (double)uin[cbase + N + q] - py;
+                    const double vm = 0.5 * (nup + (double)a.nu[q]) - 1.0;
+                    ax += vm * ((double)wt[oi] * dx + (double)wt[a.n_off + oi] * dy);
+                    ay += vm * ((double)wt[a.n_off + oi] * dx + (double)wt[2 * a.n_off + oi] * dy);
+                }
+                T2 &c = cor[(jy + M) * P + (jx + M)];
+                c.x += T(ax);
+                c.y += T(ay);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const T2 c = cor[(p + S * i) * P + ln];
+            v[i].x += c.x;
+            v[i].y += c.y;
+        }
+    }
+    // D^e, mask and fused epilogue of the inner nodes this thread holds
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    {
+        const T dth = T(0.5 * e.dt);
+        const T rinv = T(1.0 / e.rho);
+        const T sign = T(e.sign);
+        const size_t pb = (size_t)b * e.pa_stride;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int ly = p + S * i;
+            if (col_inner && ly >= M && ly < M + ny) {
+                const size_t node = (size_t)(y0 - M + ly) * Nx + gx;
+                const T fx = v[i].x + dcor[i].x, fy = v[i].y + dcor[i].y;
+                const size_t ax = cbase + node, ay = ax + N;
+                epilogue_at<T>(e, uin, ax, node + pb, fx, (fixbits >> (2 * i)) & 1u, sign, rinv, dth, acc0, acc1,
+                               acc2);
+                epilogue_at<T>(e, uin, ay, N + node + pb, fy, (fixbits >> (2 * i + 1)) & 1u, sign, rinv, dth, acc0,
+                               acc1, acc2);
+            }
+        }
+    }
+    if (e.part) {
+        double vs[3] = {acc0, acc1, acc2};
+        block_sum<3>(vs, red, tid, S * TL);
+        if (tid == 0) {
+            const size_t stride = (size_t)ntiles;
+            e.part[tile] = vs[0];
+            e.part[stride + tile] = vs[1];
+            e.part[2 * stride + tile] = vs[2];
+        }
+    }
+}
+
+template <typename T, int TL>
+__global__ __launch_bounds__(RegShape<TL>::S * TL) void k_tile_reg(PassArgs<T> a, EndArgs<T> e) {
+    tile_reg_body<T, TL>(a, e, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T>
+hipError_t launch_tile_kernel(const PassArgs<T> &a, const EndArgs<T> &e, size_t lds, bool composite, int reps,
+                              hipStream_t st) {
+    const dim3 grid(a.B * a.ttx * a.tty), block(a.tthreads);
+    hipError_t err;
+    if (a.treg) {
+        // register-resident frames: S TL threads, two TL x (TL + 1) frames
+        const size_t lr = 2 * (size_t)a.tl * (a.tl + 1) * sizeof(cplx_t<T>);
+#define MSB_TILE_REG(TLV)                                                                            \
+    case TLV:                                                                                        \
+        if ((err = allow_lds(k_tile_reg<T, TLV>, lr)) != hipSuccess) return err;                     \
+        for (int k = 0; k < reps; ++k)                                                               \
+            hipLaunchKernelGGL((k_tile_reg<T, TLV>), grid, dim3(RegShape<TLV>::S * TLV), lr, st, a, e); \
+        break;
+        switch (a.tl) {
+            MSB_TILE_REG(16)
+            MSB_TILE_REG(32)
+            MSB_TILE_REG(64)
+            default: return hipErrorInvalidValue;
+        }
+#undef MSB_TILE_REG
+        return hipGetLastError();
+    }
+    if (composite) {
+        if ((err = allow_lds(k_tile<T, 16>, lds)) != hipSuccess) return err;
+        for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile<T, 16>), grid, block, lds, st, a, e);
+    } else {
+        if ((err = allow_lds(k_tile<T, 8>, lds)) != hipSuccess) return err;
+        for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile<T, 8>), grid, block, lds, st, a, e);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_tile_kernel<double>(const PassArgs<double> &, const EndArgs<double> &, size_t, bool, int,
+                                               hipStream_t);
+template hipError_t launch_tile_kernel<float>(const PassArgs<float> &, const EndArgs<float> &, size_t, bool, int,
+                                              hipStream_t);
+
+}  // namespace msb

@@ -3,6 +3,7 @@
     python -m paper_2301_11828_amd.profiling trace DIR            # kernel-trace CSV -> per-kernel durations
     python -m paper_2301_11828_amd.profiling counters DIR_FETCH DIR_WRITE BYTES_COPY
                                                                   # FETCH_SIZE / WRITE_SIZE per dispatch
+    python -m paper_2301_11828_amd.profiling pmc DIR              # mean of every counter per dispatch
 
 DIR holds the CSV files rocprofv3 wrote with ``--output-format csv``.  The counter
 summary calibrates FETCH_SIZE and WRITE_SIZE with the largest plain copy kernel
@@ -22,15 +23,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("passes.hip", "fft_device.hpp", "passes.hpp"):
+    for f in ("passes.hip", "tile.hip", "epilogue.hpp", "fft_device.hpp", "passes.hpp"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def _short(name: str) -> str:
-    for k in ("k_xfwd", "k_line_y", "k_line_z", "k_xinv", "k_yfwd", "k_yinv", "k_cg_sums", "k_dot_parts",
-              "k_stretch", "k_scan", "k_emit"):
+    for k in ("k_tile_reg", "k_xfwd", "k_line_y", "k_line_z", "k_xinv", "k_yfwd", "k_yinv", "k_cg_sums",
+              "k_dot_parts", "k_stretch", "k_scan", "k_emit", "k_tile"):
         if k in name:
             prec = "double" if "<double" in name else ("float" if "<float" in name else "")
             return "%s<%s%s>" % (k, prec, ",wave" if "false" in name.split(k)[1][:40] else "")
@@ -101,8 +102,27 @@ def counters(dfetch: str, dwrite: str, copy_bytes: float):
     return rows
 
 
+def pmc(d: str):
+    """Mean per dispatch of every collected counter, per product kernel."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            k = _key(r)
+            if k.startswith("k_"):
+                vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for v in vals.values() for c in v})
+    print("kernel@workgroups".ljust(34) + "".join("%22s" % c for c in names))
+    for k in sorted(vals):
+        print(k.ljust(34) + "".join("%22.4g" % (sum(vals[k][c]) / len(vals[k][c]) if vals[k][c] else float("nan"))
+                                    for c in names))
+    print("source_hash: %s" % source_hash())
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2])
+    elif sys.argv[1] == "pmc":
+        pmc(sys.argv[2])
     elif sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3], float(sys.argv[4]))

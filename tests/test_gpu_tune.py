@@ -42,6 +42,8 @@ def _random_configs(rng, count, dim=2):
                         lds_inplace=int(rng.choice([0, 0, 1, 2, 3])),
                         tile=int(rng.choice([0, 0, 16, 24, 40])) if dim == 2 else 0,
                         threads_tile=64 * int(rng.integers(1, 9))))
+        # frame 16 with register-resident transforms, the other frames with LDS stages
+        out[-1]["tile_regs"] = 1 if out[-1]["tile"] == 16 else 0
     return out
 
 
