@@ -86,6 +86,8 @@ def kernel_key(plan, prec, name, n, M, nb=1):
     if name == "tile_product":
         inner = c["tile"] - 2 * M
         tiles = nb * (-(-n[0] // inner)) * (-(-n[1] // inner))
+        if c["tile_regs"]:
+            tiles = -(-tiles // c["tile_run"])     # one workgroup per run of blocks
         return "%s<%s>@%d" % ("k_tile_reg" if c["tile_regs"] else "k_tile", t, tiles)
     L = plan.padded_lengths
     wave = c["team_line"] == 1 if name == "y_line_product" else c["team_x"] == 1
@@ -215,7 +217,7 @@ def main():
 
     # the timed steps replay a hipGraph of G products (the launch gaps between the three
     # kernels of consecutive products shrink); the same steps as plain launches beside it
-    G = 10 if args.steps % 10 == 0 else 0
+    G = max([g for g in range(1, 51) if args.steps % g == 0]) if args.steps > 1 else 0
     print("bench: plate512 FP64 product, %d warmup + %d steps (graphs of %d)" % (args.warmup, args.steps, G),
           file=sys.stderr, flush=True)
     wall, ev_ms = timed(u64, f64, args.steps, args.warmup, G)

@@ -307,6 +307,10 @@ msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds
  *                   8 x 8) and a 1D transform is a radix-R butterfly, one LDS exchange
  *                   and R / S radix-S butterflies; the workgroup has S tile threads
  *                   (threads_tile is not used)
+ *   tile_run        tile_regs = 1: consecutive blocks per workgroup, 1..64; a
+ *                   workgroup issues the loads of its next block before it
+ *                   transforms the current one (the blocks of a workgroup run one
+ *                   after another, their memory and arithmetic overlapped)
  *   lds_inplace     bit 0: x passes, bit 1: line passes; a set bit runs every
  *                   Stockham stage in place (each thread reads its butterflies
  *                   into registers, a barrier, then it writes them back into the
@@ -325,7 +329,7 @@ typedef struct {
     int max_radix;
     int lds_inplace;
     int tile, threads_tile;
-    int tile_regs;
+    int tile_regs, tile_run;
 } msb_launch_config;
 
 msb_status msb_plan_get_config(msb_plan plan, msb_precision prec, msb_launch_config *cfg);

@@ -63,7 +63,8 @@ class _Info(ctypes.Structure):
 class _LaunchConfig(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int) for k in ("rows_per_wg", "team_x", "slots_fwd", "slots_inv", "threads_x",
                                             "lines_per_wg", "team_line", "lines_per_wave", "threads_line",
-                                            "max_radix", "lds_inplace", "tile", "threads_tile", "tile_regs")]
+                                            "max_radix", "lds_inplace", "tile", "threads_tile", "tile_regs",
+                                            "tile_run")]
 
 
 CONFIG_KEYS = tuple(k for k, _ in _LaunchConfig._fields_)

@@ -950,6 +950,7 @@ msb_launch_config default_config(const msb_plan_s *p, bool fp32) {
     c.tile = 0;
     c.threads_tile = 256;
     c.tile_regs = 0;
+    c.tile_run = 1;
     return c;
 }
 
@@ -1033,6 +1034,7 @@ msb_status check_config(const msb_plan_s *p, bool fp32, const msb_launch_config 
     MSB_CHECK(c.tile_regs == 0 || c.tile_regs == 1, MSB_EINVAL, "tile_regs %d: need 0 or 1", c.tile_regs);
     MSB_CHECK(!c.tile_regs || c.tile == 16 || c.tile == 32 || c.tile == 64, MSB_EINVAL,
               "tile_regs = 1 needs tile 16, 32 or 64 (got %d)", c.tile);
+    MSB_CHECK(c.tile_run >= 1 && c.tile_run <= 64, MSB_EINVAL, "tile_run %d not in [1, 64]", c.tile_run);
     return MSB_OK;
 }
 
@@ -1116,6 +1118,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.ept = (a.rows + a.F - 1) / a.F;
     a.tl = a.ttx = a.tty = 0;
     a.treg = 0;
+    a.tper = 1;
     a.tthreads = c.threads_tile;
     a.twt = nullptr;
     a.tspec = nullptr;
@@ -1137,6 +1140,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
             a.tspec_slot = multi ? (size_t)3 * c.tile * c.tile : 0;
             a.ept = a.ttx * a.tty;
             a.treg = c.tile_regs;
+            a.tper = c.tile_regs ? c.tile_run : 1;
         }
     }
     return a;

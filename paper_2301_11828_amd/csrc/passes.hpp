@@ -75,6 +75,7 @@ template <typename T> struct PassArgs {
     // (Gxx-Gyy)/2, Gxy of the generating array wrapped to tl x tl, scaled by 1/tl^2)
     int tl, ttx, tty, tthreads;
     int treg;            // 1: the register-resident frame kernel (tl = 16, 32 or 64)
+    int tper;            // register kernel: consecutive tiles per workgroup (loads of the next overlap the current)
     FftSched stl;
     const cplx_t<T> *twt;
     const T *tspec;

@@ -252,6 +252,8 @@ struct RegLine {
     }
 };
 
+// One block per workgroup (tile_run = 1): every load of the block is issued at the start
+// (spectra, u, constraint bits, D^e blocks), the D^e term is formed from u as it lands.
 template <typename T, int TL>
 __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
     using T2 = cplx_t<T>;
@@ -462,8 +464,323 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
 }
 
 template <typename T, int TL>
-__global__ __launch_bounds__(RegShape<TL>::S * TL) void k_tile_reg(PassArgs<T> a, EndArgs<T> e) {
+__global__ __launch_bounds__(RegShape<TL>::S * TL) void k_tile_reg1(PassArgs<T> a, EndArgs<T> e) {
     tile_reg_body<T, TL>(a, e, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// What a thread holds of one tile between its loads and its transforms: u at its R
+// patch points (column layout), the D^e table index of its inner points within M of a
+// face (-1 elsewhere) and the constraint bits of its inner points.
+template <typename T, int TL> struct RegTile {
+    static constexpr int R = RegShape<TL>::R;
+    cplx_t<T> v[R];
+    int di[R];
+    uint32_t fix;
+};
+
+// Geometry of tile `tile` of a launch: case, first inner node, inner nodes in the grid.
+struct TileGeom {
+    int b, x0, y0, nx, ny, edge;
+};
+template <typename T>
+__device__ __forceinline__ TileGeom tile_geom(const PassArgs<T> &a, int tile, int Tt) {
+    TileGeom g;
+    const int tpc = a.ttx * a.tty;
+    g.b = tile / tpc;
+    const int rem = tile - g.b * tpc;
+    const int ty = rem / a.ttx, tx = rem - ty * a.ttx;
+    g.x0 = tx * Tt;
+    g.y0 = ty * Tt;
+    g.nx = min(Tt, a.Nx - g.x0);
+    g.ny = min(Tt, a.Ny - g.y0);
+    g.edge = (g.x0 < a.M || g.x0 + g.nx > a.Nx - a.M || g.y0 < a.M || g.y0 + g.ny > a.Ny - a.M) ? 1 : 0;
+    return g;
+}
+
+// Issue the loads of one tile: u at the thread's patch points and the constraint bits of
+// its inner points; the D^e table index of its inner points within M of a face.
+template <typename T, int TL>
+__device__ __forceinline__ void reg_tile_load(const PassArgs<T> &a, const EndArgs<T> &e, const TileGeom &g, int ln,
+                                              int p, RegTile<T, TL> &rt) {
+    constexpr int R = RegShape<TL>::R, S = RegShape<TL>::S;
+    const int M = a.M, N = a.N, Nx = a.Nx, Ny = a.Ny, M1 = M + 1;
+    const size_t cbase = (size_t)g.b * 2 * N;
+    const T *uin = e.uin;
+    const int gx = g.x0 - M + ln;
+    const bool col_in = gx >= 0 && gx < Nx;
+    const bool col_inner = ln >= M && ln < M + g.nx;
+    rt.fix = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int ly = p + S * i, gy = g.y0 - M + ly;
+        rt.v[i].x = T(0);
+        rt.v[i].y = T(0);
+        rt.di[i] = -1;
+        if (col_in && gy >= 0 && gy < Ny) {
+            const size_t q = (size_t)gy * Nx + gx;
+            rt.v[i].x = uin[cbase + q];
+            rt.v[i].y = uin[cbase + N + q];
+            if (col_inner && ly >= M && ly < M + g.ny) {
+                if (a.fixed) rt.fix |= ((uint32_t)a.fixed[q] | ((uint32_t)a.fixed[N + q] << 1)) << (2 * i);
+                const int lx = min(gx, M), hx = min(Nx - 1 - gx, M), lo = min(gy, M), hy = min(Ny - 1 - gy, M);
+                if (g.edge && !((lx == M) & (hx == M) & (lo == M) & (hy == M)))
+                    rt.di[i] = ((lx * M1 + hx) * M1 + lo) * M1 + hy;
+            }
+        }
+    }
+}
+
+// D^e u at the thread's inner points within M of a face (eq. (tea:sc); the table is
+// small and cache-resident), formed from the loaded u before the transforms overwrite it.
+template <typename T, int TL>
+__device__ __forceinline__ void reg_tile_de(const PassArgs<T> &a, const TileGeom &g, const RegTile<T, TL> &rt,
+                                            cplx_t<T> (&dcor)[RegShape<TL>::R]) {
+    constexpr int R = RegShape<TL>::R;
+    const T *de = a.de + (size_t)g.b * a.de_slot;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        dcor[i].x = T(0);
+        dcor[i].y = T(0);
+        if (g.edge && rt.di[i] >= 0) {
+            const int di = rt.di[i];
+            const T dxx = de[di], dxy = de[a.de_stride + di], dyy = de[2 * a.de_stride + di];
+            dcor[i].x = dxx * rt.v[i].x + dxy * rt.v[i].y;
+            dcor[i].y = dxy * rt.v[i].x + dyy * rt.v[i].y;
+        }
+    }
+}
+
+// Transforms, block product, corrections and epilogue of one loaded tile.
+template <typename T, int TL>
+__device__ __forceinline__ void reg_tile_process(const PassArgs<T> &a, const EndArgs<T> &e, const TileGeom &g,
+                                                 int tile, int ntiles, int ln, int p,
+                                                 const cplx_t<T> (&tw)[RegShape<TL>::R / RegShape<TL>::S]
+                                                                      [RegShape<TL>::S],
+                                                 const T (&ga)[RegShape<TL>::R], const T (&gr)[RegShape<TL>::R],
+                                                 const T (&gi)[RegShape<TL>::R], RegTile<T, TL> &rt,
+                                                 const cplx_t<T> (&dcor)[RegShape<TL>::R], cplx_t<T> *buf0,
+                                                 cplx_t<T> *buf1, double *red) {
+    using T2 = cplx_t<T>;
+    constexpr int R = RegShape<TL>::R, S = RegShape<TL>::S, P = TL + 1;
+    const int tid = threadIdx.x;
+    const int M = a.M, Tt = TL - 2 * M;
+    const int N = a.N, Nx = a.Nx, Ny = a.Ny;
+    const size_t cbase = (size_t)g.b * 2 * N;
+    const T *uin = e.uin;
+    T2(&v)[R] = rt.v;
+    // forward: columns (line ln, element q at buf[q P + ln]), transpose, rows
+    RegLine<T, TL, -1>::run(v, buf0 + ln, P, p, tw);
+#pragma unroll
+    for (int i = 0; i < R; ++i) buf1[(p + S * i) * P + ln] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = buf1[ln * P + p + S * i];
+    RegLine<T, TL, -1>::run(v, buf0 + ln * P, 1, p, tw);
+    // block product with Z(-k) from the other frame
+#pragma unroll
+    for (int i = 0; i < R; ++i) buf1[ln * P + p + S * i] = v[i];
+    __syncthreads();
+    {
+        const int mky = ln ? TL - ln : 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int kx = p + S * i, mkx = kx ? TL - kx : 0;
+            const T2 Z = v[i], Zm = buf1[mky * P + mkx];
+            T2 W;
+            W.x = ga[i] * Z.x + gr[i] * Zm.x + gi[i] * Zm.y;
+            W.y = ga[i] * Z.y + gi[i] * Zm.x - gr[i] * Zm.y;
+            v[i] = W;
+        }
+    }
+    // inverse: rows, transpose, columns
+    RegLine<T, TL, 1>::run(v, buf0 + ln * P, 1, p, tw);
+#pragma unroll
+    for (int i = 0; i < R; ++i) buf1[ln * P + p + S * i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = buf1[(p + S * i) * P + ln];
+    RegLine<T, TL, 1>::run(v, buf0 + ln, P, p, tw);
+    // broken bonds (eq. (tea:fr)) and the surface correction (Remark 3, eq. (scr)) of the
+    // inner nodes, gathered into the free frame (zeroed first), read back by the owners
+    const bool bonds = a.br_row_ptr && g.ny > 0 && a.br_row_ptr[g.y0] < a.br_row_ptr[g.y0 + g.ny];
+    const bool surf = a.nu && g.edge;
+    if (bonds || surf) {
+        const int nt = S * TL;
+        T2 *cor = buf1;
+        for (int i = tid; i < TL * P; i += nt) {
+            cor[i].x = T(0);
+            cor[i].y = T(0);
+        }
+        __syncthreads();
+        const T *wt = a.w + (size_t)g.b * a.w_slot;
+        if (bonds) {
+            const int e0 = a.br_row_ptr[g.y0], e1 = a.br_row_ptr[g.y0 + g.ny];
+            for (int ei = e0 + tid; ei < e1; ei += nt) {
+                const int node = a.br_node_i[ei];
+                const int qy = node / Nx, qx = node - qy * Nx;
+                if (qx < g.x0 || qx >= g.x0 + g.nx) continue;
+                const bool on_e = a.nu && (qx < M || qx >= Nx - M || qy < M || qy >= Ny - M);
+                const double nup = on_e ? (double)a.nu[node] : 0.0;
+                const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
+                double fxa = 0.0, fya = 0.0;
+                for (int t0 = a.br_bond_ptr[ei], t1 = a.br_bond_ptr[ei + 1]; t0 < t1; ++t0) {
+                    const int q = a.br_q[t0], oi = a.br_off[t0];
+                    const double dx = px - (double)uin[cbase + q], dy = py - (double)uin[cbase + N + q];
+                    const double wxx = (double)wt[oi], wxy = (double)wt[a.n_off + oi],
+                                 wyy = (double)wt[2 * a.n_off + oi];
+                    const double vf = on_e ? 0.5 * (nup + (double)a.nu[q]) : 1.0;
+                    fxa += vf * (wxx * dx + wxy * dy);
+                    fya += vf * (wxy * dx + wyy * dy);
+                }
+                T2 &c = cor[(qy - g.y0 + M) * P + (qx - g.x0 + M)];
+                c.x += T(fxa);
+                c.y += T(fya);
+            }
+        }
+        __syncthreads();
+        if (surf) {
+            for (int i = tid; i < Tt * Tt; i += nt) {
+                const int jy = i / Tt, jx = i - jy * Tt;
+                if (jx >= g.nx || jy >= g.ny) continue;
+                const int qx = g.x0 + jx, qy = g.y0 + jy;
+                if (qx >= M && qx < Nx - M && qy >= M && qy < Ny - M) continue;
+                const int node = qy * Nx + qx;
+                const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
+                const double nup = (double)a.nu[node];
+                double ax = 0.0, ay = 0.0;
+                for (int oi = 0; oi < a.n_off; ++oi) {
+                    const int ox = a.offs[3 * oi], oy = a.offs[3 * oi + 1];
+                    const int xx = qx + ox, yy = qy + oy;
+                    if (xx < 0 || xx >= Nx || yy < 0 || yy >= Ny) continue;
+                    const int q = node + oy * Nx + ox;
+                    const double dx = (double)uin[cbase + q] - px, dy = (double)uin[cbase + N + q] - py;
+                    const double vm = 0.5 * (nup + (double)a.nu[q]) - 1.0;
+                    ax += vm * ((double)wt[oi] * dx + (double)wt[a.n_off + oi] * dy);
+                    ay += vm * ((double)wt[a.n_off + oi] * dx + (double)wt[2 * a.n_off + oi] * dy);
+                }
+                T2 &c = cor[(jy + M) * P + (jx + M)];
+                c.x += T(ax);
+                c.y += T(ay);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const T2 c = cor[(p + S * i) * P + ln];
+            v[i].x += c.x;
+            v[i].y += c.y;
+        }
+        // the frame is written again by the next tile's first exchange
+        __syncthreads();
+    }
+    // D^e, mask and fused epilogue of the inner nodes this thread holds
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    {
+        const T dth = T(0.5 * e.dt);
+        const T rinv = T(1.0 / e.rho);
+        const T sign = T(e.sign);
+        const size_t pb = (size_t)g.b * e.pa_stride;
+        const int gx = g.x0 - M + ln;
+        const bool col_inner = ln >= M && ln < M + g.nx;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int ly = p + S * i;
+            if (col_inner && ly >= M && ly < M + g.ny) {
+                const size_t node = (size_t)(g.y0 - M + ly) * Nx + gx;
+                const T fx = v[i].x + dcor[i].x, fy = v[i].y + dcor[i].y;
+                const size_t ax = cbase + node, ay = ax + N;
+                if (e.epi == EPI_APPLY) {
+                    e.out[ax] = (rt.fix >> (2 * i)) & 1u ? T(0) : sign * fx;
+                    e.out[ay] = (rt.fix >> (2 * i + 1)) & 1u ? T(0) : sign * fy;
+                } else {
+                    epilogue_at<T>(e, uin, ax, node + pb, fx, (rt.fix >> (2 * i)) & 1u, sign, rinv, dth, acc0, acc1,
+                                   acc2);
+                    epilogue_at<T>(e, uin, ay, N + node + pb, fy, (rt.fix >> (2 * i + 1)) & 1u, sign, rinv, dth,
+                                   acc0, acc1, acc2);
+                }
+            }
+        }
+    }
+    if (e.part) {
+        double vs[3] = {acc0, acc1, acc2};
+        block_sum<3>(vs, red, tid, S * TL);
+        if (tid == 0) {
+            const size_t stride = (size_t)ntiles;
+            e.part[tile] = vs[0];
+            e.part[stride + tile] = vs[1];
+            e.part[2 * stride + tile] = vs[2];
+        }
+    }
+}
+
+// Runs (tile_run > 1): a workgroup processes the a.tper consecutive tiles [first, first + tper) of
+// the launch's ntiles (XCD-remapped runs, so that neighbouring blocks, whose patches
+// overlap, share an L2): the loads of the next tile are issued before the transforms of
+// the current one, so memory and arithmetic of consecutive tiles overlap.
+template <typename T, int TL>
+__device__ __forceinline__ void tile_reg_run(const PassArgs<T> &a, const EndArgs<T> &e, int run, int ntiles) {
+    using T2 = cplx_t<T>;
+    constexpr int R = RegShape<TL>::R, S = RegShape<TL>::S, RA = R / S, P = TL + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[96];
+    const int tid = threadIdx.x;
+    const int ln = tid % TL, p = tid / TL;    // line and part
+    const int Tt = TL - 2 * a.M;
+    T2 *buf0 = reinterpret_cast<T2 *>(smem);
+    T2 *buf1 = buf0 + TL * P;
+    const int first = run * a.tper, last = min(first + a.tper, ntiles);
+    // second-stage twiddles of this thread's butterflies (same in both axes and every tile)
+    T2 tw[RA][S];
+#pragma unroll
+    for (int q = 0; q < RA; ++q)
+#pragma unroll
+        for (int m = 0; m < S; ++m) tw[q][m] = a.twt[(p + S * q) * m];
+    // frame spectra of Z(ky = ln, kx = p + S i): per case slot (reloaded when the case changes)
+    T ga[R], gr[R], gi[R];
+    int gb = -1;
+    RegTile<T, TL> cur, nxt;
+    TileGeom g = tile_geom(a, first, Tt);
+    if (first < last) reg_tile_load<T, TL>(a, e, g, ln, p, cur);
+    for (int t = first; t < last; ++t) {
+        TileGeom gn = g;
+        if (t + 1 < last) {
+            gn = tile_geom(a, t + 1, Tt);
+            reg_tile_load<T, TL>(a, e, gn, ln, p, nxt);
+        }
+        if (!(e.case_done && e.case_done[g.b])) {
+            const int slot = a.tspec_slot ? g.b : 0;
+            if (slot != gb) {
+                const T *gs = a.tspec + (size_t)slot * a.tspec_slot + ln * TL + p;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    ga[i] = gs[S * i];
+                    gr[i] = gs[TL * TL + S * i];
+                    gi[i] = gs[2 * TL * TL + S * i];
+                }
+                gb = slot;
+            }
+            T2 dcor[R];
+            reg_tile_de<T, TL>(a, g, cur, dcor);
+            reg_tile_process<T, TL>(a, e, g, t, ntiles, ln, p, tw, ga, gr, gi, cur, dcor, buf0, buf1, red);
+            // the next tile exchanges through the frames in the other order: its first
+            // writes go to the frame this tile last read before its final barrier
+            T2 *sw = buf0;
+            buf0 = buf1;
+            buf1 = sw;
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            cur.v[i] = nxt.v[i];
+            cur.di[i] = nxt.di[i];
+        }
+        cur.fix = nxt.fix;
+        g = gn;
+    }
+}
+
+template <typename T, int TL>
+__global__ __launch_bounds__(RegShape<TL>::S * TL) void k_tile_reg(PassArgs<T> a, EndArgs<T> e) {
+    tile_reg_run<T, TL>(a, e, xcd_tile(blockIdx.x, gridDim.x), a.B * a.ttx * a.tty);
 }
 
 template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
@@ -480,11 +797,19 @@ hipError_t launch_tile_kernel(const PassArgs<T> &a, const EndArgs<T> &e, size_t 
     if (a.treg) {
         // register-resident frames: S TL threads, two TL x (TL + 1) frames
         const size_t lr = 2 * (size_t)a.tl * (a.tl + 1) * sizeof(cplx_t<T>);
-#define MSB_TILE_REG(TLV)                                                                            \
-    case TLV:                                                                                        \
-        if ((err = allow_lds(k_tile_reg<T, TLV>, lr)) != hipSuccess) return err;                     \
-        for (int k = 0; k < reps; ++k)                                                               \
-            hipLaunchKernelGGL((k_tile_reg<T, TLV>), grid, dim3(RegShape<TLV>::S * TLV), lr, st, a, e); \
+        const int tiles = a.B * a.ttx * a.tty;
+        const dim3 gridr((tiles + a.tper - 1) / a.tper);
+#define MSB_TILE_REG(TLV)                                                                             \
+    case TLV:                                                                                         \
+        if (a.tper > 1) {                                                                             \
+            if ((err = allow_lds(k_tile_reg<T, TLV>, lr)) != hipSuccess) return err;                  \
+            for (int k = 0; k < reps; ++k)                                                            \
+                hipLaunchKernelGGL((k_tile_reg<T, TLV>), gridr, dim3(RegShape<TLV>::S * TLV), lr, st, a, e); \
+        } else {                                                                                      \
+            if ((err = allow_lds(k_tile_reg1<T, TLV>, lr)) != hipSuccess) return err;                 \
+            for (int k = 0; k < reps; ++k)                                                            \
+                hipLaunchKernelGGL((k_tile_reg1<T, TLV>), grid, dim3(RegShape<TLV>::S * TLV), lr, st, a, e); \
+        }                                                                                             \
         break;
         switch (a.tl) {
             MSB_TILE_REG(16)

@@ -133,6 +133,7 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
     msb_launch_config cur = p->cfg[f32];
     cur.tile = 0;   // the chain's settings are searched on the chain; the tiled product last
     cur.tile_regs = 0;
+    cur.tile_run = 1;
     MSB_CHECK(bn.run(cur, err), err != MSB_OK ? err : MSB_EINVAL, "current configuration is not valid");
     // about 2 ms of kernels per candidate, 3..40 products
     bn.nrep = std::max(3, std::min(kMaxRep, (int)std::ceil(2.0 / std::max(bn.total(), 1e-3))));
@@ -276,17 +277,20 @@ template <typename T> msb_status tune_precision(msb_plan_s *p, int effort, hipSt
                     }
                     MSB_TRY(err);
                 }
-        // register-resident frames (their own thread count; no radix cap)
-        for (int tl : {16, 32, 64}) {
-            msb_launch_config c = cur;
-            c.tile = tl;
-            c.tile_regs = 1;
-            if (bn.run(c, err) && bn.total() < bt) {
-                bt = bn.total();
-                best = c;
+        // register-resident frames (their own thread count; no radix cap), with runs of
+        // consecutive blocks per workgroup
+        for (int tl : {16, 32, 64})
+            for (int run : {1, 2, 3, 4, 6, 8}) {
+                msb_launch_config c = cur;
+                c.tile = tl;
+                c.tile_regs = 1;
+                c.tile_run = run;
+                if (bn.run(c, err) && bn.total() < bt) {
+                    bt = bn.total();
+                    best = c;
+                }
+                MSB_TRY(err);
             }
-            MSB_TRY(err);
-        }
         cur = best;
     }
     bn.nrep = std::max(bn.nrep, 5);

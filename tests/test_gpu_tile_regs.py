@@ -308,3 +308,59 @@ def test_register_frames_configurations_rejected():
     p7 = gpu_plan(W.small(2, (30, 30), 7, seed=737))
     with pytest.raises(msb.MsbError):
         p7.set_config("fp64", tile=16, tile_regs=1)
+
+
+@pytest.mark.parametrize("tl,run", [(16, 2), (16, 3), (32, 2), (32, 5), (64, 2)])
+def test_register_frame_runs_match_oracle(tl, run):
+    """Runs of consecutive blocks per workgroup (the next block's loads in flight during
+    the current block's transforms): runs that cross case boundaries (per-case frame
+    spectra reloaded), a ragged last run, cracks and constraints."""
+    rng = np.random.default_rng(740 + tl + run)
+    a = rng.uniform(0.1, 1.0, size=(3, 3))
+    w = W.small(2, (71, 53), 3, seed=741, fixed="mixed", crack=True, batch=3, infl=tuple(a[0]))
+    plan = gpu_plan(w)
+    plan.set_infl(a, per_case=True)
+    plan.set_config("fp64", tile=tl, tile_regs=1, tile_run=run)
+    assert plan.get_config("fp64")["tile_run"] == run
+    f = gpu_apply(plan, to_dev(w.b)).cpu().numpy()
+    for c in range(3):
+        ref = O.apply(oracle_problem(w, infl=tuple(a[c])), w.b[c], w.fixed, oracle_bonds(w))
+        err = rel_err(f[c], ref)
+        log("frame %d run %d case %d rel err %.2e" % (tl, run, c, err))
+        assert err <= FP64_TOL
+    plan.set_config("fp64", tile_run=1)
+    assert np.array_equal(gpu_apply(plan, to_dev(w.b)).cpu().numpy(), f)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
+def test_register_frame_runs_solve_with_converged_cases(prec):
+    """A CG batch whose cases converge at different iterations: blocks of converged
+    cases are skipped inside a run; every case reaches the dense solution."""
+    w = W.small(2, (52, 47), 3, seed=742, fixed="all", crack=True, batch=3)
+    b = w.b.copy()
+    b[1] *= 1e-3
+    b[2] = np.where(np.arange(w.N) % 7 == 0, b[2], 0.0)
+    plan = gpu_plan(w)
+    plan.set_config("fp64", tile=16, tile_regs=1, tile_run=3)
+    plan.set_config("fp32", tile=32, tile_regs=1, tile_run=2)
+    u, info = plan.solve(to_dev(b), precision=prec, tol=1e-12)
+    for c in range(3):
+        ref = O.solve_dense(oracle_problem(w), b[c], w.fixed, None, oracle_bonds(w))
+        err = rel_err(u.cpu().numpy()[c], ref)
+        log("runs %s case %d: %d it, rel err %.2e" % (prec, c, info[c].inner_iters, err))
+        assert info[c].status == 0 and err <= 1e-9
+
+
+def test_register_frame_run_limits():
+    import paper_2301_11828_amd as msb
+    w = W.small(2, (30, 30), 3, seed=743)
+    plan = gpu_plan(w)
+    for bad in (dict(tile=16, tile_regs=1, tile_run=0), dict(tile=16, tile_regs=1, tile_run=65)):
+        with pytest.raises(msb.MsbError) as ei:
+            plan.set_config("fp64", **bad)
+        assert ei.value.status == msb.MSB_EINVAL, bad
+    # a run longer than the launch's block count: one workgroup does every block
+    plan.set_config("fp64", tile=16, tile_regs=1, tile_run=64)
+    f = gpu_apply(plan, to_dev(w.b)).cpu().numpy()
+    ref = _oracle_apply(w, w.b)
+    assert rel_err(f[0], ref[0]) <= FP64_TOL

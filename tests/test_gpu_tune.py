@@ -44,6 +44,7 @@ def _random_configs(rng, count, dim=2):
                         threads_tile=64 * int(rng.integers(1, 9))))
         # frame 16 with register-resident transforms, the other frames with LDS stages
         out[-1]["tile_regs"] = 1 if out[-1]["tile"] == 16 else 0
+        out[-1]["tile_run"] = 3 if out[-1]["tile"] == 16 else 1
     return out
 
 
