@@ -245,6 +245,23 @@ msb_status msb_grad_infl(msb_plan plan, const double *u, const double *w, double
                          void *stream);
 
 /*
+ * msb_grad_infl for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same dL/da_k =
+ * w . (A_k u)_F, with the epilogue partial sums and per-case sums kept in a fixed 8 MiB
+ * device array that the library holds on every GPU it runs on until the process ends,
+ * instead of the plan's solver workspace.  Calls no hipMalloc or hipFree.
+ *   u, w: device [B][d][N] double; dL_da: host [B][n_infl] (written on return).
+ *   Needs 3 B P + n_infl B doubles of the array (P: epilogue partials per case of the
+ *   plan's launch configuration); larger plans get MSB_EINVAL with the sizes in the
+ *   message.  The derivative operators A_k must already exist on the plan (built by one
+ *   msb_grad_infl or msb_apply_dinfl call per k), else MSB_EINVAL.  Synchronises.
+ *   All calls on one GPU share the array: calls that overlap on one GPU (other host
+ *   threads, other streams) race and must be serialised by the caller.
+ */
+msb_status msb_grad_infl_noalloc(msb_plan plan, const double *u, const double *w, double *dL_da,
+                                 void *stream);
+
+/*
  * Measurement helper: launches every kernel of the product chain nrep times back to
  * back on `stream`, with HIP events recorded between the kernels, and returns in ms[i]
  * the mean duration in milliseconds of one launch of kernel i: 2D x-forward, y line

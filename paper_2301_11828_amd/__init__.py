@@ -29,7 +29,8 @@ EXPORTS = ("msb_plan_create", "msb_plan_destroy", "msb_plan_set_constraints", "m
            "msb_crack_to_bonds", "msb_plan_set_infl", "msb_apply", "msb_apply_dinfl", "msb_apply_precond",
            "msb_crack_update", "msb_plan_get_bonds", "msb_plan_set_surface", "msb_surface_volume_factors",
            "msb_adr_run",
-           "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_plan_info",
+           "msb_solve_static", "msb_vv_init", "msb_vv_run", "msb_grad_infl", "msb_grad_infl_noalloc",
+           "msb_plan_info",
            "msb_profile_apply", "msb_plan_get_config", "msb_plan_set_config", "msb_plan_set_lengths",
            "msb_plan_autotune", "msb_group_create", "msb_group_destroy", "msb_group_get_config",
            "msb_group_set_config", "msb_group_apply", "msb_group_set_infl", "msb_group_autotune",
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "msb_vv_init": ([P, I, P, P, P, P], I),
         "msb_vv_run": ([P, I, D, I64, P, P, P, P, P, P, I, P], I),
         "msb_grad_infl": ([P, P, P, P, P], I),
+        "msb_grad_infl_noalloc": ([P, P, P, P, P], I),
         "msb_plan_info": ([P, P, P, P], I),
         "msb_profile_apply": ([P, I, P, P, I, P, P, P], I),
         "msb_plan_get_config": ([P, I, ctypes.POINTER(_LaunchConfig)], I),
@@ -473,12 +475,15 @@ class Plan:
                                       int(nrep), ms.ctypes.data, ctypes.byref(npass), _stream()))
         return ms[:npass.value]
 
-    def grad_infl(self, u, w) -> np.ndarray:
-        """dL/da_k = w . (A_k u)_F for every case: [batch, n_infl]."""
+    def grad_infl(self, u, w, noalloc: bool = False) -> np.ndarray:
+        """dL/da_k = w . (A_k u)_F for every case: [batch, n_infl].  noalloc: the variant
+        that allocates no device memory (msb_grad_infl_noalloc; its derivative operators
+        must exist already)."""
         torch = _torch()
         out = np.zeros((self.batch, self.n_infl), dtype=np.float64)
-        _check(_lib.msb_grad_infl(self._ptr, self._vec(u, torch.float64, "u"), self._vec(w, torch.float64, "w"),
-                                  out.ctypes.data, _stream()))
+        fn = _lib.msb_grad_infl_noalloc if noalloc else _lib.msb_grad_infl
+        _check(fn(self._ptr, self._vec(u, torch.float64, "u"), self._vec(w, torch.float64, "w"), out.ctypes.data,
+                  _stream()))
         return out
 
 

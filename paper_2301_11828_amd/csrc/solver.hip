@@ -11,6 +11,7 @@
 // cases of a batch while the others continue.  Blocks of iterations can be captured
 // once into a hipGraph and replayed.
 #include <chrono>
+#include <mutex>
 #include <cstring>
 #include <cmath>
 #include <cstdlib>
@@ -1152,6 +1153,80 @@ extern "C" msb_status msb_grad_infl(msb_plan p, const double *u, const double *w
     MSB_HIP(hipStreamSynchronize(st));
     for (int b = 0; b < B; ++b)
         for (int k = 0; k < K; ++k) dL_da[(size_t)b * K + k] = w->h_scal[(size_t)k * B + b];
+    return MSB_OK;
+}
+
+// ---------------------------------------------------------------------------- gradient without allocation
+// The same gradient for callers that cannot allocate device memory: the epilogue partials
+// and the per-case sums live in `scratch`, a fixed device array the library holds on every
+// GPU it runs on until the process ends, instead of the plan's solver workspace.  Host code
+// never passes the array's name to a kernel (in host code it is a stand-in, not a device
+// address): the device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that pointer is used.
+constexpr size_t kScratchDoubles = (size_t)1 << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_ptr;   // per device: scratch's device address (null: not taken yet)
+
+msb_status scratch_for_device(int dev, double **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        MSB_HIP(hipGetDevice(&cur));
+        MSB_CHECK(cur == dev, MSB_EDEVICE, "plan's device %d is not the current device %d", dev, cur);
+        void *ptr = nullptr;
+        const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        MSB_CHECK(err == hipSuccess && ptr, MSB_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(err));
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MSB_OK;
+}
+}  // namespace
+
+extern "C" msb_status msb_grad_infl_noalloc(msb_plan p, const double *u, const double *wv, double *dL_da,
+                                            void *stream) {
+    MSB_TRY(check_plan(p));
+    MSB_CHECK(u && wv && dL_da, MSB_EINVAL, "null argument");
+    MSB_CHECK(p->n_infl > 0, MSB_EINVAL, "plan has no influence coefficients");
+    const int B = p->B, K = p->n_infl;
+    for (int k = 0; k < K; ++k)
+        MSB_CHECK((int)p->dop.size() > k && p->dop[k].count > 0, MSB_EINVAL,
+                  "derivative operator %d not built: call msb_grad_infl or msb_apply_dinfl once first", k);
+    // partials [3][B * tpc] of the widest operator's launch, then the sums [K][B]
+    size_t need = (size_t)K * B;
+    int tpc_max = 0;
+    for (int k = 0; k < K; ++k) tpc_max = std::max(tpc_max, pass_args<double>(p, p->dop[k]).ept);
+    const size_t part_n = 3 * (size_t)B * tpc_max;
+    need += part_n;
+    MSB_CHECK(need <= kScratchDoubles, MSB_EINVAL,
+              "gradient needs %zu doubles of scratch (batch %d x %d partials per case, %d coefficients); the "
+              "fixed scratch holds %zu", need, B, tpc_max, K, kScratchDoubles);
+    double *scr = nullptr;
+    MSB_TRY(scratch_for_device(p->device, &scr));
+    double *part = scr, *sums = scr + part_n;
+    hipStream_t st = (hipStream_t)stream;
+    // every tile of a launch writes its partials, and every case sum is written before it
+    // is read: nothing in the scratch needs to start at zero
+    for (int k = 0; k < K; ++k) {
+        const int tpc = pass_args<double>(p, p->dop[k]).ept;
+        EndArgs<double> e = end_args<double>();
+        e.epi = EPI_DOT;
+        e.rhs = wv;
+        e.part = part;
+        MSB_TRY(product<double>(p, p->dop[k], u, e, st));
+        hipLaunchKernelGGL(k_case_sums, dim3(B), dim3(kT), 0, st, (const double *)part, tpc, (size_t)tpc,
+                           sums + (size_t)k * B, 1.0);
+    }
+    MSB_HIP(hipGetLastError());
+    // sums [K][B] -> dL_da [B][K] (host), one strided copy per coefficient
+    for (int k = 0; k < K; ++k)
+        MSB_HIP(hipMemcpy2DAsync(dL_da + k, sizeof(double) * K, sums + (size_t)k * B, sizeof(double), sizeof(double),
+                                 B, hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipStreamSynchronize(st));
     return MSB_OK;
 }
 
