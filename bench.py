@@ -39,6 +39,23 @@ def pass_bytes(n, L, d, s):
     return [d * N * s + half, 2 * half + 3 * H * Ly * s, half + d * N * s]
 
 
+def pass_bytes_3d(n, L, s, nb):
+    """Algorithmic HBM bytes of each pass of one 3D product over nb cases (s = bytes per
+    real; d = 3; spectra 6 H Ly Lz reals read once per launch).
+    x-forward: read u, write T1 [B][d][Nz][H][Ny] complex; y-forward: read T1, write T2
+    [B][d][H][Ly][Nz] complex; z line product: read + write T2, read the spectra; y-inverse:
+    read T2, write T1; x-inverse: read T1, write f."""
+    nx, ny, nz = n
+    Lx, Ly, Lz = L
+    H = Lx // 2 + 1
+    d = 3
+    u = nb * d * nx * ny * nz * s
+    t1 = nb * d * nz * H * ny * 2 * s
+    t2 = nb * d * H * Ly * nz * 2 * s
+    spec = 6 * H * Ly * Lz * s
+    return [u + t1, t1 + t2, 2 * t2 + spec, t2 + t1, t1 + u]
+
+
 def tile_bytes(n, d, s, tl, nb=1):
     """Algorithmic HBM bytes of one launch of the tiled single-pass product over nb cases:
     read u and write f (d N reals each per case), the constraint mask (d N bytes, shared),
@@ -125,6 +142,8 @@ def main():
                     help="skip the 1 GiB copy-bandwidth measurement (counter runs: the 64 MiB copy alone "
                          "calibrates FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cube", action="store_true",
+                    help="skip the 128^3 x 16 leg of the default run (products, CG to 1e-8 in four variants)")
     ap.add_argument("--graph-block", type=int, default=int(os.environ.get("MSB_BENCH_GRAPH_BLOCK", "32")),
                     help="CG iterations per hipGraph launch in the solves (0: plain launches)")
     ap.add_argument("--no-tune", action="store_true",
@@ -381,6 +400,14 @@ def main():
                        "rel_force_residual": float(res[0]) / bn,
                        "note": "convergence of the left-clamped plate takes far more updates than CG iterations"}
 
+    if not args.no_cube and not args.no_cg:
+        # the bandwidth regime of the method: 128^3 x 16 load cases, both products and the
+        # four CG variants to 1e-8 (where refined FP32 is expected to beat FP64)
+        print("bench: cube128 x16 leg", file=sys.stderr, flush=True)
+        del pb16
+        torch.cuda.empty_cache()
+        line["cube128"] = bench_cube128(args)
+
     if not args.no_cpu:
         import oracle as O
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
@@ -394,15 +421,26 @@ def main():
             if time.perf_counter() - t0 >= args.cpu_seconds:
                 break
         dt = time.perf_counter() - t0
-        cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        cores = _cpu_cores()
         line["cpu_baseline"] = {"value": round(dofs * reps / dt / 1e9, 5), "unit": "GDOF/s",
-                                "cores": cores, "kind": "oracle",
+                                "cores": cores, "cpu_model": _cpu_model(), "kind": "oracle",
                                 "sample": "%d full FP64 bond-by-bond products of plate512 (%.1f s)" % (reps, dt)}
     print(json.dumps(line), flush=True)
 
 
 def _cpu_cores():
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+
+
+def _cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), for the CPU-baseline records."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def recorded_tuning(args, name):
@@ -441,11 +479,20 @@ def bench_crack1024(args):
     en = plan.vv_run(w.dt, w.steps, u, v, a, bf, energy_every=10)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # energy on a scale: kinetic 1/2 rho V |v|^2 and elastic -1/2 V u.(A u) of the final
+    # state (FP64 product of the FP32 state), the drift of the FP64 energy over the run
+    # relative to the larger of the two
+    V = w.h ** 2
+    u64 = u.double()
+    kin = 0.5 * w.rho * V * float((v.double() ** 2).sum())
+    ela = -0.5 * V * float((u64 * plan.apply(u64)).sum())
+    scale = max(kin, ela)
     out = {"workload": "crack1024: 2D dynamic pre-crack, 1024x1024 (2097152 DOF), delta=4h, "
                        "12654 broken bonds, FP32 velocity Verlet, FP64 energy every 10 steps",
            "steps": w.steps, "seconds": round(dt, 4), "steps_per_s": round(w.steps / dt, 1),
            "GDOF_steps_per_s": round(w.dofs * w.steps / dt / 1e9, 3),
-           "energy_first_last": [float(en[0]), float(en[-1])],
+           "energy": {"first": float(en[0]), "last": float(en[-1]), "kinetic_final": kin, "elastic_final": ela,
+                      "max_abs_change_over_run_rel_to_max_kinetic_elastic": float(np.abs(en - en[0]).max()) / scale},
            "n_bonds": plan.n_bonds, "tuned_fp32": tuned}
     # crack propagation (eq. (mu)): the stretch pass over all 2.1M x 24 half-stencil bonds
     # plus the count read-back, at a critical stretch no bond reaches (cost of the check);
@@ -470,6 +517,41 @@ def bench_crack1024(args):
                            "bonds_checked": half * w.N, "Gbond_per_s": round(half * w.N / per_call / 1e9, 2),
                            "verlet_plus_check_steps_per_s": round(nsteps / dtc, 1),
                            "bytes_per_call": 2 * w.N * 4 + 2 * w.N * 8 + w.N * 4}
+    # with real breaks: s0 set to the 2000th largest bond stretch of the loaded state (a
+    # workload parameter picked from u; the stretches near the crack tips are the largest),
+    # so one call breaks about 2000 bonds: the stretch pass, the scan, the emit pass, the
+    # host merge into the sorted broken list and the D^f list rebuild, then the product
+    # with the longer list
+    uu = u.reshape(2, w.n[1], w.n[0]).double()
+    top = []
+    for oy in range(0, w.M + 1):
+        for ox in range(-w.M, w.M + 1):
+            if (oy == 0 and ox <= 0) or ox * ox + oy * oy > w.M * w.M:
+                continue
+            dxu = uu[0, oy:, max(ox, 0):w.n[0] + min(ox, 0)] - uu[0, :w.n[1] - oy, max(-ox, 0):w.n[0] - max(ox, 0)]
+            dyu = uu[1, oy:, max(ox, 0):w.n[0] + min(ox, 0)] - uu[1, :w.n[1] - oy, max(-ox, 0):w.n[0] - max(ox, 0)]
+            r0 = w.h * (ox * ox + oy * oy) ** 0.5
+            st = torch.sqrt((ox * w.h + dxu) ** 2 + (oy * w.h + dyu) ** 2) / r0 - 1.0
+            top.append(torch.topk(st.reshape(-1), 2000).values)
+    s_break = float(torch.topk(torch.cat(top), 2000).values[-1])
+    nb0 = plan.n_bonds
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_new = plan.crack_update(u, s_break)
+    torch.cuda.synchronize()
+    t_break = time.perf_counter() - t0
+    f32 = torch.empty_like(u)
+    plan.apply(u, f32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        plan.apply(u, f32)
+    torch.cuda.synchronize()
+    out["crack_update_with_breaks"] = {
+        "s0": s_break, "bonds_before": nb0, "new_broken_bonds": n_new, "bonds_after": plan.n_bonds,
+        "ms_per_call": round(1e3 * t_break, 3),
+        "note": "one call: stretch pass over every bond, scan, emit of the new pairs, host merge, D^f rebuild",
+        "product_us_after": round(1e6 * (time.perf_counter() - t0) / 20, 2)}
     if not args.no_cpu:
         import oracle as O
         p = O.Problem(w.n, w.h, w.M, w.alpha, rho=w.rho)
@@ -478,6 +560,7 @@ def bench_crack1024(args):
         O.vv(p, np.zeros((2, w.N)), np.zeros((2, w.N)), w.b[0], w.dt, 5, None, None, br)
         dtc = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(5 / dtc, 3), "unit": "steps/s", "cores": _cpu_cores(),
+                               "cpu_model": _cpu_model(),
                                "kind": "oracle", "sample": "5 FP64 Verlet steps of crack1024"}
     return out
 
@@ -520,8 +603,19 @@ def bench_cube128(args):
         torch.cuda.synchronize()
         s = (time.perf_counter() - t0) / 10
         ks = plan.profile_apply(u, f, nrep=5)
-        out["matvec_" + str(dt)[6:]] = {"GDOF_s": round(dofs / s / 1e9, 2), "ms": round(1e3 * s, 3),
-                                        "kernels_ms": [round(float(x), 4) for x in ks]}
+        sz = 8 if dt == torch.float64 else 4
+        pb = pass_bytes_3d(w.n, plan.padded_lengths, sz, 16)
+        dom = int(np.argmax(ks))
+        names = ["x_forward", "y_forward", "z_line_product", "y_inverse", "x_inverse"]
+        ach = pb[dom] / (float(ks[dom]) * 1e-3) / 1e9
+        out["matvec_" + str(dt)[6:]] = {
+            "GDOF_s": round(dofs / s / 1e9, 2), "ms": round(1e3 * s, 3),
+            "kernels_ms": dict(zip(names, [round(float(x), 4) for x in ks])),
+            "kernels_GBs": dict(zip(names, [round(b / (float(t) * 1e-3) / 1e9, 1) for b, t in zip(pb, ks)])),
+            "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": pb[dom],
+                         "ms_per_launch": round(float(ks[dom]), 5)},
+            "chain_frac": round(sum(pb) / (float(sum(ks)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del u, f
     cg = {}
     torch.cuda.synchronize()
@@ -555,6 +649,7 @@ def bench_cube128(args):
             O.apply(p, u0, w.fixed)
         per = (time.perf_counter() - t0) / 3
         out["cpu_baseline"] = {"value": round(w.dofs / per / 1e9, 5), "unit": "GDOF/s", "cores": _cpu_cores(),
+                               "cpu_model": _cpu_model(),
                                "kind": "oracle", "sample": "3 FP64 bond-by-bond products of one 128^3 case",
                                "cg_fp64_seconds_extrapolated": round(per * 16 * cg["fp64"]["iterations_max"], 1)}
     return out
@@ -579,7 +674,13 @@ def bench_plates64(args):
         plans.append(pl)
     grp = msb.PlanGroup(plans)
     tuning = None
-    if not args.no_tune:
+    rec = recorded_tuning(args, "plates64")
+    if rec:
+        # the group tuning the gradient parity test runs at
+        grp.set_config("fp64", **rec["fp64"])
+        grp.set_config("fp32", **rec["fp32"])
+        tuning = {"fp64": rec["fp64"], "fp32": rec["fp32"], "source": "plates64_tuning.json"}
+    elif not args.no_tune:
         # the group's launch configuration picked by the group autotuner (untimed set-up)
         t0 = time.perf_counter()
         grp.autotune("fp32_refined", effort=1)

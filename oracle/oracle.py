@@ -22,13 +22,15 @@ eqs. (matrix)/(mae:e1), and the model equations built on it:
                               bond-sum apply (for grids too big to factor).
 * ``vv``                   -- velocity Verlet, Alg. 2, with a = (A u + b)/rho and
                               constrained DOFs overwritten after each update (eq. (up)).
-* ``energy``               -- kinetic + elastic - external work of the discrete system.
+* ``energy``, ``energy_parts`` -- kinetic + elastic - external work of the discrete system
+                              (and the three terms on their own).
 * ``adr_step``/``adr``     -- the quasi-static model by adaptive dynamic relaxation (Sec. 2.2,
                               eq. (ADR:e1), Alg. 1, CDEI) with the fictitious density and the
                               adaptive damping of the cited ADR method (Kilic and Madenci):
                               one update, and a run of updates.
 * ``grad_dense``           -- exact gradient of ||u - u_t||^2 w.r.t. the body force
                               and the influence coefficients a_k (omega = sum_k a_k (r/delta)^k).
+* ``grad_cg``              -- the same gradient with the two solves by CG (large plates).
 * ``crack_to_bonds``       -- broken set of eq. (mu) for a pre-crack: a bond is broken
                               iff its segment properly crosses a crack segment.
 * ``bond_stretch``         -- s of eq. (fra:s1) for given bonds, from node coordinates.
@@ -329,11 +331,9 @@ def vv(prob: Problem, u0, v0, b, dt: float, nsteps: int, fixed=None, g=None, bro
     return u, v, a, np.array(energies)
 
 
-def energy(prob: Problem, u, v, b, fixed=None, broken=None) -> float:
-    """H = 1/2 rho V sum v^2 - 1/2 V sum u (A u) - V sum b u over free DOFs.
-
-    -A is symmetric positive semidefinite, so this is the conserved energy of
-    rho u'' = A u + b (eq. (mat:e1)) and VV keeps it bounded."""
+def energy_parts(prob: Problem, u, v, b, fixed=None, broken=None):
+    """(kinetic, elastic, load) = (1/2 rho V sum v^2, -1/2 V sum u (A u), -V sum b u)
+    over free DOFs; their sum is the energy below."""
     d, N = prob.dim, prob.N
     fx = _split(prob, fixed)
     F = ~fx
@@ -342,7 +342,17 @@ def energy(prob: Problem, u, v, b, fixed=None, broken=None) -> float:
     v = np.asarray(v, dtype=np.float64).reshape(-1)
     b = np.asarray(b, dtype=np.float64).reshape(-1)
     Au = force(prob, u, broken).reshape(-1)
-    return float(0.5 * prob.rho * V * (v[F] @ v[F]) - 0.5 * V * (u[F] @ Au[F]) - V * (b[F] @ u[F]))
+    return (float(0.5 * prob.rho * V * (v[F] @ v[F])), float(-0.5 * V * (u[F] @ Au[F])),
+            float(-V * (b[F] @ u[F])))
+
+
+def energy(prob: Problem, u, v, b, fixed=None, broken=None) -> float:
+    """H = 1/2 rho V sum v^2 - 1/2 V sum u (A u) - V sum b u over free DOFs.
+
+    -A is symmetric positive semidefinite, so this is the conserved energy of
+    rho u'' = A u + b (eq. (mat:e1)) and VV keeps it bounded."""
+    kin, el, load = energy_parts(prob, u, v, b, fixed, broken)
+    return float(kin + el + load)
 
 
 def grad_dense(prob: Problem, b, u_target, fixed=None, g=None, broken=None):
@@ -371,6 +381,33 @@ def grad_dense(prob: Problem, b, u_target, fixed=None, g=None, broken=None):
         Aku = force(pk, u, broken).reshape(-1)
         ga[k] = w[F] @ Aku[F]
     return L, u.reshape(d, N), w.reshape(d, N), ga
+
+
+def grad_cg(prob: Problem, b, u_target, fixed=None, g=None, broken=None, tol: float = 1e-13,
+            maxit: int = 200000):
+    """The gradient of ``grad_dense`` with both solves by conjugate gradients (plates too
+    big to factor): u solves K(a) u = b on free DOFs (u = g on constrained), the adjoint
+    w solves K_FF w_F = 2 (u - u_t)_F (K_FF symmetric), dL/db_F = w and
+    dL/da_k = w . (A_k u)_F.  Returns (L, u, dL/db, dL/da, (iterations of u, of w),
+    (relative residuals of u, of w))."""
+    d, N = prob.dim, prob.N
+    fx = _split(prob, fixed)
+    F = ~fx
+    u, itu, resu = solve_cg(prob, b, fixed, g, broken, tol=tol, maxit=maxit)
+    u = u.reshape(-1)
+    ut = np.asarray(u_target, dtype=np.float64).reshape(-1)
+    L = float((u - ut) @ (u - ut))
+    rhs = np.where(fx, 0.0, 2.0 * (u - ut))
+    w, itw, resw = solve_cg(prob, rhs, fixed, None, broken, tol=tol, maxit=maxit)
+    w = w.reshape(-1)
+    ga = np.zeros(len(prob.infl))
+    for k in range(len(prob.infl)):
+        e = np.zeros(len(prob.infl))
+        e[k] = 1.0
+        pk = Problem(prob.n, prob.h, prob.M, prob.alpha, tuple(e), prob.rho)
+        Aku = force(pk, u, broken).reshape(-1)
+        ga[k] = w[F] @ Aku[F]
+    return L, u.reshape(d, N), w.reshape(d, N), ga, (itu, itw), (resu, resw)
 
 
 def crack_to_bonds(prob: Problem, segments) -> np.ndarray:

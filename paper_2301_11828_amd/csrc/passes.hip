@@ -366,9 +366,11 @@ __device__ __forceinline__ void line_body(const PassArgs<T> &a, const EndArgs<T>
     const int Nl = zpass ? a.Nz : a.Ny;
     const FftSched &sl = zpass ? a.sz : a.sy;
     const T2 *twg = zpass ? a.twz : a.twy;
-    const int tpc = (nlines + a.Fl - 1) / a.Fl;
-    const int b = tile / tpc;
-    const int l0 = (tile - b * tpc) * a.Fl;
+    // case-minor tile order: the B cases of a line group are consecutive tiles, which the
+    // XCD-contiguous block order runs on one XCD, so the group's spectra are read from
+    // HBM once per launch and then served from that XCD's L2 to the other cases
+    const int b = tile % a.B;
+    const int l0 = (tile / a.B) * a.Fl;
     const int nl = min(a.Fl, nlines - l0);
     const int d = a.d;
     const int L = sl.L;

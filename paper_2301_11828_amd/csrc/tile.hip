@@ -24,6 +24,45 @@ namespace msb {
 // columns; the inverse only for the T inner rows at the end).  Then D^f, the surface
 // correction and D^e are added on the inner block in LDS, and the mask and fused
 // epilogue write the outputs: u is read once (plus the halo, from L2) and f written once.
+// D^f sum of one Omega_br node p (eq. (tea:fr)): fxa, fya += sum over its directed broken
+// bonds (q, o) of v_pq W(o) (u_p - u_q), v_pq = (nu_p + nu_q) / 2 on surface-corrected rows
+// (on_e) and 1 elsewhere.  The bonds are loaded four at a time so that their index, u and
+// weight loads are in flight together; the sum runs in bond order (as one at a time).
+template <typename T>
+__device__ __forceinline__ void df_bond_sum(const PassArgs<T> &a, const T *__restrict__ uin, size_t cbase, int N,
+                                            const T *__restrict__ wt, int ei, bool on_e, double nup, double px,
+                                            double py, double &fxa, double &fya) {
+    const int t1 = a.br_bond_ptr[ei + 1];
+    for (int t0 = a.br_bond_ptr[ei]; t0 < t1; t0 += 4) {
+        int q[4], oi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = min(t0 + j, t1 - 1);
+            q[j] = a.br_q[t];
+            oi[j] = a.br_off[t];
+        }
+        double qx[4], qy[4], w0[4], w1[4], w2[4], nq[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            qx[j] = (double)uin[cbase + q[j]];
+            qy[j] = (double)uin[cbase + N + q[j]];
+            w0[j] = (double)wt[oi[j]];
+            w1[j] = (double)wt[a.n_off + oi[j]];
+            w2[j] = (double)wt[2 * a.n_off + oi[j]];
+            nq[j] = on_e ? (double)a.nu[q[j]] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (t0 + j < t1) {
+                const double dx = px - qx[j], dy = py - qy[j];
+                const double v = on_e ? 0.5 * (nup + nq[j]) : 1.0;
+                fxa += v * (w0[j] * dx + w1[j] * dy);
+                fya += v * (w1[j] * dx + w2[j] * dy);
+            }
+        }
+    }
+}
+
 template <typename T, int RMAX>
 __device__ __forceinline__ void tile_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
     using T2 = cplx_t<T>;
@@ -106,14 +145,7 @@ __device__ __forceinline__ void tile_body(const PassArgs<T> &a, const EndArgs<T>
             const double nup = on_e ? (double)a.nu[node] : 0.0;
             const double upx = (double)uin[cbase + node], upy = (double)uin[cbase + N + node];
             double fxa = 0.0, fya = 0.0;
-            for (int t0 = a.br_bond_ptr[ei], t1 = a.br_bond_ptr[ei + 1]; t0 < t1; ++t0) {
-                const int q = a.br_q[t0], oi = a.br_off[t0];
-                const double dx = upx - (double)uin[cbase + q], dy = upy - (double)uin[cbase + N + q];
-                const double wxx = (double)wt[oi], wxy = (double)wt[a.n_off + oi], wyy = (double)wt[2 * a.n_off + oi];
-                const double v = on_e ? 0.5 * (nup + (double)a.nu[q]) : 1.0;
-                fxa += v * (wxx * dx + wxy * dy);
-                fya += v * (wxy * dx + wyy * dy);
-            }
+            df_bond_sum<T>(a, uin, cbase, N, wt, ei, on_e, nup, upx, upy, fxa, fya);
             T2 &f = res[(gy - y0) * P + (gx - x0)];
             f.x += T(fxa);
             f.y += T(fya);
@@ -382,15 +414,7 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
                 const double nup = on_e ? (double)a.nu[node] : 0.0;
                 const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
                 double fxa = 0.0, fya = 0.0;
-                for (int t0 = a.br_bond_ptr[ei], t1 = a.br_bond_ptr[ei + 1]; t0 < t1; ++t0) {
-                    const int q = a.br_q[t0], oi = a.br_off[t0];
-                    const double dx = px - (double)uin[cbase + q], dy = py - (double)uin[cbase + N + q];
-                    const double wxx = (double)wt[oi], wxy = (double)wt[a.n_off + oi],
-                                 wyy = (double)wt[2 * a.n_off + oi];
-                    const double vf = on_e ? 0.5 * (nup + (double)a.nu[q]) : 1.0;
-                    fxa += vf * (wxx * dx + wxy * dy);
-                    fya += vf * (wxy * dx + wyy * dy);
-                }
+                df_bond_sum<T>(a, uin, cbase, N, wt, ei, on_e, nup, px, py, fxa, fya);
                 T2 &c = cor[(qy - y0 + M) * P + (qx - x0 + M)];
                 c.x += T(fxa);
                 c.y += T(fya);
@@ -623,15 +647,7 @@ __device__ __forceinline__ void reg_tile_process(const PassArgs<T> &a, const End
                 const double nup = on_e ? (double)a.nu[node] : 0.0;
                 const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
                 double fxa = 0.0, fya = 0.0;
-                for (int t0 = a.br_bond_ptr[ei], t1 = a.br_bond_ptr[ei + 1]; t0 < t1; ++t0) {
-                    const int q = a.br_q[t0], oi = a.br_off[t0];
-                    const double dx = px - (double)uin[cbase + q], dy = py - (double)uin[cbase + N + q];
-                    const double wxx = (double)wt[oi], wxy = (double)wt[a.n_off + oi],
-                                 wyy = (double)wt[2 * a.n_off + oi];
-                    const double vf = on_e ? 0.5 * (nup + (double)a.nu[q]) : 1.0;
-                    fxa += vf * (wxx * dx + wxy * dy);
-                    fya += vf * (wxy * dx + wyy * dy);
-                }
+                df_bond_sum<T>(a, uin, cbase, N, wt, ei, on_e, nup, px, py, fxa, fya);
                 T2 &c = cor[(qy - g.y0 + M) * P + (qx - g.x0 + M)];
                 c.x += T(fxa);
                 c.y += T(fya);

@@ -73,3 +73,68 @@ def test_per_case_influence_batch():
             Aku = O.force(oracle_problem(w, infl=tuple(e)), uu[c])
             ref = (wv[c] * Aku)[~w.fixed].sum()
             assert ga[c, k] == pytest.approx(ref, rel=1e-11, abs=1e-12 * abs(ref) + 1e-300)
+
+
+def _plates64_group(tuning_path=None):
+    """The benchmark's 64-plate batch as one plan group, at the recorded group tuning."""
+    import json
+    import os
+    import paper_2301_11828_amd as msb
+    ws = W.plates64()
+    plans = []
+    for w in ws:
+        pl = msb.Plan(w.n, w.h, w.M, w.alpha, infl=w.infl, batch=1)
+        pl.set_constraints(w.fixed)
+        plans.append(pl)
+    grp = msb.PlanGroup(plans)
+    path = tuning_path or os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                                       "plates64_tuning.json")
+    if os.path.exists(path):
+        rec = json.load(open(path))
+        grp.set_config("fp64", **rec["fp64"])
+        grp.set_config("fp32", **rec["fp32"])
+    return ws, plans, grp
+
+
+def _oracle_rows():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plates64_grad_oracle.txt")
+    rows = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows[int(f[0])] = dict(size=int(f[1]), L=float(f[2]), ga=np.array([float(x) for x in f[3:11]]))
+    return rows
+
+
+@pytest.mark.parametrize("tol", [1e-11, 1e-10])
+def test_plates64_member_gradients_vs_oracle_cg(tol):
+    """The benchmark's pipeline (target solve with the perturbed coefficients, forward
+    solve, loss, group adjoint solve, dL/da) on the 64-plate group at its recorded tuning,
+    FP32-refined: the first member of every size (64^2 ... 384^2) against the oracle's CG
+    gradient (tests/golden/plates64_grad_oracle.txt, written by make_plates64_grad.py from
+    the oracle alone; its solves to 1e-13, the adjoint's true residual 1e-13 ... 8e-12).  Error
+    bound from the solve tolerances: the gradient error is about kappa (tol + 1e-11) with
+    kappa <= 2e4 at 384^2 (1e-11 is near the FP64 residual floor eps kappa of that plate)."""
+    import torch
+    import paper_2301_11828_amd as msb
+    rows = _oracle_rows()
+    ws, plans, grp = _plates64_group()
+    bs = [torch.from_numpy(w.b).cuda().requires_grad_(True) for w in ws]
+    as_ = [torch.tensor(w.infl, dtype=torch.float64, requires_grad=True) for w in ws]
+    grp.set_infl([np.asarray(w.extra["infl_target"]) for w in ws])
+    uts, infos = grp.solve([b.detach() for b in bs], precision="fp32_refined", tol=tol)
+    us = msb.make_group_solve_function().apply(grp, "fp32_refined", tol, *bs, *as_)
+    losses = [((u - ut) ** 2).sum() for u, ut in zip(us, uts)]
+    sum(losses).backward()
+    worst = 0.0
+    for i, r in sorted(rows.items()):
+        g = as_[i].grad.numpy()
+        err = np.abs(g - r["ga"]).max() / np.abs(r["ga"]).max()
+        el = abs(losses[i].item() - r["L"]) / r["L"]
+        log("plates64[%d] %d^2 tol %.0e: dL/da max rel err %.2e, loss rel err %.2e" % (i, r["size"], tol, err, el))
+        worst = max(worst, err)
+        assert err <= (1e-6 if tol <= 1e-11 else 1e-5) and el <= (1e-6 if tol <= 1e-11 else 1e-5)
+    assert len(rows) == 5
+    grp.close()

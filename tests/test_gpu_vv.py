@@ -92,3 +92,50 @@ def test_crack1024_fp32_short_run_vs_oracle():
         log("crack1024 FP32 VV %d steps (%s configuration) vs FP64 oracle: rel err u %.2e v %.2e" %
             (w.steps, name, eu, ev))
         assert eu <= 1e-4 and ev <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_crack1024_1000_steps_vs_oracle(prec):
+    """The benchmark's dynamic run (1024^2, delta = 4h, 12,654 pre-broken bonds, opposing
+    edge loads, 1000 Verlet steps, Alg. 2) at the recorded tuning, against the oracle's FP64
+    trajectory sampled at 4096 seeded DOFs after 10, 100 and 1000 steps
+    (tests/golden/crack1024_vv_oracle.npz, written by make_crack1024_vv.py from the oracle
+    alone), and the energy every 10 steps against the oracle's.  The errors are stated;
+    FP64 keeps the 1e-12 parity bar at every sample, FP32 state is bounded at 1e-4."""
+    import json
+    import os
+    import torch
+    here = os.path.dirname(os.path.abspath(__file__))
+    g = np.load(os.path.join(here, "golden", "crack1024_vv_oracle.npz"))
+    w = W.crack1024(steps=1000)
+    assert abs(float(g["dt"]) - w.dt) <= 1e-15 * w.dt
+    plan = gpu_plan(w)
+    assert plan.n_bonds == int(g["n_bonds"])
+    rec = json.load(open(os.path.join(os.path.dirname(here), "profiles", "crack1024_tuning.json")))
+    plan.set_lengths(rec["padded"])
+    plan.set_config("fp32", **rec["fp32"])
+    dt_ = torch.float32 if prec == "fp32" else torch.float64
+    u = torch.zeros((1, 2, w.N), dtype=dt_, device="cuda")
+    v = torch.zeros_like(u)
+    b = to_dev(w.b, dt_)
+    a = plan.vv_init(u, b)
+    idx = torch.from_numpy(g["idx"]).cuda()
+    en, done = [], 0
+    for n in (10, 100, 1000):
+        en.append(plan.vv_run(w.dt, n - done, u, v, a, b, energy_every=10))
+        done = n
+        us = u.reshape(-1)[idx].double().cpu().numpy()
+        vs = v.reshape(-1)[idx].double().cpu().numpy()
+        eu, ev = rel_err(us, g["u%d" % n]), rel_err(vs, g["v%d" % n])
+        log("crack1024 %s VV step %d vs FP64 oracle (4096 sampled DOFs): rel err u %.2e v %.2e" % (prec, n, eu, ev))
+        assert eu <= (1e-4 if prec == "fp32" else 1e-12) and ev <= (1e-4 if prec == "fp32" else 1e-12)
+    en = np.concatenate(en)
+    parts = g["energy_parts"]
+    eo = parts.sum(axis=1)
+    scale = max(parts[:, 0].max(), parts[:, 1].max())     # max kinetic, max elastic over the run
+    de = np.abs(en - eo).max() / scale
+    drift = np.abs(eo - eo[0]).max() / scale
+    log("crack1024 %s energy vs oracle: max |dE| / max(kinetic, elastic) %.2e; oracle's own energy drift over "
+        "1000 steps %.2e of that scale (max kinetic %.3e, max elastic %.3e)" %
+        (prec, de, drift, parts[:, 0].max(), parts[:, 1].max()))
+    assert len(en) == 100 and de <= (1e-3 if prec == "fp32" else 1e-10)

@@ -456,6 +456,62 @@ def test_gradient_matches_central_differences():
     assert np.all(gb[fixed] == 0)
 
 
+def test_cg_gradient_equals_dense_gradient_small_plates():
+    """The CG form of the adjoint gradient (two CG solves, the derivative products)
+    equals the dense-Cholesky gradient (itself pinned by finite differences above) on
+    plates with a crack, prescribed displacements and all eight coefficients."""
+    rng = np.random.default_rng(12)
+    for nx, ny, M, crack in ((13, 11, 2, False), (17, 15, 3, True)):
+        a = rng.uniform(0.1, 1.0, size=8)
+        h = 1.0 / max(nx, ny)
+        p = O.Problem((nx, ny), h, M, O.alpha_2d(1.0, M * h), tuple(a))
+        fixed = _dirichlet_layer(p)
+        br = O.crack_to_bonds(p, [[0.2, 0.3, 0.8, 0.7]]) if crack else None
+        b = rng.standard_normal((2, p.N))
+        g = np.where(fixed, 1e-3 * rng.standard_normal((2, p.N)), 0.0)
+        ut = np.where(fixed, g, 1e-3 * rng.standard_normal((2, p.N)))
+        Ld, ud, gbd, gad = O.grad_dense(p, b, ut, fixed, g, br)
+        Lc, uc, gbc, gac, its, res = O.grad_cg(p, b, ut, fixed, g, br, tol=1e-14)
+        assert res[0] <= 1e-14 and res[1] <= 1e-14
+        assert Lc == pytest.approx(Ld, rel=1e-10)
+        assert np.abs(gac - gad).max() <= 1e-9 * np.abs(gad).max()
+        assert np.abs(gbc - gbd).max() <= 1e-9 * np.abs(gbd).max()
+
+
+def test_cg_gradient_equals_dense_gradient_on_a_64x64_plate():
+    """The 64 x 64 member of the 64-plate batch (omega = sum_k a_k (r/delta)^k, all sides
+    fixed, target from the perturbed coefficients): dense and CG gradients agree."""
+    from paper_2301_11828_amd import workloads as W
+    ws = W.plates64()
+    w = next(x for x in ws if x.n[0] == 64)
+    p = O.Problem(w.n, w.h, w.M, w.alpha, w.infl)
+    pt = O.Problem(w.n, w.h, w.M, w.alpha, w.extra["infl_target"])
+    ut, _, _ = O.solve_cg(pt, w.b[0], w.fixed, tol=1e-14)
+    Ld, _, gbd, gad = O.grad_dense(p, w.b[0], ut, w.fixed)
+    Lc, _, gbc, gac, its, res = O.grad_cg(p, w.b[0], ut, w.fixed, tol=1e-13)
+    assert Lc == pytest.approx(Ld, rel=1e-9)
+    assert np.abs(gac - gad).max() <= 1e-8 * np.abs(gad).max()
+    assert np.abs(gbc - gbd).max() <= 1e-8 * np.abs(gbd).max()
+
+
+def test_energy_parts_sum_to_the_energy():
+    """Kinetic, elastic and load terms: their sum is the energy; at u = 0 only the
+    kinetic term 1/2 rho V v.v remains (free DOFs); elastic = -1/2 V u.(A u) >= 0."""
+    rng = np.random.default_rng(13)
+    p = _prob2(11, 9, 3)
+    p.rho = 1.7
+    fixed = _dirichlet_layer(p)
+    u, v, b = (rng.standard_normal((2, p.N)) for _ in range(3))
+    kin, el, load = O.energy_parts(p, u, v, b, fixed)
+    assert kin + el + load == O.energy(p, u, v, b, fixed)
+    assert el >= 0.0 and kin >= 0.0
+    V = p.h ** 2
+    F = ~fixed.reshape(-1)
+    k0, e0, l0 = O.energy_parts(p, np.zeros((2, p.N)), v, b, fixed)
+    assert e0 == 0.0 and l0 == 0.0
+    assert k0 == pytest.approx(0.5 * p.rho * V * float(v.reshape(-1)[F] @ v.reshape(-1)[F]), rel=1e-15)
+
+
 def test_lift_equals_dense_block():
     """b_F - K_FC g_C computed with the bond-sum apply equals the dense block product."""
     rng = np.random.default_rng(12)
