@@ -77,7 +77,7 @@ def counters(dfetch: str, dwrite: str, copy_bytes: float):
     fe, wr = _counter(dfetch, "FETCH_SIZE"), _counter(dwrite, "WRITE_SIZE")
 
     def copy_kernel(vals):
-        cands = {k: v for k, v in vals.items() if "copy" in k[0].lower() or "elementwise" in k[0].lower()}
+        cands = {k: v for k, v in vals.items() if "copybuffer" in k[0].lower()}
         return max(cands.items(), key=lambda kv: max(kv[1])) if cands else (None, None)
 
     ck, cf = copy_kernel(fe)
