@@ -535,7 +535,15 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *red, int tid, 
 __device__ __forceinline__ double block_sum_partials(const double *__restrict__ p, int n,
                                                      double *red, int tid, int nt) {
     double v[1] = {0.0};
-    for (int i = tid; i < n; i += nt) v[0] += p[i];
+    // four strided loads in flight per step; each thread adds its partials in index order
+    for (int i0 = tid; i0 < n; i0 += 4 * nt) {
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = i0 + u * nt < n ? p[i0 + u * nt] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * nt < n) v[0] += x[u];
+    }
     block_sum<1>(v, red, tid, nt);
     if (tid == 0) red[64] = v[0];
     __syncthreads();
@@ -560,10 +568,19 @@ __device__ __forceinline__ void block_sum_partials_k(const double *const (&p)[K]
         v[k] = 0.0;
         nmax = n[k] > nmax ? n[k] : nmax;
     }
-    for (int i = tid; i < nmax; i += nt) {
+    // four strided loads per array in flight per step; each thread adds its partials of
+    // every array in index order (the order of one load at a time)
+    for (int i0 = tid; i0 < nmax; i0 += 4 * nt) {
+        double x[4][K];
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (i < n[k]) v[k] += p[k][i];
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) x[u][k] = i0 + u * nt < n[k] ? p[k][i0 + u * nt] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (i0 + u * nt < n[k]) v[k] += x[u][k];
     }
     block_sum<K>(v, red, tid, nt);
     if (tid == 0) {

@@ -26,24 +26,24 @@ namespace msb {
 // epilogue write the outputs: u is read once (plus the halo, from L2) and f written once.
 // D^f sum of one Omega_br node p (eq. (tea:fr)): fxa, fya += sum over its directed broken
 // bonds (q, o) of v_pq W(o) (u_p - u_q), v_pq = (nu_p + nu_q) / 2 on surface-corrected rows
-// (on_e) and 1 elsewhere.  The bonds are loaded four at a time so that their index, u and
+// (on_e) and 1 elsewhere.  The bonds are loaded U at a time so that their index, u and
 // weight loads are in flight together; the sum runs in bond order (as one at a time).
-template <typename T>
+template <typename T, int U = 4>
 __device__ __forceinline__ void df_bond_sum(const PassArgs<T> &a, const T *__restrict__ uin, size_t cbase, int N,
                                             const T *__restrict__ wt, int ei, bool on_e, double nup, double px,
                                             double py, double &fxa, double &fya) {
     const int t1 = a.br_bond_ptr[ei + 1];
-    for (int t0 = a.br_bond_ptr[ei]; t0 < t1; t0 += 4) {
-        int q[4], oi[4];
+    for (int t0 = a.br_bond_ptr[ei]; t0 < t1; t0 += U) {
+        int q[U], oi[U];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < U; ++j) {
             const int t = min(t0 + j, t1 - 1);
             q[j] = a.br_q[t];
             oi[j] = a.br_off[t];
         }
-        double qx[4], qy[4], w0[4], w1[4], w2[4], nq[4];
+        double qx[U], qy[U], w0[U], w1[U], w2[U], nq[U];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < U; ++j) {
             qx[j] = (double)uin[cbase + q[j]];
             qy[j] = (double)uin[cbase + N + q[j]];
             w0[j] = (double)wt[oi[j]];
@@ -52,7 +52,7 @@ __device__ __forceinline__ void df_bond_sum(const PassArgs<T> &a, const T *__res
             nq[j] = on_e ? (double)a.nu[q[j]] : 0.0;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < U; ++j) {
             if (t0 + j < t1) {
                 const double dx = px - qx[j], dy = py - qy[j];
                 const double v = on_e ? 0.5 * (nup + nq[j]) : 1.0;
@@ -286,7 +286,9 @@ struct RegLine {
 
 // One block per workgroup (tile_run = 1): every load of the block is issued at the start
 // (spectra, u, constraint bits, D^e blocks), the D^e term is formed from u as it lands.
-template <typename T, int TL>
+// CGQ: the CG epilogue (q = K p, partials p.q, r.q, q.q), whose p and r at the thread's
+// output points are loaded before the inverse transforms so that the loads overlap them.
+template <typename T, int TL, bool CGQ>
 __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
     using T2 = cplx_t<T>;
     constexpr int R = RegShape<TL>::R, S = RegShape<TL>::S, RA = R / S, P = TL + 1;
@@ -382,6 +384,22 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
             v[i] = W;
         }
     }
+    // CG epilogue: p (= u) and r at the output points, loaded now (in flight during the inverse)
+    T pux[R], puy[R], prx[R], pry[R];
+    if (CGQ) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int ly = p + S * i;
+            pux[i] = puy[i] = prx[i] = pry[i] = T(0);
+            if (col_inner && ly >= M && ly < M + ny) {
+                const size_t node = (size_t)(y0 - M + ly) * Nx + gx;
+                pux[i] = uin[cbase + node];
+                puy[i] = uin[cbase + N + node];
+                prx[i] = e.rhs[cbase + node];
+                pry[i] = e.rhs[cbase + N + node];
+            }
+        }
+    }
     // inverse: rows, transpose, columns
     RegLine<T, TL, 1>::run(v, buf0 + ln * P, 1, p, tw);
 #pragma unroll
@@ -468,10 +486,24 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
                 const size_t node = (size_t)(y0 - M + ly) * Nx + gx;
                 const T fx = v[i].x + dcor[i].x, fy = v[i].y + dcor[i].y;
                 const size_t ax = cbase + node, ay = ax + N;
-                epilogue_at<T>(e, uin, ax, node + pb, fx, (fixbits >> (2 * i)) & 1u, sign, rinv, dth, acc0, acc1,
-                               acc2);
-                epilogue_at<T>(e, uin, ay, N + node + pb, fy, (fixbits >> (2 * i + 1)) & 1u, sign, rinv, dth, acc0,
-                               acc1, acc2);
+                if (CGQ) {
+                    // EPI_CG_Q with the preloaded p and r (the same arithmetic as epilogue_at)
+                    const T qx = (fixbits >> (2 * i)) & 1u ? T(0) : -fx;
+                    const T qy = (fixbits >> (2 * i + 1)) & 1u ? T(0) : -fy;
+                    e.out[ax] = qx;
+                    acc0 += (double)pux[i] * (double)qx;
+                    acc1 += (double)prx[i] * (double)qx;
+                    acc2 += (double)qx * (double)qx;
+                    e.out[ay] = qy;
+                    acc0 += (double)puy[i] * (double)qy;
+                    acc1 += (double)pry[i] * (double)qy;
+                    acc2 += (double)qy * (double)qy;
+                } else {
+                    epilogue_at<T>(e, uin, ax, node + pb, fx, (fixbits >> (2 * i)) & 1u, sign, rinv, dth, acc0,
+                                   acc1, acc2);
+                    epilogue_at<T>(e, uin, ay, N + node + pb, fy, (fixbits >> (2 * i + 1)) & 1u, sign, rinv, dth,
+                                   acc0, acc1, acc2);
+                }
             }
         }
     }
@@ -487,9 +519,9 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
     }
 }
 
-template <typename T, int TL>
+template <typename T, int TL, bool CGQ>
 __global__ __launch_bounds__(RegShape<TL>::S * TL) void k_tile_reg1(PassArgs<T> a, EndArgs<T> e) {
-    tile_reg_body<T, TL>(a, e, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+    tile_reg_body<T, TL, CGQ>(a, e, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // What a thread holds of one tile between its loads and its transforms: u at its R
@@ -647,7 +679,7 @@ __device__ __forceinline__ void reg_tile_process(const PassArgs<T> &a, const End
                 const double nup = on_e ? (double)a.nu[node] : 0.0;
                 const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
                 double fxa = 0.0, fya = 0.0;
-                df_bond_sum<T>(a, uin, cbase, N, wt, ei, on_e, nup, px, py, fxa, fya);
+                df_bond_sum<T, 1>(a, uin, cbase, N, wt, ei, on_e, nup, px, py, fxa, fya);
                 T2 &c = cor[(qy - g.y0 + M) * P + (qx - g.x0 + M)];
                 c.x += T(fxa);
                 c.y += T(fya);
@@ -805,6 +837,30 @@ template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Register-frame launch for frame length TL: runs of blocks, the CG-epilogue form (frame 16,
+// whose registers leave room for the preloaded p and r) or the plain one-block form.
+template <typename T, int TL>
+static hipError_t launch_reg(const PassArgs<T> &a, const EndArgs<T> &e, dim3 gridr, dim3 grid, size_t lr, int reps,
+                             hipStream_t st) {
+    hipError_t err;
+    const dim3 block(RegShape<TL>::S * TL);
+    if (a.tper > 1) {
+        if ((err = allow_lds(k_tile_reg<T, TL>, lr)) != hipSuccess) return err;
+        for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile_reg<T, TL>), gridr, block, lr, st, a, e);
+        return hipGetLastError();
+    }
+    if constexpr (TL == 16) {
+        if (e.epi == EPI_CG_Q) {
+            if ((err = allow_lds(k_tile_reg1<T, TL, true>, lr)) != hipSuccess) return err;
+            for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile_reg1<T, TL, true>), grid, block, lr, st, a, e);
+            return hipGetLastError();
+        }
+    }
+    if ((err = allow_lds(k_tile_reg1<T, TL, false>, lr)) != hipSuccess) return err;
+    for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile_reg1<T, TL, false>), grid, block, lr, st, a, e);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_tile_kernel(const PassArgs<T> &a, const EndArgs<T> &e, size_t lds, bool composite, int reps,
                               hipStream_t st) {
@@ -815,26 +871,12 @@ hipError_t launch_tile_kernel(const PassArgs<T> &a, const EndArgs<T> &e, size_t 
         const size_t lr = 2 * (size_t)a.tl * (a.tl + 1) * sizeof(cplx_t<T>);
         const int tiles = a.B * a.ttx * a.tty;
         const dim3 gridr((tiles + a.tper - 1) / a.tper);
-#define MSB_TILE_REG(TLV)                                                                             \
-    case TLV:                                                                                         \
-        if (a.tper > 1) {                                                                             \
-            if ((err = allow_lds(k_tile_reg<T, TLV>, lr)) != hipSuccess) return err;                  \
-            for (int k = 0; k < reps; ++k)                                                            \
-                hipLaunchKernelGGL((k_tile_reg<T, TLV>), gridr, dim3(RegShape<TLV>::S * TLV), lr, st, a, e); \
-        } else {                                                                                      \
-            if ((err = allow_lds(k_tile_reg1<T, TLV>, lr)) != hipSuccess) return err;                 \
-            for (int k = 0; k < reps; ++k)                                                            \
-                hipLaunchKernelGGL((k_tile_reg1<T, TLV>), grid, dim3(RegShape<TLV>::S * TLV), lr, st, a, e); \
-        }                                                                                             \
-        break;
         switch (a.tl) {
-            MSB_TILE_REG(16)
-            MSB_TILE_REG(32)
-            MSB_TILE_REG(64)
+            case 16: return launch_reg<T, 16>(a, e, gridr, grid, lr, reps, st);
+            case 32: return launch_reg<T, 32>(a, e, gridr, grid, lr, reps, st);
+            case 64: return launch_reg<T, 64>(a, e, gridr, grid, lr, reps, st);
             default: return hipErrorInvalidValue;
         }
-#undef MSB_TILE_REG
-        return hipGetLastError();
     }
     if (composite) {
         if ((err = allow_lds(k_tile<T, 16>, lds)) != hipSuccess) return err;
