@@ -122,8 +122,13 @@ int next_smooth(int nmin, bool even_only);
 // scaled by 1/tl^2.
 struct TileSpec {
     int tl = 0;
-    double *s64 = nullptr;
+    double *s64 = nullptr;   // [slots][3][tl][tl]
     float *s32 = nullptr;
+    // frames with register-resident transforms (tl = R S: 16, 32, 64): the same values in the
+    // order the kernel's threads load them, [slots][3][R][S tl], entry (i, t) = spectrum at
+    // ky = t mod tl, kx = t div tl + S i (each register's loads are one contiguous run)
+    double *r64 = nullptr;
+    float *r32 = nullptr;
 };
 
 struct DeviceOp {

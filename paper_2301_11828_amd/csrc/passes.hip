@@ -1124,6 +1124,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.tthreads = c.threads_tile;
     a.twt = nullptr;
     a.tspec = nullptr;
+    a.tspecr = nullptr;
     a.tspec_slot = 0;
     a.stl = FftSched{};
     if (c.tile > 0 && p->dim == 2) {
@@ -1139,6 +1140,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
             a.stl = make_sched(*ta, f32, c.max_radix);
             a.twt = tw_of<T>(*ta);
             a.tspec = sel<T>(ts->s64, ts->s32);
+            a.tspecr = sel<T>(ts->r64, ts->r32);
             a.tspec_slot = multi ? (size_t)3 * c.tile * c.tile : 0;
             a.ept = a.ttx * a.tty;
             a.treg = c.tile_regs;

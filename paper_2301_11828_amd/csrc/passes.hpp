@@ -79,6 +79,7 @@ template <typename T> struct PassArgs {
     FftSched stl;
     const cplx_t<T> *twt;
     const T *tspec;
+    const T *tspecr;     // the same spectra in the register-frame thread order (tl = 16, 32, 64)
     size_t tspec_slot;
     // slots per case of the epilogue partial sums: the x-inverse tiles of the chain, or
     // the tiles of the tiled product

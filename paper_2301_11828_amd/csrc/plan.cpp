@@ -638,6 +638,8 @@ static void free_tiles(DeviceOp &op) {
     for (TileSpec &t : op.tiles) {
         if (t.s64) (void)hipFree(t.s64);
         if (t.s32) (void)hipFree(t.s32);
+        if (t.r64) (void)hipFree(t.r64);
+        if (t.r32) (void)hipFree(t.r32);
     }
     op.tiles.clear();
 }
@@ -698,8 +700,24 @@ static msb_status build_tile_spec(msb_plan_s *p, DeviceOp &op, int tl) {
     t.tl = tl;
     MSB_TRY(upload(&t.s64, all));
     msb_status st = upload(&t.s32, std::vector<float>(all.begin(), all.end()));
+    // the register-frame order: R points per thread at kx = p + S i of line ky = ln, thread
+    // t = p tl + ln; entry (i, t) of each component block
+    const int R = tl == 16 ? 4 : 8, S = tl == 64 ? 8 : 4;
+    if (st == MSB_OK && (tl == 16 || tl == 32 || tl == 64)) {
+        std::vector<double> reg(all.size());
+        const size_t blk = (size_t)tl * tl;
+        for (size_t k = 0; k < (size_t)3 * op.count; ++k)
+            for (int i = 0; i < R; ++i)
+                for (int th = 0; th < S * tl; ++th) {
+                    const int ky = th % tl, kx = th / tl + S * i;
+                    reg[k * blk + (size_t)i * S * tl + th] = all[k * blk + (size_t)ky * tl + kx];
+                }
+        st = upload(&t.r64, reg);
+        if (st == MSB_OK) st = upload(&t.r32, std::vector<float>(reg.begin(), reg.end()));
+    }
     if (st != MSB_OK) {
-        (void)hipFree(t.s64);
+        for (void *x : {(void *)t.s64, (void *)t.s32, (void *)t.r64, (void *)t.r32})
+            if (x) (void)hipFree(x);
         return st;
     }
     op.tiles.push_back(t);

@@ -316,14 +316,15 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
     for (int q = 0; q < RA; ++q)
 #pragma unroll
         for (int m = 0; m < S; ++m) tw[q][m] = a.twt[(p + S * q) * m];
-    // frame spectra of Z(ky = ln, kx = p + S i)
-    const T *g = a.tspec + (size_t)b * a.tspec_slot + ln * TL + p;
+    // frame spectra of Z(ky = ln, kx = p + S i), stored in this thread order: register i of
+    // all threads is one contiguous run
+    const T *g = a.tspecr + (size_t)b * a.tspec_slot + tid;
     T ga[R], gr[R], gi[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        ga[i] = g[S * i];
-        gr[i] = g[TL * TL + S * i];
-        gi[i] = g[2 * TL * TL + S * i];
+        ga[i] = g[i * S * TL];
+        gr[i] = g[TL * TL + i * S * TL];
+        gi[i] = g[2 * TL * TL + i * S * TL];
     }
     // load: column layout, patch (row p + S i, column ln) = grid (x0 - M + ln, y0 - M + p + S i);
     // the D^e block of inner nodes within M of a face applied to u at load time, and the
@@ -798,12 +799,12 @@ __device__ __forceinline__ void tile_reg_run(const PassArgs<T> &a, const EndArgs
         if (!(e.case_done && e.case_done[g.b])) {
             const int slot = a.tspec_slot ? g.b : 0;
             if (slot != gb) {
-                const T *gs = a.tspec + (size_t)slot * a.tspec_slot + ln * TL + p;
+                const T *gs = a.tspecr + (size_t)slot * a.tspec_slot + tid;
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    ga[i] = gs[S * i];
-                    gr[i] = gs[TL * TL + S * i];
-                    gi[i] = gs[2 * TL * TL + S * i];
+                    ga[i] = gs[i * S * TL];
+                    gr[i] = gs[TL * TL + i * S * TL];
+                    gi[i] = gs[2 * TL * TL + i * S * TL];
                 }
                 gb = slot;
             }
