@@ -34,7 +34,10 @@ def _short(name: str) -> str:
               "k_dot_parts", "k_stretch", "k_scan", "k_emit", "k_tile"):
         if k in name:
             prec = "double" if "<double" in name else ("float" if "<float" in name else "")
-            return "%s<%s%s>" % (k, prec, ",wave" if "false" in name.split(k)[1][:40] else "")
+            # chain passes: the BLOCK template flag false marks wave-owned teams
+            wave = k in ("k_xfwd", "k_line_y", "k_line_z", "k_xinv", "k_yfwd", "k_yinv") and \
+                "false" in name.split(k)[1][:40]
+            return "%s<%s%s>" % (k, prec, ",wave" if wave else "")
     return name[:60]
 
 
