@@ -315,7 +315,8 @@ msb_status msb_plan_info(msb_plan plan, int64_t *L, int64_t *N, int64_t *n_bonds
  *                   applies before the one store.  One read of u, one write of f,
  *                   one launch.  A fused solver update runs first as its own
  *                   elementwise pass (the patches overlap).  The preconditioner of
- *                   the solvers and plan groups always use the global chain.
+ *                   the solvers always uses the global chain; plan groups run one
+ *                   launch over the blocks of all members (tile_run must be 1).
  *   threads_tile    threads per workgroup of the tiled product, multiple of 64,
  *                   64..512
  *   tile_regs       0: the tiled product's frame transforms run as LDS Stockham
@@ -384,9 +385,11 @@ msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int 
 /*
  * Plan groups: several plans of the same dimension (grids of different sizes, each
  * with its own batch of cases, constraints, bonds and operator) whose products run
- * as one launch per pass.  Every kernel's grid covers the tiles of all members; each
- * workgroup finds its member in a table of tile offsets and reads that member's
- * arguments from device memory.  The group's CG advances every case of every member
+ * as one launch per pass (2D with tile > 0: one launch of the tiled product over the
+ * blocks of all members, after a transform-free pass for a fused solver update).
+ * Every kernel's grid covers the tiles of all members; each workgroup finds its
+ * member in a table of tile offsets and reads that member's arguments from device
+ * memory.  The group's CG advances every case of every member
  * in the same launches, with per-case stop flags, and hipGraph capture of blocks of
  * iterations (graph_block) as for one plan.  For many small grids this replaces one
  * latency-bound launch chain per grid by one chain for all of them.
@@ -395,7 +398,10 @@ msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int 
  *   device.  The group refers to the plans, which must outlive it and may still be
  *   used on their own (not concurrently with group calls on the same stream).  The
  *   common launch configuration is the largest member's when every member accepts
- *   it, else one row / one line per workgroup (msb_group_set_config changes it).
+ *   it (its tile_run set to 1), else one row / one line per workgroup and no tiles
+ *   (msb_group_set_config changes it: every member must accept the configuration,
+ *   tile_run > 1 with tile > 0 is MSB_EINVAL).  A tiled configuration builds each
+ *   member's frame spectra for that length.
  * msb_group_apply: f_i = A_i u_i for every member i; u, f: host arrays [nplans] of
  *   device pointers laid out as for msb_apply.  Synchronises `stream` first (the
  *   group's argument arrays are rewritten).
@@ -412,7 +418,8 @@ msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int 
  *   runs on parallel host threads, the uploads follow in member order.  Validates
  *   every member before changing any; synchronises the device.
  * msb_group_autotune: the coordinate search of msb_plan_autotune (x passes and line
- *   passes, each with two-buffer and in-place stages, then max_radix) over
+ *   passes, each with two-buffer and in-place stages, then max_radix, then in 2D the
+ *   tiled product's frame lengths at one block per workgroup) over
  *   configurations every member accepts, each timed as whole group products of all
  *   members; keeps the fastest in the group (both precisions for
  *   MSB_FP32_REFINED).  best / best_ms as for msb_plan_autotune.  Allocates one input

@@ -503,6 +503,18 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
     return x * q + (x < r ? x : r) + local;
 }
 
+// Plan groups: one grid over the workgroups of several plans, start[] their offsets
+// (start[n] = the total); the member owning workgroup g is the largest i with start[i] <= g.
+__device__ __forceinline__ int group_member(const int *__restrict__ start, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Block-wide sum of up to 4 FP64 values per thread in a fixed order (deterministic):
 // wave64 butterfly shuffles, then the waves' results added in wave order by thread 0.
 // red: LDS scratch of >= 16 K doubles (up to 16 waves).  Result valid in thread 0.

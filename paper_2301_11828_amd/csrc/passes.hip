@@ -851,17 +851,8 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
 // ---------------------------------------------------------------------------- kernels
 // Single-plan launches: the grid is the plan's tiles, remapped so that the blocks of
 // one XCD take a contiguous tile range.  Group launches: one grid over the tiles of
-// several plans; each block finds its plan in start[] (tile offsets, start[n] = the
-// total) after the same remap and takes that plan's arguments from device arrays.
-__device__ __forceinline__ int group_member(const int *__restrict__ start, int n, int g) {
-    int lo = 0, hi = n - 1;   // largest i with start[i] <= g
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
+// several plans; each block finds its plan in start[] (group_member) after the same
+// remap and takes that plan's arguments from device arrays.
 
 #define MSB_PLAN_KERNEL(NAME, BODY, ...)                                                              \
     template <typename T, bool BLOCK, int RMAX>                                                      \
@@ -1300,6 +1291,20 @@ msb_status launch_product(const PassArgs<T> &a, const EndArgs<T> &e, hipStream_t
 template <typename T>
 msb_status launch_group(const PassArgs<T> &a, const GroupGrid &gg, const PassArgs<T> *dA, const EndArgs<T> *dE,
                         bool composite, hipStream_t st) {
+    if (gg.tiled) {
+        // a solver prologue first, as the transform-free x pass over the members' rows (the
+        // members' end arguments carry no_transform), then the tiled kernel
+        if (gg.pro) {
+            const int bx = a.wave_x ? 64 * ((waves_x(a.d, a.F) + a.spw - 1) / a.spw) : a.bthreads;
+            if (a.wave_x)
+                hipLaunchKernelGGL((k_xfwd_group<T, false, 8>), dim3(gg.total_x), dim3(bx), 0, st, dA, dE, gg.start_x, gg.n);
+            else
+                hipLaunchKernelGGL((k_xfwd_group<T, true, 8>), dim3(gg.total_x), dim3(bx), 0, st, dA, dE, gg.start_x, gg.n);
+        }
+        const FftSched *const sc[3] = {&a.stl, &a.stl, &a.stl};
+        MSB_HIP(launch_tile_group<T>(a, gg, dA, dE, needs_composite(sc), st));
+        return MSB_OK;
+    }
     ChainGeom g = chain_geom(a);
     g.lds_x = gg.lds_x;
     g.lds_l = gg.lds_l;
@@ -1309,7 +1314,7 @@ msb_status launch_group(const PassArgs<T> &a, const GroupGrid &gg, const PassArg
     return dispatch_chain<T>(a, e, g, composite, st, nullptr, dA, dE, &gg);
 }
 
-void pass_tiles(const msb_plan_s *p, const msb_launch_config &c, bool fp32, int tiles[3], size_t lds[3]) {
+void pass_tiles(const msb_plan_s *p, const msb_launch_config &c, bool fp32, int tiles[4], size_t lds[4]) {
     const size_t cb = fp32 ? sizeof(float2) : sizeof(double2);
     const int d = p->dim;
     const int H = (int)p->H, Ly = (int)p->L[1], Lz = (int)p->L[2], Nz = (int)p->n[2];
@@ -1319,6 +1324,8 @@ void pass_tiles(const msb_plan_s *p, const msb_launch_config &c, bool fp32, int 
     lds[0] = lds_x_bytes(d, c.rows_per_wg, p->L[0], cb, c.lds_inplace & 1);
     lds[1] = lds_line_bytes(d, c.lines_per_wg, d == 2 ? Ly : Lz, cb, c.lds_inplace & 2);
     lds[2] = d == 3 ? lds_line_bytes(d, c.lines_per_wg, Ly, cb, c.lds_inplace & 2) : 0;
+    tiles[3] = d == 2 ? tile_count(p, c.tile) : 0;
+    lds[3] = d == 2 && c.tile > 0 ? (c.tile_regs ? 2 * (size_t)c.tile * (c.tile + 1) * cb : lds_tile_bytes(c.tile, cb)) : 0;
 }
 
 bool plan_needs_composite(const msb_plan_s *p, bool fp32, int max_radix) {

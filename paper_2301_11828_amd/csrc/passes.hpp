@@ -177,6 +177,13 @@ struct GroupGrid {
     const int *start_x = nullptr, *start_l = nullptr, *start_y = nullptr;
     int total_x = 0, total_l = 0, total_y = 0;
     size_t lds_x = 0, lds_l = 0, lds_y = 0;
+    // tiled group products (2D, tile > 0): one launch of the tiled kernel over the members'
+    // blocks (table start_t), preceded by the transform-free x pass when pro is set (the
+    // end arguments carry a solver prologue)
+    const int *start_t = nullptr;
+    int total_t = 0;
+    size_t lds_t = 0;
+    int tiled = 0, pro = 0;
 };
 // a: any member's host arguments (for the common geometry); dA/dE: device arrays of the
 // members' arguments; composite: some member's schedules use a composite radix.
@@ -184,8 +191,14 @@ template <typename T>
 msb_status launch_group(const PassArgs<T> &a, const GroupGrid &gg, const PassArgs<T> *dA, const EndArgs<T> *dE,
                         bool composite, hipStream_t st);
 // Per-case tile counts of a plan's passes under a configuration: x passes, line
-// product (2D y / 3D z), 3D y passes; and their dynamic LDS bytes.
-void pass_tiles(const msb_plan_s *p, const msb_launch_config &c, bool fp32, int tiles[3], size_t lds[3]);
+// product (2D y / 3D z), 3D y passes, blocks of the tiled product (2D, tile > 0, else 0);
+// and their dynamic LDS bytes.
+void pass_tiles(const msb_plan_s *p, const msb_launch_config &c, bool fp32, int tiles[4], size_t lds[4]);
+// The tiled kernel over the blocks of a group's members (tile.hip): a, any member's host
+// arguments (frame length and kernel form, shared by the members).
+template <typename T>
+hipError_t launch_tile_group(const PassArgs<T> &a, const GroupGrid &gg, const PassArgs<T> *dA, const EndArgs<T> *dE,
+                             bool composite, hipStream_t st);
 // Whether a plan's schedules at radix cap max_radix use a composite radix.
 bool plan_needs_composite(const msb_plan_s *p, bool fp32, int max_radix);
 

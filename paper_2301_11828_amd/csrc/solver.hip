@@ -1241,16 +1241,19 @@ struct msb_group_s {
     int dim = 2, n = 0, Btot = 0, device = 0;
     std::vector<int> case_off;                 // [n + 1]
     msb_launch_config cfg[2];                  // common launch configuration per precision
-    std::vector<int> start[2][3];              // host tile offsets per pass [n + 1]
-    size_t lds[2][3] = {};
+    std::vector<int> start[2][4];              // host workgroup offsets per pass [n + 1]: x, line, 3D y, tiled
+    size_t lds[2][4] = {};
     bool composite[2] = {};
-    int *dstart[2] = {};                       // device copies [3][n + 1]
+    bool tiled[2] = {};                        // 2D tiled product (tile > 0) in this precision
+    std::vector<int> ept[2];                   // epilogue partial sums per case of each member [n]
+    std::vector<size_t> poff;                  // member offsets into the partial arrays [n + 1]
+    int *dstart[2] = {};                       // device copies [4][n + 1]
     void *dA[2] = {};                          // device PassArgs<T>[n]
     void *dAp[2] = {};                         // device PassArgs<T>[n] of the preconditioners
     void *dE[2] = {};                          // device EndArgs<T>[kSlots][n]
     double *part_x = nullptr, *part_rr = nullptr;   // [3][tiles], [2][tiles] (largest precision)
     double *part_rz = nullptr;                      // [2][3][tiles]: r.z partials by iteration parity
-    size_t tiles_max = 0;                           // x tiles of every member at one row per tile
+    size_t tiles_max = 0;                           // partial slots of every member (poff[n])
     double *thresh = nullptr, *scal = nullptr;      // [Btot], [16][Btot]
     int *done = nullptr, *iters = nullptr, *skip = nullptr;   // [Btot]
     double *h_scal = nullptr;                  // pinned [16][Btot]
@@ -1273,49 +1276,58 @@ enum GroupSlot {
 
 msb_status group_geometry(msb_group_s *g, int f) {
     const bool f32 = f == 1;
-    for (int k = 0; k < 3; ++k) g->start[f][k].assign(g->n + 1, 0);
+    for (int k = 0; k < 4; ++k) g->start[f][k].assign(g->n + 1, 0);
     g->composite[f] = false;
-    for (int k = 0; k < 3; ++k) g->lds[f][k] = 0;
+    g->tiled[f] = g->dim == 2 && g->cfg[f].tile > 0;
+    g->ept[f].assign(g->n, 0);
+    for (int k = 0; k < 4; ++k) g->lds[f][k] = 0;
     for (int i = 0; i < g->n; ++i) {
-        int t[3];
-        size_t l[3];
+        int t[4];
+        size_t l[4];
         pass_tiles(g->m[i], g->cfg[f], f32, t, l);
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             g->start[f][k][i + 1] = g->start[f][k][i] + g->m[i]->B * t[k];
             g->lds[f][k] = std::max(g->lds[f][k], l[k]);
         }
+        g->ept[f][i] = g->tiled[f] ? t[3] : t[0];
         g->composite[f] = g->composite[f] || plan_needs_composite(g->m[i], f32, g->cfg[f].max_radix);
     }
     std::vector<int> h;
-    for (int k = 0; k < 3; ++k) h.insert(h.end(), g->start[f][k].begin(), g->start[f][k].end());
+    for (int k = 0; k < 4; ++k) h.insert(h.end(), g->start[f][k].begin(), g->start[f][k].end());
     MSB_HIP(hipMemcpy(g->dstart[f], h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
     return MSB_OK;
 }
 
 // common configuration: the largest member's, if every member accepts it, else a
-// conservative one (one row / one line per workgroup, whole-workgroup teams)
+// conservative one (one row / one line per workgroup, whole-workgroup teams, no tiles).
+// Tiled group products take one block per workgroup (tile_run 1): a run of blocks would
+// cross the members' boundaries.
 msb_status group_config(msb_group_s *g, int f, const msb_launch_config *want) {
     const bool f32 = f == 1;
     msb_launch_config c;
     if (want) {
-        MSB_CHECK(want->tile == 0, MSB_EINVAL, "plan groups run the chain of passes (tile must be 0)");
+        MSB_CHECK(want->tile == 0 || want->tile_run == 1, MSB_EINVAL,
+                  "tiled plan-group products take one block per workgroup (tile_run must be 1, got %d)",
+                  want->tile_run);
         c = *want;
     } else {
         int big = 0;
         for (int i = 1; i < g->n; ++i)
             if (g->m[i]->N * g->m[i]->B > g->m[big]->N * g->m[big]->B) big = i;
         c = g->m[big]->cfg[f];
+        c.tile_run = 1;
     }
-    c.tile = 0;   // group launches run the chain of passes: a member's tiled configuration does not carry over
     bool ok = true;
     for (int i = 0; i < g->n && ok; ++i) ok = check_config(g->m[i], f32, c) == MSB_OK;
     if (!ok && !want) {
-        c = msb_launch_config{1, 0, 1, 1, 256, 1, 0, 1, 256, 8, 0, 0, 256};
+        c = msb_launch_config{1, 0, 1, 1, 256, 1, 0, 1, 256, 8, 0, 0, 256, 0, 1};
         ok = true;
         for (int i = 0; i < g->n && ok; ++i) ok = check_config(g->m[i], f32, c) == MSB_OK;
     }
     MSB_CHECK(ok, want ? MSB_EINVAL : MSB_EUNSUPPORTED, "launch configuration not valid for every member: %s",
               msb_last_error());
+    // frame spectra of the members' operators for the tile length
+    for (int i = 0; i < g->n && c.tile > 0; ++i) MSB_TRY(ensure_tiles(g->m[i], c.tile));
     g->cfg[f] = c;
     return group_geometry(g, f);
 }
@@ -1345,7 +1357,12 @@ msb_status group_refresh(msb_group_s *g) {
 template <typename T> msb_status group_upload_args(msb_group_s *g, std::vector<PassArgs<T>> &A) {
     const int f = prec_index<T>();
     A.resize(g->n);
-    for (int i = 0; i < g->n; ++i) A[i] = pass_args<T>(g->m[i], g->m[i]->op, &g->cfg[f]);
+    for (int i = 0; i < g->n; ++i) {
+        // new coefficients drop a member's frame spectra: rebuild those of the group's tile length
+        if (g->tiled[f]) MSB_TRY(ensure_tiles(g->m[i], g->cfg[f].tile));
+        A[i] = pass_args<T>(g->m[i], g->m[i]->op, &g->cfg[f]);
+        MSB_CHECK(A[i].tl == (g->tiled[f] ? g->cfg[f].tile : 0), MSB_EDEVICE, "member %d: frame spectra missing", i);
+    }
     MSB_HIP(hipMemcpy(g->dA[f], A.data(), sizeof(PassArgs<T>) * g->n, hipMemcpyHostToDevice));
     return MSB_OK;
 }
@@ -1360,14 +1377,14 @@ template <typename T> msb_status group_upload_end(msb_group_s *g, int slot, cons
 // ones during a group CG).
 struct GroupView {
     int n = 0;
-    int total[3] = {0, 0, 0};
+    int total[4] = {0, 0, 0, 0};
 };
 
 template <typename T> GroupView full_view(const msb_group_s *g) {
     const int f = prec_index<T>();
     GroupView v;
     v.n = g->n;
-    for (int k = 0; k < 3; ++k) v.total[k] = g->start[f][k][g->n];
+    for (int k = 0; k < 4; ++k) v.total[k] = g->start[f][k][g->n];
     return v;
 }
 
@@ -1387,6 +1404,15 @@ msb_status group_launch(msb_group_s *g, const std::vector<PassArgs<T>> &A, int s
     gg.lds_x = g->lds[f][0];
     gg.lds_l = g->lds[f][1];
     gg.lds_y = g->lds[f][2];
+    // the preconditioners' chains carry no corrections and stay untiled; the CG slots'
+    // end arguments hold a prologue (run first as the transform-free x pass)
+    if (g->tiled[f] && !pre) {
+        gg.tiled = 1;
+        gg.pro = slot < G_LIFT;
+        gg.start_t = g->dstart[f] + 3 * (v.n + 1);
+        gg.total_t = v.total[3];
+        gg.lds_t = g->lds[f][3];
+    }
     const EndArgs<T> *dE = static_cast<const EndArgs<T> *>(g->dE[f]) + (size_t)slot * g->n;
     return launch_group<T>(A[0], gg, static_cast<const PassArgs<T> *>(pre ? g->dAp[f] : g->dA[f]), dE,
                            g->composite[f], st);
@@ -1401,18 +1427,18 @@ msb_status group_load_members(msb_group_s *g, const std::vector<int> &act, const
     const int f = prec_index<T>();
     const int na = (int)act.size();
     std::vector<PassArgs<T>> Aa(na), Apa(Ap ? na : 0);
-    std::vector<int> st3(3 * (na + 1), 0);
+    std::vector<int> st3(4 * (na + 1), 0);
     v.n = na;
-    for (int k = 0; k < 3; ++k) v.total[k] = 0;
+    for (int k = 0; k < 4; ++k) v.total[k] = 0;
     for (int j = 0; j < na; ++j) {
         const int i = act[j];
         Aa[j] = A[i];
         if (Ap) Apa[j] = (*Ap)[i];
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             st3[k * (na + 1) + j + 1] = st3[k * (na + 1) + j] + (g->start[f][k][i + 1] - g->start[f][k][i]);
         }
     }
-    for (int k = 0; k < 3; ++k) v.total[k] = st3[k * (na + 1) + na];
+    for (int k = 0; k < 4; ++k) v.total[k] = st3[k * (na + 1) + na];
     MSB_HIP(hipMemcpy(g->dA[f], Aa.data(), sizeof(PassArgs<T>) * na, hipMemcpyHostToDevice));
     if (Ap) MSB_HIP(hipMemcpy(g->dAp[f], Apa.data(), sizeof(PassArgs<T>) * na, hipMemcpyHostToDevice));
     MSB_HIP(hipMemcpy(g->dstart[f], st3.data(), sizeof(int) * st3.size(), hipMemcpyHostToDevice));
@@ -1468,7 +1494,8 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
         const int parity = (slot == G_ODD || slot == G_UPD_ODD) ? 1 : 0;
         const int prv = (parity + 1) & 1;
         for (int i = 0; i < g->n; ++i) {
-            const int sx = g->start[f][0][i], nt = g->start[f][0][i + 1] - sx;
+            const size_t po = g->poff[i];
+            const int nt = g->start[f][0][i + 1] - g->start[f][0][i];
             const int co = g->case_off[i];
             EndArgs<T> e = end_args<T>();
             e.pro = pcg ? PRO_PCG_R : PRO_CG_P;
@@ -1477,10 +1504,12 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
             e.cx = x[i];
             e.cr = r[i];
             e.cq = q[i];
-            e.cg3 = g->part_x + 3 * (size_t)sx;
-            e.rr_prev = g->part_rr + 2 * (size_t)sx + (size_t)prv * nt;
-            e.rr_out = g->part_rr + 2 * (size_t)sx + (size_t)parity * nt;
-            if (pcg) e.rz_k = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * (size_t)sx;
+            e.cg3 = g->part_x + 3 * po;
+            e.n_cg3 = g->ept[f][i];
+            e.s_cg3 = (size_t)g->m[i]->B * g->ept[f][i];
+            e.rr_prev = g->part_rr + 2 * po + (size_t)prv * nt;
+            e.rr_out = g->part_rr + 2 * po + (size_t)parity * nt;
+            if (pcg) e.rz_k = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * po;
             e.first = slot == G_FIRST;
             e.update_only = slot == G_UPD_EVEN || slot == G_UPD_ODD;
             e.iters = g->iters + co;
@@ -1493,13 +1522,14 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
                 e.uin = r[i];
                 e.out = (*z)[i];
                 e.sign = 1.0;
-                e.part = g->part_rz + (size_t)parity * 3 * g->tiles_max + 3 * (size_t)sx;
+                e.part = g->part_rz + (size_t)parity * 3 * g->tiles_max + 3 * po;
             } else {
                 e.epi = EPI_CG_Q;
                 e.uin = pv[i];
                 e.out = q[i];
                 e.rhs = r[i];
-                e.part = g->part_x + 3 * (size_t)sx;
+                e.part = g->part_x + 3 * po;
+                e.no_transform = g->tiled[f];   // the tiled product: the x pass is the prologue alone
             }
             Eslots[slot][i] = e;
         }
@@ -1510,20 +1540,21 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
         const int parity = slot == G_PA_ODD ? 1 : 0;
         const int prv = (parity + 1) & 1;
         for (int i = 0; i < g->n; ++i) {
-            const int sx = g->start[f][0][i];
+            const size_t po = g->poff[i];
             EndArgs<T> e = end_args<T>();
             e.pro = PRO_PCG_P;
             e.pr = (*z)[i];
             e.pio = pv[i];
-            e.rz_k = g->part_rz + (size_t)parity * 3 * g->tiles_max + 3 * (size_t)sx;
-            e.rz_km1 = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * (size_t)sx;
+            e.rz_k = g->part_rz + (size_t)parity * 3 * g->tiles_max + 3 * po;
+            e.rz_km1 = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * po;
             e.first = slot == G_PA_FIRST;
             e.case_done = g->done + (size_t)parity * g->Btot + g->case_off[i];
             e.epi = EPI_CG_Q;
             e.uin = pv[i];
             e.out = q[i];
             e.rhs = r[i];
-            e.part = g->part_x + 3 * (size_t)sx;
+            e.part = g->part_x + 3 * po;
+            e.no_transform = g->tiled[f];
             Eslots[slot][i] = e;
         }
     }
@@ -1607,16 +1638,16 @@ msb_status group_residual(msb_group_s *g, const std::vector<PassArgs<double>> &A
         e.epi = EPI_RESID;
         e.rhs = rhs[i];
         e.out = out[i];
-        e.part = g->part_x + 3 * (size_t)g->start[0][0][i];
+        e.part = g->part_x + 3 * g->poff[i];
         E[i] = e;
     }
     MSB_TRY(group_quiesce(g, g->st));
     MSB_TRY(group_upload_end<double>(g, argslot, E));
     MSB_TRY(group_launch<double>(g, A, argslot, g->st));
     for (int i = 0; i < g->n; ++i) {
-        const int tpc = (g->start[0][0][i + 1] - g->start[0][0][i]) / g->m[i]->B;
+        const int tpc = g->ept[0][i];   // partials per case of the product's epilogue
         hipLaunchKernelGGL(k_case_sums, dim3(g->m[i]->B), dim3(kT), 0, g->st,
-                           (const double *)(g->part_x + 3 * (size_t)g->start[0][0][i]), tpc, (size_t)tpc,
+                           (const double *)(g->part_x + 3 * g->poff[i]), tpc, (size_t)tpc,
                            g->scal + (size_t)slot * g->Btot + g->case_off[i], 1.0);
     }
     MSB_HIP(hipGetLastError());
@@ -1678,9 +1709,8 @@ extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_gr
         return s;
     };
     const size_t nb = (size_t)g->Btot;
-    size_t tiles_max = 0;
     for (int f = 0; f < 2; ++f) {
-        if (hipMalloc(&g->dstart[f], sizeof(int) * 3 * (nplans + 1)) != hipSuccess) return fail(MSB_ENOMEM);
+        if (hipMalloc(&g->dstart[f], sizeof(int) * 4 * (nplans + 1)) != hipSuccess) return fail(MSB_ENOMEM);
         const size_t pa = f ? sizeof(PassArgs<float>) : sizeof(PassArgs<double>);
         const size_t ea = f ? sizeof(EndArgs<float>) : sizeof(EndArgs<double>);
         if (hipMalloc(&g->dA[f], pa * nplans) != hipSuccess) return fail(MSB_ENOMEM);
@@ -1689,8 +1719,11 @@ extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_gr
         msb_status s = group_config(g, f, nullptr);
         if (s != MSB_OK) return fail(s);
     }
-    // tile partials sized for any configuration: at most one x tile per grid row
-    for (int i = 0; i < nplans; ++i) tiles_max += (size_t)plans[i]->B * rows_total(plans[i]);
+    // partial sums sized for any configuration: one x tile per grid row or the blocks of
+    // the smallest tiled inner block, whichever is more
+    g->poff.assign(nplans + 1, 0);
+    for (int i = 0; i < nplans; ++i) g->poff[i + 1] = g->poff[i] + (size_t)plans[i]->B * partial_slots(plans[i]);
+    const size_t tiles_max = g->poff[nplans];
     g->tiles_max = tiles_max;
     g->layout_seen.resize(nplans);
     for (int i = 0; i < nplans; ++i) g->layout_seen[i] = plans[i]->layout_version;
@@ -1770,9 +1803,10 @@ static msb_status group_apply_t(msb_group_s *g, const void *const *u, void *cons
 }
 
 // Group autotuner: the plan autotuner's coordinate search (x passes, line passes, each
-// with two-buffer and in-place stages; then the radix cap) over configurations every
-// member accepts, each timed as whole group products (HIP events around nrep launches of
-// f_i = A_i u_i on the group's stream).  Leaves the fastest in the group.
+// with two-buffer and in-place stages; then the radix cap; then, in 2D, the tiled
+// product) over configurations every member accepts, each timed as whole group products
+// (HIP events around nrep launches of f_i = A_i u_i on the group's stream).  Leaves the
+// fastest in the group.
 template <typename T> static msb_status group_tune_t(msb_group_s *g, int effort, double *best_ms) {
     const int f = prec_index<T>();
     const int n = g->n;
@@ -1826,6 +1860,8 @@ template <typename T> static msb_status group_tune_t(msb_group_s *g, int effort,
         return MSB_OK;
     };
     msb_launch_config best = g->cfg[f];
+    best.tile = 0, best.tile_regs = 0, best.tile_run = 1;   // the chain's settings first, the tiled product last
+    MSB_TRY(group_config(g, f, &best));
     double bt = 0.0;
     MSB_TRY(time_now(bt));
     nrep = std::max(3, std::min(40, (int)std::ceil(2.0 / std::max(bt, 1e-3))));   // about 2 ms per candidate
@@ -1877,6 +1913,25 @@ template <typename T> static msb_status group_tune_t(msb_group_s *g, int effort,
         msb_launch_config c = best;
         c.max_radix = r;
         consider(c);
+    }
+    if (g->dim == 2) {
+        // the tiled product over the members' blocks (one block per workgroup): LDS frames of
+        // several lengths, then register-resident frames; the chain's settings stay for the
+        // preconditioners and the solver prologues
+        const msb_launch_config chain = best;
+        const std::vector<int> tls = effort ? std::vector<int>{16, 20, 24, 30, 32, 36, 40, 48, 60, 64}
+                                            : std::vector<int>{24, 32, 40, 48, 64};
+        for (int tl : tls)
+            for (int th : ths) {
+                msb_launch_config c = chain;
+                c.tile = tl, c.threads_tile = th, c.tile_regs = 0, c.tile_run = 1;
+                consider(c);
+            }
+        for (int tl : {16, 32, 64}) {
+            msb_launch_config c = chain;
+            c.tile = tl, c.tile_regs = 1, c.tile_run = 1;
+            consider(c);
+        }
     }
     MSB_TRY(err);
     MSB_TRY(group_config(g, f, &best));

@@ -832,6 +832,28 @@ __global__ __launch_bounds__(RegShape<TL>::S * TL) void k_tile_reg(PassArgs<T> a
     tile_reg_run<T, TL>(a, e, xcd_tile(blockIdx.x, gridDim.x), a.B * a.ttx * a.tty);
 }
 
+// ---------------------------------------------------------------------------- plan groups
+// One launch over the blocks of several plans: each workgroup finds its member in start[]
+// after the XCD remap and takes that member's arguments from the device arrays.
+
+template <typename T, int RMAX>
+__global__ __launch_bounds__(kMaxBlock) void k_tile_group(const PassArgs<T> *__restrict__ A,
+                                                          const EndArgs<T> *__restrict__ E,
+                                                          const int *__restrict__ start, int n) {
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    const int m = group_member(start, n, g);
+    tile_body<T, RMAX>(A[m], E[m], g - start[m], start[m + 1] - start[m]);
+}
+
+template <typename T, int TL, bool CGQ>
+__global__ __launch_bounds__(RegShape<TL>::S * TL) void k_tile_reg1_group(const PassArgs<T> *__restrict__ A,
+                                                                       const EndArgs<T> *__restrict__ E,
+                                                                       const int *__restrict__ start, int n) {
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    const int m = group_member(start, n, g);
+    tile_reg_body<T, TL, CGQ>(A[m], E[m], g - start[m], start[m + 1] - start[m]);
+}
+
 template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
     if (bytes <= 64 * 1024) return hipSuccess;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -893,5 +915,47 @@ template hipError_t launch_tile_kernel<double>(const PassArgs<double> &, const E
                                                hipStream_t);
 template hipError_t launch_tile_kernel<float>(const PassArgs<float> &, const EndArgs<float> &, size_t, bool, int,
                                               hipStream_t);
+
+}  // namespace msb
+
+namespace msb {
+
+template <typename T, int TL, bool CGQ>
+static hipError_t launch_reg_group(const GroupGrid &gg, const PassArgs<T> *dA, const EndArgs<T> *dE, hipStream_t st) {
+    const hipError_t err = allow_lds(k_tile_reg1_group<T, TL, CGQ>, gg.lds_t);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_tile_reg1_group<T, TL, CGQ>), dim3(gg.total_t), dim3(RegShape<TL>::S * TL), gg.lds_t, st, dA,
+                       dE, gg.start_t, gg.n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tile_group(const PassArgs<T> &a, const GroupGrid &gg, const PassArgs<T> *dA, const EndArgs<T> *dE,
+                             bool composite, hipStream_t st) {
+    hipError_t err;
+    const dim3 grid(gg.total_t);
+    if (a.treg) {
+        switch (a.tl) {
+            // CG slots (epilogue q = K p) at frame 16: the form that preloads p and r
+            case 16: return gg.pro ? launch_reg_group<T, 16, true>(gg, dA, dE, st)
+                                   : launch_reg_group<T, 16, false>(gg, dA, dE, st);
+            case 32: return launch_reg_group<T, 32, false>(gg, dA, dE, st);
+            case 64: return launch_reg_group<T, 64, false>(gg, dA, dE, st);
+            default: return hipErrorInvalidValue;
+        }
+    } else if (composite) {
+        if ((err = allow_lds(k_tile_group<T, 16>, gg.lds_t)) != hipSuccess) return err;
+        hipLaunchKernelGGL((k_tile_group<T, 16>), grid, dim3(a.tthreads), gg.lds_t, st, dA, dE, gg.start_t, gg.n);
+    } else {
+        if ((err = allow_lds(k_tile_group<T, 8>, gg.lds_t)) != hipSuccess) return err;
+        hipLaunchKernelGGL((k_tile_group<T, 8>), grid, dim3(a.tthreads), gg.lds_t, st, dA, dE, gg.start_t, gg.n);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_tile_group<double>(const PassArgs<double> &, const GroupGrid &, const PassArgs<double> *,
+                                              const EndArgs<double> *, bool, hipStream_t);
+template hipError_t launch_tile_group<float>(const PassArgs<float> &, const GroupGrid &, const PassArgs<float> *,
+                                             const EndArgs<float> *, bool, hipStream_t);
 
 }  // namespace msb

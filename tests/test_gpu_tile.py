@@ -326,11 +326,12 @@ def test_tiled_configurations_rejected():
     p3 = gpu_plan(w3)
     with pytest.raises(msb.MsbError):
         p3.set_config("fp64", tile=16)
-    # plan groups run the chain: a tiled group configuration is refused, a member's
-    # tiled configuration does not carry over
+    # plan groups take a member's tiled configuration; the limits of a plan apply to them
     _tiled(plan, 24)
     grp = msb.PlanGroup([plan])
-    assert grp.get_config("fp64")["tile"] == 0
-    with pytest.raises(msb.MsbError):
-        grp.set_config("fp64", tile=24)
+    assert grp.get_config("fp64")["tile"] == 24
+    for bad in (dict(tile=11), dict(tile=72), dict(tile=24, threads_tile=96)):
+        with pytest.raises(msb.MsbError):
+            grp.set_config("fp64", **bad)
+    assert grp.get_config("fp64")["tile"] == 24
     grp.close()
