@@ -380,22 +380,21 @@ def main():
         plan.apply_precond(b)            # builds the circulant preconditioner (host spectra + upload)
         torch.cuda.synchronize()
         cg["precond_build_seconds"] = round(time.perf_counter() - t0, 4)
-        for prec, pre in (("fp64", False), ("fp32_refined", False), ("fp64", True), ("fp32_refined", True)):
-            key = prec + ("_pcg" if pre else "")
+        for prec, pre, rel in CG_VARIANTS:
+            key = cg_key(prec, pre, rel)
             print("bench: CG %s to 1e-10" % key, file=sys.stderr, flush=True)
-            plan.solve(b, precision=prec, tol=1e-10, maxit=200000, graph_block=args.graph_block, precond=pre)
+            plan.solve(b, precision=prec, tol=1e-10, maxit=200000, graph_block=args.graph_block, precond=pre,
+                       reliable_update=rel)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             x, info = plan.solve(b, precision=prec, tol=1e-10, maxit=200000, graph_block=args.graph_block,
-                                 precond=pre)
+                                 precond=pre, reliable_update=rel)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             cg[key] = {"seconds": round(dt, 4), "iterations": info[0].inner_iters,
                        "outer": info[0].outer_iters, "rel_residual_fp64": info[0].rel_residual,
                        "status": info[0].status}
-        cg["speedup_fp32_refined_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp32_refined"]["seconds"], 3)
-        cg["speedup_fp64_pcg_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp64_pcg"]["seconds"], 3)
-        cg["speedup_fp32_refined_pcg_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp32_refined_pcg"]["seconds"], 3)
+        cg_speedups(cg)
         line["cg"] = cg
         # the paper's own static solver: adaptive dynamic relaxation (Alg. 1), FP64, one
         # fused product chain per update; updates/s and the force residual reached
@@ -464,6 +463,28 @@ def recorded_tuning(args, name):
     if args.retune or args.no_tune or not os.path.exists(path):
         return None
     return json.load(open(path))
+
+
+
+# CG variants timed to a tolerance: (precision, preconditioned, reliable updates).  The
+# refined solver restarts CG after each FP64 residual update, or (reliable) keeps the
+# search direction across the replacement.
+CG_VARIANTS = (("fp64", False, 0), ("fp32_refined", False, 0), ("fp32_refined", False, 1),
+               ("fp64", True, 0), ("fp32_refined", True, 0), ("fp32_refined", True, 1))
+
+
+def cg_key(prec, pre, rel):
+    return prec + ("_reliable" if rel else "") + ("_pcg" if pre else "")
+
+
+def cg_speedups(cg):
+    """FP64 seconds over each other variant's, against the same preconditioning."""
+    for k in list(cg):
+        if not isinstance(cg[k], dict) or k in ("fp64", "fp64_pcg"):
+            continue
+        base = "fp64_pcg" if k.endswith("_pcg") else "fp64"
+        cg["speedup_%s_vs_%s" % (k, base)] = round(cg[base]["seconds"] / cg[k]["seconds"], 3)
+    cg["speedup_fp64_pcg_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp64_pcg"]["seconds"], 3)
 
 
 def bench_crack1024(args):
@@ -645,18 +666,18 @@ def bench_cube128(args):
     plan.apply_precond(b)
     torch.cuda.synchronize()
     cg["precond_build_seconds"] = round(time.perf_counter() - t0, 3)
-    for prec, pre in (("fp64", False), ("fp32_refined", False), ("fp64", True), ("fp32_refined", True)):
-        key = prec + ("_pcg" if pre else "")
+    for prec, pre, rel in CG_VARIANTS:
+        key = cg_key(prec, pre, rel)
         print("bench: cube128 CG %s to 1e-8" % key, file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        _, info = plan.solve(b, precision=prec, tol=1e-8, maxit=100000, graph_block=args.graph_block, precond=pre)
+        _, info = plan.solve(b, precision=prec, tol=1e-8, maxit=100000, graph_block=args.graph_block, precond=pre,
+                             reliable_update=rel)
         torch.cuda.synchronize()
         cg[key] = {"seconds": round(time.perf_counter() - t0, 3),
                    "iterations_max": max(i.inner_iters for i in info),
-                   "max_rel_residual": max(i.rel_residual for i in info)}
-    cg["speedup_fp32_refined_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp32_refined"]["seconds"], 3)
-    cg["speedup_fp64_pcg_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp64_pcg"]["seconds"], 3)
-    cg["speedup_fp32_refined_pcg_vs_fp64"] = round(cg["fp64"]["seconds"] / cg["fp32_refined_pcg"]["seconds"], 3)
+                   "max_rel_residual": max(i.rel_residual for i in info),
+                   "status": max((i.status for i in info), key=abs)}
+    cg_speedups(cg)
     out["cg_to_1e-8"] = cg
     if not args.no_cpu:
         # the oracle's bond-by-bond FP64 product on one case (3 runs), and the CG time it

@@ -159,7 +159,9 @@ typedef struct {
     int graph_block;        /* CG iterations per hipGraph launch (0 = no graph, plain launches) */
     int reliable_update;    /* FP32_REFINED: 0 = restart CG after each FP64 residual update
                                (iterative refinement); 1 = keep the search direction and
-                               replace the residual by the FP64 one (reliable updates) */
+                               replace the residual by the FP64 one (reliable updates): the
+                               first beta after a replacement is the new r.r (r.z with
+                               precond) over that of the step that formed the direction */
     int precond;            /* 0 = plain CG; 1 = CG preconditioned by the circulant inverse
                                of the periodic operator on the padded grid (prior fast
                                methods cited in the introduction): per frequency the d x d
@@ -170,8 +172,7 @@ typedef struct {
                                freed when the influence coefficients change.  Two product
                                chains per iteration (for a plan group, two group launches:
                                every member's preconditioner chain, then every member's
-                               stiffness chain).  Not with reliable_update
-                               (MSB_EUNSUPPORTED). */
+                               stiffness chain). */
 } msb_solve_opts;
 
 typedef struct {

@@ -275,7 +275,10 @@ struct SumSrc {
     const double *p[5];
     int n[5];   // partials per case of each array
 };
-template <int K> __global__ void k_cg_sums(SumSrc src, double *out) {
+// 16 waves: a case's partials (a few thousand per array at most tiles) are loaded in one or
+// two rounds of independent loads, the reduction being latency-bound
+constexpr int kSumT = 1024;
+template <int K> __global__ __launch_bounds__(kSumT) void k_cg_sums(SumSrc src, double *out) {
     __shared__ double red[96];
     const int b = blockIdx.x;
     const double *parts[K];
@@ -321,7 +324,7 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
     e.update_only = update_only;
     if (it > 0 && std::max(c.tpc, ept) > kFusedReduceMaxTiles) {
         const SumSrc src{{e.rr_prev, e.cg3, e.cg3 + ne, e.cg3 + 2 * ne, nullptr}, {c.tpc, ept, ept, ept, 0}};
-        hipLaunchKernelGGL(k_cg_sums<4>, dim3(B), dim3(kT), 0, c.st, src, w->case4);
+        hipLaunchKernelGGL(k_cg_sums<4>, dim3(B), dim3(kSumT), 0, c.st, src, w->case4);
         e.case4 = w->case4;
     }
     e.iters = w->iters;
@@ -401,11 +404,16 @@ template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_bl
     return run_iterations(c.w, c.p->B, c.st, iter, maxit, graph_block, it_out);
 }
 
-// per case: dst[b][.] = latest r.r partials, part_rr[iters[b] & 1][b][.]
-__global__ void k_save_rr(const double *part_rr, const int *iters, int P, int B, double *dst) {
+// Denominator of the first beta after a residual replacement (reliable update): the
+// partials of the step that formed the search direction the run ended with.  Iteration
+// k >= 1 applies update k, so after K updates of case b that direction was formed at
+// iteration K - 1, whose partials sit in parity slot (K - 1) & 1 (part + slot * pstride):
+// r.r for CG, r.z for preconditioned CG.  No update (K = 0): zeros (beta = 0, a restart).
+__global__ void k_save_last(const double *part, size_t pstride, const int *iters, int P, double *dst) {
     const int b = blockIdx.x;
-    const double *src = part_rr + (size_t)(iters[b] & 1) * B * P + (size_t)b * P;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) dst[(size_t)b * P + i] = src[i];
+    const int K = iters[b];
+    const double *src = part + (size_t)((K + 1) & 1) * pstride + (size_t)b * P;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) dst[(size_t)b * P + i] = K > 0 ? src[i] : 0.0;
 }
 
 // Prepare and run CG on K d = rhs (rhs already masked); x0 = 0.  With prev_rr the
@@ -454,6 +462,7 @@ template <typename T> struct Pcg {
     PassArgs<T> pa;   // stiffness product
     PassArgs<T> pp;   // preconditioner product (spectral symbol only)
     int tpc;
+    const double *prev_rz;   // r.z partials before a residual replacement (first beta), or null
 };
 
 // One preconditioned CG iteration = two product chains.
@@ -490,7 +499,7 @@ template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool up
         e.update_only = update_only;
         if (reduce) {
             const SumSrc src{{e.rr_prev, e.rz_k, e.cg3, e.cg3 + ne, e.cg3 + 2 * ne}, {c.tpc, c.tpc, ept, ept, ept}};
-            hipLaunchKernelGGL(k_cg_sums<5>, dim3(B), dim3(kT), 0, c.st, src, w->case4);
+            hipLaunchKernelGGL(k_cg_sums<5>, dim3(B), dim3(kSumT), 0, c.st, src, w->case4);
             e.case4 = w->case4;
         }
         e.iters = w->iters;
@@ -513,9 +522,13 @@ template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool up
     e.rz_k = w->part_rz + (size_t)cur * 3 * nt;
     e.rz_km1 = w->part_rz + (size_t)prv * 3 * nt;
     e.first = it == 0;
+    if (it == 0 && c.prev_rz) {   // continuation: p = z + (r.z / previous r.z) p with the kept p
+        e.first = false;
+        e.rz_km1 = c.prev_rz;
+    }
     if (reduce) {
         const SumSrc src{{e.rz_k, e.rz_km1, nullptr, nullptr, nullptr}, {c.tpc, c.tpc, 0, 0, 0}};
-        hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kT), 0, c.st, src, w->case4);
+        hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kSumT), 0, c.st, src, w->case4);
         e.case4 = w->case4;
     }
     e.case_done = w->done + (size_t)cur * B;
@@ -528,19 +541,20 @@ template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool up
 }
 
 // Preconditioned CG on K d = rhs (rhs already masked), x0 = 0, with the same flags,
-// thresholds and iteration counters as cg_solve.
+// thresholds and iteration counters as cg_solve.  With prev_rz the search direction pv
+// is kept (reliable update) and the first beta is (new r.z) / prev_rz.
 template <typename T>
 static msb_status pcg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *rhs, T *x, T *r, T *pv, T *q,
                             T *z, double tol, int maxit, int graph_block, const int *skip, int *iters_out = nullptr,
-                            const double *tol2_case = nullptr) {
+                            const double *tol2_case = nullptr, const double *prev_rz = nullptr) {
     MSB_TRY(ensure_pre(p));
     const size_t n = w->nvec;
     const int B = p->B, P = w->P;
-    Pcg<T> c{p, w, st, x, r, pv, q, z, pass_args<T>(p, p->op), pass_args<T>(p, p->pre), 0};
+    Pcg<T> c{p, w, st, x, r, pv, q, z, pass_args<T>(p, p->op), pass_args<T>(p, p->pre), 0, prev_rz};
     c.pp.corr = 0;
     c.tpc = x_tiles_per_case(p, c.pa.F);
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, x, n, T(0));
-    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
+    if (!prev_rz) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
     hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(n)), dim3(kT), 0, st, r, rhs, n);
     hipLaunchKernelGGL(k_dot_parts<T>, dim3(B * P), dim3(kT), 0, st, (const T *)r, (const T *)r, w->part_aux,
                        (size_t)p->dim * p->N, P);
@@ -707,8 +721,6 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
     MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
     MSB_CHECK(opts->precond == 0 || opts->precond == 1, MSB_EINVAL, "precond must be 0 or 1");
     MSB_CHECK(!p->nu64, MSB_EUNSUPPORTED, "the surface-corrected operator is not symmetric: no CG solve");
-    MSB_CHECK(!(opts->precond && opts->reliable_update), MSB_EUNSUPPORTED,
-              "the preconditioned solver refines by restarts only (reliable_update = 0)");
     const bool pre = opts->precond != 0;
     SolverWs *w = nullptr;
     MSB_TRY(get_ws(p, w));
@@ -833,7 +845,7 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
         float *r32 = w->v32[0], *d32 = w->v32[1], *p32 = w->v32[2];
         double *r64 = w->v64[2];
         if (reliable) MSB_HIP(hipMalloc(&prev_buf.p, sizeof(double) * (size_t)B * rows_total(p)));
-        double *prev = static_cast<double *>(prev_buf.p);   // [B][tiles] r.r partials before the replacement
+        double *prev = static_cast<double *>(prev_buf.p);   // [B][x tiles] r.r (r.z) partials before the replacement
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kT), 0, st, u, n, 0.0);
         hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(kT), 0, st, p32, n, 0.0f);
         hipLaunchKernelGGL((k_cast<double, double>), dim3(grid_for(n)), dim3(kT), 0, st, r64, (const double *)bp, n);
@@ -867,7 +879,8 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
             hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kT), 0, st, r32, (const double *)r64, n);
             if (pre)
                 MSB_TRY(pcg_solve<float>(p, w, st, r32, d32, p32, w->v32[3], w->v32[4], w->v32[5], itol,
-                                         opts->maxit - used, gb, skip, nullptr, t2d));
+                                         opts->maxit - used, gb, skip, nullptr, t2d,
+                                         (reliable && !first) ? prev : nullptr));
             else
                 MSB_TRY(cg_solve<float>(p, w, st, r32, d32, p32, w->v32[3], w->v32[4], itol, opts->maxit - used, gb,
                                         skip, (reliable && !first) ? prev : nullptr, nullptr, t2d));
@@ -884,9 +897,12 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
             }
             used += mx;
             if (reliable) {
+                // r.r partials [parity][B][tpc] (CG) or the first array of the r.z partials
+                // [parity][3][B][tpc] (PCG), written with the x passes' tiles
                 const int tpc = x_tiles_per_case(p, pass_args<float>(p, p->op).F);
-                hipLaunchKernelGGL(k_save_rr, dim3(B), dim3(64), 0, st, (const double *)w->part_rr,
-                                   (const int *)w->iters, tpc, B, prev);
+                const size_t nt = (size_t)B * tpc;
+                hipLaunchKernelGGL(k_save_last, dim3(B), dim3(64), 0, st, (const double *)(pre ? w->part_rz : w->part_rr),
+                                   pre ? 3 * nt : nt, (const int *)w->iters, tpc, prev);
             }
             hipLaunchKernelGGL(k_add_to<float>, dim3(grid_for(n)), dim3(kT), 0, st, u, (const float *)d32, n);
             MSB_TRY(true_residual(p, w, st, u, bp, r64, 0));
@@ -1070,7 +1086,7 @@ static msb_status adr_run_t(msb_plan_s *p, msb_precision prec, int64_t nsteps, i
         e.s_cg3 = nt;
         if (!first && tpc > kFusedReduceMaxTiles) {
             const SumSrc src{{w->part_adr, w->part_adr + nt, nullptr, nullptr, nullptr}, {tpc, tpc, 0, 0, 0}};
-            hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kT), 0, st, src, w->case4);
+            hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kSumT), 0, st, src, w->case4);
             e.case4 = w->case4;
         }
         e.epi = EPI_ADR;

@@ -149,13 +149,32 @@ def test_pcg_many_tiles_per_case():
         assert rel <= 1e-10 and d <= 1e-8
 
 
-def test_pcg_rejects_reliable_update():
-    import paper_2301_11828_amd as msb
-    w = W.small(2, (20, 16), 3, seed=211, fixed="left")
+@pytest.mark.parametrize("precond", [False, True])
+@pytest.mark.parametrize("tiled", [False, True])
+def test_reliable_update_matches_cholesky(precond, tiled):
+    """FP32 CG inside FP64 refinement that keeps its search direction across residual
+    replacements (plain and preconditioned; chain and tiled products), with a crack, a lift
+    and three cases, against each case's dense Cholesky solve; certified residual <= tol."""
+    w = W.small(2, (34, 27), 3, seed=211, fixed="left", crack=True, batch=3)
+    rng = np.random.default_rng(212)
+    g = np.where(w.fixed[None], 1e-2 * rng.standard_normal((w.batch, 2, w.N)), 0.0)
     plan = gpu_plan(w)
-    with pytest.raises(msb.MsbError) as e:
-        plan.solve(to_dev(w.b), precision="fp32_refined", reliable_update=1, precond=True)
-    assert e.value.status == msb.MSB_EUNSUPPORTED
+    if tiled:
+        for f in ("fp64", "fp32"):
+            plan.set_config(f, tile=16, tile_regs=1, tile_run=1)
+    tol = 1e-11
+    u, info = plan.solve(to_dev(w.b), to_dev(g), precision="fp32_refined", tol=tol, reliable_update=1,
+                         precond=precond)
+    _, info_r = plan.solve(to_dev(w.b), to_dev(g), precision="fp32_refined", tol=tol, precond=precond)
+    uu = u.cpu().numpy()
+    for c in range(w.batch):
+        ref = O.solve_dense(oracle_problem(w), w.b[c], w.fixed, g[c], oracle_bonds(w))
+        err = rel_err(uu[c], ref)
+        log("reliable updates precond=%d tiled=%d case %d: %d outer %d inner (restarted: %d outer %d inner), "
+            "residual %.2e, rel err %.2e" % (precond, tiled, c, info[c].outer_iters, info[c].inner_iters,
+                                             info_r[c].outer_iters, info_r[c].inner_iters, info[c].rel_residual, err))
+        assert info[c].status == 0 and info[c].rel_residual <= tol
+        assert err <= 1e-9
 
 
 def test_plate512_pcg_at_the_benchmark_tuning_certified_by_oracle():
