@@ -729,6 +729,8 @@ def bench_plates64(args):
         grp.autotune("fp32_refined", effort=1)
         tuning = {"seconds": round(time.perf_counter() - t0, 2), "fp64": grp.get_config("fp64"),
                   "fp32": grp.get_config("fp32")}
+    # CG iterations in hipGraph blocks (every solve of the three modes, autograd ones included)
+    grp.graph_block = args.graph_block
     GSolve = msb.make_group_solve_function()
     Solve = msb.make_solve_function()
     by_size = {}
@@ -740,7 +742,10 @@ def bench_plates64(args):
         w0 = ws[by_size[sz][0]]
         pl = msb.Plan(w0.n, w0.h, w0.M, w0.alpha, infl=w0.infl, batch=len(by_size[sz]))
         pl.set_constraints(w0.fixed)
+        pl.graph_block = args.graph_block
         splans.append(pl)
+    for pl in plans:
+        pl.graph_block = args.graph_block
 
     def inputs():
         bs = [torch.from_numpy(w.b).cuda().requires_grad_(True) for w in ws]
@@ -809,7 +814,11 @@ def bench_plates64(args):
     return {"workload": "plates64: 64 plates, sizes %s, delta=3h, omega=sum_k a_k (r/delta)^k per plate, "
                         "target + forward + adjoint FP32-refined solves to 1e-10 and dL/da" % sizes,
             "plates": len(ws), "dofs_total": dofs, "solves": 3 * len(ws),
-            "seconds": round(dt, 3), "mode": "64 plans in one plan group (one launch per pass)",
+            "seconds": round(dt, 3), "mode": "64 plans in one plan group (one launch per pass; a 2D tiled "
+                                              "configuration: one launch of the block kernel per product)",
+            "graph_block": args.graph_block,
+            "work_list": "per-pass group launches over the members still iterating (rebuilt at each flag "
+                         "check), not a persistent kernel",
             "seconds_group_pcg": round(dtc, 3), "speedup_group_pcg_vs_group": round(dt / dtc, 2),
             "grad_max_rel_diff_pcg_vs_cg": gdiff(grads_c, grads),
             "seconds_64_plans_one_after_another": round(dtp, 3),

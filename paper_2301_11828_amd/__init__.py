@@ -231,6 +231,7 @@ class Plan:
         # broken bonds, surface factors), which it cannot restore
         self._infl_state = (np.array(infl, dtype=np.float64), False)
         self._struct_version = 0
+        self.graph_block = 0   # default of solve(): CG iterations per hipGraph launch (0: none)
 
     def close(self):
         if self._ptr:
@@ -411,14 +412,17 @@ class Plan:
         return out
 
     def solve(self, b, g=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
-              inner_tol: float = 0.0, graph_block: int = 0, reliable_update: int = 0, out=None,
+              inner_tol: float = 0.0, graph_block=None, reliable_update: int = 0, out=None,
               check: bool = True, precond: bool = False):
         """Static model: K u = b on free DOFs, u = g on constrained (K = -A).  Returns (u, infos).
-        precond: CG preconditioned by the circulant inverse of the periodic operator."""
+        precond: CG preconditioned by the circulant inverse of the periodic operator;
+        graph_block: CG iterations per hipGraph launch (None: the plan's `graph_block`
+        attribute, 0 unless set, which the autograd function's solves also use)."""
         torch = _torch()
         if out is None:
             out = torch.empty_like(b)
-        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), int(reliable_update), int(bool(precond)))
+        gb = self.graph_block if graph_block is None else int(graph_block)
+        opts = _Opts(tol, int(maxit), float(inner_tol), gb, int(reliable_update), int(bool(precond)))
         infos = (_Info * self.batch)()
         gp = self._vec(g, torch.float64, "g") if g is not None else None
         st = _lib.msb_solve_static(self._ptr, _PREC[precision], self._vec(b, torch.float64, "b"), gp,
@@ -502,6 +506,7 @@ class PlanGroup:
         _check(lib.msb_group_create(arr, len(self.plans), ctypes.byref(self._ptr)))
         self.total_cases = sum(p.batch for p in self.plans)
         self.precond = bool(precond)   # default of solve(): circulant-preconditioned CG
+        self.graph_block = 0           # default of solve(): CG iterations per hipGraph launch (0: none)
 
     def close(self):
         if self._ptr:
@@ -576,15 +581,17 @@ class PlanGroup:
             p._infl_state = (a.copy(), c)
 
     def solve(self, bs, gs=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
-              inner_tol: float = 0.0, graph_block: int = 0, outs=None, check: bool = True, precond=None):
+              inner_tol: float = 0.0, graph_block=None, outs=None, check: bool = True, precond=None):
         """Static solves of every member at once; returns (list of u, list of per-member info lists).
-        precond: each member's CG preconditioned by its circulant inverse (None: the
-        group's `precond` attribute, which the autograd function's solves also use)."""
+        precond: each member's CG preconditioned by its circulant inverse; graph_block: CG
+        iterations per hipGraph launch (None: the group's `precond` / `graph_block`
+        attributes, which the autograd function's solves also use)."""
         torch = _torch()
         if outs is None:
             outs = [torch.empty_like(b) for b in bs]
         pre = self.precond if precond is None else bool(precond)
-        opts = _Opts(tol, int(maxit), float(inner_tol), int(graph_block), 0, int(pre))
+        gb = self.graph_block if graph_block is None else int(graph_block)
+        opts = _Opts(tol, int(maxit), float(inner_tol), gb, 0, int(pre))
         infos = (_Info * self.total_cases)()
         gp = None
         if gs is not None:

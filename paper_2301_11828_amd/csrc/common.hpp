@@ -81,7 +81,7 @@ struct FftSched {
 };
 
 inline FftSched sched_of(const FftAxis &a, bool fp32 = false) {
-    FftSched s;
+    FftSched s{};   // unused passes zero: argument blocks compare bytewise (cached solver graphs)
     s.L = a.L;
     s.np = fp32 ? a.np32 : a.np;
     const int *radix = fp32 ? a.radix32 : a.radix;

@@ -1052,6 +1052,7 @@ template <> const float *sel<float>(const double *, const float *b) { return b; 
 
 template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp &op, const msb_launch_config *cfg) {
     PassArgs<T> a;
+    memset(&a, 0, sizeof(a));   // padding zero: argument blocks compare bytewise (cached solver graphs)
     const bool f32 = sizeof(T) == 4;
     a.d = p->dim;
     a.B = p->B;

@@ -55,7 +55,21 @@ struct SolverWs {
     int P = 1;                       // vector-kernel blocks per case
     hipStream_t st = nullptr;        // internal stream (graph capture needs a non-null stream)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // captured blocks of CG iterations kept for later solves with the same arguments (the
+    // inner solves of the refinement loop): key = every argument the iterations read
+    struct CgGraph {
+        std::vector<unsigned char> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    } graphs[2];
+    int graph_next = 0;              // entry the next new graph replaces
 };
+
+static void drop_graph(SolverWs::CgGraph &g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = SolverWs::CgGraph();
+}
 
 void solver_cache_free(msb_plan_s *p) {
     SolverWs *w = static_cast<SolverWs *>(p->solver_cache);
@@ -70,6 +84,7 @@ void solver_cache_free(msb_plan_s *p) {
         if (x) (void)hipFree(x);
     if (w->h_scal) (void)hipHostFree(w->h_scal);
     if (w->h_int) (void)hipHostFree(w->h_int);
+    for (auto &g : w->graphs) drop_graph(g);
     if (w->ev_in) (void)hipEventDestroy(w->ev_in);
     if (w->ev_out) (void)hipEventDestroy(w->ev_out);
     if (w->st) (void)hipStreamDestroy(w->st);
@@ -298,6 +313,40 @@ template <int K> __global__ __launch_bounds__(kSumT) void k_cg_sums(SumSrc src, 
 // Tiles per case above which the per-case sums come from k_cg_sums.
 constexpr int kFusedReduceMaxTiles = 1024;
 
+// The per-case sums of one plan-group member for one CG slot: K arrays of partials (p[k] +
+// case * n[k]), results to out[case * K + k]; out null: the member reduces in its prologue
+// (few tiles per case), as the plan alone does.
+struct GroupSum {
+    const double *p[5];
+    int n[5];
+    double *out;
+};
+
+// k_cg_sums over the cases of several members: one workgroup per case; cstart[] holds the
+// members' case offsets (cstart[n] = the cases of the launch).
+template <int K>
+__global__ __launch_bounds__(kSumT) void k_group_sums(const GroupSum *__restrict__ S, const int *__restrict__ cstart,
+                                                      int n) {
+    __shared__ double red[96];
+    const int c = blockIdx.x;
+    const int j = group_member(cstart, n, c);
+    const GroupSum &s = S[j];
+    if (!s.out) return;   // uniform over the workgroup
+    const int b = c - cstart[j];
+    const double *parts[K];
+    int cnt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        parts[k] = s.p[k] + (size_t)b * s.n[k];
+        cnt[k] = s.n[k];
+    }
+    double sums[K];
+    block_sum_partials_k<K>(parts, cnt, sums, red, threadIdx.x, blockDim.x);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < K; ++k) s.out[(size_t)b * K + k] = sums[k];
+    }
+}
+
 // One CG iteration = one product chain.  The x-forward prologue applies the
 // previous iteration's update (x += alpha p, r -= alpha q, alpha and beta from the
 // previous partial sums) and forms p = r + beta p; the x-inverse epilogue forms
@@ -352,12 +401,24 @@ constexpr int kPollIterations = 32;
 // tolerance but the residual b' - K u does not.
 constexpr int kPolish = 4;
 
+// Argument bytes of a captured block of iterations (the cache key of its graph).
+struct GraphKey {
+    std::vector<unsigned char> b;
+    template <typename V> void add(const V &v) {
+        const unsigned char *q = reinterpret_cast<const unsigned char *>(&v);
+        b.insert(b.end(), q, q + sizeof(V));
+    }
+};
+
 // Run CG iterations iter(it, update_only) from the prepared state (vectors, partials,
 // thresholds and both parity slots of the flags set).  Stops when every case has a
-// flag or after maxit iterations; the final flags end in slot 0.
+// flag or after maxit iterations; the final flags end in slot 0.  Blocks of iterations
+// 1 .. (every block starts at an odd iteration, so all are alike) run as one hipGraph
+// when graph_block > 0; with a key, the graph is kept in the workspace and replayed by
+// later calls with the same key (no new capture per inner solve).
 template <typename It>
 static msb_status run_iterations(SolverWs *w, int B, hipStream_t st, It iter, int maxit, int graph_block,
-                                 int *it_out) {
+                                 int *it_out, GraphKey *key = nullptr) {
     int it = 0;
     MSB_TRY(iter(0, false));
     it = 1;
@@ -365,6 +426,15 @@ static msb_status run_iterations(SolverWs *w, int B, hipStream_t st, It iter, in
     const int block = poll + (poll & 1);   // even: keeps the partial-sum parity of replays fixed
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
+    bool cached = false;                   // exec belongs to the workspace cache
+    if (key && graph_block > 0) {
+        key->add(block);
+        for (auto &g : w->graphs)
+            if (g.exec && g.key == key->b) {
+                exec = g.exec;
+                cached = true;
+            }
+    }
     msb_status s = MSB_OK;
     while (it < maxit && s == MSB_OK) {
         MSB_HIP(hipMemcpyAsync(w->h_int, w->done + (size_t)((it - 1) & 1) * B, sizeof(int) * B,
@@ -382,6 +452,16 @@ static msb_status run_iterations(SolverWs *w, int B, hipStream_t st, It iter, in
                 if (s != MSB_OK) break;
                 MSB_HIP(e1);
                 MSB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+                if (key) {   // keep it: replaces the older entry
+                    SolverWs::CgGraph &g = w->graphs[w->graph_next];
+                    w->graph_next = (w->graph_next + 1) % 2;
+                    drop_graph(g);
+                    g.key = key->b;
+                    g.graph = graph;
+                    g.exec = exec;
+                    graph = nullptr;
+                    cached = true;
+                }
             }
             MSB_HIP(hipGraphLaunch(exec, st));
         } else {
@@ -389,7 +469,7 @@ static msb_status run_iterations(SolverWs *w, int B, hipStream_t st, It iter, in
         }
         it += k;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
+    if (exec && !cached) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     // iteration cap: apply the pending update of the cases still running
     if (s == MSB_OK) s = iter(it, true);
@@ -401,7 +481,13 @@ static msb_status run_iterations(SolverWs *w, int B, hipStream_t st, It iter, in
 
 template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_block, int *it_out) {
     auto iter = [&c](int it, bool upd) { return cg_iteration(c, it, upd); };
-    return run_iterations(c.w, c.p->B, c.st, iter, maxit, graph_block, it_out);
+    // everything iterations >= 1 read (c.prev_rr only enters iteration 0)
+    GraphKey key;
+    key.add((int)sizeof(T));
+    key.add(0);
+    key.add(c.pa);
+    key.add(c.x), key.add(c.r), key.add(c.pv), key.add(c.q), key.add(c.tpc), key.add(c.st);
+    return run_iterations(c.w, c.p->B, c.st, iter, maxit, graph_block, it_out, &key);
 }
 
 // Denominator of the first beta after a residual replacement (reliable update): the
@@ -563,7 +649,12 @@ static msb_status pcg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T 
     MSB_HIP(hipGetLastError());
     int it = 0;
     auto iter = [&c](int k, bool upd) { return pcg_iteration(c, k, upd); };
-    msb_status r0 = run_iterations(w, B, st, iter, maxit, graph_block, &it);
+    GraphKey key;   // everything iterations >= 1 read (c.prev_rz only enters iteration 0)
+    key.add((int)sizeof(T));
+    key.add(1);
+    key.add(c.pa), key.add(c.pp);
+    key.add(c.x), key.add(c.r), key.add(c.pv), key.add(c.q), key.add(c.z), key.add(c.tpc), key.add(c.st);
+    msb_status r0 = run_iterations(w, B, st, iter, maxit, graph_block, &it, &key);
     if (iters_out) *iters_out = it;
     return r0;
 }
@@ -1277,6 +1368,11 @@ struct msb_group_s {
     std::vector<int64_t> layout_seen;          // members' layout versions the tile tables were built for
     hipStream_t st = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    SolverWs::CgGraph graphs[2];               // captured iteration blocks kept across group CG runs
+    int graph_next = 0;
+    double *case4 = nullptr;                   // [Btot][5] per-case CG sums (members with many tiles)
+    void *dS = nullptr;                        // device GroupSum[kSlots][n]: their sources per slot
+    int *dcase = nullptr;                      // [n + 1] case offsets of the members a launch covers
 };
 
 namespace msb {
@@ -1394,6 +1490,7 @@ template <typename T> msb_status group_upload_end(msb_group_s *g, int slot, cons
 struct GroupView {
     int n = 0;
     int total[4] = {0, 0, 0, 0};
+    int cases = 0;   // cases of the members covered
 };
 
 template <typename T> GroupView full_view(const msb_group_s *g) {
@@ -1401,6 +1498,7 @@ template <typename T> GroupView full_view(const msb_group_s *g) {
     GroupView v;
     v.n = g->n;
     for (int k = 0; k < 4; ++k) v.total[k] = g->start[f][k][g->n];
+    v.cases = g->Btot;
     return v;
 }
 
@@ -1439,7 +1537,8 @@ msb_status group_launch(msb_group_s *g, const std::vector<PassArgs<T>> &A, int s
 template <typename T>
 msb_status group_load_members(msb_group_s *g, const std::vector<int> &act, const std::vector<PassArgs<T>> &A,
                               const std::vector<std::vector<EndArgs<T>>> &Eslots, GroupView &v,
-                              const std::vector<PassArgs<T>> *Ap = nullptr) {
+                              const std::vector<PassArgs<T>> *Ap = nullptr,
+                              const std::vector<std::vector<GroupSum>> *Sslots = nullptr) {
     const int f = prec_index<T>();
     const int na = (int)act.size();
     std::vector<PassArgs<T>> Aa(na), Apa(Ap ? na : 0);
@@ -1463,6 +1562,17 @@ msb_status group_load_members(msb_group_s *g, const std::vector<int> &act, const
         for (int j = 0; j < na; ++j) Ea[j] = Eslots[slot][act[j]];
         EndArgs<T> *dst = static_cast<EndArgs<T> *>(g->dE[f]) + slot * g->n;
         MSB_HIP(hipMemcpy(dst, Ea.data(), sizeof(EndArgs<T>) * na, hipMemcpyHostToDevice));
+    }
+    std::vector<int> cs(na + 1, 0);
+    for (int j = 0; j < na; ++j) cs[j + 1] = cs[j] + g->m[act[j]]->B;
+    v.cases = cs[na];
+    MSB_HIP(hipMemcpy(g->dcase, cs.data(), sizeof(int) * (na + 1), hipMemcpyHostToDevice));
+    for (size_t slot = 0; Sslots && slot < Sslots->size(); ++slot) {
+        if ((*Sslots)[slot].empty()) continue;
+        std::vector<GroupSum> Sa(na);
+        for (int j = 0; j < na; ++j) Sa[j] = (*Sslots)[slot][act[j]];
+        GroupSum *dst = static_cast<GroupSum *>(g->dS) + slot * g->n;
+        MSB_HIP(hipMemcpy(dst, Sa.data(), sizeof(GroupSum) * na, hipMemcpyHostToDevice));
     }
     return MSB_OK;
 }
@@ -1506,6 +1616,16 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     // end arguments of the iteration slots (no kernel of an earlier solve still reads them)
     MSB_HIP(hipStreamSynchronize(st));
     std::vector<std::vector<EndArgs<T>>> Eslots((pcg ? G_PA_ODD : G_UPD_ODD) + 1, std::vector<EndArgs<T>>(g->n));
+    // members with many tiles per case take their per-case sums from k_group_sums before the
+    // prologue (the rule of the plan alone, so that a member's arithmetic is its own solve's)
+    std::vector<std::vector<GroupSum>> Sslots(Eslots.size());
+    std::vector<int> many(g->n, 0);
+    bool need_sums = false;
+    for (int i = 0; i < g->n; ++i) {
+        const int tpc = (g->start[f][0][i + 1] - g->start[f][0][i]) / g->m[i]->B;
+        many[i] = std::max(tpc, g->ept[f][i]) > kFusedReduceMaxTiles;
+        need_sums = need_sums || many[i];
+    }
     for (int slot = G_FIRST; slot <= G_UPD_ODD; ++slot) {
         const int parity = (slot == G_ODD || slot == G_UPD_ODD) ? 1 : 0;
         const int prv = (parity + 1) & 1;
@@ -1547,6 +1667,18 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
                 e.part = g->part_x + 3 * po;
                 e.no_transform = g->tiled[f];   // the tiled product: the x pass is the prologue alone
             }
+            GroupSum sm{};
+            if (many[i] && slot != G_FIRST) {
+                const int tpc = nt / g->m[i]->B, ept = e.n_cg3;
+                const double *c3 = e.cg3;
+                const size_t s3 = e.s_cg3;
+                if (pcg) sm = GroupSum{{e.rr_prev, e.rz_k, c3, c3 + s3, c3 + 2 * s3}, {tpc, tpc, ept, ept, ept}, nullptr};
+                else sm = GroupSum{{e.rr_prev, c3, c3 + s3, c3 + 2 * s3, nullptr}, {tpc, ept, ept, ept, 0}, nullptr};
+                sm.out = g->case4 + 5 * (size_t)co;
+                e.case4 = sm.out;
+            }
+            if (Sslots[slot].empty()) Sslots[slot].resize(g->n);
+            Sslots[slot][i] = sm;
             Eslots[slot][i] = e;
         }
     }
@@ -1571,6 +1703,15 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
             e.rhs = r[i];
             e.part = g->part_x + 3 * po;
             e.no_transform = g->tiled[f];
+            GroupSum sm{};
+            if (many[i] && slot != G_PA_FIRST) {
+                const int tpc = (g->start[f][0][i + 1] - g->start[f][0][i]) / g->m[i]->B;
+                sm = GroupSum{{e.rz_k, e.rz_km1, nullptr, nullptr, nullptr}, {tpc, tpc, 0, 0, 0},
+                              g->case4 + 5 * (size_t)g->case_off[i]};
+                e.case4 = sm.out;
+            }
+            if (Sslots[slot].empty()) Sslots[slot].resize(g->n);
+            Sslots[slot][i] = sm;
             Eslots[slot][i] = e;
         }
     }
@@ -1579,12 +1720,46 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     std::vector<int> act(g->n);
     for (int i = 0; i < g->n; ++i) act[i] = i;
     GroupView view;
-    MSB_TRY(group_load_members<T>(g, act, A, Eslots, view, Ap));
+    MSB_TRY(group_load_members<T>(g, act, A, Eslots, view, Ap, &Sslots));
+    // A captured block of iterations reads the argument arrays and tile tables at run time;
+    // what it fixes is the launch geometry of the view: a graph of an earlier run (the
+    // inner solves of the refinement loop) with the same geometry is replayed, not recaptured
+    auto graph_key = [&](int block) {
+        GraphKey k;
+        k.add((int)sizeof(T));
+        k.add((int)pcg);
+        k.add(A[0]);
+        k.add(view.n);
+        k.add(view.total);
+        k.add(g->lds[f]);
+        k.add(g->composite[f]);
+        k.add(g->tiled[f]);
+        k.add(st);
+        k.add(block);
+        k.add(view.cases);
+        k.add(need_sums);
+        return k.b;
+    };
+    // per-case sums of the members with many tiles, before a slot's prologue (not on the
+    // first iteration, whose prologue reduces nothing)
+    auto sums = [&](int slot) {
+        if (!need_sums || slot == G_FIRST || slot == G_PA_FIRST) return;
+        const GroupSum *S = static_cast<const GroupSum *>(g->dS) + (size_t)slot * g->n;
+        if (slot >= G_PA_FIRST)
+            hipLaunchKernelGGL(k_group_sums<2>, dim3(view.cases), dim3(kSumT), 0, st, S, g->dcase, view.n);
+        else if (pcg)
+            hipLaunchKernelGGL(k_group_sums<5>, dim3(view.cases), dim3(kSumT), 0, st, S, g->dcase, view.n);
+        else
+            hipLaunchKernelGGL(k_group_sums<4>, dim3(view.cases), dim3(kSumT), 0, st, S, g->dcase, view.n);
+    };
     auto iteration = [&](int it, bool upd) -> msb_status {
         const int slot = upd ? ((it & 1) ? G_UPD_ODD : G_UPD_EVEN) : (it == 0 ? G_FIRST : ((it & 1) ? G_ODD : G_EVEN));
+        sums(slot);
         MSB_TRY(group_launch<T>(g, A, slot, st, &view, pcg));
         if (!pcg || upd) return MSB_OK;
-        return group_launch<T>(g, A, it == 0 ? G_PA_FIRST : ((it & 1) ? G_PA_ODD : G_PA_EVEN), st, &view);
+        const int slot2 = it == 0 ? G_PA_FIRST : ((it & 1) ? G_PA_ODD : G_PA_EVEN);
+        sums(slot2);
+        return group_launch<T>(g, A, slot2, st, &view);
     };
     MSB_TRY(iteration(0, false));
     int it = 1;
@@ -1592,6 +1767,14 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     const int block = poll + (poll & 1);   // even: keeps the partial-sum parity of replays fixed
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
+    auto find_graph = [&]() -> hipGraphExec_t {
+        if (graph_block <= 0) return nullptr;
+        const std::vector<unsigned char> k = graph_key(block);
+        for (auto &e : g->graphs)
+            if (e.exec && e.key == k) return e.exec;
+        return nullptr;
+    };
+    exec = find_graph();
     msb_status s = MSB_OK;
     while (it < maxit && s == MSB_OK) {
         MSB_HIP(hipMemcpyAsync(g->h_int, g->done + (size_t)((it - 1) & 1) * g->Btot, sizeof(int) * g->Btot,
@@ -1606,11 +1789,8 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
         if (now.empty()) break;
         if (now != act) {   // the stream is idle here (synchronised above)
             act = now;
-            MSB_TRY(group_load_members<T>(g, act, A, Eslots, view, Ap));
-            if (exec) (void)hipGraphExecDestroy(exec);
-            if (graph) (void)hipGraphDestroy(graph);
-            exec = nullptr;
-            graph = nullptr;
+            MSB_TRY(group_load_members<T>(g, act, A, Eslots, view, Ap, &Sslots));
+            exec = find_graph();   // cached graphs stay in the cache
         }
         const int k = std::min(block, maxit - it);
         if (graph_block > 0 && k == block) {
@@ -1618,9 +1798,23 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
                 MSB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 for (int j = 0; j < block && s == MSB_OK; ++j) s = iteration(it + j, false);
                 hipError_t e1 = hipStreamEndCapture(st, &graph);
-                if (s != MSB_OK) break;
+                if (s != MSB_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    break;
+                }
                 MSB_HIP(e1);
-                MSB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+                hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (e2 != hipSuccess) {
+                    (void)hipGraphDestroy(graph);
+                    MSB_HIP(e2);
+                }
+                SolverWs::CgGraph &c = g->graphs[g->graph_next];   // kept: replaces the older entry
+                g->graph_next = (g->graph_next + 1) % 2;
+                drop_graph(c);
+                c.key = graph_key(block);
+                c.graph = graph;
+                c.exec = exec;
+                graph = nullptr;
             }
             MSB_HIP(hipGraphLaunch(exec, st));
         } else {
@@ -1628,8 +1822,6 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
         }
         it += k;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     if (s == MSB_OK) s = iteration(it, true);   // iteration cap: pending update of running cases
     if (s == MSB_OK && (it & 1))                  // the final flags into slot 0
         MSB_HIP(hipMemcpyAsync(g->done, g->done + g->Btot, sizeof(int) * g->Btot, hipMemcpyDeviceToDevice, st));
@@ -1637,7 +1829,7 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     MSB_HIP(hipStreamSynchronize(st));
     std::vector<int> all(g->n);
     for (int i = 0; i < g->n; ++i) all[i] = i;
-    if (s == MSB_OK) s = group_load_members<T>(g, all, A, Eslots, view, Ap);
+    if (s == MSB_OK) s = group_load_members<T>(g, all, A, Eslots, view, Ap, &Sslots);
     return s;
 }
 
@@ -1679,13 +1871,15 @@ msb_status group_fetch(msb_group_s *g, int nslots) {
 }
 
 void group_free(msb_group_s *g) {
+    for (auto &c : g->graphs) drop_graph(c);
     for (int f = 0; f < 2; ++f) {
         if (g->dstart[f]) (void)hipFree(g->dstart[f]);
         if (g->dA[f]) (void)hipFree(g->dA[f]);
         if (g->dAp[f]) (void)hipFree(g->dAp[f]);
         if (g->dE[f]) (void)hipFree(g->dE[f]);
     }
-    void *b[] = {g->part_x, g->part_rr, g->part_rz, g->thresh, g->scal, g->done, g->iters, g->skip};
+    void *b[] = {g->part_x, g->part_rr, g->part_rz, g->thresh, g->scal, g->done, g->iters, g->skip, g->case4, g->dS,
+                 g->dcase};
     for (void *x : b)
         if (x) (void)hipFree(x);
     if (g->h_scal) (void)hipHostFree(g->h_scal);
@@ -1732,6 +1926,9 @@ extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_gr
         if (hipMalloc(&g->dA[f], pa * nplans) != hipSuccess) return fail(MSB_ENOMEM);
         if (hipMalloc(&g->dAp[f], pa * nplans) != hipSuccess) return fail(MSB_ENOMEM);
         if (hipMalloc(&g->dE[f], ea * kSlots * nplans) != hipSuccess) return fail(MSB_ENOMEM);
+        if (f == 0 && (hipMalloc(&g->dS, sizeof(GroupSum) * kSlots * nplans) != hipSuccess ||
+                       hipMalloc(&g->dcase, sizeof(int) * (nplans + 1)) != hipSuccess))
+            return fail(MSB_ENOMEM);
         msb_status s = group_config(g, f, nullptr);
         if (s != MSB_OK) return fail(s);
     }
@@ -1747,6 +1944,7 @@ extern "C" msb_status msb_group_create(const msb_plan *plans, int nplans, msb_gr
         hipMalloc(&g->part_rr, sizeof(double) * 2 * tiles_max) != hipSuccess ||
         hipMalloc(&g->part_rz, sizeof(double) * 6 * tiles_max) != hipSuccess ||
         hipMalloc(&g->thresh, sizeof(double) * nb) != hipSuccess ||
+        hipMalloc(&g->case4, sizeof(double) * 5 * nb) != hipSuccess ||
         hipMalloc(&g->scal, sizeof(double) * 16 * nb) != hipSuccess ||
         hipMalloc(&g->done, sizeof(int) * 2 * nb) != hipSuccess || hipMalloc(&g->iters, sizeof(int) * nb) != hipSuccess ||
         hipMalloc(&g->skip, sizeof(int) * nb) != hipSuccess ||

@@ -197,3 +197,32 @@ def test_plate512_pcg_at_the_benchmark_tuning_certified_by_oracle():
         res = np.linalg.norm(r) / np.linalg.norm(bp)
         log("plate512 PCG %s: %d it, oracle residual %.2e" % (prec, info[0].inner_iters, res))
         assert info[0].status == 0 and res <= 1.05e-10
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_refined_graph_blocks_reused_across_solves_equal_plain(precond):
+    """The refinement loop's inner solves replay one captured block of iterations (kept in the
+    plan's workspace across calls): every solve equals its plain-launch twin bit for bit,
+    also after new coefficients and after a configuration change (a new capture)."""
+    import torch
+    w = W.small(2, (40, 31), 3, seed=221, fixed="left", crack=True, batch=2, infl=(0.7, 0.2))
+    plan = gpu_plan(w)
+    rng = np.random.default_rng(222)
+    steps = [None, dict(infl=(0.5, 0.4)), dict(cfg=dict(tile=16, tile_regs=1, tile_run=1)), None]
+    for k, step in enumerate(steps):
+        if step and "infl" in step:
+            plan.set_infl(np.array(step["infl"]))
+        if step and "cfg" in step:
+            for f in ("fp64", "fp32"):
+                plan.set_config(f, **step["cfg"])
+        b = to_dev(rng.standard_normal((w.batch, 2, w.N)))
+        for rel in (0, 1):
+            a, ia = plan.solve(b, precision="fp32_refined", tol=1e-11, graph_block=8, precond=precond,
+                               reliable_update=rel)
+            a = a.clone()
+            c, ic = plan.solve(b, precision="fp32_refined", tol=1e-11, graph_block=0, precond=precond,
+                               reliable_update=rel)
+            log("graph reuse step %d reliable %d: %s vs %s iterations" % (k, rel, [x.inner_iters for x in ia],
+                                                                        [x.inner_iters for x in ic]))
+            assert torch.equal(a, c)
+            assert [x.inner_iters for x in ia] == [x.inner_iters for x in ic]
