@@ -409,7 +409,8 @@ msb_status msb_plan_autotune(msb_plan plan, msb_precision prec, int effort, int 
  * msb_group_solve_static: the static solve of msb_solve_static for every member at
  *   once: b, u: host arrays [nplans] of device pointers; g: null or such an array
  *   (entries may be null); info: host [total cases], member-major.  MSB_FP64,
- *   MSB_FP32 or MSB_FP32_REFINED (restarted refinement; reliable_update must be 0).
+ *   MSB_FP32 or MSB_FP32_REFINED (restarts, or reliable_update keeping each member's
+ *   search direction, as for one plan).
  *   opts->precond = 1 preconditions every member by its own circulant inverse (each
  *   built on first use, as for one plan; the host work of the missing ones runs on
  *   parallel host threads).

@@ -507,6 +507,7 @@ class PlanGroup:
         self.total_cases = sum(p.batch for p in self.plans)
         self.precond = bool(precond)   # default of solve(): circulant-preconditioned CG
         self.graph_block = 0           # default of solve(): CG iterations per hipGraph launch (0: none)
+        self.reliable_update = 0       # default of solve(): FP32_REFINED keeps the search direction
 
     def close(self):
         if self._ptr:
@@ -581,17 +582,21 @@ class PlanGroup:
             p._infl_state = (a.copy(), c)
 
     def solve(self, bs, gs=None, precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
-              inner_tol: float = 0.0, graph_block=None, outs=None, check: bool = True, precond=None):
+              inner_tol: float = 0.0, graph_block=None, outs=None, check: bool = True, precond=None,
+              reliable_update=None):
         """Static solves of every member at once; returns (list of u, list of per-member info lists).
         precond: each member's CG preconditioned by its circulant inverse; graph_block: CG
-        iterations per hipGraph launch (None: the group's `precond` / `graph_block`
-        attributes, which the autograd function's solves also use)."""
+        iterations per hipGraph launch; reliable_update: FP32_REFINED keeps the search
+        directions across residual replacements (None: the group's `precond` /
+        `graph_block` / `reliable_update` attributes, which the autograd function's solves
+        also use)."""
         torch = _torch()
         if outs is None:
             outs = [torch.empty_like(b) for b in bs]
         pre = self.precond if precond is None else bool(precond)
         gb = self.graph_block if graph_block is None else int(graph_block)
-        opts = _Opts(tol, int(maxit), float(inner_tol), gb, 0, int(pre))
+        rel = self.reliable_update if reliable_update is None else int(reliable_update)
+        opts = _Opts(tol, int(maxit), float(inner_tol), gb, int(rel), int(pre))
         infos = (_Info * self.total_cases)()
         gp = None
         if gs is not None:

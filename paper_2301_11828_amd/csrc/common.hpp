@@ -252,7 +252,9 @@ void free_operator(DeviceOp &op);
 // Frame spectra of every operator of the plan (op and the derivative operators) and the
 // frame axis for the tile lengths of both launch configurations and `extra` (if > 0);
 // host work and uploads, so never during graph capture (plan.cpp).
-msb_status ensure_tiles(msb_plan_s *p, int extra = 0);
+// Frame spectra for the plan's configured tile lengths and `extra` (all operators; for
+// `extra` only the stiffness operator when extra_op_only: a plan group's frame length).
+msb_status ensure_tiles(msb_plan_s *p, int extra = 0, bool extra_op_only = false);
 const TileSpec *find_tile_spec(const DeviceOp &op, int tl);
 const FftAxis *find_tile_axis(const msb_plan_s *p, int tl);
 void solver_cache_free(msb_plan_s *p);

@@ -724,10 +724,11 @@ static msb_status build_tile_spec(msb_plan_s *p, DeviceOp &op, int tl) {
     return MSB_OK;
 }
 
-msb_status ensure_tiles(msb_plan_s *p, int extra) {
+msb_status ensure_tiles(msb_plan_s *p, int extra, bool extra_op_only) {
     if (p->dim != 2) return MSB_OK;
     const int want[3] = {p->cfg[0].tile, p->cfg[1].tile, extra};
-    for (int tl : want) {
+    for (int w = 0; w < 3; ++w) {
+        const int tl = want[w];
         if (tl <= 0) continue;
         if (!find_tile_axis(p, tl)) {
             FftAxis ax;
@@ -735,6 +736,7 @@ msb_status ensure_tiles(msb_plan_s *p, int extra) {
             p->tax.push_back(ax);
         }
         if (p->op.count > 0 && !find_tile_spec(p->op, tl)) MSB_TRY(build_tile_spec(p, p->op, tl));
+        if (w == 2 && extra_op_only) continue;
         for (DeviceOp &d : p->dop)
             if (d.count > 0 && !find_tile_spec(d, tl)) MSB_TRY(build_tile_spec(p, d, tl));
     }

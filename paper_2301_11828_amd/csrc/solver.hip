@@ -1368,7 +1368,10 @@ struct msb_group_s {
     std::vector<int64_t> layout_seen;          // members' layout versions the tile tables were built for
     hipStream_t st = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    SolverWs::CgGraph graphs[2];               // captured iteration blocks kept across group CG runs
+    // captured iteration blocks kept across group CG runs: one per work list seen (members
+    // leave the list as they converge), replaced oldest first
+    static constexpr int kGraphs = 32;
+    SolverWs::CgGraph graphs[kGraphs];
     int graph_next = 0;
     double *case4 = nullptr;                   // [Btot][5] per-case CG sums (members with many tiles)
     void *dS = nullptr;                        // device GroupSum[kSlots][n]: their sources per slot
@@ -1439,7 +1442,7 @@ msb_status group_config(msb_group_s *g, int f, const msb_launch_config *want) {
     MSB_CHECK(ok, want ? MSB_EINVAL : MSB_EUNSUPPORTED, "launch configuration not valid for every member: %s",
               msb_last_error());
     // frame spectra of the members' operators for the tile length
-    for (int i = 0; i < g->n && c.tile > 0; ++i) MSB_TRY(ensure_tiles(g->m[i], c.tile));
+    for (int i = 0; i < g->n && c.tile > 0; ++i) MSB_TRY(ensure_tiles(g->m[i], c.tile, true));
     g->cfg[f] = c;
     return group_geometry(g, f);
 }
@@ -1471,7 +1474,7 @@ template <typename T> msb_status group_upload_args(msb_group_s *g, std::vector<P
     A.resize(g->n);
     for (int i = 0; i < g->n; ++i) {
         // new coefficients drop a member's frame spectra: rebuild those of the group's tile length
-        if (g->tiled[f]) MSB_TRY(ensure_tiles(g->m[i], g->cfg[f].tile));
+        if (g->tiled[f]) MSB_TRY(ensure_tiles(g->m[i], g->cfg[f].tile, true));
         A[i] = pass_args<T>(g->m[i], g->m[i]->op, &g->cfg[f]);
         MSB_CHECK(A[i].tl == (g->tiled[f] ? g->cfg[f].tile : 0), MSB_EDEVICE, "member %d: frame spectra missing", i);
     }
@@ -1592,18 +1595,22 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
                     const std::vector<T *> &x, const std::vector<T *> &r, const std::vector<T *> &pv,
                     const std::vector<T *> &q, double tol, int maxit, int graph_block, const int *skip,
                     const double *tol2_case = nullptr, const std::vector<PassArgs<T>> *Ap = nullptr,
-                    const std::vector<T *> *z = nullptr) {
+                    const std::vector<T *> *z = nullptr, const double *prev = nullptr) {
+    // prev (reliable update): [poff] the r.r (r.z) partials of the step that formed each
+    // member's kept search direction pv; the first beta continues from them
     const int f = prec_index<T>();
     hipStream_t st = g->st;
     const bool pcg = Ap != nullptr;
     if (pcg && !z) return MSB_EINVAL;
+    std::vector<SolverWs *> ws(g->n);
     for (int i = 0; i < g->n; ++i) {
         msb_plan_s *p = g->m[i];
         SolverWs *w = nullptr;
         MSB_TRY(get_ws(p, w));
+        ws[i] = w;
         const size_t nv = w->nvec;
         hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kT), 0, st, x[i], nv, T(0));
-        hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kT), 0, st, pv[i], nv, T(0));
+        if (!prev) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kT), 0, st, pv[i], nv, T(0));
         hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(nv)), dim3(kT), 0, st, r[i], rhs[i], nv);
         hipLaunchKernelGGL(k_dot_parts<T>, dim3(p->B * w->P), dim3(kT), 0, st, (const T *)r[i], (const T *)r[i],
                            w->part_aux, (size_t)p->dim * p->N, w->P);
@@ -1648,6 +1655,12 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
             if (pcg) e.rz_k = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * po;
             e.first = slot == G_FIRST;
             e.update_only = slot == G_UPD_EVEN || slot == G_UPD_ODD;
+            if (slot == G_FIRST && prev && !pcg) {   // continuation: beta = (new r.r) / saved r.r
+                e.beta_num = ws[i]->part_aux;
+                e.n_num = ws[i]->P;
+                e.beta_den = prev + po;
+                e.n_den = nt / g->m[i]->B;
+            }
             e.iters = g->iters + co;
             e.done_prev = g->done + (size_t)prv * g->Btot + co;
             e.case_done = g->done + (size_t)parity * g->Btot + co;
@@ -1696,6 +1709,10 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
             e.rz_k = g->part_rz + (size_t)parity * 3 * g->tiles_max + 3 * po;
             e.rz_km1 = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * po;
             e.first = slot == G_PA_FIRST;
+            if (slot == G_PA_FIRST && prev) {   // continuation: beta = (new r.z) / saved r.z
+                e.first = false;
+                e.rz_km1 = prev + po;
+            }
             e.case_done = g->done + (size_t)parity * g->Btot + g->case_off[i];
             e.epi = EPI_CG_Q;
             e.uin = pv[i];
@@ -1809,7 +1826,7 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
                     MSB_HIP(e2);
                 }
                 SolverWs::CgGraph &c = g->graphs[g->graph_next];   // kept: replaces the older entry
-                g->graph_next = (g->graph_next + 1) % 2;
+                g->graph_next = (g->graph_next + 1) % msb_group_s::kGraphs;
                 drop_graph(c);
                 c.key = graph_key(block);
                 c.graph = graph;
@@ -1831,6 +1848,21 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     for (int i = 0; i < g->n; ++i) all[i] = i;
     if (s == MSB_OK) s = group_load_members<T>(g, all, A, Eslots, view, Ap, &Sslots);
     return s;
+}
+
+// Reliable updates: each member's r.r (pcg: r.z) partials of the step that formed its search
+// direction, into prev + poff[i] (k_save_last), after a group CG run in precision f.
+msb_status group_save_last(msb_group_s *g, int f, bool pcg, double *prev) {
+    for (int i = 0; i < g->n; ++i) {
+        const int B = g->m[i]->B;
+        const int nt = g->start[f][0][i + 1] - g->start[f][0][i];
+        const size_t po = g->poff[i];
+        const double *part = pcg ? g->part_rz + 3 * po : g->part_rr + 2 * po;
+        hipLaunchKernelGGL(k_save_last, dim3(B), dim3(64), 0, g->st, part, pcg ? 3 * g->tiles_max : (size_t)nt,
+                           (const int *)(g->iters + g->case_off[i]), nt / B, prev + po);
+    }
+    MSB_HIP(hipGetLastError());
+    return MSB_OK;
 }
 
 // per-case ||rhs_i + A x_i||^2 on free DOFs into g->scal[slot*Btot + case], residual into out_i
@@ -2191,7 +2223,6 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
     MSB_CHECK(opts->tol > 0 && opts->tol < 1 && opts->maxit > 0, MSB_EINVAL, "need 0 < tol < 1 and maxit > 0");
     MSB_CHECK(prec == MSB_FP64 || prec == MSB_FP32 || prec == MSB_FP32_REFINED, MSB_EINVAL, "bad precision");
     MSB_CHECK(opts->graph_block >= 0 && opts->graph_block <= 4096, MSB_EINVAL, "graph_block out of range");
-    MSB_CHECK(opts->reliable_update == 0, MSB_EUNSUPPORTED, "groups refine by restarts only (reliable_update = 0)");
     MSB_CHECK(opts->precond == 0 || opts->precond == 1, MSB_EINVAL, "precond must be 0 or 1");
     for (int i = 0; i < g->n; ++i)
         MSB_CHECK(!g->m[i]->nu64, MSB_EUNSUPPORTED, "member %d: the surface-corrected operator is not symmetric", i);
@@ -2342,9 +2373,15 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
             outer[c] = 1;
         }
     } else {
-        // restarted iterative refinement, as msb_solve_static: FP32 CG on K d = r to a
-        // reduction of inner_tol, u += d in FP64, r = b' - K u with the FP64 product
-        const double itol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
+        // iterative refinement, as msb_solve_static: FP32 CG on K d = r to a reduction of
+        // inner_tol, u += d in FP64, r = b' - K u with the FP64 product; CG restarts, or
+        // (reliable_update) keeps each member's search direction across the replacement
+        const bool reliable = opts->reliable_update != 0;
+        const double itol = opts->inner_tol > 0 ? opts->inner_tol : (reliable ? 0.1 : 1e-4);
+        CallBuf prev_buf;
+        if (reliable) MSB_HIP(hipMalloc(&prev_buf.p, sizeof(double) * g->tiles_max));
+        double *prev = static_cast<double *>(prev_buf.p);
+        bool first = true;
         std::vector<const float *> r32c(n);
         std::vector<float *> r32(n), d32(n), p32(n), q32(n), rr32(n);
         std::vector<double *> r64(n), uu(u, u + n);
@@ -2382,7 +2419,9 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
             for (int i = 0; i < n; ++i)
                 hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(w[i]->nvec)), dim3(kT), 0, st, r32[i], (const double *)r64[i], w[i]->nvec);
             MSB_TRY(group_cg<float>(g, A32, r32c, d32, rr32, p32, q32, itol, opts->maxit - used, gb, g->skip, t2d, ap32,
-                                    zz32));
+                                    zz32, (reliable && !first) ? prev : nullptr));
+            first = false;
+            if (reliable) MSB_TRY(group_save_last(g, 1, pre, prev));
             MSB_TRY(group_fetch(g, 0));
             int mx = 0;
             for (int c = 0; c < Bt; ++c) {

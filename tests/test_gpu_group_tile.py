@@ -176,3 +176,37 @@ def test_group_tiled_configuration_rules():
         assert err <= FP64_TOL
     g2.close()
     grp.close()
+
+
+@pytest.mark.parametrize("precond", [False, True])
+@pytest.mark.parametrize("cfg", [None, TILED[0]], ids=["chain", "t16r"])
+def test_group_reliable_update_matches_cholesky(precond, cfg):
+    """Group refinement that keeps every member's search direction across the FP64 residual
+    replacements (plain and preconditioned, chain and tiled products) against each member's
+    dense Cholesky solve; certified residual <= tol."""
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (25, 22), 3, seed=751, fixed="left", crack=True, batch=2),
+          W.small(2, (14, 18), 3, seed=752, fixed="all", batch=1, infl=(0.5, 0.2)),
+          W.small(2, (117, 6), 3, seed=753, fixed="bottom", batch=2)]
+    rng = np.random.default_rng(754)
+    gs = [np.where(w.fixed[None], 1e-2 * rng.standard_normal((w.batch, 2, w.N)), 0.0) for w in ws]
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    if cfg:
+        for f in ("fp64", "fp32"):
+            grp.set_config(f, **cfg)
+    tol = 1e-11
+    us, infos = grp.solve([to_dev(w.b) for w in ws], [to_dev(g) for g in gs], precision="fp32_refined", tol=tol,
+                          precond=precond, reliable_update=1, graph_block=8)
+    _, infos_r = grp.solve([to_dev(w.b) for w in ws], [to_dev(g) for g in gs], precision="fp32_refined", tol=tol,
+                           precond=precond)
+    for i, w in enumerate(ws):
+        uu = us[i].cpu().numpy()
+        for c in range(w.batch):
+            ref = O.solve_dense(oracle_problem(w), w.b[c], w.fixed, gs[i][c], oracle_bonds(w))
+            err = rel_err(uu[c], ref)
+            log("group reliable %s precond=%d member %d case %d: %d outer %d inner (restarted %d), residual %.2e, "
+                "rel err %.2e" % ("chain" if cfg is None else "t16r", precond, i, c, infos[i][c].outer_iters,
+                                  infos[i][c].inner_iters, infos_r[i][c].inner_iters, infos[i][c].rel_residual, err))
+            assert infos[i][c].status == 0 and infos[i][c].rel_residual <= tol
+            assert err <= 1e-9
