@@ -30,7 +30,7 @@ def source_hash() -> str:
 
 
 def _short(name: str) -> str:
-    for k in ("k_tile_reg", "k_xfwd", "k_line_y", "k_line_z", "k_xinv", "k_yfwd", "k_yinv", "k_cg_sums",
+    for k in ("k_tile_reg", "k_xfwd", "k_line_y", "k_line_z", "k_xinv", "k_yfwd", "k_yinv", "k_cg_sums", "k_group_sums",
               "k_dot_parts", "k_stretch", "k_scan", "k_emit", "k_tile"):
         if k in name:
             prec = "double" if "<double" in name else ("float" if "<float" in name else "")
