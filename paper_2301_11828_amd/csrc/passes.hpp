@@ -120,6 +120,17 @@ template <typename T> struct EndArgs {
     // tiles may differ from the x tiles of this launch); 0: this launch's x tiles
     int n_cg3;
     size_t s_cg3;
+    // fused CG step in the frame-16 register kernel (cg_fused): the update of the previous
+    // step is applied on the patch as it loads, from the previous vectors pio (p), cr (r),
+    // cq (q) and the case sums case4; the new p and r of the block's inner nodes go to
+    // p_new / r_new (patches overlap: the previous vectors stay readable), x is updated in
+    // place, q = K p to out; r.r of the block's inner nodes to rr_out[block].  rr_tiles:
+    // the unfused CG epilogue also writes the r.r of the block's inner nodes (r = rhs) to
+    // rr_out[block], so that a fused step can follow.
+    T *p_new;
+    T *r_new;
+    int cg_fused;
+    int rr_tiles;
     int *iters;                // [B] completed updates
     const int *case_done;      // [B] per-case stop flags (skip work) or null
     // CG chains keep the flags in two arrays by iteration parity: the x-forward stops on

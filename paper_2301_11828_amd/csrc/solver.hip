@@ -30,6 +30,8 @@ struct SolverWs {
     size_t nvec = 0;                 // B * d * N
     double *v64[6] = {};             // FP64 vectors
     float *v32[6] = {};              // FP32 vectors
+    double *alt64[3] = {};           // fused CG: the second r, p, q (allocated on first use)
+    float *alt32[3] = {};
     double *part_x = nullptr;        // [3][B * rows] x-inverse epilogue partials
     double *part_rr = nullptr;       // [2][B][tiles] true r.r partials (by iteration parity)
     double *part_aux = nullptr;      // [3][B][P] dot partials
@@ -78,6 +80,10 @@ void solver_cache_free(msb_plan_s *p) {
         if (x) (void)hipFree(x);
     for (auto x : w->v32)
         if (x) (void)hipFree(x);
+    for (auto x : w->alt64)
+        if (x) (void)hipFree(x);
+    for (auto x : w->alt32)
+        if (x) (void)hipFree(x);
     void *b[] = {w->part_x, w->part_rr, w->part_aux, w->case4, w->part_rz, w->part_adr, w->adr_D64, w->adr_D32,
                  w->thresh, w->scal, w->energy, w->done, w->iters, w->ecount};
     for (void *x : b)
@@ -120,7 +126,8 @@ static msb_status alloc_ws(msb_plan_s *p, SolverWs *w) {
     for (auto &x : w->v64) MSB_HIP(hipMalloc(&x, sizeof(double) * w->nvec));
     for (auto &x : w->v32) MSB_HIP(hipMalloc(&x, sizeof(float) * w->nvec));
     MSB_HIP(hipMalloc(&w->part_x, sizeof(double) * 3 * (size_t)B * partial_slots(p)));
-    MSB_HIP(hipMalloc(&w->part_rr, sizeof(double) * 2 * (size_t)B * std::max<int64_t>(rows_total(p), w->P)));
+    // r.r partials by parity: x tiles of the prologue, or blocks of the fused CG step
+    MSB_HIP(hipMalloc(&w->part_rr, sizeof(double) * 2 * (size_t)B * std::max<int64_t>(partial_slots(p), w->P)));
     MSB_HIP(hipMalloc(&w->part_aux, sizeof(double) * 3 * (size_t)B * w->P));
     MSB_HIP(hipMalloc(&w->case4, sizeof(double) * 5 * (size_t)B));
     MSB_HIP(hipMalloc(&w->part_rz, sizeof(double) * 6 * (size_t)B * rows_total(p)));
@@ -272,6 +279,10 @@ template <typename T> static EndArgs<T> end_args() {
 }
 
 // ------------------------------------------------------------------ conjugate gradients
+template <typename T> static T **alt_vectors(SolverWs *w);
+template <> double **alt_vectors<double>(SolverWs *w) { return w->alt64; }
+template <> float **alt_vectors<float>(SolverWs *w) { return w->alt32; }
+
 template <typename T> struct Cg {
     msb_plan_s *p;
     SolverWs *w;
@@ -280,7 +291,30 @@ template <typename T> struct Cg {
     PassArgs<T> pa;
     int tpc;
     const double *prev_rr;   // r.r partials before a residual replacement (first beta), or null
+    // fused steps: iteration it >= 1 reads r, p, q of set (it + 1) & 1 and writes set it & 1
+    // (set 0: r, pv, q; set 1: r1, p1, q1); r.r partials per block, parity stride B rr_slots
+    bool fused = false;
+    T *r1 = nullptr, *p1 = nullptr, *q1 = nullptr;
+    int rr_slots = 0;
 };
+
+// r.r partials of a CG run on a plan: per case count and parity stride (the x tiles of
+// the prologue, or the product's blocks when the steps are fused into the tiled kernel).
+template <typename T> static bool cg_fusable(const PassArgs<T> &pa) {
+    // the frame-16 register kernel with the CG epilogue, one block per workgroup, and no
+    // term that reads the transformed vector off the block's own nodes (broken bonds,
+    // surface correction): the patch forms the new p itself
+    return pa.tl == 16 && pa.treg && pa.tper == 1 && pa.corr && !pa.br_row_ptr && !pa.nu;
+}
+struct RrLayout {
+    int per_case;   // partials per case
+    size_t stride;  // between the two parity arrays
+};
+template <typename T> static RrLayout cg_rr_layout(const msb_plan_s *p, const PassArgs<T> &pa) {
+    const int tpc = x_tiles_per_case(p, pa.F);
+    if (!cg_fusable(pa)) return RrLayout{tpc, (size_t)p->B * tpc};
+    return RrLayout{pa.ept, (size_t)p->B * std::max(tpc, pa.ept)};
+}
 
 // Per-case sums of the tile partials the next CG step needs, one block per case
 // (src[k] + b tiles: the K arrays in the order the prologue reduces them).  Used when a
@@ -355,9 +389,39 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
     msb_plan_s *p = c.p;
     SolverWs *w = c.w;
     const int B = p->B;
-    const size_t nt = (size_t)B * c.tpc;
+    const size_t nt = (size_t)B * (c.fused ? c.rr_slots : c.tpc);
     const int ept = c.pa.ept;                 // epilogue partials per case (x-inverse or tiles)
     const size_t ne = (size_t)B * ept;
+    if (c.fused && it > 0) {
+        // one launch: the previous step's update applied on the patches, then q = K p
+        T *rs[2] = {c.r, c.r1}, *ps[2] = {c.pv, c.p1}, *qs[2] = {c.q, c.q1};
+        const int rd = (it + 1) & 1, wr = it & 1;
+        const double *rr_prev = w->part_rr + (size_t)rd * nt;
+        const SumSrc src{{rr_prev, w->part_x, w->part_x + ne, w->part_x + 2 * ne, nullptr}, {ept, ept, ept, ept, 0}};
+        hipLaunchKernelGGL(k_cg_sums<4>, dim3(B), dim3(kSumT), 0, c.st, src, w->case4);
+        EndArgs<T> e = end_args<T>();
+        e.pro = PRO_NONE;
+        e.cg_fused = 1;
+        e.pio = ps[rd];
+        e.cr = rs[rd];
+        e.cq = qs[rd];
+        e.cx = c.x;
+        e.p_new = ps[wr];
+        e.r_new = rs[wr];
+        e.case4 = w->case4;
+        e.rr_out = w->part_rr + (size_t)wr * nt;
+        e.update_only = update_only;
+        e.iters = w->iters;
+        e.done_prev = w->done + (size_t)rd * B;
+        e.done_rw = w->done + (size_t)wr * B;
+        e.thresh = w->thresh;
+        e.epi = EPI_CG_Q;
+        e.uin = ps[wr];
+        e.out = qs[wr];
+        e.rhs = rs[wr];
+        e.part = w->part_x;
+        return launch_product<T>(c.pa, e, c.st);
+    }
     EndArgs<T> e = end_args<T>();
     e.pro = PRO_CG_P;
     e.pio = c.pv;
@@ -381,8 +445,9 @@ template <typename T> static msb_status cg_iteration(Cg<T> &c, int it, bool upda
         e.beta_num = w->part_aux;
         e.n_num = w->P;
         e.beta_den = c.prev_rr;
-        e.n_den = c.tpc;
+        e.n_den = c.fused ? ept : c.tpc;
     }
+    e.rr_tiles = c.fused;   // the next (fused) step reads r.r partials per block
     e.done_prev = w->done + (size_t)((it + 1) & 1) * B;
     e.case_done = w->done + (size_t)(it & 1) * B;
     e.done_rw = w->done + (size_t)(it & 1) * B;
@@ -487,6 +552,7 @@ template <typename T> static msb_status run_cg(Cg<T> &c, int maxit, int graph_bl
     key.add(0);
     key.add(c.pa);
     key.add(c.x), key.add(c.r), key.add(c.pv), key.add(c.q), key.add(c.tpc), key.add(c.st);
+    key.add(c.fused), key.add(c.r1), key.add(c.p1), key.add(c.q1), key.add(c.rr_slots);
     return run_iterations(c.w, c.p->B, c.st, iter, maxit, graph_block, it_out, &key);
 }
 
@@ -514,6 +580,14 @@ static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *
     const int B = p->B, P = w->P;
     Cg<T> c{p, w, st, x, r, pv, q, pass_args<T>(p, p->op), 0, prev_rr};
     c.tpc = x_tiles_per_case(p, c.pa.F);
+    if (cg_fusable(c.pa)) {
+        T **alt = alt_vectors<T>(w);
+        for (int k = 0; k < 3; ++k)
+            if (!alt[k]) MSB_HIP(hipMalloc(&alt[k], sizeof(T) * n));
+        c.fused = true;
+        c.r1 = alt[0], c.p1 = alt[1], c.q1 = alt[2];
+        c.rr_slots = std::max(c.tpc, c.pa.ept);
+    }
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, x, n, T(0));
     if (!prev_rr) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
     hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(n)), dim3(kT), 0, st, r, rhs, n);
@@ -524,6 +598,11 @@ static msb_status cg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T *
     MSB_HIP(hipGetLastError());
     int it = 0;
     msb_status r0 = run_cg(c, maxit, graph_block, &it);
+    if (r0 == MSB_OK && c.fused && (it & 1)) {
+        // the last step wrote set 1: r and the search direction back to the caller's vectors
+        MSB_HIP(hipMemcpyAsync(r, c.r1, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
+        MSB_HIP(hipMemcpyAsync(pv, c.p1, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
+    }
     if (iters_out) *iters_out = it;
     return r0;
 }
@@ -935,7 +1014,7 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
         int *skip = static_cast<int *>(skip_buf.p);
         float *r32 = w->v32[0], *d32 = w->v32[1], *p32 = w->v32[2];
         double *r64 = w->v64[2];
-        if (reliable) MSB_HIP(hipMalloc(&prev_buf.p, sizeof(double) * (size_t)B * rows_total(p)));
+        if (reliable) MSB_HIP(hipMalloc(&prev_buf.p, sizeof(double) * (size_t)B * partial_slots(p)));
         double *prev = static_cast<double *>(prev_buf.p);   // [B][x tiles] r.r (r.z) partials before the replacement
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kT), 0, st, u, n, 0.0);
         hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(kT), 0, st, p32, n, 0.0f);
@@ -988,12 +1067,17 @@ extern "C" msb_status msb_solve_static(msb_plan p, msb_precision prec, const dou
             }
             used += mx;
             if (reliable) {
-                // r.r partials [parity][B][tpc] (CG) or the first array of the r.z partials
-                // [parity][3][B][tpc] (PCG), written with the x passes' tiles
-                const int tpc = x_tiles_per_case(p, pass_args<float>(p, p->op).F);
-                const size_t nt = (size_t)B * tpc;
-                hipLaunchKernelGGL(k_save_last, dim3(B), dim3(64), 0, st, (const double *)(pre ? w->part_rz : w->part_rr),
-                                   pre ? 3 * nt : nt, (const int *)w->iters, tpc, prev);
+                // r.r partials [parity] (CG: x tiles of the prologue, or blocks of the fused
+                // steps) or the first array of the r.z partials [parity][3][B][tpc] (PCG)
+                const PassArgs<float> pa32 = pass_args<float>(p, p->op);
+                const int tpc = x_tiles_per_case(p, pa32.F);
+                const RrLayout lay = cg_rr_layout(p, pa32);
+                if (pre)
+                    hipLaunchKernelGGL(k_save_last, dim3(B), dim3(64), 0, st, (const double *)w->part_rz,
+                                       3 * (size_t)B * tpc, (const int *)w->iters, tpc, prev);
+                else
+                    hipLaunchKernelGGL(k_save_last, dim3(B), dim3(64), 0, st, (const double *)w->part_rr, lay.stride,
+                                       (const int *)w->iters, lay.per_case, prev);
             }
             hipLaunchKernelGGL(k_add_to<float>, dim3(grid_for(n)), dim3(kT), 0, st, u, (const float *)d32, n);
             MSB_TRY(true_residual(p, w, st, u, bp, r64, 0));

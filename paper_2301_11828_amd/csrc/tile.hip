@@ -305,11 +305,60 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
     const int nx = min(Tt, a.Nx - x0), ny = min(Tt, a.Ny - y0);
     T2 *buf0 = reinterpret_cast<T2 *>(smem);
     T2 *buf1 = buf0 + TL * P;
-    if (e.case_done && e.case_done[b]) return;
     const int N = a.N, Nx = a.Nx, Ny = a.Ny;
     const size_t cbase = (size_t)b * 2 * N;
     const T *uin = e.uin;
     const bool edge = x0 < M || x0 + nx > Nx - M || y0 < M || y0 + ny > Ny - M;
+    const int gx = x0 - M + ln;
+    const bool col_in = gx >= 0 && gx < Nx;
+    const bool col_inner = ln >= M && ln < M + nx;
+    // fused CG step: alpha = r.r / p.q, the new r.r = r.r - 2 alpha r.q + alpha^2 q.q and
+    // beta = new r.r / r.r from the case sums, with the stop and breakdown tests of the
+    // prologue (one block per case writes the flags)
+    const bool fused = CGQ && e.cg_fused;
+    T alpha = T(0), beta = T(0);
+    bool conv = false;
+    if (fused) {
+        const bool lead = rem == 0 && tid == 0;
+        if (e.done_prev[b]) {
+            // stopped before this step: carry the flag, and r, p of the inner nodes over to
+            // the new vectors (every case's current vectors are then the new ones)
+            if (lead) e.done_rw[b] = e.done_prev[b];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int ly = p + S * i;
+                if (col_inner && ly >= M && ly < M + ny) {
+                    const size_t ax = cbase + (size_t)(y0 - M + ly) * Nx + gx, ay = ax + N;
+                    e.r_new[ax] = e.cr[ax];
+                    e.r_new[ay] = e.cr[ay];
+                    e.p_new[ax] = e.pio[ax];
+                    e.p_new[ay] = e.pio[ay];
+                }
+            }
+            return;
+        }
+        const double rr = e.case4[(size_t)b * 4], pq = e.case4[(size_t)b * 4 + 1];
+        const double rq = e.case4[(size_t)b * 4 + 2], qq = e.case4[(size_t)b * 4 + 3];
+        const double al = rr / pq;
+        if (!(pq > 0.0) || !(al == al) || al > 1e300) {   // K not positive definite on p
+            if (lead) e.done_rw[b] = 2;
+            return;
+        }
+        const double rrn = rr - 2.0 * al * rq + al * al * qq;
+        if (!(rrn == rrn)) {
+            if (lead) e.done_rw[b] = 3;
+            return;
+        }
+        alpha = T(al);
+        beta = T(rr > 0.0 ? rrn / rr : 0.0);
+        conv = e.update_only || (e.thresh && !(rrn > e.thresh[b]));
+        if (lead) {
+            e.iters[b] += 1;
+            e.done_rw[b] = conv ? (e.update_only ? 5 : 1) : 0;
+        }
+    } else if (e.case_done && e.case_done[b]) {
+        return;
+    }
     // second-stage twiddles of this thread's butterflies (same in both axes)
     T2 tw[RA][S];
 #pragma unroll
@@ -328,12 +377,12 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
     }
     // load: column layout, patch (row p + S i, column ln) = grid (x0 - M + ln, y0 - M + p + S i);
     // the D^e block of inner nodes within M of a face applied to u at load time, and the
-    // constraint bits of the inner nodes
+    // constraint bits of the inner nodes.  Fused CG: u = p_new = r - alpha q + beta p from
+    // the previous vectors at every patch node; the inner nodes' x, r, p updated.
     T2 v[R], dcor[R];
+    T pux[R], puy[R], prx[R], pry[R];   // CG epilogue: p and r at the thread's inner nodes
+    double rr_acc = 0.0;                // r.r of the inner nodes (fused step, rr_tiles)
     uint32_t fixbits = 0;
-    const int gx = x0 - M + ln;
-    const bool col_in = gx >= 0 && gx < Nx;
-    const bool col_inner = ln >= M && ln < M + nx;
     const T *de = a.de + (size_t)b * a.de_slot;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -342,10 +391,30 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
         v[i].y = T(0);
         dcor[i].x = T(0);
         dcor[i].y = T(0);
+        if (CGQ) pux[i] = puy[i] = prx[i] = pry[i] = T(0);
         if (col_in && gy >= 0 && gy < Ny) {
             const size_t q = (size_t)gy * Nx + gx;
-            v[i].x = uin[cbase + q];
-            v[i].y = uin[cbase + N + q];
+            if (fused) {
+                const size_t ax = cbase + q, ay = ax + N;
+                const T px = e.pio[ax], py = e.pio[ay];
+                const T rx = e.cr[ax] - alpha * e.cq[ax], ry = e.cr[ay] - alpha * e.cq[ay];
+                v[i].x = rx + beta * px;
+                v[i].y = ry + beta * py;
+                if (col_inner && ly >= M && ly < M + ny) {
+                    e.cx[ax] += alpha * px;
+                    e.cx[ay] += alpha * py;
+                    e.r_new[ax] = rx;
+                    e.r_new[ay] = ry;
+                    // a converged case keeps its last search direction (continuation)
+                    e.p_new[ax] = conv ? px : v[i].x;
+                    e.p_new[ay] = conv ? py : v[i].y;
+                    rr_acc += (double)rx * (double)rx;
+                    rr_acc += (double)ry * (double)ry;
+                }
+            } else {
+                v[i].x = uin[cbase + q];
+                v[i].y = uin[cbase + N + q];
+            }
             if (col_inner && ly >= M && ly < M + ny) {
                 if (a.fixed) fixbits |= ((uint32_t)a.fixed[q] | ((uint32_t)a.fixed[N + q] << 1)) << (2 * i);
                 if (edge) {
@@ -360,6 +429,12 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
                 }
             }
         }
+    }
+    if (fused && conv) {   // the final update only: no product
+        double vs[1] = {rr_acc};
+        block_sum<1>(vs, red, tid, S * TL);
+        if (tid == 0) e.rr_out[tile] = vs[0];
+        return;
     }
     // forward: columns (line ln, element q at buf[q P + ln]), transpose, rows
     RegLine<T, TL, -1>::run(v, buf0 + ln, P, p, tw);
@@ -385,13 +460,12 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
             v[i] = W;
         }
     }
-    // CG epilogue: p (= u) and r at the output points, loaded now (in flight during the inverse)
-    T pux[R], puy[R], prx[R], pry[R];
+    // CG epilogue: p (= u) and r at the output points, loaded now (in flight during the inverse);
+    // fused: the new p and r this thread stored at those points in the load phase
     if (CGQ) {
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int ly = p + S * i;
-            pux[i] = puy[i] = prx[i] = pry[i] = T(0);
             if (col_inner && ly >= M && ly < M + ny) {
                 const size_t node = (size_t)(y0 - M + ly) * Nx + gx;
                 pux[i] = uin[cbase + node];
@@ -499,6 +573,10 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
                     acc0 += (double)puy[i] * (double)qy;
                     acc1 += (double)pry[i] * (double)qy;
                     acc2 += (double)qy * (double)qy;
+                    if (e.rr_tiles) {   // r.r of r = rhs (unfused step followed by fused ones)
+                        rr_acc += (double)prx[i] * (double)prx[i];
+                        rr_acc += (double)pry[i] * (double)pry[i];
+                    }
                 } else {
                     epilogue_at<T>(e, uin, ax, node + pb, fx, (fixbits >> (2 * i)) & 1u, sign, rinv, dth, acc0,
                                    acc1, acc2);
@@ -508,7 +586,17 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
             }
         }
     }
-    if (e.part) {
+    if (CGQ && (fused || e.rr_tiles)) {
+        double vs[4] = {acc0, acc1, acc2, rr_acc};
+        block_sum<4>(vs, red, tid, S * TL);
+        if (tid == 0) {
+            const size_t stride = (size_t)ntiles;
+            e.part[tile] = vs[0];
+            e.part[stride + tile] = vs[1];
+            e.part[2 * stride + tile] = vs[2];
+            e.rr_out[tile] = vs[3];
+        }
+    } else if (e.part) {
         double vs[3] = {acc0, acc1, acc2};
         block_sum<3>(vs, red, tid, S * TL);
         if (tid == 0) {
