@@ -438,6 +438,35 @@ def main():
         line["cpu_baseline"] = {"value": round(dofs * reps / dt / 1e9, 5), "unit": "GDOF/s",
                                 "cores": cores, "cpu_model": _cpu_model(), "kind": "oracle",
                                 "sample": "%d full FP64 bond-by-bond products of plate512 (%.1f s)" % (reps, dt)}
+        # context: the paper's fast method itself on the same CPU (the oracle's FFT product,
+        # scipy's multithreaded FFT), the FP64 CG time it implies at the GPU's iteration
+        # count, and config 1 (32^2 plate) solved by dense Cholesky and by the oracle's CG
+        t0 = time.perf_counter()
+        fs = O.fft_setup(p, plan.padded_lengths, workers=cores)
+        t_setup = time.perf_counter() - t0
+        O.fft_apply(p, u, w.fixed, workers=cores, setup=fs)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 3.0:
+            O.fft_apply(p, u, w.fixed, workers=cores, setup=fs)
+            reps += 1
+        per = (time.perf_counter() - t0) / reps
+        its = line.get("cg", {}).get("fp64", {}).get("iterations")
+        line["cpu_baseline"]["fft_method"] = {
+            "GDOF_s": round(dofs / per / 1e9, 5), "ms_per_product": round(per * 1e3, 2), "threads": cores,
+            "assembly_seconds": round(t_setup, 3),
+            "sample": "%d FP64 products of plate512 at the GPU's padded lengths" % reps,
+            "cg_fp64_seconds_extrapolated": round(per * its, 1) if its else None}
+        w1 = W.plate32()
+        p1 = O.Problem(w1.n, w1.h, w1.M, w1.alpha)
+        t0 = time.perf_counter()
+        x1 = O.solve_dense(p1, w1.b[0], w1.fixed)
+        t_chol = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        x2, its1 = O.solve_cg(p1, w1.b[0], w1.fixed, tol=1e-10)[:2]
+        t_cg = time.perf_counter() - t0
+        line["cpu_baseline"]["config1_plate32"] = {
+            "dense_cholesky_seconds": round(t_chol, 4), "cg_to_1e-10_seconds": round(t_cg, 4),
+            "cg_iterations": int(its1), "cg_vs_cholesky_rel_diff": float(np.linalg.norm(x2 - x1) / np.linalg.norm(x1))}
     print(json.dumps(line), flush=True)
 
 

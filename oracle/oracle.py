@@ -41,6 +41,10 @@ eqs. (matrix)/(mae:e1), and the model equations built on it:
                               displacement at the centre of a (2M+1)^d grid.
 * ``periodic_apply``       -- the L-periodic operator with that generating array, by
                               direct convolution (for pins).
+* ``fft_setup``/``fft_apply`` -- f = A u by the paper's fast method itself on the CPU (the
+                              assembly of spectra and D^e; then Alg. 3 / Alg. 4 with D^e and
+                              D^f, Sec. 3.3-3.6), with scipy's FFT: a timing reference for the
+                              CPU baseline, pinned to ``apply``.
 * ``precond_apply``        -- the circulant preconditioner of the preconditioned solver
                               (prior fast methods cited in Sec. 1; not part of MSBFM):
                               z = Pi_F E^T (K_per + s I)^{-1} E r, K_per = -A_per,
@@ -503,6 +507,92 @@ def periodic_apply(prob: Problem, L: Sequence[int], v: np.ndarray, G: Optional[n
         shifted = np.roll(v, shift=o, axis=tuple(range(1, d + 1)))   # shifted_p = v_{p - o}
         out += np.einsum("ac,c...->a...", blk, shifted)
     return out.reshape(d, -1)
+
+
+def fft_setup(prob: Problem, L: Optional[Sequence[int]] = None, workers: Optional[int] = None,
+              G: Optional[np.ndarray] = None) -> dict:
+    """The assembly of the fast method (Sec. 3.3): the spectra of the full-horizon generating
+    array G (Sec. 3.2 / 4) wrapped onto a zero-padded grid of lengths L >= N + M per axis
+    (default N + M; the paper pads to 2N), and the D^e blocks: a node whose horizon leaves the
+    grid keeps in its diagonal block only the bonds inside the grid while G(0) sums all of them,
+    so D^e_p = sum of W(o) = G(o) over the offsets o != 0 with p + o outside (eq. (mat:se))."""
+    import scipy.fft as sfft
+    d, M = prob.dim, prob.M
+    shp = _grid_shape(prob.n)                       # (z,) y, x
+    if L is None:
+        L = tuple(reversed([n + M for n in shp]))  # x fastest, like prob.n
+    Ls = _grid_shape(L)
+    if any(a < n + M for a, n in zip(Ls, shp)):
+        raise ValueError("padded lengths must be >= N + M per axis")
+    if G is None:
+        G = generating_blocks(prob)
+    m = 2 * M + 1
+    arr = np.zeros((d, d) + Ls)                     # G(o) at index o mod L
+    idx = np.ix_(*[[(o - M) % Lk for o in range(m)] for Lk in Ls])
+    for a in range(d):
+        for c in range(d):
+            arr[(a, c) + idx] = G[a, c]
+    Gh = sfft.fftn(arr, axes=tuple(range(2, d + 2)), workers=workers)
+    De = np.zeros((d, d) + shp)
+    coords = np.meshgrid(*[np.arange(n) for n in shp], indexing="ij")
+    for o in np.ndindex(*([m] * d)):
+        off = tuple(k - M for k in o)
+        blk = G[(slice(None), slice(None)) + o]
+        if not any(off) or not blk.any():
+            continue
+        out = np.zeros(shp, dtype=bool)
+        for k in range(d):
+            out |= (coords[k] + off[k] < 0) | (coords[k] + off[k] >= shp[k])
+        if out.any():
+            De[:, :, out] += blk[:, :, None]
+    return {"L": Ls, "Gh": Gh, "De": De, "G": G}
+
+
+def fft_apply(prob: Problem, u: np.ndarray, fixed: Optional[np.ndarray] = None, broken=None,
+              L: Optional[Sequence[int]] = None, workers: Optional[int] = None, setup: Optional[dict] = None):
+    """f = A u by the matrix-structure-based fast method (Sec. 3.3-3.6) on the CPU.
+
+    The Toeplitz part: u embedded in the zero-padded grid, forward FFT, the d x d block
+    product with the spectra of G, inverse FFT, cropped to the grid (Alg. 3 in 2D, Alg. 4 in
+    3D).  Then D^e u (``fft_setup``), and D^f: each broken bond's term W(q - p)(u_q - u_p)
+    removed from both ends (eq. (df) / (tea:fr)).  Rows of constrained DOFs reported as 0, as
+    ``apply``.  workers: scipy's FFT threads; setup: ``fft_setup``'s result (else built)."""
+    import scipy.fft as sfft
+    d, M = prob.dim, prob.M
+    if setup is None:
+        setup = fft_setup(prob, L, workers)
+    Ls, Gh, De, G = setup["L"], setup["Gh"], setup["De"], setup["G"]
+    shp = _grid_shape(prob.n)
+    sp = tuple(range(1, d + 1))
+    inner = (slice(None),) + tuple(slice(0, n) for n in shp)
+    u = np.asarray(u, dtype=np.float64).reshape((d,) + shp)
+    uu = np.zeros((d,) + Ls)
+    uu[inner] = u
+    uh = sfft.fftn(uu, axes=sp, workers=workers)
+    fh = np.einsum("ac...,c...->a...", Gh, uh)
+    f = sfft.ifftn(fh, axes=sp, workers=workers).real[inner]
+    f += np.einsum("ac...,c...->a...", De, u)
+    if broken is not None and len(broken):
+        pr = np.asarray(broken, dtype=np.int64).reshape(-1, 2)
+        uf = u.reshape(d, -1)
+        ff = f.reshape(d, -1)
+        nx = list(prob.n) + [1, 1]
+
+        def zyx(node):
+            return [node // (nx[0] * nx[1]), (node // nx[0]) % nx[1], node % nx[0]][3 - d:]
+        cp, cq = zyx(pr[:, 0]), zyx(pr[:, 1])
+        for e in range(len(pr)):
+            p_, q_ = pr[e]
+            o = tuple(int(cq[k][e] - cp[k][e]) + M for k in range(d))      # q - p, per (z,) y, x
+            om = tuple(2 * M - k for k in o)                               # p - q
+            du = uf[:, q_] - uf[:, p_]
+            ff[:, p_] -= G[(slice(None), slice(None)) + o] @ du
+            ff[:, q_] += G[(slice(None), slice(None)) + om] @ du
+        f = ff.reshape((d,) + shp)
+    f = f.reshape(d, -1)
+    if fixed is not None:
+        f[np.asarray(fixed, dtype=bool).reshape(f.shape)] = 0.0
+    return f
 
 
 def precond_symbol(prob: Problem, L: Sequence[int], G: Optional[np.ndarray] = None):
