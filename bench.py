@@ -224,14 +224,19 @@ def main():
         for _ in range(-(-warmup // per)):
             run()
         torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        for _ in range(steps // per):
+            run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # device time of the same steps between two events, in a pass of its own (the event
+        # records stay out of the wall-clock region)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(steps // per):
             run()
         ev1.record()
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         return wall, ev0.elapsed_time(ev1) / steps
 
     # the timed steps replay a hipGraph of G products (the launch gaps between the three
