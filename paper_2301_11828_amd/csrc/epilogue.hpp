@@ -72,6 +72,10 @@ __device__ __forceinline__ void epilogue_at(const EndArgs<T> &e, const T *__rest
             }
             e.ea[addr] = an;
             e.ev[addr] = vn;
+            if (e.u_next) {   // Alg. 2's displacement update of the next step (the prologue's arithmetic)
+                const T dtt = T(e.dt), hdt2 = T(0.5 * e.dt * e.dt);
+                e.u_next[addr] = fx ? (e.pg ? e.pg[addr] : T(0)) : uin[addr] + dtt * vn + hdt2 * an;
+            }
             break;
         }
         default:  // EPI_DOT

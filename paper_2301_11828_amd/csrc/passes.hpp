@@ -148,6 +148,9 @@ template <typename T> struct EndArgs {
     const T *rhs;        // EPI_RESID rhs; EPI_VV b; EPI_DOT w; EPI_CG_Q r
     T *ev;               // EPI_VV: v
     T *ea;               // EPI_VV: a
+    T *u_next;           // EPI_VV: if set, the next step's displacement u + dt v' + dt^2/2 a' (g on
+                         // constrained DOFs, pg) into this vector, so that the next product needs
+                         // no prologue pass (u itself is read by neighbouring blocks: not in place)
     double sign;         // EPI_APPLY sign
     double rho;
     int energy;          // EPI_VV: accumulate energy partials

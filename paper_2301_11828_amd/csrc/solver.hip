@@ -1162,19 +1162,30 @@ static msb_status vv_run_t(msb_plan_s *p, double dt, int64_t nsteps, T *u, T *v,
     const int tiles = p->B * pa.ept;   // epilogue partials of the whole batch
     double V = 1.0;
     for (int q = 0; q < p->dim; ++q) V *= p->h;
+    // The first step's displacement update runs as the prologue (in place); after that each
+    // step's epilogue writes the next displacement into the other of two vectors (u and a
+    // workspace copy, alternating), so steps 2.. are the product kernels alone.
+    T *us[2] = {u, u};
+    if (nsteps > 1) {
+        T **alt = alt_vectors<T>(w);
+        if (!alt[0]) MSB_HIP(hipMalloc(&alt[0], sizeof(T) * w->nvec));
+        us[1] = alt[0];
+    }
     for (int64_t s = 1; s <= nsteps; ++s) {
+        T *uc = us[(s - 1) & 1];   // u of this step (after its update)
         EndArgs<T> e = end_args<T>();
-        e.pro = PRO_VV_U;
-        e.pio = u;
+        e.pro = s == 1 ? PRO_VV_U : PRO_NONE;
+        e.pio = uc;
         e.pr = v;
         e.pa = a;
         e.pg = g;
         e.dt = dt;
         e.epi = EPI_VV;
-        e.uin = u;
+        e.uin = uc;
         e.rhs = bf;
         e.ev = v;
         e.ea = a;
+        e.u_next = s < nsteps ? us[s & 1] : nullptr;
         e.rho = p->rho;
         const bool en = ne > 0 && (s % every) == 0 && s / every <= ne;
         e.energy = en ? 1 : 0;
@@ -1182,6 +1193,8 @@ static msb_status vv_run_t(msb_plan_s *p, double dt, int64_t nsteps, T *u, T *v,
         MSB_TRY(launch_product<T>(pa, e, st));
         if (en) hipLaunchKernelGGL(k_energy, dim3(1), dim3(kT), 0, st, (const double *)w->part_x, tiles, p->rho, V, w->energy, w->ecount);
     }
+    if (nsteps > 1 && ((nsteps - 1) & 1))   // the last step's u is the workspace copy
+        MSB_HIP(hipMemcpyAsync(u, us[1], sizeof(T) * w->nvec, hipMemcpyDeviceToDevice, st));
     MSB_HIP(hipGetLastError());
     if (ne > 0) {
         MSB_HIP(hipMemcpyAsync(energy, w->energy, sizeof(double) * ne, hipMemcpyDeviceToHost, st));

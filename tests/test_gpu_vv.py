@@ -139,3 +139,39 @@ def test_crack1024_1000_steps_vs_oracle(prec):
         "1000 steps %.2e of that scale (max kinetic %.3e, max elastic %.3e)" %
         (prec, de, drift, parts[:, 0].max(), parts[:, 1].max()))
     assert len(en) == 100 and de <= (1e-3 if prec == "fp32" else 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("cfg", [None, dict(tile=16, tile_regs=1, tile_run=1), dict(tile=32, tile_regs=1, tile_run=1),
+                                 dict(tile=24, tile_regs=0, tile_run=1)], ids=["chain", "t16r", "t32r", "t24"])
+@pytest.mark.parametrize("nsteps", [1, 2, 7, 8])
+def test_vv_steps_in_one_call_equal_single_steps(prec, cfg, nsteps):
+    """After the first step of a call, each step's epilogue forms the next displacement
+    (Alg. 2's update) into a second vector and the next product runs without a prologue
+    pass: n steps in one call equal n calls of one step bit for bit (crack, constraints with
+    prescribed g, energies), for odd and even n, on the chain and the tiled kernels."""
+    import torch
+    w = W.small(2, (41, 33), 3, seed=37, fixed="left", crack=True, batch=2)
+    w.rho = 1.3
+    u0, v0 = _setup(w, 3)
+    g = np.where(w.fixed[None], 1e-4, 0.0)
+    u0 = np.where(w.fixed[None], g, u0)
+    dt = _stable_dt(w)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    plan = gpu_plan(w)
+    if cfg:
+        plan.set_config(prec, **cfg)
+    b, gd = to_dev(w.b, dtype), to_dev(np.broadcast_to(g, (w.batch, 2, w.N)).copy(), dtype)
+    res = []
+    for one_call in (True, False):
+        u, v = to_dev(np.broadcast_to(u0, (w.batch, 2, w.N)).copy(), dtype), to_dev(np.broadcast_to(v0, (w.batch, 2, w.N)).copy(), dtype)
+        a = plan.vv_init(u, b)
+        if one_call:
+            en = plan.vv_run(dt, nsteps, u, v, a, b, g=gd, energy_every=1)
+        else:
+            en = np.concatenate([plan.vv_run(dt, 1, u, v, a, b, g=gd, energy_every=1) for _ in range(nsteps)])
+        res.append((u.clone(), v.clone(), a.clone(), en))
+    (u1, v1, a1, e1), (u2, v2, a2, e2) = res
+    log("VV %s %s %d steps one call vs single steps: max |du| %.1e" % (prec, cfg, nsteps, float((u1 - u2).abs().max())))
+    assert torch.equal(u1, u2) and torch.equal(v1, v2) and torch.equal(a1, a2)
+    assert np.array_equal(e1, e2)
