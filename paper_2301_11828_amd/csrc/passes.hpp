@@ -198,6 +198,7 @@ struct GroupGrid {
     int total_t = 0;
     size_t lds_t = 0;
     int tiled = 0, pro = 0;
+    int cgq = 0;   // CG slots: the tiled kernel's CG-epilogue form (with or without a prologue)
 };
 // a: any member's host arguments (for the common geometry); dA/dE: device arrays of the
 // members' arguments; composite: some member's schedules use a composite radix.

@@ -301,10 +301,11 @@ template <typename T> struct Cg {
 // r.r partials of a CG run on a plan: per case count and parity stride (the x tiles of
 // the prologue, or the product's blocks when the steps are fused into the tiled kernel).
 template <typename T> static bool cg_fusable(const PassArgs<T> &pa) {
-    // the frame-16 register kernel with the CG epilogue, one block per workgroup, and no
-    // term that reads the transformed vector off the block's own nodes (broken bonds,
-    // surface correction): the patch forms the new p itself
-    return pa.tl == 16 && pa.treg && pa.tper == 1 && pa.corr && !pa.br_row_ptr && !pa.nu;
+    // a register kernel with the CG-epilogue form (frames 16 and 32, and 64 in FP32), one
+    // block per workgroup, and no term that reads the transformed vector off the block's own
+    // nodes (broken bonds, surface correction): the patch forms the new p itself
+    const bool form = pa.tl == 16 || pa.tl == 32 || (pa.tl == 64 && sizeof(T) == 4);
+    return form && pa.treg && pa.tper == 1 && pa.corr && !pa.br_row_ptr && !pa.nu;
 }
 struct RrLayout {
     int per_case;   // partials per case
@@ -1471,6 +1472,7 @@ struct msb_group_s {
     SolverWs::CgGraph graphs[kGraphs];
     int graph_next = 0;
     double *case4 = nullptr;                   // [Btot][5] per-case CG sums (members with many tiles)
+    bool cg_fused = false;                     // the running group CG fuses its steps into the tiled kernel
     void *dS = nullptr;                        // device GroupSum[kSlots][n]: their sources per slot
     int *dcase = nullptr;                      // [n + 1] case offsets of the members a launch covers
 };
@@ -1622,7 +1624,10 @@ msb_status group_launch(msb_group_s *g, const std::vector<PassArgs<T>> &A, int s
     // end arguments hold a prologue (run first as the transform-free x pass)
     if (g->tiled[f] && !pre) {
         gg.tiled = 1;
-        gg.pro = slot < G_LIFT;
+        gg.cgq = slot < G_LIFT;
+        // fused CG steps carry their update in the tiled kernel: a prologue pass only for the
+        // first step (or for every step when not fused)
+        gg.pro = slot < G_LIFT && (!g->cg_fused || slot == G_FIRST);
         gg.start_t = g->dstart[f] + 3 * (v.n + 1);
         gg.total_t = v.total[3];
         gg.lds_t = g->lds[f][3];
@@ -1699,6 +1704,11 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     hipStream_t st = g->st;
     const bool pcg = Ap != nullptr;
     if (pcg && !z) return MSB_EINVAL;
+    // plain CG on a tiled configuration whose every member can fuse its steps (see
+    // cg_fusable): r, p, q alternate between the caller's vectors and workspace copies
+    bool fused = !pcg && g->tiled[f];
+    for (int i = 0; i < g->n && fused; ++i) fused = cg_fusable(A[i]);
+    std::vector<T *> r1(g->n, nullptr), p1(g->n, nullptr), q1(g->n, nullptr);
     std::vector<SolverWs *> ws(g->n);
     for (int i = 0; i < g->n; ++i) {
         msb_plan_s *p = g->m[i];
@@ -1706,6 +1716,12 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
         MSB_TRY(get_ws(p, w));
         ws[i] = w;
         const size_t nv = w->nvec;
+        if (fused) {
+            T **alt = alt_vectors<T>(w);
+            for (int k = 0; k < 3; ++k)
+                if (!alt[k]) MSB_HIP(hipMalloc(&alt[k], sizeof(T) * nv));
+            r1[i] = alt[0], p1[i] = alt[1], q1[i] = alt[2];
+        }
         hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kT), 0, st, x[i], nv, T(0));
         if (!prev) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kT), 0, st, pv[i], nv, T(0));
         hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(nv)), dim3(kT), 0, st, r[i], rhs[i], nv);
@@ -1727,9 +1743,10 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     bool need_sums = false;
     for (int i = 0; i < g->n; ++i) {
         const int tpc = (g->start[f][0][i + 1] - g->start[f][0][i]) / g->m[i]->B;
-        many[i] = std::max(tpc, g->ept[f][i]) > kFusedReduceMaxTiles;
+        many[i] = fused || std::max(tpc, g->ept[f][i]) > kFusedReduceMaxTiles;   // fused steps: always
         need_sums = need_sums || many[i];
     }
+    g->cg_fused = fused;
     for (int slot = G_FIRST; slot <= G_UPD_ODD; ++slot) {
         const int parity = (slot == G_ODD || slot == G_UPD_ODD) ? 1 : 0;
         const int prv = (parity + 1) & 1;
@@ -1737,6 +1754,42 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
             const size_t po = g->poff[i];
             const int nt = g->start[f][0][i + 1] - g->start[f][0][i];
             const int co = g->case_off[i];
+            if (fused && slot != G_FIRST) {
+                // the whole step in the tiled kernel: previous r, p, q from set prv, new ones to
+                // set parity; r.r partials per block at the fused parity stride
+                const int B = g->m[i]->B, ept = g->ept[f][i];
+                const size_t nrr = (size_t)B * partial_slots(g->m[i]);
+                T *rs[2] = {r[i], r1[i]}, *ps[2] = {pv[i], p1[i]}, *qs[2] = {q[i], q1[i]};
+                EndArgs<T> e = end_args<T>();
+                e.pro = PRO_NONE;
+                e.cg_fused = 1;
+                e.pio = ps[prv];
+                e.cr = rs[prv];
+                e.cq = qs[prv];
+                e.cx = x[i];
+                e.p_new = ps[parity];
+                e.r_new = rs[parity];
+                e.rr_out = g->part_rr + 2 * po + (size_t)parity * nrr;
+                e.update_only = slot == G_UPD_EVEN || slot == G_UPD_ODD;
+                e.iters = g->iters + co;
+                e.done_prev = g->done + (size_t)prv * g->Btot + co;
+                e.done_rw = g->done + (size_t)parity * g->Btot + co;
+                e.thresh = g->thresh + co;
+                e.epi = EPI_CG_Q;
+                e.uin = ps[parity];
+                e.out = qs[parity];
+                e.rhs = rs[parity];
+                e.part = g->part_x + 3 * po;
+                const double *rrp = g->part_rr + 2 * po + (size_t)prv * nrr;
+                const size_t s3 = (size_t)B * ept;
+                GroupSum sm{{rrp, e.part, e.part + s3, e.part + 2 * s3, nullptr}, {ept, ept, ept, ept, 0},
+                            g->case4 + 5 * (size_t)co};
+                e.case4 = sm.out;
+                if (Sslots[slot].empty()) Sslots[slot].resize(g->n);
+                Sslots[slot][i] = sm;
+                Eslots[slot][i] = e;
+                continue;
+            }
             EndArgs<T> e = end_args<T>();
             e.pro = pcg ? PRO_PCG_R : PRO_CG_P;
             if (pcg) e.pr = pv[i];
@@ -1749,6 +1802,10 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
             e.s_cg3 = (size_t)g->m[i]->B * g->ept[f][i];
             e.rr_prev = g->part_rr + 2 * po + (size_t)prv * nt;
             e.rr_out = g->part_rr + 2 * po + (size_t)parity * nt;
+            if (fused) {   // the first step: the tile kernel writes the r.r partials per block
+                e.rr_out = g->part_rr + 2 * po + (size_t)parity * g->m[i]->B * partial_slots(g->m[i]);
+                e.rr_tiles = 1;
+            }
             if (pcg) e.rz_k = g->part_rz + (size_t)prv * 3 * g->tiles_max + 3 * po;
             e.first = slot == G_FIRST;
             e.update_only = slot == G_UPD_EVEN || slot == G_UPD_ODD;
@@ -1756,7 +1813,7 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
                 e.beta_num = ws[i]->part_aux;
                 e.n_num = ws[i]->P;
                 e.beta_den = prev + po;
-                e.n_den = nt / g->m[i]->B;
+                e.n_den = fused ? g->ept[f][i] : nt / g->m[i]->B;
             }
             e.iters = g->iters + co;
             e.done_prev = g->done + (size_t)prv * g->Btot + co;
@@ -1852,6 +1909,7 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
         k.add(block);
         k.add(view.cases);
         k.add(need_sums);
+        k.add(fused);
         return k.b;
     };
     // per-case sums of the members with many tiles, before a slot's prologue (not on the
@@ -1939,6 +1997,15 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
     if (s == MSB_OK) s = iteration(it, true);   // iteration cap: pending update of running cases
     if (s == MSB_OK && (it & 1))                  // the final flags into slot 0
         MSB_HIP(hipMemcpyAsync(g->done, g->done + g->Btot, sizeof(int) * g->Btot, hipMemcpyDeviceToDevice, st));
+    if (s == MSB_OK && fused && (it & 1)) {
+        // the last fused step wrote set 1: r, p back for the members it covered (a member that
+        // left the work list stopped after an even step, so its vectors are in set 0)
+        for (int i : act) {
+            MSB_HIP(hipMemcpyAsync(r[i], r1[i], sizeof(T) * ws[i]->nvec, hipMemcpyDeviceToDevice, st));
+            MSB_HIP(hipMemcpyAsync(pv[i], p1[i], sizeof(T) * ws[i]->nvec, hipMemcpyDeviceToDevice, st));
+        }
+    }
+    g->cg_fused = false;
     // all members again for the next launches
     MSB_HIP(hipStreamSynchronize(st));
     std::vector<int> all(g->n);
@@ -1949,14 +2016,17 @@ msb_status group_cg(msb_group_s *g, const std::vector<PassArgs<T>> &A, const std
 
 // Reliable updates: each member's r.r (pcg: r.z) partials of the step that formed its search
 // direction, into prev + poff[i] (k_save_last), after a group CG run in precision f.
-msb_status group_save_last(msb_group_s *g, int f, bool pcg, double *prev) {
+msb_status group_save_last(msb_group_s *g, int f, bool pcg, double *prev, bool fused) {
     for (int i = 0; i < g->n; ++i) {
         const int B = g->m[i]->B;
         const int nt = g->start[f][0][i + 1] - g->start[f][0][i];
         const size_t po = g->poff[i];
         const double *part = pcg ? g->part_rz + 3 * po : g->part_rr + 2 * po;
-        hipLaunchKernelGGL(k_save_last, dim3(B), dim3(64), 0, g->st, part, pcg ? 3 * g->tiles_max : (size_t)nt,
-                           (const int *)(g->iters + g->case_off[i]), nt / B, prev + po);
+        // fused steps: r.r partials per block at the parity stride B partial_slots
+        const size_t pstride = pcg ? 3 * g->tiles_max : fused ? (size_t)B * partial_slots(g->m[i]) : (size_t)nt;
+        const int per = fused && !pcg ? g->ept[f][i] : nt / B;
+        hipLaunchKernelGGL(k_save_last, dim3(B), dim3(64), 0, g->st, part, pstride,
+                           (const int *)(g->iters + g->case_off[i]), per, prev + po);
     }
     MSB_HIP(hipGetLastError());
     return MSB_OK;
@@ -2518,7 +2588,11 @@ extern "C" msb_status msb_group_solve_static(msb_group g, msb_precision prec, co
             MSB_TRY(group_cg<float>(g, A32, r32c, d32, rr32, p32, q32, itol, opts->maxit - used, gb, g->skip, t2d, ap32,
                                     zz32, (reliable && !first) ? prev : nullptr));
             first = false;
-            if (reliable) MSB_TRY(group_save_last(g, 1, pre, prev));
+            if (reliable) {
+                bool fz = !pre && g->tiled[1];   // the group CG fused its steps (as group_cg decides)
+                for (int i = 0; i < n && fz; ++i) fz = cg_fusable(A32[i]);
+                MSB_TRY(group_save_last(g, 1, pre, prev, fz));
+            }
             MSB_TRY(group_fetch(g, 0));
             int mx = 0;
             for (int c = 0; c < Bt; ++c) {

@@ -248,6 +248,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_tile(PassArgs<T> a, EndArgs<T> e)
 // Exchanges alternate between two LDS frames, so one barrier per exchange suffices: a
 // frame is written again only two exchanges later, after every thread has passed the
 // barrier that follows its last read.
+// The CG-epilogue form of the register kernel (p and r preloaded during the inverse
+// transforms; the fused CG step) exists where its registers fit without spills: every frame
+// in FP32, frames 16 and 32 in FP64.
+template <typename T, int TL> constexpr bool cgq_form() { return sizeof(T) == 4 || TL <= 32; }
+
 template <int TL> struct RegShape;
 template <> struct RegShape<16> { static constexpr int R = 4, S = 4; };
 template <> struct RegShape<32> { static constexpr int R = 8, S = 4; };
@@ -960,7 +965,7 @@ static hipError_t launch_reg(const PassArgs<T> &a, const EndArgs<T> &e, dim3 gri
         for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile_reg<T, TL>), gridr, block, lr, st, a, e);
         return hipGetLastError();
     }
-    if constexpr (TL == 16) {
+    if constexpr (cgq_form<T, TL>()) {
         if (e.epi == EPI_CG_Q) {
             if ((err = allow_lds(k_tile_reg1<T, TL, true>, lr)) != hipSuccess) return err;
             for (int k = 0; k < reps; ++k) hipLaunchKernelGGL((k_tile_reg1<T, TL, true>), grid, block, lr, st, a, e);
@@ -1025,10 +1030,14 @@ hipError_t launch_tile_group(const PassArgs<T> &a, const GroupGrid &gg, const Pa
     if (a.treg) {
         switch (a.tl) {
             // CG slots (epilogue q = K p) at frame 16: the form that preloads p and r
-            case 16: return gg.pro ? launch_reg_group<T, 16, true>(gg, dA, dE, st)
+            case 16: return gg.cgq ? launch_reg_group<T, 16, true>(gg, dA, dE, st)
                                    : launch_reg_group<T, 16, false>(gg, dA, dE, st);
-            case 32: return launch_reg_group<T, 32, false>(gg, dA, dE, st);
-            case 64: return launch_reg_group<T, 64, false>(gg, dA, dE, st);
+            case 32: return gg.cgq ? launch_reg_group<T, 32, true>(gg, dA, dE, st)
+                                   : launch_reg_group<T, 32, false>(gg, dA, dE, st);
+            case 64:
+                if constexpr (cgq_form<T, 64>())
+                    if (gg.cgq) return launch_reg_group<T, 64, true>(gg, dA, dE, st);
+                return launch_reg_group<T, 64, false>(gg, dA, dE, st);
             default: return hipErrorInvalidValue;
         }
     } else if (composite) {

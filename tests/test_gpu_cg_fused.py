@@ -86,3 +86,40 @@ def test_fused_cg_iteration_cap():
         assert torch.equal(a, c)
         assert all(x.status == msb.MSB_ENOCONV for x in ia) and all(x.inner_iters == k for x in ia)
         assert err <= 1e-10
+
+
+@pytest.mark.parametrize("prec,rel,tile", [("fp64", 0, 16), ("fp64", 0, 32), ("fp32_refined", 0, 32),
+                                           ("fp32_refined", 1, 16)])
+def test_group_fused_cg_equals_members_and_cholesky(prec, rel, tile):
+    """Plan groups fuse the steps too when every member can (no crack, no surface factors):
+    members of different sizes stop at different steps and leave the work list; each member's
+    solution equals its own fused solve bit for bit and the dense Cholesky solution."""
+    import torch
+    import paper_2301_11828_amd as msb
+    ws = [W.small(2, (40, 31), 3, seed=831, fixed="left", batch=2),
+          W.small(2, (18, 23), 3, seed=832, fixed="all", batch=1, infl=(0.5, 0.2)),
+          W.small(2, (57, 12), 3, seed=833, fixed="bottom", batch=2)]
+    cfg = dict(tile=tile, tile_regs=1, tile_run=1)
+    plans = [gpu_plan(w) for w in ws]
+    grp = msb.PlanGroup(plans)
+    for f in ("fp64", "fp32"):
+        grp.set_config(f, **cfg)
+    tol = 1e-11
+    bs = [to_dev(w.b) for w in ws]
+    us, infos = grp.solve(bs, precision=prec, tol=tol, reliable_update=rel, graph_block=8)
+    us = [u.clone() for u in us]
+    us0, _ = grp.solve(bs, precision=prec, tol=tol, reliable_update=rel, graph_block=0)
+    for i, (w, p) in enumerate(zip(ws, plans)):
+        assert torch.equal(us[i], us0[i]), "member %d: graph blocks differ from plain launches" % i
+        for f in ("fp64", "fp32"):
+            p.set_config(f, **grp.get_config(f))
+        own, own_info = p.solve(bs[i], precision=prec, tol=tol, reliable_update=rel)
+        if prec == "fp64":
+            assert torch.equal(us[i], own), "member %d differs from its own fused solve" % i
+        for c in range(w.batch):
+            ref = O.solve_dense(oracle_problem(w), w.b[c], w.fixed, None, oracle_bonds(w))
+            err = rel_err(us[i].cpu().numpy()[c], ref)
+            log("group fused %s rel %d t%d member %d case %d: %d it (own %d), residual %.2e, rel err %.2e" %
+                (prec, rel, tile, i, c, infos[i][c].inner_iters, own_info[c].inner_iters, infos[i][c].rel_residual, err))
+            assert infos[i][c].status == 0 and infos[i][c].rel_residual <= tol
+            assert err <= 100 * tol
