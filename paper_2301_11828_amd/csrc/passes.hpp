@@ -127,6 +127,9 @@ template <typename T> struct EndArgs {
     // place, q = K p to out; r.r of the block's inner nodes to rr_out[block].  rr_tiles:
     // the unfused CG epilogue also writes the r.r of the block's inner nodes (r = rhs) to
     // rr_out[block], so that a fused step can follow.
+    // cg_fused = 2: the stiffness step of preconditioned CG, p = z + beta p (z in pr, the
+    // previous p in pio, beta = r.z / previous r.z from case4), p of the inner nodes to p_new,
+    // then q = K p (in place: no block reads q off its own nodes) and its partials
     T *p_new;
     T *r_new;
     int cg_fused;

@@ -301,10 +301,10 @@ template <typename T> struct Cg {
 // r.r partials of a CG run on a plan: per case count and parity stride (the x tiles of
 // the prologue, or the product's blocks when the steps are fused into the tiled kernel).
 template <typename T> static bool cg_fusable(const PassArgs<T> &pa) {
-    // a register kernel with the CG-epilogue form (frames 16 and 32, and 64 in FP32), one
-    // block per workgroup, and no term that reads the transformed vector off the block's own
-    // nodes (broken bonds, surface correction): the patch forms the new p itself
-    const bool form = pa.tl == 16 || pa.tl == 32 || (pa.tl == 64 && sizeof(T) == 4);
+    // a register kernel with the CG-epilogue form (frame 16, and 32 and 64 in FP32), one block
+    // per workgroup, and no term that reads the transformed vector off the block's own nodes
+    // (broken bonds, surface correction): the patch forms the new p itself
+    const bool form = pa.tl == 16 || ((pa.tl == 32 || pa.tl == 64) && sizeof(T) == 4);
     return form && pa.treg && pa.tper == 1 && pa.corr && !pa.br_row_ptr && !pa.nu;
 }
 struct RrLayout {
@@ -629,6 +629,10 @@ template <typename T> struct Pcg {
     PassArgs<T> pp;   // preconditioner product (spectral symbol only)
     int tpc;
     const double *prev_rz;   // r.z partials before a residual replacement (first beta), or null
+    // fused stiffness steps (iterations >= 1): p alternates between pv (set 0) and p1 (set 1);
+    // iteration it reads set (it + 1) & 1 and writes set it & 1
+    bool fused = false;
+    T *p1 = nullptr;
 };
 
 // One preconditioned CG iteration = two product chains.
@@ -648,10 +652,11 @@ template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool up
     const size_t ne = (size_t)B * ept;
     const int cur = it & 1, prv = (it + 1) & 1;
     const bool reduce = it > 0 && std::max(c.tpc, ept) > kFusedReduceMaxTiles;
+    T *ps[2] = {c.pv, c.fused ? c.p1 : c.pv};
     {
         EndArgs<T> e = end_args<T>();
         e.pro = PRO_PCG_R;
-        e.pr = c.pv;
+        e.pr = ps[prv];   // the search direction of the previous iteration
         e.cx = c.x;
         e.cr = c.r;
         e.cq = c.q;
@@ -681,6 +686,27 @@ template <typename T> static msb_status pcg_iteration(Pcg<T> &c, int it, bool up
         MSB_TRY(launch_product<T>(c.pp, e, c.st));
     }
     if (update_only) return MSB_OK;
+    if (c.fused && it > 0) {
+        // one launch: p = z + beta p on the patches (beta from the case sums), then q = K p
+        const SumSrc src{{w->part_rz + (size_t)cur * 3 * nt, w->part_rz + (size_t)prv * 3 * nt, nullptr, nullptr,
+                          nullptr},
+                         {c.tpc, c.tpc, 0, 0, 0}};
+        hipLaunchKernelGGL(k_cg_sums<2>, dim3(B), dim3(kSumT), 0, c.st, src, w->case4);
+        EndArgs<T> e = end_args<T>();
+        e.pro = PRO_NONE;
+        e.cg_fused = 2;
+        e.pr = c.z;
+        e.pio = ps[prv];
+        e.p_new = ps[cur];
+        e.case4 = w->case4;
+        e.case_done = w->done + (size_t)cur * B;
+        e.epi = EPI_CG_Q;
+        e.uin = ps[cur];
+        e.out = c.q;
+        e.rhs = c.r;
+        e.part = w->part_x;
+        return launch_product<T>(c.pa, e, c.st);
+    }
     EndArgs<T> e = end_args<T>();
     e.pro = PRO_PCG_P;
     e.pr = c.z;
@@ -719,6 +745,12 @@ static msb_status pcg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T 
     Pcg<T> c{p, w, st, x, r, pv, q, z, pass_args<T>(p, p->op), pass_args<T>(p, p->pre), 0, prev_rz};
     c.pp.corr = 0;
     c.tpc = x_tiles_per_case(p, c.pa.F);
+    if (cg_fusable(c.pa)) {
+        T **alt = alt_vectors<T>(w);
+        if (!alt[1]) MSB_HIP(hipMalloc(&alt[1], sizeof(T) * n));
+        c.fused = true;
+        c.p1 = alt[1];
+    }
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, x, n, T(0));
     if (!prev_rz) hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kT), 0, st, pv, n, T(0));
     hipLaunchKernelGGL((k_cast<T, T>), dim3(grid_for(n)), dim3(kT), 0, st, r, rhs, n);
@@ -734,7 +766,12 @@ static msb_status pcg_solve(msb_plan_s *p, SolverWs *w, hipStream_t st, const T 
     key.add(1);
     key.add(c.pa), key.add(c.pp);
     key.add(c.x), key.add(c.r), key.add(c.pv), key.add(c.q), key.add(c.z), key.add(c.tpc), key.add(c.st);
+    key.add(c.fused), key.add(c.p1);
     msb_status r0 = run_iterations(w, B, st, iter, maxit, graph_block, &it, &key);
+    // the last stiffness step (iteration it - 1; iteration it updated only) wrote set 1: the
+    // search direction back to pv
+    if (r0 == MSB_OK && c.fused && it >= 1 && ((it - 1) & 1))
+        MSB_HIP(hipMemcpyAsync(pv, c.p1, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
     if (iters_out) *iters_out = it;
     return r0;
 }

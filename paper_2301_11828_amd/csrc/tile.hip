@@ -249,9 +249,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_tile(PassArgs<T> a, EndArgs<T> e)
 // frame is written again only two exchanges later, after every thread has passed the
 // barrier that follows its last read.
 // The CG-epilogue form of the register kernel (p and r preloaded during the inverse
-// transforms; the fused CG step) exists where its registers fit without spills: every frame
-// in FP32, frames 16 and 32 in FP64.
-template <typename T, int TL> constexpr bool cgq_form() { return sizeof(T) == 4 || TL <= 32; }
+// transforms; the fused CG steps) exists where its registers keep the plain form's waves per
+// SIMD: every frame in FP32, frame 16 in FP64 (FP64 frame 32 would take 258 registers).
+template <typename T, int TL> constexpr bool cgq_form() { return sizeof(T) == 4 || TL == 16; }
 
 template <int TL> struct RegShape;
 template <> struct RegShape<16> { static constexpr int R = 4, S = 4; };
@@ -320,10 +320,26 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
     // fused CG step: alpha = r.r / p.q, the new r.r = r.r - 2 alpha r.q + alpha^2 q.q and
     // beta = new r.r / r.r from the case sums, with the stop and breakdown tests of the
     // prologue (one block per case writes the flags)
-    const bool fused = CGQ && e.cg_fused;
+    const bool fused = CGQ && e.cg_fused == 1;
+    const bool pfused = CGQ && e.cg_fused == 2;
     T alpha = T(0), beta = T(0);
     bool conv = false;
-    if (fused) {
+    if (pfused) {
+        if (e.case_done[b]) {   // stopped: p of the inner nodes carried over to the new vector
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int ly = p + S * i;
+                if (col_inner && ly >= M && ly < M + ny) {
+                    const size_t ax = cbase + (size_t)(y0 - M + ly) * Nx + gx, ay = ax + N;
+                    e.p_new[ax] = e.pio[ax];
+                    e.p_new[ay] = e.pio[ay];
+                }
+            }
+            return;
+        }
+        const double rz = e.case4[(size_t)b * 2], rzp = e.case4[(size_t)b * 2 + 1];
+        beta = T(rzp > 0.0 ? rz / rzp : 0.0);
+    } else if (fused) {
         const bool lead = rem == 0 && tid == 0;
         if (e.done_prev[b]) {
             // stopped before this step: carry the flag, and r, p of the inner nodes over to
@@ -399,7 +415,15 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
         if (CGQ) pux[i] = puy[i] = prx[i] = pry[i] = T(0);
         if (col_in && gy >= 0 && gy < Ny) {
             const size_t q = (size_t)gy * Nx + gx;
-            if (fused) {
+            if (pfused) {   // p = z + beta p (the prologue's arithmetic)
+                const size_t ax = cbase + q, ay = ax + N;
+                v[i].x = e.pr[ax] + beta * e.pio[ax];
+                v[i].y = e.pr[ay] + beta * e.pio[ay];
+                if (col_inner && ly >= M && ly < M + ny) {
+                    e.p_new[ax] = v[i].x;
+                    e.p_new[ay] = v[i].y;
+                }
+            } else if (fused) {
                 const size_t ax = cbase + q, ay = ax + N;
                 const T px = e.pio[ax], py = e.pio[ay];
                 const T rx = e.cr[ax] - alpha * e.cq[ax], ry = e.cr[ay] - alpha * e.cq[ay];
@@ -1032,8 +1056,10 @@ hipError_t launch_tile_group(const PassArgs<T> &a, const GroupGrid &gg, const Pa
             // CG slots (epilogue q = K p) at frame 16: the form that preloads p and r
             case 16: return gg.cgq ? launch_reg_group<T, 16, true>(gg, dA, dE, st)
                                    : launch_reg_group<T, 16, false>(gg, dA, dE, st);
-            case 32: return gg.cgq ? launch_reg_group<T, 32, true>(gg, dA, dE, st)
-                                   : launch_reg_group<T, 32, false>(gg, dA, dE, st);
+            case 32:
+                if constexpr (cgq_form<T, 32>())
+                    if (gg.cgq) return launch_reg_group<T, 32, true>(gg, dA, dE, st);
+                return launch_reg_group<T, 32, false>(gg, dA, dE, st);
             case 64:
                 if constexpr (cgq_form<T, 64>())
                     if (gg.cgq) return launch_reg_group<T, 64, true>(gg, dA, dE, st);

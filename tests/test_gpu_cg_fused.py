@@ -123,3 +123,34 @@ def test_group_fused_cg_equals_members_and_cholesky(prec, rel, tile):
                 (prec, rel, tile, i, c, infos[i][c].inner_iters, own_info[c].inner_iters, infos[i][c].rel_residual, err))
             assert infos[i][c].status == 0 and infos[i][c].rel_residual <= tol
             assert err <= 100 * tol
+
+
+@pytest.mark.parametrize("prec,rel", [("fp64", 0), ("fp32_refined", 0), ("fp32_refined", 1)])
+def test_fused_pcg_matches_cholesky_and_graphs(prec, rel):
+    """Preconditioned CG with its stiffness step fused (p = z + beta p on the patches, p
+    alternating between two vectors): cases stopping at different steps (a zero and a small
+    load), against dense Cholesky, graph-block replays bit for bit, and FP64 iteration counts
+    of the unfused chain."""
+    import torch
+    w = W.small(2, (46, 35), 3, seed=841, fixed="left", batch=4, infl=(0.7, 0.4))
+    b = w.b.copy()
+    b[0] = 0.0
+    b[2] *= 1e-3
+    plan = _plan(w)
+    tol = 1e-11
+    u, info = plan.solve(to_dev(b), precision=prec, tol=tol, reliable_update=rel, precond=True, graph_block=8)
+    u = u.clone()
+    u0, info0 = plan.solve(to_dev(b), precision=prec, tol=tol, reliable_update=rel, precond=True, graph_block=0)
+    assert torch.equal(u, u0)
+    assert [x.inner_iters for x in info] == [x.inner_iters for x in info0]
+    chain = gpu_plan(w)
+    _, info_c = chain.solve(to_dev(b), precision=prec, tol=tol, reliable_update=rel, precond=True)
+    for c in range(w.batch):
+        ref = O.solve_dense(oracle_problem(w), b[c], w.fixed, None, oracle_bonds(w))
+        err = rel_err(u.cpu().numpy()[c], ref) if c else float(u[c].abs().max())
+        log("fused PCG %s rel %d case %d: %d it (chain %d), residual %.2e, err %.2e" %
+            (prec, rel, c, info[c].inner_iters, info_c[c].inner_iters, info[c].rel_residual, err))
+        assert info[c].status == 0 and info[c].rel_residual <= tol
+        assert err <= 100 * tol
+        if prec == "fp64":
+            assert abs(info[c].inner_iters - info_c[c].inner_iters) <= 3
