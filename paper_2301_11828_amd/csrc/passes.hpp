@@ -155,6 +155,8 @@ template <typename T> struct EndArgs {
                          // constrained DOFs, pg) into this vector, so that the next product needs
                          // no prologue pass (u itself is read by neighbouring blocks: not in place)
     double sign;         // EPI_APPLY sign
+    int wt;              // EPI_APPLY in the block kernels: the output written through the L2 (set
+                         // by the block-kernel launcher, see st_wt)
     double rho;
     int energy;          // EPI_VV: accumulate energy partials
     double *part;        // partial sums [K][B*tiles]

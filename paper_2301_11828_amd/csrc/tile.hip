@@ -856,8 +856,15 @@ __device__ __forceinline__ void reg_tile_process(const PassArgs<T> &a, const End
                 const T fx = v[i].x + dcor[i].x, fy = v[i].y + dcor[i].y;
                 const size_t ax = cbase + node, ay = ax + N;
                 if (e.epi == EPI_APPLY) {
-                    e.out[ax] = (rt.fix >> (2 * i)) & 1u ? T(0) : sign * fx;
-                    e.out[ay] = (rt.fix >> (2 * i + 1)) & 1u ? T(0) : sign * fy;
+                    const T ox = (rt.fix >> (2 * i)) & 1u ? T(0) : sign * fx;
+                    const T oy = (rt.fix >> (2 * i + 1)) & 1u ? T(0) : sign * fy;
+                    if (e.wt) {
+                        st_wt(&e.out[ax], ox);
+                        st_wt(&e.out[ay], oy);
+                    } else {
+                        e.out[ax] = ox;
+                        e.out[ay] = oy;
+                    }
                 } else {
                     epilogue_at<T>(e, uin, ax, node + pb, fx, (rt.fix >> (2 * i)) & 1u, sign, rinv, dth, acc0, acc1,
                                    acc2);
@@ -977,6 +984,9 @@ template <typename K> static hipError_t allow_lds(K kern, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Largest plain-product output written through the L2s (a quarter of their 8 x 4 MB).
+constexpr size_t kWtMaxBytes = 8u << 20;
+
 // Register-frame launch for frame length TL: runs of blocks, the CG-epilogue form (frame 16,
 // whose registers leave room for the preloaded p and r) or the plain one-block form.
 template <typename T, int TL>
@@ -1002,10 +1012,13 @@ static hipError_t launch_reg(const PassArgs<T> &a, const EndArgs<T> &e, dim3 gri
 }
 
 template <typename T>
-hipError_t launch_tile_kernel(const PassArgs<T> &a, const EndArgs<T> &e, size_t lds, bool composite, int reps,
+hipError_t launch_tile_kernel(const PassArgs<T> &a, const EndArgs<T> &e0, size_t lds, bool composite, int reps,
                               hipStream_t st) {
     const dim3 grid(a.B * a.ttx * a.tty), block(a.tthreads);
     hipError_t err;
+    // a plain product whose output is at most kWtMaxBytes is written through the L2s (st_wt)
+    EndArgs<T> e = e0;
+    e.wt = e.epi == EPI_APPLY && (size_t)a.B * 2 * a.N * sizeof(T) <= kWtMaxBytes;
     if (a.treg) {
         // register-resident frames: S TL threads, two TL x (TL + 1) frames
         const size_t lr = 2 * (size_t)a.tl * (a.tl + 1) * sizeof(cplx_t<T>);
