@@ -299,6 +299,7 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
     constexpr int R = RegShape<TL>::R, S = RegShape<TL>::S, RA = R / S, P = TL + 1;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[96];
+    __shared__ int nbr;   // listed Omega_br entries of the block
     const int tid = threadIdx.x;
     const int ln = tid % TL, p = tid / TL;    // line and part
     const int M = a.M, Tt = TL - 2 * M;
@@ -524,14 +525,40 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
             cor[i].x = T(0);
             cor[i].y = T(0);
         }
+        if (tid == 0) nbr = 0;
         __syncthreads();
         const T *wt = a.w + (size_t)b * a.w_slot;
         if (bonds) {
+            // the Omega_br entries of the block's rows span the whole grid width: they are
+            // scanned kScan per thread at a time (independent loads), the block's own listed
+            // in the free frame buf0 as (entry, node) pairs (at most Tt^2 nodes: 2 Tt^2 ints
+            // fit in its TL (TL + 1) complex elements), then summed one entry per thread.  Each
+            // entry is a distinct node, so the order of the list does not change the result.
+            int *lst = reinterpret_cast<int *>(buf0);
             const int e0 = a.br_row_ptr[y0], e1 = a.br_row_ptr[y0 + ny];
-            for (int ei = e0 + tid; ei < e1; ei += nt) {
-                const int node = a.br_node_i[ei];
+            constexpr int kScan = 8;
+            for (int base = e0; base < e1; base += kScan * nt) {
+                int nd[kScan];
+#pragma unroll
+                for (int j = 0; j < kScan; ++j) {
+                    const int ei = base + j * nt + tid;
+                    nd[j] = ei < e1 ? a.br_node_i[ei] : -1;
+                }
+#pragma unroll
+                for (int j = 0; j < kScan; ++j) {
+                    const int qx = nd[j] - (nd[j] / Nx) * Nx;
+                    if (nd[j] >= 0 && qx >= x0 && qx < x0 + nx) {
+                        const int k = atomicAdd(&nbr, 1);
+                        lst[2 * k] = base + j * nt + tid;
+                        lst[2 * k + 1] = nd[j];
+                    }
+                }
+            }
+            __syncthreads();
+            const int cnt = nbr;
+            for (int k = tid; k < cnt; k += nt) {
+                const int ei = lst[2 * k], node = lst[2 * k + 1];
                 const int qy = node / Nx, qx = node - qy * Nx;
-                if (qx < x0 || qx >= x0 + nx) continue;
                 const bool on_e = a.nu && (qx < M || qx >= Nx - M || qy < M || qy >= Ny - M);
                 const double nup = on_e ? (double)a.nu[node] : 0.0;
                 const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
