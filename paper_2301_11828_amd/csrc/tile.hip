@@ -63,6 +63,42 @@ __device__ __forceinline__ void df_bond_sum(const PassArgs<T> &a, const T *__res
     }
 }
 
+// The broken-bond entries (the Omega_br nodes of eq. (tea:fr)) of a block's inner nodes,
+// columns [x0, x0 + nx) of rows [y0, y0 + ny).  The entries of those rows span the whole
+// grid width, so they are scanned kScan per thread at a time (independent loads) and the
+// block's own are listed in lst as (entry, node) pairs; returns their count to every thread.
+// lst holds 2 nx ny ints, and no thread may still use its memory when the first one calls.
+// Each entry is a distinct node, so the order of the list does not change per-entry sums.
+template <typename T>
+__device__ __forceinline__ int list_block_bonds(const PassArgs<T> &a, int x0, int nx, int y0, int ny, int *lst,
+                                                int tid, int nt) {
+    __shared__ int cnt;
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+    const int Nx = a.Nx;
+    const int e0 = a.br_row_ptr[y0], e1 = a.br_row_ptr[y0 + ny];
+    constexpr int kScan = 8;
+    for (int base = e0; base < e1; base += kScan * nt) {
+        int nd[kScan];
+#pragma unroll
+        for (int j = 0; j < kScan; ++j) {
+            const int ei = base + j * nt + tid;
+            nd[j] = ei < e1 ? a.br_node_i[ei] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < kScan; ++j) {
+            const int qx = nd[j] - (nd[j] / Nx) * Nx;
+            if (nd[j] >= 0 && qx >= x0 && qx < x0 + nx) {
+                const int k = atomicAdd(&cnt, 1);
+                lst[2 * k] = base + j * nt + tid;
+                lst[2 * k + 1] = nd[j];
+            }
+        }
+    }
+    __syncthreads();
+    return cnt;
+}
+
 template <typename T, int RMAX>
 __device__ __forceinline__ void tile_body(const PassArgs<T> &a, const EndArgs<T> &e, int tile, int ntiles) {
     using T2 = cplx_t<T>;
@@ -136,11 +172,14 @@ __device__ __forceinline__ void tile_body(const PassArgs<T> &a, const EndArgs<T>
     // the per-row lists; f_p += sum_q W(q - p) (u_p - u_q) (with the surface correction a
     // bond of an Omega_e row carries v_pq W)
     if (a.br_row_ptr && ny > 0) {
-        const int e0 = a.br_row_ptr[y0], e1 = a.br_row_ptr[y0 + ny];
-        for (int ei = e0 + tid; ei < e1; ei += nt) {
-            const int node = a.br_node_i[ei];
+        // the block's entries listed in the frame that does not hold the result, then summed
+        // one per thread
+        T2 *fr = r - (size_t)M * P == bufA ? bufB : bufA;
+        const int cnt = list_block_bonds(a, x0, nx, y0, ny, reinterpret_cast<int *>(fr), tid, nt);
+        const int *lst = reinterpret_cast<const int *>(fr);
+        for (int k = tid; k < cnt; k += nt) {
+            const int ei = lst[2 * k], node = lst[2 * k + 1];
             const int gy = node / Nx, gx = node - gy * Nx;
-            if (gx < x0 || gx >= x0 + nx) continue;
             const bool on_e = a.nu && (gx < M || gx >= Nx - M || gy < M || gy >= Ny - M);
             const double nup = on_e ? (double)a.nu[node] : 0.0;
             const double upx = (double)uin[cbase + node], upy = (double)uin[cbase + N + node];
@@ -299,7 +338,6 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
     constexpr int R = RegShape<TL>::R, S = RegShape<TL>::S, RA = R / S, P = TL + 1;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[96];
-    __shared__ int nbr;   // listed Omega_br entries of the block
     const int tid = threadIdx.x;
     const int ln = tid % TL, p = tid / TL;    // line and part
     const int M = a.M, Tt = TL - 2 * M;
@@ -525,37 +563,13 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
             cor[i].x = T(0);
             cor[i].y = T(0);
         }
-        if (tid == 0) nbr = 0;
         __syncthreads();
         const T *wt = a.w + (size_t)b * a.w_slot;
         if (bonds) {
-            // the Omega_br entries of the block's rows span the whole grid width: they are
-            // scanned kScan per thread at a time (independent loads), the block's own listed
-            // in the free frame buf0 as (entry, node) pairs (at most Tt^2 nodes: 2 Tt^2 ints
-            // fit in its TL (TL + 1) complex elements), then summed one entry per thread.  Each
-            // entry is a distinct node, so the order of the list does not change the result.
-            int *lst = reinterpret_cast<int *>(buf0);
-            const int e0 = a.br_row_ptr[y0], e1 = a.br_row_ptr[y0 + ny];
-            constexpr int kScan = 8;
-            for (int base = e0; base < e1; base += kScan * nt) {
-                int nd[kScan];
-#pragma unroll
-                for (int j = 0; j < kScan; ++j) {
-                    const int ei = base + j * nt + tid;
-                    nd[j] = ei < e1 ? a.br_node_i[ei] : -1;
-                }
-#pragma unroll
-                for (int j = 0; j < kScan; ++j) {
-                    const int qx = nd[j] - (nd[j] / Nx) * Nx;
-                    if (nd[j] >= 0 && qx >= x0 && qx < x0 + nx) {
-                        const int k = atomicAdd(&nbr, 1);
-                        lst[2 * k] = base + j * nt + tid;
-                        lst[2 * k + 1] = nd[j];
-                    }
-                }
-            }
-            __syncthreads();
-            const int cnt = nbr;
+            // the block's entries listed in the free frame buf0 (2 Tt^2 ints fit in its
+            // TL (TL + 1) complex elements), then summed one entry per thread
+            const int cnt = list_block_bonds(a, x0, nx, y0, ny, reinterpret_cast<int *>(buf0), tid, nt);
+            const int *lst = reinterpret_cast<const int *>(buf0);
             for (int k = tid; k < cnt; k += nt) {
                 const int ei = lst[2 * k], node = lst[2 * k + 1];
                 const int qy = node / Nx, qx = node - qy * Nx;
@@ -815,11 +829,12 @@ __device__ __forceinline__ void reg_tile_process(const PassArgs<T> &a, const End
         __syncthreads();
         const T *wt = a.w + (size_t)g.b * a.w_slot;
         if (bonds) {
-            const int e0 = a.br_row_ptr[g.y0], e1 = a.br_row_ptr[g.y0 + g.ny];
-            for (int ei = e0 + tid; ei < e1; ei += nt) {
-                const int node = a.br_node_i[ei];
+            // the block's entries listed in the free frame buf0, then summed one per thread
+            const int cnt = list_block_bonds(a, g.x0, g.nx, g.y0, g.ny, reinterpret_cast<int *>(buf0), tid, nt);
+            const int *lst = reinterpret_cast<const int *>(buf0);
+            for (int k = tid; k < cnt; k += nt) {
+                const int ei = lst[2 * k], node = lst[2 * k + 1];
                 const int qy = node / Nx, qx = node - qy * Nx;
-                if (qx < g.x0 || qx >= g.x0 + g.nx) continue;
                 const bool on_e = a.nu && (qx < M || qx >= Nx - M || qy < M || qy >= Ny - M);
                 const double nup = on_e ? (double)a.nu[node] : 0.0;
                 const double px = (double)uin[cbase + node], py = (double)uin[cbase + N + node];
