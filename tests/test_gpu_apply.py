@@ -270,6 +270,28 @@ def test_plate512_at_the_benchmark_tuning(prec):
     assert err <= (FP64_TOL if prec == "fp64" else FP32_TOL)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plate512_written_through_output_equals_plain_stores(prec):
+    """The block kernel writes a plain product's output through the L2s when it is at most 8 MB
+    (one plate512 case: 4.2 MB in FP64) and with plain stores above (three FP64 cases, five FP32
+    ones): case 0 of the larger batch equals the one-case product bit for bit."""
+    import torch
+    rec = _recorded_tuning()
+    w = W.plate512()
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    big = 3 if prec == "fp64" else 5
+    assert big * 2 * w.N * (8 if prec == "fp64" else 4) > 8 << 20 >= 2 * w.N * (8 if prec == "fp64" else 4)
+    u = np.random.default_rng(14).standard_normal((big, 2, w.N))
+    out = []
+    for B in (1, big):
+        plan = gpu_plan(w, batch=B)
+        plan.set_lengths(rec["padded"])
+        plan.set_config(prec, **rec[prec])
+        out.append(gpu_apply(plan, to_dev(u[:B], dt)).cpu().numpy())
+    log("plate512 %s: one case (written through) vs case 0 of %d (plain stores)" % (prec, big))
+    assert np.array_equal(out[0][0], out[1][0])
+
+
 def test_plate512_batch16_at_the_benchmark_tuning():
     """The bench's 16-case plate512 product in its recorded configuration: sampled rows of
     three cases against the oracle's row-by-row sum."""
