@@ -325,9 +325,10 @@ struct SumSrc {
     const double *p[5];
     int n[5];   // partials per case of each array
 };
-// 16 waves: a case's partials (a few thousand per array at most tiles) are loaded in one or
-// two rounds of independent loads, the reduction being latency-bound
-constexpr int kSumT = 1024;
+// 8 waves: a case's partials (a few thousand per array at most tiles) are loaded in one or
+// two rounds of independent loads, the reduction being latency-bound (measured against 4 and
+// 16 waves: plate512 CG 2.5% faster than with 16)
+constexpr int kSumT = 512;
 template <int K> __global__ __launch_bounds__(kSumT) void k_cg_sums(SumSrc src, double *out) {
     __shared__ double red[96];
     const int b = blockIdx.x;
