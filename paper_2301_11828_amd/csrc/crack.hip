@@ -134,6 +134,7 @@ msb_status upload_mask(msb_plan_s *p, CrackWs *w) {
 
 struct Grid {
     int d, nx, ny, nz, N, nh, words;
+    int M;   // horizon in nodes: every half-stencil offset component is within [-M, M]
 };
 
 // The bonds {p, p + o} of the half stencil that are unbroken and break now: with
@@ -142,8 +143,10 @@ struct Grid {
 // (thr2, one value per offset), so neither a square root nor a division is needed.
 // Branch-free over the offsets (a bond outside the grid or already broken reads node p
 // itself and is masked out), so the loads of several bonds are in flight at once.
-// nw: the new bits per mask word; returns their number.
-template <typename T, int D>
+// nw: the new bits per mask word; returns their number.  IN: node p is at least M nodes from
+// every face, so every neighbour p + o lies in the grid and no bounds are tested (the same
+// arithmetic and result as the general form).
+template <typename T, int D, bool IN = false>
 __device__ __forceinline__ int node_breaks(const Grid &g, const T *__restrict__ u, const int *__restrict__ hoff,
                                            const double *__restrict__ thr2, const uint32_t *__restrict__ mu,
                                            int p, uint32_t (&nw)[kMaxWords], double h) {
@@ -159,9 +162,11 @@ __device__ __forceinline__ int node_breaks(const Grid &g, const T *__restrict__ 
 #pragma unroll 4
         for (int b = 32 * wd; b < kend; ++b) {
             const int ox = hoff[3 * b], oy = hoff[3 * b + 1], oz = hoff[3 * b + 2];
-            const bool ok = !((old >> (b & 31)) & 1u) && (unsigned)(i + ox) < (unsigned)g.nx &&
-                            (unsigned)(j + oy) < (unsigned)g.ny && (unsigned)(k + oz) < (unsigned)g.nz;
-            const int q = ok ? p + (oz * g.ny + oy) * g.nx + ox : p;
+            const bool unbroken = !((old >> (b & 31)) & 1u);
+            const bool ok = IN ? unbroken
+                               : unbroken && (unsigned)(i + ox) < (unsigned)g.nx && (unsigned)(j + oy) < (unsigned)g.ny &&
+                                     (unsigned)(k + oz) < (unsigned)g.nz;
+            const int q = IN || ok ? p + (oz * g.ny + oy) * g.nx + ox : p;
             const int o3[3] = {ox, oy, oz};
             double s2 = 0.0;
 #pragma unroll
@@ -216,7 +221,15 @@ __global__ __launch_bounds__(kCT) void k_stretch(Grid g, const T *__restrict__ u
     int cnt = 0;
     if (p < g.N) {
         uint32_t nw[kMaxWords];
-        cnt = node_breaks<T, D>(g, u, hoff, thr2, mu, p, nw, h);
+        // a wave whose nodes are all at least M from every face takes the form without bounds
+        // tests (the branch is uniform across the wave)
+        const int i = p % g.nx, j = (p / g.nx) % g.ny, k = p / (g.nx * g.ny);
+        const bool in = i >= g.M && i < g.nx - g.M && j >= g.M && j < g.ny - g.M &&
+                        (D == 2 || (k >= g.M && k < g.nz - g.M));
+        if (__all(in))
+            cnt = node_breaks<T, D, true>(g, u, hoff, thr2, mu, p, nw, h);
+        else
+            cnt = node_breaks<T, D>(g, u, hoff, thr2, mu, p, nw, h);
         count[p] = (uint8_t)cnt;
     }
     int v = cnt;
@@ -300,7 +313,7 @@ msb_status crack_update_t(msb_plan_s *p, const T *u, double s0, int64_t *n_new, 
         MSB_HIP(hipMemcpyAsync(w->thr2, w->h_thr2, sizeof(double) * w->nh, hipMemcpyHostToDevice, st));
         w->s0 = s0;
     }
-    const Grid g{p->dim, (int)p->n[0], (int)p->n[1], (int)p->n[2], (int)p->N, w->nh, p->mu_words};
+    const Grid g{p->dim, (int)p->n[0], (int)p->n[1], (int)p->n[2], (int)p->N, w->nh, p->mu_words, p->M};
     const int nblk = (int)((p->N + kCT - 1) / kCT);
     if (p->dim == 2)
         hipLaunchKernelGGL((k_stretch<T, 2>), dim3(nblk), dim3(kCT), 0, st, g, u, (const int *)w->hoff,
