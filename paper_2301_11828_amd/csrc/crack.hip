@@ -28,7 +28,8 @@ struct CrackWs {
     int *hoff = nullptr;        // [nh][3]
     double *thr2 = nullptr;     // [nh] ((1 + s0) |o| h)^2 of the current call
     uint8_t *count = nullptr;   // [N] new breaks per node
-    int64_t *blk = nullptr;     // [nblk + 1] per-block counts, then their exclusive scan
+    int64_t *blk = nullptr;     // [nblk + 2] per-block counts, then their exclusive scan and the total;
+                                // blk[nblk + 1]: the total the stretch pass accumulates (0 between calls)
     int64_t *pairs = nullptr;   // [cap][2]
     int64_t cap = 0;
     int64_t *h_total = nullptr; // pinned
@@ -101,7 +102,8 @@ msb_status alloc_crack_ws(msb_plan_s *p, CrackWs *w, const std::vector<int> &hof
     if (nh) MSB_HIP(hipMemcpy(w->hoff, hoff.data(), sizeof(int) * hoff.size(), hipMemcpyHostToDevice));
     MSB_HIP(hipMalloc(&p->mu_mask, sizeof(uint32_t) * N * p->mu_words));
     MSB_HIP(hipMalloc(&w->count, N));
-    MSB_HIP(hipMalloc(&w->blk, sizeof(int64_t) * (nblk + 1)));
+    MSB_HIP(hipMalloc(&w->blk, sizeof(int64_t) * (nblk + 2)));
+    MSB_HIP(hipMemset(w->blk, 0, sizeof(int64_t) * (nblk + 2)));
     MSB_HIP(hipHostMalloc(&w->h_total, sizeof(int64_t)));
     MSB_HIP(hipHostMalloc(&w->h_thr2, sizeof(double) * std::max(1, nh)));
     p->mu_valid = false;
@@ -211,7 +213,9 @@ __device__ __forceinline__ long long block_exclusive_scan(long long x, long long
 }
 
 // One thread per node: count of the bonds that break now (fresh bits are not stored:
-// the emit pass recomputes them for the few nodes with a break); block totals to blk.
+// the emit pass recomputes them for the few nodes with a break); block totals to blk, and
+// the blocks with a break add theirs to blk[nblk + 1] (integer adds: the total is exact in any
+// order), so that a call without breaks needs no scan.
 template <typename T, int D>
 __global__ __launch_bounds__(kCT) void k_stretch(Grid g, const T *__restrict__ u, const int *__restrict__ hoff,
                                                  const double *__restrict__ thr2, const uint32_t *__restrict__ mu,
@@ -240,6 +244,7 @@ __global__ __launch_bounds__(kCT) void k_stretch(Grid g, const T *__restrict__ u
         int64_t t = 0;
         for (int wv = 0; wv < kCT / 64; ++wv) t += red[wv];
         blk[blockIdx.x] = t;
+        if (t) atomicAdd(reinterpret_cast<unsigned long long *>(blk + gridDim.x + 1), (unsigned long long)t);
     }
 }
 
@@ -321,12 +326,15 @@ msb_status crack_update_t(msb_plan_s *p, const T *u, double s0, int64_t *n_new, 
     else
         hipLaunchKernelGGL((k_stretch<T, 3>), dim3(nblk), dim3(kCT), 0, st, g, u, (const int *)w->hoff,
                            (const double *)w->thr2, (const uint32_t *)p->mu_mask, w->count, w->blk, p->h);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanT), 0, st, w->blk, nblk);
     MSB_HIP(hipGetLastError());
-    MSB_HIP(hipMemcpyAsync(w->h_total, w->blk + nblk, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipMemcpyAsync(w->h_total, w->blk + nblk + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     MSB_HIP(hipStreamSynchronize(st));
     const int64_t total = *w->h_total;
     if (total == 0) return MSB_OK;
+    // breaks: the running total back to 0 for the next call, then the block offsets
+    MSB_HIP(hipMemsetAsync(w->blk + nblk + 1, 0, sizeof(int64_t), st));
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanT), 0, st, w->blk, nblk);
+    MSB_HIP(hipGetLastError());
     if (total > w->cap) {
         if (w->pairs) MSB_HIP(hipFree(w->pairs));
         w->pairs = nullptr;
