@@ -161,7 +161,7 @@ __device__ __forceinline__ int node_breaks(const Grid &g, const T *__restrict__ 
         const uint32_t old = mu[(size_t)p * g.words + wd];
         uint32_t bits = 0;
         const int kend = min(g.nh, 32 * (wd + 1));
-#pragma unroll 4
+#pragma unroll 8
         for (int b = 32 * wd; b < kend; ++b) {
             const int ox = hoff[3 * b], oy = hoff[3 * b + 1], oz = hoff[3 * b + 2];
             const bool unbroken = !((old >> (b & 31)) & 1u);
@@ -176,10 +176,11 @@ __device__ __forceinline__ int node_breaks(const Grid &g, const T *__restrict__ 
                 const double e = o3[c] * h + ((double)u[(size_t)c * g.N + q] - up[c]);
                 s2 += e * e;
             }
-            if (ok && s2 >= thr2[b]) {
-                bits |= 1u << (b & 31);
-                ++cnt;
-            }
+            // both tests evaluated (no short circuit): the loads above then stay unconditional and
+            // those of the unrolled bonds are in flight together
+            const bool brk = ok & (s2 >= thr2[b]);
+            bits |= (uint32_t)brk << (b & 31);
+            cnt += (int)brk;
         }
         nw[wd] = bits;
     }
