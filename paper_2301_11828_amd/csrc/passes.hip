@@ -624,6 +624,13 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
     const FastDiv by_nr((uint32_t)nr, (uint32_t)(2 * S));
     const FastDiv by_ny((uint32_t)a.Ny, (uint32_t)a.rows);
     stage_twiddles(twl, a.twx, Lx, threadIdx.x, blockDim.x);   // published by the barrier after the gather
+    // the constraint class of each signal's x-row (published by the same barrier), so that the
+    // epilogue neither waits for it nor reads the mask of rows with none or all constrained
+    __shared__ uint8_t rfl[48];   // d F signals: F <= 16 rows per workgroup, d <= 3
+    for (int t = threadIdx.x; t < nsig; t += blockDim.x) {
+        const int c = (int)by_nr.div((uint32_t)t), row = r0 + t - c * nr;
+        rfl[t] = a.fixed ? a.row_fix[(size_t)c * a.rows + row] : 0;
+    }
     int s0, ns;
     tm.slots(S, a.spw_i, s0, ns);
 
@@ -815,7 +822,9 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
             int c, row, rpart;
             const bool rint = row_of(sl, c, row, rpart);
             const size_t rbase = cbase + (size_t)c * a.N + (size_t)row * a.Nx;
-            const uint8_t *fxrow = a.fixed ? a.fixed + (size_t)c * a.N + (size_t)row * a.Nx : nullptr;
+            // the mask is read only on x-rows with some (not all) DOFs constrained
+            const int rf = rfl[2 * s0 + sl];
+            const uint8_t *fxrow = rf == 2 ? a.fixed + (size_t)c * a.N + (size_t)row * a.Nx : nullptr;
             const T *Rrow = Rr + 2 * (size_t)(sl >> 1) * Lx + (sl & 1);
             const T *dec[3];
             for (int cb = 0; cb < 3; ++cb) dec[cb] = de + (size_t)comp_of(c, cb < d ? cb : 0, d) * a.de_stride + rpart;
@@ -830,7 +839,7 @@ __device__ __forceinline__ void xinv_body(const PassArgs<T> &a, const EndArgs<T>
                         for (int cb = 0; cb < d; ++cb) f += dec[cb][dx] * urow[cb * a.N + n];
                     }
                 }
-                const bool fx = fxrow && fxrow[n];
+                const bool fx = rf == 1 || (fxrow && fxrow[n]);
                 epilogue_at<T>(e, uin, addr, addr - cbase + (size_t)b * e.pa_stride, f, fx, sign, rinv, dth, acc0, acc1,
                                acc2);
             }
@@ -1102,6 +1111,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.de_stride = p->de_stride;
     a.n_off = p->n_off;
     a.fixed = p->fixed;
+    a.row_fix = p->row_fix;
     a.nu = sel<T>(p->nu64, p->nu32);
     a.offs = p->off_dev;
     a.br_row_ptr = p->n_pairs ? p->br_row_ptr : nullptr;

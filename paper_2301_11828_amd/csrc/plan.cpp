@@ -898,7 +898,7 @@ extern "C" void msb_plan_destroy(msb_plan p) {
     free_operator(p->op);
     free_operator(p->pre);
     for (auto &o : p->dop) free_operator(o);
-    void *bufs[] = {p->fixed, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off, p->T1, p->T2,
+    void *bufs[] = {p->fixed, p->row_fix, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off, p->T1, p->T2,
                     p->nu64, p->nu32, p->off_dev};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -922,7 +922,9 @@ extern "C" msb_status msb_plan_set_constraints(msb_plan p, const uint8_t *fixed)
     const size_t n = (size_t)p->dim * p->N;
     if (!fixed) {
         if (p->fixed) hipFree(p->fixed);
+        if (p->row_fix) hipFree(p->row_fix);
         p->fixed = nullptr;
+        p->row_fix = nullptr;
         p->n_fixed = 0;
         return MSB_OK;
     }
@@ -932,8 +934,19 @@ extern "C" msb_status msb_plan_set_constraints(msb_plan p, const uint8_t *fixed)
         x = x ? 1 : 0;
         cnt += x;
     }
+    // the class of every x-row of every component (no constrained DOF / all / some), so that
+    // the x-inverse reads the mask only on rows with some
+    const int64_t nx = p->n[0], rows = p->N / nx;
+    std::vector<uint8_t> rc((size_t)p->dim * rows);
+    for (int64_t r = 0; r < (int64_t)rc.size(); ++r) {
+        int64_t k = 0;
+        for (int64_t i = 0; i < nx; ++i) k += v[(size_t)r * nx + i];
+        rc[r] = k == 0 ? 0 : (k == nx ? 1 : 2);
+    }
     if (!p->fixed) MSB_HIP(hipMalloc(&p->fixed, n));
+    if (!p->row_fix) MSB_HIP(hipMalloc(&p->row_fix, rc.size()));
     MSB_HIP(hipMemcpy(p->fixed, v.data(), n, hipMemcpyHostToDevice));
+    MSB_HIP(hipMemcpy(p->row_fix, rc.data(), rc.size(), hipMemcpyHostToDevice));
     p->n_fixed = cnt;
     return MSB_OK;
 }
