@@ -190,6 +190,7 @@ struct msb_plan_s {
     // constraints
     uint8_t *fixed = nullptr;   // device [d][N] or null
     uint8_t *row_fix = nullptr; // device [d][Ny Nz]: per x-row, 0 no constrained DOF, 1 all, 2 some
+    int32_t *fix_sat = nullptr; // 2D: device [(Ny + 1)][(Nx + 1)] constrained DOFs in [0, x) x [0, y)
     int64_t n_fixed = 0;
 
     // broken bonds (device), grouped by grid row (row = k*Ny + j)

@@ -1112,6 +1112,7 @@ template <typename T> PassArgs<T> pass_args(const msb_plan_s *p, const DeviceOp 
     a.n_off = p->n_off;
     a.fixed = p->fixed;
     a.row_fix = p->row_fix;
+    a.fix_sat = p->fix_sat;
     a.nu = sel<T>(p->nu64, p->nu32);
     a.offs = p->off_dev;
     a.br_row_ptr = p->n_pairs ? p->br_row_ptr : nullptr;

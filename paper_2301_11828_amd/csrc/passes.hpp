@@ -65,6 +65,7 @@ template <typename T> struct PassArgs {
     // constraints and bonds
     const uint8_t *fixed;          // [d][N] or null
     const uint8_t *row_fix;        // [d][rows] with fixed: per x-row 0 none constrained, 1 all, 2 some
+    const int32_t *fix_sat;        // 2D with fixed: [(Ny + 1)][(Nx + 1)] summed-area table of the mask
     const int32_t *br_row_ptr;     // [rows+1] or null
     const int32_t *br_node_i;
     const int32_t *br_bond_ptr;

@@ -898,7 +898,7 @@ extern "C" void msb_plan_destroy(msb_plan p) {
     free_operator(p->op);
     free_operator(p->pre);
     for (auto &o : p->dop) free_operator(o);
-    void *bufs[] = {p->fixed, p->row_fix, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off, p->T1, p->T2,
+    void *bufs[] = {p->fixed, p->row_fix, p->fix_sat, p->br_row_ptr, p->br_node_i, p->br_bond_ptr, p->br_q, p->br_off, p->T1, p->T2,
                     p->nu64, p->nu32, p->off_dev};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -923,8 +923,10 @@ extern "C" msb_status msb_plan_set_constraints(msb_plan p, const uint8_t *fixed)
     if (!fixed) {
         if (p->fixed) hipFree(p->fixed);
         if (p->row_fix) hipFree(p->row_fix);
+        if (p->fix_sat) hipFree(p->fix_sat);
         p->fixed = nullptr;
         p->row_fix = nullptr;
+        p->fix_sat = nullptr;
         p->n_fixed = 0;
         return MSB_OK;
     }
@@ -947,6 +949,20 @@ extern "C" msb_status msb_plan_set_constraints(msb_plan p, const uint8_t *fixed)
     if (!p->row_fix) MSB_HIP(hipMalloc(&p->row_fix, rc.size()));
     MSB_HIP(hipMemcpy(p->fixed, v.data(), n, hipMemcpyHostToDevice));
     MSB_HIP(hipMemcpy(p->row_fix, rc.data(), rc.size(), hipMemcpyHostToDevice));
+    if (p->dim == 2) {
+        // summed-area table of the constrained DOFs (both components) for the tiled product:
+        // a block whose inner nodes hold none reads no mask
+        const int64_t ny = p->n[1], W = nx + 1;
+        std::vector<int32_t> sat((size_t)(ny + 1) * W, 0);
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                const int32_t k = v[(size_t)y * nx + x] + v[(size_t)p->N + y * nx + x];
+                sat[(size_t)(y + 1) * W + x + 1] = sat[(size_t)y * W + x + 1] + sat[(size_t)(y + 1) * W + x] -
+                                                   sat[(size_t)y * W + x] + k;
+            }
+        if (!p->fix_sat) MSB_HIP(hipMalloc(&p->fix_sat, sizeof(int32_t) * sat.size()));
+        MSB_HIP(hipMemcpy(p->fix_sat, sat.data(), sizeof(int32_t) * sat.size(), hipMemcpyHostToDevice));
+    }
     p->n_fixed = cnt;
     return MSB_OK;
 }

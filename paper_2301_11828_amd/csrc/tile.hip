@@ -444,6 +444,17 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
     double rr_acc = 0.0;                // r.r of the inner nodes (fused step, rr_tiles)
     uint32_t fixbits = 0;
     const T *de = a.de + (size_t)b * a.de_slot;
+    // constrained DOFs among the block's inner nodes, from the summed-area table of the mask:
+    // without any, the block reads no mask.  Frames 32 and 64 only: their launches run in several
+    // rounds of blocks, which hide the table's load; frame-16 blocks (one wave each, typically
+    // all resident at once) wait for it at the start, which cost more than the mask loads saved
+    // (one-case 512^2 FP32 product 6.4 -> 6.8 us; 16 cases at frame 32: 12% faster)
+    bool bfix = a.fixed != nullptr;
+    if (TL >= 32 && bfix && a.fix_sat) {
+        const int W = Nx + 1;
+        const int32_t *st = a.fix_sat;
+        bfix = st[(y0 + ny) * W + x0 + nx] - st[y0 * W + x0 + nx] - st[(y0 + ny) * W + x0] + st[y0 * W + x0] > 0;
+    }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int ly = p + S * i, gy = y0 - M + ly;
@@ -484,7 +495,7 @@ __device__ __forceinline__ void tile_reg_body(const PassArgs<T> &a, const EndArg
                 v[i].y = uin[cbase + N + q];
             }
             if (col_inner && ly >= M && ly < M + ny) {
-                if (a.fixed) fixbits |= ((uint32_t)a.fixed[q] | ((uint32_t)a.fixed[N + q] << 1)) << (2 * i);
+                if (bfix) fixbits |= ((uint32_t)a.fixed[q] | ((uint32_t)a.fixed[N + q] << 1)) << (2 * i);
                 if (edge) {
                     const int M1 = M + 1;
                     const int lx = min(gx, M), hx = min(Nx - 1 - gx, M), lo = min(gy, M), hy = min(Ny - 1 - gy, M);
